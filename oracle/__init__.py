@@ -1,0 +1,206 @@
+"""Plain serial FP64 CPU oracle for the Cahn-Hilliard ADI hot path.
+
+TEST INFRASTRUCTURE ONLY: only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the HIP library (``paper_2101_06550_amd``) and never imports it;
+the library never imports this package.
+
+The arithmetic lives in ``oracle.c`` (gcc -O2 -ffp-contract=off); this module
+only marshals numpy arrays through ctypes.  Each wrapper names the passage of
+the thesis (arXiv 2101.06550) that the C routine follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+_D = ctypes.c_double
+_I = ctypes.c_int
+_P = ctypes.POINTER(ctypes.c_double)
+
+
+def build(out: str = _LIB, src: str = _SRC, extra: tuple = ()) -> str:
+    """Compile the oracle with gcc (no FMA contraction); returns the path."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+           "-fPIC", "-shared", "-I", _HERE, *extra, src, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def load(path: str | None = None):
+    """Load (building first if absent) the oracle shared library."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    p = path or _LIB
+    if not os.path.exists(p):
+        build(p)
+    lib = ctypes.CDLL(p)
+    lib.orc_penta_lr_factor.restype = _I
+    lib.orc_penta_lr_factor.argtypes = [_I] + [_P] * 10
+    lib.orc_penta_lr_solve.restype = None
+    lib.orc_penta_lr_solve.argtypes = [_I] + [_P] * 7
+    lib.orc_tri_prefactor.restype = _I
+    lib.orc_tri_prefactor.argtypes = [_I] + [_P] * 5
+    lib.orc_tri_solve.restype = None
+    lib.orc_tri_solve.argtypes = [_I] + [_P] * 5
+    lib.orc_cyclic_penta_solve.restype = _I
+    lib.orc_cyclic_penta_solve.argtypes = [_I, _D, _D, _D, _D, _D, _P, _P]
+    lib.orc_cyclic_tri_solve.restype = _I
+    lib.orc_cyclic_tri_solve.argtypes = [_I, _D, _D, _D, _P, _P]
+    lib.orc_cpenta_lines.restype = _I
+    lib.orc_cpenta_lines.argtypes = [_I, _I, _I, _D, _D, _D, _D, _D, _P]
+    lib.orc_ctri_lines.restype = _I
+    lib.orc_ctri_lines.argtypes = [_I, _I, _I, _D, _D, _D, _P]
+    lib.orc_stencil2d.restype = _I
+    lib.orc_stencil2d.argtypes = [_P, _P, _I, _I, _P, _I, _I, _I, _I, _I, _I]
+    lib.orc_ch_rhs.restype = None
+    lib.orc_ch_rhs.argtypes = [_P, _P, _I, _I, _D, _D, _D, _D, _D]
+    lib.orc_ch_step.restype = _I
+    lib.orc_ch_step.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D]
+    lib.orc_ch_mass.restype = _D
+    lib.orc_ch_mass.argtypes = [_P, _I, _I, _D, _D]
+    lib.orc_ch_energy.restype = _D
+    lib.orc_ch_energy.argtypes = [_P, _I, _I, _D, _D, _D]
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Bound view of one compiled oracle library (the default one, or a
+    mutant build made by a test)."""
+
+    def __init__(self, lib=None):
+        self.lib = lib if lib is not None else load()
+
+    # Ch.4 "Solution of the pentadiagonal system" (general LR, non-cyclic)
+    def penta_lr_solve(self, a, b, c, d, e, f):
+        a, b, c, d, e, f = map(_f64, (a, b, c, d, e, f))
+        n = f.shape[0]
+        fac = [np.zeros(n) for _ in range(5)]
+        rc = self.lib.orc_penta_lr_factor(n, _ptr(a), _ptr(b), _ptr(c), _ptr(d),
+                                          _ptr(e), *[_ptr(x) for x in fac])
+        if rc:
+            raise ValueError("zero or non-finite pivot")
+        x = np.zeros(n)
+        self.lib.orc_penta_lr_solve(n, *[_ptr(v) for v in fac], _ptr(f), _ptr(x))
+        return x
+
+    # Ch.5 "Tridiagonal Inversion Algorithm" (general Thomas, non-cyclic)
+    def tri_solve(self, a, b, c, f):
+        a, b, c, f = map(_f64, (a, b, c, f))
+        n = f.shape[0]
+        chat, den = np.zeros(n), np.zeros(n)
+        if self.lib.orc_tri_prefactor(n, _ptr(a), _ptr(b), _ptr(c), _ptr(chat),
+                                      _ptr(den)):
+            raise ValueError("zero or non-finite pivot")
+        x = np.zeros(n)
+        self.lib.orc_tri_solve(n, _ptr(a), _ptr(chat), _ptr(den), _ptr(f), _ptr(x))
+        return x
+
+    # Ch.4 "The pentadiagonal matrix system" (Navon bordering) + LR
+    def cyclic_penta_solve(self, coefs, f):
+        f = _f64(f)
+        x = np.zeros_like(f)
+        rc = self.lib.orc_cyclic_penta_solve(f.shape[0], *map(float, coefs), _ptr(f),
+                                             _ptr(x))
+        if rc:
+            raise ValueError(f"cyclic penta solve failed ({rc})")
+        return x
+
+    # Ch.5 "Periodic Tridiagonal Matrix" (Sherman-Morrison) + Thomas
+    def cyclic_tri_solve(self, coefs, f):
+        f = _f64(f)
+        x = np.zeros_like(f)
+        rc = self.lib.orc_cyclic_tri_solve(f.shape[0], *map(float, coefs), _ptr(f),
+                                           _ptr(x))
+        if rc:
+            raise ValueError(f"cyclic tri solve failed ({rc})")
+        return x
+
+    def cpenta_lines(self, data2d, direction, coefs):
+        """Solve every row (direction 0) or column (direction 1) of a
+        row-major (ny, nx) array with one cyclic penta matrix; returns a copy."""
+        out = _f64(data2d).copy()
+        ny, nx = out.shape
+        rc = self.lib.orc_cpenta_lines(nx, ny, direction, *map(float, coefs), _ptr(out))
+        if rc:
+            raise ValueError(f"cyclic penta lines failed ({rc})")
+        return out
+
+    def ctri_lines(self, data2d, direction, coefs):
+        out = _f64(data2d).copy()
+        ny, nx = out.shape
+        rc = self.lib.orc_ctri_lines(nx, ny, direction, *map(float, coefs), _ptr(out))
+        if rc:
+            raise ValueError(f"cyclic tri lines failed ({rc})")
+        return out
+
+    # Ch.3 "Software API" (cuSten-style stencil, xy direction)
+    def stencil2d(self, x2d, weights, left, right, top, bottom, periodic=True,
+                  premap=0, out=None):
+        x2d = _f64(x2d)
+        ny, nx = x2d.shape
+        w = _f64(weights).ravel()
+        assert w.size == (left + right + 1) * (top + bottom + 1)
+        o = np.zeros_like(x2d) if out is None else _f64(out).copy()
+        rc = self.lib.orc_stencil2d(_ptr(x2d), _ptr(o), nx, ny, _ptr(w), left, right,
+                                    top, bottom, int(bool(periodic)), int(premap))
+        if rc:
+            raise ValueError("bad stencil arguments")
+        return o
+
+    # Ch.2 eq. 2:ch / Ch.3 eq. 3:ch_adi (first-order ADI right-hand side)
+    def ch_rhs(self, c2d, lx, ly, D, gamma, dt):
+        c = _f64(c2d)
+        ny, nx = c.shape
+        r = np.zeros_like(c)
+        self.lib.orc_ch_rhs(_ptr(c), _ptr(r), nx, ny, lx, ly, D, gamma, dt)
+        return r
+
+    def ch_step(self, c2d, lx, ly, D, gamma, dt, nsteps=1):
+        c = _f64(c2d).copy()
+        ny, nx = c.shape
+        for _ in range(nsteps):
+            rc = self.lib.orc_ch_step(_ptr(c), nx, ny, lx, ly, D, gamma, dt)
+            if rc:
+                raise ValueError(f"ch step failed ({rc})")
+        return c
+
+    def ch_mass(self, c2d, lx, ly):
+        c = _f64(c2d)
+        ny, nx = c.shape
+        return self.lib.orc_ch_mass(_ptr(c), nx, ny, lx, ly)
+
+    def ch_energy(self, c2d, lx, ly, gamma):
+        c = _f64(c2d)
+        ny, nx = c.shape
+        return self.lib.orc_ch_energy(_ptr(c), nx, ny, lx, ly, gamma)
+
+
+_default = None
+
+
+def oracle() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default

@@ -1,0 +1,146 @@
+"""Planted mistakes: each test copies the oracle's C source, plants one
+plausible mistake (a dropped term, a wrong sign or index, a transposed
+operand), compiles the mutant on the CPU and checks that the pins reject it.
+This shows that the pins are sensitive to exactly the mistakes they are meant
+to catch.  Nothing here touches the GPU library."""
+import math
+import os
+import shutil
+
+import numpy as np
+import pytest
+
+import oracle as oracle_pkg
+from paper_2101_06550_amd import inputs
+
+L = 2 * math.pi
+SRC = os.path.join(os.path.dirname(oracle_pkg.__file__), "oracle.c")
+HDR = os.path.join(os.path.dirname(oracle_pkg.__file__), "oracle.h")
+
+
+def _dense_cyclic(n, coefs):
+    w = len(coefs) // 2
+    A = np.zeros((n, n))
+    for i in range(n):
+        for k, v in enumerate(coefs):
+            A[i, (i + k - w) % n] += v
+    return A
+
+
+def _kappa2(n):
+    h = L / n
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    return (4.0 / h ** 2) * np.sin(np.pi * m / n) ** 2
+
+
+def pin_penta_dense(o):
+    rng = np.random.default_rng(3)
+    for n in (5, 6, 9, 20):
+        a, b, d, e = rng.uniform(-0.9, 0.9, 4)
+        co = (a, b, 4.2, d, e)
+        f = rng.uniform(-1, 1, n)
+        x = o.cyclic_penta_solve(co, f)
+        if np.max(np.abs(x - np.linalg.solve(_dense_cyclic(n, co), f))) > 1e-12:
+            return False
+    return True
+
+
+def pin_tri_dense(o):
+    rng = np.random.default_rng(4)
+    for n in (3, 5, 17):
+        a, c = rng.uniform(-0.9, 0.9, 2)
+        co = (a, 2.7, c)
+        f = rng.uniform(-1, 1, n)
+        x = o.cyclic_tri_solve(co, f)
+        if np.max(np.abs(x - np.linalg.solve(_dense_cyclic(n, co), f))) > 1e-12:
+            return False
+    return True
+
+
+def pin_step_fft(o):
+    n, D, g, dt = 32, 1.0, 0.01, 1e-3
+    c = inputs.noise_field(n, n, 5)
+    k2x, k2y = _kappa2(n)[None, :], _kappa2(n)[:, None]
+    mu = c ** 3 - c
+    r = c + D * dt * np.real(np.fft.ifft2(-(k2x + k2y) * np.fft.fft2(mu))) \
+        - 2 * D * g * dt * np.real(np.fft.ifft2(k2x * k2y * np.fft.fft2(c)))
+    ref = np.real(np.fft.ifft2(np.fft.fft2(r) / ((1 + D * g * dt * k2x ** 2) *
+                                                  (1 + D * g * dt * k2y ** 2))))
+    out = o.ch_step(c, L, L, D, g, dt)
+    return np.max(np.abs(out - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+def pin_energy_closed_form(o):
+    n, s, k, g = 64, 0.3, 5, 0.01
+    h = L / n
+    c0 = np.tile(s * np.sin(k * np.arange(n) * h), (n, 1))
+    bulk = 0.25 * (s ** 4 * 3 * n / 8 - 2 * s ** 2 * n / 2 + n) * n
+    grad = s ** 2 * 4 * math.sin(k * h / 2) ** 2 * (n / 2) / h ** 2 * n
+    F = (bulk + 0.5 * g * grad) * h * h
+    return abs(o.ch_energy(c0, L, L, g) - F) < 1e-12 * F
+
+
+def pin_stencil_asymmetric(o):
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, (9, 11))
+    w = rng.uniform(-1, 1, (3, 4))  # top=0, bottom=2, left=1, right=2
+    out = o.stencil2d(x, w, 1, 2, 0, 2, periodic=True)
+    ref = np.zeros_like(x)
+    for q in range(0, 3):
+        for p in range(-1, 3):
+            ref += w[q, p + 1] * np.roll(np.roll(x, -q, axis=0), -p, axis=1)
+    return np.max(np.abs(out - ref)) < 1e-13
+
+
+ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
+            pin_stencil_asymmetric]
+
+MUTANTS = {
+    "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
+                        "r[(size_t)j * nx + i] = cc + D * dt * lap;"),
+    "laplacian_sign": ("= cc + D * dt * lap - 2.0", "= cc - D * dt * lap - 2.0"),
+    "grid_spacing_n_plus_1": ("const double dx = lx / nx, dy = ly / ny;\n  for (int j = 0; j < ny; ++j) {\n    const int jm",
+                              "const double dx = lx / (nx + 1), dy = ly / ny;\n  for (int j = 0; j < ny; ++j) {\n    const int jm"),
+    "lr_delta_index": ("if (i >= 2) al = al - a[i] * del[i - 2];", "if (i >= 2) al = al - a[i] * del[i - 1];"),
+    "lr_forward_drops_eps": ("if (i >= 2) num = num - eps[i] * g[i - 2];", ""),
+    "navon_untransposed": ("rc = orc_penta_lr_factor(m, ta, tb, tc, td, te, talpha,",
+                           "rc = orc_penta_lr_factor(m, ea, eb, ec, ed, ee, talpha,"),
+    "navon_k_column": ("p->kcol1[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 1);",
+                       "p->kcol1[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 2);"),
+    "corner_swap": ("if (off == n - 2) v = v + a;\n  if (off == n - 1) v = v + b;",
+                    "if (off == n - 2) v = v + b;\n  if (off == n - 1) v = v + a;"),
+    "sherman_morrison_sign": ("for (int i = 0; i < n; ++i) x[i] = y[i] - fac * p->z[i];",
+                              "for (int i = 0; i < n; ++i) x[i] = y[i] + fac * p->z[i];"),
+    "thomas_back_typo": ("for (int i = n - 2; i >= 0; --i) x[i] = dh[i] - chat[i] * x[i + 1];",
+                         "for (int i = n - 2; i >= 0; --i) x[i] = dh[i] - a[i] * chat[i];"),
+    "energy_half_bulk": ("double v = 0.25 * w * w", "double v = 0.5 * w * w"),
+    "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
+                                   "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
+}
+
+
+def test_unmutated_oracle_passes_all_pins(orc):
+    for pin in ALL_PINS:
+        assert pin(orc), pin.__name__
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique/found"
+    shutil.copy(HDR, tmp_path / "oracle.h")
+    (tmp_path / "oracle.c").write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    oracle_pkg.build(out=so, src=str(tmp_path / "oracle.c"),
+                     extra=("-I", str(tmp_path)))
+    mutant = oracle_pkg.Oracle(oracle_pkg.load(so))
+    failed = []
+    for pin in ALL_PINS:
+        try:
+            ok = pin(mutant)
+        except (ValueError, FloatingPointError, np.linalg.LinAlgError):
+            ok = False
+        if not ok:
+            failed.append(pin.__name__)
+    assert failed, f"no pin caught the planted mistake {name}"
