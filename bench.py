@@ -1,0 +1,223 @@
+"""Benchmark: periodic 2D Cahn-Hilliard ADI steps on one MI355X.
+
+Default workload (the large single run at HBM scale): 8192 x 8192 grid on
+(0, 2 pi)^2, D = 1, gamma = 0.001, dt = 1e-6, c0 = 0.05 sin(3x) sin(5y) +
+U[-0.01, 0.01] (seed 5), FP64, mass and free energy recorded every step.
+One step = the explicit right-hand side + batched cyclic pentadiagonal solves
+along every column and every row (the whole hot path); the state stays
+resident in HBM.
+
+Prints one JSON line: throughput in grid-point updates/s, the roofline of the
+dominant kernel (per-kernel HIP-event timing on the library's stream), the
+oracle timed on the host, and the standalone batched-solve throughput.
+
+    python bench.py [--gpus 1] [--steps 500] [--warmup 10]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CH ADI grid-pt updates/s; penta-solve HBM GB/s % peak; FP32-refined vs FP64"
+HBM_PEAK_GBS = 8000.0
+CHUNK = 32  # unknowns per thread-chunk in the library's chunked kernels
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def column_pass_bytes(nx, ny):
+    """Algorithmic HBM bytes of one column-pass launch: read the state once,
+    write the chunk-interior solution, write 4 separator parts per chunk."""
+    n = nx * ny
+    sc = ny // CHUNK
+    return 8 * n + 8 * nx * (ny - 2 * sc) + 8 * 4 * sc * nx
+
+
+def row_pass_bytes(nx, ny):
+    return 16 * nx * ny
+
+
+def reduced_bytes(nx, ny):
+    sc = ny // CHUNK
+    return 8 * 4 * sc * nx + 8 * 2 * sc * nx
+
+
+def cpu_baseline(c0, L, D, gamma, dt, budget_s=12.0, max_steps=3):
+    import oracle
+    orc = oracle.oracle()
+    n = c0.size
+    steps, t0 = 0, time.perf_counter()
+    c = c0
+    while steps < max_steps:
+        c = orc.ch_step(c, L, L, D, gamma, dt)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": n * steps / el, "unit": "grid-point updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} serial FP64 oracle ADI steps of the {c0.shape[1]}x{c0.shape[0]} "
+                      f"workload ({el:.1f} s, single thread)"}
+
+
+def solve_throughput(chx, torch, reps=10):
+    """Standalone batched cyclic penta solves, N = 1024, alpha = 0.5, scaled
+    batch of 131072 systems (1 GiB FP64), interleaved and contiguous."""
+    from paper_2101_06550_amd import inputs
+    n, batch, a = 1024, 131072, 0.5
+    plan = chx.penta_factor(n, a, -4 * a, 1 + 6 * a, -4 * a, a)
+    out = {}
+    for name, layout, shape, bpu in (("interleaved", 0, (n, batch), None),
+                                     ("contiguous", 1, (batch, n), 16)):
+        x = torch.tensor(inputs.uniform(2, shape, -1, 1), device="cuda")
+        ws = torch.empty(chx.penta_solve_ws_bytes(plan, batch, layout) + 256, dtype=torch.uint8,
+                         device="cuda")
+        chx.penta_solve_batch(plan, batch, x, layout=layout, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            chx.penta_solve_batch(plan, batch, x, layout=layout, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        if bpu is None:
+            # chunk sweep (read f, write y, 4 parts/chunk) + separators + correction
+            mi = CHUNK - 2
+            bpu = (8 + 8 * mi / CHUNK + 32 / CHUNK) + (32 + 16) / CHUNK + \
+                  (2 * 8 * mi / CHUNK + 32 / CHUNK)
+        gbs = bpu * n * batch / (ms * 1e-3) / 1e9
+        out[name] = {"systems": batch, "n": n, "ms_per_solve_batch": round(ms, 4),
+                     "solves_per_s": batch / (ms * 1e-3),
+                     "algorithmic_bytes_per_unknown": round(bpu, 3),
+                     "effective_GBps": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        del x, ws
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solves", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2101_06550_amd import chx, inputs
+    if not os.path.exists(chx.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    chx.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    L = 2 * math.pi
+    n, D, gamma, dt = args.n, 1.0, 0.001, 1e-6
+    log(f"building initial state {n}x{n}")
+    c0 = inputs.mode_plus_noise(n, 5)
+    h = chx.ch_create(n, n, L, L, D, gamma, dt)
+    c = torch.tensor(c0, device="cuda")
+    K, W = args.steps, args.warmup
+    diag = torch.zeros(2 * (K + 1), dtype=torch.float64, device="cuda")
+    if W > 0:
+        log(f"warmup {W} steps")
+        cw = c.clone()
+        chx.ch_adi_step(h, cw, nsteps=W, diag_out=torch.zeros(2 * (W + 1), dtype=torch.float64,
+                                                              device="cuda"))
+        torch.cuda.synchronize()
+        del cw
+    log(f"timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chx.ch_adi_step(h, c, nsteps=K, diag_out=diag)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = diag.cpu().numpy()
+    mass, energy = d[0::2], d[1::2]
+    l1 = float(np.sum(np.abs(c0))) * (L / n) ** 2
+    mass_drift = float(np.max(np.abs(mass - mass[0])) / l1)
+    energy_monotone = bool(np.all(np.diff(energy) <= 1e-12 * np.abs(energy[:-1])))
+
+    log("per-kernel timing run")
+    ct = torch.tensor(c0, device="cuda")
+    phase_ms, phase_n = chx.ch_adi_step_timed(h, ct, nsteps=min(K, 100),
+                                              diag_out=torch.zeros(2 * (min(K, 100) + 1),
+                                                                   dtype=torch.float64,
+                                                                   device="cuda"))
+    del ct
+    names = ["column_pass", "column_separators", "row_pass", "finalize_and_diag"]
+    bytes_per = [column_pass_bytes(n, n), reduced_bytes(n, n), row_pass_bytes(n, n), None]
+    phases = {}
+    for k, nm in enumerate(names):
+        if phase_n[k] == 0:
+            continue
+        avg = phase_ms[k] / phase_n[k]
+        ent = {"launches": phase_n[k], "avg_ms": round(avg, 5), "total_ms": round(phase_ms[k], 3)}
+        if bytes_per[k]:
+            ent["algorithmic_bytes"] = bytes_per[k]
+            ent["achieved_GBps"] = round(bytes_per[k] / (avg * 1e-3) / 1e9, 1)
+        phases[nm] = ent
+    dom = max((k for k in range(3) if phase_n[k]), key=lambda k: phase_ms[k])
+    dom_avg = phase_ms[dom] / phase_n[dom]
+    achieved = bytes_per[dom] / (dom_avg * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None}
+
+    extra = {}
+    if not args.no_solves:
+        log("standalone batched solves")
+        extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        cpu = cpu_baseline(c0, L, D, gamma, dt)
+
+    res = {
+        "metric": METRIC,
+        "value": n * n * K / el,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(1e3 * el / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"large single run: {n}x{n} periodic Cahn-Hilliard ADI on "
+                               f"(0,2pi)^2, D=1, gamma=0.001, dt=1e-6, c0=0.05 sin3x sin5y + "
+                               f"U[-0.01,0.01] (seed 5), FP64, mass+energy every step",
+                   "nx": n, "ny": n, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": phases,
+        "checks": {"mass_drift_rel_L1": mass_drift, "energy_monotone": energy_monotone},
+        "extra": extra,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

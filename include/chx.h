@@ -1,0 +1,218 @@
+/*
+ * chx.h -- C-ABI of the MI355X (gfx950) Cahn-Hilliard ADI library.
+ *
+ * The library implements the hot path of A. Gloster's thesis (arXiv
+ * 2101.06550): batched constant-coefficient cyclic pentadiagonal and
+ * tridiagonal solves (Ch.4 "cuPentBatch", Ch.5 single-LHS batched solvers),
+ * cuSten-style 2D stencils (Ch.3 "Software API") and one semi-implicit ADI
+ * time step of the periodic 2D Cahn-Hilliard equation (Ch.2 eq. 2:ch,
+ * Ch.3 eq. 3:ch_adi), all on HIP kernels written for gfx950.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: CHX_OK (0) or a negative CHX_E*
+ *    code.  No C++ exception crosses this boundary.
+ *  - Pointers named "device" are HIP device pointers (for instance
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor); pointers named "host" are
+ *    ordinary host memory.  The caller owns every field, right-hand side,
+ *    workspace and output buffer.  The library owns only the opaque plan and
+ *    handle objects and the small device tables inside them; *_destroy frees
+ *    them.
+ *  - Device work is enqueued asynchronously on the caller's stream
+ *    (chx_stream = hipStream_t; 0 = the null stream).  Argument checks are
+ *    synchronous and happen before anything is enqueued.  A failed kernel
+ *    launch returns CHX_EHIP.
+ *  - Plans and handles are immutable after creation, so one plan may be used
+ *    from several streams and host threads at once; calls that share a
+ *    workspace or an output buffer must not overlap.
+ *  - Arrays are FP64 unless said otherwise.  2D fields are row-major with x
+ *    (index i) fastest: element (i, j) at j*ld + i, ld >= nx.
+ *  - There is no CPU fallback: without a usable gfx950 device the calls that
+ *    launch work return CHX_EHIP.
+ */
+#ifndef CHX_H
+#define CHX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHX_OK = 0,
+  CHX_EINVAL = -1,          /* bad argument (null pointer, ld too small, ...)  */
+  CHX_EUNSUPPORTED_N = -2,  /* system size below the minimum (5 penta, 3 tri)  */
+  CHX_EPIVOT = -3,          /* zero, negative or non-finite pivot in a factor  */
+  CHX_EHIP = -4,            /* a HIP runtime call or kernel launch failed      */
+  CHX_ENONFINITE = -5,      /* a diagnostic sum is NaN or infinite             */
+  CHX_ENOMEM = -6,          /* workspace too small / allocation failed         */
+  CHX_EREFINE = -7          /* iterative refinement did not reduce the error   */
+};
+
+enum chx_dtype {
+  CHX_F64 = 0,              /* FP64 sweeps and storage                          */
+  CHX_F32_REFINED = 1       /* FP32 sweeps + FP64 residual refinement (FP64 I/O) */
+};
+
+enum chx_layout {
+  CHX_INTERLEAVED = 0,      /* element i of system s at i*ld + s, ld >= batch    */
+  CHX_CONTIGUOUS = 1        /* element i of system s at s*ld + i, ld >= n        */
+};
+
+typedef struct chx_penta_plan_s* chx_penta_plan;
+typedef struct chx_tri_plan_s* chx_tri_plan;
+typedef struct chx_ch_s* chx_ch;
+typedef void* chx_stream;
+
+/* Library version, e.g. 100 for 0.1.0. */
+int chx_version(void);
+/* Human-readable text for a status code (static storage). */
+const char* chx_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Pentadiagonal systems (Ch.4 "The pentadiagonal matrix system",
+ * "Solution of the pentadiagonal system"; Ch.5 "Pentadiagonal Systems").
+ * Row i of the n x n matrix is a x[i-2] + b x[i-1] + c x[i] + d x[i+1] +
+ * e x[i+2]; periodic != 0 wraps the indices mod n (the corners of the
+ * cyclic matrix, removed by Navon's bordering of the last two unknowns),
+ * periodic == 0 drops the entries that fall outside the matrix.
+ *
+ * penta_factor: factor once (host, FP64 accumulated in extended precision)
+ *   and upload the plan's tables -- the LR factors of the bordered block,
+ *   the bordering (Schur-complement) vectors and their FP32 copies -- so that
+ *   every later solve only sweeps.  n >= 5, else CHX_EUNSUPPORTED_N.  The
+ *   factorisation does not pivot (as in the thesis): a pivot alpha_i <= 0 or
+ *   not finite gives CHX_EPIVOT; the matrix should be symmetric positive
+ *   definite or diagonally dominant.  The device that is current when this is
+ *   called holds the tables; solves must run on that device.
+ * penta_plan_destroy: frees the plan (NULL is accepted).
+ */
+int penta_factor(int n, double a, double b, double c, double d, double e,
+                 int periodic, chx_penta_plan* out);
+int penta_plan_destroy(chx_penta_plan p);
+
+/* Bytes of device workspace that penta_solve_batch needs for (batch, layout,
+ * dtype, refine_passes); 0 means no workspace is used (ws may be NULL). */
+size_t penta_solve_ws_bytes(chx_penta_plan p, int batch, int layout, int dtype,
+                            int refine_passes);
+
+/* penta_solve_batch: solve A x_s = f_s for batch systems sharing the plan's
+ *   single LHS (Ch.5 "single LHS, interleaved RHS").  x_inout (device) holds
+ *   the right-hand sides on entry and the solutions on return, FP64, in the
+ *   given layout with leading dimension ld (ld >= batch interleaved, ld >= n
+ *   contiguous).  dtype CHX_F64 sweeps in FP64; CHX_F32_REFINED sweeps in FP32
+ *   and applies refine_passes (1..3) FP64-residual refinement passes.  ws
+ *   (device) must hold penta_solve_ws_bytes(...) bytes, aligned to 256 B.
+ *   Returns CHX_EINVAL for bad arguments, CHX_ENOMEM if ws_bytes is short. */
+int penta_solve_batch(chx_penta_plan p, int batch, void* x_inout, long ld,
+                      int layout, int dtype, int refine_passes, void* ws,
+                      size_t ws_bytes, chx_stream s);
+
+/* ------------------------------------------------------------------------
+ * Tridiagonal systems (Ch.5 "Tridiagonal Inversion Algorithm",
+ * "Periodic Tridiagonal Matrix").  Row i is a x[i-1] + b x[i] + c x[i+1];
+ * periodic wraps (top-right corner a, bottom-left corner c).  n >= 3.  The
+ * other conventions are those of the pentadiagonal calls.
+ */
+int tri_factor(int n, double a, double b, double c, int periodic,
+               chx_tri_plan* out);
+int tri_plan_destroy(chx_tri_plan p);
+size_t tri_solve_ws_bytes(chx_tri_plan p, int batch, int layout, int dtype,
+                          int refine_passes);
+int tri_solve_batch(chx_tri_plan p, int batch, void* x_inout, long ld,
+                    int layout, int dtype, int refine_passes, void* ws,
+                    size_t ws_bytes, chx_stream s);
+
+/* ------------------------------------------------------------------------
+ * stencil2d_apply: cuSten-style 2D stencil in the xy direction (Ch.3
+ *   "Software API").  out[j][i] = sum_{q=-top..bottom} sum_{p=-left..right}
+ *   w[(q+top)*(left+right+1) + (p+left)] * pre(in[j+q][i+p]),
+ *   pre(v) = v (premap 0) or v^3 - v (premap 1, the non-linear Cahn-Hilliard
+ *   term that the thesis applies through a function-pointer stencil).
+ *   Weights (host, FP64) are listed from the top-left of the stencil, left to
+ *   right, row by row; "top" is the smaller j.  Extents are 0..4 each.
+ *   periodic != 0 wraps indices; periodic == 0 writes only the points whose
+ *   whole stencil lies inside the array and leaves the boundary cells of out
+ *   untouched.  in and out (device, nx x ny, leading dimension ld >= nx) must
+ *   not overlap (the thesis's separate input and output buffers).
+ */
+int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
+                    const double* weights, int left, int right, int top,
+                    int bottom, int periodic, int premap, chx_stream s);
+
+/* ------------------------------------------------------------------------
+ * Cahn-Hilliard ADI stepping (Ch.2 eq. 2:ch, Ch.3 eq. 3:ch_adi).
+ * One step on the periodic box [0,lx) x [0,ly), nx x ny points, dx = lx/nx:
+ *   r = c + D dt Lap5(c^3 - c) - 2 D gamma dt (d2x d2y) c
+ *   (I + sx P_x)(I + sy P_y) c_new = r,   P = circ(1,-4,6,-4,1),
+ *   s = D gamma dt / h^4,
+ * i.e. the explicit right-hand side by stencils, then batched cyclic
+ * pentadiagonal solves along every row and every column.
+ */
+typedef struct {
+  int nx, ny;            /* grid points (>= 5 each)                        */
+  double lx, ly;         /* box lengths (the thesis uses 2 pi)            */
+  double D, gamma, dt;   /* mobility, interface parameter, time step      */
+  int dtype;             /* CHX_F64 or CHX_F32_REFINED                    */
+  int refine_passes;     /* 1..3 for CHX_F32_REFINED, ignored for FP64    */
+} chx_ch_params;
+
+/* ch_create: factor both directions once and pick the kernel shapes.
+ * ch_destroy: free (NULL accepted).  ch_ws_bytes: workspace for ch_adi_step. */
+int ch_create(const chx_ch_params* prm, chx_ch* out);
+int ch_destroy(chx_ch h);
+size_t ch_ws_bytes(chx_ch h);
+
+/* ch_adi_step: advance c_inout (device, nx x ny, leading dimension ld >= nx)
+ *   by nsteps >= 1 ADI steps in place.  ws (device) holds ch_ws_bytes(h)
+ *   bytes; its contents are scratch between calls.  diag_out (device, may be
+ *   NULL) receives 2*(nsteps+1) doubles: mass and free energy of the state
+ *   before each step and after the last (as ch_diagnostics defines them).
+ *   Asynchronous on stream s.  Calls sharing ws must not overlap. */
+int ch_adi_step(chx_ch h, double* c_inout, long ld, int nsteps,
+                double* diag_out, void* ws, size_t ws_bytes, chx_stream s);
+
+/* ch_adi_step_timed: ch_adi_step with a HIP event recorded on stream s
+ *   around every kernel it launches; synchronises s and returns, per phase,
+ *   the summed kernel time in milliseconds (phase_ms, host, 4 doubles) and the
+ *   number of launches (phase_launches, host, 4 ints).  Phases: 0 column pass
+ *   (right-hand side + column sweeps), 1 column separator system, 2 row solves,
+ *   3 finalize and diagnostic reductions.  For measurement; the events add a
+ *   little overhead between kernels. */
+int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
+                      double* diag_out, void* ws, size_t ws_bytes, chx_stream s,
+                      double* phase_ms, int* phase_launches);
+
+/* ch_diagnostics: mass = dx dy sum c and discrete free energy
+ *   F = dx dy sum[(c^2-1)^2/4 + gamma/2 ((D+x c)^2 + (D+y c)^2)] of the field c
+ *   (device), by a fixed-order reduction (bitwise repeatable).  Synchronises
+ *   stream s; writes the host doubles *mass and *energy.  Returns
+ *   CHX_ENONFINITE if either is NaN or infinite. */
+int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
+                   double* energy, chx_stream s);
+
+/* ------------------------------------------------------------------------
+ * Host-side plan inspection (no device work; usable without a GPU).  They
+ * return the tables that penta_factor / tri_factor compute and upload, so the
+ * host factorisation can be checked on a CPU.  P = 2 (coef = a,b,c,d,e) or
+ * P = 1 (coef = a,b,c); the matrix is cyclic.
+ *
+ * chx_host_chunk_tables: tables for chunks of m unknowns (n % m == 0,
+ *   m >= 3P): per interior position p < m-P, 8 values {1/alpha, L(p,p-1),
+ *   R(p,p+1), R(p,p+2), Zl_0, Zl_1, Zr_0, Zr_1} (rec, capacity rec_cap
+ *   doubles); reduced-system blocks B_d, d = dlo..dlo+dcount-1, as 2x2
+ *   row-major (blocks, capacity blocks_cap doubles); info[0..3] = {m-P, n/m,
+ *   dlo, dcount}.  Arrays that are NULL or too small are skipped.
+ * chx_host_whole_tables: bordering tables of the whole system: per position
+ *   i < mi, {1/alpha, L(i,i-1), R(i,i+1), R(i,i+2), q_0, q_1, Z_0, Z_1}; minv =
+ *   [C22 - h^T E^{-1} k]^{-1} (2x2, row-major); *mi_out = n-P (periodic) or n.
+ */
+int chx_host_chunk_tables(int P, const double* coef, int n, int m, double* rec,
+                          int rec_cap, double* blocks, int blocks_cap, int* info);
+int chx_host_whole_tables(int P, const double* coef, int n, int periodic,
+                          double* rec, int rec_cap, double* minv, int* mi_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

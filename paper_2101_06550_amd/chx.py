@@ -1,0 +1,368 @@
+"""Thin ctypes binding of ``libchx.so`` (the C-ABI in ``include/chx.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C-ABI.  PyTorch provides device memory (tensors) and
+streams; functions accept CUDA/HIP ``torch.Tensor`` objects (float64) and use
+the current torch stream unless one is given.  There is no CPU fallback: if
+the library is missing, loading raises ``ChxError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("CHX_LIBRARY", os.path.join(HERE, "libchx.so"))
+
+CHX_OK = 0
+CHX_EINVAL = -1
+CHX_EUNSUPPORTED_N = -2
+CHX_EPIVOT = -3
+CHX_EHIP = -4
+CHX_ENONFINITE = -5
+CHX_ENOMEM = -6
+CHX_EREFINE = -7
+
+CHX_F64 = 0
+CHX_F32_REFINED = 1
+CHX_INTERLEAVED = 0
+CHX_CONTIGUOUS = 1
+
+# Every symbol that include/chx.h declares.
+EXPORTED = [
+    "chx_version", "chx_status_string",
+    "penta_factor", "penta_plan_destroy", "penta_solve_ws_bytes", "penta_solve_batch",
+    "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
+    "stencil2d_apply",
+    "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_timed",
+    "ch_diagnostics",
+    "chx_host_chunk_tables", "chx_host_whole_tables",
+]
+
+
+class ChxError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _status_string(status) if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+
+
+class ChParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("D", ctypes.c_double), ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("dtype", ctypes.c_int), ("refine_passes", ctypes.c_int)]
+
+
+_lib = None
+_V = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_long
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+def load(path: str | None = None):
+    """Load libchx.so (raises ChxError(CHX_EHIP) if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ChxError(CHX_EHIP, f"HIP library not built ({p}); run "
+                       "python -m paper_2101_06550_amd.csrc.build")
+    lib = ctypes.CDLL(p)
+    sig = {
+        "chx_version": (_I, []),
+        "chx_status_string": (ctypes.c_char_p, [_I]),
+        "penta_factor": (_I, [_I, _D, _D, _D, _D, _D, _I, ctypes.POINTER(_V)]),
+        "penta_plan_destroy": (_I, [_V]),
+        "penta_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
+        "penta_solve_batch": (_I, [_V, _I, _V, _L, _I, _I, _I, _V, _S, _V]),
+        "tri_factor": (_I, [_I, _D, _D, _D, _I, ctypes.POINTER(_V)]),
+        "tri_plan_destroy": (_I, [_V]),
+        "tri_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
+        "tri_solve_batch": (_I, [_V, _I, _V, _L, _I, _I, _I, _V, _S, _V]),
+        "stencil2d_apply": (_I, [_V, _V, _I, _I, _L, _DP, _I, _I, _I, _I, _I, _I, _V]),
+        "ch_create": (_I, [ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
+        "ch_destroy": (_I, [_V]),
+        "ch_ws_bytes": (_S, [_V]),
+        "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
+        "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
+        "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
+        "chx_host_chunk_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _I, _IP]),
+        "chx_host_whole_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _IP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _status_string(st: int) -> str:
+    return _lib.chx_status_string(st).decode()
+
+
+def _check(st: int, what: str):
+    if st != CHX_OK:
+        raise ChxError(st, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _devptr(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ChxError(CHX_EINVAL, f"{what} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ChxError(CHX_EINVAL, f"{what} must be float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, ws, device):
+    import torch
+    if nbytes == 0:
+        return None, ctypes.c_void_p(0), 0
+    if ws is None:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = ws.data_ptr()
+    aligned = (base + 255) & ~255
+    avail = ws.numel() * ws.element_size() - (aligned - base)
+    return ws, ctypes.c_void_p(aligned), avail
+
+
+# ----------------------------------------------------------------------- version
+def chx_version() -> int:
+    return load().chx_version()
+
+
+def chx_status_string(status: int) -> str:
+    return load().chx_status_string(status).decode()
+
+
+# ------------------------------------------------------------------------- plans
+class _Plan:
+    _destroy = None
+
+    def __init__(self, handle, n, P, periodic):
+        self.handle = handle
+        self.n = n
+        self.P = P
+        self.periodic = periodic
+
+    def close(self):
+        if self.handle:
+            getattr(load(), self._destroy)(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PentaPlan(_Plan):
+    _destroy = "penta_plan_destroy"
+
+
+class TriPlan(_Plan):
+    _destroy = "tri_plan_destroy"
+
+
+def penta_factor(n: int, a: float, b: float, c: float, d: float, e: float,
+                 periodic: bool = True) -> PentaPlan:
+    h = ctypes.c_void_p()
+    _check(load().penta_factor(n, a, b, c, d, e, int(bool(periodic)), ctypes.byref(h)),
+           "penta_factor")
+    return PentaPlan(h, n, 2, periodic)
+
+
+def penta_plan_destroy(plan: PentaPlan) -> None:
+    plan.close()
+
+
+def tri_factor(n: int, a: float, b: float, c: float, periodic: bool = True) -> TriPlan:
+    h = ctypes.c_void_p()
+    _check(load().tri_factor(n, a, b, c, int(bool(periodic)), ctypes.byref(h)), "tri_factor")
+    return TriPlan(h, n, 1, periodic)
+
+
+def tri_plan_destroy(plan: TriPlan) -> None:
+    plan.close()
+
+
+def penta_solve_ws_bytes(plan, batch, layout=CHX_INTERLEAVED, dtype=CHX_F64, refine_passes=0):
+    return load().penta_solve_ws_bytes(plan.handle, batch, layout, dtype, refine_passes)
+
+
+def tri_solve_ws_bytes(plan, batch, layout=CHX_INTERLEAVED, dtype=CHX_F64, refine_passes=0):
+    return load().tri_solve_ws_bytes(plan.handle, batch, layout, dtype, refine_passes)
+
+
+def _solve(kind, plan, batch, x, ld, layout, dtype, refine_passes, ws, stream):
+    lib = load()
+    if ld is None:
+        ld = x.stride(0) if x.dim() == 2 else (batch if layout == CHX_INTERLEAVED else plan.n)
+    nbytes = getattr(lib, f"{kind}_solve_ws_bytes")(plan.handle, batch, layout, dtype,
+                                                    refine_passes)
+    keep, wsp, avail = _workspace(nbytes, ws, x.device)
+    st = getattr(lib, f"{kind}_solve_batch")(plan.handle, batch, _devptr(x, "x"), ld, layout,
+                                             dtype, refine_passes, wsp, avail, _stream(stream))
+    _check(st, f"{kind}_solve_batch")
+    return keep
+
+
+def penta_solve_batch(plan: PentaPlan, batch: int, x, ld: int | None = None,
+                      layout: int = CHX_INTERLEAVED, dtype: int = CHX_F64,
+                      refine_passes: int = 0, ws=None, stream=None):
+    """Solve in place: x (float64 device tensor) holds the right-hand sides
+    and receives the solutions.  Returns the workspace tensor used (keep it
+    alive until the stream has finished if it was allocated here)."""
+    return _solve("penta", plan, batch, x, ld, layout, dtype, refine_passes, ws, stream)
+
+
+def tri_solve_batch(plan: TriPlan, batch: int, x, ld: int | None = None,
+                    layout: int = CHX_INTERLEAVED, dtype: int = CHX_F64,
+                    refine_passes: int = 0, ws=None, stream=None):
+    return _solve("tri", plan, batch, x, ld, layout, dtype, refine_passes, ws, stream)
+
+
+# ----------------------------------------------------------------------- stencil
+def stencil2d_apply(inp, out, weights, left: int, right: int, top: int, bottom: int,
+                    periodic: bool = True, premap: int = 0, ld: int | None = None,
+                    stream=None) -> None:
+    ny, nx = inp.shape
+    ld = inp.stride(0) if ld is None else ld
+    w = (ctypes.c_double * len(weights))(*[float(v) for v in weights])
+    _check(load().stencil2d_apply(_devptr(inp, "in"), _devptr(out, "out"), nx, ny, ld, w,
+                                  left, right, top, bottom, int(bool(periodic)), premap,
+                                  _stream(stream)), "stencil2d_apply")
+
+
+# ----------------------------------------------------------------- Cahn-Hilliard
+class CH:
+    """Handle of ch_create (factored operators for one grid and time step)."""
+
+    def __init__(self, nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0):
+        self.params = ChParams(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes)
+        h = ctypes.c_void_p()
+        _check(load().ch_create(ctypes.byref(self.params), ctypes.byref(h)), "ch_create")
+        self.handle = h
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            load().ch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ch_create(nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0) -> CH:
+    return CH(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes)
+
+
+def ch_destroy(h: CH) -> None:
+    h.close()
+
+
+def ch_ws_bytes(h: CH) -> int:
+    return load().ch_ws_bytes(h.handle)
+
+
+def ch_adi_step(h: CH, c, nsteps: int = 1, diag_out=None, ws=None, ld: int | None = None,
+                stream=None):
+    """Advance the float64 device field c (ny, nx) by nsteps in place.  The
+    workspace is allocated on first use and cached on the handle unless
+    given.  diag_out: optional float64 device tensor of 2*(nsteps+1)."""
+    lib = load()
+    ld = c.stride(0) if ld is None else ld
+    nbytes = lib.ch_ws_bytes(h.handle)
+    if ws is None:
+        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
+            import torch
+            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
+        ws = h._ws
+    _, wsp, avail = _workspace(nbytes, ws, c.device)
+    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
+    _check(lib.ch_adi_step(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
+                           _stream(stream)), "ch_adi_step")
+
+
+def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
+                      ld: int | None = None, stream=None):
+    """ch_adi_step with per-phase HIP-event kernel timing; returns
+    (phase_ms[4], phase_launches[4]) for phases column pass, column
+    separators, row solves, finalize/diagnostics.  Synchronises."""
+    lib = load()
+    ld = c.stride(0) if ld is None else ld
+    nbytes = lib.ch_ws_bytes(h.handle)
+    if ws is None:
+        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
+            import torch
+            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
+        ws = h._ws
+    _, wsp, avail = _workspace(nbytes, ws, c.device)
+    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int * 4)()
+    _check(lib.ch_adi_step_timed(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
+                                 _stream(stream), ms, cnt), "ch_adi_step_timed")
+    return list(ms), list(cnt)
+
+
+def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):
+    """(mass, free energy) of the device field c; synchronises the stream."""
+    ld = c.stride(0) if ld is None else ld
+    m, e = ctypes.c_double(), ctypes.c_double()
+    st = load().ch_diagnostics(h.handle, _devptr(c, "c"), ld, ctypes.byref(m), ctypes.byref(e),
+                               _stream(stream))
+    if st not in (CHX_OK, CHX_ENONFINITE):
+        _check(st, "ch_diagnostics")
+    return m.value, e.value, st
+
+
+# ------------------------------------------------------------- host inspection
+def chx_host_chunk_tables(P: int, coef, n: int, m: int):
+    """Host-only: (rec[mi,8], blocks[dcount,2,2], dlo) of the chunk tables."""
+    import numpy as np
+    lib = load()
+    cf = (ctypes.c_double * 5)(*[float(v) for v in coef])
+    info = (ctypes.c_int * 4)()
+    _check(lib.chx_host_chunk_tables(P, cf, n, m, None, 0, None, 0, info), "chunk tables")
+    mi, S, dlo, dcount = list(info)
+    rec = np.zeros(mi * 8)
+    blocks = np.zeros(dcount * 4)
+    _check(lib.chx_host_chunk_tables(P, cf, n, m, rec.ctypes.data_as(_DP), rec.size,
+                                     blocks.ctypes.data_as(_DP), blocks.size, info),
+           "chunk tables")
+    return rec.reshape(mi, 8), blocks.reshape(dcount, 2, 2), dlo
+
+
+def chx_host_whole_tables(P: int, coef, n: int, periodic: bool = True):
+    import numpy as np
+    lib = load()
+    cf = (ctypes.c_double * 5)(*[float(v) for v in coef])
+    mi = ctypes.c_int()
+    _check(lib.chx_host_whole_tables(P, cf, n, int(periodic), None, 0, None, ctypes.byref(mi)),
+           "whole tables")
+    rec = np.zeros(mi.value * 8)
+    minv = np.zeros(4)
+    _check(lib.chx_host_whole_tables(P, cf, n, int(periodic), rec.ctypes.data_as(_DP), rec.size,
+                                     minv.ctypes.data_as(_DP), ctypes.byref(mi)), "whole tables")
+    return rec.reshape(mi.value, 8), minv.reshape(2, 2)

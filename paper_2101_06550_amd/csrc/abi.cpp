@@ -1,0 +1,546 @@
+// abi.cpp -- the extern "C" boundary declared in include/chx.h: argument
+// checks, plan construction and upload, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ch_launch.hpp"
+#include "chx.h"
+#include "common.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+using namespace chx;
+
+namespace {
+
+// A factored constant-coefficient band matrix and its device tables.
+struct BandPlan {
+  int P = 2, n = 0, periodic = 1;
+  double coef[5] = {};
+  WholeTables whole;
+  ChunkTables chunk;
+  bool has_chunk = false;
+  DevWhole dwhole;
+  DevChunk dchunk;
+  void* dmem = nullptr;
+  int device = 0;
+
+  ~BandPlan() {
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int upload(BandPlan* p) {
+  size_t off = 0;
+  const size_t o_w = off; off = align256(off + p->whole.rec.size() * sizeof(double));
+  const size_t o_w32 = off; off = align256(off + p->whole.rec32.size() * sizeof(float));
+  const size_t o_c = off; off = align256(off + p->chunk.rec.size() * sizeof(double));
+  const size_t o_c32 = off; off = align256(off + p->chunk.rec32.size() * sizeof(float));
+  const size_t o_b = off; off = align256(off + p->chunk.blocks.size() * sizeof(double));
+  const size_t o_b32 = off; off = align256(off + p->chunk.blocks32.size() * sizeof(float));
+  if (hipGetDevice(&p->device) != hipSuccess) return CHX_EHIP;
+  if (hipMalloc(&p->dmem, off > 0 ? off : 256) != hipSuccess) {
+    p->dmem = nullptr;
+    return CHX_EHIP;
+  }
+  std::vector<unsigned char> host(off > 0 ? off : 256, 0);
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + o, src, bytes);
+  };
+  put(o_w, p->whole.rec.data(), p->whole.rec.size() * sizeof(double));
+  put(o_w32, p->whole.rec32.data(), p->whole.rec32.size() * sizeof(float));
+  put(o_c, p->chunk.rec.data(), p->chunk.rec.size() * sizeof(double));
+  put(o_c32, p->chunk.rec32.data(), p->chunk.rec32.size() * sizeof(float));
+  put(o_b, p->chunk.blocks.data(), p->chunk.blocks.size() * sizeof(double));
+  put(o_b32, p->chunk.blocks32.data(), p->chunk.blocks32.size() * sizeof(float));
+  if (hipMemcpy(p->dmem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return CHX_EHIP;
+  auto* base = static_cast<unsigned char*>(p->dmem);
+  p->dwhole.n = p->n;
+  p->dwhole.P = p->P;
+  p->dwhole.periodic = p->periodic;
+  for (int k = 0; k < 5; ++k) p->dwhole.coef[k] = p->coef[k];
+  for (int k = 0; k < 4; ++k) p->dwhole.minv[k] = p->whole.minv[k];
+  p->dwhole.rec = reinterpret_cast<const double*>(base + o_w);
+  p->dwhole.rec32 = reinterpret_cast<const float*>(base + o_w32);
+  if (p->has_chunk) {
+    p->dchunk.n = p->n;
+    p->dchunk.P = p->P;
+    p->dchunk.S = p->chunk.S;
+    p->dchunk.dlo = p->chunk.dlo;
+    p->dchunk.dcount = p->chunk.dcount;
+    for (int k = 0; k < 5; ++k) p->dchunk.coef[k] = p->coef[k];
+    p->dchunk.rec = reinterpret_cast<const double*>(base + o_c);
+    p->dchunk.rec32 = reinterpret_cast<const float*>(base + o_c32);
+    p->dchunk.blocks = reinterpret_cast<const double*>(base + o_b);
+    p->dchunk.blocks32 = reinterpret_cast<const float*>(base + o_b32);
+  }
+  return CHX_OK;
+}
+
+bool finite_all(const double* v, int n) {
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(v[k])) return false;
+  return true;
+}
+
+// Build (host) and upload (device) a band plan.
+template <class PlanT>
+int make_plan(int P, int n, const double* coef, int periodic, PlanT** out) {
+  if (!out) return CHX_EINVAL;
+  *out = nullptr;
+  const int nmin = (P == 2) ? 5 : 3;
+  if (n < nmin) return CHX_EUNSUPPORTED_N;
+  if (!finite_all(coef, 2 * P + 1)) return CHX_EINVAL;
+  PlanT* p = new (std::nothrow) PlanT();
+  if (!p) return CHX_ENOMEM;
+  p->P = P;
+  p->n = n;
+  p->periodic = periodic ? 1 : 0;
+  for (int k = 0; k < 2 * P + 1; ++k) p->coef[k] = coef[k];
+  Band band;
+  band.P = P;
+  band.periodic = p->periodic != 0;
+  for (int k = 0; k < 2 * P + 1; ++k) band.coef[k] = coef[k];
+  int rc = build_whole(band, n, &p->whole);
+  if (rc == CHX_OK && p->periodic && n % kChunk == 0) {
+    rc = build_chunk(band, n, kChunk, &p->chunk);
+    p->has_chunk = (rc == CHX_OK);
+    if (rc == CHX_EINVAL) rc = CHX_OK;  // shape not eligible: keep the whole-system path
+  }
+  if (rc == CHX_OK) rc = upload(p);
+  if (rc != CHX_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return CHX_OK;
+}
+
+size_t solve_ws(const BandPlan* p, int batch, int layout, int dtype) {
+  (void)dtype;
+  if (!p || batch <= 0) return 0;
+  if (layout == CHX_INTERLEAVED && p->has_chunk)
+    return align256((size_t)p->chunk.S * 2 * p->P * (size_t)batch * sizeof(double));
+  return 0;
+}
+
+int solve(const BandPlan* p, int batch, void* x, long ld, int layout, int dtype, int refine,
+          void* ws, size_t ws_bytes, chx_stream s) {
+  if (!p) return CHX_EINVAL;
+  if (batch < 0) return CHX_EINVAL;
+  if (batch == 0) return CHX_OK;
+  if (!x) return CHX_EINVAL;
+  if (layout != CHX_INTERLEAVED && layout != CHX_CONTIGUOUS) return CHX_EINVAL;
+  if (dtype != CHX_F64) {
+    (void)refine;
+    return CHX_EINVAL;  // the FP32-refined solve is not available in this build
+  }
+  if (layout == CHX_INTERLEAVED && ld < batch) return CHX_EINVAL;
+  if (layout == CHX_CONTIGUOUS && ld < p->n) return CHX_EINVAL;
+  const size_t need = solve_ws(p, batch, layout, dtype);
+  if (need > 0 && (!ws || ws_bytes < need)) return CHX_ENOMEM;
+  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255)) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  double* xd = static_cast<double*>(x);
+  hipError_t e = hipSuccess;
+  if (layout == CHX_INTERLEAVED) {
+    if (p->has_chunk) {
+      e = (p->P == 2) ? launch_chunked_il<2>(p->dchunk, xd, ld, batch, static_cast<double*>(ws), st)
+                      : launch_chunked_il<1>(p->dchunk, xd, ld, batch, static_cast<double*>(ws), st);
+    } else {
+      e = (p->P == 2) ? launch_whole<2>(p->dwhole, xd, 1, ld, batch, st)
+                      : launch_whole<1>(p->dwhole, xd, 1, ld, batch, st);
+    }
+  } else {
+    if (p->has_chunk && p->chunk.S <= 256) {
+      e = (p->P == 2) ? launch_rows_lds<2>(p->dchunk, xd, ld, batch, st)
+                      : launch_rows_lds<1>(p->dchunk, xd, ld, batch, st);
+    } else {
+      e = (p->P == 2) ? launch_whole<2>(p->dwhole, xd, ld, 1, batch, st)
+                      : launch_whole<1>(p->dwhole, xd, ld, 1, batch, st);
+    }
+  }
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
+}  // namespace
+
+struct chx_penta_plan_s : BandPlan {};
+struct chx_tri_plan_s : BandPlan {};
+
+// ---------------------------------------------------------------------------
+// Cahn-Hilliard handle
+struct chx_ch_s {
+  chx_ch_params prm{};
+  BandPlan* px = nullptr;  // rows: length nx, sigma_x
+  BandPlan* py = nullptr;  // columns: length ny, sigma_y
+  bool fast = false;
+  ChCoef K{};
+  size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
+  long part_count = 0;
+  double* dscratch = nullptr;  // ch_diagnostics: partials + 2 outputs
+  long dscratch_parts = 0;
+  ~chx_ch_s() {
+    delete px;
+    delete py;
+    if (dscratch) (void)hipFree(dscratch);
+  }
+};
+
+extern "C" {
+
+int chx_version(void) { return 100; }
+
+const char* chx_status_string(int status) {
+  switch (status) {
+    case CHX_OK: return "ok";
+    case CHX_EINVAL: return "invalid argument";
+    case CHX_EUNSUPPORTED_N: return "system size below the minimum";
+    case CHX_EPIVOT: return "zero, negative or non-finite pivot";
+    case CHX_EHIP: return "HIP runtime or launch failure";
+    case CHX_ENONFINITE: return "non-finite diagnostic";
+    case CHX_ENOMEM: return "workspace too small or allocation failed";
+    case CHX_EREFINE: return "iterative refinement did not converge";
+    default: return "unknown status";
+  }
+}
+
+int penta_factor(int n, double a, double b, double c, double d, double e, int periodic,
+                 chx_penta_plan* out) {
+  if (!out) return CHX_EINVAL;
+  const double coef[5] = {a, b, c, d, e};
+  return make_plan(2, n, coef, periodic, out);
+}
+
+int penta_plan_destroy(chx_penta_plan p) {
+  delete p;
+  return CHX_OK;
+}
+
+size_t penta_solve_ws_bytes(chx_penta_plan p, int batch, int layout, int dtype,
+                            int refine_passes) {
+  (void)refine_passes;
+  return solve_ws(p, batch, layout, dtype);
+}
+
+int penta_solve_batch(chx_penta_plan p, int batch, void* x_inout, long ld, int layout, int dtype,
+                      int refine_passes, void* ws, size_t ws_bytes, chx_stream s) {
+  if (p && p->P != 2) return CHX_EINVAL;
+  return solve(p, batch, x_inout, ld, layout, dtype, refine_passes, ws, ws_bytes, s);
+}
+
+int tri_factor(int n, double a, double b, double c, int periodic, chx_tri_plan* out) {
+  if (!out) return CHX_EINVAL;
+  const double coef[3] = {a, b, c};
+  return make_plan(1, n, coef, periodic, out);
+}
+
+int tri_plan_destroy(chx_tri_plan p) {
+  delete p;
+  return CHX_OK;
+}
+
+size_t tri_solve_ws_bytes(chx_tri_plan p, int batch, int layout, int dtype, int refine_passes) {
+  (void)refine_passes;
+  return solve_ws(p, batch, layout, dtype);
+}
+
+int tri_solve_batch(chx_tri_plan p, int batch, void* x_inout, long ld, int layout, int dtype,
+                    int refine_passes, void* ws, size_t ws_bytes, chx_stream s) {
+  if (p && p->P != 1) return CHX_EINVAL;
+  return solve(p, batch, x_inout, ld, layout, dtype, refine_passes, ws, ws_bytes, s);
+}
+
+int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
+                    const double* weights, int left, int right, int top, int bottom, int periodic,
+                    int premap, chx_stream s) {
+  if (!in || !out || !weights) return CHX_EINVAL;
+  if (nx < 1 || ny < 1 || ld < nx) return CHX_EINVAL;
+  if (left < 0 || right < 0 || top < 0 || bottom < 0) return CHX_EINVAL;
+  if (left > 4 || right > 4 || top > 4 || bottom > 4) return CHX_EINVAL;
+  if (premap != 0 && premap != 1) return CHX_EINVAL;
+  const char* a0 = reinterpret_cast<const char*>(in);
+  const char* b0 = reinterpret_cast<const char*>(out);
+  const size_t span = ((size_t)(ny - 1) * ld + nx) * sizeof(double);
+  if (a0 < b0 + span && b0 < a0 + span) return CHX_EINVAL;  // buffers overlap
+  const int nw = (left + right + 1) * (top + bottom + 1);
+  if (!finite_all(weights, nw)) return CHX_EINVAL;
+  hipError_t e = launch_stencil2d(in, out, nx, ny, ld, weights, left, right, top, bottom,
+                                  periodic ? 1 : 0, premap, static_cast<hipStream_t>(s));
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
+int ch_create(const chx_ch_params* prm, chx_ch* out) {
+  if (!prm || !out) return CHX_EINVAL;
+  *out = nullptr;
+  const chx_ch_params& q = *prm;
+  if (q.nx < 5 || q.ny < 5) return CHX_EUNSUPPORTED_N;
+  if (!(q.lx > 0) || !(q.ly > 0) || !(q.dt > 0) || !(q.D >= 0) || !(q.gamma >= 0) ||
+      !std::isfinite(q.lx) || !std::isfinite(q.ly) || !std::isfinite(q.dt) ||
+      !std::isfinite(q.D) || !std::isfinite(q.gamma))
+    return CHX_EINVAL;
+  if (q.dtype != CHX_F64) return CHX_EINVAL;  // FP32-refined stepping not available yet
+  chx_ch_s* h = new (std::nothrow) chx_ch_s();
+  if (!h) return CHX_ENOMEM;
+  h->prm = q;
+  const double dx = q.lx / q.nx, dy = q.ly / q.ny;
+  const double sx = q.D * q.gamma * q.dt / (dx * dx * dx * dx);
+  const double sy = q.D * q.gamma * q.dt / (dy * dy * dy * dy);
+  const double cxs[5] = {sx, -4 * sx, 1 + 6 * sx, -4 * sx, sx};
+  const double cys[5] = {sy, -4 * sy, 1 + 6 * sy, -4 * sy, sy};
+  int rc = make_plan(2, q.nx, cxs, 1, &h->px);
+  if (rc == CHX_OK) rc = make_plan(2, q.ny, cys, 1, &h->py);
+  if (rc != CHX_OK) {
+    delete h;
+    return rc;
+  }
+  h->K.cx = q.D * q.dt / (dx * dx);
+  h->K.cy = q.D * q.dt / (dy * dy);
+  h->K.ccross = 2.0 * q.D * q.gamma * q.dt / (dx * dx * dy * dy);
+  h->K.inv_dx = 1.0 / dx;
+  h->K.inv_dy = 1.0 / dy;
+  h->K.half_gamma = 0.5 * q.gamma;
+  h->K.dxdy = dx * dy;
+  h->fast = (q.nx % 64 == 0) && (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
+            h->px->chunk.S <= 256;
+  const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
+  const long diag_parts = ch_diag_partial_blocks(q.nx, q.ny);
+  size_t off = 0;
+  if (h->fast) {
+    h->off_b0 = off; off += field;
+    h->off_b1 = off; off += field;
+    h->off_rho = off;
+    off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(double));
+    h->part_count = std::max(ch_column_pass_blocks(q.nx, h->py->chunk.S), diag_parts);
+  } else {
+    h->off_r = off; off += field;
+    h->part_count = diag_parts;
+  }
+  h->off_part = off;
+  off += align256((size_t)h->part_count * 2 * sizeof(double));
+  h->ws_total = off;
+  h->dscratch_parts = diag_parts;
+  if (hipMalloc(&h->dscratch, (size_t)(diag_parts * 2 + 2) * sizeof(double)) != hipSuccess) {
+    h->dscratch = nullptr;
+    delete h;
+    return CHX_EHIP;
+  }
+  *out = h;
+  return CHX_OK;
+}
+
+int ch_destroy(chx_ch h) {
+  delete h;
+  return CHX_OK;
+}
+
+size_t ch_ws_bytes(chx_ch h) { return h ? h->ws_total : 0; }
+
+// Per-phase event timing of ch_adi_step (phase 0 column pass, 1 column
+// separators, 2 row pass, 3 finalize + diagnostics reductions).
+struct PhaseTimer {
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  bool failed = false;
+  void begin() {
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) { failed = true; return; }
+    ev.push_back(a);
+    if (hipEventRecord(a, st) != hipSuccess) failed = true;
+  }
+  void end(int ph) {
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) { failed = true; return; }
+    ev.push_back(b);
+    phase.push_back(ph);
+    if (hipEventRecord(b, st) != hipSuccess) failed = true;
+  }
+  ~PhaseTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
+                     size_t ws_bytes, hipStream_t st, PhaseTimer* tm) {
+  if (!h || !c) return CHX_EINVAL;
+  const int nx = h->prm.nx, ny = h->prm.ny;
+  if (ld < nx || nsteps < 1) return CHX_EINVAL;
+  if (!ws || ws_bytes < h->ws_total) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  auto* base = static_cast<unsigned char*>(ws);
+  double* part = reinterpret_cast<double*>(base + h->off_part);
+  hipError_t e = hipSuccess;
+  auto ok = [&]() { return e == hipSuccess; };
+  auto B = [&]() { if (tm) tm->begin(); };
+  auto E = [&](int ph) { if (tm) tm->end(ph); };
+  if (h->fast) {
+    double* buf[2] = {reinterpret_cast<double*>(base + h->off_b0),
+                      reinterpret_cast<double*>(base + h->off_b1)};
+    double* rho = reinterpret_cast<double*>(base + h->off_rho);
+    const double* src = c;
+    long lds = ld;
+    bool recon = false;
+    const long colblocks = ch_column_pass_blocks(nx, h->py->chunk.S);
+    for (int n = 0; n < nsteps && ok(); ++n) {
+      double* dst = buf[n & 1];
+      const bool diag = diag_out != nullptr;
+      B();
+      e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho, h->K,
+                                part, st);
+      E(0);
+      if (ok() && diag) {
+        B();
+        e = launch_ch_diag_final(part, colblocks, h->K.dxdy, diag_out + 2 * n, st);
+        E(3);
+      }
+      if (ok()) {
+        B();
+        e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st);
+        E(1);
+      }
+      if (ok()) {
+        B();
+        e = launch_rows_lds<2>(h->px->dchunk, dst, nx, ny, st);
+        E(2);
+      }
+      src = dst;
+      lds = nx;
+      recon = true;
+    }
+    if (ok()) {
+      B();
+      e = launch_ch_finalize(src, lds, c, ld, nx, ny, h->py->dchunk, st);
+      E(3);
+    }
+  } else {
+    double* r = reinterpret_cast<double*>(base + h->off_r);
+    for (int n = 0; n < nsteps && ok(); ++n) {
+      if (diag_out) {
+        B();
+        e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
+        E(3);
+      }
+      if (ok()) {
+        B();
+        e = launch_ch_rhs_plain(c, ld, r, nx, nx, ny, h->K, st);
+        E(0);
+      }
+      if (ok()) {
+        B();
+        e = launch_whole<2>(h->py->dwhole, r, 1, nx, nx, st);
+        E(0);
+      }
+      if (ok()) {
+        B();
+        e = launch_whole<2>(h->px->dwhole, r, nx, 1, ny, st);
+        E(2);
+      }
+      if (ok()) {
+        B();
+        e = hipMemcpy2DAsync(c, ld * sizeof(double), r, nx * sizeof(double), nx * sizeof(double),
+                             ny, hipMemcpyDeviceToDevice, st);
+        E(3);
+      }
+    }
+  }
+  if (ok() && diag_out) {
+    B();
+    e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
+    E(3);
+  }
+  if (tm && tm->failed) return CHX_EHIP;
+  return ok() ? CHX_OK : CHX_EHIP;
+}
+
+int ch_adi_step(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
+                size_t ws_bytes, chx_stream s) {
+  return run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, static_cast<hipStream_t>(s),
+                   nullptr);
+}
+
+int ch_adi_step_timed(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
+                      size_t ws_bytes, chx_stream s, double* phase_ms, int* phase_launches) {
+  if (!phase_ms || !phase_launches) return CHX_EINVAL;
+  PhaseTimer tm;
+  tm.st = static_cast<hipStream_t>(s);
+  int rc = run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, tm.st, &tm);
+  if (rc) return rc;
+  if (hipStreamSynchronize(tm.st) != hipSuccess) return CHX_EHIP;
+  for (int k = 0; k < 4; ++k) {
+    phase_ms[k] = 0.0;
+    phase_launches[k] = 0;
+  }
+  for (size_t k = 0; k < tm.phase.size(); ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, tm.ev[2 * k], tm.ev[2 * k + 1]) != hipSuccess) return CHX_EHIP;
+    phase_ms[tm.phase[k]] += ms;
+    phase_launches[tm.phase[k]] += 1;
+  }
+  return CHX_OK;
+}
+
+int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass, double* energy,
+                   chx_stream s) {
+  if (!h || !c || !mass || !energy) return CHX_EINVAL;
+  if (ld < h->prm.nx) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  double* out = h->dscratch + 2 * h->dscratch_parts;
+  hipError_t e = launch_ch_diag(c, ld, h->prm.nx, h->prm.ny, h->K, h->dscratch, out, st);
+  double host[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return CHX_EHIP;
+  *mass = host[0];
+  *energy = host[1];
+  if (!std::isfinite(host[0]) || !std::isfinite(host[1])) return CHX_ENONFINITE;
+  return CHX_OK;
+}
+
+// Host-side plan inspection (no device work): the factorisation tables that
+// penta_factor / tri_factor upload, for checking the host logic on a CPU.
+int chx_host_chunk_tables(int P, const double* coef, int n, int m, double* rec, int rec_cap,
+                          double* blocks, int blocks_cap, int* info) {
+  if ((P != 1 && P != 2) || !coef || !info) return CHX_EINVAL;
+  Band band;
+  band.P = P;
+  band.periodic = true;
+  for (int k = 0; k < 2 * P + 1; ++k) band.coef[k] = coef[k];
+  ChunkTables t;
+  int rc = build_chunk(band, n, m, &t);
+  if (rc) return rc;
+  info[0] = t.mi;
+  info[1] = t.S;
+  info[2] = t.dlo;
+  info[3] = t.dcount;
+  if (rec && rec_cap >= (int)t.rec.size()) std::memcpy(rec, t.rec.data(), t.rec.size() * 8);
+  if (blocks && blocks_cap >= (int)t.blocks.size())
+    std::memcpy(blocks, t.blocks.data(), t.blocks.size() * 8);
+  return CHX_OK;
+}
+
+int chx_host_whole_tables(int P, const double* coef, int n, int periodic, double* rec,
+                          int rec_cap, double* minv, int* mi_out) {
+  if ((P != 1 && P != 2) || !coef || !mi_out) return CHX_EINVAL;
+  Band band;
+  band.P = P;
+  band.periodic = periodic != 0;
+  for (int k = 0; k < 2 * P + 1; ++k) band.coef[k] = coef[k];
+  WholeTables t;
+  int rc = build_whole(band, n, &t);
+  if (rc) return rc;
+  *mi_out = t.mi;
+  if (rec && rec_cap >= (int)t.rec.size()) std::memcpy(rec, t.rec.data(), t.rec.size() * 8);
+  if (minv) std::memcpy(minv, t.minv, sizeof(t.minv));
+  return CHX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,351 @@
+// ch.hip -- Cahn-Hilliard ADI step kernels (thesis Ch.2 eq. 2:ch, Ch.3
+// eq. 3:ch_adi; first-order splitting with the 1D operator of Ch.6
+// eq. 6:1Dnumerical in each direction).
+//
+// One step is  r = c + D dt Lap5(c^3 - c) - 2 D gamma dt d2x d2y c,
+//              (I + sx Px)(I + sy Py) c_new = r.
+// The two factors commute, so the step runs the column (y) solves first and
+// the row (x) solves second:
+//   ch_column_pass   reads the state, forms r on the fly (rolling 3-row window
+//                    in registers, x-neighbours by DPP lane shifts), sweeps the
+//                    interior of each 32-row chunk of every column in registers,
+//                    writes the chunk-local solution y and the separator parts,
+//                    and (optionally) per-block mass / free-energy partial sums.
+//   reduced_il       (solve.hip) writes the separator unknowns into the
+//                    separator rows of the same buffer.
+//   row_solve_lds    (solve.hip) solves every row of that buffer completely.
+// The column-chunk correction x = y - Zl s_prev - Zr s_own mixes rows only and
+// the row solve mixes columns only, so the correction is applied AFTER the row
+// solve, by the next step's column pass while it reads the state (or by
+// ch_finalize after the last step).  Separator rows then hold the row-solved
+// separator values T, and the state is X(j) = V(j) - Zl T_prev - Zr T_own.
+#include <hip/hip_runtime.h>
+
+#include "ch_launch.hpp"
+#include "common.hpp"
+
+namespace chx {
+
+namespace {
+
+constexpr int M = kChunk;
+constexpr int P = 2;
+constexpr int MI = M - P;
+
+// Wave-level fixed-order butterfly sum (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block (256 threads) fixed-order sum of two values; result valid in thread 0.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wave * 2] = a;
+    sh[wave * 2 + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = sh[0] + sh[2] + sh[4] + sh[6];
+    b = sh[1] + sh[3] + sh[5] + sh[7];
+  }
+}
+
+// State value at row-position p (0..M-1) of a chunk for one column, given V
+// at that row and the separator rows (row-solved values T) of the previous
+// chunk (tp) and of the chunk itself (to).  Separator rows are the state.
+template <bool RECON>
+__device__ __forceinline__ double recon_value(double v, int p, const double* __restrict__ rec,
+                                              const double (&tp)[P], const double (&to)[P]) {
+  if (!RECON || p >= MI) return v;
+  double x = v;
+#pragma unroll
+  for (int a = 0; a < P; ++a) x = x - rec[p * 8 + 4 + a] * tp[a] - rec[p * 8 + 6 + a] * to[a];
+  return x;
+}
+
+}  // namespace
+
+template <bool RECON, bool DIAG>
+__global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
+                                                      double* __restrict__ ybuf, long ldy, int nx,
+                                                      int ny, int Sc,
+                                                      const double* __restrict__ rec,
+                                                      BandT<double> bd, double* __restrict__ rho,
+                                                      ChCoef K, double* __restrict__ part) {
+  __shared__ double red[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int seg = blockIdx.x;
+  const int kc = blockIdx.y * 4 + wave;
+  const bool live = kc < Sc;
+  const int i = seg * 64 + lane;
+  const int ie = (lane == 0) ? ((seg * 64 - 1 + nx) % nx) : ((seg * 64 + 64) % nx);
+  const bool edge = (lane == 0) || (lane == 63);
+  const int kcm = (kc - 1 + Sc) % Sc, kcp = (kc + 1) % Sc;
+
+  double msum = 0.0, esum = 0.0;
+  if (live) {
+    // separator rows (row-solved T values) of chunks kc-1, kc, kc+1
+    double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
+    double etp[P] = {0, 0}, eto[P] = {0, 0}, etn[P] = {0, 0};
+    if (RECON) {
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        tp[a] = src[((long)kcm * M + MI + a) * lds + i];
+        to[a] = src[((long)kc * M + MI + a) * lds + i];
+        tn[a] = src[((long)kcp * M + MI + a) * lds + i];
+      }
+      if (edge) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          etp[a] = src[((long)kcm * M + MI + a) * lds + ie];
+          eto[a] = src[((long)kc * M + MI + a) * lds + ie];
+          etn[a] = src[((long)kcp * M + MI + a) * lds + ie];
+        }
+      }
+    }
+    // raw rows kc*M-1 .. kc*M+M (wrapped)
+    double v[M + 2], ve[M + 2];
+    const long rowm1 = ((long)kc * M - 1 + ny) % ny;
+    const long rowp = ((long)kc * M + M) % ny;
+    v[0] = src[rowm1 * lds + i];
+#pragma unroll
+    for (int p = 0; p < M; ++p) v[p + 1] = src[((long)kc * M + p) * lds + i];
+    v[M + 1] = src[rowp * lds + i];
+    if (edge) {
+      ve[0] = src[rowm1 * lds + ie];
+#pragma unroll
+      for (int p = 0; p < M; ++p) ve[p + 1] = src[((long)kc * M + p) * lds + ie];
+      ve[M + 1] = src[rowp * lds + ie];
+    } else {
+#pragma unroll
+      for (int p = 0; p < M + 2; ++p) ve[p] = 0.0;
+    }
+    // state values with the deferred column correction applied
+    double X[M + 2];
+#pragma unroll
+    for (int q = 0; q < M + 2; ++q) {
+      double xv, xe;
+      if (q == 0) {  // last row of chunk kc-1: a separator row
+        xv = v[q];
+        xe = ve[q];
+      } else if (q == M + 1) {  // row 0 of chunk kc+1: previous = kc, own = kc+1
+        xv = recon_value<RECON>(v[q], 0, rec, to, tn);
+        xe = recon_value<RECON>(ve[q], 0, rec, eto, etn);
+      } else {
+        xv = recon_value<RECON>(v[q], q - 1, rec, tp, to);
+        xe = recon_value<RECON>(ve[q], q - 1, rec, etp, eto);
+      }
+      X[q] = xv;
+      ve[q] = xe;
+    }
+    // rolling stencil window + diagnostics
+    double f[M];
+    double xl_m, xc_m, xr_m, xl_c, xc_c, xr_c;
+    xc_m = X[0];
+    xl_m = dpp_from_left(X[0], ve[0]);
+    xr_m = dpp_from_right(X[0], ve[0]);
+    xc_c = X[1];
+    xl_c = dpp_from_left(X[1], ve[1]);
+    xr_c = dpp_from_right(X[1], ve[1]);
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      const double xc_p = X[p + 2];
+      const double xl_p = dpp_from_left(X[p + 2], ve[p + 2]);
+      const double xr_p = dpp_from_right(X[p + 2], ve[p + 2]);
+      const double mu_c = xc_c * xc_c * xc_c - xc_c;
+      const double mu_l = xl_c * xl_c * xl_c - xl_c;
+      const double mu_r = xr_c * xr_c * xr_c - xr_c;
+      const double mu_s = xc_m * xc_m * xc_m - xc_m;
+      const double mu_n = xc_p * xc_p * xc_p - xc_p;
+      const double lap = K.cx * (mu_r + mu_l - 2.0 * mu_c) + K.cy * (mu_n + mu_s - 2.0 * mu_c);
+      const double dyy_w = xl_p + xl_m - 2.0 * xl_c;
+      const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
+      const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
+      f[p] = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+      if (DIAG) {
+        const double w = xc_c * xc_c - 1.0;
+        const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
+        msum += xc_c;
+        esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
+      }
+      xl_m = xl_c; xc_m = xc_c; xr_m = xr_c;
+      xl_c = xl_p; xc_c = xc_p; xr_c = xr_p;
+    }
+    chunk_sweep<P, M, double>(f, rec, bd.c[0]);
+    double pa[P], pb[P];
+    chunk_parts<P, M, double>(f, bd, pa, pb);
+#pragma unroll
+    for (int p = 0; p < MI; ++p) ybuf[((long)kc * M + p) * ldy + i] = f[p];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
+      rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+    }
+  }
+  if (DIAG) {
+    block_sum2(msum, esum, red);
+    if (threadIdx.x == 0) {
+      const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+      part[2 * b] = msum;
+      part[2 * b + 1] = esum;
+    }
+  }
+}
+
+// State X = V - Zl T_prev - Zr T_own written out to the caller's array.
+__global__ __launch_bounds__(256) void ch_finalize(const double* __restrict__ src, long lds,
+                                                   double* __restrict__ dst, long ldd, int nx,
+                                                   int ny, int Sc,
+                                                   const double* __restrict__ rec) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= nx || j >= ny) return;
+  const int kc = j / M, p = j - kc * M;
+  double v = src[(long)j * lds + i];
+  if (p < MI) {
+    const int kcm = (kc - 1 + Sc) % Sc;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const double tp = src[((long)kcm * M + MI + a) * lds + i];
+      const double to = src[((long)kc * M + MI + a) * lds + i];
+      v = v - rec[p * 8 + 4 + a] * tp - rec[p * 8 + 6 + a] * to;
+    }
+  }
+  dst[(long)j * ldd + i] = v;
+}
+
+// Mass and free-energy partial sums of a plain field, one per block of
+// 64 columns x 16 rows (fixed order within the block).
+__global__ __launch_bounds__(256) void ch_diag_partial(const double* __restrict__ c, long ld,
+                                                       int nx, int ny, ChCoef K,
+                                                       double* __restrict__ part) {
+  __shared__ double red[8];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+  double ms = 0.0, es = 0.0;
+  if (i < nx) {
+    const int ip = (i + 1) % nx;
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u;
+      if (j >= ny) break;
+      const int jp = (j + 1) % ny;
+      const double x = c[(long)j * ld + i];
+      const double gx = (c[(long)j * ld + ip] - x) * K.inv_dx;
+      const double gy = (c[(long)jp * ld + i] - x) * K.inv_dy;
+      const double w = x * x - 1.0;
+      ms += x;
+      es += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
+    }
+  }
+  block_sum2(ms, es, red);
+  if (threadIdx.x == 0) {
+    const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = ms;
+    part[2 * b + 1] = es;
+  }
+}
+
+// Fixed-order final sum of nparts (mass, energy) pairs, scaled by dx dy.
+__global__ __launch_bounds__(256) void ch_diag_final(const double* __restrict__ part, long nparts,
+                                                     double scale, double* __restrict__ out) {
+  __shared__ double sm[256], se[256];
+  double m = 0.0, e = 0.0;
+  for (long b = threadIdx.x; b < nparts; b += 256) {
+    m += part[2 * b];
+    e += part[2 * b + 1];
+  }
+  sm[threadIdx.x] = m;
+  se[threadIdx.x] = e;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sm[threadIdx.x] += sm[threadIdx.x + h];
+      se[threadIdx.x] += se[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sm[0] * scale;
+    out[1] = se[0] * scale;
+  }
+}
+
+// Plain RHS kernel for grids the fused path does not cover.
+__global__ __launch_bounds__(256) void ch_rhs_plain(const double* __restrict__ c, long ld,
+                                                    double* __restrict__ r, long ldr, int nx,
+                                                    int ny, ChCoef K) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= nx || j >= ny) return;
+  const int im = (i - 1 + nx) % nx, ip = (i + 1) % nx;
+  const int jm = (j - 1 + ny) % ny, jp = (j + 1) % ny;
+  auto at = [&](int jj, int ii) { return c[(long)jj * ld + ii]; };
+  const double xc = at(j, i), xl = at(j, im), xr = at(j, ip), xs = at(jm, i), xn = at(jp, i);
+  const double mu_c = xc * xc * xc - xc, mu_l = xl * xl * xl - xl, mu_r = xr * xr * xr - xr;
+  const double mu_s = xs * xs * xs - xs, mu_n = xn * xn * xn - xn;
+  const double lap = K.cx * (mu_r + mu_l - 2.0 * mu_c) + K.cy * (mu_n + mu_s - 2.0 * mu_c);
+  const double dyy_w = at(jp, im) + at(jm, im) - 2.0 * xl;
+  const double dyy_c = xn + xs - 2.0 * xc;
+  const double dyy_e = at(jp, ip) + at(jm, ip) - 2.0 * xr;
+  r[(long)j * ldr + i] = xc + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
+                                 double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
+                                 double* rho, const ChCoef& K, double* part, hipStream_t st) {
+  BandT<double> bd;
+  for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
+  dim3 grid(nx / 64, (cy.S + 3) / 4);
+  const int Sc = cy.S;
+#define CHX_COLPASS(R, D)                                                                      \
+  hipLaunchKernelGGL((ch_column_pass<R, D>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
+                     ny, Sc, cy.rec, bd, rho, K, part)
+  if (recon && diag) CHX_COLPASS(true, true);
+  else if (recon) CHX_COLPASS(true, false);
+  else if (diag) CHX_COLPASS(false, true);
+  else CHX_COLPASS(false, false);
+#undef CHX_COLPASS
+  return hipGetLastError();
+}
+
+long ch_column_pass_blocks(int nx, int Sc) { return (long)(nx / 64) * ((Sc + 3) / 4); }
+
+hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
+                              const DevChunk& cy, hipStream_t st) {
+  dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(ch_finalize, grid, dim3(256), 0, st, src, lds, dst, ldd, nx, ny, cy.S,
+                     cy.rec);
+  return hipGetLastError();
+}
+
+long ch_diag_partial_blocks(int nx, int ny) { return (long)((nx + 63) / 64) * ((ny + 15) / 16); }
+
+hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef& K, double* part,
+                          double* out, hipStream_t st) {
+  dim3 grid((nx + 63) / 64, (ny + 15) / 16);
+  hipLaunchKernelGGL(ch_diag_partial, grid, dim3(256), 0, st, c, ld, nx, ny, K, part);
+  hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part,
+                     (long)grid.x * grid.y, K.dxdy, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, nparts, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, int nx, int ny,
+                               const ChCoef& K, hipStream_t st) {
+  dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(ch_rhs_plain, grid, dim3(256), 0, st, c, ld, r, ldr, nx, ny, K);
+  return hipGetLastError();
+}
+
+}  // namespace chx

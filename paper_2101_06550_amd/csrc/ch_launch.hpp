@@ -1,0 +1,33 @@
+// ch_launch.hpp -- Cahn-Hilliard kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+
+namespace chx {
+
+// Scalar coefficients of the explicit right-hand side and the diagnostics.
+struct ChCoef {
+  double cx, cy;        // D dt / dx^2, D dt / dy^2
+  double ccross;        // 2 D gamma dt / (dx^2 dy^2)
+  double inv_dx, inv_dy;
+  double half_gamma;    // gamma / 2
+  double dxdy;          // cell area (mass and energy scale)
+};
+
+hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
+                                 double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
+                                 double* rho, const ChCoef& K, double* part, hipStream_t st);
+long ch_column_pass_blocks(int nx, int Sc);
+hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
+                              const DevChunk& cy, hipStream_t st);
+long ch_diag_partial_blocks(int nx, int ny);
+hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef& K, double* part,
+                          double* out, hipStream_t st);
+hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
+                                hipStream_t st);
+hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, int nx, int ny,
+                               const ChCoef& K, hipStream_t st);
+
+}  // namespace chx

@@ -1,0 +1,106 @@
+// common.hpp -- small device/host helpers shared by the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chx {
+
+// Constant band coefficients handed to kernels by value: coef[o + P] is the
+// coefficient of x[i + o].
+template <typename T>
+struct BandT {
+  T c[5];
+};
+
+// Chunk length of the chunked kernels (unknowns per thread-chunk).
+constexpr int kChunk = 32;
+
+__device__ __forceinline__ int wrap_once(int j, int S) {
+  j += (j < 0) ? S : 0;
+  j -= (j >= S) ? S : 0;
+  return j;
+}
+
+// Lane l receives the value of lane l-1 (wave_shr:1); lane 0 keeps `edge`.
+__device__ __forceinline__ double dpp_from_left(double v, double edge) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  int elo = __double2loint(edge), ehi = __double2hiint(edge);
+  lo = __builtin_amdgcn_update_dpp(elo, lo, 0x138, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(ehi, hi, 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Lane l receives the value of lane l+1 (wave_shl:1); lane 63 keeps `edge`.
+__device__ __forceinline__ double dpp_from_right(double v, double edge) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  int elo = __double2loint(edge), ehi = __double2hiint(edge);
+  lo = __builtin_amdgcn_update_dpp(elo, lo, 0x130, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(ehi, hi, 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Forward + back sweep of one chunk held in registers (compile-time
+// unrolled).  On entry f[0..M) holds the chunk's right-hand side; on exit
+// f[0..M-P) holds y = E_m^{-1} f_interior and the separator values f[M-P..M)
+// are untouched.  rec: kRec values per interior position (1/alpha, L(i,i-1),
+// R(i,i+1), R(i,i+2), ...).  eps = L(i,i-2) = the band's outermost
+// sub-diagonal (P = 2 only).
+template <int P, int M, typename T>
+__device__ __forceinline__ void chunk_sweep(T (&f)[M], const T* __restrict__ rec, T eps) {
+  constexpr int MI = M - P;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) {
+    T v = f[p];
+    if (P == 2 && p >= 2) v = v - eps * f[p - 2];
+    if (p >= 1) v = v - rec[p * 8 + 1] * f[p - 1];
+    f[p] = v * rec[p * 8 + 0];
+  }
+#pragma unroll
+  for (int p = MI - 1; p >= 0; --p) {
+    T v = f[p];
+    if (P == 2 && p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
+    if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
+    f[p] = v;
+  }
+}
+
+// Separator right-hand-side parts of one chunk after its sweep:
+//   pa[a] = f_sep[a] - (coupling of separator a to this chunk's interior) y
+//   pb[a] = (coupling of the previous chunk's separator a to this interior) y
+// so that the reduced right-hand side of chunk k is pa_k - pb_{k+1}.
+template <int P, int M, typename T>
+__device__ __forceinline__ void chunk_parts(const T (&f)[M], const BandT<T>& bd, T (&pa)[P],
+                                            T (&pb)[P]) {
+  constexpr int MI = M - P;
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    T v = f[MI + a];
+#pragma unroll
+    for (int p = MI + a - P; p < MI; ++p) v = v - bd.c[(p - MI - a) + P] * f[p];
+    pa[a] = v;
+    T w = T(0);
+#pragma unroll
+    for (int q = 0; q <= a; ++q) w = w + bd.c[(q + P - a) + P] * f[q];
+    pb[a] = w;
+  }
+}
+
+// Interior correction x = y - Zl s_prev - Zr s_own (rec[4..5] = Zl, rec[6..7] = Zr),
+// separators set to s_own.
+template <int P, int M, typename T>
+__device__ __forceinline__ void chunk_correct(T (&f)[M], const T* __restrict__ rec,
+                                              const T (&sp)[P], const T (&so)[P]) {
+  constexpr int MI = M - P;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) {
+    T v = f[p];
+#pragma unroll
+    for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
+    f[p] = v;
+  }
+#pragma unroll
+  for (int a = 0; a < P; ++a) f[MI + a] = so[a];
+}
+
+}  // namespace chx

@@ -1,0 +1,43 @@
+// launch.hpp -- device-resident plan views and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace chx {
+
+// Device copy of WholeTables (one-thread-per-system kernels).
+struct DevWhole {
+  int n = 0, P = 2, periodic = 1;
+  double coef[5] = {};
+  double minv[4] = {1, 0, 0, 1};
+  const double* rec = nullptr;   // device, mi * 8
+  const float* rec32 = nullptr;  // device, mi * 8
+};
+
+// Device copy of ChunkTables (chunked kernels, chunk length kChunk).
+struct DevChunk {
+  int n = 0, P = 2, S = 0, dlo = 0, dcount = 0;
+  double coef[5] = {};
+  const double* rec = nullptr;      // device, (kChunk - P) * 8
+  const double* blocks = nullptr;   // device, dcount * 4
+  const float* rec32 = nullptr;
+  const float* blocks32 = nullptr;
+};
+
+template <int P>
+hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
+                        hipStream_t st);
+template <int P>
+hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
+                             hipStream_t st);
+template <int P>
+hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
+                             int drow_stride, int drow_off, hipStream_t st);
+template <int P>
+hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st);
+
+hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long ld,
+                            const double* w, int left, int right, int top, int bottom,
+                            int periodic, int premap, hipStream_t st);
+
+}  // namespace chx

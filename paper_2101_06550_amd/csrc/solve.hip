@@ -1,0 +1,312 @@
+// solve.hip -- batched constant-coefficient banded solves on gfx950.
+//
+// Kernels (P = half bandwidth: 2 penta, 1 tri; T = FP64 or FP32 sweeps):
+//  whole_sweep     one thread per system, any n, any strides: the thesis's
+//                  own arrangement (Ch.4 "Implementation on GPU": one thread
+//                  per system, factor once, forward + back sweep), with the
+//                  bordering of the last P unknowns fused in (q^T f gathered
+//                  in the forward sweep, Z x_tail applied in the back sweep).
+//  chunk_sweep_il  interleaved layout, one thread per (system, chunk of 32):
+//                  in-register sweep of the chunk interior, separator parts.
+//  reduced_il      separator unknowns of every chunk from the reduced
+//                  right-hand sides (block-circulant inverse, truncated).
+//  correct_il      interior correction x = y - Zl s_prev - Zr s_own.
+//  row_solve_lds   contiguous layout: whole rows staged through LDS (the
+//                  transpose of the thesis, done in LDS), chunk sweeps in
+//                  registers, reduced system and correction inside the
+//                  workgroup, coalesced store.  Two HBM accesses per unknown.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace chx {
+
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+__global__ __launch_bounds__(256) void whole_sweep(double* __restrict__ x, long ss, long es,
+                                                   int batch, int n, int periodic,
+                                                   const T* __restrict__ rec, BandT<T> bd,
+                                                   T mi00, T mi01, T mi10, T mi11) {
+  const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  double* xs = x + s * ss;
+  const int mi = periodic ? n - P : n;
+  const T eps = bd.c[0];
+  T g1 = 0, g2 = 0, q0 = 0, q1 = 0;
+  for (int i = 0; i < mi; ++i) {
+    const T f = (T)xs[(long)i * es];
+    const T* r = rec + (long)i * 8;
+    if (periodic) {
+      q0 = q0 + r[4] * f;
+      if (P == 2) q1 = q1 + r[5] * f;
+    }
+    T v = f;
+    if (P == 2) v = v - eps * g2;
+    v = v - r[1] * g1;
+    v = v * r[0];
+    xs[(long)i * es] = (double)v;
+    g2 = g1;
+    g1 = v;
+  }
+  T t0 = 0, t1 = 0;
+  if (periodic) {
+    const T r0 = (T)xs[(long)mi * es] - q0;
+    const T r1 = (P == 2) ? (T)xs[(long)(mi + 1) * es] - q1 : T(0);
+    t0 = mi00 * r0 + mi01 * r1;
+    t1 = mi10 * r0 + mi11 * r1;
+  }
+  T y1 = 0, y2 = 0;
+  for (int i = mi - 1; i >= 0; --i) {
+    const T* r = rec + (long)i * 8;
+    T v = (T)xs[(long)i * es];
+    if (P == 2) v = v - r[3] * y2;
+    v = v - r[2] * y1;
+    y2 = y1;
+    y1 = v;
+    T out = v;
+    if (periodic) {
+      out = out - r[6] * t0;
+      if (P == 2) out = out - r[7] * t1;
+    }
+    xs[(long)i * es] = (double)out;
+  }
+  if (periodic) {
+    xs[(long)mi * es] = (double)t0;
+    if (P == 2) xs[(long)(mi + 1) * es] = (double)t1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interleaved layout: element i of system s at i*ld + s.  Block = 64 systems
+// (one wave, 512-byte coalesced rows) x 4 chunks (4 waves).
+template <int P, int M, typename T>
+__global__ __launch_bounds__(256) void chunk_sweep_il(double* x, long ld, int batch, int S,
+                                                      const T* __restrict__ rec, BandT<T> bd,
+                                                      T* __restrict__ rho) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const int k = blockIdx.y * 4 + wave;
+  if (s >= batch || k >= S) return;
+  T f[M];
+  double* base = x + (long)k * M * ld + s;
+#pragma unroll
+  for (int p = 0; p < M; ++p) f[p] = (T)base[(long)p * ld];
+  chunk_sweep<P, M, T>(f, rec, bd.c[0]);
+  T pa[P], pb[P];
+  chunk_parts<P, M, T>(f, bd, pa, pb);
+#pragma unroll
+  for (int p = 0; p < M - P; ++p) base[(long)p * ld] = (double)f[p];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    rho[((long)k * 2 * P + a) * batch + s] = pa[a];
+    rho[((long)k * 2 * P + P + a) * batch + s] = pb[a];
+  }
+}
+
+// Reduced separator system: sep_k = sum_d B_d (pa_{k+d} - pb_{k+d+1}).
+// Writes separator a of chunk k to dst row (k * drow_stride + drow_off + a).
+template <int P, typename T>
+__global__ __launch_bounds__(256) void reduced_il(const T* __restrict__ rho, int batch, int S,
+                                                  const T* __restrict__ blocks, int dlo,
+                                                  int dcount, double* __restrict__ dst, long ld,
+                                                  int drow_stride, int drow_off) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const int k = blockIdx.y * 4 + wave;
+  if (s >= batch || k >= S) return;
+  T acc[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) acc[a] = 0;
+  for (int t = 0; t < dcount; ++t) {
+    const int j = wrap_once(k + dlo + t, S);
+    const int jn = wrap_once(j + 1, S);
+    T r[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+      r[a] = rho[((long)j * 2 * P + a) * batch + s] - rho[((long)jn * 2 * P + P + a) * batch + s];
+    const T* B = blocks + (long)t * 4;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+      for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * r[c];
+  }
+#pragma unroll
+  for (int a = 0; a < P; ++a)
+    dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
+}
+
+template <int P, int M, typename T>
+__global__ __launch_bounds__(256) void correct_il(double* x, long ld, int batch, int S,
+                                                  const T* __restrict__ rec) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const int k = blockIdx.y * 4 + wave;
+  if (s >= batch || k >= S) return;
+  constexpr int MI = M - P;
+  const int kp = wrap_once(k - 1, S);
+  T sp[P], so[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    sp[a] = (T)x[((long)kp * M + MI + a) * ld + s];
+    so[a] = (T)x[((long)k * M + MI + a) * ld + s];
+  }
+  double* base = x + (long)k * M * ld + s;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) {
+    T v = (T)base[(long)p * ld];
+#pragma unroll
+    for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
+    base[(long)p * ld] = (double)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contiguous layout, whole rows through LDS.  256 threads = 256 chunks of M;
+// a workgroup holds R = 256 / S rows of n = S * M unknowns.  Element
+// (row r, chunk k, position p) lives at tile[(r*S + k)*(M+1) + p]; the +1
+// pad spreads the per-thread chunks over the LDS banks.
+template <int P, int M, typename T>
+__global__ __launch_bounds__(256) void row_solve_lds(double* x, long ld, int rows, int n, int S,
+                                                     int R, int log2n, const T* __restrict__ rec,
+                                                     BandT<T> bd, const T* __restrict__ blocks,
+                                                     int dlo, int dcount) {
+  __shared__ T tile[256 * (M + 1)];
+  __shared__ T rhol[256 * 2 * P];
+  __shared__ T sepl[256 * P];
+  const int t = threadIdx.x;
+  const long row0 = (long)blockIdx.x * R;
+  const int nel = R * n;
+  // coalesced load of R rows into the padded tile
+  for (int e = t; e < nel; e += 256) {
+    const int r = (log2n >= 0) ? (e >> log2n) : (e / n);
+    const int i = e - r * n;
+    if (row0 + r < rows)
+      tile[(r * S + i / M) * (M + 1) + (i % M)] = (T)x[(row0 + r) * ld + i];
+  }
+  __syncthreads();
+  const int r = t / S, k = t - r * S;
+  const bool active = (r < R) && (row0 + r < rows);
+  T f[M];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < M; ++p) f[p] = tile[t * (M + 1) + p];
+    chunk_sweep<P, M, T>(f, rec, bd.c[0]);
+    T pa[P], pb[P];
+    chunk_parts<P, M, T>(f, bd, pa, pb);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      rhol[t * 2 * P + a] = pa[a];
+      rhol[t * 2 * P + P + a] = pb[a];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    T acc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) acc[a] = 0;
+    for (int u = 0; u < dcount; ++u) {
+      const int j = wrap_once(k + dlo + u, S);
+      const int jn = wrap_once(j + 1, S);
+      T rr[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+        rr[a] = rhol[(r * S + j) * 2 * P + a] - rhol[(r * S + jn) * 2 * P + P + a];
+      const T* B = blocks + u * 4;
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * rr[c];
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a) sepl[t * P + a] = acc[a];
+  }
+  __syncthreads();
+  if (active) {
+    const int kp = wrap_once(k - 1, S);
+    T sp[P], so[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      sp[a] = sepl[(r * S + kp) * P + a];
+      so[a] = sepl[t * P + a];
+    }
+    chunk_correct<P, M, T>(f, rec, sp, so);
+#pragma unroll
+    for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
+  }
+  __syncthreads();
+  for (int e = t; e < nel; e += 256) {
+    const int rr = (log2n >= 0) ? (e >> log2n) : (e / n);
+    const int i = e - rr * n;
+    if (row0 + rr < rows)
+      x[(row0 + rr) * ld + i] = (double)tile[(rr * S + i / M) * (M + 1) + (i % M)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+static int log2_exact(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+template <int P>
+hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
+                        hipStream_t st) {
+  BandT<double> bd;
+  for (int i = 0; i < 5; ++i) bd.c[i] = w.coef[i];
+  dim3 grid((batch + 255) / 256);
+  hipLaunchKernelGGL((whole_sweep<P, double>), grid, dim3(256), 0, st, x, ss, es, batch, w.n,
+                     w.periodic, w.rec, bd, w.minv[0], w.minv[1], w.minv[2], w.minv[3]);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
+                             hipStream_t st) {
+  BandT<double> bd;
+  for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
+  dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch,
+                     c.S, c.rec, bd, rho);
+  hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S, c.blocks,
+                     c.dlo, c.dcount, x, ld, kChunk, kChunk - P);
+  hipLaunchKernelGGL((correct_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch, c.S,
+                     c.rec);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
+                             int drow_stride, int drow_off, hipStream_t st) {
+  dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+  hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S, c.blocks,
+                     c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
+  BandT<double> bd;
+  for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
+  const int R = 256 / c.S;
+  dim3 grid((rows + R - 1) / R);
+  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, rows, c.n,
+                     c.S, R, log2_exact(c.n), c.rec, bd, c.blocks, c.dlo, c.dcount);
+  return hipGetLastError();
+}
+
+template hipError_t launch_whole<1>(const DevWhole&, double*, long, long, int, hipStream_t);
+template hipError_t launch_whole<2>(const DevWhole&, double*, long, long, int, hipStream_t);
+template hipError_t launch_chunked_il<1>(const DevChunk&, double*, long, int, double*, hipStream_t);
+template hipError_t launch_chunked_il<2>(const DevChunk&, double*, long, int, double*, hipStream_t);
+template hipError_t launch_reduced_il<1>(const DevChunk&, const double*, int, double*, long, int,
+                                        int, hipStream_t);
+template hipError_t launch_reduced_il<2>(const DevChunk&, const double*, int, double*, long, int,
+                                        int, hipStream_t);
+template hipError_t launch_rows_lds<1>(const DevChunk&, double*, long, int, hipStream_t);
+template hipError_t launch_rows_lds<2>(const DevChunk&, double*, long, int, hipStream_t);
+
+}  // namespace chx
