@@ -309,7 +309,7 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   h->K.inv_dy = 1.0 / dy;
   h->K.half_gamma = 0.5 * q.gamma;
   h->K.dxdy = dx * dy;
-  h->fast = (q.nx % 64 == 0) && (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
+  h->fast = (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
             h->px->chunk.S <= 256;
   const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
   const long diag_parts = ch_diag_partial_blocks(q.nx, q.ny);

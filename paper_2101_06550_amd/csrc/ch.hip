@@ -70,6 +70,13 @@ __device__ __forceinline__ double recon_value(double v, int p, const double* __r
 
 }  // namespace
 
+// Waves overlap by two columns: lane l of segment g works on column
+// g*62 - 1 + l (mod nx); lanes 1..62 own their column's outputs, lanes 0 and
+// 63 exist only to hand their state values to lanes 1 and 62 through the DPP
+// lane shifts, so every x-neighbour comes from a register and no lane needs an
+// extra load.  Block = 4 waves = 4 consecutive chunks of the same columns.
+constexpr int kOwn = 62;
+
 template <bool RECON, bool DIAG>
 __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
                                                       double* __restrict__ ybuf, long ldy, int nx,
@@ -79,19 +86,17 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
                                                       ChCoef K, double* __restrict__ part) {
   __shared__ double red[8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int seg = blockIdx.x;
   const int kc = blockIdx.y * 4 + wave;
   const bool live = kc < Sc;
-  const int i = seg * 64 + lane;
-  const int ie = (lane == 0) ? ((seg * 64 - 1 + nx) % nx) : ((seg * 64 + 64) % nx);
-  const bool edge = (lane == 0) || (lane == 63);
+  const int iu = blockIdx.x * kOwn - 1 + lane;  // unwrapped column
+  const int i = ((iu % nx) + nx) % nx;
+  const bool own = (lane >= 1) && (lane <= kOwn) && (iu < nx);
   const int kcm = (kc - 1 + Sc) % Sc, kcp = (kc + 1) % Sc;
 
   double msum = 0.0, esum = 0.0;
   if (live) {
-    // separator rows (row-solved T values) of chunks kc-1, kc, kc+1
+    // separator rows (row-solved values T) of chunks kc-1, kc, kc+1
     double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
-    double etp[P] = {0, 0}, eto[P] = {0, 0}, etn[P] = {0, 0};
     if (RECON) {
 #pragma unroll
       for (int a = 0; a < P; ++a) {
@@ -99,64 +104,36 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
         to[a] = src[((long)kc * M + MI + a) * lds + i];
         tn[a] = src[((long)kcp * M + MI + a) * lds + i];
       }
-      if (edge) {
-#pragma unroll
-        for (int a = 0; a < P; ++a) {
-          etp[a] = src[((long)kcm * M + MI + a) * lds + ie];
-          eto[a] = src[((long)kc * M + MI + a) * lds + ie];
-          etn[a] = src[((long)kcp * M + MI + a) * lds + ie];
-        }
-      }
     }
-    // raw rows kc*M-1 .. kc*M+M (wrapped)
-    double v[M + 2], ve[M + 2];
+    // rows kc*M-1 .. kc*M+M (wrapped), then the state with the deferred
+    // column correction applied
+    double X[M + 2];
     const long rowm1 = ((long)kc * M - 1 + ny) % ny;
     const long rowp = ((long)kc * M + M) % ny;
-    v[0] = src[rowm1 * lds + i];
+    X[0] = src[rowm1 * lds + i];
 #pragma unroll
-    for (int p = 0; p < M; ++p) v[p + 1] = src[((long)kc * M + p) * lds + i];
-    v[M + 1] = src[rowp * lds + i];
-    if (edge) {
-      ve[0] = src[rowm1 * lds + ie];
-#pragma unroll
-      for (int p = 0; p < M; ++p) ve[p + 1] = src[((long)kc * M + p) * lds + ie];
-      ve[M + 1] = src[rowp * lds + ie];
-    } else {
-#pragma unroll
-      for (int p = 0; p < M + 2; ++p) ve[p] = 0.0;
-    }
-    // state values with the deferred column correction applied
-    double X[M + 2];
-#pragma unroll
-    for (int q = 0; q < M + 2; ++q) {
-      double xv, xe;
-      if (q == 0) {  // last row of chunk kc-1: a separator row
-        xv = v[q];
-        xe = ve[q];
-      } else if (q == M + 1) {  // row 0 of chunk kc+1: previous = kc, own = kc+1
-        xv = recon_value<RECON>(v[q], 0, rec, to, tn);
-        xe = recon_value<RECON>(ve[q], 0, rec, eto, etn);
-      } else {
-        xv = recon_value<RECON>(v[q], q - 1, rec, tp, to);
-        xe = recon_value<RECON>(ve[q], q - 1, rec, etp, eto);
-      }
-      X[q] = xv;
-      ve[q] = xe;
-    }
-    // rolling stencil window + diagnostics
+    for (int p = 0; p < M; ++p) X[p + 1] = src[((long)kc * M + p) * lds + i];
+    X[M + 1] = src[rowp * lds + i];
+    X[M + 1] = recon_value<RECON>(X[M + 1], 0, rec, to, tn);
+    // Rows are processed strictly in order (scheduling barrier per row): the
+    // column's raw values stay in registers, a 3-row window of state values
+    // and x-neighbours is live, and the forward sweep of the chunk interior
+    // runs as soon as each right-hand-side value exists (g overwrites f).
     double f[M];
-    double xl_m, xc_m, xr_m, xl_c, xc_c, xr_c;
-    xc_m = X[0];
-    xl_m = dpp_from_left(X[0], ve[0]);
-    xr_m = dpp_from_right(X[0], ve[0]);
-    xc_c = X[1];
-    xl_c = dpp_from_left(X[1], ve[1]);
-    xr_c = dpp_from_right(X[1], ve[1]);
+    const double eps = bd.c[0];
+    double xl_m = dpp_from_left(X[0], X[0]), xc_m = X[0], xr_m = dpp_from_right(X[0], X[0]);
+    double xc_c = recon_value<RECON>(X[1], 0, rec, tp, to);
+    double xl_c = dpp_from_left(xc_c, xc_c), xr_c = dpp_from_right(xc_c, xc_c);
 #pragma unroll
     for (int p = 0; p < M; ++p) {
-      const double xc_p = X[p + 2];
-      const double xl_p = dpp_from_left(X[p + 2], ve[p + 2]);
-      const double xr_p = dpp_from_right(X[p + 2], ve[p + 2]);
+      // An empty volatile asm on the next row's raw value: volatile asms keep
+      // their order, and everything of row p+1 depends on this one, so no
+      // pass can compute row p+1 (and keep its neighbours live) before row p.
+      double xn = X[p + 2];
+      asm volatile("" : "+v"(xn));
+      const double xc_p = (p + 1 < M) ? recon_value<RECON>(xn, p + 1, rec, tp, to) : xn;
+      const double xl_p = dpp_from_left(xc_p, xc_p);
+      const double xr_p = dpp_from_right(xc_p, xc_p);
       const double mu_c = xc_c * xc_c * xc_c - xc_c;
       const double mu_l = xl_c * xl_c * xl_c - xl_c;
       const double mu_r = xr_c * xr_c * xr_c - xr_c;
@@ -166,25 +143,47 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
       const double dyy_w = xl_p + xl_m - 2.0 * xl_c;
       const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
       const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
-      f[p] = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+      double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
       if (DIAG) {
         const double w = xc_c * xc_c - 1.0;
         const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
         msum += xc_c;
         esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
       }
+      if (p < MI) {  // forward sweep step of the chunk interior
+        if (p >= 2) r = r - eps * f[p - 2];
+        if (p >= 1) r = r - rec[p * 8 + 1] * f[p - 1];
+        r = r * rec[p * 8 + 0];
+      }
+      // row p's results exist before row p+1 starts
+      if (DIAG) asm volatile("" : "+v"(r), "+v"(msum), "+v"(esum));
+      else asm volatile("" : "+v"(r));
+      f[p] = r;
       xl_m = xl_c; xc_m = xc_c; xr_m = xr_c;
       xl_c = xl_p; xc_c = xc_p; xr_c = xr_p;
+      __builtin_amdgcn_sched_barrier(0);
     }
-    chunk_sweep<P, M, double>(f, rec, bd.c[0]);
-    double pa[P], pb[P];
-    chunk_parts<P, M, double>(f, bd, pa, pb);
+    // back sweep of the interior (y = R^{-1} g)
 #pragma unroll
-    for (int p = 0; p < MI; ++p) ybuf[((long)kc * M + p) * ldy + i] = f[p];
+    for (int p = MI - 1; p >= 0; --p) {
+      double v = f[p];
+      if (p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
+      if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
+      f[p] = v;
+    }
+    if (!own) {
+      msum = 0.0;
+      esum = 0.0;
+    } else {
+      double pa[P], pb[P];
+      chunk_parts<P, M, double>(f, bd, pa, pb);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
-      rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+      for (int p = 0; p < MI; ++p) ybuf[((long)kc * M + p) * ldy + i] = f[p];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
+        rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+      }
     }
   }
   if (DIAG) {
@@ -251,11 +250,26 @@ __global__ __launch_bounds__(256) void ch_diag_partial(const double* __restrict_
 }
 
 // Fixed-order final sum of nparts (mass, energy) pairs, scaled by dx dy.
+// Each thread owns a contiguous slice and issues 8 independent loads per
+// round; the partial sums are then combined by a fixed tree.
 __global__ __launch_bounds__(256) void ch_diag_final(const double* __restrict__ part, long nparts,
                                                      double scale, double* __restrict__ out) {
   __shared__ double sm[256], se[256];
+  const long per = (nparts + 255) / 256;
+  const long b0 = (long)threadIdx.x * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
   double m = 0.0, e = 0.0;
-  for (long b = threadIdx.x; b < nparts; b += 256) {
+  long b = b0;
+  for (; b + 8 <= b1; b += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = reinterpret_cast<const double2*>(part)[b + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      m += v[u].x;
+      e += v[u].y;
+    }
+  }
+  for (; b < b1; ++b) {
     m += part[2 * b];
     e += part[2 * b + 1];
   }
@@ -301,7 +315,7 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
                                  double* rho, const ChCoef& K, double* part, hipStream_t st) {
   BandT<double> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
-  dim3 grid(nx / 64, (cy.S + 3) / 4);
+  dim3 grid((nx + kOwn - 1) / kOwn, (cy.S + 3) / 4);
   const int Sc = cy.S;
 #define CHX_COLPASS(R, D)                                                                      \
   hipLaunchKernelGGL((ch_column_pass<R, D>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
@@ -314,7 +328,9 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
   return hipGetLastError();
 }
 
-long ch_column_pass_blocks(int nx, int Sc) { return (long)(nx / 64) * ((Sc + 3) / 4); }
+long ch_column_pass_blocks(int nx, int Sc) {
+  return (long)((nx + kOwn - 1) / kOwn) * ((Sc + 3) / 4);
+}
 
 hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
                               const DevChunk& cy, hipStream_t st) {

@@ -176,13 +176,23 @@ __global__ __launch_bounds__(256) void row_solve_lds(double* x, long ld, int row
   __shared__ T sepl[256 * P];
   const int t = threadIdx.x;
   const long row0 = (long)blockIdx.x * R;
-  const int nel = R * n;
-  // coalesced load of R rows into the padded tile
-  for (int e = t; e < nel; e += 256) {
+  const int nel = R * n;  // <= 256 * M
+  // coalesced load of R rows: all M loads of a thread are issued before the
+  // first LDS store, so a workgroup keeps its whole tile in flight
+  double vin[M];
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    const int e = t + 256 * u;
     const int r = (log2n >= 0) ? (e >> log2n) : (e / n);
     const int i = e - r * n;
-    if (row0 + r < rows)
-      tile[(r * S + i / M) * (M + 1) + (i % M)] = (T)x[(row0 + r) * ld + i];
+    vin[u] = (e < nel && row0 + r < rows) ? x[(row0 + r) * ld + i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    const int e = t + 256 * u;
+    const int r = (log2n >= 0) ? (e >> log2n) : (e / n);
+    const int i = e - r * n;
+    if (e < nel) tile[(r * S + i / M) * (M + 1) + (i % M)] = (T)vin[u];
   }
   __syncthreads();
   const int r = t / S, k = t - r * S;
@@ -235,11 +245,59 @@ __global__ __launch_bounds__(256) void row_solve_lds(double* x, long ld, int row
     for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
   }
   __syncthreads();
-  for (int e = t; e < nel; e += 256) {
+#pragma unroll
+  for (int u = 0; u < M; ++u) {
+    const int e = t + 256 * u;
     const int rr = (log2n >= 0) ? (e >> log2n) : (e / n);
     const int i = e - rr * n;
-    if (row0 + rr < rows)
+    if (e < nel && row0 + rr < rows)
       x[(row0 + rr) * ld + i] = (double)tile[(rr * S + i / M) * (M + 1) + (i % M)];
+  }
+}
+
+// Reduced separator system with an LDS window: a block owns 64 systems and KB
+// consecutive chunks; it stages rho_j = pa_j - pb_{j+1} for the KB + dcount - 1
+// chunks its convolutions touch, then each wave sweeps its chunks from LDS.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
+                                                      const T* __restrict__ blocks, int dlo,
+                                                      int dcount, int KB, double* __restrict__ dst,
+                                                      long ld, int drow_stride, int drow_off) {
+  extern __shared__ unsigned char smraw[];
+  T* sm = reinterpret_cast<T*>(smraw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const int k0 = blockIdx.y * KB;
+  const int nwin = KB + dcount - 1;
+  const bool sv = s < batch;
+  for (int w = wave; w < nwin; w += 4) {
+    int j = (k0 + dlo + w) % S;
+    j += (j < 0) ? S : 0;
+    const int jn = (j + 1 == S) ? 0 : j + 1;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+      sm[(w * P + a) * 64 + lane] =
+          sv ? rho[((long)j * 2 * P + a) * batch + s] - rho[((long)jn * 2 * P + P + a) * batch + s]
+             : T(0);
+  }
+  __syncthreads();
+  if (!sv) return;
+  for (int kk = wave; kk < KB; kk += 4) {
+    const int k = k0 + kk;
+    if (k >= S) break;
+    T acc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) acc[a] = 0;
+    for (int u = 0; u < dcount; ++u) {
+      const T* B = blocks + u * 4;
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * sm[((kk + u) * P + c) * 64 + lane];
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+      dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
   }
 }
 
@@ -264,6 +322,27 @@ hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batc
 }
 
 template <int P>
+hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
+                             int drow_stride, int drow_off, hipStream_t st) {
+  int KB = c.S < 64 ? ((c.S + 3) / 4) * 4 : 64;
+  size_t lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
+  while (lds > 64 * 1024 && KB > 4) {
+    KB /= 2;
+    lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
+  }
+  if (lds <= 64 * 1024) {
+    dim3 grid((batch + 63) / 64, (c.S + KB - 1) / KB);
+    hipLaunchKernelGGL((reduced_il_lds<P, double>), grid, dim3(256), lds, st, rho, batch, c.S,
+                       c.blocks, c.dlo, c.dcount, KB, dst, ld, drow_stride, drow_off);
+  } else {
+    dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+    hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S,
+                       c.blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
+  }
+  return hipGetLastError();
+}
+
+template <int P>
 hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
                              hipStream_t st) {
   BandT<double> bd;
@@ -271,19 +350,10 @@ hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, d
   dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
   hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch,
                      c.S, c.rec, bd, rho);
-  hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S, c.blocks,
-                     c.dlo, c.dcount, x, ld, kChunk, kChunk - P);
+  hipError_t e = launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((correct_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch, c.S,
                      c.rec);
-  return hipGetLastError();
-}
-
-template <int P>
-hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
-                             int drow_stride, int drow_off, hipStream_t st) {
-  dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
-  hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S, c.blocks,
-                     c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
   return hipGetLastError();
 }
 
