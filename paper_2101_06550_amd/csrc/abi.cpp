@@ -309,7 +309,7 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   h->K.inv_dy = 1.0 / dy;
   h->K.half_gamma = 0.5 * q.gamma;
   h->K.dxdy = dx * dy;
-  h->fast = (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
+  h->fast = (q.nx % 64 == 0) && (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
             h->px->chunk.S <= 256;
   const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
   const long diag_parts = ch_diag_partial_blocks(q.nx, q.ny);
@@ -397,14 +397,11 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho, h->K,
                                 part, st);
       E(0);
-      if (ok() && diag) {
-        B();
-        e = launch_ch_diag_final(part, colblocks, h->K.dxdy, diag_out + 2 * n, st);
-        E(3);
-      }
       if (ok()) {
         B();
-        e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st);
+        e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st,
+                                 diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
+                                 diag ? diag_out + 2 * n : nullptr);
         E(1);
       }
       if (ok()) {

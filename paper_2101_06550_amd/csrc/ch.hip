@@ -70,12 +70,22 @@ __device__ __forceinline__ double recon_value(double v, int p, const double* __r
 
 }  // namespace
 
-// Waves overlap by two columns: lane l of segment g works on column
-// g*62 - 1 + l (mod nx); lanes 1..62 own their column's outputs, lanes 0 and
-// 63 exist only to hand their state values to lanes 1 and 62 through the DPP
-// lane shifts, so every x-neighbour comes from a register and no lane needs an
-// extra load.  Block = 4 waves = 4 consecutive chunks of the same columns.
-constexpr int kOwn = 62;
+// Block = 4 waves = 4 adjacent 64-column segments (256 columns) of one
+// 32-row chunk; every load is a full, aligned 512-byte row segment.  The
+// x-neighbours come from the DPP lane shifts inside a wave; across waves the
+// lane-0 and lane-63 state values are exchanged through LDS (one barrier),
+// and the two columns just outside the block are loaded and reconstructed by
+// 68 threads of the block before the barrier.
+template <bool RECON>
+__device__ __forceinline__ double recon_row(double v, int q, const double* __restrict__ rec,
+                                            const double (&tp)[P], const double (&to)[P],
+                                            const double (&tn)[P]) {
+  // q = 0: last row of chunk kc-1 (separator); q = 1..M: own row q-1;
+  // q = M+1: row 0 of chunk kc+1
+  if (q == 0) return v;
+  if (q == M + 1) return recon_value<RECON>(v, 0, rec, to, tn);
+  return recon_value<RECON>(v, q - 1, rec, tp, to);
+}
 
 template <bool RECON, bool DIAG>
 __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
@@ -85,18 +95,40 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
                                                       BandT<double> bd, double* __restrict__ rho,
                                                       ChCoef K, double* __restrict__ part) {
   __shared__ double red[8];
+  __shared__ double edge[10][M + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kc = blockIdx.y * 4 + wave;
-  const bool live = kc < Sc;
-  const int iu = blockIdx.x * kOwn - 1 + lane;  // unwrapped column
-  const int i = ((iu % nx) + nx) % nx;
-  const bool own = (lane >= 1) && (lane <= kOwn) && (iu < nx);
+  const int kc = blockIdx.y;
+  const int nseg = nx >> 6;
+  const int seg0 = blockIdx.x * 4;
+  const int nw = (nseg - seg0 < 4) ? nseg - seg0 : 4;  // active waves of this block
+  const bool live = wave < nw;
+  const int i = (seg0 + wave) * 64 + lane;
   const int kcm = (kc - 1 + Sc) % Sc, kcp = (kc + 1) % Sc;
+  const long rowm1 = ((long)kc * M - 1 + ny) % ny;
+  const long rowp = ((long)kc * M + M) % ny;
 
-  double msum = 0.0, esum = 0.0;
+  // the two columns outside the block: thread t < 2(M+2) takes side t/(M+2), row t%(M+2)
+  if (threadIdx.x < 2 * (M + 2)) {
+    const int side = threadIdx.x / (M + 2), q = threadIdx.x - side * (M + 2);
+    const int ic = side == 0 ? (seg0 * 64 - 1 + nx) % nx : (seg0 * 64 + nw * 64) % nx;
+    const long row = q == 0 ? rowm1 : (q == M + 1 ? rowp : (long)kc * M + q - 1);
+    double v = src[row * lds + ic];
+    if (RECON) {
+      double tp[P], to[P], tn[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        tp[a] = src[((long)kcm * M + MI + a) * lds + ic];
+        to[a] = src[((long)kc * M + MI + a) * lds + ic];
+        tn[a] = src[((long)kcp * M + MI + a) * lds + ic];
+      }
+      v = recon_row<RECON>(v, q, rec, tp, to, tn);
+    }
+    edge[side][q] = v;
+  }
+
+  double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
+  double X[M + 2];
   if (live) {
-    // separator rows (row-solved values T) of chunks kc-1, kc, kc+1
-    double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
     if (RECON) {
 #pragma unroll
       for (int a = 0; a < P; ++a) {
@@ -105,35 +137,44 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
         tn[a] = src[((long)kcp * M + MI + a) * lds + i];
       }
     }
-    // rows kc*M-1 .. kc*M+M (wrapped), then the state with the deferred
-    // column correction applied
-    double X[M + 2];
-    const long rowm1 = ((long)kc * M - 1 + ny) % ny;
-    const long rowp = ((long)kc * M + M) % ny;
     X[0] = src[rowm1 * lds + i];
 #pragma unroll
     for (int p = 0; p < M; ++p) X[p + 1] = src[((long)kc * M + p) * lds + i];
     X[M + 1] = src[rowp * lds + i];
-    X[M + 1] = recon_value<RECON>(X[M + 1], 0, rec, to, tn);
-    // Rows are processed strictly in order (scheduling barrier per row): the
-    // column's raw values stay in registers, a 3-row window of state values
-    // and x-neighbours is live, and the forward sweep of the chunk interior
-    // runs as soon as each right-hand-side value exists (g overwrites f).
+#pragma unroll
+    for (int q = 0; q < M + 2; ++q) X[q] = recon_row<RECON>(X[q], q, rec, tp, to, tn);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < M + 2; ++q) edge[2 + wave][q] = X[q];
+    } else if (lane == 63) {
+#pragma unroll
+      for (int q = 0; q < M + 2; ++q) edge[6 + wave][q] = X[q];
+    }
+  }
+  __syncthreads();
+
+  double msum = 0.0, esum = 0.0;
+  if (live) {
+    // the neighbour slot this lane reads: lane 0 <- left, lane 63 <- right
+    const int slot = (lane == 0) ? (wave > 0 ? 6 + wave - 1 : 0)
+                                 : (wave < nw - 1 ? 2 + wave + 1 : 1);
+    const double* es = &edge[slot][0];
+    // Rows are processed strictly in order: an empty volatile asm on the next
+    // row's value (volatile asms keep their order) and on each row's result
+    // stop the compiler from computing every row's neighbours up front.
     double f[M];
     const double eps = bd.c[0];
-    double xl_m = dpp_from_left(X[0], X[0]), xc_m = X[0], xr_m = dpp_from_right(X[0], X[0]);
-    double xc_c = recon_value<RECON>(X[1], 0, rec, tp, to);
-    double xl_c = dpp_from_left(xc_c, xc_c), xr_c = dpp_from_right(xc_c, xc_c);
+    double xc_m = X[0];
+    double xl_m = dpp_from_left(xc_m, es[0]), xr_m = dpp_from_right(xc_m, es[0]);
+    double xc_c = X[1];
+    double xl_c = dpp_from_left(xc_c, es[1]), xr_c = dpp_from_right(xc_c, es[1]);
 #pragma unroll
     for (int p = 0; p < M; ++p) {
-      // An empty volatile asm on the next row's raw value: volatile asms keep
-      // their order, and everything of row p+1 depends on this one, so no
-      // pass can compute row p+1 (and keep its neighbours live) before row p.
-      double xn = X[p + 2];
-      asm volatile("" : "+v"(xn));
-      const double xc_p = (p + 1 < M) ? recon_value<RECON>(xn, p + 1, rec, tp, to) : xn;
-      const double xl_p = dpp_from_left(xc_p, xc_p);
-      const double xr_p = dpp_from_right(xc_p, xc_p);
+      double xc_p = X[p + 2];
+      double en = es[p + 2];
+      asm volatile("" : "+v"(xc_p), "+v"(en));
+      const double xl_p = dpp_from_left(xc_p, en);
+      const double xr_p = dpp_from_right(xc_p, en);
       const double mu_c = xc_c * xc_c * xc_c - xc_c;
       const double mu_l = xl_c * xl_c * xl_c - xl_c;
       const double mu_r = xr_c * xr_c * xr_c - xr_c;
@@ -150,18 +191,16 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
         msum += xc_c;
         esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
       }
-      if (p < MI) {  // forward sweep step of the chunk interior
+      if (p < MI) {  // forward sweep step of the chunk interior (g overwrites f)
         if (p >= 2) r = r - eps * f[p - 2];
         if (p >= 1) r = r - rec[p * 8 + 1] * f[p - 1];
         r = r * rec[p * 8 + 0];
       }
-      // row p's results exist before row p+1 starts
       if (DIAG) asm volatile("" : "+v"(r), "+v"(msum), "+v"(esum));
       else asm volatile("" : "+v"(r));
       f[p] = r;
       xl_m = xl_c; xc_m = xc_c; xr_m = xr_c;
       xl_c = xl_p; xc_c = xc_p; xr_c = xr_p;
-      __builtin_amdgcn_sched_barrier(0);
     }
     // back sweep of the interior (y = R^{-1} g)
 #pragma unroll
@@ -171,19 +210,14 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
       if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
       f[p] = v;
     }
-    if (!own) {
-      msum = 0.0;
-      esum = 0.0;
-    } else {
-      double pa[P], pb[P];
-      chunk_parts<P, M, double>(f, bd, pa, pb);
+    double pa[P], pb[P];
+    chunk_parts<P, M, double>(f, bd, pa, pb);
 #pragma unroll
-      for (int p = 0; p < MI; ++p) ybuf[((long)kc * M + p) * ldy + i] = f[p];
+    for (int p = 0; p < MI; ++p) ybuf[((long)kc * M + p) * ldy + i] = f[p];
 #pragma unroll
-      for (int a = 0; a < P; ++a) {
-        rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
-        rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
-      }
+    for (int a = 0; a < P; ++a) {
+      rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
+      rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
     }
   }
   if (DIAG) {
@@ -315,7 +349,7 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
                                  double* rho, const ChCoef& K, double* part, hipStream_t st) {
   BandT<double> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
-  dim3 grid((nx + kOwn - 1) / kOwn, (cy.S + 3) / 4);
+  dim3 grid(((nx >> 6) + 3) / 4, cy.S);
   const int Sc = cy.S;
 #define CHX_COLPASS(R, D)                                                                      \
   hipLaunchKernelGGL((ch_column_pass<R, D>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
@@ -328,9 +362,7 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
   return hipGetLastError();
 }
 
-long ch_column_pass_blocks(int nx, int Sc) {
-  return (long)((nx + kOwn - 1) / kOwn) * ((Sc + 3) / 4);
-}
+long ch_column_pass_blocks(int nx, int Sc) { return (long)(((nx >> 6) + 3) / 4) * Sc; }
 
 hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
                               const DevChunk& cy, hipStream_t st) {

@@ -32,7 +32,9 @@ hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, d
                              hipStream_t st);
 template <int P>
 hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
-                             int drow_stride, int drow_off, hipStream_t st);
+                             int drow_stride, int drow_off, hipStream_t st,
+                             const double* dpart = nullptr, long dnparts = 0, double dscale = 0.0,
+                             double* dout = nullptr);
 template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st);
 

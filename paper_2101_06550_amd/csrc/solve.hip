@@ -165,104 +165,162 @@ __global__ __launch_bounds__(256) void correct_il(double* x, long ld, int batch,
 // Contiguous layout, whole rows through LDS.  256 threads = 256 chunks of M;
 // a workgroup holds R = 256 / S rows of n = S * M unknowns.  Element
 // (row r, chunk k, position p) lives at tile[(r*S + k)*(M+1) + p]; the +1
-// pad spreads the per-thread chunks over the LDS banks.
+// pad spreads the per-thread chunks over the LDS banks.  Workgroups loop over
+// row groups (grid-stride); two resident workgroups per CU overlap one's
+// loads with the other's sweeps.
+// Element e of a workgroup's tile is row e / n, column e % n of its row
+// group; its LDS slot is e + e / M (the +1 pad per chunk).  Dense rows
+// (ld == n) need no division: the group is one contiguous range, loaded with
+// every load of a thread in flight before the first LDS store.  Strided rows
+// (ld > n) take a compact loop.
 template <int P, int M, typename T>
-__global__ __launch_bounds__(256) void row_solve_lds(double* x, long ld, int rows, int n, int S,
-                                                     int R, int log2n, const T* __restrict__ rec,
-                                                     BandT<T> bd, const T* __restrict__ blocks,
-                                                     int dlo, int dcount) {
+__device__ __forceinline__ void row_group_stage(T* tile, const double* x, long ld, int rows, int n,
+                                                long row0, int nel, int t, bool dense) {
+  if (dense) {
+    const long nvalid = ((long)rows - row0) * n;
+    const double* base = x + row0 * n;
+    double vin[M];
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int e = t + 256 * u;
+      vin[u] = (e < nel && e < nvalid) ? base[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+      const int e = t + 256 * u;
+      if (e < nel) tile[e + e / M] = (T)vin[u];
+    }
+  } else {
+#pragma unroll 1
+    for (int u = 0; u < M; ++u) {
+      const int e = t + 256 * u;
+      const int r = e / n;
+      const int i = e - r * n;
+      if (e < nel) tile[e + e / M] = (row0 + r < rows) ? (T)x[(row0 + r) * ld + i] : T(0);
+    }
+  }
+}
+
+template <int P, int M, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds(
+    double* x, long ld, int rows, int n, int S, int R, const T* __restrict__ rec, BandT<T> bd,
+    const T* __restrict__ blocks, int dlo, int dcount) {
   __shared__ T tile[256 * (M + 1)];
   __shared__ T rhol[256 * 2 * P];
   __shared__ T sepl[256 * P];
   const int t = threadIdx.x;
-  const long row0 = (long)blockIdx.x * R;
   const int nel = R * n;  // <= 256 * M
-  // coalesced load of R rows: all M loads of a thread are issued before the
-  // first LDS store, so a workgroup keeps its whole tile in flight
-  double vin[M];
-#pragma unroll
-  for (int u = 0; u < M; ++u) {
-    const int e = t + 256 * u;
-    const int r = (log2n >= 0) ? (e >> log2n) : (e / n);
-    const int i = e - r * n;
-    vin[u] = (e < nel && row0 + r < rows) ? x[(row0 + r) * ld + i] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < M; ++u) {
-    const int e = t + 256 * u;
-    const int r = (log2n >= 0) ? (e >> log2n) : (e / n);
-    const int i = e - r * n;
-    if (e < nel) tile[(r * S + i / M) * (M + 1) + (i % M)] = (T)vin[u];
-  }
-  __syncthreads();
+  const long ngroups = ((long)rows + R - 1) / R;
   const int r = t / S, k = t - r * S;
-  const bool active = (r < R) && (row0 + r < rows);
-  T f[M];
-  if (active) {
+  const bool dense = (ld == n);
+  for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const long row0 = g * R;
+    row_group_stage<P, M, T>(tile, x, ld, rows, n, row0, nel, t, dense);
+    __syncthreads();
+    const bool active = (r < R) && (row0 + r < rows);
+    T f[M];
+    if (active) {
 #pragma unroll
-    for (int p = 0; p < M; ++p) f[p] = tile[t * (M + 1) + p];
-    chunk_sweep<P, M, T>(f, rec, bd.c[0]);
-    T pa[P], pb[P];
-    chunk_parts<P, M, T>(f, bd, pa, pb);
+      for (int p = 0; p < M; ++p) f[p] = tile[t * (M + 1) + p];
+      chunk_sweep<P, M, T>(f, rec, bd.c[0]);
+      T pa[P], pb[P];
+      chunk_parts<P, M, T>(f, bd, pa, pb);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      rhol[t * 2 * P + a] = pa[a];
-      rhol[t * 2 * P + P + a] = pb[a];
+      for (int a = 0; a < P; ++a) {
+        rhol[a * 256 + t] = pa[a];
+        rhol[(P + a) * 256 + t] = pb[a];
+      }
     }
-  }
-  __syncthreads();
-  if (active) {
-    T acc[P];
+    __syncthreads();
+    if (active) {
+      // rho_j = pa_j - pb_{j+1} for the chunks j = k + dlo + u of this row;
+      // struct-of-arrays LDS rows keep lanes on distinct banks, and the loop
+      // is unrolled by four so LDS latency overlaps
+      T acc[P];
 #pragma unroll
-    for (int a = 0; a < P; ++a) acc[a] = 0;
-    for (int u = 0; u < dcount; ++u) {
-      const int j = wrap_once(k + dlo + u, S);
-      const int jn = wrap_once(j + 1, S);
-      T rr[P];
+      for (int a = 0; a < P; ++a) acc[a] = 0;
+      const int rs = r * S;
+      int u = 0;
+      for (; u + 4 <= dcount; u += 4) {
+        T rr2[4][P];
 #pragma unroll
-      for (int a = 0; a < P; ++a)
-        rr[a] = rhol[(r * S + j) * 2 * P + a] - rhol[(r * S + jn) * 2 * P + P + a];
-      const T* B = blocks + u * 4;
+        for (int q = 0; q < 4; ++q) {
+          const int j = wrap_once(k + dlo + u + q, S);
+          const int jn = wrap_once(j + 1, S);
 #pragma unroll
-      for (int a = 0; a < P; ++a)
+          for (int a = 0; a < P; ++a)
+            rr2[q][a] = rhol[a * 256 + rs + j] - rhol[(P + a) * 256 + rs + jn];
+        }
 #pragma unroll
-        for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * rr[c];
+        for (int q = 0; q < 4; ++q) {
+          const T* B = blocks + (u + q) * 4;
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * rr2[q][c];
+        }
+      }
+      for (; u < dcount; ++u) {
+        const int j = wrap_once(k + dlo + u, S);
+        const int jn = wrap_once(j + 1, S);
+        const T* B = blocks + u * 4;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int c = 0; c < P; ++c)
+            acc[a] = acc[a] + B[a * 2 + c] * (rhol[c * 256 + rs + j] - rhol[(P + c) * 256 + rs + jn]);
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) sepl[a * 256 + t] = acc[a];
     }
+    __syncthreads();
+    if (active) {
+      const int kp = wrap_once(k - 1, S);
+      T sp[P], so[P];
 #pragma unroll
-    for (int a = 0; a < P; ++a) sepl[t * P + a] = acc[a];
-  }
-  __syncthreads();
-  if (active) {
-    const int kp = wrap_once(k - 1, S);
-    T sp[P], so[P];
+      for (int a = 0; a < P; ++a) {
+        sp[a] = sepl[a * 256 + r * S + kp];
+        so[a] = sepl[a * 256 + t];
+      }
+      chunk_correct<P, M, T>(f, rec, sp, so);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      sp[a] = sepl[(r * S + kp) * P + a];
-      so[a] = sepl[t * P + a];
+      for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
     }
-    chunk_correct<P, M, T>(f, rec, sp, so);
+    __syncthreads();
+    if (dense) {
+      const long nvalid = ((long)rows - row0) * n;
+      double* base = x + row0 * n;
 #pragma unroll
-    for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < M; ++u) {
-    const int e = t + 256 * u;
-    const int rr = (log2n >= 0) ? (e >> log2n) : (e / n);
-    const int i = e - rr * n;
-    if (e < nel && row0 + rr < rows)
-      x[(row0 + rr) * ld + i] = (double)tile[(rr * S + i / M) * (M + 1) + (i % M)];
+      for (int u = 0; u < M; ++u) {
+        const int e = t + 256 * u;
+        if (e < nel && e < nvalid) base[e] = (double)tile[e + e / M];
+      }
+    } else {
+#pragma unroll 1
+      for (int u = 0; u < M; ++u) {
+        const int e = t + 256 * u;
+        const int rr = e / n;
+        const int i = e - rr * n;
+        if (e < nel && row0 + rr < rows) x[(row0 + rr) * ld + i] = (double)tile[e + e / M];
+      }
+    }
+    __syncthreads();
   }
 }
 
 // Reduced separator system with an LDS window: a block owns 64 systems and KB
 // consecutive chunks; it stages rho_j = pa_j - pb_{j+1} for the KB + dcount - 1
-// chunks its convolutions touch, then each wave sweeps its chunks from LDS.
+// chunks its convolutions touch (eight window rows in flight per wave), then
+// each wave sweeps its chunks from LDS.  Block (0,0) can also finish a
+// fixed-order sum of per-block (mass, energy) partials (diag != nullptr).
 template <int P, typename T>
 __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
                                                       const T* __restrict__ blocks, int dlo,
                                                       int dcount, int KB, double* __restrict__ dst,
-                                                      long ld, int drow_stride, int drow_off) {
+                                                      long ld, int drow_stride, int drow_off,
+                                                      const double* __restrict__ dpart,
+                                                      long dnparts, double dscale,
+                                                      double* __restrict__ dout) {
   extern __shared__ unsigned char smraw[];
   T* sm = reinterpret_cast<T*>(smraw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -270,45 +328,109 @@ __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho,
   const int k0 = blockIdx.y * KB;
   const int nwin = KB + dcount - 1;
   const bool sv = s < batch;
-  for (int w = wave; w < nwin; w += 4) {
-    int j = (k0 + dlo + w) % S;
-    j += (j < 0) ? S : 0;
-    const int jn = (j + 1 == S) ? 0 : j + 1;
+  constexpr int U = 8;
+  for (int w0 = wave; w0 < nwin; w0 += 4 * U) {
+    T v[U][P];
 #pragma unroll
-    for (int a = 0; a < P; ++a)
-      sm[(w * P + a) * 64 + lane] =
-          sv ? rho[((long)j * 2 * P + a) * batch + s] - rho[((long)jn * 2 * P + P + a) * batch + s]
-             : T(0);
-  }
-  __syncthreads();
-  if (!sv) return;
-  for (int kk = wave; kk < KB; kk += 4) {
-    const int k = k0 + kk;
-    if (k >= S) break;
-    T acc[P];
-#pragma unroll
-    for (int a = 0; a < P; ++a) acc[a] = 0;
-    for (int u = 0; u < dcount; ++u) {
-      const T* B = blocks + u * 4;
+    for (int u = 0; u < U; ++u) {
+      const int w = w0 + 4 * u;
+      int j = k0 + dlo + w;
+      while (j >= S) j -= S;
+      while (j < 0) j += S;
+      const int jn = (j + 1 == S) ? 0 : j + 1;
 #pragma unroll
       for (int a = 0; a < P; ++a)
-#pragma unroll
-        for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * sm[((kk + u) * P + c) * 64 + lane];
+        v[u][a] = (sv && w < nwin) ? rho[((long)j * 2 * P + a) * batch + s] -
+                                         rho[((long)jn * 2 * P + P + a) * batch + s]
+                                   : T(0);
     }
 #pragma unroll
-    for (int a = 0; a < P; ++a)
-      dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
+    for (int u = 0; u < U; ++u) {
+      const int w = w0 + 4 * u;
+      if (w < nwin) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) sm[(w * P + a) * 64 + lane] = v[u][a];
+      }
+    }
+  }
+  __syncthreads();
+  if (sv) {
+    for (int kk = wave; kk < KB; kk += 4) {
+      const int k = k0 + kk;
+      if (k >= S) break;
+      T acc[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) acc[a] = 0;
+      int u = 0;
+      for (; u + 4 <= dcount; u += 4) {
+        T q4[4][P];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < P; ++c) q4[q][c] = sm[((kk + u + q) * P + c) * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T* B = blocks + (u + q) * 4;
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * q4[q][c];
+        }
+      }
+      for (; u < dcount; ++u) {
+        const T* B = blocks + u * 4;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int c = 0; c < P; ++c)
+            acc[a] = acc[a] + B[a * 2 + c] * sm[((kk + u) * P + c) * 64 + lane];
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+        dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
+    }
+  }
+  if (dout != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
+    __syncthreads();
+    double* sm2 = reinterpret_cast<double*>(smraw);
+    const long per = (dnparts + 255) / 256;
+    const long b0 = (long)threadIdx.x * per;
+    const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
+    double m = 0.0, e = 0.0;
+    long b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      double2 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        m += q[u].x;
+        e += q[u].y;
+      }
+    }
+    for (; b < b1; ++b) {
+      m += dpart[2 * b];
+      e += dpart[2 * b + 1];
+    }
+    sm2[threadIdx.x] = m;
+    sm2[256 + threadIdx.x] = e;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        sm2[threadIdx.x] += sm2[threadIdx.x + h];
+        sm2[256 + threadIdx.x] += sm2[256 + threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      dout[0] = sm2[0] * dscale;
+      dout[1] = sm2[256] * dscale;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
-static int log2_exact(int n) {
-  if (n <= 0 || (n & (n - 1))) return -1;
-  int l = 0;
-  while ((1 << l) < n) ++l;
-  return l;
-}
 
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
@@ -323,18 +445,22 @@ hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batc
 
 template <int P>
 hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
-                             int drow_stride, int drow_off, hipStream_t st) {
-  int KB = c.S < 64 ? ((c.S + 3) / 4) * 4 : 64;
+                             int drow_stride, int drow_off, hipStream_t st, const double* dpart,
+                             long dnparts, double dscale, double* dout) {
+  int KB = c.S < 32 ? ((c.S + 3) / 4) * 4 : 32;
   size_t lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
   while (lds > 64 * 1024 && KB > 4) {
     KB /= 2;
     lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
   }
+  if (dout && lds < 512 * sizeof(double)) lds = 512 * sizeof(double);
   if (lds <= 64 * 1024) {
     dim3 grid((batch + 63) / 64, (c.S + KB - 1) / KB);
     hipLaunchKernelGGL((reduced_il_lds<P, double>), grid, dim3(256), lds, st, rho, batch, c.S,
-                       c.blocks, c.dlo, c.dcount, KB, dst, ld, drow_stride, drow_off);
+                       c.blocks, c.dlo, c.dcount, KB, dst, ld, drow_stride, drow_off, dpart,
+                       dnparts, dscale, dout);
   } else {
+    if (dout) return hipErrorInvalidValue;
     dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
     hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S,
                        c.blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
@@ -350,7 +476,8 @@ hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, d
   dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
   hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch,
                      c.S, c.rec, bd, rho);
-  hipError_t e = launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st);
+  hipError_t e =
+      launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0, 0.0, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((correct_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch, c.S,
                      c.rec);
@@ -362,9 +489,22 @@ hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipS
   BandT<double> bd;
   for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
   const int R = 256 / c.S;
-  dim3 grid((rows + R - 1) / R);
-  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, rows, c.n,
-                     c.S, R, log2_exact(c.n), c.rec, bd, c.blocks, c.dlo, c.dcount);
+  const long ngroups = ((long)rows + R - 1) / R;
+  static int resident = 0;  // workgroups resident per device at once
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, row_solve_lds<P, kChunk, double>, 256,
+                                                     0) == hipSuccess &&
+        cus > 0 && per > 0)
+      resident = cus * per;
+    else
+      resident = 512;
+  }
+  const long gx = ngroups < resident ? ngroups : resident;
+  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), dim3((unsigned)gx), dim3(256), 0, st, x,
+                     ld, rows, c.n, c.S, R, c.rec, bd, c.blocks, c.dlo, c.dcount);
   return hipGetLastError();
 }
 
@@ -373,9 +513,9 @@ template hipError_t launch_whole<2>(const DevWhole&, double*, long, long, int, h
 template hipError_t launch_chunked_il<1>(const DevChunk&, double*, long, int, double*, hipStream_t);
 template hipError_t launch_chunked_il<2>(const DevChunk&, double*, long, int, double*, hipStream_t);
 template hipError_t launch_reduced_il<1>(const DevChunk&, const double*, int, double*, long, int,
-                                        int, hipStream_t);
+                                        int, hipStream_t, const double*, long, double, double*);
 template hipError_t launch_reduced_il<2>(const DevChunk&, const double*, int, double*, long, int,
-                                        int, hipStream_t);
+                                        int, hipStream_t, const double*, long, double, double*);
 template hipError_t launch_rows_lds<1>(const DevChunk&, double*, long, int, hipStream_t);
 template hipError_t launch_rows_lds<2>(const DevChunk&, double*, long, int, hipStream_t);
 
