@@ -165,9 +165,8 @@ __global__ __launch_bounds__(256) void correct_il(double* x, long ld, int batch,
 // Contiguous layout, whole rows through LDS.  256 threads = 256 chunks of M;
 // a workgroup holds R = 256 / S rows of n = S * M unknowns.  Element
 // (row r, chunk k, position p) lives at tile[(r*S + k)*(M+1) + p]; the +1
-// pad spreads the per-thread chunks over the LDS banks.  Workgroups loop over
-// row groups (grid-stride); two resident workgroups per CU overlap one's
-// loads with the other's sweeps.
+// pad spreads the per-thread chunks over the LDS banks.  One workgroup per row
+// group; two are resident per CU, so one's loads overlap the other's sweeps.
 // Element e of a workgroup's tile is row e / n, column e % n of its row
 // group; its LDS slot is e + e / M (the +1 pad per chunk).  Dense rows
 // (ld == n) need no division: the group is one contiguous range, loaded with
@@ -180,10 +179,15 @@ __device__ __forceinline__ void row_group_stage(T* tile, const double* x, long l
     const long nvalid = ((long)rows - row0) * n;
     const double* base = x + row0 * n;
     double vin[M];
+    if (nel == 256 * M && nvalid >= nel) {  // a full group: no guards
 #pragma unroll
-    for (int u = 0; u < M; ++u) {
-      const int e = t + 256 * u;
-      vin[u] = (e < nel && e < nvalid) ? base[e] : 0.0;
+      for (int u = 0; u < M; ++u) vin[u] = base[t + 256 * u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < M; ++u) {
+        const int e = t + 256 * u;
+        vin[u] = (e < nel && e < nvalid) ? base[e] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < M; ++u) {
@@ -210,11 +214,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   __shared__ T sepl[256 * P];
   const int t = threadIdx.x;
   const int nel = R * n;  // <= 256 * M
-  const long ngroups = ((long)rows + R - 1) / R;
   const int r = t / S, k = t - r * S;
   const bool dense = (ld == n);
-  for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const long row0 = g * R;
+  {
+    const long row0 = (long)blockIdx.x * R;
     row_group_stage<P, M, T>(tile, x, ld, rows, n, row0, nel, t, dense);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
@@ -490,21 +493,8 @@ hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipS
   for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
   const int R = 256 / c.S;
   const long ngroups = ((long)rows + R - 1) / R;
-  static int resident = 0;  // workgroups resident per device at once
-  if (resident == 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, row_solve_lds<P, kChunk, double>, 256,
-                                                     0) == hipSuccess &&
-        cus > 0 && per > 0)
-      resident = cus * per;
-    else
-      resident = 512;
-  }
-  const long gx = ngroups < resident ? ngroups : resident;
-  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), dim3((unsigned)gx), dim3(256), 0, st, x,
-                     ld, rows, c.n, c.S, R, c.rec, bd, c.blocks, c.dlo, c.dcount);
+  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), dim3((unsigned)ngroups), dim3(256), 0, st,
+                     x, ld, rows, c.n, c.S, R, c.rec, bd, c.blocks, c.dlo, c.dcount);
   return hipGetLastError();
 }
 
