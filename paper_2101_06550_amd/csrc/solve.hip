@@ -311,15 +311,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   }
 }
 
-// Reduced separator system with an LDS window: a block owns 64 systems and KB
-// consecutive chunks; it stages rho_j = pa_j - pb_{j+1} for the KB + dcount - 1
-// chunks its convolutions touch (eight window rows in flight per wave), then
-// each wave sweeps its chunks from LDS.  Block (0,0) can also finish a
-// fixed-order sum of per-block (mass, energy) partials (diag != nullptr).
+// Reduced separator system with an LDS window: a block (8 waves) owns 64
+// systems and KB = 8 G consecutive chunks; it stages rho_j = pa_j - pb_{j+1}
+// for the KB + dcount - 1 chunks its convolutions touch, then each wave
+// computes G consecutive chunks at once, reading every window entry from LDS
+// a single time (register blocking).  Block (0,0) can also finish a
+// fixed-order sum of per-block (mass, energy) partials (dout != nullptr).
+constexpr int kRedG = 4;
+constexpr int kRedWaves = 8;
+constexpr int kRedKB = kRedG * kRedWaves;
+
 template <int P, typename T>
-__global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
+__global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
                                                       const T* __restrict__ blocks, int dlo,
-                                                      int dcount, int KB, double* __restrict__ dst,
+                                                      int dcount, double* __restrict__ dst,
                                                       long ld, int drow_stride, int drow_off,
                                                       const double* __restrict__ dpart,
                                                       long dnparts, double dscale,
@@ -328,15 +333,15 @@ __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho,
   T* sm = reinterpret_cast<T*>(smraw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)blockIdx.x * 64 + lane;
-  const int k0 = blockIdx.y * KB;
-  const int nwin = KB + dcount - 1;
+  const int k0 = blockIdx.y * kRedKB;
+  const int nwin = kRedKB + dcount - 1;
   const bool sv = s < batch;
-  constexpr int U = 8;
-  for (int w0 = wave; w0 < nwin; w0 += 4 * U) {
+  constexpr int U = 4;
+  for (int w0 = wave; w0 < nwin; w0 += kRedWaves * U) {
     T v[U][P];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + 4 * u;
+      const int w = w0 + kRedWaves * u;
       int j = k0 + dlo + w;
       while (j >= S) j -= S;
       while (j < 0) j += S;
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho,
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + 4 * u;
+      const int w = w0 + kRedWaves * u;
       if (w < nwin) {
 #pragma unroll
         for (int a = 0; a < P; ++a) sm[(w * P + a) * 64 + lane] = v[u][a];
@@ -357,46 +362,45 @@ __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho,
     }
   }
   __syncthreads();
-  if (sv) {
-    for (int kk = wave; kk < KB; kk += 4) {
-      const int k = k0 + kk;
-      if (k >= S) break;
-      T acc[P];
+  const int kk0 = wave * kRedG;  // first chunk (within the block) of this wave
+  if (sv && k0 + kk0 < S) {
+    T acc[kRedG][P];
 #pragma unroll
-      for (int a = 0; a < P; ++a) acc[a] = 0;
-      int u = 0;
-      for (; u + 4 <= dcount; u += 4) {
-        T q4[4][P];
+    for (int g = 0; g < kRedG; ++g)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+      for (int a = 0; a < P; ++a) acc[g][a] = 0;
+    // window entry kk0 + u feeds output g through block t = u - g
+    for (int u = 0; u < kRedG + dcount - 1; ++u) {
+      T rv[P];
 #pragma unroll
-          for (int c = 0; c < P; ++c) q4[q][c] = sm[((kk + u + q) * P + c) * 64 + lane];
+      for (int c = 0; c < P; ++c) rv[c] = sm[((kk0 + u) * P + c) * 64 + lane];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T* B = blocks + (u + q) * 4;
+      for (int g = 0; g < kRedG; ++g) {
+        const int t = u - g;
+        if (t >= 0 && t < dcount) {
+          const T* B = blocks + t * 4;
 #pragma unroll
           for (int a = 0; a < P; ++a)
 #pragma unroll
-            for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * q4[q][c];
+            for (int c = 0; c < P; ++c) acc[g][a] = acc[g][a] + B[a * 2 + c] * rv[c];
         }
       }
-      for (; u < dcount; ++u) {
-        const T* B = blocks + u * 4;
+    }
+#pragma unroll
+    for (int g = 0; g < kRedG; ++g) {
+      const int k = k0 + kk0 + g;
+      if (k < S) {
 #pragma unroll
         for (int a = 0; a < P; ++a)
-#pragma unroll
-          for (int c = 0; c < P; ++c)
-            acc[a] = acc[a] + B[a * 2 + c] * sm[((kk + u) * P + c) * 64 + lane];
+          dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[g][a];
       }
-#pragma unroll
-      for (int a = 0; a < P; ++a)
-        dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
     }
   }
   if (dout != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
     __syncthreads();
     double* sm2 = reinterpret_cast<double*>(smraw);
-    const long per = (dnparts + 255) / 256;
+    const int nt = blockDim.x;
+    const long per = (dnparts + nt - 1) / nt;
     const long b0 = (long)threadIdx.x * per;
     const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
     double m = 0.0, e = 0.0;
@@ -416,18 +420,18 @@ __global__ __launch_bounds__(256) void reduced_il_lds(const T* __restrict__ rho,
       e += dpart[2 * b + 1];
     }
     sm2[threadIdx.x] = m;
-    sm2[256 + threadIdx.x] = e;
+    sm2[nt + threadIdx.x] = e;
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
+    for (int h = nt / 2; h >= 1; h >>= 1) {
       if ((int)threadIdx.x < h) {
         sm2[threadIdx.x] += sm2[threadIdx.x + h];
-        sm2[256 + threadIdx.x] += sm2[256 + threadIdx.x + h];
+        sm2[nt + threadIdx.x] += sm2[nt + threadIdx.x + h];
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       dout[0] = sm2[0] * dscale;
-      dout[1] = sm2[256] * dscale;
+      dout[1] = sm2[nt] * dscale;
     }
   }
 }
@@ -450,18 +454,13 @@ template <int P>
 hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
                              int drow_stride, int drow_off, hipStream_t st, const double* dpart,
                              long dnparts, double dscale, double* dout) {
-  int KB = c.S < 32 ? ((c.S + 3) / 4) * 4 : 32;
-  size_t lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
-  while (lds > 64 * 1024 && KB > 4) {
-    KB /= 2;
-    lds = (size_t)(KB + c.dcount - 1) * P * 64 * sizeof(double);
-  }
-  if (dout && lds < 512 * sizeof(double)) lds = 512 * sizeof(double);
+  size_t lds = (size_t)(kRedKB + c.dcount - 1) * P * 64 * sizeof(double);
+  if (dout && lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
   if (lds <= 64 * 1024) {
-    dim3 grid((batch + 63) / 64, (c.S + KB - 1) / KB);
-    hipLaunchKernelGGL((reduced_il_lds<P, double>), grid, dim3(256), lds, st, rho, batch, c.S,
-                       c.blocks, c.dlo, c.dcount, KB, dst, ld, drow_stride, drow_off, dpart,
-                       dnparts, dscale, dout);
+    dim3 grid((batch + 63) / 64, (c.S + kRedKB - 1) / kRedKB);
+    hipLaunchKernelGGL((reduced_il_lds<P, double>), grid, dim3(64 * kRedWaves), lds, st, rho,
+                       batch, c.S, c.blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off,
+                       dpart, dnparts, dscale, dout);
   } else {
     if (dout) return hipErrorInvalidValue;
     dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
