@@ -192,6 +192,38 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
                    double* energy, chx_stream s);
 
 /* ------------------------------------------------------------------------
+ * Uneven ensembles (the thesis's statistical ensembles of coarsening runs,
+ * Ch.7 "2D Cahn--Hilliard Methodology", and its proposal of variable system
+ * lengths within a batch with one stored LHS per distinct matrix, Ch.8
+ * "Future Work").  Many independent
+ * runs, each with its own grid and parameters, advance together: every
+ * kernel launch covers all runs (one launch per phase per step), runs of the
+ * same grid and parameters share one factorisation, and with use_graph the
+ * whole nsteps sequence is captured once in a hipGraph and replayed.
+ *
+ * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array).  Every run
+ *   must use CHX_F64 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 16
+ *   distinct (grid, D, gamma, dt) classes; else CHX_EINVAL.
+ * ch_ensemble_ws_bytes: device workspace for ch_ensemble_step.
+ * ch_ensemble_step: advance every run by nsteps >= 1 steps in place.
+ *   c_runs: host array of nruns device pointers (row-major fields); ld_runs:
+ *   host array of leading dimensions (NULL = nx).  diag_out (device, may be
+ *   NULL): run r's mass and free energy before each step and after the last
+ *   at diag_out[r*2*(nsteps+1) + 2*k + {0,1}].  use_graph != 0 replays a
+ *   cached hipGraph of the call (re-captured when nsteps, diag_out or ws
+ *   change).  Asynchronous on s, except that a change of the run pointers
+ *   synchronises s before the run table is updated.  Calls on one handle
+ *   must not overlap.
+ */
+typedef struct chx_ens_s* chx_ens;
+int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out);
+int ch_ensemble_destroy(chx_ens e);
+size_t ch_ensemble_ws_bytes(chx_ens e);
+int ch_ensemble_step(chx_ens e, double* const* c_runs, const long* ld_runs,
+                     int nsteps, double* diag_out, void* ws, size_t ws_bytes,
+                     int use_graph, chx_stream s);
+
+/* ------------------------------------------------------------------------
  * Host-side plan inspection (no device work; usable without a GPU).  They
  * return the tables that penta_factor / tri_factor compute and upload, so the
  * host factorisation can be checked on a CPU.  P = 2 (coef = a,b,c,d,e) or

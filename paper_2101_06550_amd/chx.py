@@ -36,6 +36,7 @@ EXPORTED = [
     "stencil2d_apply",
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_timed",
     "ch_diagnostics",
+    "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
 
@@ -92,6 +93,11 @@ def load(path: str | None = None):
         "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
+        "ch_ensemble_create": (_I, [_I, ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
+        "ch_ensemble_destroy": (_I, [_V]),
+        "ch_ensemble_ws_bytes": (_S, [_V]),
+        "ch_ensemble_step": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _I, _V, _V, _S,
+                                  _I, _V]),
         "chx_host_chunk_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _I, _IP]),
         "chx_host_whole_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _IP]),
     }
@@ -366,3 +372,64 @@ def chx_host_whole_tables(P: int, coef, n: int, periodic: bool = True):
     _check(lib.chx_host_whole_tables(P, cf, n, int(periodic), rec.ctypes.data_as(_DP), rec.size,
                                      minv.ctypes.data_as(_DP), ctypes.byref(mi)), "whole tables")
     return rec.reshape(mi.value, 8), minv.reshape(2, 2)
+
+
+# --------------------------------------------------------------------- ensembles
+class Ensemble:
+    """Handle of ch_ensemble_create: many independent runs (each a tuple
+    (nx, ny, lx, ly, D, gamma, dt)) advanced together."""
+
+    def __init__(self, runs):
+        lib = load()
+        arr = (ChParams * len(runs))(*[ChParams(nx, ny, lx, ly, D, g, dt, CHX_F64, 0)
+                                       for (nx, ny, lx, ly, D, g, dt) in runs])
+        h = ctypes.c_void_p()
+        _check(lib.ch_ensemble_create(len(runs), arr, ctypes.byref(h)), "ch_ensemble_create")
+        self.handle = h
+        self.nruns = len(runs)
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            load().ch_ensemble_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ch_ensemble_create(runs) -> Ensemble:
+    return Ensemble(runs)
+
+
+def ch_ensemble_destroy(e: Ensemble) -> None:
+    e.close()
+
+
+def ch_ensemble_ws_bytes(e: Ensemble) -> int:
+    return load().ch_ensemble_ws_bytes(e.handle)
+
+
+def ch_ensemble_step(e: Ensemble, fields, nsteps: int = 1, diag_out=None, use_graph: bool = True,
+                     ws=None, stream=None):
+    """Advance every run's float64 device field (list of (ny, nx) tensors) by
+    nsteps in place.  diag_out: optional float64 device tensor of
+    nruns * 2 * (nsteps + 1) values."""
+    import torch
+    lib = load()
+    if len(fields) != e.nruns:
+        raise ChxError(CHX_EINVAL, "one field per run")
+    nbytes = lib.ch_ensemble_ws_bytes(e.handle)
+    if ws is None:
+        if e._ws is None or e._ws.numel() < nbytes + 256:
+            e._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=fields[0].device)
+        ws = e._ws
+    _, wsp, avail = _workspace(nbytes, ws, fields[0].device)
+    ptrs = (ctypes.c_void_p * e.nruns)(*[_devptr(f, "field").value for f in fields])
+    lds = (ctypes.c_long * e.nruns)(*[f.stride(0) for f in fields])
+    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
+    _check(lib.ch_ensemble_step(e.handle, ptrs, lds, nsteps, dptr, wsp, avail, int(use_graph),
+                                _stream(stream)), "ch_ensemble_step")

@@ -11,6 +11,7 @@
 #include "ch_launch.hpp"
 #include "chx.h"
 #include "common.hpp"
+#include "ens.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
 
@@ -194,6 +195,82 @@ struct chx_ch_s {
     if (dscratch) (void)hipFree(dscratch);
   }
 };
+
+// ---------------------------------------------------------------------------
+// Uneven ensemble handle
+struct chx_ens_s {
+  int nruns = 0;
+  std::vector<chx_ch_params> prm;
+  std::vector<BandPlan*> px, py;  // per size class
+  std::vector<EnsRun> runs;       // host copy of the run table
+  std::vector<EnsClass> classes;
+  void* dmem = nullptr;           // run table, class table, work items
+  EnsRun* druns = nullptr;
+  EnsClass* dcls = nullptr;
+  int4* ditems = nullptr;
+  int n_col = 0, n_red = 0, n_row = 0, n_fin = 0, n_dpart = 0;
+  long o_col = 0, o_red = 0, o_row = 0, o_fin = 0, o_dpart = 0;
+  size_t ws_total = 0, red_lds = 0;
+  long max_points = 0;
+  // cached hipGraph of a whole call (nsteps, diag, ws)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;
+  int g_nsteps = -1;
+  double* g_diag = nullptr;
+  void* g_ws = nullptr;
+  ~chx_ens_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (auto* p : px) delete p;
+    for (auto* p : py) delete p;
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+namespace {
+
+bool same_grid(const chx_ch_params& a, const chx_ch_params& b) {
+  return a.nx == b.nx && a.ny == b.ny && a.lx == b.lx && a.ly == b.ly && a.D == b.D &&
+         a.gamma == b.gamma && a.dt == b.dt;
+}
+
+ChCoef make_coef(const chx_ch_params& q) {
+  const double dx = q.lx / q.nx, dy = q.ly / q.ny;
+  ChCoef K;
+  K.cx = q.D * q.dt / (dx * dx);
+  K.cy = q.D * q.dt / (dy * dy);
+  K.ccross = 2.0 * q.D * q.gamma * q.dt / (dx * dx * dy * dy);
+  K.inv_dx = 1.0 / dx;
+  K.inv_dy = 1.0 / dy;
+  K.half_gamma = 0.5 * q.gamma;
+  K.dxdy = dx * dy;
+  return K;
+}
+
+int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws,
+                   hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const long dstride = 2L * (nsteps + 1);
+  const int4* it = E->ditems;
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->druns, E->dcls, it + E->o_col,
+                               E->n_col, ws, n, st);
+    if (e == hipSuccess)
+      e = launch_ens_reduced(E->druns, E->dcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
+                             E->red_lds, st);
+    if (e == hipSuccess) e = launch_ens_rows(E->druns, E->dcls, it + E->o_row, E->n_row, ws, n, st);
+  }
+  if (e == hipSuccess)
+    e = launch_ens_finalize(E->druns, E->dcls, it + E->o_fin, E->n_fin, ws, nsteps - 1, st);
+  if (e == hipSuccess && diag_out)
+    e = launch_ens_diag(E->druns, E->dcls, it + E->o_dpart, E->n_dpart, E->nruns, ws, diag_out,
+                        dstride, nsteps, st);
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -500,6 +577,211 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass, double* ene
   *energy = host[1];
   if (!std::isfinite(host[0]) || !std::isfinite(host[1])) return CHX_ENONFINITE;
   return CHX_OK;
+}
+
+int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
+  if (!out || !prm || nruns < 1) return CHX_EINVAL;
+  *out = nullptr;
+  chx_ens_s* E = new (std::nothrow) chx_ens_s();
+  if (!E) return CHX_ENOMEM;
+  E->nruns = nruns;
+  E->prm.assign(prm, prm + nruns);
+  std::vector<int> cls_of(nruns, -1);
+  std::vector<chx_ch_params> reps;
+  for (int r = 0; r < nruns; ++r) {
+    const chx_ch_params& q = prm[r];
+    if (q.dtype != CHX_F64 || q.nx % 64 != 0 || q.ny % kChunk != 0 || q.nx / kChunk > 256 ||
+        !(q.lx > 0) || !(q.ly > 0) || !(q.dt > 0) || !(q.D >= 0) || !(q.gamma >= 0)) {
+      delete E;
+      return CHX_EINVAL;
+    }
+    for (size_t c = 0; c < reps.size(); ++c)
+      if (same_grid(reps[c], q)) cls_of[r] = (int)c;
+    if (cls_of[r] < 0) {
+      if ((int)reps.size() == kEnsMaxClasses) {
+        delete E;
+        return CHX_EINVAL;
+      }
+      cls_of[r] = (int)reps.size();
+      reps.push_back(q);
+    }
+  }
+  size_t lds_max = 0;
+  for (const auto& q : reps) {
+    const double dx = q.lx / q.nx, dy = q.ly / q.ny;
+    const double sx = q.D * q.gamma * q.dt / (dx * dx * dx * dx);
+    const double sy = q.D * q.gamma * q.dt / (dy * dy * dy * dy);
+    const double cxs[5] = {sx, -4 * sx, 1 + 6 * sx, -4 * sx, sx};
+    const double cys[5] = {sy, -4 * sy, 1 + 6 * sy, -4 * sy, sy};
+    BandPlan *a = nullptr, *b = nullptr;
+    int rc = make_plan(2, q.nx, cxs, 1, &a);
+    if (rc == CHX_OK) rc = make_plan(2, q.ny, cys, 1, &b);
+    if (rc == CHX_OK && (!a->has_chunk || !b->has_chunk)) rc = CHX_EINVAL;
+    E->px.push_back(a);
+    E->py.push_back(b);
+    if (rc != CHX_OK) {
+      delete E;
+      return rc;
+    }
+    EnsClass ec;
+    ec.px = a->dchunk;
+    ec.py = b->dchunk;
+    ec.K = make_coef(q);
+    E->classes.push_back(ec);
+    lds_max = std::max(lds_max, ens_reduced_lds_bytes(b->chunk.dcount));
+  }
+  if (lds_max > 64 * 1024) {
+    delete E;
+    return CHX_EINVAL;
+  }
+  E->red_lds = lds_max;
+  // workspace layout and run table; larger runs first in every work list
+  std::vector<int> order(nruns);
+  for (int r = 0; r < nruns; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long)prm[a].nx * prm[a].ny > (long)prm[b].nx * prm[b].ny;
+  });
+  size_t off = 0;
+  E->runs.resize(nruns);
+  for (int r = 0; r < nruns; ++r) {
+    const chx_ch_params& q = prm[r];
+    EnsRun& R = E->runs[r];
+    R.c = nullptr;
+    R.ldc = q.nx;
+    R.nx = q.nx;
+    R.ny = q.ny;
+    R.cls = cls_of[r];
+    R.ncb = ((q.nx >> 6) + 3) / 4;
+    R.Sc = q.ny / kChunk;
+    R.ndbx = (q.nx + 63) / 64;
+    R.ndby = (q.ny + 15) / 16;
+    R.ncolblocks = (long)R.ncb * R.Sc;
+    const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
+    R.off_b0 = off; off += field;
+    R.off_b1 = off; off += field;
+    R.off_rho = off; off += align256((size_t)R.Sc * 4 * q.nx * sizeof(double));
+    R.off_part = off;
+    off += align256((size_t)std::max(R.ncolblocks, (long)R.ndbx * R.ndby) * 2 * sizeof(double));
+    E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
+  }
+  E->ws_total = off;
+  std::vector<int4> items;
+  auto add = [&](int r, int a, int b) { items.push_back(make_int4(r, a, b, 0)); };
+  E->o_col = (long)items.size();
+  for (int r : order)
+    for (int kc = 0; kc < E->runs[r].Sc; ++kc)
+      for (int cb = 0; cb < E->runs[r].ncb; ++cb) add(r, cb, kc);
+  E->n_col = (int)(items.size() - E->o_col);
+  E->o_red = (long)items.size();
+  for (int r : order) {
+    const int nby = (E->runs[r].Sc + 31) / 32, nbx = (E->runs[r].nx + 63) / 64;
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) add(r, bx, by);
+  }
+  E->n_red = (int)(items.size() - E->o_red);
+  E->o_row = (long)items.size();
+  for (int r : order) {
+    const int S = E->runs[r].nx / kChunk, R = 256 / S;
+    const int ng = (E->runs[r].ny + R - 1) / R;
+    for (int g = 0; g < ng; ++g) add(r, g, 0);
+  }
+  E->n_row = (int)(items.size() - E->o_row);
+  E->o_fin = (long)items.size();
+  for (int r : order)
+    for (int by = 0; by < (E->runs[r].ny + 3) / 4; ++by)
+      for (int bx = 0; bx < (E->runs[r].nx + 63) / 64; ++bx) add(r, bx, by);
+  E->n_fin = (int)(items.size() - E->o_fin);
+  E->o_dpart = (long)items.size();
+  for (int r : order)
+    for (int by = 0; by < E->runs[r].ndby; ++by)
+      for (int bx = 0; bx < E->runs[r].ndbx; ++bx) add(r, bx, by);
+  E->n_dpart = (int)(items.size() - E->o_dpart);
+  const size_t b_runs = align256(sizeof(EnsRun) * nruns);
+  const size_t b_cls = align256(sizeof(EnsClass) * E->classes.size());
+  const size_t b_items = align256(sizeof(int4) * items.size());
+  if (hipMalloc(&E->dmem, b_runs + b_cls + b_items) != hipSuccess) {
+    E->dmem = nullptr;
+    delete E;
+    return CHX_EHIP;
+  }
+  auto* base = static_cast<unsigned char*>(E->dmem);
+  E->druns = reinterpret_cast<EnsRun*>(base);
+  E->dcls = reinterpret_cast<EnsClass*>(base + b_runs);
+  E->ditems = reinterpret_cast<int4*>(base + b_runs + b_cls);
+  if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * nruns, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(E->dcls, E->classes.data(), sizeof(EnsClass) * E->classes.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(E->ditems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    delete E;
+    return CHX_EHIP;
+  }
+  *out = E;
+  return CHX_OK;
+}
+
+int ch_ensemble_destroy(chx_ens e) {
+  delete e;
+  return CHX_OK;
+}
+
+size_t ch_ensemble_ws_bytes(chx_ens e) { return e ? e->ws_total : 0; }
+
+int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int nsteps,
+                     double* diag_out, void* ws, size_t ws_bytes, int use_graph, chx_stream s) {
+  if (!E || !c_runs || nsteps < 1) return CHX_EINVAL;
+  if (!ws || ws_bytes < E->ws_total) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  bool changed = false;
+  for (int r = 0; r < E->nruns; ++r) {
+    if (!c_runs[r]) return CHX_EINVAL;
+    const long ld = ld_runs ? ld_runs[r] : E->runs[r].nx;
+    if (ld < E->runs[r].nx) return CHX_EINVAL;
+    if (E->runs[r].c != c_runs[r] || E->runs[r].ldc != ld) {
+      E->runs[r].c = c_runs[r];
+      E->runs[r].ldc = ld;
+      changed = true;
+    }
+  }
+  if (changed) {  // work already queued may still read the table
+    if (hipStreamSynchronize(st) != hipSuccess) return CHX_EHIP;
+    if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * E->nruns, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return CHX_EHIP;
+  }
+  auto* w = static_cast<unsigned char*>(ws);
+  if (!use_graph) return ens_launch_all(E, nsteps, diag_out, w, st);
+  if (!E->gexec || E->g_nsteps != nsteps || E->g_diag != diag_out || E->g_ws != ws) {
+    if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
+    if (E->graph) (void)hipGraphDestroy(E->graph);
+    E->gexec = nullptr;
+    E->graph = nullptr;
+    if (!E->cap && hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking) != hipSuccess) {
+      E->cap = nullptr;
+      return CHX_EHIP;
+    }
+    if (hipStreamBeginCapture(E->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return CHX_EHIP;
+    int rc = ens_launch_all(E, nsteps, diag_out, w, E->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(E->cap, &g);
+    if (rc != CHX_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != CHX_OK ? rc : CHX_EHIP;
+    }
+    if (hipGraphInstantiate(&E->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      E->gexec = nullptr;
+      return CHX_EHIP;
+    }
+    E->graph = g;
+    E->g_nsteps = nsteps;
+    E->g_diag = diag_out;
+    E->g_ws = ws;
+  }
+  return hipGraphLaunch(E->gexec, st) == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
 // Host-side plan inspection (no device work): the factorisation tables that

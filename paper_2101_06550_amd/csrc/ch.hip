@@ -23,6 +23,7 @@
 
 #include "ch_launch.hpp"
 #include "common.hpp"
+#include "ens.hpp"
 
 namespace chx {
 
@@ -87,19 +88,21 @@ __device__ __forceinline__ double recon_row(double v, int q, const double* __res
   return recon_value<RECON>(v, q - 1, rec, tp, to);
 }
 
+// Body shared by the single-field kernel and the ensemble kernel: column
+// block cb (256 columns), chunk kc; slot = where this block's (mass, energy)
+// partial goes (DIAG only).
 template <bool RECON, bool DIAG>
-__global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
-                                                      double* __restrict__ ybuf, long ldy, int nx,
-                                                      int ny, int Sc,
-                                                      const double* __restrict__ rec,
-                                                      BandT<double> bd, double* __restrict__ rho,
-                                                      ChCoef K, double* __restrict__ part) {
+__device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
+                                                 double* __restrict__ ybuf, long ldy, int nx,
+                                                 int ny, int Sc, const double* __restrict__ rec,
+                                                 const BandT<double>& bd, double* __restrict__ rho,
+                                                 const ChCoef& K, double* __restrict__ slot,
+                                                 int cb, int kc) {
   __shared__ double red[8];
   __shared__ double edge[10][M + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kc = blockIdx.y;
   const int nseg = nx >> 6;
-  const int seg0 = blockIdx.x * 4;
+  const int seg0 = cb * 4;
   const int nw = (nseg - seg0 < 4) ? nseg - seg0 : 4;  // active waves of this block
   const bool live = wave < nw;
   const int i = (seg0 + wave) * 64 + lane;
@@ -223,20 +226,32 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
   if (DIAG) {
     block_sum2(msum, esum, red);
     if (threadIdx.x == 0) {
-      const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
-      part[2 * b] = msum;
-      part[2 * b + 1] = esum;
+      slot[0] = msum;
+      slot[1] = esum;
     }
   }
 }
 
-// State X = V - Zl T_prev - Zr T_own written out to the caller's array.
-__global__ __launch_bounds__(256) void ch_finalize(const double* __restrict__ src, long lds,
-                                                   double* __restrict__ dst, long ldd, int nx,
-                                                   int ny, int Sc,
-                                                   const double* __restrict__ rec) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+template <bool RECON, bool DIAG>
+__global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
+                                                      double* __restrict__ ybuf, long ldy, int nx,
+                                                      int ny, int Sc,
+                                                      const double* __restrict__ rec,
+                                                      BandT<double> bd, double* __restrict__ rho,
+                                                      ChCoef K, double* __restrict__ part) {
+  const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+  column_pass_body<RECON, DIAG>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
+                                DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y);
+}
+
+// State X = V - Zl T_prev - Zr T_own written out to the caller's array;
+// block (bx, by) covers 64 columns x 4 rows.
+__device__ __forceinline__ void finalize_body(const double* __restrict__ src, long lds,
+                                              double* __restrict__ dst, long ldd, int nx, int ny,
+                                              int Sc, const double* __restrict__ rec, int bx,
+                                              int by) {
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int j = by * 4 + (threadIdx.x >> 6);
   if (i >= nx || j >= ny) return;
   const int kc = j / M, p = j - kc * M;
   double v = src[(long)j * lds + i];
@@ -252,14 +267,21 @@ __global__ __launch_bounds__(256) void ch_finalize(const double* __restrict__ sr
   dst[(long)j * ldd + i] = v;
 }
 
+__global__ __launch_bounds__(256) void ch_finalize(const double* __restrict__ src, long lds,
+                                                   double* __restrict__ dst, long ldd, int nx,
+                                                   int ny, int Sc,
+                                                   const double* __restrict__ rec) {
+  finalize_body(src, lds, dst, ldd, nx, ny, Sc, rec, blockIdx.x, blockIdx.y);
+}
+
 // Mass and free-energy partial sums of a plain field, one per block of
 // 64 columns x 16 rows (fixed order within the block).
-__global__ __launch_bounds__(256) void ch_diag_partial(const double* __restrict__ c, long ld,
-                                                       int nx, int ny, ChCoef K,
-                                                       double* __restrict__ part) {
+__device__ __forceinline__ void diag_partial_body(const double* __restrict__ c, long ld, int nx,
+                                                  int ny, const ChCoef& K,
+                                                  double* __restrict__ slot, int bx, int by) {
   __shared__ double red[8];
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int j0 = by * 16 + (threadIdx.x >> 6) * 4;
   double ms = 0.0, es = 0.0;
   if (i < nx) {
     const int ip = (i + 1) % nx;
@@ -277,17 +299,23 @@ __global__ __launch_bounds__(256) void ch_diag_partial(const double* __restrict_
   }
   block_sum2(ms, es, red);
   if (threadIdx.x == 0) {
-    const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
-    part[2 * b] = ms;
-    part[2 * b + 1] = es;
+    slot[0] = ms;
+    slot[1] = es;
   }
+}
+
+__global__ __launch_bounds__(256) void ch_diag_partial(const double* __restrict__ c, long ld,
+                                                       int nx, int ny, ChCoef K,
+                                                       double* __restrict__ part) {
+  const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+  diag_partial_body(c, ld, nx, ny, K, part + 2 * b, blockIdx.x, blockIdx.y);
 }
 
 // Fixed-order final sum of nparts (mass, energy) pairs, scaled by dx dy.
 // Each thread owns a contiguous slice and issues 8 independent loads per
 // round; the partial sums are then combined by a fixed tree.
-__global__ __launch_bounds__(256) void ch_diag_final(const double* __restrict__ part, long nparts,
-                                                     double scale, double* __restrict__ out) {
+__device__ __forceinline__ void diag_final_body(const double* __restrict__ part, long nparts,
+                                                double scale, double* __restrict__ out) {
   __shared__ double sm[256], se[256];
   const long per = (nparts + 255) / 256;
   const long b0 = (long)threadIdx.x * per, b1 = (b0 + per < nparts) ? b0 + per : nparts;
@@ -321,6 +349,11 @@ __global__ __launch_bounds__(256) void ch_diag_final(const double* __restrict__ 
     out[0] = sm[0] * scale;
     out[1] = se[0] * scale;
   }
+}
+
+__global__ __launch_bounds__(256) void ch_diag_final(const double* __restrict__ part, long nparts,
+                                                     double scale, double* __restrict__ out) {
+  diag_final_body(part, nparts, scale, out);
 }
 
 // Plain RHS kernel for grids the fused path does not cover.
@@ -393,6 +426,93 @@ hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, in
                                const ChCoef& K, hipStream_t st) {
   dim3 grid((nx + 63) / 64, (ny + 3) / 4);
   hipLaunchKernelGGL(ch_rhs_plain, grid, dim3(256), 0, st, c, ld, r, ldr, nx, ny, K);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
+__device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, int step) {
+  return reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+}
+
+template <bool RECON, bool DIAG>
+__global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict__ runs,
+                                                       const EnsClass* __restrict__ cls,
+                                                       const int4* __restrict__ items,
+                                                       unsigned char* ws, int step) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const EnsClass& C = cls[R.cls];
+  const double* src = (step == 0) ? R.c : ens_buf(ws, R, step - 1);
+  const long lds = (step == 0) ? R.ldc : (long)R.nx;
+  BandT<double> bd;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) bd.c[k] = C.py.coef[k];
+  double* part = reinterpret_cast<double*>(ws + R.off_part);
+  double* rho = reinterpret_cast<double*>(ws + R.off_rho);
+  column_pass_body<RECON, DIAG>(src, lds, ens_buf(ws, R, step), R.nx, R.nx, R.ny, R.Sc, C.py.rec,
+                                bd, rho, C.K, DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
+                                it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) void ens_finalize(const EnsRun* __restrict__ runs,
+                                                    const EnsClass* __restrict__ cls,
+                                                    const int4* __restrict__ items,
+                                                    unsigned char* ws, int last_step) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  finalize_body(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx, R.ny, R.Sc, cls[R.cls].py.rec,
+                it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) void ens_diag_partial(const EnsRun* __restrict__ runs,
+                                                        const EnsClass* __restrict__ cls,
+                                                        const int4* __restrict__ items,
+                                                        unsigned char* ws) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  double* part = reinterpret_cast<double*>(ws + R.off_part);
+  diag_partial_body(R.c, R.ldc, R.nx, R.ny, cls[R.cls].K,
+                    part + 2 * ((long)it.z * R.ndbx + it.y), it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__ runs,
+                                                      const EnsClass* __restrict__ cls,
+                                                      unsigned char* ws, double* diag_out,
+                                                      long diag_stride, int index) {
+  const EnsRun R = runs[blockIdx.x];
+  const double* part = reinterpret_cast<const double*>(ws + R.off_part);
+  diag_final_body(part, (long)R.ndbx * R.ndby, cls[R.cls].K.dxdy,
+                  diag_out + blockIdx.x * diag_stride + 2 * (long)index);
+}
+
+hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, const EnsClass* cls,
+                                  const int4* items, int nitems, unsigned char* ws, int step,
+                                  hipStream_t st) {
+#define CHX_ENSCOL(R, D)                                                                        \
+  hipLaunchKernelGGL((ens_column_pass<R, D>), dim3(nitems), dim3(256), 0, st, runs, cls, items, \
+                     ws, step)
+  if (recon && diag) CHX_ENSCOL(true, true);
+  else if (recon) CHX_ENSCOL(true, false);
+  else if (diag) CHX_ENSCOL(false, true);
+  else CHX_ENSCOL(false, false);
+#undef CHX_ENSCOL
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClass* cls, const int4* items,
+                               int nitems, unsigned char* ws, int last_step, hipStream_t st) {
+  hipLaunchKernelGGL(ens_finalize, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws,
+                     last_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_diag(const EnsRun* runs, const EnsClass* cls, const int4* items, int nitems,
+                           int nruns, unsigned char* ws, double* diag_out, long diag_stride,
+                           int index, hipStream_t st) {
+  hipLaunchKernelGGL(ens_diag_partial, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws);
+  hipLaunchKernelGGL(ens_diag_final, dim3(nruns), dim3(256), 0, st, runs, cls, ws, diag_out,
+                     diag_stride, index);
   return hipGetLastError();
 }
 

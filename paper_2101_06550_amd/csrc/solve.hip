@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "ens.hpp"
 #include "launch.hpp"
 
 namespace chx {
@@ -206,9 +207,10 @@ __device__ __forceinline__ void row_group_stage(T* tile, const double* x, long l
 }
 
 template <int P, int M, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds(
-    double* x, long ld, int rows, int n, int S, int R, const T* __restrict__ rec, BandT<T> bd,
-    const T* __restrict__ blocks, int dlo, int dcount) {
+__device__ __forceinline__ void row_solve_body(double* x, long ld, int rows, int n, int S, int R,
+                                               const T* __restrict__ rec, const BandT<T>& bd,
+                                               const T* __restrict__ blocks, int dlo, int dcount,
+                                               long group) {
   __shared__ T tile[256 * (M + 1)];
   __shared__ T rhol[256 * 2 * P];
   __shared__ T sepl[256 * P];
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   const int r = t / S, k = t - r * S;
   const bool dense = (ld == n);
   {
-    const long row0 = (long)blockIdx.x * R;
+    const long row0 = group * R;
     row_group_stage<P, M, T>(tile, x, ld, rows, n, row0, nel, t, dense);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
@@ -311,6 +313,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   }
 }
 
+template <int P, int M, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds(
+    double* x, long ld, int rows, int n, int S, int R, const T* __restrict__ rec, BandT<T> bd,
+    const T* __restrict__ blocks, int dlo, int dcount) {
+  row_solve_body<P, M, T>(x, ld, rows, n, S, R, rec, bd, blocks, dlo, dcount, blockIdx.x);
+}
+
 // Reduced separator system with an LDS window: a block (8 waves) owns 64
 // systems and KB = 8 G consecutive chunks; it stages rho_j = pa_j - pb_{j+1}
 // for the KB + dcount - 1 chunks its convolutions touch, then each wave
@@ -322,18 +331,17 @@ constexpr int kRedWaves = 8;
 constexpr int kRedKB = kRedG * kRedWaves;
 
 template <int P, typename T>
-__global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
-                                                      const T* __restrict__ blocks, int dlo,
-                                                      int dcount, double* __restrict__ dst,
-                                                      long ld, int drow_stride, int drow_off,
-                                                      const double* __restrict__ dpart,
-                                                      long dnparts, double dscale,
-                                                      double* __restrict__ dout) {
+__device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batch, int S,
+                                             const T* __restrict__ blocks, int dlo, int dcount,
+                                             double* __restrict__ dst, long ld, int drow_stride,
+                                             int drow_off, const double* __restrict__ dpart,
+                                             long dnparts, double dscale,
+                                             double* __restrict__ dout, int bx, int by) {
   extern __shared__ unsigned char smraw[];
   T* sm = reinterpret_cast<T*>(smraw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long s = (long)blockIdx.x * 64 + lane;
-  const int k0 = blockIdx.y * kRedKB;
+  const long s = (long)bx * 64 + lane;
+  const int k0 = by * kRedKB;
   const int nwin = kRedKB + dcount - 1;
   const bool sv = s < batch;
   constexpr int U = 4;
@@ -396,7 +404,7 @@ __global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho,
       }
     }
   }
-  if (dout != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {
+  if (dout != nullptr) {  // the caller passes dout to one block only
     __syncthreads();
     double* sm2 = reinterpret_cast<double*>(smraw);
     const int nt = blockDim.x;
@@ -434,6 +442,73 @@ __global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho,
       dout[1] = sm2[nt] * dscale;
     }
   }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
+                                                      const T* __restrict__ blocks, int dlo,
+                                                      int dcount, double* __restrict__ dst,
+                                                      long ld, int drow_stride, int drow_off,
+                                                      const double* __restrict__ dpart,
+                                                      long dnparts, double dscale,
+                                                      double* __restrict__ dout) {
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  reduced_body<P, T>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride, drow_off, dpart,
+                     dnparts, dscale, first ? dout : nullptr, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
+__global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ runs,
+                                                   const EnsClass* __restrict__ cls,
+                                                   const int4* __restrict__ items,
+                                                   unsigned char* ws, int step, double* diag_out,
+                                                   long diag_stride) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const DevChunk& c = cls[R.cls].py;
+  double* dst = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+  const double* rho = reinterpret_cast<const double*>(ws + R.off_rho);
+  const double* part = reinterpret_cast<const double*>(ws + R.off_part);
+  double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
+                     ? diag_out + it.x * diag_stride + 2 * (long)step
+                     : nullptr;
+  reduced_body<2, double>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx, kChunk,
+                          kChunk - 2, part, R.ncolblocks, cls[R.cls].K.dxdy, dout, it.y, it.z);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ens_rows(
+    const EnsRun* __restrict__ runs, const EnsClass* __restrict__ cls,
+    const int4* __restrict__ items, unsigned char* ws, int step) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const DevChunk& c = cls[R.cls].px;
+  BandT<double> bd;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) bd.c[k] = c.coef[k];
+  double* x = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+  row_solve_body<2, kChunk, double>(x, R.nx, R.ny, R.nx, c.S, 256 / c.S, c.rec, bd, c.blocks,
+                                    c.dlo, c.dcount, it.y);
+}
+
+hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClass* cls, const int4* items,
+                              int nitems, unsigned char* ws, int step, double* diag_out,
+                              long diag_stride, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(ens_reduced, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs, cls,
+                     items, ws, step, diag_out, diag_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_rows(const EnsRun* runs, const EnsClass* cls, const int4* items, int nitems,
+                           unsigned char* ws, int step, hipStream_t st) {
+  hipLaunchKernelGGL(ens_rows, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, step);
+  return hipGetLastError();
+}
+
+size_t ens_reduced_lds_bytes(int dcount) {
+  size_t lds = (size_t)(kRedKB + dcount - 1) * 2 * 64 * sizeof(double);
+  if (lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
+  return lds;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,128 @@
+"""GPU parity of the uneven ensemble path (one launch per phase for all runs,
+hipGraph replay) against the oracle and against the single-field path."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2101_06550_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def chx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_06550_amd import chx as m
+    m.load()
+    return m
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# (nx, ny, D, gamma, dt, seed): several size classes and parameter classes
+RUNS = [(64, 64, 1.0, 0.01, 1e-4, 1000), (64, 64, 1.0, 0.01, 1e-4, 1001),
+        (128, 128, 1.0, 0.01, 1e-4, 1002), (256, 128, 1.0, 0.01, 1e-4, 1003),
+        (128, 128, 1.0, 0.02, 5e-5, 1004), (512, 512, 1.0, 0.01, 1e-4, 1005),
+        (64, 96, 1.0, 0.01, 1e-4, 1006), (128, 128, 1.0, 0.01, 1e-4, 1007)]
+
+
+def make(chx, runs):
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs])
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, _, _, _, seed) in runs]
+    return ens, c0
+
+
+def test_one_step_each_run_vs_oracle(chx, orc):
+    ens, c0 = make(chx, RUNS)
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    print("[case] ensemble one step, 8 runs", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=1, use_graph=False)
+    torch.cuda.synchronize()
+    for (nx, ny, D, g, dt, seed), c, f in zip(RUNS, c0, fields):
+        ref = orc.ch_step(c, L, L, D, g, dt)
+        assert rel(f.cpu().numpy(), ref) < 1e-12, (nx, ny, seed)
+
+
+def test_multistep_bitwise_equals_single_field_path(chx):
+    ens, c0 = make(chx, RUNS)
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    n = 5
+    diag = torch.zeros(len(RUNS) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    print("[case] ensemble 5 steps vs single-field", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=n, diag_out=diag, use_graph=False)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(RUNS), n + 1, 2)
+    for r, ((nx, ny, D, g, dt, seed), c) in enumerate(zip(RUNS, c0)):
+        h = chx.ch_create(nx, ny, L, L, D, g, dt)
+        single = torch.tensor(c, device="cuda")
+        sd = torch.zeros(2 * (n + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, single, nsteps=n, diag_out=sd)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), fields[r].cpu().numpy()), r
+        assert np.array_equal(sd.cpu().numpy().reshape(n + 1, 2), d[r]), r
+
+
+def test_graph_replays_match_eager(chx):
+    """The captured graph is replayed several times, with eager launches and
+    synchronisations in between; every replay must equal the eager result."""
+    ens_g, c0 = make(chx, RUNS)
+    ens_e, _ = make(chx, RUNS)
+    fg = [torch.tensor(c, device="cuda") for c in c0]
+    fe = [torch.tensor(c, device="cuda") for c in c0]
+    n = 3
+    dg = torch.zeros(len(RUNS) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    de = torch.zeros_like(dg)
+    for rep in range(4):
+        print(f"[case] ensemble graph replay {rep}", flush=True)
+        chx.ch_ensemble_step(ens_g, fg, nsteps=n, diag_out=dg, use_graph=True)
+        chx.ch_ensemble_step(ens_e, fe, nsteps=n, diag_out=de, use_graph=False)
+        torch.cuda.synchronize()
+        for a, b in zip(fg, fe):
+            assert torch.equal(a, b), rep
+        assert torch.equal(dg, de), rep
+
+
+def test_new_field_pointers_are_picked_up(chx, orc):
+    ens, c0 = make(chx, RUNS[:3])
+    f1 = [torch.tensor(c, device="cuda") for c in c0]
+    chx.ch_ensemble_step(ens, f1, nsteps=1)
+    f2 = [torch.tensor(c, device="cuda") for c in c0]
+    chx.ch_ensemble_step(ens, f2, nsteps=1)
+    torch.cuda.synchronize()
+    for a, b in zip(f1, f2):
+        assert torch.equal(a, b)
+
+
+def test_invalid_runs_rejected(chx):
+    with pytest.raises(chx.ChxError):
+        chx.ch_ensemble_create([(100, 64, L, L, 1.0, 0.01, 1e-4)])
+    with pytest.raises(chx.ChxError):
+        chx.ch_ensemble_create([(64, 70, L, L, 1.0, 0.01, 1e-4)])
+
+
+def test_uneven_workload_full_size(chx, orc):
+    """96 x 128^2 + 96 x 256^2 + 64 x 512^2 runs (seeds 1000-1255): every run
+    advanced one step in one ensemble call (graph), mass conserved in every
+    run, and one run of each size checked against the oracle."""
+    sizes = [128] * 96 + [256] * 96 + [512] * 64
+    runs = [(n, n, 1.0, 0.01, 1e-4, 1000 + r) for r, n in enumerate(sizes)]
+    ens, c0 = make(chx, runs)
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    diag = torch.zeros(len(runs) * 4, dtype=torch.float64, device="cuda")
+    print("[case] ensemble 256 runs one step", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=1, diag_out=diag, use_graph=True)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(runs), 2, 2)
+    for r, (n, c) in enumerate(zip(sizes, c0)):
+        l1 = np.sum(np.abs(c)) * (L / n) ** 2
+        assert abs(d[r, 1, 0] - d[r, 0, 0]) / l1 < 1e-12
+    for r in (0, 96, 192, 255):
+        n = sizes[r]
+        ref = orc.ch_step(c0[r], L, L, 1.0, 0.01, 1e-4)
+        assert rel(fields[r].cpu().numpy(), ref) < 1e-12, r
