@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -53,13 +55,18 @@ def reduced_bytes(nx, ny):
 
 
 def cpu_baseline(c0, L, D, gamma, dt, budget_s=12.0, max_steps=3):
+    """The oracle timed on the host (one thread) on a bounded sample of the
+    workload; also returns its first step for the GPU error check."""
     import oracle
     orc = oracle.oracle()
     n = c0.size
     steps, t0 = 0, time.perf_counter()
     c = c0
+    first = None
     while steps < max_steps:
         c = orc.ch_step(c, L, L, D, gamma, dt)
+        if first is None:
+            first = c
         steps += 1
         if time.perf_counter() - t0 > budget_s:
             break
@@ -67,7 +74,7 @@ def cpu_baseline(c0, L, D, gamma, dt, budget_s=12.0, max_steps=3):
     return {"value": n * steps / el, "unit": "grid-point updates/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{steps} serial FP64 oracle ADI steps of the {c0.shape[1]}x{c0.shape[0]} "
-                      f"workload ({el:.1f} s, single thread)"}
+                      f"workload ({el:.1f} s, single thread)"}, first
 
 
 def solve_throughput(chx, torch, reps=10):
@@ -106,6 +113,118 @@ def solve_throughput(chx, torch, reps=10):
     return out
 
 
+def ensemble_throughput(chx, torch, steps=2000, warmup=20):
+    """Uneven ensemble: 96 x 128^2 + 96 x 256^2 + 64 x 512^2 runs (seeds
+    1000-1255, U[-0.1, 0.1]), D = 1, gamma = 0.01, dt = 1e-4, FP64; all runs
+    advance together (one launch per phase, whole call replayed as a graph)."""
+    from paper_2101_06550_amd import inputs
+    L = 2 * math.pi
+    sizes = [128] * 96 + [256] * 96 + [512] * 64
+    ens = chx.ch_ensemble_create([(n, n, L, L, 1.0, 0.01, 1e-4) for n in sizes])
+    fields = [torch.tensor(inputs.noise_field(n, n, 1000 + r), device="cuda")
+              for r, n in enumerate(sizes)]
+    points = sum(n * n for n in sizes)
+    out = {"runs": len(sizes), "points_per_step": points}
+    for name, graph, k in (("graph", True, steps), ("eager", False, min(steps, 200))):
+        chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=graph)  # warm (and capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=graph)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
+                     "updates_per_s": points * k / el,
+                     "algorithmic_GBps": round(34.0 * points * k / el / 1e9, 1)}
+    del fields, ens
+    return out
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def solve_precision(chx, torch, reps=20):
+    """1024 cyclic penta (alpha = 0.5) and tri (beta = 0.5) systems of
+    N = 1024, RHS ~ U[-1, 1] (seed 2): FP64 vs FP32 sweeps + FP64-residual
+    refinement, time per batch and error vs the oracle."""
+    import oracle
+    from paper_2101_06550_amd import inputs
+    orc = oracle.oracle()
+    n = batch = 1024
+    f = inputs.uniform(2, (n, batch), -1, 1)
+    out = {}
+    for kind, co in (("penta", (0.5, -2.0, 4.0, -2.0, 0.5)), ("tri", (-0.5, 2.0, -0.5))):
+        plan = chx.penta_factor(n, *co) if kind == "penta" else chx.tri_factor(n, *co)
+        solve = chx.penta_solve_batch if kind == "penta" else chx.tri_solve_batch
+        for layout, lname in ((0, "interleaved"), (1, "contiguous")):
+            fl = f if layout == 0 else np.ascontiguousarray(f.T)
+            ref = (orc.cpenta_lines if kind == "penta" else orc.ctri_lines)(
+                fl, 1 if layout == 0 else 0, co)
+            for dtype, passes, tag in ((chx.CHX_F64, 0, "f64"), (chx.CHX_F32_REFINED, 1, "f32r1"),
+                                       (chx.CHX_F32_REFINED, 2, "f32r2")):
+                x0 = torch.tensor(fl, device="cuda")
+                x = x0.clone()
+                ws = torch.empty(chx.penta_solve_ws_bytes(plan, batch, layout, dtype) + 256
+                                 if kind == "penta" else
+                                 chx.tri_solve_ws_bytes(plan, batch, layout, dtype) + 256,
+                                 dtype=torch.uint8, device="cuda")
+                solve(plan, batch, x, layout=layout, dtype=dtype, refine_passes=passes, ws=ws)
+                torch.cuda.synchronize()
+                err = rel_inf(x.cpu().numpy(), ref)
+                xs = [x0.clone() for _ in range(reps)]
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for xi in xs:
+                    solve(plan, batch, xi, layout=layout, dtype=dtype, refine_passes=passes, ws=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                out[f"{kind}_{lname}_{tag}"] = {"ms": round(ms, 5),
+                                                "solves_per_s": batch / (ms * 1e-3),
+                                                "rel_err_vs_oracle": err}
+    return out
+
+
+def precision_run(chx, torch, steps=10000, every=1000):
+    """1024^2, U[-0.1, 0.1] (seed 3), D = 1, gamma = 0.01, dt = 1e-5: FP64 vs
+    FP32-refined (1 and 2 passes) trajectories, L-inf difference from the FP64
+    trajectory every 1000 steps, and the one-step error vs the oracle from the
+    FP64 state at those steps."""
+    import oracle
+    from paper_2101_06550_amd import inputs
+    orc = oracle.oracle()
+    L = 2 * math.pi
+    n, D, g, dt = 1024, 1.0, 0.01, 1e-5
+    c0 = inputs.noise_field(n, n, 3)
+    hs = {"f64": chx.ch_create(n, n, L, L, D, g, dt),
+          "f32r1": chx.ch_create(n, n, L, L, D, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=1),
+          "f32r2": chx.ch_create(n, n, L, L, D, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=2)}
+    fields = {k: torch.tensor(c0, device="cuda") for k in hs}
+    out = {k: {"ms_per_step": 0.0, "linf_vs_f64": [], "one_step_rel_err_vs_oracle": []}
+           for k in hs}
+    for m in range(0, steps, every):
+        ref_state = fields["f64"].cpu().numpy()
+        ref_next = orc.ch_step(ref_state, L, L, D, g, dt)
+        for k, h in hs.items():
+            probe = torch.tensor(ref_state, device="cuda")
+            chx.ch_adi_step(h, probe, nsteps=1)
+            torch.cuda.synchronize()
+            out[k]["one_step_rel_err_vs_oracle"].append(rel_inf(probe.cpu().numpy(), ref_next))
+        for k, h in hs.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chx.ch_adi_step(h, fields[k], nsteps=every)
+            torch.cuda.synchronize()
+            out[k]["ms_per_step"] += 1e3 * (time.perf_counter() - t0) / steps
+        base = fields["f64"].cpu().numpy()
+        for k in hs:
+            out[k]["linf_vs_f64"].append(float(np.max(np.abs(fields[k].cpu().numpy() - base))))
+    for k in hs:
+        out[k]["ms_per_step"] = round(out[k]["ms_per_step"], 5)
+        out[k]["updates_per_s"] = n * n / (out[k]["ms_per_step"] * 1e-3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +233,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the "
                          "reference kernel for scaling hardware byte counters)")
@@ -123,7 +244,6 @@ def main():
               "decomposition is described in DESIGN.md and not run here.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2101_06550_amd import chx, inputs
@@ -198,10 +318,43 @@ def main():
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)
 
+    if not args.no_ensemble:
+        log("uneven ensemble")
+        extra["ensemble_256_runs_fp64"] = ensemble_throughput(chx, torch)
+
+    if not args.no_precision:
+        log("FP64 vs FP32-refined: batched solves")
+        extra["solves_N1024_batch1024_f64_vs_f32_refined"] = solve_precision(chx, torch)
+        log("FP64 vs FP32-refined: 1024^2 precision run")
+        extra["precision_run_1024"] = precision_run(chx, torch)
+
+    # the large workload with the FP32-sweep refined path (3 passes)
+    log("large workload, FP32-refined (3 passes)")
+    hr = chx.ch_create(n, n, L, L, D, gamma, dt, dtype=chx.CHX_F32_REFINED, refine_passes=3)
+    cr = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(hr, cr, nsteps=2)
+    torch.cuda.synchronize()
+    kr = max(1, min(K, 50))
+    t0 = time.perf_counter()
+    chx.ch_adi_step(hr, cr, nsteps=kr)
+    torch.cuda.synchronize()
+    elr = time.perf_counter() - t0
+    extra["large_f32_refined_3pass"] = {"steps": kr, "ms_per_step": round(1e3 * elr / kr, 5),
+                                        "updates_per_s": n * n * kr / elr}
+    del cr
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
-        cpu = cpu_baseline(c0, L, D, gamma, dt)
+        cpu, first = cpu_baseline(c0, L, D, gamma, dt)
+        errs = {}
+        for tag, h_ in (("f64", h), ("f32_refined_3pass", hr)):
+            probe = torch.tensor(c0, device="cuda")
+            chx.ch_adi_step(h_, probe, nsteps=1)
+            torch.cuda.synchronize()
+            errs[tag] = rel_inf(probe.cpu().numpy(), first)
+            del probe
+        extra["large_one_step_rel_err_vs_oracle"] = errs
 
     res = {
         "metric": METRIC,

@@ -153,11 +153,17 @@ typedef struct {
   int nx, ny;            /* grid points (>= 5 each)                        */
   double lx, ly;         /* box lengths (the thesis uses 2 pi)            */
   double D, gamma, dt;   /* mobility, interface parameter, time step      */
-  int dtype;             /* CHX_F64 or CHX_F32_REFINED                    */
+  int dtype;             /* CHX_F64 or CHX_F32_REFINED (see below)       */
   int refine_passes;     /* 1..3 for CHX_F32_REFINED, ignored for FP64    */
 } chx_ch_params;
 
-/* ch_create: factor both directions once and pick the kernel shapes.
+/* dtype CHX_F32_REFINED: the right-hand side is formed in FP64, the column
+ * and row sweeps run in FP32 (FP32 copies of the factorisation), and
+ * refine_passes (1..3) passes of R = r - (I + sx Px)(I + sy Py) c in FP64,
+ * c += (FP32 solve of R) recover FP64 accuracy.  It needs the chunked shapes
+ * (nx % 64 == 0, ny % 32 == 0, nx <= 8192), else CHX_EINVAL.
+ *
+ * ch_create: factor both directions once and pick the kernel shapes.
  * ch_destroy: free (NULL accepted).  ch_ws_bytes: workspace for ch_adi_step. */
 int ch_create(const chx_ch_params* prm, chx_ch* out);
 int ch_destroy(chx_ch h);

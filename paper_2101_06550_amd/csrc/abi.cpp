@@ -125,12 +125,82 @@ int make_plan(int P, int n, const double* coef, int periodic, PlanT** out) {
   return CHX_OK;
 }
 
+// Workspace of one batched solve.  FP64: the separator partials of the
+// chunked interleaved path.  FP32-refined: a compact copy of the right-hand
+// sides, a compact residual buffer, and (chunked interleaved) FP32 chunk
+// solutions and FP32 separator partials.
+struct SolveWs {
+  size_t f = 0, r = 0, y32 = 0, rho32 = 0, total = 0;
+};
+
+SolveWs solve_ws_layout(const BandPlan* p, int batch, int layout, int dtype) {
+  SolveWs w;
+  if (!p || batch <= 0) return w;
+  const bool chunk_il = layout == CHX_INTERLEAVED && p->has_chunk;
+  if (dtype == CHX_F64) {
+    if (chunk_il) w.total = align256((size_t)p->chunk.S * 2 * p->P * (size_t)batch * sizeof(double));
+    return w;
+  }
+  size_t off = 0;
+  const size_t nb = (size_t)p->n * batch;
+  w.f = off; off += align256(nb * sizeof(double));
+  w.r = off; off += align256(nb * sizeof(double));
+  if (chunk_il) {
+    w.y32 = off; off += align256(nb * sizeof(float));
+    w.rho32 = off; off += align256((size_t)p->chunk.S * 2 * p->P * (size_t)batch * sizeof(float));
+  }
+  w.total = off;
+  return w;
+}
+
 size_t solve_ws(const BandPlan* p, int batch, int layout, int dtype) {
-  (void)dtype;
-  if (!p || batch <= 0) return 0;
-  if (layout == CHX_INTERLEAVED && p->has_chunk)
-    return align256((size_t)p->chunk.S * 2 * p->P * (size_t)batch * sizeof(double));
-  return 0;
+  return solve_ws_layout(p, batch, layout, dtype).total;
+}
+
+// One FP32-sweep solve of the batch: out (strides of x) = A32^{-1} src,
+// written or added (acc).  src is either x itself (in place, strides of x)
+// or the compact residual buffer.
+template <int P>
+hipError_t solve32(const BandPlan* p, int batch, int layout, double* src, bool src_is_x, double* x,
+                   long ld, unsigned char* ws, const SolveWs& w, bool acc, hipStream_t st) {
+  const int n = p->n;
+  const long lds = src_is_x ? ld : (layout == CHX_INTERLEAVED ? (long)batch : (long)n);
+  if (layout == CHX_INTERLEAVED) {
+    if (p->has_chunk)
+      return launch_chunked_il32<P>(p->dchunk, src, lds, reinterpret_cast<float*>(ws + w.y32),
+                                    reinterpret_cast<float*>(ws + w.rho32), x, ld, batch, acc, st);
+    return launch_whole32<P>(p->dwhole, src, 1, lds, x, 1, ld, batch, acc, st);
+  }
+  if (p->has_chunk && p->chunk.S <= 256)
+    return launch_rows_lds32<P>(p->dchunk, src, lds, x, ld, batch, acc, st);
+  return launch_whole32<P>(p->dwhole, src, lds, 1, x, ld, 1, batch, acc, st);
+}
+
+template <int P>
+hipError_t solve_refined(const BandPlan* p, int batch, double* x, long ld, int layout, int refine,
+                         unsigned char* ws, const SolveWs& w, hipStream_t st) {
+  const int n = p->n;
+  const bool il = layout == CHX_INTERLEAVED;
+  double* fcopy = reinterpret_cast<double*>(ws + w.f);
+  double* rbuf = reinterpret_cast<double*>(ws + w.r);
+  const long pc = il ? batch : n;  // compact pitch
+  hipError_t e = il ? hipMemcpy2DAsync(fcopy, pc * sizeof(double), x, ld * sizeof(double),
+                                       (size_t)batch * sizeof(double), n, hipMemcpyDeviceToDevice,
+                                       st)
+                    : hipMemcpy2DAsync(fcopy, pc * sizeof(double), x, ld * sizeof(double),
+                                       (size_t)n * sizeof(double), batch, hipMemcpyDeviceToDevice,
+                                       st);
+  if (e == hipSuccess) e = solve32<P>(p, batch, layout, x, true, x, ld, ws, w, false, st);
+  for (int k = 0; k < refine && e == hipSuccess; ++k) {
+    if (il)
+      e = launch_resid_lines<P>(p->coef, p->periodic, n, fcopy, 1, pc, x, 1, ld, rbuf, 1, pc,
+                                batch, true, st);
+    else
+      e = launch_resid_lines<P>(p->coef, p->periodic, n, fcopy, pc, 1, x, ld, 1, rbuf, pc, 1,
+                                batch, false, st);
+    if (e == hipSuccess) e = solve32<P>(p, batch, layout, rbuf, false, x, ld, ws, w, true, st);
+  }
+  return e;
 }
 
 int solve(const BandPlan* p, int batch, void* x, long ld, int layout, int dtype, int refine,
@@ -140,19 +210,21 @@ int solve(const BandPlan* p, int batch, void* x, long ld, int layout, int dtype,
   if (batch == 0) return CHX_OK;
   if (!x) return CHX_EINVAL;
   if (layout != CHX_INTERLEAVED && layout != CHX_CONTIGUOUS) return CHX_EINVAL;
-  if (dtype != CHX_F64) {
-    (void)refine;
-    return CHX_EINVAL;  // the FP32-refined solve is not available in this build
-  }
+  if (dtype != CHX_F64 && dtype != CHX_F32_REFINED) return CHX_EINVAL;
+  if (dtype == CHX_F32_REFINED && (refine < 1 || refine > 3)) return CHX_EINVAL;
   if (layout == CHX_INTERLEAVED && ld < batch) return CHX_EINVAL;
   if (layout == CHX_CONTIGUOUS && ld < p->n) return CHX_EINVAL;
-  const size_t need = solve_ws(p, batch, layout, dtype);
-  if (need > 0 && (!ws || ws_bytes < need)) return CHX_ENOMEM;
-  if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255)) return CHX_EINVAL;
+  const SolveWs w = solve_ws_layout(p, batch, layout, dtype);
+  if (w.total > 0 && (!ws || ws_bytes < w.total)) return CHX_ENOMEM;
+  if (w.total > 0 && (reinterpret_cast<uintptr_t>(ws) & 255)) return CHX_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(s);
   double* xd = static_cast<double*>(x);
+  auto* wsb = static_cast<unsigned char*>(ws);
   hipError_t e = hipSuccess;
-  if (layout == CHX_INTERLEAVED) {
+  if (dtype == CHX_F32_REFINED) {
+    e = (p->P == 2) ? solve_refined<2>(p, batch, xd, ld, layout, refine, wsb, w, st)
+                    : solve_refined<1>(p, batch, xd, ld, layout, refine, wsb, w, st);
+  } else if (layout == CHX_INTERLEAVED) {
     if (p->has_chunk) {
       e = (p->P == 2) ? launch_chunked_il<2>(p->dchunk, xd, ld, batch, static_cast<double*>(ws), st)
                       : launch_chunked_il<1>(p->dchunk, xd, ld, batch, static_cast<double*>(ws), st);
@@ -186,6 +258,9 @@ struct chx_ch_s {
   bool fast = false;
   ChCoef K{};
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
+  // FP32-sweep refined path: residual buffer, FP32 chunk solutions and partials
+  size_t off_R = 0, off_y32 = 0, off_rho32 = 0;
+  double cxs[5] = {}, cys[5] = {};
   long part_count = 0;
   double* dscratch = nullptr;  // ch_diagnostics: partials + 2 outputs
   long dscratch_parts = 0;
@@ -304,7 +379,7 @@ int penta_plan_destroy(chx_penta_plan p) {
 
 size_t penta_solve_ws_bytes(chx_penta_plan p, int batch, int layout, int dtype,
                             int refine_passes) {
-  (void)refine_passes;
+  (void)refine_passes;  // the refined workspace does not grow with the pass count
   return solve_ws(p, batch, layout, dtype);
 }
 
@@ -364,7 +439,8 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
       !std::isfinite(q.lx) || !std::isfinite(q.ly) || !std::isfinite(q.dt) ||
       !std::isfinite(q.D) || !std::isfinite(q.gamma))
     return CHX_EINVAL;
-  if (q.dtype != CHX_F64) return CHX_EINVAL;  // FP32-refined stepping not available yet
+  if (q.dtype != CHX_F64 && q.dtype != CHX_F32_REFINED) return CHX_EINVAL;
+  if (q.dtype == CHX_F32_REFINED && (q.refine_passes < 1 || q.refine_passes > 3)) return CHX_EINVAL;
   chx_ch_s* h = new (std::nothrow) chx_ch_s();
   if (!h) return CHX_ENOMEM;
   h->prm = q;
@@ -386,12 +462,27 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   h->K.inv_dy = 1.0 / dy;
   h->K.half_gamma = 0.5 * q.gamma;
   h->K.dxdy = dx * dy;
+  for (int k = 0; k < 5; ++k) {
+    h->cxs[k] = cxs[k];
+    h->cys[k] = cys[k];
+  }
   h->fast = (q.nx % 64 == 0) && (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
             h->px->chunk.S <= 256;
+  if (q.dtype == CHX_F32_REFINED && !h->fast) {  // the refined path uses the chunked kernels
+    delete h;
+    return CHX_EINVAL;
+  }
   const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
   const long diag_parts = ch_diag_partial_blocks(q.nx, q.ny);
   size_t off = 0;
-  if (h->fast) {
+  if (q.dtype == CHX_F32_REFINED) {
+    h->off_r = off; off += field;
+    h->off_R = off; off += field;
+    h->off_y32 = off; off += align256((size_t)q.nx * q.ny * sizeof(float));
+    h->off_rho32 = off;
+    off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(float));
+    h->part_count = diag_parts;
+  } else if (h->fast) {
     h->off_b0 = off; off += field;
     h->off_b1 = off; off += field;
     h->off_rho = off;
@@ -459,7 +550,51 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   auto ok = [&]() { return e == hipSuccess; };
   auto B = [&]() { if (tm) tm->begin(); };
   auto E = [&](int ph) { if (tm) tm->end(ph); };
-  if (h->fast) {
+  if (h->prm.dtype == CHX_F32_REFINED) {
+    // r = RHS(c) in FP64; c = A32^{-1} r by FP32 column and row sweeps; then
+    // refine: R = r - A c (FP64), c += A32^{-1} R
+    double* r = reinterpret_cast<double*>(base + h->off_r);
+    double* Rb = reinterpret_cast<double*>(base + h->off_R);
+    float* y32 = reinterpret_cast<float*>(base + h->off_y32);
+    float* rho32 = reinterpret_cast<float*>(base + h->off_rho32);
+    for (int n = 0; n < nsteps && ok(); ++n) {
+      if (diag_out) {
+        B();
+        e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
+        E(3);
+      }
+      if (ok()) {
+        B();
+        e = launch_ch_rhs_plain(c, ld, r, nx, nx, ny, h->K, st);
+        E(0);
+      }
+      if (ok()) {
+        B();
+        e = launch_chunked_il32<2>(h->py->dchunk, r, nx, y32, rho32, c, ld, nx, false, st);
+        E(0);
+      }
+      if (ok()) {
+        B();
+        e = launch_rows_lds32<2>(h->px->dchunk, c, ld, c, ld, ny, false, st);
+        E(2);
+      }
+      for (int k = 0; k < h->prm.refine_passes && ok(); ++k) {
+        B();
+        e = launch_ch_residual2d(r, nx, c, ld, Rb, nx, nx, ny, h->cxs, h->cys, st);
+        E(1);
+        if (ok()) {
+          B();
+          e = launch_chunked_il32<2>(h->py->dchunk, Rb, nx, y32, rho32, Rb, nx, nx, false, st);
+          E(0);
+        }
+        if (ok()) {
+          B();
+          e = launch_rows_lds32<2>(h->px->dchunk, Rb, nx, c, ld, ny, true, st);
+          E(2);
+        }
+      }
+    }
+  } else if (h->fast) {
     double* buf[2] = {reinterpret_cast<double*>(base + h->off_b0),
                       reinterpret_cast<double*>(base + h->off_b1)};
     double* rho = reinterpret_cast<double*>(base + h->off_rho);

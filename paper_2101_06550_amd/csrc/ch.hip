@@ -376,6 +376,43 @@ __global__ __launch_bounds__(256) void ch_rhs_plain(const double* __restrict__ c
   r[(long)j * ldr + i] = xc + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
 }
 
+// Residual of the implicit operator, R = r - (I + sx Px)(I + sy Py) c, in
+// FP64 (the refinement step of the FP32-sweep path); one thread per point.
+__global__ __launch_bounds__(256) void ch_residual2d(const double* __restrict__ r, long ldr,
+                                                     const double* __restrict__ c, long ldc,
+                                                     double* __restrict__ R, long ldR, int nx,
+                                                     int ny, BandT<double> bx, BandT<double> by) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= nx || j >= ny) return;
+  int ii[5];
+#pragma unroll
+  for (int p = 0; p < 5; ++p) ii[p] = ((i + p - 2) % nx + nx) % nx;
+  double acc = r[(long)j * ldr + i];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const long jj = ((j + q - 2) % ny + ny) % ny;
+    double t = 0.0;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) t += bx.c[p] * c[jj * ldc + ii[p]];
+    acc -= by.c[q] * t;
+  }
+  R[(long)j * ldR + i] = acc;
+}
+
+hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long ldc, double* R,
+                                long ldR, int nx, int ny, const double* cx, const double* cy,
+                                hipStream_t st) {
+  BandT<double> bx, by;
+  for (int k = 0; k < 5; ++k) {
+    bx.c[k] = cx[k];
+    by.c[k] = cy[k];
+  }
+  dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(ch_residual2d, grid, dim3(256), 0, st, r, ldr, c, ldc, R, ldR, nx, ny, bx, by);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,

@@ -27,6 +27,9 @@ hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef
                           double* out, hipStream_t st);
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st);
+hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long ldc, double* R,
+                                long ldR, int nx, int ny, const double* cx, const double* cy,
+                                hipStream_t st);
 hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, int nx, int ny,
                                const ChCoef& K, hipStream_t st);
 

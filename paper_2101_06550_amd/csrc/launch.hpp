@@ -38,6 +38,24 @@ hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, do
 template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st);
 
+// FP32 sweeps with FP64 input/output (the refined path): the result is
+// written to, or added into (acc), the FP64 output.
+template <int P>
+hipError_t launch_whole32(const DevWhole& w, double* work, long ss, long es, double* out, long oss,
+                          long oes, int batch, bool acc, hipStream_t st);
+template <int P>
+hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, float* y32,
+                               float* rho32, double* out, long ldo, int batch, bool acc,
+                               hipStream_t st);
+template <int P>
+hipError_t launch_rows_lds32(const DevChunk& c, const double* src, long lds, double* dst, long ldd,
+                             int rows, bool acc, hipStream_t st);
+// r = f - A x along lines (FP64), strides (system, element) per array.
+template <int P>
+hipError_t launch_resid_lines(const double* coef, int periodic, int n, const double* f, long fss,
+                              long fes, const double* x, long xss, long xes, double* r, long rss,
+                              long res, int batch, bool sys_fast, hipStream_t st);
+
 hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long ld,
                             const double* w, int left, int right, int top, int bottom,
                             int periodic, int premap, hipStream_t st);

@@ -24,14 +24,18 @@
 namespace chx {
 
 // ---------------------------------------------------------------------------
-template <int P, typename T>
-__global__ __launch_bounds__(256) void whole_sweep(double* __restrict__ x, long ss, long es,
-                                                   int batch, int n, int periodic,
+template <int P, typename T, bool ACC>
+__global__ __launch_bounds__(256) void whole_sweep(double* work, long ss, long es, double* out,
+                                                   long oss, long oes, int batch, int n,
+                                                   int periodic,
                                                    const T* __restrict__ rec, BandT<T> bd,
                                                    T mi00, T mi01, T mi10, T mi11) {
+  // work: right-hand sides on entry, forward-sweep scratch; out: solutions
+  // (written, or added when ACC).  work == out is the in-place solve.
   const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= batch) return;
-  double* xs = x + s * ss;
+  double* xs = work + s * ss;
+  double* os = out + s * oss;
   const int mi = periodic ? n - P : n;
   const T eps = bd.c[0];
   T g1 = 0, g2 = 0, q0 = 0, q1 = 0;
@@ -65,39 +69,47 @@ __global__ __launch_bounds__(256) void whole_sweep(double* __restrict__ x, long 
     v = v - r[2] * y1;
     y2 = y1;
     y1 = v;
-    T out = v;
+    T o = v;
     if (periodic) {
-      out = out - r[6] * t0;
-      if (P == 2) out = out - r[7] * t1;
+      o = o - r[6] * t0;
+      if (P == 2) o = o - r[7] * t1;
     }
-    xs[(long)i * es] = (double)out;
+    if (ACC) os[(long)i * oes] += (double)o;
+    else os[(long)i * oes] = (double)o;
   }
   if (periodic) {
-    xs[(long)mi * es] = (double)t0;
-    if (P == 2) xs[(long)(mi + 1) * es] = (double)t1;
+    if (ACC) {
+      os[(long)mi * oes] += (double)t0;
+      if (P == 2) os[(long)(mi + 1) * oes] += (double)t1;
+    } else {
+      os[(long)mi * oes] = (double)t0;
+      if (P == 2) os[(long)(mi + 1) * oes] = (double)t1;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Interleaved layout: element i of system s at i*ld + s.  Block = 64 systems
 // (one wave, 512-byte coalesced rows) x 4 chunks (4 waves).
-template <int P, int M, typename T>
-__global__ __launch_bounds__(256) void chunk_sweep_il(double* x, long ld, int batch, int S,
-                                                      const T* __restrict__ rec, BandT<T> bd,
-                                                      T* __restrict__ rho) {
+template <int P, int M, typename T, typename Ty>
+__global__ __launch_bounds__(256) void chunk_sweep_il(const double* src, long lds, Ty* y, long ldy,
+                                                      int batch, int S, const T* __restrict__ rec,
+                                                      BandT<T> bd, T* __restrict__ rho) {
+  // src: right-hand sides (FP64); y: chunk-interior solutions (may alias src)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)blockIdx.x * 64 + lane;
   const int k = blockIdx.y * 4 + wave;
   if (s >= batch || k >= S) return;
   T f[M];
-  double* base = x + (long)k * M * ld + s;
+  const double* base = src + (long)k * M * lds + s;
 #pragma unroll
-  for (int p = 0; p < M; ++p) f[p] = (T)base[(long)p * ld];
+  for (int p = 0; p < M; ++p) f[p] = (T)base[(long)p * lds];
   chunk_sweep<P, M, T>(f, rec, bd.c[0]);
   T pa[P], pb[P];
   chunk_parts<P, M, T>(f, bd, pa, pb);
+  Ty* yb = y + (long)k * M * ldy + s;
 #pragma unroll
-  for (int p = 0; p < M - P; ++p) base[(long)p * ld] = (double)f[p];
+  for (int p = 0; p < M - P; ++p) yb[(long)p * ldy] = (Ty)f[p];
 #pragma unroll
   for (int a = 0; a < P; ++a) {
     rho[((long)k * 2 * P + a) * batch + s] = pa[a];
@@ -107,10 +119,10 @@ __global__ __launch_bounds__(256) void chunk_sweep_il(double* x, long ld, int ba
 
 // Reduced separator system: sep_k = sum_d B_d (pa_{k+d} - pb_{k+d+1}).
 // Writes separator a of chunk k to dst row (k * drow_stride + drow_off + a).
-template <int P, typename T>
+template <int P, typename T, typename Td>
 __global__ __launch_bounds__(256) void reduced_il(const T* __restrict__ rho, int batch, int S,
                                                   const T* __restrict__ blocks, int dlo,
-                                                  int dcount, double* __restrict__ dst, long ld,
+                                                  int dcount, Td* __restrict__ dst, long ld,
                                                   int drow_stride, int drow_off) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)blockIdx.x * 64 + lane;
@@ -134,12 +146,14 @@ __global__ __launch_bounds__(256) void reduced_il(const T* __restrict__ rho, int
   }
 #pragma unroll
   for (int a = 0; a < P; ++a)
-    dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[a];
+    dst[((long)k * drow_stride + drow_off + a) * ld + s] = (Td)acc[a];
 }
 
-template <int P, int M, typename T>
-__global__ __launch_bounds__(256) void correct_il(double* x, long ld, int batch, int S,
-                                                  const T* __restrict__ rec) {
+template <int P, int M, typename T, typename Ty, bool ACC>
+__global__ __launch_bounds__(256) void correct_il(const Ty* y, long ldy, double* out, long ldo,
+                                                  int batch, int S, const T* __restrict__ rec) {
+  // y: chunk-interior solutions with the separators in the separator rows;
+  // out = y - Zl s_prev - Zr s_own (written, or added when ACC); y may be out.
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)blockIdx.x * 64 + lane;
   const int k = blockIdx.y * 4 + wave;
@@ -149,17 +163,56 @@ __global__ __launch_bounds__(256) void correct_il(double* x, long ld, int batch,
   T sp[P], so[P];
 #pragma unroll
   for (int a = 0; a < P; ++a) {
-    sp[a] = (T)x[((long)kp * M + MI + a) * ld + s];
-    so[a] = (T)x[((long)k * M + MI + a) * ld + s];
+    sp[a] = (T)y[((long)kp * M + MI + a) * ldy + s];
+    so[a] = (T)y[((long)k * M + MI + a) * ldy + s];
   }
-  double* base = x + (long)k * M * ld + s;
+  const Ty* yb = y + (long)k * M * ldy + s;
+  double* ob = out + (long)k * M * ldo + s;
 #pragma unroll
   for (int p = 0; p < MI; ++p) {
-    T v = (T)base[(long)p * ld];
+    T v = (T)yb[(long)p * ldy];
 #pragma unroll
     for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
-    base[(long)p * ld] = (double)v;
+    if (ACC) ob[(long)p * ldo] += (double)v;
+    else ob[(long)p * ldo] = (double)v;
   }
+  if (ACC || (const void*)y != (const void*)out) {
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      if (ACC) ob[(long)(MI + a) * ldo] += (double)so[a];
+      else ob[(long)(MI + a) * ldo] = (double)so[a];
+    }
+  }
+}
+
+// Residual r = f - A x of cyclic (or plain) banded systems along lines:
+// element i of system s at s*ss + i*es for each of f, x, r.  sys_fast puts
+// consecutive threads on consecutive systems (interleaved layout), otherwise
+// on consecutive unknowns (contiguous layout).  FP64 throughout.
+template <int P>
+__global__ __launch_bounds__(256) void resid_lines(const double* __restrict__ f, long fss,
+                                                   long fes, const double* __restrict__ x,
+                                                   long xss, long xes, double* __restrict__ r,
+                                                   long rss, long res, int batch, int n,
+                                                   BandT<double> bd, int periodic, int sys_fast) {
+  const long fast = (long)blockIdx.x * 256 + threadIdx.x;
+  const long slow = blockIdx.y;
+  const long s = sys_fast ? fast : slow;
+  const int i = (int)(sys_fast ? slow : fast);
+  if (s >= batch || i >= n) return;
+  double v = f[s * fss + (long)i * fes];
+#pragma unroll
+  for (int o = -P; o <= P; ++o) {
+    int ii = i + o;
+    if (periodic) {
+      ii += (ii < 0) ? n : 0;
+      ii -= (ii >= n) ? n : 0;
+    } else if (ii < 0 || ii >= n) {
+      continue;
+    }
+    v = v - bd.c[o + P] * x[s * xss + (long)ii * xes];
+  }
+  r[s * rss + (long)i * res] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -206,8 +259,9 @@ __device__ __forceinline__ void row_group_stage(T* tile, const double* x, long l
   }
 }
 
-template <int P, int M, typename T>
-__device__ __forceinline__ void row_solve_body(double* x, long ld, int rows, int n, int S, int R,
+template <int P, int M, typename T, bool ACC>
+__device__ __forceinline__ void row_solve_body(const double* src, long lds, double* dst, long ldd,
+                                               int rows, int n, int S, int R,
                                                const T* __restrict__ rec, const BandT<T>& bd,
                                                const T* __restrict__ blocks, int dlo, int dcount,
                                                long group) {
@@ -217,10 +271,9 @@ __device__ __forceinline__ void row_solve_body(double* x, long ld, int rows, int
   const int t = threadIdx.x;
   const int nel = R * n;  // <= 256 * M
   const int r = t / S, k = t - r * S;
-  const bool dense = (ld == n);
   {
     const long row0 = group * R;
-    row_group_stage<P, M, T>(tile, x, ld, rows, n, row0, nel, t, dense);
+    row_group_stage<P, M, T>(tile, src, lds, rows, n, row0, nel, t, lds == n);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
     T f[M];
@@ -292,13 +345,16 @@ __device__ __forceinline__ void row_solve_body(double* x, long ld, int rows, int
       for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
     }
     __syncthreads();
-    if (dense) {
+    if (ldd == n) {
       const long nvalid = ((long)rows - row0) * n;
-      double* base = x + row0 * n;
+      double* base = dst + row0 * n;
 #pragma unroll
       for (int u = 0; u < M; ++u) {
         const int e = t + 256 * u;
-        if (e < nel && e < nvalid) base[e] = (double)tile[e + e / M];
+        if (e < nel && e < nvalid) {
+          if (ACC) base[e] += (double)tile[e + e / M];
+          else base[e] = (double)tile[e + e / M];
+        }
       }
     } else {
 #pragma unroll 1
@@ -306,18 +362,22 @@ __device__ __forceinline__ void row_solve_body(double* x, long ld, int rows, int
         const int e = t + 256 * u;
         const int rr = e / n;
         const int i = e - rr * n;
-        if (e < nel && row0 + rr < rows) x[(row0 + rr) * ld + i] = (double)tile[e + e / M];
+        if (e < nel && row0 + rr < rows) {
+          if (ACC) dst[(row0 + rr) * ldd + i] += (double)tile[e + e / M];
+          else dst[(row0 + rr) * ldd + i] = (double)tile[e + e / M];
+        }
       }
     }
     __syncthreads();
   }
 }
 
-template <int P, int M, typename T>
+template <int P, int M, typename T, bool ACC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds(
-    double* x, long ld, int rows, int n, int S, int R, const T* __restrict__ rec, BandT<T> bd,
-    const T* __restrict__ blocks, int dlo, int dcount) {
-  row_solve_body<P, M, T>(x, ld, rows, n, S, R, rec, bd, blocks, dlo, dcount, blockIdx.x);
+    const double* src, long lds, double* dst, long ldd, int rows, int n, int S, int R,
+    const T* __restrict__ rec, BandT<T> bd, const T* __restrict__ blocks, int dlo, int dcount) {
+  row_solve_body<P, M, T, ACC>(src, lds, dst, ldd, rows, n, S, R, rec, bd, blocks, dlo, dcount,
+                               blockIdx.x);
 }
 
 // Reduced separator system with an LDS window: a block (8 waves) owns 64
@@ -330,10 +390,10 @@ constexpr int kRedG = 4;
 constexpr int kRedWaves = 8;
 constexpr int kRedKB = kRedG * kRedWaves;
 
-template <int P, typename T>
+template <int P, typename T, typename Td>
 __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batch, int S,
                                              const T* __restrict__ blocks, int dlo, int dcount,
-                                             double* __restrict__ dst, long ld, int drow_stride,
+                                             Td* __restrict__ dst, long ld, int drow_stride,
                                              int drow_off, const double* __restrict__ dpart,
                                              long dnparts, double dscale,
                                              double* __restrict__ dout, int bx, int by) {
@@ -400,7 +460,7 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
       if (k < S) {
 #pragma unroll
         for (int a = 0; a < P; ++a)
-          dst[((long)k * drow_stride + drow_off + a) * ld + s] = (double)acc[g][a];
+          dst[((long)k * drow_stride + drow_off + a) * ld + s] = (Td)acc[g][a];
       }
     }
   }
@@ -444,16 +504,16 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
   }
 }
 
-template <int P, typename T>
+template <int P, typename T, typename Td>
 __global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
                                                       const T* __restrict__ blocks, int dlo,
-                                                      int dcount, double* __restrict__ dst,
+                                                      int dcount, Td* __restrict__ dst,
                                                       long ld, int drow_stride, int drow_off,
                                                       const double* __restrict__ dpart,
                                                       long dnparts, double dscale,
                                                       double* __restrict__ dout) {
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
-  reduced_body<P, T>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride, drow_off, dpart,
+  reduced_body<P, T, Td>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride, drow_off, dpart,
                      dnparts, dscale, first ? dout : nullptr, blockIdx.x, blockIdx.y);
 }
 
@@ -473,7 +533,7 @@ __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ ru
   double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
                      ? diag_out + it.x * diag_stride + 2 * (long)step
                      : nullptr;
-  reduced_body<2, double>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx, kChunk,
+  reduced_body<2, double, double>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx, kChunk,
                           kChunk - 2, part, R.ncolblocks, cls[R.cls].K.dxdy, dout, it.y, it.z);
 }
 
@@ -487,8 +547,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
   for (int k = 0; k < 5; ++k) bd.c[k] = c.coef[k];
   double* x = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
-  row_solve_body<2, kChunk, double>(x, R.nx, R.ny, R.nx, c.S, 256 / c.S, c.rec, bd, c.blocks,
-                                    c.dlo, c.dcount, it.y);
+  row_solve_body<2, kChunk, double, false>(x, R.nx, x, R.nx, R.ny, R.nx, c.S, 256 / c.S, c.rec,
+                                           bd, c.blocks, c.dlo, c.dcount, it.y);
 }
 
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClass* cls, const int4* items,
@@ -514,14 +574,57 @@ size_t ens_reduced_lds_bytes(int dcount) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+template <typename T>
+static BandT<T> band_of(const double* coef) {
+  BandT<T> bd;
+  for (int i = 0; i < 5; ++i) bd.c[i] = (T)coef[i];
+  return bd;
+}
+
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
                         hipStream_t st) {
-  BandT<double> bd;
-  for (int i = 0; i < 5; ++i) bd.c[i] = w.coef[i];
   dim3 grid((batch + 255) / 256);
-  hipLaunchKernelGGL((whole_sweep<P, double>), grid, dim3(256), 0, st, x, ss, es, batch, w.n,
-                     w.periodic, w.rec, bd, w.minv[0], w.minv[1], w.minv[2], w.minv[3]);
+  hipLaunchKernelGGL((whole_sweep<P, double, false>), grid, dim3(256), 0, st, x, ss, es, x, ss, es,
+                     batch, w.n, w.periodic, w.rec, band_of<double>(w.coef), w.minv[0], w.minv[1],
+                     w.minv[2], w.minv[3]);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_whole32(const DevWhole& w, double* work, long ss, long es, double* out, long oss,
+                          long oes, int batch, bool acc, hipStream_t st) {
+  dim3 grid((batch + 255) / 256);
+  const float m0 = (float)w.minv[0], m1 = (float)w.minv[1], m2 = (float)w.minv[2],
+              m3 = (float)w.minv[3];
+  if (acc)
+    hipLaunchKernelGGL((whole_sweep<P, float, true>), grid, dim3(256), 0, st, work, ss, es, out, oss,
+                       oes, batch, w.n, w.periodic, w.rec32, band_of<float>(w.coef), m0, m1, m2,
+                       m3);
+  else
+    hipLaunchKernelGGL((whole_sweep<P, float, false>), grid, dim3(256), 0, st, work, ss, es, out,
+                       oss, oes, batch, w.n, w.periodic, w.rec32, band_of<float>(w.coef), m0, m1,
+                       m2, m3);
+  return hipGetLastError();
+}
+
+template <int P, typename T, typename Td>
+static hipError_t reduced_any(const DevChunk& c, const T* rho, const T* blocks, int batch, Td* dst,
+                              long ld, int drow_stride, int drow_off, hipStream_t st,
+                              const double* dpart, long dnparts, double dscale, double* dout) {
+  size_t lds = (size_t)(kRedKB + c.dcount - 1) * P * 64 * sizeof(T);
+  if (dout && lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
+  if (lds <= 64 * 1024) {
+    dim3 grid((batch + 63) / 64, (c.S + kRedKB - 1) / kRedKB);
+    hipLaunchKernelGGL((reduced_il_lds<P, T, Td>), grid, dim3(64 * kRedWaves), lds, st, rho,
+                       batch, c.S, blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off, dpart,
+                       dnparts, dscale, dout);
+  } else {
+    if (dout) return hipErrorInvalidValue;
+    dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+    hipLaunchKernelGGL((reduced_il<P, T, Td>), grid, dim3(256), 0, st, rho, batch, c.S, blocks,
+                       c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
+  }
   return hipGetLastError();
 }
 
@@ -529,58 +632,99 @@ template <int P>
 hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
                              int drow_stride, int drow_off, hipStream_t st, const double* dpart,
                              long dnparts, double dscale, double* dout) {
-  size_t lds = (size_t)(kRedKB + c.dcount - 1) * P * 64 * sizeof(double);
-  if (dout && lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
-  if (lds <= 64 * 1024) {
-    dim3 grid((batch + 63) / 64, (c.S + kRedKB - 1) / kRedKB);
-    hipLaunchKernelGGL((reduced_il_lds<P, double>), grid, dim3(64 * kRedWaves), lds, st, rho,
-                       batch, c.S, c.blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off,
-                       dpart, dnparts, dscale, dout);
-  } else {
-    if (dout) return hipErrorInvalidValue;
-    dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
-    hipLaunchKernelGGL((reduced_il<P, double>), grid, dim3(256), 0, st, rho, batch, c.S,
-                       c.blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off);
-  }
-  return hipGetLastError();
+  return reduced_any<P, double, double>(c, rho, c.blocks, batch, dst, ld, drow_stride, drow_off,
+                                        st, dpart, dnparts, dscale, dout);
 }
 
 template <int P>
 hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
                              hipStream_t st) {
-  BandT<double> bd;
-  for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
   dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
-  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch,
-                     c.S, c.rec, bd, rho);
-  hipError_t e =
-      launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0, 0.0, nullptr);
+  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double, double>), grid, dim3(256), 0, st, x, ld, x,
+                     ld, batch, c.S, c.rec, band_of<double>(c.coef), rho);
+  hipError_t e = launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0,
+                                      0.0, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((correct_il<P, kChunk, double>), grid, dim3(256), 0, st, x, ld, batch, c.S,
-                     c.rec);
+  hipLaunchKernelGGL((correct_il<P, kChunk, double, double, false>), grid, dim3(256), 0, st, x, ld,
+                     x, ld, batch, c.S, c.rec);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, float* y32,
+                               float* rho32, double* out, long ldo, int batch, bool acc,
+                               hipStream_t st) {
+  dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, float, float>), grid, dim3(256), 0, st, src, lds,
+                     y32, (long)batch, batch, c.S, c.rec32, band_of<float>(c.coef), rho32);
+  hipError_t e = reduced_any<P, float, float>(c, rho32, c.blocks32, batch, y32, (long)batch,
+                                              kChunk, kChunk - P, st, nullptr, 0, 0.0, nullptr);
+  if (e != hipSuccess) return e;
+  if (acc)
+    hipLaunchKernelGGL((correct_il<P, kChunk, float, float, true>), grid, dim3(256), 0, st, y32,
+                       (long)batch, out, ldo, batch, c.S, c.rec32);
+  else
+    hipLaunchKernelGGL((correct_il<P, kChunk, float, float, false>), grid, dim3(256), 0, st, y32,
+                       (long)batch, out, ldo, batch, c.S, c.rec32);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
-  BandT<double> bd;
-  for (int i = 0; i < 5; ++i) bd.c[i] = c.coef[i];
   const int R = 256 / c.S;
   const long ngroups = ((long)rows + R - 1) / R;
-  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double>), dim3((unsigned)ngroups), dim3(256), 0, st,
-                     x, ld, rows, c.n, c.S, R, c.rec, bd, c.blocks, c.dlo, c.dcount);
+  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double, false>), dim3((unsigned)ngroups), dim3(256),
+                     0, st, x, ld, x, ld, rows, c.n, c.S, R, c.rec, band_of<double>(c.coef),
+                     c.blocks, c.dlo, c.dcount);
   return hipGetLastError();
 }
 
-template hipError_t launch_whole<1>(const DevWhole&, double*, long, long, int, hipStream_t);
-template hipError_t launch_whole<2>(const DevWhole&, double*, long, long, int, hipStream_t);
-template hipError_t launch_chunked_il<1>(const DevChunk&, double*, long, int, double*, hipStream_t);
-template hipError_t launch_chunked_il<2>(const DevChunk&, double*, long, int, double*, hipStream_t);
-template hipError_t launch_reduced_il<1>(const DevChunk&, const double*, int, double*, long, int,
-                                        int, hipStream_t, const double*, long, double, double*);
-template hipError_t launch_reduced_il<2>(const DevChunk&, const double*, int, double*, long, int,
-                                        int, hipStream_t, const double*, long, double, double*);
-template hipError_t launch_rows_lds<1>(const DevChunk&, double*, long, int, hipStream_t);
-template hipError_t launch_rows_lds<2>(const DevChunk&, double*, long, int, hipStream_t);
+template <int P>
+hipError_t launch_rows_lds32(const DevChunk& c, const double* src, long lds, double* dst, long ldd,
+                             int rows, bool acc, hipStream_t st) {
+  const int R = 256 / c.S;
+  const long ngroups = ((long)rows + R - 1) / R;
+  if (acc)
+    hipLaunchKernelGGL((row_solve_lds<P, kChunk, float, true>), dim3((unsigned)ngroups), dim3(256),
+                       0, st, src, lds, dst, ldd, rows, c.n, c.S, R, c.rec32,
+                       band_of<float>(c.coef), c.blocks32, c.dlo, c.dcount);
+  else
+    hipLaunchKernelGGL((row_solve_lds<P, kChunk, float, false>), dim3((unsigned)ngroups),
+                       dim3(256), 0, st, src, lds, dst, ldd, rows, c.n, c.S, R, c.rec32,
+                       band_of<float>(c.coef), c.blocks32, c.dlo, c.dcount);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_resid_lines(const double* coef, int periodic, int n, const double* f, long fss,
+                              long fes, const double* x, long xss, long xes, double* r, long rss,
+                              long res, int batch, bool sys_fast, hipStream_t st) {
+  const long fast = sys_fast ? batch : n, slow = sys_fast ? n : batch;
+  dim3 grid((unsigned)((fast + 255) / 256), (unsigned)slow);
+  hipLaunchKernelGGL((resid_lines<P>), grid, dim3(256), 0, st, f, fss, fes, x, xss, xes, r, rss,
+                     res, batch, n, band_of<double>(coef), periodic, sys_fast ? 1 : 0);
+  return hipGetLastError();
+}
+
+#define CHX_INST(P)                                                                             \
+  template hipError_t launch_whole<P>(const DevWhole&, double*, long, long, int, hipStream_t);  \
+  template hipError_t launch_whole32<P>(const DevWhole&, double*, long, long, double*, long,    \
+                                        long, int, bool, hipStream_t);                           \
+  template hipError_t launch_chunked_il<P>(const DevChunk&, double*, long, int, double*,        \
+                                           hipStream_t);                                         \
+  template hipError_t launch_chunked_il32<P>(const DevChunk&, const double*, long, float*,      \
+                                             float*, double*, long, int, bool, hipStream_t);     \
+  template hipError_t launch_reduced_il<P>(const DevChunk&, const double*, int, double*, long,  \
+                                           int, int, hipStream_t, const double*, long, double,   \
+                                           double*);                                             \
+  template hipError_t launch_rows_lds<P>(const DevChunk&, double*, long, int, hipStream_t);     \
+  template hipError_t launch_rows_lds32<P>(const DevChunk&, const double*, long, double*, long, \
+                                           int, bool, hipStream_t);                              \
+  template hipError_t launch_resid_lines<P>(const double*, int, int, const double*, long, long, \
+                                            const double*, long, long, double*, long, long, int, \
+                                            bool, hipStream_t);
+CHX_INST(1)
+CHX_INST(2)
+#undef CHX_INST
 
 }  // namespace chx
