@@ -208,7 +208,7 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
  * whole nsteps sequence is captured once in a hipGraph and replayed.
  *
  * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array).  Every run
- *   must use CHX_F64 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 16
+ *   must use CHX_F64 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 8
  *   distinct (grid, D, gamma, dt) classes; else CHX_EINVAL.
  * ch_ensemble_ws_bytes: device workspace for ch_ensemble_step.
  * ch_ensemble_step: advance every run by nsteps >= 1 steps in place.

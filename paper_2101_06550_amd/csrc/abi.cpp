@@ -281,7 +281,7 @@ struct chx_ens_s {
   std::vector<EnsClass> classes;
   void* dmem = nullptr;           // run table, class table, work items
   EnsRun* druns = nullptr;
-  EnsClass* dcls = nullptr;
+  EnsClasses hcls{};              // class tables passed by value to the kernels
   int4* ditems = nullptr;
   int n_col = 0, n_red = 0, n_row = 0, n_fin = 0, n_dpart = 0;
   long o_col = 0, o_red = 0, o_row = 0, o_fin = 0, o_dpart = 0;
@@ -330,17 +330,17 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
   const long dstride = 2L * (nsteps + 1);
   const int4* it = E->ditems;
   for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-    e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->druns, E->dcls, it + E->o_col,
+    e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->druns, E->hcls, it + E->o_col,
                                E->n_col, ws, n, st);
     if (e == hipSuccess)
-      e = launch_ens_reduced(E->druns, E->dcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
+      e = launch_ens_reduced(E->druns, E->hcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
                              E->red_lds, st);
-    if (e == hipSuccess) e = launch_ens_rows(E->druns, E->dcls, it + E->o_row, E->n_row, ws, n, st);
+    if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st);
   }
   if (e == hipSuccess)
-    e = launch_ens_finalize(E->druns, E->dcls, it + E->o_fin, E->n_fin, ws, nsteps - 1, st);
+    e = launch_ens_finalize(E->druns, E->hcls, it + E->o_fin, E->n_fin, ws, nsteps - 1, st);
   if (e == hipSuccess && diag_out)
-    e = launch_ens_diag(E->druns, E->dcls, it + E->o_dpart, E->n_dpart, E->nruns, ws, diag_out,
+    e = launch_ens_diag(E->druns, E->hcls, it + E->o_dpart, E->n_dpart, E->nruns, ws, diag_out,
                         dstride, nsteps, st);
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
@@ -831,22 +831,19 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     for (int by = 0; by < E->runs[r].ndby; ++by)
       for (int bx = 0; bx < E->runs[r].ndbx; ++bx) add(r, bx, by);
   E->n_dpart = (int)(items.size() - E->o_dpart);
+  for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
-  const size_t b_cls = align256(sizeof(EnsClass) * E->classes.size());
   const size_t b_items = align256(sizeof(int4) * items.size());
-  if (hipMalloc(&E->dmem, b_runs + b_cls + b_items) != hipSuccess) {
+  if (hipMalloc(&E->dmem, b_runs + b_items) != hipSuccess) {
     E->dmem = nullptr;
     delete E;
     return CHX_EHIP;
   }
   auto* base = static_cast<unsigned char*>(E->dmem);
   E->druns = reinterpret_cast<EnsRun*>(base);
-  E->dcls = reinterpret_cast<EnsClass*>(base + b_runs);
-  E->ditems = reinterpret_cast<int4*>(base + b_runs + b_cls);
+  E->ditems = reinterpret_cast<int4*>(base + b_runs);
   if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * nruns, hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(E->dcls, E->classes.data(), sizeof(EnsClass) * E->classes.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(E->ditems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice) !=
           hipSuccess) {
     delete E;

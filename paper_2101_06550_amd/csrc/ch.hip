@@ -474,12 +474,12 @@ __device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, i
 
 template <bool RECON, bool DIAG>
 __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict__ runs,
-                                                       const EnsClass* __restrict__ cls,
+                                                       EnsClasses cls,
                                                        const int4* __restrict__ items,
                                                        unsigned char* ws, int step) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  const EnsClass& C = cls[R.cls];
+  const EnsClass& C = cls.c[R.cls];
   const double* src = (step == 0) ? R.c : ens_buf(ws, R, step - 1);
   const long lds = (step == 0) ? R.ldc : (long)R.nx;
   BandT<double> bd;
@@ -493,37 +493,37 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
 }
 
 __global__ __launch_bounds__(256) void ens_finalize(const EnsRun* __restrict__ runs,
-                                                    const EnsClass* __restrict__ cls,
+                                                    EnsClasses cls,
                                                     const int4* __restrict__ items,
                                                     unsigned char* ws, int last_step) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  finalize_body(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx, R.ny, R.Sc, cls[R.cls].py.rec,
+  finalize_body(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx, R.ny, R.Sc, cls.c[R.cls].py.rec,
                 it.y, it.z);
 }
 
 __global__ __launch_bounds__(256) void ens_diag_partial(const EnsRun* __restrict__ runs,
-                                                        const EnsClass* __restrict__ cls,
+                                                        EnsClasses cls,
                                                         const int4* __restrict__ items,
                                                         unsigned char* ws) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
   double* part = reinterpret_cast<double*>(ws + R.off_part);
-  diag_partial_body(R.c, R.ldc, R.nx, R.ny, cls[R.cls].K,
+  diag_partial_body(R.c, R.ldc, R.nx, R.ny, cls.c[R.cls].K,
                     part + 2 * ((long)it.z * R.ndbx + it.y), it.y, it.z);
 }
 
 __global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__ runs,
-                                                      const EnsClass* __restrict__ cls,
+                                                      EnsClasses cls,
                                                       unsigned char* ws, double* diag_out,
                                                       long diag_stride, int index) {
   const EnsRun R = runs[blockIdx.x];
   const double* part = reinterpret_cast<const double*>(ws + R.off_part);
-  diag_final_body(part, (long)R.ndbx * R.ndby, cls[R.cls].K.dxdy,
+  diag_final_body(part, (long)R.ndbx * R.ndby, cls.c[R.cls].K.dxdy,
                   diag_out + blockIdx.x * diag_stride + 2 * (long)index);
 }
 
-hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, const EnsClass* cls,
+hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, const EnsClasses& cls,
                                   const int4* items, int nitems, unsigned char* ws, int step,
                                   hipStream_t st) {
 #define CHX_ENSCOL(R, D)                                                                        \
@@ -537,14 +537,14 @@ hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, con
   return hipGetLastError();
 }
 
-hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClass* cls, const int4* items,
+hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                                int nitems, unsigned char* ws, int last_step, hipStream_t st) {
   hipLaunchKernelGGL(ens_finalize, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws,
                      last_step);
   return hipGetLastError();
 }
 
-hipError_t launch_ens_diag(const EnsRun* runs, const EnsClass* cls, const int4* items, int nitems,
+hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
                            int nruns, unsigned char* ws, double* diag_out, long diag_stride,
                            int index, hipStream_t st) {
   hipLaunchKernelGGL(ens_diag_partial, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws);

@@ -11,7 +11,7 @@
 
 namespace chx {
 
-constexpr int kEnsMaxClasses = 16;
+constexpr int kEnsMaxClasses = 8;
 
 struct EnsRun {
   double* c;               // the caller's field of this run (set per call)
@@ -29,19 +29,25 @@ struct EnsClass {
   ChCoef K;         // right-hand side and diagnostic coefficients
 };
 
+// Passed by value: kernel arguments live in the constant segment, so the
+// plan-table pointers and the table reads stay scalar (uniform) loads.
+struct EnsClasses {
+  EnsClass c[kEnsMaxClasses];
+};
+
 // Work items are int4 {run, a, b, 0}.
 hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs,
-                                  const EnsClass* cls, const int4* items, int nitems,
+                                  const EnsClasses& cls, const int4* items, int nitems,
                                   unsigned char* ws, int step, hipStream_t st);
-hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClass* cls, const int4* items,
+hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
                               long diag_stride, size_t lds_bytes, hipStream_t st);
 size_t ens_reduced_lds_bytes(int dcount);
-hipError_t launch_ens_rows(const EnsRun* runs, const EnsClass* cls, const int4* items, int nitems,
+hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
                            unsigned char* ws, int step, hipStream_t st);
-hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClass* cls, const int4* items,
+hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                                int nitems, unsigned char* ws, int last_step, hipStream_t st);
-hipError_t launch_ens_diag(const EnsRun* runs, const EnsClass* cls, const int4* items,
+hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                            int nitems, int nruns, unsigned char* ws, double* diag_out,
                            long diag_stride, int index, hipStream_t st);
 

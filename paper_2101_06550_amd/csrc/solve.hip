@@ -233,9 +233,21 @@ __device__ __forceinline__ void row_group_stage(T* tile, const double* x, long l
     const long nvalid = ((long)rows - row0) * n;
     const double* base = x + row0 * n;
     double vin[M];
-    if (nel == 256 * M && nvalid >= nel) {  // a full group: no guards
+    if (nel == 256 * M && nvalid >= nel) {  // a full group: 16-byte loads, no guards
+      const double2* b2 = reinterpret_cast<const double2*>(base);
 #pragma unroll
-      for (int u = 0; u < M; ++u) vin[u] = base[t + 256 * u];
+      for (int u = 0; u < M / 2; ++u) {
+        const double2 v = b2[t + 256 * u];
+        vin[2 * u] = v.x;
+        vin[2 * u + 1] = v.y;
+      }
+#pragma unroll
+      for (int u = 0; u < M / 2; ++u) {
+        const int e = 2 * t + 512 * u;
+        tile[e + e / M] = (T)vin[2 * u];
+        tile[e + 1 + e / M] = (T)vin[2 * u + 1];
+      }
+      return;
     } else {
 #pragma unroll
       for (int u = 0; u < M; ++u) {
@@ -345,7 +357,22 @@ __device__ __forceinline__ void row_solve_body(const double* src, long lds, doub
       for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
     }
     __syncthreads();
-    if (ldd == n) {
+    if (ldd == n && nel == 256 * M && ((long)rows - row0) * n >= nel) {
+      double2* b2 = reinterpret_cast<double2*>(dst + row0 * n);
+#pragma unroll
+      for (int u = 0; u < M / 2; ++u) {
+        const int e = 2 * t + 512 * u;
+        double2 v;
+        v.x = (double)tile[e + e / M];
+        v.y = (double)tile[e + 1 + e / M];
+        if (ACC) {
+          const double2 o = b2[t + 256 * u];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        b2[t + 256 * u] = v;
+      }
+    } else if (ldd == n) {
       const long nvalid = ((long)rows - row0) * n;
       double* base = dst + row0 * n;
 #pragma unroll
@@ -520,13 +547,13 @@ __global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho,
 // ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
 __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ runs,
-                                                   const EnsClass* __restrict__ cls,
+                                                   EnsClasses cls,
                                                    const int4* __restrict__ items,
                                                    unsigned char* ws, int step, double* diag_out,
                                                    long diag_stride) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  const DevChunk& c = cls[R.cls].py;
+  const DevChunk& c = cls.c[R.cls].py;
   double* dst = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
   const double* rho = reinterpret_cast<const double*>(ws + R.off_rho);
   const double* part = reinterpret_cast<const double*>(ws + R.off_part);
@@ -534,15 +561,15 @@ __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ ru
                      ? diag_out + it.x * diag_stride + 2 * (long)step
                      : nullptr;
   reduced_body<2, double, double>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx, kChunk,
-                          kChunk - 2, part, R.ncolblocks, cls[R.cls].K.dxdy, dout, it.y, it.z);
+                          kChunk - 2, part, R.ncolblocks, cls.c[R.cls].K.dxdy, dout, it.y, it.z);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ens_rows(
-    const EnsRun* __restrict__ runs, const EnsClass* __restrict__ cls,
+    const EnsRun* __restrict__ runs, EnsClasses cls,
     const int4* __restrict__ items, unsigned char* ws, int step) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  const DevChunk& c = cls[R.cls].px;
+  const DevChunk& c = cls.c[R.cls].px;
   BandT<double> bd;
 #pragma unroll
   for (int k = 0; k < 5; ++k) bd.c[k] = c.coef[k];
@@ -551,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                                            bd, c.blocks, c.dlo, c.dcount, it.y);
 }
 
-hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClass* cls, const int4* items,
+hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
                               long diag_stride, size_t lds_bytes, hipStream_t st) {
   hipLaunchKernelGGL(ens_reduced, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs, cls,
@@ -559,7 +586,7 @@ hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClass* cls, const int
   return hipGetLastError();
 }
 
-hipError_t launch_ens_rows(const EnsRun* runs, const EnsClass* cls, const int4* items, int nitems,
+hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
                            unsigned char* ws, int step, hipStream_t st) {
   hipLaunchKernelGGL(ens_rows, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, step);
   return hipGetLastError();
