@@ -29,6 +29,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "CH ADI grid-pt updates/s; penta-solve HBM GB/s % peak; FP32-refined vs FP64"
+CSRC = os.path.join(ROOT, "paper_2101_06550_amd", "csrc")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ch_adi_8192x8192_fp64_traffic.md")
+KERNEL_OF_PHASE = {"column_pass": "ch_column_pass", "column_separators": "reduced_il_lds",
+                   "row_pass": "row_solve_lds"}
 HBM_PEAK_GBS = 8000.0
 CHUNK = 32  # unknowns per thread-chunk in the library's chunked kernels
 
@@ -52,6 +56,94 @@ def row_pass_bytes(nx, ny):
 def reduced_bytes(nx, ny):
     sc = ny // CHUNK
     return 8 * 4 * sc * nx + 8 * 2 * sc * nx
+
+
+def source_hash():
+    """sha256 over the HIP/C++ sources of the library (what the counters
+    were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into per-kernel HBM bytes per dispatch, scaled by what the same
+    counters read for the plain 1 GiB elementwise copy run first
+    (--calibrate-copy): scale = true KiB / counter KiB."""
+    import collections
+    import csv
+
+    def load(d, counter):
+        rows = []
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith("counter_collection.csv"):
+                    with open(os.path.join(root, f)) as fh:
+                        rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        return rows
+
+    true_kib = float(1 << 20)  # 1 GiB copy: 1 GiB read and 1 GiB written
+    per = {}
+    scale = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = load(d, counter)
+        calib = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
+        calib = [v for v in calib if 0.5 * true_kib < v < 2 * true_kib]
+        scale[counter] = true_kib / (sum(calib) / len(calib))
+        acc = collections.defaultdict(list)
+        for r in rows:
+            name = r["Kernel_Name"]
+            short = name.split("(")[0].replace("void ", "").split("<")[0].split("::")[-1]
+            acc[short].append(float(r["Counter_Value"]))
+        per[counter] = {k: sum(v) / len(v) for k, v in acc.items()}
+    # the library's kernels only (not the calibration copy, fills or blits)
+    kernels = sorted(k for k in set(per["FETCH_SIZE"]) & set(per["WRITE_SIZE"])
+                     if not k.startswith("__amd") and "elementwise" not in k)
+    table = {}
+    for k in kernels:
+        fb = per["FETCH_SIZE"][k] * scale["FETCH_SIZE"] * 1024
+        wb = per["WRITE_SIZE"][k] * scale["WRITE_SIZE"] * 1024
+        table[k] = {"fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb}
+    blob = {"source_sha256": source_hash(), "scale": scale, "kernels": table}
+    lines = ["# HBM traffic per dispatch: CH ADI step, 8192 x 8192, FP64", "",
+             "Commands (run from the repository root on one MI355X, each pass on its own):", "",
+             "    " + command.replace("{C}", "FETCH_SIZE"), "    " + command.replace("{C}", "WRITE_SIZE"),
+             "", "Summarised with `python bench.py --summarize-pmc <fetch dir> <write dir>`.",
+             f"Copy calibration (1 GiB elementwise copy, same run): FETCH_SIZE x "
+             f"{scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}.", "",
+             "| Kernel | fetch MB/dispatch | write MB/dispatch | total MB |", "|---|---|---|---|"]
+    for k, v in table.items():
+        lines.append(f"| {k} | {v['fetch_bytes']/1e6:.1f} | {v['write_bytes']/1e6:.1f} | "
+                     f"{v['traffic_bytes']/1e6:.1f} |")
+    lines += ["", "Algorithmic bytes per dispatch at 8192 x 8192 (what bench.py divides by "
+              "the launch time): ch_column_pass 1107.3 MB (read c, write the "
+              "half-solved field and the separator right-hand sides, read the previous "
+              "step's separator corrections), reduced_il_lds 100.7 MB, row_solve_lds "
+              "1073.7 MB (read and write the field once).",
+              "", "Valid for the library sources with this hash (bench.py reports `traffic` only "
+              "while it matches):", "", "<!-- traffic-json: " + json.dumps(blob) + " -->", ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    return blob
+
+
+def stored_traffic(kernel):
+    """Bytes per dispatch of `kernel` from the committed profile, or None if
+    the profile is absent or was taken on different sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        blob = json.loads(text.split("<!-- traffic-json: ", 1)[1].split(" -->", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != source_hash():
+        return None
+    ent = blob["kernels"].get(kernel)
+    return None if ent is None else ent["traffic_bytes"]
 
 
 def cpu_baseline(c0, L, D, gamma, dt, budget_s=12.0, max_steps=3):
@@ -234,11 +326,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device-to-device copy three times (the "
+                    help="first run a plain 1 GiB elementwise copy three times (the "
                          "reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {C} -d gpurun_out/pmc_{C} -o run "
+               "--output-format csv -- python3 bench.py --steps 3 --warmup 0 --no-cpu-baseline "
+               "--no-solves --no-ensemble --no-precision --no-refined --calibrate-copy")
+        print(json.dumps(summarize_pmc(*args.summarize_pmc, TRAFFIC_PROFILE, cmd)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is described in DESIGN.md and not run here.", file=sys.stderr)
@@ -257,7 +358,7 @@ def main():
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
     L = 2 * math.pi
@@ -309,9 +410,11 @@ def main():
     dom = max((k for k in range(3) if phase_n[k]), key=lambda k: phase_ms[k])
     dom_avg = phase_ms[dom] / phase_n[dom]
     achieved = bytes_per[dom] / (dom_avg * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None}
+    traffic = stored_traffic(KERNEL_OF_PHASE[names[dom]])
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE[names[dom]],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic)}
 
     extra = {}
     if not args.no_solves:
@@ -328,20 +431,22 @@ def main():
         log("FP64 vs FP32-refined: 1024^2 precision run")
         extra["precision_run_1024"] = precision_run(chx, torch)
 
-    # the large workload with the FP32-sweep refined path (3 passes)
-    log("large workload, FP32-refined (3 passes)")
-    hr = chx.ch_create(n, n, L, L, D, gamma, dt, dtype=chx.CHX_F32_REFINED, refine_passes=3)
-    cr = torch.tensor(c0, device="cuda")
-    chx.ch_adi_step(hr, cr, nsteps=2)
-    torch.cuda.synchronize()
-    kr = max(1, min(K, 50))
-    t0 = time.perf_counter()
-    chx.ch_adi_step(hr, cr, nsteps=kr)
-    torch.cuda.synchronize()
-    elr = time.perf_counter() - t0
-    extra["large_f32_refined_3pass"] = {"steps": kr, "ms_per_step": round(1e3 * elr / kr, 5),
-                                        "updates_per_s": n * n * kr / elr}
-    del cr
+    hr = None
+    if not args.no_refined:
+        # the large workload with the FP32-sweep refined path (3 passes)
+        log("large workload, FP32-refined (3 passes)")
+        hr = chx.ch_create(n, n, L, L, D, gamma, dt, dtype=chx.CHX_F32_REFINED, refine_passes=3)
+        cr = torch.tensor(c0, device="cuda")
+        chx.ch_adi_step(hr, cr, nsteps=2)
+        torch.cuda.synchronize()
+        kr = max(1, min(K, 50))
+        t0 = time.perf_counter()
+        chx.ch_adi_step(hr, cr, nsteps=kr)
+        torch.cuda.synchronize()
+        elr = time.perf_counter() - t0
+        extra["large_f32_refined_3pass"] = {"steps": kr, "ms_per_step": round(1e3 * elr / kr, 5),
+                                            "updates_per_s": n * n * kr / elr}
+        del cr
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -349,6 +454,8 @@ def main():
         cpu, first = cpu_baseline(c0, L, D, gamma, dt)
         errs = {}
         for tag, h_ in (("f64", h), ("f32_refined_3pass", hr)):
+            if h_ is None:
+                continue
             probe = torch.tensor(c0, device="cuda")
             chx.ch_adi_step(h_, probe, nsteps=1)
             torch.cuda.synchronize()
