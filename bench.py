@@ -231,6 +231,67 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
     return out
 
 
+def small_run(chx, torch, steps=1000):
+    """128^2, U[-0.1, 0.1] (seed 1), D = 1, gamma = 0.01, dt = 1e-4, 1000
+    steps, FP64: the single-workgroup path (field resident in LDS, one launch
+    for all steps) against the multi-kernel path (three launches per step),
+    eager and replayed from a captured graph (the ensemble entry point with
+    one run)."""
+    from paper_2101_06550_amd import inputs
+    L = 2 * math.pi
+    n = 128
+    c0 = inputs.noise_field(n, n, 1)
+    out = {"points": n * n, "steps": steps}
+    h = chx.ch_create(n, n, L, L, 1.0, 0.01, 1e-4)
+    res = {}
+    for name, small in (("single_workgroup_lds", 1), ("multi_kernel", 0)):
+        chx.ch_set_tuning(h, small, what=chx.CHX_TUNE_SMALL_PATH)
+        c = torch.tensor(c0, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=10)
+        torch.cuda.synchronize()
+        c = torch.tensor(c0, device="cuda")
+        t0 = time.perf_counter()
+        chx.ch_adi_step(h, c, nsteps=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"ms_per_step": round(1e3 * el / steps, 5), "updates_per_s": n * n * steps / el}
+        res[name] = c.cpu().numpy()
+    out["paths_max_abs_diff"] = float(np.max(np.abs(res["single_workgroup_lds"] -
+                                                    res["multi_kernel"])))
+    ens = chx.ch_ensemble_create([(n, n, L, L, 1.0, 0.01, 1e-4)])
+    g = [torch.tensor(c0, device="cuda")]
+    chx.ch_ensemble_step(ens, g, nsteps=steps, use_graph=True)  # capture
+    torch.cuda.synchronize()
+    g[0].copy_(torch.tensor(c0, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chx.ch_ensemble_step(ens, g, nsteps=steps, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["graph_single_workgroup"] = {"ms_per_step": round(1e3 * el / steps, 5),
+                                     "updates_per_s": n * n * steps / el}
+    return out
+
+
+def copy_reference(torch, reps=20):
+    """A plain 1 GiB FP64 device copy (one elementwise kernel): the HBM rate
+    a streaming kernel reaches on this part, for context next to the 8 TB/s
+    peak."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes": 2 << 30, "ms": round(ms, 4), "GBps": round((2 << 30) / (ms * 1e-3) / 1e9, 1)}
+
+
 def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
@@ -328,6 +389,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small"],
+                    help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -354,6 +417,12 @@ def main():
     chx.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.only:
+        fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
+              "small": small_run, "precision": lambda c, t: {
+                  "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
+        print(json.dumps({args.only: fn(chx, torch)}), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -416,7 +485,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic)}
 
-    extra = {}
+    extra = {"hbm_copy_reference_1GiB": copy_reference(torch)}
+    log("small 128^2 run")
+    extra["small_128_1000_steps"] = small_run(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)
@@ -483,6 +554,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
+        "tuning": {"separator_kernel_shape": chx.ch_get_tuning(h),
+                   "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH)},
         "checks": {"mass_drift_rel_L1": mass_drift, "energy_monotone": energy_monotone},
         "extra": extra,
     }

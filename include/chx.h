@@ -183,11 +183,38 @@ int ch_adi_step(chx_ch h, double* c_inout, long ld, int nsteps,
  *   the summed kernel time in milliseconds (phase_ms, host, 4 doubles) and the
  *   number of launches (phase_launches, host, 4 ints).  Phases: 0 column pass
  *   (right-hand side + column sweeps), 1 column separator system, 2 row solves,
- *   3 finalize and diagnostic reductions.  For measurement; the events add a
+ *   3 finalize and diagnostic reductions; on the single-workgroup small-grid
+ *   path its one launch counts as phase 0.  For measurement; the events add a
  *   little overhead between kernels. */
 int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
                       double* diag_out, void* ws, size_t ws_bytes, chx_stream s,
                       double* phase_ms, int* phase_launches);
+
+/* Kernel choices of the FP64 step (autotuning).
+ * CHX_TUNE_SMALL_PATH: grids with nx % 64 == 0, ny % 32 == 0, nx ny <= 16384
+ *   and an LDS footprint of 9.25 bytes per point (151.5 KB at 128 x 128) that
+ *   the device's per-workgroup LDS holds run every step of a call in ONE
+ *   workgroup with the field resident in LDS (value 1, the default where it
+ *   fits); value 0 selects the multi-kernel path.  The two paths apply the
+ *   column correction at different times and agree to rounding, not bit for
+ *   bit.  Setting 1 where it does not fit is CHX_EINVAL.
+ * CHX_TUNE_REDUCED_SHAPE: tile shape of the multi-kernel path's column
+ *   separator kernel (0 .. CHX_NUM_REDUCED_SHAPES-1: waves per block x chunks
+ *   per wave x window entries staged at once).  ch_create times every
+ *   candidate on zeroed scratch buffers of the handle's size and keeps the
+ *   fastest; the choice is cached per (nx, plan) for the life of the
+ *   process.  Environment variable CHX_AUTOTUNE=0 skips the timing (shape 0).
+ *   Every shape sums the same terms in the same order, so results are
+ *   bitwise identical whatever the shape.
+ * ch_get_tuning: *value = the current choice of `what`.
+ * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown
+ *   `what` or a value out of range.  Not to be called while work of h is
+ *   queued on a stream that is being captured. */
+#define CHX_TUNE_REDUCED_SHAPE 0
+#define CHX_TUNE_SMALL_PATH 1
+#define CHX_NUM_REDUCED_SHAPES 7
+int ch_get_tuning(chx_ch h, int what, int* value);
+int ch_set_tuning(chx_ch h, int what, int value);
 
 /* ch_diagnostics: mass = dx dy sum c and discrete free energy
  *   F = dx dy sum[(c^2-1)^2/4 + gamma/2 ((D+x c)^2 + (D+y c)^2)] of the field c

@@ -35,7 +35,7 @@ EXPORTED = [
     "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
     "stencil2d_apply",
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_timed",
-    "ch_diagnostics",
+    "ch_get_tuning", "ch_set_tuning", "ch_diagnostics",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
@@ -92,6 +92,8 @@ def load(path: str | None = None):
         "ch_ws_bytes": (_S, [_V]),
         "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
+        "ch_get_tuning": (_I, [_V, _I, _IP]),
+        "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
         "ch_ensemble_create": (_I, [_I, ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
         "ch_ensemble_destroy": (_I, [_V]),
@@ -330,6 +332,24 @@ def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
     _check(lib.ch_adi_step_timed(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
                                  _stream(stream), ms, cnt), "ch_adi_step_timed")
     return list(ms), list(cnt)
+
+
+CHX_TUNE_REDUCED_SHAPE = 0
+CHX_TUNE_SMALL_PATH = 1
+CHX_NUM_REDUCED_SHAPES = 7
+
+
+def ch_get_tuning(h: CH, what: int = CHX_TUNE_REDUCED_SHAPE) -> int:
+    """Current kernel choice `what` of the handle (separator tile shape, or
+    1/0 for the single-workgroup small-grid path)."""
+    v = ctypes.c_int()
+    _check(load().ch_get_tuning(h.handle, int(what), ctypes.byref(v)), "ch_get_tuning")
+    return v.value
+
+
+def ch_set_tuning(h: CH, value: int, what: int = CHX_TUNE_REDUCED_SHAPE):
+    """Set kernel choice `what` of the handle to value from now on."""
+    _check(load().ch_set_tuning(h.handle, int(what), int(value)), "ch_set_tuning")
 
 
 def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):

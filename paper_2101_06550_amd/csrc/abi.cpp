@@ -4,8 +4,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "ch_launch.hpp"
@@ -256,6 +260,8 @@ struct chx_ch_s {
   BandPlan* px = nullptr;  // rows: length nx, sigma_x
   BandPlan* py = nullptr;  // columns: length ny, sigma_y
   bool fast = false;
+  bool small_ok = false;  // the single-workgroup LDS-resident path fits
+  bool small = false;     // ... and is in use
   ChCoef K{};
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
   // FP32-sweep refined path: residual buffer, FP32 chunk solutions and partials
@@ -283,6 +289,12 @@ struct chx_ens_s {
   EnsRun* druns = nullptr;
   EnsClasses hcls{};              // class tables passed by value to the kernels
   int4* ditems = nullptr;
+  int* dsmall = nullptr;          // runs on the single-workgroup LDS path
+  int* dbig = nullptr;            // the other runs
+  int nsmall = 0, nbig = 0, small_threads = 0;
+  size_t small_lds = 0;
+  hipStream_t side = nullptr;     // small runs overlap the big runs' phases
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int n_col = 0, n_red = 0, n_row = 0, n_fin = 0, n_dpart = 0;
   long o_col = 0, o_red = 0, o_row = 0, o_fin = 0, o_dpart = 0;
   size_t ws_total = 0, red_lds = 0;
@@ -298,6 +310,9 @@ struct chx_ens_s {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (auto* p : px) delete p;
     for (auto* p : py) delete p;
     if (dmem) (void)hipFree(dmem);
@@ -329,7 +344,22 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
   hipError_t e = hipSuccess;
   const long dstride = 2L * (nsteps + 1);
   const int4* it = E->ditems;
-  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+  // small runs: one launch for all steps, on the side stream when big runs
+  // run beside them (fork / join by events, also under graph capture)
+  const bool fork = E->nsmall > 0 && E->nbig > 0;
+  if (E->nsmall > 0) {
+    hipStream_t ss = st;
+    if (fork) {
+      e = hipEventRecord(E->ev_fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(E->side, E->ev_fork, 0);
+      ss = E->side;
+    }
+    if (e == hipSuccess)
+      e = launch_ens_small_steps(E->druns, E->hcls, E->dsmall, E->nsmall, E->small_threads,
+                                 E->small_lds, nsteps, diag_out, dstride, ss);
+    if (e == hipSuccess && fork) e = hipEventRecord(E->ev_join, E->side);
+  }
+  for (int n = 0; E->nbig > 0 && n < nsteps && e == hipSuccess; ++n) {
     e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->druns, E->hcls, it + E->o_col,
                                E->n_col, ws, n, st);
     if (e == hipSuccess)
@@ -337,11 +367,15 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
                              E->red_lds, st);
     if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st);
   }
-  if (e == hipSuccess)
+  if (e == hipSuccess && E->nbig > 0)
     e = launch_ens_finalize(E->druns, E->hcls, it + E->o_fin, E->n_fin, ws, nsteps - 1, st);
-  if (e == hipSuccess && diag_out)
-    e = launch_ens_diag(E->druns, E->hcls, it + E->o_dpart, E->n_dpart, E->nruns, ws, diag_out,
-                        dstride, nsteps, st);
+  if (e == hipSuccess && diag_out && E->nbig > 0)
+    e = launch_ens_diag(E->druns, E->hcls, it + E->o_dpart, E->n_dpart, E->dbig, E->nbig, ws,
+                        diag_out, dstride, nsteps, st);
+  if (fork) {  // join even after a failure, so no capture is left open
+    const hipError_t j = hipStreamWaitEvent(st, E->ev_join, 0);
+    if (e == hipSuccess) e = j;
+  }
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
@@ -430,6 +464,86 @@ int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Autotuning of the column separator kernel's tile shape: every candidate
+// whose LDS fits is launched on zeroed scratch buffers of the real size (two
+// warm-up launches, then five timed with events on a private stream) and the
+// fastest is kept.  Results are cached per (columns, chunks, window) for the
+// process, so handles of the same size are tuned once.
+std::mutex g_tune_mu;
+
+size_t device_max_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return (size_t)v;
+}
+
+std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
+
+int tune_reduced(BandPlan* py, int nx, int ny) {
+  const DevChunk& c = py->dchunk;
+  const auto key = std::make_tuple(nx, c.S, c.dlo, c.dcount);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end()) return it->second;
+  int best = 0;
+  const char* env = std::getenv("CHX_AUTOTUNE");
+  if (env && env[0] == '0') return best;
+  const size_t rho_bytes = (size_t)c.S * 4 * nx * sizeof(double);
+  const size_t dst_bytes = (size_t)ny * nx * sizeof(double);
+  double *rho = nullptr, *dst = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipMalloc(&rho, rho_bytes) == hipSuccess && hipMalloc(&dst, dst_bytes) == hipSuccess &&
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+            hipMemsetAsync(rho, 0, rho_bytes, st) == hipSuccess &&
+            hipMemsetAsync(dst, 0, dst_bytes, st) == hipSuccess;
+  float best_ms = 0.f;
+  DevChunk trial = c;
+  for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
+    if (reduced_lds_bytes(shape, 2, sizeof(double), c.dcount, true) > 64 * 1024) continue;
+    trial.red_shape = shape;
+    for (int k = 0; ok && k < 2; ++k)
+      ok = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st) == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; ok && k < 5; ++k)
+      ok = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && (shape == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = shape;
+    }
+  }
+  if (st) (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  if (rho) (void)hipFree(rho);
+  if (dst) (void)hipFree(dst);
+  if (!ok) {
+    (void)hipGetLastError();  // a failed trial leaves the default shape
+    return 0;
+  }
+  g_tune_cache[key] = best;
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+static_assert(kNumRedShapes == CHX_NUM_REDUCED_SHAPES, "shape count mismatch");
+
 int ch_create(const chx_ch_params* prm, chx_ch* out) {
   if (!prm || !out) return CHX_EINVAL;
   *out = nullptr;
@@ -501,8 +615,36 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     delete h;
     return CHX_EHIP;
   }
+  h->small_ok = h->fast && q.dtype == CHX_F64 && ch_small_fits(q.nx, q.ny, device_max_lds());
+  h->small = h->small_ok;
+  if (h->fast && q.dtype == CHX_F64 && !h->small)
+    h->py->dchunk.red_shape = tune_reduced(h->py, q.nx, q.ny);
   *out = h;
   return CHX_OK;
+}
+
+int ch_get_tuning(chx_ch h, int what, int* value) {
+  if (!h || !value) return CHX_EINVAL;
+  switch (what) {
+    case CHX_TUNE_REDUCED_SHAPE: *value = h->py->dchunk.red_shape; return CHX_OK;
+    case CHX_TUNE_SMALL_PATH: *value = h->small ? 1 : 0; return CHX_OK;
+    default: return CHX_EINVAL;
+  }
+}
+
+int ch_set_tuning(chx_ch h, int what, int value) {
+  if (!h) return CHX_EINVAL;
+  switch (what) {
+    case CHX_TUNE_REDUCED_SHAPE:
+      if (value < 0 || value >= kNumRedShapes) return CHX_EINVAL;
+      h->py->dchunk.red_shape = value;
+      return CHX_OK;
+    case CHX_TUNE_SMALL_PATH:
+      if (value != 0 && (value != 1 || !h->small_ok)) return CHX_EINVAL;
+      h->small = value == 1;
+      return CHX_OK;
+    default: return CHX_EINVAL;
+  }
 }
 
 int ch_destroy(chx_ch h) {
@@ -594,6 +736,15 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
         }
       }
     }
+  } else if (h->small) {
+    // one workgroup, field resident in LDS for all steps; it also writes the
+    // diagnostics of every state, the final one included
+    B();
+    e = launch_ch_small_steps(c, ld, nx, ny, nsteps, h->py->dchunk, h->px->dchunk, h->K, diag_out,
+                              st);
+    E(0);
+    if (tm && tm->failed) return CHX_EHIP;
+    return ok() ? CHX_OK : CHX_EHIP;
   } else if (h->fast) {
     double* buf[2] = {reinterpret_cast<double*>(base + h->off_b0),
                       reinterpret_cast<double*>(base + h->off_b1)};
@@ -770,14 +921,30 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     return CHX_EINVAL;
   }
   E->red_lds = lds_max;
-  // workspace layout and run table; larger runs first in every work list
-  std::vector<int> order(nruns);
-  for (int r = 0; r < nruns; ++r) order[r] = r;
+  // runs that fit one workgroup's LDS take the single-workgroup path (the
+  // rule ch_create applies, so a run advances identically alone or here);
+  // the others get work items, larger runs first in every work list
+  const size_t max_lds = device_max_lds();
+  std::vector<int> small_list, big_list, order;
+  for (int r = 0; r < nruns; ++r) {
+    if (ch_small_fits(prm[r].nx, prm[r].ny, max_lds)) {
+      small_list.push_back(r);
+      E->small_threads = std::max(E->small_threads, prm[r].nx * prm[r].ny / kChunk);
+      E->small_lds = std::max(E->small_lds, ch_small_lds_bytes(prm[r].nx, prm[r].ny));
+    } else {
+      big_list.push_back(r);
+      order.push_back(r);
+    }
+  }
+  E->nsmall = (int)small_list.size();
+  E->nbig = (int)big_list.size();
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return (long)prm[a].nx * prm[a].ny > (long)prm[b].nx * prm[b].ny;
   });
   size_t off = 0;
   E->runs.resize(nruns);
+  std::vector<char> is_small(nruns, 0);
+  for (int r : small_list) is_small[r] = 1;
   for (int r = 0; r < nruns; ++r) {
     const chx_ch_params& q = prm[r];
     EnsRun& R = E->runs[r];
@@ -791,15 +958,19 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     R.ndbx = (q.nx + 63) / 64;
     R.ndby = (q.ny + 15) / 16;
     R.ncolblocks = (long)R.ncb * R.Sc;
+    E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
+    if (is_small[r]) {  // no workspace: the field stays in LDS
+      R.off_b0 = R.off_b1 = R.off_rho = R.off_part = 0;
+      continue;
+    }
     const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
     R.off_b0 = off; off += field;
     R.off_b1 = off; off += field;
     R.off_rho = off; off += align256((size_t)R.Sc * 4 * q.nx * sizeof(double));
     R.off_part = off;
     off += align256((size_t)std::max(R.ncolblocks, (long)R.ndbx * R.ndby) * 2 * sizeof(double));
-    E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
   }
-  E->ws_total = off;
+  E->ws_total = std::max(off, (size_t)256);
   std::vector<int4> items;
   auto add = [&](int r, int a, int b) { items.push_back(make_int4(r, a, b, 0)); };
   E->o_col = (long)items.size();
@@ -833,8 +1004,9 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   E->n_dpart = (int)(items.size() - E->o_dpart);
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
-  const size_t b_items = align256(sizeof(int4) * items.size());
-  if (hipMalloc(&E->dmem, b_runs + b_items) != hipSuccess) {
+  const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
+  const size_t b_lists = align256(sizeof(int) * nruns);
+  if (hipMalloc(&E->dmem, b_runs + b_items + 2 * b_lists) != hipSuccess) {
     E->dmem = nullptr;
     delete E;
     return CHX_EHIP;
@@ -842,10 +1014,24 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   auto* base = static_cast<unsigned char*>(E->dmem);
   E->druns = reinterpret_cast<EnsRun*>(base);
   E->ditems = reinterpret_cast<int4*>(base + b_runs);
-  if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * nruns, hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(E->ditems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice) !=
-          hipSuccess) {
+  E->dsmall = reinterpret_cast<int*>(base + b_runs + b_items);
+  E->dbig = reinterpret_cast<int*>(base + b_runs + b_items + b_lists);
+  bool ok = hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * nruns, hipMemcpyHostToDevice) ==
+            hipSuccess;
+  if (ok && !items.empty())
+    ok = hipMemcpy(E->ditems, items.data(), sizeof(int4) * items.size(),
+                   hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && E->nsmall)
+    ok = hipMemcpy(E->dsmall, small_list.data(), sizeof(int) * E->nsmall,
+                   hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && E->nbig)
+    ok = hipMemcpy(E->dbig, big_list.data(), sizeof(int) * E->nbig, hipMemcpyHostToDevice) ==
+         hipSuccess;
+  if (ok && E->nsmall && E->nbig)
+    ok = hipStreamCreateWithFlags(&E->side, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&E->ev_fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     delete E;
     return CHX_EHIP;
   }

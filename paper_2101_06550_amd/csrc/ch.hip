@@ -467,6 +467,279 @@ hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, in
 }
 
 // ---------------------------------------------------------------------------
+// Small grids: the whole field stays in one workgroup's LDS for every step of
+// a call, so a step costs no HBM traffic and no launch.  LDS holds the field F
+// (row pitch nx + nx/32: one pad element after every 32-element row segment,
+// so the row phase's per-thread segments start on different banks) and the
+// separator parts Q (four arrays of one value per task).  Every phase gives
+// one task to each thread: column phases take (column chunk kc, column i),
+// row phases (row j, row chunk kr); both count nx ny / 32 tasks.  Per step:
+//   C1  right-hand side of the state (3-row register window, x-neighbours by
+//       DPP lane shifts, wave edges read from F), diagnostics of the state;
+//   C2  interior sweep of the column chunk, separator parts -> Q, y -> F;
+//   C3  column separators (window convolution with the reduced blocks) -> F;
+//   C4  column correction x = y - Zl s_prev - Zr s_own in F;
+//   R1  row chunk sweep in registers, parts -> Q;
+//   R2  row separators -> F;  R3  row correction, row chunk -> F.
+// The correction is applied at once here (the multi-kernel path defers it to
+// the next step's column pass), so the two paths agree to rounding, not bit
+// for bit.
+__device__ __forceinline__ int sfi(int j, int i, int PX) { return j * PX + i + (i >> 5); }
+
+__device__ __forceinline__ int wrap_mod(int j, int S) {
+  j %= S;
+  return j < 0 ? j + S : j;
+}
+
+template <bool DIAG>
+__device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ldc, int nx, int ny,
+                                                 int nsteps, const DevChunk& cy,
+                                                 const DevChunk& cx, const ChCoef& K,
+                                                 double* __restrict__ diag, double* smem) {
+  __shared__ double red[2 * (kSmallMaxThreads / 64)];
+  const int PX = nx + (nx >> 5);
+  double* F = smem;
+  const int ntask = nx * ny / M;
+  double* Q = smem + (long)ny * PX;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwave = ntask >> 6;
+  const int Sy = ny / M, Sx = nx / M;
+  const bool act = tid < ntask;  // whole waves: ntask is a multiple of 64
+  for (int e = tid; e < nx * ny; e += blockDim.x) {
+    const int j = e / nx, i = e - j * nx;
+    F[sfi(j, i, PX)] = c[(long)j * ldc + i];
+  }
+  BandT<double> bdy, bdx;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    bdy.c[k] = cy.coef[k];
+    bdx.c[k] = cx.coef[k];
+  }
+  __syncthreads();
+  for (int n = 0;; ++n) {
+    if (!DIAG && n == nsteps) break;
+    // task coordinates, re-derived every step from an opaque copy of the
+    // thread index: otherwise the compiler keeps every LDS address of every
+    // phase live across the step loop (well over the register budget)
+    int tv = tid;
+    asm volatile("" : "+v"(tv));
+    const int kc = tv / nx, ic = tv - kc * nx;
+    const int il = (ic == 0) ? nx - 1 : ic - 1, ir = (ic == nx - 1) ? 0 : ic + 1;
+    const int jr = tv / Sx, kr = tv - jr * Sx;
+    const int rbase = jr * PX + kr * (M + 1);  // = sfi(jr, kr * M, PX)
+    // C1: right-hand side of the state and its diagnostics
+    double f[M];
+    double msum = 0.0, esum = 0.0;
+    if (act) {
+      auto row_of = [&](int q) {  // q = 0 .. M+1 -> rows kc*M - 1 .. kc*M + M
+        int r = kc * M - 1 + q;
+        r += (r < 0) ? ny : 0;
+        r -= (r >= ny) ? ny : 0;
+        return r;
+      };
+      auto edge = [&](int row) {
+        return lane == 0 ? F[sfi(row, il, PX)] : (lane == 63 ? F[sfi(row, ir, PX)] : 0.0);
+      };
+      double xc_m = F[sfi(row_of(0), ic, PX)];
+      double e0 = edge(row_of(0));
+      double xl_m = dpp_from_left(xc_m, e0), xr_m = dpp_from_right(xc_m, e0);
+      double xc_c = F[sfi(row_of(1), ic, PX)];
+      double e1 = edge(row_of(1));
+      double xl_c = dpp_from_left(xc_c, e1), xr_c = dpp_from_right(xc_c, e1);
+#pragma unroll
+      for (int p = 0; p < M; ++p) {
+        const int rp = row_of(p + 2);
+        double xc_p = F[sfi(rp, ic, PX)];
+        double en = edge(rp);
+        asm volatile("" : "+v"(xc_p), "+v"(en));
+        const double xl_p = dpp_from_left(xc_p, en);
+        const double xr_p = dpp_from_right(xc_p, en);
+        const double mu_c = xc_c * xc_c * xc_c - xc_c;
+        const double mu_l = xl_c * xl_c * xl_c - xl_c;
+        const double mu_r = xr_c * xr_c * xr_c - xr_c;
+        const double mu_s = xc_m * xc_m * xc_m - xc_m;
+        const double mu_n = xc_p * xc_p * xc_p - xc_p;
+        const double lap = K.cx * (mu_r + mu_l - 2.0 * mu_c) + K.cy * (mu_n + mu_s - 2.0 * mu_c);
+        const double dyy_w = xl_p + xl_m - 2.0 * xl_c;
+        const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
+        const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
+        double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+        if (DIAG) {
+          const double w = xc_c * xc_c - 1.0;
+          const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
+          msum += xc_c;
+          esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
+          asm volatile("" : "+v"(r), "+v"(msum), "+v"(esum));
+        } else {
+          asm volatile("" : "+v"(r));
+        }
+        f[p] = r;
+        xl_m = xl_c; xc_m = xc_c; xr_m = xr_c;
+        xl_c = xl_p; xc_c = xc_p; xr_c = xr_p;
+        // keep the next row's LDS loads below this row's work (bounded
+        // register pressure: the 32 right-hand sides stay live to C2)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (DIAG && act) {
+      msum = wave_sum(msum);
+      esum = wave_sum(esum);
+      if (lane == 0) {
+        red[2 * wave] = msum;
+        red[2 * wave + 1] = esum;
+      }
+    }
+    __syncthreads();
+    if (DIAG && tid == 0) {
+      double m = 0.0, e = 0.0;
+      for (int w = 0; w < nwave; ++w) {
+        m += red[2 * w];
+        e += red[2 * w + 1];
+      }
+      diag[2 * n] = m * K.dxdy;
+      diag[2 * n + 1] = e * K.dxdy;
+    }
+    if (n == nsteps) break;
+    // C2: column chunk sweep, separator parts, y
+    if (act) {
+      chunk_sweep<2, M, double>(f, cy.rec, bdy.c[0]);
+      double pa[P], pb[P];
+      chunk_parts<P, M, double>(f, bdy, pa, pb);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        Q[a * ntask + tid] = pa[a];
+        Q[(P + a) * ntask + tid] = pb[a];
+      }
+#pragma unroll
+      for (int p = 0; p < MI; ++p) F[sfi(kc * M + p, ic, PX)] = f[p];
+    }
+    __syncthreads();
+    // C3: column separators s_kc(ic) from the parts of the window chunks
+    if (act) {
+      double acc[P] = {0.0, 0.0};
+      for (int t = 0; t < cy.dcount; ++t) {
+        const int j = wrap_mod(kc + cy.dlo + t, Sy);
+        const int jn = (j + 1 == Sy) ? 0 : j + 1;
+        double rv[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          rv[a] = Q[a * ntask + j * nx + ic] - Q[(P + a) * ntask + jn * nx + ic];
+        const double* B = cy.blocks + t * 4;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int q = 0; q < P; ++q) acc[a] = acc[a] + B[a * 2 + q] * rv[q];
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) F[sfi(kc * M + MI + a, ic, PX)] = acc[a];
+    }
+    __syncthreads();
+    // C4: column correction of the chunk interior
+    if (act) {
+      const int kp = (kc == 0) ? Sy - 1 : kc - 1;
+      double sp[P], so[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        sp[a] = F[sfi(kp * M + MI + a, ic, PX)];
+        so[a] = F[sfi(kc * M + MI + a, ic, PX)];
+      }
+#pragma unroll
+      for (int p = 0; p < MI; ++p) {
+        double v = F[sfi(kc * M + p, ic, PX)];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          v = v - cy.rec[p * 8 + 4 + a] * sp[a] - cy.rec[p * 8 + 6 + a] * so[a];
+        F[sfi(kc * M + p, ic, PX)] = v;
+      }
+    }
+    __syncthreads();
+    // R1: row chunk sweep, parts
+    double so[P] = {0.0, 0.0};
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < M; ++p) f[p] = F[rbase + p];
+      chunk_sweep<2, M, double>(f, cx.rec, bdx.c[0]);
+      double pa[P], pb[P];
+      chunk_parts<P, M, double>(f, bdx, pa, pb);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        Q[a * ntask + tid] = pa[a];
+        Q[(P + a) * ntask + tid] = pb[a];
+      }
+    }
+    __syncthreads();
+    // R2: row separators
+    if (act) {
+      const int rs = jr * Sx;
+      for (int t = 0; t < cx.dcount; ++t) {
+        const int j = wrap_mod(kr + cx.dlo + t, Sx);
+        const int jn = (j + 1 == Sx) ? 0 : j + 1;
+        double rv[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          rv[a] = Q[a * ntask + rs + j] - Q[(P + a) * ntask + rs + jn];
+        const double* B = cx.blocks + t * 4;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int q = 0; q < P; ++q) so[a] = so[a] + B[a * 2 + q] * rv[q];
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) F[rbase + MI + a] = so[a];
+    }
+    __syncthreads();
+    // R3: row correction, the row chunk back into F
+    if (act) {
+      const int kp = (kr == 0) ? Sx - 1 : kr - 1;
+      double sp[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) sp[a] = F[jr * PX + kp * (M + 1) + MI + a];
+      chunk_correct<P, M, double>(f, cx.rec, sp, so);
+#pragma unroll
+      for (int p = 0; p < M; ++p) F[rbase + p] = f[p];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nx * ny; e += blockDim.x) {
+    const int j = e / nx, i = e - j * nx;
+    c[(long)j * ldc + i] = F[sfi(j, i, PX)];
+  }
+}
+
+template <bool DIAG>
+__global__ __launch_bounds__(kSmallMaxThreads) void ch_small_steps(double* c, long ldc, int nx,
+                                                                   int ny, int nsteps, DevChunk cy,
+                                                                   DevChunk cx, ChCoef K,
+                                                                   double* diag) {
+  extern __shared__ double smem_small[];
+  small_steps_body<DIAG>(c, ldc, nx, ny, nsteps, cy, cx, K, diag, smem_small);
+}
+
+size_t ch_small_lds_bytes(int nx, int ny) {
+  return ((size_t)ny * (nx + nx / M) + (size_t)4 * nx * ny / M) * sizeof(double);
+}
+
+bool ch_small_fits(int nx, int ny, size_t max_lds) {
+  if (nx % 64 != 0 || ny % M != 0) return false;
+  const long ntask = (long)nx * ny / M;
+  return ntask <= kSmallMaxThreads && ch_small_lds_bytes(nx, ny) <= max_lds;
+}
+
+hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps,
+                                 const DevChunk& cy, const DevChunk& cx, const ChCoef& K,
+                                 double* diag, hipStream_t st) {
+  const int nt = nx * ny / M;
+  const size_t lds = ch_small_lds_bytes(nx, ny);
+  if (diag)
+    hipLaunchKernelGGL(ch_small_steps<true>, dim3(1), dim3(nt), lds, st, c, ldc, nx, ny, nsteps,
+                       cy, cx, K, diag);
+  else
+    hipLaunchKernelGGL(ch_small_steps<false>, dim3(1), dim3(nt), lds, st, c, ldc, nx, ny, nsteps,
+                       cy, cx, K, diag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
 __device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, int step) {
   return reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
@@ -514,13 +787,41 @@ __global__ __launch_bounds__(256) void ens_diag_partial(const EnsRun* __restrict
 }
 
 __global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__ runs,
-                                                      EnsClasses cls,
+                                                      EnsClasses cls, const int* __restrict__ big,
                                                       unsigned char* ws, double* diag_out,
                                                       long diag_stride, int index) {
-  const EnsRun R = runs[blockIdx.x];
+  const int r = big[blockIdx.x];
+  const EnsRun R = runs[r];
   const double* part = reinterpret_cast<const double*>(ws + R.off_part);
   diag_final_body(part, (long)R.ndbx * R.ndby, cls.c[R.cls].K.dxdy,
-                  diag_out + blockIdx.x * diag_stride + 2 * (long)index);
+                  diag_out + r * diag_stride + 2 * (long)index);
+}
+
+// Small runs of an ensemble: block b advances run small[b] through all nsteps
+// steps with its field resident in LDS (blockDim and LDS sized for the
+// largest small run; the threads beyond a smaller run's tasks stay idle).
+template <bool DIAG>
+__global__ __launch_bounds__(kSmallMaxThreads) void ens_small_steps(
+    const EnsRun* __restrict__ runs, EnsClasses cls, const int* __restrict__ small, int nsteps,
+    double* diag_out, long diag_stride) {
+  extern __shared__ double smem_small[];
+  const int r = small[blockIdx.x];
+  const EnsRun R = runs[r];
+  const EnsClass& C = cls.c[R.cls];
+  small_steps_body<DIAG>(R.c, R.ldc, R.nx, R.ny, nsteps, C.py, C.px, C.K,
+                         DIAG ? diag_out + r * diag_stride : nullptr, smem_small);
+}
+
+hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, const int* small,
+                                  int nsmall, int threads, size_t lds, int nsteps,
+                                  double* diag_out, long diag_stride, hipStream_t st) {
+  if (diag_out)
+    hipLaunchKernelGGL(ens_small_steps<true>, dim3(nsmall), dim3(threads), lds, st, runs, cls,
+                       small, nsteps, diag_out, diag_stride);
+  else
+    hipLaunchKernelGGL(ens_small_steps<false>, dim3(nsmall), dim3(threads), lds, st, runs, cls,
+                       small, nsteps, diag_out, diag_stride);
+  return hipGetLastError();
 }
 
 hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, const EnsClasses& cls,
@@ -545,10 +846,10 @@ hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const 
 }
 
 hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
-                           int nruns, unsigned char* ws, double* diag_out, long diag_stride,
-                           int index, hipStream_t st) {
+                           const int* big, int nbig, unsigned char* ws, double* diag_out,
+                           long diag_stride, int index, hipStream_t st) {
   hipLaunchKernelGGL(ens_diag_partial, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws);
-  hipLaunchKernelGGL(ens_diag_final, dim3(nruns), dim3(256), 0, st, runs, cls, ws, diag_out,
+  hipLaunchKernelGGL(ens_diag_final, dim3(nbig), dim3(256), 0, st, runs, cls, big, ws, diag_out,
                      diag_stride, index);
   return hipGetLastError();
 }

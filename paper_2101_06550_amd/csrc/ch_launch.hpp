@@ -30,6 +30,14 @@ hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, d
 hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long ldc, double* R,
                                 long ldR, int nx, int ny, const double* cx, const double* cy,
                                 hipStream_t st);
+// Small grids (one workgroup, field resident in LDS for all nsteps steps):
+// at most kSmallMaxThreads tasks (nx ny / 32) and the LDS of ch_small_lds_bytes.
+constexpr int kSmallMaxThreads = 512;
+size_t ch_small_lds_bytes(int nx, int ny);
+bool ch_small_fits(int nx, int ny, size_t max_lds);
+hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps,
+                                 const DevChunk& cy, const DevChunk& cx, const ChCoef& K,
+                                 double* diag, hipStream_t st);
 hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, int nx, int ny,
                                const ChCoef& K, hipStream_t st);
 

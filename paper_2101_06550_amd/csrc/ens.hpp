@@ -47,8 +47,14 @@ hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4
                            unsigned char* ws, int step, hipStream_t st);
 hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                                int nitems, unsigned char* ws, int last_step, hipStream_t st);
+// Runs small enough for one workgroup's LDS: all nsteps in one launch,
+// block b = run small[b]; threads / lds sized for the largest of them.
+hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, const int* small,
+                                  int nsmall, int threads, size_t lds, int nsteps,
+                                  double* diag_out, long diag_stride, hipStream_t st);
+// Diagnostics of the final state of the runs big[0..nbig).
 hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items,
-                           int nitems, int nruns, unsigned char* ws, double* diag_out,
-                           long diag_stride, int index, hipStream_t st);
+                           int nitems, const int* big, int nbig, unsigned char* ws,
+                           double* diag_out, long diag_stride, int index, hipStream_t st);
 
 }  // namespace chx

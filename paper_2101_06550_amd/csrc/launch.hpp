@@ -22,7 +22,14 @@ struct DevChunk {
   const double* blocks = nullptr;   // device, dcount * 4
   const float* rec32 = nullptr;
   const float* blocks32 = nullptr;
+  int red_shape = 0;                // separator-kernel tile shape (index into the candidates)
 };
+
+// Number of candidate tile shapes of the separator kernel, and the LDS one
+// launch of shape `shape` needs (elem = sizeof the sweep type; diag = the
+// launch also finishes the diagnostics sum).
+constexpr int kNumRedShapes = 7;
+size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag);
 
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,

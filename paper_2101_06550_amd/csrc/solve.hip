@@ -407,36 +407,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                blockIdx.x);
 }
 
-// Reduced separator system with an LDS window: a block (8 waves) owns 64
-// systems and KB = 8 G consecutive chunks; it stages rho_j = pa_j - pb_{j+1}
-// for the KB + dcount - 1 chunks its convolutions touch, then each wave
-// computes G consecutive chunks at once, reading every window entry from LDS
-// a single time (register blocking).  Block (0,0) can also finish a
-// fixed-order sum of per-block (mass, energy) partials (dout != nullptr).
-constexpr int kRedG = 4;
-constexpr int kRedWaves = 8;
-constexpr int kRedKB = kRedG * kRedWaves;
-
-template <int P, typename T, typename Td>
+// Reduced separator system with an LDS window: a block (W waves) owns 64
+// systems and KB = W G consecutive chunks; it stages rho_j = pa_j - pb_{j+1}
+// for the KB + dcount - 1 chunks its convolutions touch (U window entries
+// per wave in flight at once), then each wave computes G consecutive chunks
+// at once, reading every window entry from LDS a single time (register
+// blocking).  Every output sums its dcount terms in the same order whatever
+// (W, G, U), so all shapes give bitwise identical results.  Block (0,0) can
+// also finish a fixed-order sum of per-block (mass, energy) partials
+// (dout != nullptr).
+template <int P, typename T, typename Td, int W, int G, int U>
 __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batch, int S,
                                              const T* __restrict__ blocks, int dlo, int dcount,
                                              Td* __restrict__ dst, long ld, int drow_stride,
                                              int drow_off, const double* __restrict__ dpart,
                                              long dnparts, double dscale,
                                              double* __restrict__ dout, int bx, int by) {
+  constexpr int KB = W * G;
   extern __shared__ unsigned char smraw[];
   T* sm = reinterpret_cast<T*>(smraw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)bx * 64 + lane;
-  const int k0 = by * kRedKB;
-  const int nwin = kRedKB + dcount - 1;
+  const int k0 = by * KB;
+  const int nwin = KB + dcount - 1;
   const bool sv = s < batch;
-  constexpr int U = 4;
-  for (int w0 = wave; w0 < nwin; w0 += kRedWaves * U) {
+  for (int w0 = wave; w0 < nwin; w0 += W * U) {
     T v[U][P];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + kRedWaves * u;
+      const int w = w0 + W * u;
       int j = k0 + dlo + w;
       while (j >= S) j -= S;
       while (j < 0) j += S;
@@ -449,7 +448,7 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + kRedWaves * u;
+      const int w = w0 + W * u;
       if (w < nwin) {
 #pragma unroll
         for (int a = 0; a < P; ++a) sm[(w * P + a) * 64 + lane] = v[u][a];
@@ -457,20 +456,20 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
     }
   }
   __syncthreads();
-  const int kk0 = wave * kRedG;  // first chunk (within the block) of this wave
+  const int kk0 = wave * G;  // first chunk (within the block) of this wave
   if (sv && k0 + kk0 < S) {
-    T acc[kRedG][P];
+    T acc[G][P];
 #pragma unroll
-    for (int g = 0; g < kRedG; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int a = 0; a < P; ++a) acc[g][a] = 0;
     // window entry kk0 + u feeds output g through block t = u - g
-    for (int u = 0; u < kRedG + dcount - 1; ++u) {
+    for (int u = 0; u < G + dcount - 1; ++u) {
       T rv[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) rv[c] = sm[((kk0 + u) * P + c) * 64 + lane];
 #pragma unroll
-      for (int g = 0; g < kRedG; ++g) {
+      for (int g = 0; g < G; ++g) {
         const int t = u - g;
         if (t >= 0 && t < dcount) {
           const T* B = blocks + t * 4;
@@ -482,7 +481,7 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
       }
     }
 #pragma unroll
-    for (int g = 0; g < kRedG; ++g) {
+    for (int g = 0; g < G; ++g) {
       const int k = k0 + kk0 + g;
       if (k < S) {
 #pragma unroll
@@ -531,18 +530,25 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
   }
 }
 
-template <int P, typename T, typename Td>
-__global__ __launch_bounds__(512) void reduced_il_lds(const T* __restrict__ rho, int batch, int S,
-                                                      const T* __restrict__ blocks, int dlo,
-                                                      int dcount, Td* __restrict__ dst,
-                                                      long ld, int drow_stride, int drow_off,
-                                                      const double* __restrict__ dpart,
-                                                      long dnparts, double dscale,
-                                                      double* __restrict__ dout) {
+template <int P, typename T, typename Td, int W, int G, int U>
+__global__ __launch_bounds__(64 * W) void reduced_il_lds(const T* __restrict__ rho, int batch,
+                                                         int S, const T* __restrict__ blocks,
+                                                         int dlo, int dcount, Td* __restrict__ dst,
+                                                         long ld, int drow_stride, int drow_off,
+                                                         const double* __restrict__ dpart,
+                                                         long dnparts, double dscale,
+                                                         double* __restrict__ dout) {
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
-  reduced_body<P, T, Td>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride, drow_off, dpart,
-                     dnparts, dscale, first ? dout : nullptr, blockIdx.x, blockIdx.y);
+  reduced_body<P, T, Td, W, G, U>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride,
+                                  drow_off, dpart, dnparts, dscale, first ? dout : nullptr,
+                                  blockIdx.x, blockIdx.y);
 }
+
+// The ensemble's separator kernel uses one fixed shape (runs of several
+// classes share the launch).
+constexpr int kRedWaves = 8;
+constexpr int kRedG = 4;
+constexpr int kRedKB = kRedWaves * kRedG;
 
 // ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
@@ -560,8 +566,10 @@ __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ ru
   double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
                      ? diag_out + it.x * diag_stride + 2 * (long)step
                      : nullptr;
-  reduced_body<2, double, double>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx, kChunk,
-                          kChunk - 2, part, R.ncolblocks, cls.c[R.cls].K.dxdy, dout, it.y, it.z);
+  reduced_body<2, double, double, kRedWaves, kRedG, 4>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount,
+                                                      dst, R.nx, kChunk, kChunk - 2, part,
+                                                      R.ncolblocks, cls.c[R.cls].K.dxdy, dout,
+                                                      it.y, it.z);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ens_rows(
@@ -635,17 +643,60 @@ hipError_t launch_whole32(const DevWhole& w, double* work, long ss, long es, dou
   return hipGetLastError();
 }
 
+// Candidate tile shapes of the separator kernel: (waves per block, chunks
+// per wave, window entries staged per wave at once).
+struct RedShape {
+  int W, G, U;
+};
+constexpr RedShape kRedShapes[kNumRedShapes] = {{8, 4, 4}, {8, 4, 8}, {8, 2, 4}, {4, 8, 4},
+                                                {4, 8, 8}, {4, 4, 4}, {16, 2, 4}};
+
+size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag) {
+  const RedShape& r = kRedShapes[shape];
+  size_t lds = (size_t)(r.W * r.G + dcount - 1) * P * 64 * elem;
+  const size_t dmin = 2 * (size_t)(64 * r.W) * sizeof(double);
+  if (diag && lds < dmin) lds = dmin;
+  return lds;
+}
+
+template <int P, typename T, typename Td, int W, int G, int U>
+static void reduced_launch(dim3 grid, size_t lds, hipStream_t st, const T* rho, int batch,
+                           const DevChunk& c, const T* blocks, Td* dst, long ld, int drow_stride,
+                           int drow_off, const double* dpart, long dnparts, double dscale,
+                           double* dout) {
+  hipLaunchKernelGGL((reduced_il_lds<P, T, Td, W, G, U>), grid, dim3(64 * W), lds, st, rho, batch,
+                     c.S, blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off, dpart, dnparts,
+                     dscale, dout);
+}
+
 template <int P, typename T, typename Td>
 static hipError_t reduced_any(const DevChunk& c, const T* rho, const T* blocks, int batch, Td* dst,
                               long ld, int drow_stride, int drow_off, hipStream_t st,
-                              const double* dpart, long dnparts, double dscale, double* dout) {
-  size_t lds = (size_t)(kRedKB + c.dcount - 1) * P * 64 * sizeof(T);
-  if (dout && lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
+                              const double* dpart, long dnparts, double dscale, double* dout,
+                              int shape) {
+  if (shape < 0 || shape >= kNumRedShapes) shape = 0;
+  size_t lds = reduced_lds_bytes(shape, P, sizeof(T), c.dcount, dout != nullptr);
+  if (lds > 64 * 1024 && shape != 0) {
+    shape = 0;
+    lds = reduced_lds_bytes(0, P, sizeof(T), c.dcount, dout != nullptr);
+  }
   if (lds <= 64 * 1024) {
-    dim3 grid((batch + 63) / 64, (c.S + kRedKB - 1) / kRedKB);
-    hipLaunchKernelGGL((reduced_il_lds<P, T, Td>), grid, dim3(64 * kRedWaves), lds, st, rho,
-                       batch, c.S, blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off, dpart,
-                       dnparts, dscale, dout);
+    const RedShape& r = kRedShapes[shape];
+    const int kb = r.W * r.G;
+    dim3 grid((batch + 63) / 64, (c.S + kb - 1) / kb);
+#define CHX_RED(W_, G_, U_)                                                                   \
+  reduced_launch<P, T, Td, W_, G_, U_>(grid, lds, st, rho, batch, c, blocks, dst, ld,         \
+                                       drow_stride, drow_off, dpart, dnparts, dscale, dout)
+    switch (shape) {
+      case 0: CHX_RED(8, 4, 4); break;
+      case 1: CHX_RED(8, 4, 8); break;
+      case 2: CHX_RED(8, 2, 4); break;
+      case 3: CHX_RED(4, 8, 4); break;
+      case 4: CHX_RED(4, 8, 8); break;
+      case 5: CHX_RED(4, 4, 4); break;
+      default: CHX_RED(16, 2, 4); break;
+    }
+#undef CHX_RED
   } else {
     if (dout) return hipErrorInvalidValue;
     dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
@@ -660,7 +711,7 @@ hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, do
                              int drow_stride, int drow_off, hipStream_t st, const double* dpart,
                              long dnparts, double dscale, double* dout) {
   return reduced_any<P, double, double>(c, rho, c.blocks, batch, dst, ld, drow_stride, drow_off,
-                                        st, dpart, dnparts, dscale, dout);
+                                        st, dpart, dnparts, dscale, dout, c.red_shape);
 }
 
 template <int P>
@@ -685,7 +736,8 @@ hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, f
   hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, float, float>), grid, dim3(256), 0, st, src, lds,
                      y32, (long)batch, batch, c.S, c.rec32, band_of<float>(c.coef), rho32);
   hipError_t e = reduced_any<P, float, float>(c, rho32, c.blocks32, batch, y32, (long)batch,
-                                              kChunk, kChunk - P, st, nullptr, 0, 0.0, nullptr);
+                                              kChunk, kChunk - P, st, nullptr, 0, 0.0, nullptr,
+                                              c.red_shape);
   if (e != hipSuccess) return e;
   if (acc)
     hipLaunchKernelGGL((correct_il<P, kChunk, float, float, true>), grid, dim3(256), 0, st, y32,

@@ -92,6 +92,92 @@ def test_deterministic_bitwise(chx):
     assert np.array_equal(a, b) and np.array_equal(da, db)
 
 
+@pytest.mark.parametrize("ny,nx,dt", [(1024, 1024, 1e-5), (256, 2048, 1e-6), (96, 192, 1e-4)])
+def test_every_separator_shape_gives_identical_steps(chx, orc, ny, nx, dt):
+    """Autotuning picks among tile shapes of the column separator kernel; all
+    of them must give bitwise identical steps and diagnostics, and match the
+    oracle."""
+    c0 = inputs.noise_field(ny, nx, 13)
+    h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, dt)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)  # the multi-kernel path
+    assert 0 <= chx.ch_get_tuning(h) < chx.CHX_NUM_REDUCED_SHAPES
+    ref = None
+    for shape in range(chx.CHX_NUM_REDUCED_SHAPES):
+        print(f"[case] separator shape {shape} {ny}x{nx}", flush=True)
+        chx.ch_set_tuning(h, shape)
+        assert chx.ch_get_tuning(h) == shape
+        c = torch.tensor(c0, device="cuda")
+        d = torch.zeros(2 * 4, dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=3, diag_out=d)
+        torch.cuda.synchronize()
+        out = (c.cpu().numpy(), d.cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
+    chx.ch_set_tuning(h, 0)
+    c = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(h, c, nsteps=1)
+    torch.cuda.synchronize()
+    assert rel(c.cpu().numpy(), orc.ch_step(c0, L, L, 1.0, 0.01, dt)) < 1e-12
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, chx.CHX_NUM_REDUCED_SHAPES)
+
+
+@pytest.mark.parametrize("ny,nx,dt,seed", [(128, 128, 1e-4, 1), (64, 64, 1e-3, 2), (32, 64, 1e-4, 3),
+                                           (256, 64, 1e-4, 4), (96, 64, 1e-4, 5),
+                                           (32, 512, 1e-4, 6)])
+def test_single_workgroup_path(chx, orc, ny, nx, dt, seed):
+    """Grids that fit one workgroup's LDS run every step in one launch; it
+    must match the oracle step by step and the multi-kernel path to
+    rounding, with matching diagnostics."""
+    c0 = inputs.noise_field(ny, nx, seed)
+    h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, dt)
+    assert chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH) == 1
+    print(f"[case] single-workgroup path {ny}x{nx}", flush=True)
+    n = 6
+    out = {}
+    for small in (1, 0):
+        chx.ch_set_tuning(h, small, what=chx.CHX_TUNE_SMALL_PATH)
+        c = torch.tensor(c0, device="cuda")
+        d = torch.zeros(2 * (n + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=n, diag_out=d)
+        torch.cuda.synchronize()
+        out[small] = (c.cpu().numpy(), d.cpu().numpy().reshape(n + 1, 2))
+    assert rel(out[1][0], out[0][0]) < 1e-12
+    assert np.allclose(out[1][1], out[0][1], rtol=1e-12, atol=1e-13)
+    # one step from the same state against the oracle
+    chx.ch_set_tuning(h, 1, what=chx.CHX_TUNE_SMALL_PATH)
+    c = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(h, c, nsteps=1)
+    torch.cuda.synchronize()
+    assert rel(c.cpu().numpy(), orc.ch_step(c0, L, L, 1.0, 0.01, dt)) < 1e-12
+    m, e, st = chx.ch_diagnostics(h, torch.tensor(c0, device="cuda"))
+    assert abs(m - out[1][1][0, 0]) <= 1e-12 * np.sum(np.abs(c0)) * (L / nx) * (L / ny)
+    assert abs(e - out[1][1][0, 1]) <= 1e-12 * abs(e)
+
+
+def test_single_workgroup_path_leading_dimension(chx, orc):
+    c0 = inputs.noise_field(128, 128, 8)
+    h = chx.ch_create(128, 128, L, L, 1.0, 0.01, 1e-4)
+    big = torch.full((128, 200), 7.0, dtype=torch.float64, device="cuda")
+    big[:, :128] = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(h, big, nsteps=1)
+    torch.cuda.synchronize()
+    b = big.cpu().numpy()
+    assert rel(b[:, :128], orc.ch_step(c0, L, L, 1.0, 0.01, 1e-4)) < 1e-12
+    assert np.all(b[:, 128:] == 7.0)
+
+
+def test_single_workgroup_path_not_settable_where_it_does_not_fit(chx):
+    h = chx.ch_create(256, 256, L, L, 1.0, 0.01, 1e-4)
+    assert chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH) == 0
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 1, what=chx.CHX_TUNE_SMALL_PATH)
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 0, what=5)
+
+
 def test_diagnostics_entry(chx, orc):
     c0 = inputs.noise_field(96, 64, 13)
     h = chx.ch_create(64, 96, L, L, 1.0, 0.01, 1e-4)

@@ -68,6 +68,16 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.ch_create(ctypes.byref(prm), ctypes.byref(h)) == chx.CHX_EUNSUPPORTED_N
     prm = chx.ChParams(64, 64, 6.28, 6.28, 1.0, 0.01, -1.0, 0, 0)
     assert lib.ch_create(ctypes.byref(prm), ctypes.byref(h)) == chx.CHX_EINVAL
+    v = ctypes.c_int()
+    assert lib.ch_get_tuning(None, 0, ctypes.byref(v)) == chx.CHX_EINVAL
+    assert lib.ch_set_tuning(None, 0, 0) == chx.CHX_EINVAL
+
+
+def test_shape_count_matches_header():
+    text = open(HEADER).read()
+    for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH"):
+        m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
+        assert m and int(m.group(1)) == getattr(chx, name), name
 
 
 def test_non_positive_pivot_is_reported():
