@@ -32,7 +32,8 @@ METRIC = "CH ADI grid-pt updates/s; penta-solve HBM GB/s % peak; FP32-refined vs
 CSRC = os.path.join(ROOT, "paper_2101_06550_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ch_adi_8192x8192_fp64_traffic.md")
 KERNEL_OF_PHASE = {"column_pass": "ch_column_pass", "column_separators": "reduced_il_lds",
-                   "row_pass": "row_solve_lds"}
+                   "row_pass": "row_solve_lds", "separator_rows": "rows_sep",
+                   "separators_and_interior_rows": "rows_split_fused"}
 HBM_PEAK_GBS = 8000.0
 CHUNK = 32  # unknowns per thread-chunk in the library's chunked kernels
 
@@ -73,7 +74,7 @@ def source_hash():
 def summarize_pmc(fetch_dir, write_dir, out_path, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch) into per-kernel HBM bytes per dispatch, scaled by what the same
-    counters read for the plain 1 GiB elementwise copy run first
+    counters read for the library's plain 1 GiB streaming copy run first
     (--calibrate-copy): scale = true KiB / counter KiB."""
     import collections
     import csv
@@ -92,7 +93,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
     scale = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = load(d, counter)
-        calib = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
+        calib = [float(r["Counter_Value"]) for r in rows if "stream_copy_kernel" in r["Kernel_Name"]]
         calib = [v for v in calib if 0.5 * true_kib < v < 2 * true_kib]
         scale[counter] = true_kib / (sum(calib) / len(calib))
         acc = collections.defaultdict(list)
@@ -103,7 +104,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
         per[counter] = {k: sum(v) / len(v) for k, v in acc.items()}
     # the library's kernels only (not the calibration copy, fills or blits)
     kernels = sorted(k for k in set(per["FETCH_SIZE"]) & set(per["WRITE_SIZE"])
-                     if not k.startswith("__amd") and "elementwise" not in k)
+                     if not k.startswith("__amd") and "elementwise" not in k
+                     and "stream_copy" not in k)
     table = {}
     for k in kernels:
         fb = per["FETCH_SIZE"][k] * scale["FETCH_SIZE"] * 1024
@@ -114,7 +116,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
              "Commands (run from the repository root on one MI355X, each pass on its own):", "",
              "    " + command.replace("{C}", "FETCH_SIZE"), "    " + command.replace("{C}", "WRITE_SIZE"),
              "", "Summarised with `python bench.py --summarize-pmc <fetch dir> <write dir>`.",
-             f"Copy calibration (1 GiB elementwise copy, same run): FETCH_SIZE x "
+             f"Copy calibration (1 GiB streaming copy, same run): FETCH_SIZE x "
              f"{scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}.", "",
              "| Kernel | fetch MB/dispatch | write MB/dispatch | total MB |", "|---|---|---|---|"]
     for k, v in table.items():
@@ -273,23 +275,53 @@ def small_run(chx, torch, steps=1000):
     return out
 
 
-def copy_reference(torch, reps=20):
-    """A plain 1 GiB FP64 device copy (one elementwise kernel): the HBM rate
-    a streaming kernel reaches on this part, for context next to the 8 TB/s
-    peak."""
+def copy_reference(chx, torch, reps=20):
+    """The library's plain streaming copy of 1 GiB of FP64 (read 1 GiB, write
+    1 GiB): the HBM rate a simple streaming kernel reaches on this part, for
+    context next to the 8 TB/s peak."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    chx.chx_stream_copy(src, dst)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        torch.mul(src, 1.0, out=dst)
+        chx.chx_stream_copy(src, dst)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(src, dst))
     del src, dst
-    return {"bytes": 2 << 30, "ms": round(ms, 4), "GBps": round((2 << 30) / (ms * 1e-3) / 1e9, 1)}
+    return {"bytes": 2 << 30, "ms": round(ms, 4), "GBps": round((2 << 30) / (ms * 1e-3) / 1e9, 1),
+            "copy_exact": ok}
+
+
+def tuning_sweep(chx, torch, n=8192, steps=20):
+    """Per-phase kernel times of the large workload for every separator tile
+    shape (plain row pass) and every split-row-pass shape."""
+    from paper_2101_06550_amd import inputs
+    L = 2 * math.pi
+    h = chx.ch_create(n, n, L, L, 1.0, 0.001, 1e-6)
+    c0 = torch.tensor(inputs.mode_plus_noise(n, 5), device="cuda")
+    out = {"tuned": {"separator_shape": chx.ch_get_tuning(h),
+                     "row_split": chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)}}
+    choices = [("shape", k, -1) for k in range(chx.CHX_NUM_REDUCED_SHAPES)] + \
+              [("split", 0, k) for k in range(chx.CHX_NUM_SPLIT_SHAPES)]
+    for kind, shape, split in choices:
+        chx.ch_set_tuning(h, shape)
+        chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
+        c = c0.clone()
+        ms, cnt = chx.ch_adi_step_timed(h, c, nsteps=steps)
+        c = c0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chx.ch_adi_step(h, c, nsteps=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{kind}_{shape if kind == 'shape' else split}"] = {
+            "phase_avg_ms": [round(m / k, 5) if k else 0.0 for m, k in zip(ms, cnt)],
+            "ms_per_step": round(1e3 * el / steps, 5)}
+    return out
 
 
 def rel_inf(a, b):
@@ -389,12 +421,12 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
-    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small"],
+    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB elementwise copy three times (the "
+                    help="first run the plain 1 GiB streaming copy three times (the "
                          "reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -419,7 +451,7 @@ def main():
 
     if args.only:
         fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
-              "small": small_run, "precision": lambda c, t: {
+              "small": small_run, "tuning": tuning_sweep, "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
         return
@@ -427,7 +459,7 @@ def main():
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
+            chx.chx_stream_copy(src, dst)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
     L = 2 * math.pi
@@ -464,8 +496,16 @@ def main():
                                                                    dtype=torch.float64,
                                                                    device="cuda"))
     del ct
-    names = ["column_pass", "column_separators", "row_pass", "finalize_and_diag"]
-    bytes_per = [column_pass_bytes(n, n), reduced_bytes(n, n), row_pass_bytes(n, n), None]
+    split = chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)
+    if split >= 0:  # separators fused with the interior rows, then the separator rows
+        names = ["column_pass", "separator_rows", "separators_and_interior_rows",
+                 "finalize_and_diag"]
+        sep_rows = row_pass_bytes(n, n) * 2 // CHUNK
+        bytes_per = [column_pass_bytes(n, n), sep_rows,
+                     row_pass_bytes(n, n) - sep_rows + reduced_bytes(n, n), None]
+    else:
+        names = ["column_pass", "column_separators", "row_pass", "finalize_and_diag"]
+        bytes_per = [column_pass_bytes(n, n), reduced_bytes(n, n), row_pass_bytes(n, n), None]
     phases = {}
     for k, nm in enumerate(names):
         if phase_n[k] == 0:
@@ -485,7 +525,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic)}
 
-    extra = {"hbm_copy_reference_1GiB": copy_reference(torch)}
+    extra = {"hbm_copy_reference_1GiB": copy_reference(chx, torch)}
     log("small 128^2 run")
     extra["small_128_1000_steps"] = small_run(chx, torch)
     if not args.no_solves:
@@ -555,6 +595,7 @@ def main():
         "cpu_baseline": cpu,
         "phases": phases,
         "tuning": {"separator_kernel_shape": chx.ch_get_tuning(h),
+                   "row_split_shape": split,
                    "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH)},
         "checks": {"mass_drift_rel_L1": mass_drift, "energy_monotone": energy_monotone},
         "extra": extra,

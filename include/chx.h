@@ -66,6 +66,14 @@ typedef void* chx_stream;
 
 /* Library version, e.g. 100 for 0.1.0. */
 int chx_version(void);
+
+/* chx_stream_copy: dst[i] = src[i], i < n (device FP64 arrays, 16-byte
+ *   aligned, not overlapping), one streaming kernel, asynchronous on stream s.
+ *   A measurement helper, not part of the method: its rate is the HBM
+ *   bandwidth a plain streaming kernel reaches (the practical ceiling next to
+ *   the published peak), and hardware byte counters are calibrated on it.
+ *   CHX_EINVAL for NULL, misaligned or overlapping arrays. */
+int chx_stream_copy(const double* src, double* dst, size_t n, chx_stream s);
 /* Human-readable text for a status code (static storage). */
 const char* chx_status_string(int status);
 
@@ -184,7 +192,9 @@ int ch_adi_step(chx_ch h, double* c_inout, long ld, int nsteps,
  *   number of launches (phase_launches, host, 4 ints).  Phases: 0 column pass
  *   (right-hand side + column sweeps), 1 column separator system, 2 row solves,
  *   3 finalize and diagnostic reductions; on the single-workgroup small-grid
- *   path its one launch counts as phase 0.  For measurement; the events add a
+ *   path its one launch counts as phase 0; with the split row pass
+ *   (CHX_TUNE_ROW_SPLIT >= 0) phase 2 is the launch that runs the separators
+ *   and the interior rows, phase 1 the separator rows.  For measurement; the events add a
  *   little overhead between kernels. */
 int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
                       double* diag_out, void* ws, size_t ws_bytes, chx_stream s,
@@ -206,13 +216,21 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   process.  Environment variable CHX_AUTOTUNE=0 skips the timing (shape 0).
  *   Every shape sums the same terms in the same order, so results are
  *   bitwise identical whatever the shape.
+ * CHX_TUNE_ROW_SPLIT: for rows of 4096 or 8192 points, -1 runs the column
+ *   separator kernel and then the row pass; 0 .. CHX_NUM_SPLIT_SHAPES-1 run
+ *   the separators in the same launch as the rows that do not need them
+ *   (every row but the last two of each 32-row chunk), in that tile shape,
+ *   then the remaining rows.  Chosen by the same timing as the tile shape.
+ *   Results are bitwise identical either way.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown
  *   `what` or a value out of range.  Not to be called while work of h is
  *   queued on a stream that is being captured. */
 #define CHX_TUNE_REDUCED_SHAPE 0
 #define CHX_TUNE_SMALL_PATH 1
+#define CHX_TUNE_ROW_SPLIT 2
 #define CHX_NUM_REDUCED_SHAPES 7
+#define CHX_NUM_SPLIT_SHAPES 3
 int ch_get_tuning(chx_ch h, int what, int* value);
 int ch_set_tuning(chx_ch h, int what, int value);
 

@@ -30,7 +30,7 @@ CHX_CONTIGUOUS = 1
 
 # Every symbol that include/chx.h declares.
 EXPORTED = [
-    "chx_version", "chx_status_string",
+    "chx_version", "chx_status_string", "chx_stream_copy",
     "penta_factor", "penta_plan_destroy", "penta_solve_ws_bytes", "penta_solve_batch",
     "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
     "stencil2d_apply",
@@ -78,6 +78,7 @@ def load(path: str | None = None):
     sig = {
         "chx_version": (_I, []),
         "chx_status_string": (ctypes.c_char_p, [_I]),
+        "chx_stream_copy": (_I, [_V, _V, _S, _V]),
         "penta_factor": (_I, [_I, _D, _D, _D, _D, _D, _I, ctypes.POINTER(_V)]),
         "penta_plan_destroy": (_I, [_V]),
         "penta_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
@@ -334,9 +335,20 @@ def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
     return list(ms), list(cnt)
 
 
+def chx_stream_copy(src, dst, stream=None):
+    """dst[:] = src[:] (float64 device tensors of equal size) with the
+    library's plain streaming copy kernel (a measurement reference)."""
+    if src.numel() != dst.numel():
+        raise ChxError(CHX_EINVAL, "chx_stream_copy: sizes differ")
+    _check(load().chx_stream_copy(_devptr(src, "src"), _devptr(dst, "dst"), src.numel(),
+                                  _stream(stream)), "chx_stream_copy")
+
+
 CHX_TUNE_REDUCED_SHAPE = 0
 CHX_TUNE_SMALL_PATH = 1
+CHX_TUNE_ROW_SPLIT = 2
 CHX_NUM_REDUCED_SHAPES = 7
+CHX_NUM_SPLIT_SHAPES = 3
 
 
 def ch_get_tuning(h: CH, what: int = CHX_TUNE_REDUCED_SHAPE) -> int:

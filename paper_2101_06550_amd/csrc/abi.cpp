@@ -262,6 +262,7 @@ struct chx_ch_s {
   bool fast = false;
   bool small_ok = false;  // the single-workgroup LDS-resident path fits
   bool small = false;     // ... and is in use
+  int split = -1;         // split row pass shape (-1: plain separators + rows)
   ChCoef K{};
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
   // FP32-sweep refined path: residual buffer, FP32 chunk solutions and partials
@@ -468,12 +469,20 @@ int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
 
 namespace {
 
-// Autotuning of the column separator kernel's tile shape: every candidate
-// whose LDS fits is launched on zeroed scratch buffers of the real size (two
-// warm-up launches, then five timed with events on a private stream) and the
-// fastest is kept.  Results are cached per (columns, chunks, window) for the
-// process, so handles of the same size are tuned once.
+// Autotuning of the multi-kernel step's separator stage: every candidate is
+// launched on zeroed scratch buffers of the real size (two warm-up rounds,
+// then five timed with events on a private stream): the separator kernel in
+// each tile shape whose LDS fits, followed by the row pass, and the split row
+// pass in each of its shapes (fused separators + interior rows, then the
+// separator rows).  The fastest combination is kept.  Results are cached per
+// (grid, chunks, window) for the process, so handles of the same size are
+// tuned once.
+struct Tuned {
+  int red_shape = 0;
+  int split = -1;
+};
 std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, Tuned> g_tune_cache;
 
 size_t device_max_lds() {
   int dev = 0, v = 0;
@@ -485,15 +494,13 @@ size_t device_max_lds() {
   return (size_t)v;
 }
 
-std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
-
-int tune_reduced(BandPlan* py, int nx, int ny) {
+Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   const DevChunk& c = py->dchunk;
-  const auto key = std::make_tuple(nx, c.S, c.dlo, c.dcount);
+  const auto key = std::make_tuple(nx, ny, c.S, c.dlo, c.dcount);
   std::lock_guard<std::mutex> lock(g_tune_mu);
   auto it = g_tune_cache.find(key);
   if (it != g_tune_cache.end()) return it->second;
-  int best = 0;
+  Tuned best;
   const char* env = std::getenv("CHX_AUTOTUNE");
   if (env && env[0] == '0') return best;
   const size_t rho_bytes = (size_t)c.S * 4 * nx * sizeof(double);
@@ -506,22 +513,40 @@ int tune_reduced(BandPlan* py, int nx, int ny) {
             hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
             hipMemsetAsync(rho, 0, rho_bytes, st) == hipSuccess &&
             hipMemsetAsync(dst, 0, dst_bytes, st) == hipSuccess;
-  float best_ms = 0.f;
+  // time(run) = milliseconds of five rounds of run() after two warm-up rounds
+  auto time_it = [&](auto&& run) {
+    float ms = -1.f;
+    for (int k = 0; ok && k < 2; ++k) ok = run() == hipSuccess;
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; ok && k < 5; ++k) ok = run() == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    return ms;
+  };
   DevChunk trial = c;
+  float best_ms = -1.f;
   for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
     if (reduced_lds_bytes(shape, 2, sizeof(double), c.dcount, true) > 64 * 1024) continue;
     trial.red_shape = shape;
-    for (int k = 0; ok && k < 2; ++k)
-      ok = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st) == hipSuccess;
-    ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    for (int k = 0; ok && k < 5; ++k)
-      ok = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st) == hipSuccess;
-    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-    float ms = 0.f;
-    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    if (ok && (shape == 0 || ms < best_ms)) {
+    const float ms = time_it([&]() {
+      hipError_t e = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st);
+      return e == hipSuccess ? launch_rows_lds<2>(px->dchunk, dst, nx, ny, st) : e;
+    });
+    if (ok && (best_ms < 0.f || ms < best_ms)) {
       best_ms = ms;
-      best = shape;
+      best.red_shape = shape;
+    }
+  }
+  for (int shape = 0; ok && shape < kNumSplitShapes; ++shape) {
+    if (!split_fits(c, px->dchunk, shape)) continue;
+    const float ms = time_it([&]() {
+      hipError_t e = launch_rows_split_fused(shape, c, rho, dst, nx, ny, px->dchunk, nullptr, 0,
+                                             0.0, nullptr, st);
+      return e == hipSuccess ? launch_rows_sep(dst, nx, ny, px->dchunk, st) : e;
+    });
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best.split = shape;
     }
   }
   if (st) (void)hipStreamSynchronize(st);
@@ -531,8 +556,8 @@ int tune_reduced(BandPlan* py, int nx, int ny) {
   if (rho) (void)hipFree(rho);
   if (dst) (void)hipFree(dst);
   if (!ok) {
-    (void)hipGetLastError();  // a failed trial leaves the default shape
-    return 0;
+    (void)hipGetLastError();  // a failed trial leaves the defaults
+    return Tuned{};
   }
   g_tune_cache[key] = best;
   return best;
@@ -543,6 +568,7 @@ int tune_reduced(BandPlan* py, int nx, int ny) {
 extern "C" {
 
 static_assert(kNumRedShapes == CHX_NUM_REDUCED_SHAPES, "shape count mismatch");
+static_assert(kNumSplitShapes == CHX_NUM_SPLIT_SHAPES, "shape count mismatch");
 
 int ch_create(const chx_ch_params* prm, chx_ch* out) {
   if (!prm || !out) return CHX_EINVAL;
@@ -617,8 +643,11 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   }
   h->small_ok = h->fast && q.dtype == CHX_F64 && ch_small_fits(q.nx, q.ny, device_max_lds());
   h->small = h->small_ok;
-  if (h->fast && q.dtype == CHX_F64 && !h->small)
-    h->py->dchunk.red_shape = tune_reduced(h->py, q.nx, q.ny);
+  if (h->fast && q.dtype == CHX_F64 && !h->small) {
+    const Tuned t = tune_step(h->py, h->px, q.nx, q.ny);
+    h->py->dchunk.red_shape = t.red_shape;
+    h->split = t.split;
+  }
   *out = h;
   return CHX_OK;
 }
@@ -628,6 +657,7 @@ int ch_get_tuning(chx_ch h, int what, int* value) {
   switch (what) {
     case CHX_TUNE_REDUCED_SHAPE: *value = h->py->dchunk.red_shape; return CHX_OK;
     case CHX_TUNE_SMALL_PATH: *value = h->small ? 1 : 0; return CHX_OK;
+    case CHX_TUNE_ROW_SPLIT: *value = h->split; return CHX_OK;
     default: return CHX_EINVAL;
   }
 }
@@ -642,6 +672,12 @@ int ch_set_tuning(chx_ch h, int what, int value) {
     case CHX_TUNE_SMALL_PATH:
       if (value != 0 && (value != 1 || !h->small_ok)) return CHX_EINVAL;
       h->small = value == 1;
+      return CHX_OK;
+    case CHX_TUNE_ROW_SPLIT:
+      if (value != -1 &&
+          !(h->fast && h->prm.dtype == CHX_F64 && split_fits(h->py->dchunk, h->px->dchunk, value)))
+        return CHX_EINVAL;
+      h->split = value;
       return CHX_OK;
     default: return CHX_EINVAL;
   }
@@ -760,17 +796,32 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho, h->K,
                                 part, st);
       E(0);
-      if (ok()) {
+      if (ok() && h->split >= 0) {
+        // separators fused with the interior rows (phase 2), then the
+        // separator rows (phase 1)
         B();
-        e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st,
-                                 diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
-                                 diag ? diag_out + 2 * n : nullptr);
-        E(1);
-      }
-      if (ok()) {
-        B();
-        e = launch_rows_lds<2>(h->px->dchunk, dst, nx, ny, st);
+        e = launch_rows_split_fused(h->split, h->py->dchunk, rho, dst, nx, ny, h->px->dchunk,
+                                    diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
+                                    diag ? diag_out + 2 * n : nullptr, st);
         E(2);
+        if (ok()) {
+          B();
+          e = launch_rows_sep(dst, nx, ny, h->px->dchunk, st);
+          E(1);
+        }
+      } else {
+        if (ok()) {
+          B();
+          e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st,
+                                   diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
+                                   diag ? diag_out + 2 * n : nullptr);
+          E(1);
+        }
+        if (ok()) {
+          B();
+          e = launch_rows_lds<2>(h->px->dchunk, dst, nx, ny, st);
+          E(2);
+        }
       }
       src = dst;
       lds = nx;

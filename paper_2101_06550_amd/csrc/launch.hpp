@@ -31,6 +31,17 @@ struct DevChunk {
 constexpr int kNumRedShapes = 7;
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag);
 
+// Split row pass of the ADI step (penta, FP64, rows of 4096 or 8192 points):
+// column separators fused with the interior rows, then the separator rows.
+// kNumSplitShapes shapes of the fused kernel's separator part; split_fits
+// says whether a shape's window fits the row tile's LDS.
+constexpr int kNumSplitShapes = 3;
+bool split_fits(const DevChunk& cy, const DevChunk& cx, int shape);
+hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* rho, double* x,
+                                   int nx, int ny, const DevChunk& cx, const double* dpart,
+                                   long dnparts, double dscale, double* dout, hipStream_t st);
+hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
+
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
                         hipStream_t st);

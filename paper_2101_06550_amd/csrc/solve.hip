@@ -271,20 +271,29 @@ __device__ __forceinline__ void row_group_stage(T* tile, const double* x, long l
   }
 }
 
+// LDS of one row group (the caller declares it, so a kernel that also runs
+// other work can alias it).
+template <int P, int M, typename T>
+struct RowLds {
+  T tile[256 * (M + 1)];
+  T rhol[256 * 2 * P];
+  T sepl[256 * P];
+};
+
+// Rows row0 .. row0 + R - 1 (R = 256 / S rows of n = S M unknowns each).
 template <int P, int M, typename T, bool ACC>
 __device__ __forceinline__ void row_solve_body(const double* src, long lds, double* dst, long ldd,
                                                int rows, int n, int S, int R,
                                                const T* __restrict__ rec, const BandT<T>& bd,
                                                const T* __restrict__ blocks, int dlo, int dcount,
-                                               long group) {
-  __shared__ T tile[256 * (M + 1)];
-  __shared__ T rhol[256 * 2 * P];
-  __shared__ T sepl[256 * P];
+                                               long row0, RowLds<P, M, T>& sh) {
+  T* tile = sh.tile;
+  T* rhol = sh.rhol;
+  T* sepl = sh.sepl;
   const int t = threadIdx.x;
   const int nel = R * n;  // <= 256 * M
   const int r = t / S, k = t - r * S;
   {
-    const long row0 = group * R;
     row_group_stage<P, M, T>(tile, src, lds, rows, n, row0, nel, t, lds == n);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
@@ -403,8 +412,9 @@ template <int P, int M, typename T, bool ACC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds(
     const double* src, long lds, double* dst, long ldd, int rows, int n, int S, int R,
     const T* __restrict__ rec, BandT<T> bd, const T* __restrict__ blocks, int dlo, int dcount) {
+  __shared__ RowLds<P, M, T> sh;
   row_solve_body<P, M, T, ACC>(src, lds, dst, ldd, rows, n, S, R, rec, bd, blocks, dlo, dcount,
-                               blockIdx.x);
+                               (long)blockIdx.x * R, sh);
 }
 
 // Reduced separator system with an LDS window: a block (W waves) owns 64
@@ -422,9 +432,9 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
                                              Td* __restrict__ dst, long ld, int drow_stride,
                                              int drow_off, const double* __restrict__ dpart,
                                              long dnparts, double dscale,
-                                             double* __restrict__ dout, int bx, int by) {
+                                             double* __restrict__ dout, int bx, int by,
+                                             unsigned char* smraw) {
   constexpr int KB = W * G;
-  extern __shared__ unsigned char smraw[];
   T* sm = reinterpret_cast<T*>(smraw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)bx * 64 + lane;
@@ -491,30 +501,34 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
     }
   }
   if (dout != nullptr) {  // the caller passes dout to one block only
+    // a fixed 256-way split and tree, whatever the block size, so the sum's
+    // order (and rounding) does not depend on the tile shape
     __syncthreads();
     double* sm2 = reinterpret_cast<double*>(smraw);
-    const int nt = blockDim.x;
-    const long per = (dnparts + nt - 1) / nt;
-    const long b0 = (long)threadIdx.x * per;
-    const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
-    double m = 0.0, e = 0.0;
-    long b = b0;
-    for (; b + 8 <= b1; b += 8) {
-      double2 q[8];
+    constexpr int nt = 256;
+    if ((int)threadIdx.x < nt) {
+      const long per = (dnparts + nt - 1) / nt;
+      const long b0 = (long)threadIdx.x * per;
+      const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
+      double m = 0.0, e = 0.0;
+      long b = b0;
+      for (; b + 8 <= b1; b += 8) {
+        double2 q[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
+        for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        m += q[u].x;
-        e += q[u].y;
+        for (int u = 0; u < 8; ++u) {
+          m += q[u].x;
+          e += q[u].y;
+        }
       }
+      for (; b < b1; ++b) {
+        m += dpart[2 * b];
+        e += dpart[2 * b + 1];
+      }
+      sm2[threadIdx.x] = m;
+      sm2[nt + threadIdx.x] = e;
     }
-    for (; b < b1; ++b) {
-      m += dpart[2 * b];
-      e += dpart[2 * b + 1];
-    }
-    sm2[threadIdx.x] = m;
-    sm2[nt + threadIdx.x] = e;
     __syncthreads();
     for (int h = nt / 2; h >= 1; h >>= 1) {
       if ((int)threadIdx.x < h) {
@@ -538,10 +552,103 @@ __global__ __launch_bounds__(64 * W) void reduced_il_lds(const T* __restrict__ r
                                                          const double* __restrict__ dpart,
                                                          long dnparts, double dscale,
                                                          double* __restrict__ dout) {
+  extern __shared__ unsigned char smraw[];
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
   reduced_body<P, T, Td, W, G, U>(rho, batch, S, blocks, dlo, dcount, dst, ld, drow_stride,
                                   drow_off, dpart, dnparts, dscale, first ? dout : nullptr,
-                                  blockIdx.x, blockIdx.y);
+                                  blockIdx.x, blockIdx.y, smraw);
+}
+
+template <typename T>
+static BandT<T> band_of(const double* coef) {
+  BandT<T> bd;
+  for (int i = 0; i < 5; ++i) bd.c[i] = (T)coef[i];
+  return bd;
+}
+
+// ---------------------------------------------------------------------------
+// Split row pass, for rows of 4096 or 8192 points (R = 2 or 1 rows per
+// group).  Only the separator rows (the last P rows of every 32-row column
+// chunk) need the column separators; every other row can be row-solved while
+// the separators are being computed.  rows_split_fused does both in one
+// launch: blocks [0, nred) run the separator convolution (4 waves, the row
+// group's LDS tile reused as the window), the others solve interior row
+// groups; rows_sep then solves the separator rows.  The two sets of rows are
+// disjoint, and each row is solved by the same code as in the plain pass, so
+// results are bitwise identical to it.
+__device__ __forceinline__ long split_row0(long g, int R, bool sep) {
+  const int gper = (sep ? 2 : kChunk - 2) / R;
+  return kChunk * (g / gper) + (sep ? kChunk - 2 : 0) + R * (g % gper);
+}
+
+template <int G, int U>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rows_split_fused(
+    const double* __restrict__ rho, DevChunk cy, double* x, int nx, int ny, DevChunk cx,
+    BandT<double> bdx, int nred, int nbx, const double* __restrict__ dpart, long dnparts,
+    double dscale, double* __restrict__ dout) {
+  __shared__ RowLds<2, kChunk, double> sh;
+  const int b = blockIdx.x;
+  if (b < nred) {
+    reduced_body<2, double, double, 4, G, U>(rho, nx, cy.S, cy.blocks, cy.dlo, cy.dcount, x, nx,
+                                             kChunk, kChunk - 2, dpart, dnparts, dscale,
+                                             b == 0 ? dout : nullptr, b % nbx, b / nbx,
+                                             reinterpret_cast<unsigned char*>(sh.tile));
+  } else {
+    const int R = 256 / cx.S;
+    row_solve_body<2, kChunk, double, false>(x, nx, x, nx, ny, nx, cx.S, R, cx.rec, bdx,
+                                             cx.blocks, cx.dlo, cx.dcount,
+                                             split_row0(b - nred, R, false), sh);
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rows_sep(
+    double* x, int nx, int ny, DevChunk cx, BandT<double> bdx) {
+  __shared__ RowLds<2, kChunk, double> sh;
+  const int R = 256 / cx.S;
+  row_solve_body<2, kChunk, double, false>(x, nx, x, nx, ny, nx, cx.S, R, cx.rec, bdx, cx.blocks,
+                                           cx.dlo, cx.dcount, split_row0(blockIdx.x, R, true),
+                                           sh);
+}
+
+// (chunks per wave, window entries staged at once) of the fused kernel's
+// separator part.
+constexpr int kSplitG[kNumSplitShapes] = {8, 8, 4};
+
+bool split_fits(const DevChunk& cy, const DevChunk& cx, int shape) {
+  if (shape < 0 || shape >= kNumSplitShapes) return false;
+  if (cx.S != 128 && cx.S != 256) return false;
+  const size_t win = (size_t)(4 * kSplitG[shape] + cy.dcount - 1) * 2 * 64 * sizeof(double);
+  return win <= sizeof(RowLds<2, kChunk, double>::tile) && cy.dcount <= cy.S;
+}
+
+hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* rho, double* x,
+                                   int nx, int ny, const DevChunk& cx, const double* dpart,
+                                   long dnparts, double dscale, double* dout, hipStream_t st) {
+  if (!split_fits(cy, cx, shape)) return hipErrorInvalidValue;
+  const int R = 256 / cx.S;
+  const int nbx = (nx + 63) / 64;
+  const int kb = 4 * kSplitG[shape];
+  const int nred = nbx * ((cy.S + kb - 1) / kb);
+  const long nint = (long)(ny / kChunk) * ((kChunk - 2) / R);
+  const BandT<double> bdx = band_of<double>(cx.coef);
+  const dim3 grid((unsigned)(nred + nint));
+#define CHX_SPLIT(G_, U_)                                                                        \
+  hipLaunchKernelGGL((rows_split_fused<G_, U_>), grid, dim3(256), 0, st, rho, cy, x, nx, ny, cx, \
+                     bdx, nred, nbx, dpart, dnparts, dscale, dout)
+  switch (shape) {
+    case 0: CHX_SPLIT(8, 4); break;
+    case 1: CHX_SPLIT(8, 8); break;
+    default: CHX_SPLIT(4, 4); break;
+  }
+#undef CHX_SPLIT
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st) {
+  const int R = 256 / cx.S;
+  const dim3 grid((unsigned)((ny / kChunk) * (2 / R)));
+  hipLaunchKernelGGL(rows_sep, grid, dim3(256), 0, st, x, nx, ny, cx, band_of<double>(cx.coef));
+  return hipGetLastError();
 }
 
 // The ensemble's separator kernel uses one fixed shape (runs of several
@@ -566,10 +673,11 @@ __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ ru
   double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
                      ? diag_out + it.x * diag_stride + 2 * (long)step
                      : nullptr;
+  extern __shared__ unsigned char smraw[];
   reduced_body<2, double, double, kRedWaves, kRedG, 4>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount,
                                                       dst, R.nx, kChunk, kChunk - 2, part,
                                                       R.ncolblocks, cls.c[R.cls].K.dxdy, dout,
-                                                      it.y, it.z);
+                                                      it.y, it.z, smraw);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ens_rows(
@@ -582,8 +690,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
   for (int k = 0; k < 5; ++k) bd.c[k] = c.coef[k];
   double* x = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+  __shared__ RowLds<2, kChunk, double> sh;
   row_solve_body<2, kChunk, double, false>(x, R.nx, x, R.nx, R.ny, R.nx, c.S, 256 / c.S, c.rec,
-                                           bd, c.blocks, c.dlo, c.dcount, it.y);
+                                           bd, c.blocks, c.dlo, c.dcount,
+                                           (long)it.y * (256 / c.S), sh);
 }
 
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
@@ -609,12 +719,6 @@ size_t ens_reduced_lds_bytes(int dcount) {
 // ---------------------------------------------------------------------------
 // Launchers
 
-template <typename T>
-static BandT<T> band_of(const double* coef) {
-  BandT<T> bd;
-  for (int i = 0; i < 5; ++i) bd.c[i] = (T)coef[i];
-  return bd;
-}
 
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
@@ -654,7 +758,7 @@ constexpr RedShape kRedShapes[kNumRedShapes] = {{8, 4, 4}, {8, 4, 8}, {8, 2, 4},
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag) {
   const RedShape& r = kRedShapes[shape];
   size_t lds = (size_t)(r.W * r.G + dcount - 1) * P * 64 * elem;
-  const size_t dmin = 2 * (size_t)(64 * r.W) * sizeof(double);
+  const size_t dmin = 2 * (size_t)256 * sizeof(double);
   if (diag && lds < dmin) lds = dmin;
   return lds;
 }

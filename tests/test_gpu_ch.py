@@ -178,6 +178,44 @@ def test_single_workgroup_path_not_settable_where_it_does_not_fit(chx):
         chx.ch_set_tuning(h, 0, what=5)
 
 
+@pytest.mark.parametrize("ny,nx,dt", [(64, 4096, 1e-6), (96, 8192, 1e-6), (512, 8192, 1e-6)])
+def test_split_row_pass_bitwise(chx, orc, ny, nx, dt):
+    """Rows of 4096 / 8192 points may solve the column separators in the same
+    launch as the rows that do not need them; every choice (and the plain
+    pass) must give bitwise identical steps, matching the oracle."""
+    c0 = inputs.noise_field(ny, nx, 21)
+    h = chx.ch_create(nx, ny, L, L, 1.0, 0.001, dt)
+    tuned = chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)
+    assert -1 <= tuned < chx.CHX_NUM_SPLIT_SHAPES
+    ref = None
+    for split in [-1] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
+        print(f"[case] row split {split} {ny}x{nx}", flush=True)
+        chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
+        c = torch.tensor(c0, device="cuda")
+        d = torch.zeros(2 * 4, dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=3, diag_out=d)
+        torch.cuda.synchronize()
+        out = (c.cpu().numpy(), d.cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), split
+    chx.ch_set_tuning(h, tuned, what=chx.CHX_TUNE_ROW_SPLIT)
+    c = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(h, c, nsteps=1)
+    torch.cuda.synchronize()
+    assert rel(c.cpu().numpy(), orc.ch_step(c0, L, L, 1.0, 0.001, dt)) < 1e-12
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, chx.CHX_NUM_SPLIT_SHAPES, what=chx.CHX_TUNE_ROW_SPLIT)
+
+
+def test_split_row_pass_not_settable_for_short_rows(chx):
+    h = chx.ch_create(1024, 64, L, L, 1.0, 0.01, 1e-5)
+    assert chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT) == -1
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_ROW_SPLIT)
+
+
 def test_diagnostics_entry(chx, orc):
     c0 = inputs.noise_field(96, 64, 13)
     h = chx.ch_create(64, 96, L, L, 1.0, 0.01, 1e-4)

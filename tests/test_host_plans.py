@@ -75,7 +75,8 @@ def test_bad_arguments_rejected_on_host(lib):
 
 def test_shape_count_matches_header():
     text = open(HEADER).read()
-    for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH"):
+    for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH",
+                 "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES"):
         m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
         assert m and int(m.group(1)) == getattr(chx, name), name
 
