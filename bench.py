@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 METRIC = "CH ADI grid-pt updates/s; penta-solve HBM GB/s % peak; FP32-refined vs FP64"
 CSRC = os.path.join(ROOT, "paper_2101_06550_amd", "csrc")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ch_adi_8192x8192_fp64_traffic.md")
+KERNEL_PROFILE = os.path.join(ROOT, "profiles", "ch_adi_8192x8192_fp64_kernel_stats.md")
 KERNEL_OF_PHASE = {"column_pass": "ch_column_pass", "column_separators": "reduced_il_lds",
                    "row_pass": "row_solve_lds", "separator_rows": "rows_sep",
                    "separators_and_interior_rows": "rows_split_fused"}
@@ -88,6 +89,12 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
                         rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
         return rows
 
+    def after_marker(rows):
+        # the calibration copies run after the handle is created (and tuned):
+        # only the dispatches that follow them belong to the timed workload
+        last = max(int(r["Dispatch_Id"]) for r in rows if "stream_copy_kernel" in r["Kernel_Name"])
+        return [r for r in rows if int(r["Dispatch_Id"]) > last]
+
     true_kib = float(1 << 20)  # 1 GiB copy: 1 GiB read and 1 GiB written
     per = {}
     scale = {}
@@ -97,7 +104,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
         calib = [v for v in calib if 0.5 * true_kib < v < 2 * true_kib]
         scale[counter] = true_kib / (sum(calib) / len(calib))
         acc = collections.defaultdict(list)
-        for r in rows:
+        for r in after_marker(rows):
             name = r["Kernel_Name"]
             short = name.split("(")[0].replace("void ", "").split("<")[0].split("::")[-1]
             acc[short].append(float(r["Counter_Value"]))
@@ -132,6 +139,42 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines))
     return blob
+
+
+def summarize_trace(trace_dir, out_path, command, note):
+    """Per-kernel duration statistics of the dispatches that follow the last
+    calibration copy in a rocprofv3 --kernel-trace run (the timed workload,
+    without the autotuning launches of handle creation)."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(trace_dir):
+        for f in files:
+            if f.endswith("kernel_trace.csv"):
+                with open(os.path.join(root, f)) as fh:
+                    rows += list(csv.DictReader(fh))
+    last = max(int(r["Dispatch_Id"]) for r in rows if "stream_copy_kernel" in r["Kernel_Name"])
+    stats = {}
+    for r in rows:
+        if int(r["Dispatch_Id"]) <= last:
+            continue
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").split("<")[0].split("::")[-1]
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        stats.setdefault(name, []).append(d)
+    total = sum(sum(v) for v in stats.values())
+    lines = ["# Kernel trace: CH ADI step, 8192 x 8192, FP64 (large single-run workload)", "",
+             "Command (run from the repository root on one MI355X):", "", "    " + command, "",
+             "Summarised with `python bench.py --summarize-trace <trace dir>` over the "
+             "dispatches that follow the calibration copy (the warm-up, timed and "
+             "per-kernel-timing steps; not the autotuning launches of handle creation).", "",
+             note, "",
+             "| Kernel | Calls | Total ns | Average ns | % | Min ns | Max ns |",
+             "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| {name} | {len(v)} | {sum(v)} | {sum(v) / len(v):.1f} | "
+                     f"{100.0 * sum(v) / total:.2f} | {min(v)} | {max(v)} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return {k: sum(v) / len(v) for k, v in stats.items()}
 
 
 def stored_traffic(kernel):
@@ -425,6 +468,12 @@ def main():
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace run into the kernel profile")
+    ap.add_argument("--trace-note", default="",
+                    help="text added to the kernel profile (--summarize-trace)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large workload: no side measurements (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run the plain 1 GiB streaming copy three times (the "
                          "reference kernel for scaling hardware byte counters)")
@@ -432,8 +481,15 @@ def main():
     if args.summarize_pmc:
         cmd = ("timeout -s KILL 120 rocprofv3 --pmc {C} -d gpurun_out/pmc_{C} -o run "
                "--output-format csv -- python3 bench.py --steps 3 --warmup 0 --no-cpu-baseline "
-               "--no-solves --no-ensemble --no-precision --no-refined --calibrate-copy")
+               "--large-only --calibrate-copy")
         print(json.dumps(summarize_pmc(*args.summarize_pmc, TRAFFIC_PROFILE, cmd)))
+        return
+    if args.summarize_trace:
+        cmd = ("rocprofv3 --kernel-trace --stats -T -d gpurun_out/prof_large -o run "
+               "--output-format csv -- python3 bench.py --no-cpu-baseline --large-only "
+               "--calibrate-copy --steps 20 --warmup 2")
+        print(json.dumps(summarize_trace(args.summarize_trace, KERNEL_PROFILE, cmd,
+                                         args.trace_note)))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -455,18 +511,18 @@ def main():
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
         return
-    if args.calibrate_copy:
+    L = 2 * math.pi
+    n, D, gamma, dt = args.n, 1.0, 0.001, 1e-6
+    log(f"building initial state {n}x{n}")
+    c0 = inputs.mode_plus_noise(n, 5)
+    h = chx.ch_create(n, n, L, L, D, gamma, dt)  # factors and autotunes
+    if args.calibrate_copy:  # after creation: also marks where the workload starts
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             chx.chx_stream_copy(src, dst)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
-    L = 2 * math.pi
-    n, D, gamma, dt = args.n, 1.0, 0.001, 1e-6
-    log(f"building initial state {n}x{n}")
-    c0 = inputs.mode_plus_noise(n, 5)
-    h = chx.ch_create(n, n, L, L, D, gamma, dt)
     c = torch.tensor(c0, device="cuda")
     K, W = args.steps, args.warmup
     diag = torch.zeros(2 * (K + 1), dtype=torch.float64, device="cuda")
@@ -525,9 +581,13 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic)}
 
-    extra = {"hbm_copy_reference_1GiB": copy_reference(chx, torch)}
-    log("small 128^2 run")
-    extra["small_128_1000_steps"] = small_run(chx, torch)
+    extra = {}
+    if args.large_only:
+        args.no_solves = args.no_ensemble = args.no_precision = args.no_refined = True
+    else:
+        extra["hbm_copy_reference_1GiB"] = copy_reference(chx, torch)
+        log("small 128^2 run")
+        extra["small_128_1000_steps"] = small_run(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)
