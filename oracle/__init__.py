@@ -67,6 +67,10 @@ def load(path: str | None = None):
     lib.orc_ch_rhs.argtypes = [_P, _P, _I, _I, _D, _D, _D, _D, _D]
     lib.orc_ch_step.restype = _I
     lib.orc_ch_step.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D]
+    lib.orc_ch2_rhs.restype = None
+    lib.orc_ch2_rhs.argtypes = [_P, _P, _P, _I, _I, _D, _D, _D, _D, _D]
+    lib.orc_ch2_step.restype = _I
+    lib.orc_ch2_step.argtypes = [_P, _P, _I, _I, _D, _D, _D, _D, _D]
     lib.orc_ch_mass.restype = _D
     lib.orc_ch_mass.argtypes = [_P, _I, _I, _D, _D]
     lib.orc_ch_energy.restype = _D
@@ -184,6 +188,24 @@ class Oracle:
             if rc:
                 raise ValueError(f"ch step failed ({rc})")
         return c
+
+    # Ch.3 eq. 3:ch_adi (the thesis's delta-form scheme with 2/3 factors)
+    def ch2_rhs(self, c2d, cprev2d, lx, ly, D, gamma, dt):
+        c, cp = _f64(c2d), _f64(cprev2d)
+        ny, nx = c.shape
+        r = np.zeros_like(c)
+        self.lib.orc_ch2_rhs(_ptr(c), _ptr(cp), _ptr(r), nx, ny, lx, ly, D, gamma, dt)
+        return r
+
+    def ch2_step(self, c2d, cprev2d, lx, ly, D, gamma, dt, nsteps=1):
+        """Advance (C^n, C^{n-1}) by nsteps; returns the new (C, C_prev)."""
+        c, cp = _f64(c2d).copy(), _f64(cprev2d).copy()
+        ny, nx = c.shape
+        for _ in range(nsteps):
+            rc = self.lib.orc_ch2_step(_ptr(c), _ptr(cp), nx, ny, lx, ly, D, gamma, dt)
+            if rc:
+                raise ValueError(f"ch2 step failed ({rc})")
+        return c, cp
 
     def ch_mass(self, c2d, lx, ly):
         c = _f64(c2d)

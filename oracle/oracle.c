@@ -343,6 +343,7 @@ int orc_ctri_lines(int nx, int ny, int direction, double a, double b, double c,
  * untouched); premap 1 applies the stencil to c^3 - c instead of c, the role
  * of the function-pointer stencil in the Cahn-Hilliard example. */
 static int wrap(int k, int n) { return ((k % n) + n) % n; }
+static double mu_of(double v) { return v * v * v - v; }
 
 int orc_stencil2d(const double* in, double* out, int nx, int ny,
                   const double* w, int left, int right, int top, int bottom,
@@ -420,6 +421,74 @@ int orc_ch_step(double* c, int nx, int ny, double lx, double ly, double D,
                           sy, r);
   if (rc == 0) memcpy(c, r, sizeof(double) * (size_t)nx * ny);
   free(r);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ch.3 eq. 3:ch_adi, the thesis's own scheme, in its order:
+ *   L_x w = -2/3 (C^n - C^{n-1}) - 2/3 D gamma dt Lap^2 Cbar + 2/3 D dt Lap (C^3 - C)^n
+ *   L_y v = w,   C^{n+1} = Cbar + v,   L = I + 2/3 D gamma dt d4 (per direction)
+ * with the readings: Cbar = 2 C^n - C^{n-1} (the extrapolation of the stable
+ * hyperdiffusion ADI the thesis builds on), D gamma in the biharmonic term
+ * (as in L_x), C^{-1} = C^0 at the start, second-order central differences:
+ * Lap = d2x + d2y (5 points), Lap^2 = d4x + 2 d2x d2y + d4y (13 points in the
+ * 5 x 5 square), d4 = (1, -4, 6, -4, 1) / h^4. */
+void orc_ch2_rhs(const double* c, const double* cprev, double* r, int nx,
+                 int ny, double lx, double ly, double D, double gamma,
+                 double dt) {
+  const double dx = lx / nx, dy = ly / ny;
+  const double dx2 = dx * dx, dy2 = dy * dy;
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      /* Cbar at offsets (p, q), p along x, q along y */
+#define CB(p, q)                                                      \
+  (2.0 * c[(size_t)wrap(j + (q), ny) * nx + wrap(i + (p), nx)] -      \
+   cprev[(size_t)wrap(j + (q), ny) * nx + wrap(i + (p), nx)])
+#define MU(p, q) mu_of(c[(size_t)wrap(j + (q), ny) * nx + wrap(i + (p), nx)])
+      double d4x = (CB(-2, 0) - 4.0 * CB(-1, 0) + 6.0 * CB(0, 0) -
+                    4.0 * CB(1, 0) + CB(2, 0)) / (dx2 * dx2);
+      double d4y = (CB(0, -2) - 4.0 * CB(0, -1) + 6.0 * CB(0, 0) -
+                    4.0 * CB(0, 1) + CB(0, 2)) / (dy2 * dy2);
+      /* d2x d2y Cbar: second difference in x of the second differences in y */
+      double dyy_w = CB(-1, 1) + CB(-1, -1) - 2.0 * CB(-1, 0);
+      double dyy_c = CB(0, 1) + CB(0, -1) - 2.0 * CB(0, 0);
+      double dyy_e = CB(1, 1) + CB(1, -1) - 2.0 * CB(1, 0);
+      double dxxyy = (dyy_e + dyy_w - 2.0 * dyy_c) / (dx2 * dy2);
+      double bih = d4x + 2.0 * dxxyy + d4y;
+      double lap = (MU(1, 0) + MU(-1, 0) - 2.0 * MU(0, 0)) / dx2 +
+                   (MU(0, 1) + MU(0, -1) - 2.0 * MU(0, 0)) / dy2;
+#undef CB
+#undef MU
+      const size_t k = (size_t)j * nx + i;
+      r[k] = -(2.0 / 3.0) * (c[k] - cprev[k]) -
+             (2.0 / 3.0) * D * gamma * dt * bih + (2.0 / 3.0) * D * dt * lap;
+    }
+  }
+}
+
+int orc_ch2_step(double* c, double* cprev, int nx, int ny, double lx,
+                 double ly, double D, double gamma, double dt) {
+  if (nx < 5 || ny < 5) return -1;
+  const double dx = lx / nx, dy = ly / ny;
+  const double sx = (2.0 / 3.0) * D * gamma * dt / (dx * dx * dx * dx);
+  const double sy = (2.0 / 3.0) * D * gamma * dt / (dy * dy * dy * dy);
+  const size_t n = (size_t)nx * ny;
+  double* w = (double*)malloc(sizeof(double) * n);
+  orc_ch2_rhs(c, cprev, w, nx, ny, lx, ly, D, gamma, dt);
+  /* L_x w = RHS (rows), then L_y v = w (columns), in place */
+  int rc = orc_cpenta_lines(nx, ny, 0, sx, -4.0 * sx, 1.0 + 6.0 * sx,
+                            -4.0 * sx, sx, w);
+  if (rc == 0)
+    rc = orc_cpenta_lines(nx, ny, 1, sy, -4.0 * sy, 1.0 + 6.0 * sy, -4.0 * sy,
+                          sy, w);
+  if (rc == 0) {
+    for (size_t k = 0; k < n; ++k) {
+      const double cbar = 2.0 * c[k] - cprev[k];
+      cprev[k] = c[k];
+      c[k] = cbar + w[k];
+    }
+  }
+  free(w);
   return rc;
 }
 

@@ -124,6 +124,14 @@ int orc_ch_step(double* c, int nx, int ny, double lx, double ly, double D,
                 double gamma, double dt);
 /* Mass dx dy sum(c) (compensated sum) and the discrete free energy
  *   dx dy sum[ (c^2-1)^2/4 + gamma/2 ((D+x c)^2 + (D+y c)^2) ]. */
+/* Ch.3 eq. 3:ch_adi (the thesis's own delta-form scheme with 2/3 factors):
+ * right-hand side from C^n (c) and C^{n-1} (cprev), and one step that
+ * advances both in place (cprev <- C^n, c <- C^{n+1}). */
+void orc_ch2_rhs(const double* c, const double* cprev, double* r, int nx,
+                 int ny, double lx, double ly, double D, double gamma,
+                 double dt);
+int orc_ch2_step(double* c, double* cprev, int nx, int ny, double lx,
+                 double ly, double D, double gamma, double dt);
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly);
 double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
                      double gamma);

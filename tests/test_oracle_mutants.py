@@ -92,8 +92,29 @@ def pin_stencil_asymmetric(o):
     return np.max(np.abs(out - ref)) < 1e-13
 
 
+def pin_p2_step_fft(o):
+    """One step of the thesis's delta-form scheme (Ch.3 eq. 3:ch_adi) against
+    its Fourier-space solution (c, c_prev arbitrary; the cube is pointwise)."""
+    nx, ny, D, g, dt = 32, 24, 1.0, 0.01, 1e-3
+    c = inputs.noise_field(ny, nx, 6)
+    cp = inputs.noise_field(ny, nx, 7)
+    k2x = (4.0 / (L / nx) ** 2) * np.sin(np.pi * np.fft.fftfreq(nx, d=1.0 / nx) / nx) ** 2
+    k2y = (4.0 / (L / ny) ** 2) * np.sin(np.pi * np.fft.fftfreq(ny, d=1.0 / ny) / ny) ** 2
+    k2x, k2y = k2x[None, :], k2y[:, None]
+    a, b = 2.0 / 3.0 * D * g * dt, 2.0 / 3.0 * D * dt
+    cbar = 2 * c - cp
+    r = -2.0 / 3.0 * (c - cp) \
+        - a * np.real(np.fft.ifft2((k2x + k2y) ** 2 * np.fft.fft2(cbar))) \
+        + b * np.real(np.fft.ifft2(-(k2x + k2y) * np.fft.fft2(c ** 3 - c)))
+    v = np.real(np.fft.ifft2(np.fft.fft2(r) / ((1 + a * k2x ** 2) * (1 + a * k2y ** 2))))
+    out, prev = o.ch2_step(c, cp, L, L, D, g, dt)
+    ref = cbar + v
+    return (np.max(np.abs(out - ref)) / np.max(np.abs(ref)) < 1e-13 and
+            np.array_equal(prev, c))
+
+
 ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
-            pin_stencil_asymmetric]
+            pin_stencil_asymmetric, pin_p2_step_fft]
 
 MUTANTS = {
     "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
@@ -114,6 +135,17 @@ MUTANTS = {
     "thomas_back_typo": ("for (int i = n - 2; i >= 0; --i) x[i] = dh[i] - chat[i] * x[i + 1];",
                          "for (int i = n - 2; i >= 0; --i) x[i] = dh[i] - a[i] * chat[i];"),
     "energy_half_bulk": ("double v = 0.25 * w * w", "double v = 0.5 * w * w"),
+    "p2_biharmonic_cross_once": ("double bih = d4x + 2.0 * dxxyy + d4y;",
+                                 "double bih = d4x + dxxyy + d4y;"),
+    "p2_difference_sign": ("r[k] = -(2.0 / 3.0) * (c[k] - cprev[k]) -",
+                           "r[k] = (2.0 / 3.0) * (c[k] - cprev[k]) -"),
+    "p2_no_extrapolation": ("const double cbar = 2.0 * c[k] - cprev[k];",
+                            "const double cbar = c[k];"),
+    "p2_operator_without_two_thirds": (
+        "const double sx = (2.0 / 3.0) * D * gamma * dt / (dx * dx * dx * dx);",
+        "const double sx = D * gamma * dt / (dx * dx * dx * dx);"),
+    "p2_biharmonic_without_gamma": ("(2.0 / 3.0) * D * gamma * dt * bih",
+                                    "(2.0 / 3.0) * dt * bih"),
     "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
                                    "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
 }
