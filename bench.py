@@ -318,6 +318,35 @@ def small_run(chx, torch, steps=1000):
     return out
 
 
+def p2_run(chx, torch):
+    """The thesis's own delta-form scheme (Ch.3 eq. 3:ch_adi): time per step
+    at 1024^2 (dt = 1e-5, gamma = 0.01) and 8192^2 (the large workload's
+    parameters), FP64, and the one-step error against the oracle at 1024^2."""
+    import oracle
+    from paper_2101_06550_amd import inputs
+    L = 2 * math.pi
+    out = {}
+    for n, g, dt, c0, k in ((1024, 0.01, 1e-5, inputs.noise_field(1024, 1024, 3), 200),
+                           (8192, 0.001, 1e-6, inputs.mode_plus_noise(8192, 5), 20)):
+        h = chx.ch_create(n, n, L, L, 1.0, g, dt, scheme=chx.CHX_SCHEME_P2)
+        c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
+        chx.ch_adi_step_p2(h, c, cp, nsteps=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chx.ch_adi_step_p2(h, c, cp, nsteps=k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ent = {"steps": k, "ms_per_step": round(1e3 * el / k, 5), "updates_per_s": n * n * k / el}
+        if n == 1024:
+            c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
+            chx.ch_adi_step_p2(h, c, cp, nsteps=1)
+            ref, _ = oracle.oracle().ch2_step(c0, c0, L, L, 1.0, g, dt)
+            ent["one_step_rel_err_vs_oracle"] = rel_inf(c.cpu().numpy(), ref)
+        out[f"{n}x{n}"] = ent
+        del c, cp, h
+    return out
+
+
 def copy_reference(chx, torch, reps=20):
     """The library's plain streaming copy of 1 GiB of FP64 (read 1 GiB, write
     1 GiB): the HBM rate a simple streaming kernel reaches on this part, for
@@ -464,7 +493,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
-    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning"],
+    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -507,7 +536,8 @@ def main():
 
     if args.only:
         fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
-              "small": small_run, "tuning": tuning_sweep, "precision": lambda c, t: {
+              "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
+              "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
         return
@@ -588,6 +618,8 @@ def main():
         extra["hbm_copy_reference_1GiB"] = copy_reference(chx, torch)
         log("small 128^2 run")
         extra["small_128_1000_steps"] = small_run(chx, torch)
+        log("thesis delta-form scheme")
+        extra["thesis_scheme_p2"] = p2_run(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)

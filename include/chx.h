@@ -163,7 +163,17 @@ typedef struct {
   double D, gamma, dt;   /* mobility, interface parameter, time step      */
   int dtype;             /* CHX_F64 or CHX_F32_REFINED (see below)       */
   int refine_passes;     /* 1..3 for CHX_F32_REFINED, ignored for FP64    */
+  int scheme;            /* CHX_SCHEME_P1 (above) or CHX_SCHEME_P2 (below) */
 } chx_ch_params;
+
+/* scheme CHX_SCHEME_P2: the thesis's own delta-form scheme (Ch.3
+ * eq. 3:ch_adi), with Cbar = 2 C^n - C^{n-1}:
+ *   r = -2/3 (C^n - C^{n-1}) - 2/3 D gamma dt Lap^2 Cbar + 2/3 D dt Lap (C^3 - C)^n
+ *   (I + s' P_x)(I + s' P_y) v = r,  s' = 2/3 D gamma dt / h^4,  C^{n+1} = Cbar + v,
+ * Lap the 5-point and Lap^2 the 13-point (5 x 5) second-order stencils.  It
+ * needs two states and is advanced by ch_adi_step_p2; FP64 only. */
+#define CHX_SCHEME_P1 0
+#define CHX_SCHEME_P2 1
 
 /* dtype CHX_F32_REFINED: the right-hand side is formed in FP64, the column
  * and row sweeps run in FP32 (FP32 copies of the factorisation), and
@@ -185,6 +195,17 @@ size_t ch_ws_bytes(chx_ch h);
  *   Asynchronous on stream s.  Calls sharing ws must not overlap. */
 int ch_adi_step(chx_ch h, double* c_inout, long ld, int nsteps,
                 double* diag_out, void* ws, size_t ws_bytes, chx_stream s);
+
+/* ch_adi_step_p2: advance a CHX_SCHEME_P2 handle's two states in place by
+ *   nsteps >= 1 steps: on entry c_inout = C^n and cprev_inout = C^{n-1} (pass
+ *   a copy of C^0 as C^{-1} to start, the thesis's choice), on exit
+ *   C^{n+nsteps} and C^{n+nsteps-1}.  Both device arrays nx x ny with leading
+ *   dimension ld >= nx, not overlapping; ws, diag_out and the stream as for
+ *   ch_adi_step.  CHX_EINVAL on a P1 handle (and ch_adi_step, ch_adi_step_timed
+ *   return CHX_EINVAL on a P2 handle). */
+int ch_adi_step_p2(chx_ch h, double* c_inout, double* cprev_inout, long ld,
+                   int nsteps, double* diag_out, void* ws, size_t ws_bytes,
+                   chx_stream s);
 
 /* ch_adi_step_timed: ch_adi_step with a HIP event recorded on stream s
  *   around every kernel it launches; synchronises s and returns, per phase,
@@ -253,7 +274,7 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
  * whole nsteps sequence is captured once in a hipGraph and replayed.
  *
  * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array).  Every run
- *   must use CHX_F64 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 8
+ *   must use CHX_F64 and CHX_SCHEME_P1 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 8
  *   distinct (grid, D, gamma, dt) classes; else CHX_EINVAL.
  * ch_ensemble_ws_bytes: device workspace for ch_ensemble_step.
  * ch_ensemble_step: advance every run by nsteps >= 1 steps in place.

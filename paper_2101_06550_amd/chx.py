@@ -23,6 +23,8 @@ CHX_ENONFINITE = -5
 CHX_ENOMEM = -6
 CHX_EREFINE = -7
 
+CHX_SCHEME_P1 = 0
+CHX_SCHEME_P2 = 1
 CHX_F64 = 0
 CHX_F32_REFINED = 1
 CHX_INTERLEAVED = 0
@@ -34,7 +36,8 @@ EXPORTED = [
     "penta_factor", "penta_plan_destroy", "penta_solve_ws_bytes", "penta_solve_batch",
     "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
     "stencil2d_apply",
-    "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_timed",
+    "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
+    "ch_adi_step_timed",
     "ch_get_tuning", "ch_set_tuning", "ch_diagnostics",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
@@ -52,7 +55,8 @@ class ChParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("D", ctypes.c_double), ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
-                ("dtype", ctypes.c_int), ("refine_passes", ctypes.c_int)]
+                ("dtype", ctypes.c_int), ("refine_passes", ctypes.c_int),
+                ("scheme", ctypes.c_int)]
 
 
 _lib = None
@@ -93,6 +97,7 @@ def load(path: str | None = None):
         "ch_ws_bytes": (_S, [_V]),
         "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
+        "ch_adi_step_p2": (_I, [_V, _V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_get_tuning": (_I, [_V, _I, _IP]),
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
@@ -263,8 +268,9 @@ def stencil2d_apply(inp, out, weights, left: int, right: int, top: int, bottom: 
 class CH:
     """Handle of ch_create (factored operators for one grid and time step)."""
 
-    def __init__(self, nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0):
-        self.params = ChParams(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes)
+    def __init__(self, nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0,
+                 scheme=CHX_SCHEME_P1):
+        self.params = ChParams(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes, scheme)
         h = ctypes.c_void_p()
         _check(load().ch_create(ctypes.byref(self.params), ctypes.byref(h)), "ch_create")
         self.handle = h
@@ -282,8 +288,9 @@ class CH:
             pass
 
 
-def ch_create(nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0) -> CH:
-    return CH(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes)
+def ch_create(nx, ny, lx, ly, D, gamma, dt, dtype=CHX_F64, refine_passes=0,
+              scheme=CHX_SCHEME_P1) -> CH:
+    return CH(nx, ny, lx, ly, D, gamma, dt, dtype, refine_passes, scheme)
 
 
 def ch_destroy(h: CH) -> None:
@@ -311,6 +318,27 @@ def ch_adi_step(h: CH, c, nsteps: int = 1, diag_out=None, ws=None, ld: int | Non
     dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
     _check(lib.ch_adi_step(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
                            _stream(stream)), "ch_adi_step")
+
+
+def ch_adi_step_p2(h: CH, c, cprev, nsteps: int = 1, diag_out=None, ws=None,
+                   ld: int | None = None, stream=None):
+    """Advance the two float64 device states of a CHX_SCHEME_P2 handle in
+    place: c = C^n, cprev = C^{n-1} on entry (a copy of C^0 to start), the
+    states nsteps later on exit."""
+    lib = load()
+    ld = c.stride(0) if ld is None else ld
+    if cprev.stride(0) != ld:
+        raise ChxError(CHX_EINVAL, "ch_adi_step_p2: c and cprev need one leading dimension")
+    nbytes = lib.ch_ws_bytes(h.handle)
+    if ws is None:
+        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
+            import torch
+            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
+        ws = h._ws
+    _, wsp, avail = _workspace(nbytes, ws, c.device)
+    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
+    _check(lib.ch_adi_step_p2(h.handle, _devptr(c, "c"), _devptr(cprev, "cprev"), ld, nsteps,
+                              dptr, wsp, avail, _stream(stream)), "ch_adi_step_p2")
 
 
 def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,

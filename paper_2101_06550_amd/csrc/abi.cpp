@@ -264,6 +264,7 @@ struct chx_ch_s {
   bool small = false;     // ... and is in use
   int split = -1;         // split row pass shape (-1: plain separators + rows)
   ChCoef K{};
+  Ch2Coef K2{};           // the thesis's delta-form scheme (CHX_SCHEME_P2)
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
   // FP32-sweep refined path: residual buffer, FP32 chunk solutions and partials
   size_t off_R = 0, off_y32 = 0, off_rho32 = 0;
@@ -581,12 +582,16 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     return CHX_EINVAL;
   if (q.dtype != CHX_F64 && q.dtype != CHX_F32_REFINED) return CHX_EINVAL;
   if (q.dtype == CHX_F32_REFINED && (q.refine_passes < 1 || q.refine_passes > 3)) return CHX_EINVAL;
+  if (q.scheme != CHX_SCHEME_P1 && q.scheme != CHX_SCHEME_P2) return CHX_EINVAL;
+  if (q.scheme == CHX_SCHEME_P2 && q.dtype != CHX_F64) return CHX_EINVAL;
   chx_ch_s* h = new (std::nothrow) chx_ch_s();
   if (!h) return CHX_ENOMEM;
   h->prm = q;
   const double dx = q.lx / q.nx, dy = q.ly / q.ny;
-  const double sx = q.D * q.gamma * q.dt / (dx * dx * dx * dx);
-  const double sy = q.D * q.gamma * q.dt / (dy * dy * dy * dy);
+  // P2 (the thesis's delta form) factors I + 2/3 D gamma dt d4 per direction
+  const double wgt = q.scheme == CHX_SCHEME_P2 ? 2.0 / 3.0 : 1.0;
+  const double sx = wgt * q.D * q.gamma * q.dt / (dx * dx * dx * dx);
+  const double sy = wgt * q.D * q.gamma * q.dt / (dy * dy * dy * dy);
   const double cxs[5] = {sx, -4 * sx, 1 + 6 * sx, -4 * sx, sx};
   const double cys[5] = {sy, -4 * sy, 1 + 6 * sy, -4 * sy, sy};
   int rc = make_plan(2, q.nx, cxs, 1, &h->px);
@@ -606,8 +611,15 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     h->cxs[k] = cxs[k];
     h->cys[k] = cys[k];
   }
-  h->fast = (q.nx % 64 == 0) && (q.ny % kChunk == 0) && h->px->has_chunk && h->py->has_chunk &&
-            h->px->chunk.S <= 256;
+  h->K2.a = (2.0 / 3.0) * q.D * q.gamma * q.dt;
+  h->K2.b = (2.0 / 3.0) * q.D * q.dt;
+  h->K2.inv_dx4 = 1.0 / (dx * dx * dx * dx);
+  h->K2.inv_dy4 = 1.0 / (dy * dy * dy * dy);
+  h->K2.inv_dx2dy2 = 1.0 / (dx * dx * dy * dy);
+  h->K2.inv_dx2 = 1.0 / (dx * dx);
+  h->K2.inv_dy2 = 1.0 / (dy * dy);
+  h->fast = q.scheme == CHX_SCHEME_P1 && (q.nx % 64 == 0) && (q.ny % kChunk == 0) &&
+            h->px->has_chunk && h->py->has_chunk && h->px->chunk.S <= 256;
   if (q.dtype == CHX_F32_REFINED && !h->fast) {  // the refined path uses the chunked kernels
     delete h;
     return CHX_EINVAL;
@@ -630,6 +642,10 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     h->part_count = std::max(ch_column_pass_blocks(q.nx, h->py->chunk.S), diag_parts);
   } else {
     h->off_r = off; off += field;
+    if (q.scheme == CHX_SCHEME_P2 && h->py->has_chunk) {  // column solve partials
+      h->off_rho = off;
+      off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(double));
+    }
     h->part_count = diag_parts;
   }
   h->off_part = off;
@@ -718,6 +734,7 @@ struct PhaseTimer {
 static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
                      size_t ws_bytes, hipStream_t st, PhaseTimer* tm) {
   if (!h || !c) return CHX_EINVAL;
+  if (h->prm.scheme != CHX_SCHEME_P1) return CHX_EINVAL;  // P2 handles: ch_adi_step_p2
   const int nx = h->prm.nx, ny = h->prm.ny;
   if (ld < nx || nsteps < 1) return CHX_EINVAL;
   if (!ws || ws_bytes < h->ws_total) return CHX_ENOMEM;
@@ -872,6 +889,45 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   return ok() ? CHX_OK : CHX_EHIP;
 }
 
+int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, double* diag_out,
+                   void* ws, size_t ws_bytes, chx_stream s) {
+  if (!h || !c || !cprev) return CHX_EINVAL;
+  if (h->prm.scheme != CHX_SCHEME_P2) return CHX_EINVAL;
+  const int nx = h->prm.nx, ny = h->prm.ny;
+  if (ld < nx || nsteps < 1) return CHX_EINVAL;
+  if (!ws || ws_bytes < h->ws_total) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  {  // the two states must not overlap
+    const char* a = reinterpret_cast<const char*>(c);
+    const char* b = reinterpret_cast<const char*>(cprev);
+    const size_t span = ((size_t)(ny - 1) * ld + nx) * sizeof(double);
+    if (a < b + span && b < a + span) return CHX_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(s);
+  auto* base = static_cast<unsigned char*>(ws);
+  double* r = reinterpret_cast<double*>(base + h->off_r);
+  double* rho = reinterpret_cast<double*>(base + h->off_rho);
+  double* part = reinterpret_cast<double*>(base + h->off_part);
+  const bool col_chunk = h->py->has_chunk;
+  const bool row_lds = h->px->has_chunk && h->px->chunk.S <= 256;
+  hipError_t e = hipSuccess;
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    if (diag_out) e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
+    if (e == hipSuccess) e = launch_ch2_rhs(c, cprev, ld, r, nx, nx, ny, h->K2, st);
+    // v = L_y^{-1} L_x^{-1} r: columns (interleaved), then rows (the two commute)
+    if (e == hipSuccess)
+      e = col_chunk ? launch_chunked_il<2>(h->py->dchunk, r, nx, nx, rho, st)
+                    : launch_whole<2>(h->py->dwhole, r, 1, nx, nx, st);
+    if (e == hipSuccess)
+      e = row_lds ? launch_rows_lds<2>(h->px->dchunk, r, nx, ny, st)
+                  : launch_whole<2>(h->px->dwhole, r, nx, 1, ny, st);
+    if (e == hipSuccess) e = launch_ch2_update(c, cprev, ld, r, nx, nx, ny, st);
+  }
+  if (e == hipSuccess && diag_out)
+    e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
 int ch_adi_step(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
                 size_t ws_bytes, chx_stream s) {
   return run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, static_cast<hipStream_t>(s),
@@ -927,7 +983,8 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   std::vector<chx_ch_params> reps;
   for (int r = 0; r < nruns; ++r) {
     const chx_ch_params& q = prm[r];
-    if (q.dtype != CHX_F64 || q.nx % 64 != 0 || q.ny % kChunk != 0 || q.nx / kChunk > 256 ||
+    if (q.dtype != CHX_F64 || q.scheme != CHX_SCHEME_P1 || q.nx % 64 != 0 ||
+        q.ny % kChunk != 0 || q.nx / kChunk > 256 ||
         !(q.lx > 0) || !(q.ly > 0) || !(q.dt > 0) || !(q.D >= 0) || !(q.gamma >= 0)) {
       delete E;
       return CHX_EINVAL;

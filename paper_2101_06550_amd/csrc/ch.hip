@@ -467,6 +467,86 @@ hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, in
 }
 
 // ---------------------------------------------------------------------------
+// The thesis's own scheme (Ch.3 eq. 3:ch_adi, delta form with 2/3 factors):
+//   r = -2/3 (C - Cp) - a Lap^2 (2C - Cp) + b Lap (C^3 - C),  a = 2/3 D gamma dt,
+//   b = 2/3 D dt;  v = (I + s' Px)^{-1} (I + s' Py)^{-1} r;  Cp <- C, C <- 2C - Cp + v.
+// ch2_rhs stages a 16 x 64 tile with a 2-point halo of Cbar = 2C - Cp,
+// mu = C^3 - C and d = C - Cp in LDS and evaluates the 13-point biharmonic and
+// the 5-point Laplacian from there.
+constexpr int kT2X = 64, kT2Y = 16, kT2H = 2;
+constexpr int kT2W = kT2X + 2 * kT2H, kT2R = kT2Y + 2 * kT2H;
+
+__global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c,
+                                               const double* __restrict__ cp, long ld,
+                                               double* __restrict__ r, long ldr, int nx, int ny,
+                                               Ch2Coef K) {
+  __shared__ double cb[kT2R][kT2W];
+  __shared__ double mu[kT2R][kT2W];
+  __shared__ double df[kT2R][kT2W];
+  const int i0 = blockIdx.x * kT2X, j0 = blockIdx.y * kT2Y;
+  for (int e = threadIdx.x; e < kT2R * kT2W; e += 256) {
+    const int tr = e / kT2W, tc = e - tr * kT2W;
+    int j = j0 - kT2H + tr, i = i0 - kT2H + tc;
+    j = (j % ny + ny) % ny;
+    i = (i % nx + nx) % nx;
+    const double vc = c[(long)j * ld + i], vp = cp[(long)j * ld + i];
+    cb[tr][tc] = 2.0 * vc - vp;
+    mu[tr][tc] = vc * vc * vc - vc;
+    df[tr][tc] = vc - vp;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i = i0 + tx;
+  if (i >= nx) return;
+  const int q = tx + kT2H;
+#pragma unroll
+  for (int u = 0; u < kT2Y / 4; ++u) {
+    const int j = j0 + ty + 4 * u;
+    if (j >= ny) break;
+    const int w = ty + 4 * u + kT2H;
+    const double d4x = (cb[w][q - 2] - 4.0 * cb[w][q - 1] + 6.0 * cb[w][q] - 4.0 * cb[w][q + 1] +
+                        cb[w][q + 2]) * K.inv_dx4;
+    const double d4y = (cb[w - 2][q] - 4.0 * cb[w - 1][q] + 6.0 * cb[w][q] - 4.0 * cb[w + 1][q] +
+                        cb[w + 2][q]) * K.inv_dy4;
+    const double dyy_w = cb[w + 1][q - 1] + cb[w - 1][q - 1] - 2.0 * cb[w][q - 1];
+    const double dyy_c = cb[w + 1][q] + cb[w - 1][q] - 2.0 * cb[w][q];
+    const double dyy_e = cb[w + 1][q + 1] + cb[w - 1][q + 1] - 2.0 * cb[w][q + 1];
+    const double dxxyy = (dyy_e + dyy_w - 2.0 * dyy_c) * K.inv_dx2dy2;
+    const double bih = d4x + 2.0 * dxxyy + d4y;
+    const double lap = (mu[w][q + 1] + mu[w][q - 1] - 2.0 * mu[w][q]) * K.inv_dx2 +
+                       (mu[w + 1][q] + mu[w - 1][q] - 2.0 * mu[w][q]) * K.inv_dy2;
+    r[(long)j * ldr + i] = -(2.0 / 3.0) * df[w][q] - K.a * bih + K.b * lap;
+  }
+}
+
+// Cp <- C, C <- (2C - Cp) + v, elementwise.
+__global__ __launch_bounds__(256) void ch2_update(double* __restrict__ c, double* __restrict__ cp,
+                                                  long ld, const double* __restrict__ v, long ldv,
+                                                  int nx, int ny) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= nx || j >= ny) return;
+  const long k = (long)j * ld + i;
+  const double vc = c[k], vp = cp[k];
+  cp[k] = vc;
+  c[k] = (2.0 * vc - vp) + v[(long)j * ldv + i];
+}
+
+hipError_t launch_ch2_rhs(const double* c, const double* cp, long ld, double* r, long ldr, int nx,
+                          int ny, const Ch2Coef& K, hipStream_t st) {
+  dim3 grid((nx + kT2X - 1) / kT2X, (ny + kT2Y - 1) / kT2Y);
+  hipLaunchKernelGGL(ch2_rhs, grid, dim3(256), 0, st, c, cp, ld, r, ldr, nx, ny, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_ch2_update(double* c, double* cp, long ld, const double* v, long ldv, int nx,
+                             int ny, hipStream_t st) {
+  dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+  hipLaunchKernelGGL(ch2_update, grid, dim3(256), 0, st, c, cp, ld, v, ldv, nx, ny);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Small grids: the whole field stays in one workgroup's LDS for every step of
 // a call, so a step costs no HBM traffic and no launch.  LDS holds the field F
 // (row pitch nx + nx/32: one pad element after every 32-element row segment,

@@ -16,6 +16,16 @@ struct ChCoef {
   double dxdy;          // cell area (mass and energy scale)
 };
 
+// Coefficients of the thesis's delta-form scheme (Ch.3 eq. 3:ch_adi).
+struct Ch2Coef {
+  double a, b;                   // 2/3 D gamma dt, 2/3 D dt
+  double inv_dx4, inv_dy4, inv_dx2dy2, inv_dx2, inv_dy2;
+};
+hipError_t launch_ch2_rhs(const double* c, const double* cp, long ld, double* r, long ldr, int nx,
+                          int ny, const Ch2Coef& K, hipStream_t st);
+hipError_t launch_ch2_update(double* c, double* cp, long ld, const double* v, long ldv, int nx,
+                             int ny, hipStream_t st);
+
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
                                  double* rho, const ChCoef& K, double* part, hipStream_t st);
