@@ -347,6 +347,47 @@ def p2_run(chx, torch):
     return out
 
 
+def table31_run(chx, torch, sizes=(64, 128, 256, 512, 1024, 2048, 4096), T=10.0,
+                eps_values=(1e-6, 1.0)):
+    """The convergence study of Table 3.1 with the thesis's scheme on the GPU:
+    C(x, 0) = eps tanh(r - pi), r = |x|, D = 1, gamma = 0.01, to T = 10 with
+    dt = 0.1 dx (rounded to a whole number of steps ending exactly at T), and
+    E_N = mean over the coarse cells of |(2 x 2 average of C_N) - C_{N/2}|;
+    eps = 1e-6 as printed, and eps = 1 (an interface of full amplitude)."""
+    return {f"eps_{e:g}": _table31_one(chx, torch, sizes, T, e) for e in eps_values}
+
+
+def _table31_one(chx, torch, sizes, T, eps):
+    L = 2 * math.pi
+    fields, out = {}, {}
+    for n in sizes:
+        dx = L / n
+        steps = int(round(T / (0.1 * dx)))
+        dt = T / steps
+        x = np.arange(n) * dx
+        c0 = eps * np.tanh(np.sqrt(x[None, :] ** 2 + x[:, None] ** 2) - math.pi)
+        h = chx.ch_create(n, n, L, L, 1.0, 0.01, dt, scheme=chx.CHX_SCHEME_P2)
+        c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chx.ch_adi_step_p2(h, c, cp, nsteps=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        fields[n] = c.cpu().numpy()
+        out[str(n)] = {"steps": steps, "dt": dt, "seconds": round(el, 3),
+                       "max_abs_C": float(np.max(np.abs(fields[n])))}
+        log(f"table 3.1 run eps={eps:g} N={n}: {steps} steps in {el:.2f} s")
+        del c, cp, h
+    for n in sizes[1:]:
+        f, cg = fields[n], fields[n // 2]
+        avg = 0.25 * (f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2])
+        out[str(n)]["E_N"] = float(np.mean(np.abs(avg - cg)))
+    for n in sizes[1:-1]:
+        out[str(n)]["log2_E_N_over_E_2N"] = math.log2(out[str(n)]["E_N"] /
+                                                      out[str(2 * n)]["E_N"])
+    return out
+
+
 def copy_reference(chx, torch, reps=20):
     """The library's plain streaming copy of 1 GiB of FP64 (read 1 GiB, write
     1 GiB): the HBM rate a simple streaming kernel reaches on this part, for
@@ -493,7 +534,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
-    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2"],
+    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2",
+                                       "table31"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -537,6 +579,7 @@ def main():
     if args.only:
         fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
               "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
+              "table31": table31_run,
               "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
