@@ -379,7 +379,7 @@ __device__ __forceinline__ void row_solve_body(const double* src, long lds, doub
           v.x += o.x;
           v.y += o.y;
         }
-        b2[t + 256 * u] = v;
+        store_stream(b2 + t + 256 * u, v);  // streamed: not re-read before the next pass
       }
     } else if (ldd == n) {
       const long nvalid = ((long)rows - row0) * n;
