@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void chunk_sweep_il(const double* src, long ld
   chunk_parts<P, M, T>(f, bd, pa, pb);
   Ty* yb = y + (long)k * M * ldy + s;
 #pragma unroll
-  for (int p = 0; p < M - P; ++p) yb[(long)p * ldy] = (Ty)f[p];
+  for (int p = 0; p < M - P; ++p) __builtin_nontemporal_store((Ty)f[p], &yb[(long)p * ldy]);
 #pragma unroll
   for (int a = 0; a < P; ++a) {
     rho[((long)k * 2 * P + a) * batch + s] = pa[a];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void correct_il(const Ty* y, long ldy, double*
 #pragma unroll
     for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
     if (ACC) ob[(long)p * ldo] += (double)v;
-    else ob[(long)p * ldo] = (double)v;
+    else __builtin_nontemporal_store((double)v, &ob[(long)p * ldo]);
   }
   if (ACC || (const void*)y != (const void*)out) {
 #pragma unroll
