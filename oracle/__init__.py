@@ -67,6 +67,8 @@ def load(path: str | None = None):
     lib.orc_ch_rhs.argtypes = [_P, _P, _I, _I, _D, _D, _D, _D, _D]
     lib.orc_ch_step.restype = _I
     lib.orc_ch_step.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D]
+    lib.orc_batch1d_step.restype = _I
+    lib.orc_batch1d_step.argtypes = [_I, _P, _I, _I, _D, _D, _D, _D]
     lib.orc_ch2_rhs.restype = None
     lib.orc_ch2_rhs.argtypes = [_P, _P, _P, _I, _I, _D, _D, _D, _D, _D]
     lib.orc_ch2_step.restype = _I
@@ -206,6 +208,17 @@ class Oracle:
             if rc:
                 raise ValueError(f"ch2 step failed ({rc})")
         return c, cp
+
+    # Ch.4 eq. disc / Ch.5 eq. 5:1ddiffscheme / Ch.6 eq. 6:1Dnumerical
+    def batch1d_step(self, kind, x2d, L, dt, a, D=1.0, nsteps=1):
+        """x2d: (n, batch) interleaved systems; returns the state nsteps later."""
+        x = _f64(x2d).copy()
+        n, batch = x.shape
+        for _ in range(nsteps):
+            rc = self.lib.orc_batch1d_step(int(kind), _ptr(x), n, batch, L, dt, a, D)
+            if rc:
+                raise ValueError(f"batch1d step failed ({rc})")
+        return x
 
     def ch_mass(self, c2d, lx, ly):
         c = _f64(c2d)

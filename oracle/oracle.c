@@ -492,6 +492,59 @@ int orc_ch2_step(double* c, double* cprev, int nx, int ny, double lx,
   return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Batched 1D periodic schemes on (0, L), dx = L/n, x interleaved: unknown i
+ * of system s at x[i * batch + s].  Each step forms the right-hand side of
+ * the chapter's scheme and solves the cyclic system of that chapter:
+ *  kind 0, Ch.4 eq. disc (Crank-Nicolson hyperdiffusion C_t = -a C_xxxx):
+ *    s = a dt / (2 dx^4);  (s, -4s, 1+6s, -4s, s) C^{n+1}
+ *                          = (-s, 4s, 1-6s, 4s, -s) C^n
+ *  kind 1, Ch.5 eq. 5:1ddiffscheme (Crank-Nicolson diffusion C_t = a C_xx):
+ *    s = a dt / (2 dx^2);  (-s, 1+2s, -s) C^{n+1} = (s, 1-2s, s) C^n
+ *  kind 2, Ch.6 eq. 6:1Dnumerical (1D Cahn-Hilliard, gamma = a):
+ *    s = a D dt / dx^4, al = D dt / dx^2, N = C^3 - C;
+ *    (s, -4s, 1+6s, -4s, s) C^{n+1} = C^n + al (N_{i-1} - 2 N_i + N_{i+1})
+ * (the printed f of Ch.6 omits the C^n of eq. 6:1Dnumerical; it is kept). */
+int orc_batch1d_step(int kind, double* x, int n, int batch, double L,
+                     double dt, double a, double D) {
+  if (kind < 0 || kind > 2 || batch < 1) return -1;
+  if (n < (kind == 1 ? 3 : 5)) return -1;
+  const double dx = L / n;
+  double* f = (double*)malloc(sizeof(double) * (size_t)n);
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  double s = 0.0, al = 0.0;
+  if (kind == 0) s = a * dt / (2.0 * dx * dx * dx * dx);
+  if (kind == 1) s = a * dt / (2.0 * dx * dx);
+  if (kind == 2) {
+    s = a * D * dt / (dx * dx * dx * dx);
+    al = D * dt / (dx * dx);
+  }
+  int rc = 0;
+  for (int b = 0; b < batch && rc == 0; ++b) {
+#define XV(i) x[(size_t)wrap((i), n) * batch + b]
+    for (int i = 0; i < n; ++i) {
+      if (kind == 0)
+        f[i] = -s * XV(i - 2) + 4.0 * s * XV(i - 1) + (1.0 - 6.0 * s) * XV(i) +
+               4.0 * s * XV(i + 1) - s * XV(i + 2);
+      else if (kind == 1)
+        f[i] = s * XV(i - 1) + (1.0 - 2.0 * s) * XV(i) + s * XV(i + 1);
+      else
+        f[i] = XV(i) + al * (mu_of(XV(i - 1)) - 2.0 * mu_of(XV(i)) +
+                             mu_of(XV(i + 1)));
+    }
+#undef XV
+    if (kind == 1)
+      rc = orc_cyclic_tri_solve(n, -s, 1.0 + 2.0 * s, -s, f, y);
+    else
+      rc = orc_cyclic_penta_solve(n, s, -4.0 * s, 1.0 + 6.0 * s, -4.0 * s, s,
+                                  f, y);
+    for (int i = 0; i < n; ++i) x[(size_t)i * batch + b] = y[i];
+  }
+  free(f);
+  free(y);
+  return rc;
+}
+
 /* Ch.2: conservation of the integral of C.  Neumaier-compensated sum. */
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly) {
   double s = 0.0, comp = 0.0;

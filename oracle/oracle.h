@@ -132,6 +132,12 @@ void orc_ch2_rhs(const double* c, const double* cprev, double* r, int nx,
                  double dt);
 int orc_ch2_step(double* c, double* cprev, int nx, int ny, double lx,
                  double ly, double D, double gamma, double dt);
+/* Batched 1D periodic schemes (unknown i of system s at x[i*batch + s]),
+ * one step in place: kind 0 Crank-Nicolson hyperdiffusion C_t = -a C_xxxx
+ * (Ch.4), kind 1 Crank-Nicolson diffusion C_t = a C_xx (Ch.5), kind 2 1D
+ * Cahn-Hilliard with gamma = a and mobility D (Ch.6 eq. 6:1Dnumerical). */
+int orc_batch1d_step(int kind, double* x, int n, int batch, double L,
+                     double dt, double a, double D);
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly);
 double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
                      double gamma);

@@ -113,8 +113,35 @@ def pin_p2_step_fft(o):
             np.array_equal(prev, c))
 
 
+def pin_batch1d_modes(o):
+    """Single Fourier modes of the three batched 1D schemes against their
+    exact discrete amplification factors (Ch.4, Ch.5, Ch.6)."""
+    n = 64
+    i = np.arange(n)[:, None]
+    m = np.array([1, 3, 7, 20])[None, :]
+    th = 2 * np.pi * m / n
+    s2, s4 = 4 * np.sin(th / 2) ** 2, 16 * np.sin(th / 2) ** 4
+    for kind, length, dt, a in ((0, 1.0, 1e-7, 1.0), (1, 1.0, 1e-4, 1.0), (2, L, 1e-3, 0.01)):
+        dx = length / n
+        eps = 1e-9 if kind == 2 else 1.0
+        x = eps * np.cos(2 * np.pi * m * i / n)
+        if kind == 0:
+            s = a * dt / (2 * dx ** 4)
+            G = (1 - s * s4) / (1 + s * s4)
+        elif kind == 1:
+            s = a * dt / (2 * dx ** 2)
+            G = (1 - s * s2) / (1 + s * s2)
+        else:
+            s, al = a * dt / dx ** 4, dt / dx ** 2
+            G = (1 + al * s2) / (1 + s * s4)
+        out = o.batch1d_step(kind, x, length, dt, a, 1.0, nsteps=3)
+        if np.max(np.abs(out - x * G ** 3)) > 1e-12 * eps:
+            return False
+    return True
+
+
 ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
-            pin_stencil_asymmetric, pin_p2_step_fft]
+            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes]
 
 MUTANTS = {
     "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
@@ -146,6 +173,11 @@ MUTANTS = {
         "const double sx = D * gamma * dt / (dx * dx * dx * dx);"),
     "p2_biharmonic_without_gamma": ("(2.0 / 3.0) * D * gamma * dt * bih",
                                     "(2.0 / 3.0) * dt * bih"),
+    "batch1d_cn_explicit_sign": ("(1.0 - 6.0 * s) * XV(i)", "(1.0 + 6.0 * s) * XV(i)"),
+    "batch1d_diffusion_full_weight": ("if (kind == 1) s = a * dt / (2.0 * dx * dx);",
+                                      "if (kind == 1) s = a * dt / (dx * dx);"),
+    "batch1d_ch_printed_rhs_without_state": ("f[i] = XV(i) + al * (mu_of(XV(i - 1))",
+                                             "f[i] = al * (mu_of(XV(i - 1))"),
     "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
                                    "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
 }
