@@ -388,6 +388,35 @@ def _table31_one(chx, torch, sizes, T, eps):
     return out
 
 
+def batch1d_run(chx, torch):
+    """Batched 1D periodic schemes: the 1D Cahn-Hilliard batch of the thesis's
+    coarsening statistics (2^20 systems of N = 256 on (0, 2 pi), gamma = 0.01,
+    dt = 0.1 dx, U[-0.1, 0.1], Ch.6-7) and Crank-Nicolson hyperdiffusion
+    (65536 systems of N = 1024, dt = 1e-12, the Ch.4 scheme); FP64, 100 steps;
+    algorithmic traffic 34 B per unknown per step."""
+    from paper_2101_06550_amd import inputs
+    out = {}
+    for name, kind, n, batch, L, dt, a in (
+            ("cahn_hilliard_1d_1048576x256", 2, 256, 1 << 20, 2 * math.pi,
+             0.1 * 2 * math.pi / 256, 0.01),
+            ("hyperdiffusion_cn_65536x1024", 0, 1024, 1 << 16, 1.0, 1e-12, 1.0)):
+        b = chx.batch1d_create(kind, n, L, dt, a)
+        x = torch.tensor(inputs.uniform(60, (n, batch), -0.1, 0.1), device="cuda")
+        chx.batch1d_step(b, x, nsteps=5)
+        torch.cuda.synchronize()
+        k = 100
+        t0 = time.perf_counter()
+        chx.batch1d_step(b, x, nsteps=k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
+                     "system_steps_per_s": batch * k / el,
+                     "algorithmic_GBps": round(34.0 * n * batch * k / el / 1e9, 1),
+                     "finite": bool(torch.isfinite(x).all())}
+        del x, b
+    return out
+
+
 def copy_reference(chx, torch, reps=20):
     """The library's plain streaming copy of 1 GiB of FP64 (read 1 GiB, write
     1 GiB): the HBM rate a simple streaming kernel reaches on this part, for
@@ -535,7 +564,7 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2",
-                                       "table31"],
+                                       "table31", "batch1d"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -579,7 +608,7 @@ def main():
     if args.only:
         fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
               "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
-              "table31": table31_run,
+              "table31": table31_run, "batch1d": batch1d_run,
               "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
@@ -663,6 +692,8 @@ def main():
         extra["small_128_1000_steps"] = small_run(chx, torch)
         log("thesis delta-form scheme")
         extra["thesis_scheme_p2"] = p2_run(chx, torch)
+        log("batched 1D schemes")
+        extra["batched_1d"] = batch1d_run(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)

@@ -149,6 +149,34 @@ int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
                     int bottom, int periodic, int premap, chx_stream s);
 
 /* ------------------------------------------------------------------------
+ * Batched 1D periodic time stepping: many independent systems of n unknowns
+ * on (0, L), dx = L / n, interleaved (unknown i of system b at i*ld + b,
+ * ld >= batch), one constant cyclic matrix factored once (batch1d_create).
+ * Each step forms the scheme's right-hand side from the state and solves:
+ *   CHX_1D_HYPERDIFFUSION_CN (Ch.4 eq. disc): C_t = -a C_xxxx, Crank-Nicolson,
+ *     s = a dt / (2 dx^4): (s,-4s,1+6s,-4s,s) C+ = (-s,4s,1-6s,4s,-s) C;
+ *   CHX_1D_DIFFUSION_CN (Ch.5 eq. 5:1ddiffscheme): C_t = a C_xx,
+ *     s = a dt / (2 dx^2): (-s,1+2s,-s) C+ = (s,1-2s,s) C;
+ *   CHX_1D_CAHN_HILLIARD (Ch.6 eq. 6:1Dnumerical), gamma = a, mobility D:
+ *     s = a D dt / dx^4, al = D dt / dx^2, N = C^3 - C:
+ *     (s,-4s,1+6s,-4s,s) C+ = C + al (N[i-1] - 2 N[i] + N[i+1]).
+ * batch1d_create: kind, n (>= 5, >= 3 for diffusion: else
+ *   CHX_EUNSUPPORTED_N), L, dt > 0, a, D >= 0 (D used by Cahn-Hilliard).
+ * batch1d_ws_bytes: device workspace (256-byte aligned) for batch systems.
+ * batch1d_step: advance x_inout (device) by nsteps >= 1 steps in place,
+ *   asynchronous on stream s; calls sharing ws must not overlap. */
+#define CHX_1D_HYPERDIFFUSION_CN 0
+#define CHX_1D_DIFFUSION_CN 1
+#define CHX_1D_CAHN_HILLIARD 2
+typedef struct chx_batch1d_s* chx_batch1d;
+int batch1d_create(int kind, int n, double L, double dt, double a, double D,
+                   chx_batch1d* out);
+int batch1d_destroy(chx_batch1d b);
+size_t batch1d_ws_bytes(chx_batch1d b, int batch);
+int batch1d_step(chx_batch1d b, int batch, double* x_inout, long ld, int nsteps,
+                 void* ws, size_t ws_bytes, chx_stream s);
+
+/* ------------------------------------------------------------------------
  * Cahn-Hilliard ADI stepping (Ch.2 eq. 2:ch, Ch.3 eq. 3:ch_adi).
  * One step on the periodic box [0,lx) x [0,ly), nx x ny points, dx = lx/nx:
  *   r = c + D dt Lap5(c^3 - c) - 2 D gamma dt (d2x d2y) c

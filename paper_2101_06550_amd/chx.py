@@ -39,6 +39,7 @@ EXPORTED = [
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
     "ch_get_tuning", "ch_set_tuning", "ch_diagnostics",
+    "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
@@ -101,6 +102,10 @@ def load(path: str | None = None):
         "ch_get_tuning": (_I, [_V, _I, _IP]),
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
+        "batch1d_create": (_I, [_I, _I, _D, _D, _D, _D, ctypes.POINTER(_V)]),
+        "batch1d_destroy": (_I, [_V]),
+        "batch1d_ws_bytes": (_S, [_V, _I]),
+        "batch1d_step": (_I, [_V, _I, _V, _L, _I, _V, _S, _V]),
         "ch_ensemble_create": (_I, [_I, ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
         "ch_ensemble_destroy": (_I, [_V]),
         "ch_ensemble_ws_bytes": (_S, [_V]),
@@ -370,6 +375,55 @@ def chx_stream_copy(src, dst, stream=None):
         raise ChxError(CHX_EINVAL, "chx_stream_copy: sizes differ")
     _check(load().chx_stream_copy(_devptr(src, "src"), _devptr(dst, "dst"), src.numel(),
                                   _stream(stream)), "chx_stream_copy")
+
+
+CHX_1D_HYPERDIFFUSION_CN = 0
+CHX_1D_DIFFUSION_CN = 1
+CHX_1D_CAHN_HILLIARD = 2
+
+
+class Batch1D:
+    """Handle of batch1d_create (one factored cyclic matrix for a batched 1D
+    periodic scheme)."""
+
+    def __init__(self, kind, n, L, dt, a, D=1.0):
+        h = ctypes.c_void_p()
+        _check(load().batch1d_create(int(kind), int(n), float(L), float(dt), float(a), float(D),
+                                     ctypes.byref(h)), "batch1d_create")
+        self.handle, self.n, self._ws = h, n, None
+
+    def close(self):
+        if self.handle:
+            load().batch1d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch1d_create(kind, n, L, dt, a, D=1.0) -> Batch1D:
+    return Batch1D(kind, n, L, dt, a, D)
+
+
+def batch1d_step(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None = None, stream=None):
+    """Advance the interleaved float64 device batch x (n, batch) in place."""
+    lib = load()
+    if x.dim() != 2 or x.shape[0] != b.n:
+        raise ChxError(CHX_EINVAL, "batch1d_step: x must be (n, batch)")
+    batch = x.shape[1]
+    ld = x.stride(0) if ld is None else ld
+    nbytes = lib.batch1d_ws_bytes(b.handle, batch)
+    if ws is None:
+        if b._ws is None or b._ws.numel() < nbytes + 256 or b._ws.device != x.device:
+            import torch
+            b._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=x.device)
+        ws = b._ws
+    _, wsp, avail = _workspace(nbytes, ws, x.device)
+    _check(lib.batch1d_step(b.handle, batch, _devptr(x, "x"), ld, nsteps, wsp, avail,
+                            _stream(stream)), "batch1d_step")
 
 
 CHX_TUNE_REDUCED_SHAPE = 0

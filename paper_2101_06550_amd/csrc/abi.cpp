@@ -447,6 +447,86 @@ int tri_solve_batch(chx_tri_plan p, int batch, void* x_inout, long ld, int layou
   return solve(p, batch, x_inout, ld, layout, dtype, refine_passes, ws, ws_bytes, s);
 }
 
+}  // extern "C"
+
+struct chx_batch1d_s {
+  int kind = 0, n = 0;
+  double s = 0.0, al = 0.0;
+  BandPlan* plan = nullptr;
+  ~chx_batch1d_s() { delete plan; }
+};
+
+extern "C" {
+
+int batch1d_create(int kind, int n, double L, double dt, double a, double D, chx_batch1d* out) {
+  if (!out) return CHX_EINVAL;
+  *out = nullptr;
+  if (kind < CHX_1D_HYPERDIFFUSION_CN || kind > CHX_1D_CAHN_HILLIARD) return CHX_EINVAL;
+  if (!(L > 0) || !(dt > 0) || !(a >= 0) || !(D >= 0) || !std::isfinite(L) ||
+      !std::isfinite(dt) || !std::isfinite(a) || !std::isfinite(D))
+    return CHX_EINVAL;
+  const int P = kind == CHX_1D_DIFFUSION_CN ? 1 : 2;
+  if (n < (P == 1 ? 3 : 5)) return CHX_EUNSUPPORTED_N;
+  chx_batch1d_s* b = new (std::nothrow) chx_batch1d_s();
+  if (!b) return CHX_ENOMEM;
+  b->kind = kind;
+  b->n = n;
+  const double dx = L / n;
+  int rc;
+  if (kind == CHX_1D_HYPERDIFFUSION_CN) {
+    b->s = a * dt / (2.0 * dx * dx * dx * dx);
+  } else if (kind == CHX_1D_DIFFUSION_CN) {
+    b->s = a * dt / (2.0 * dx * dx);
+  } else {
+    b->s = a * D * dt / (dx * dx * dx * dx);
+    b->al = D * dt / (dx * dx);
+  }
+  if (P == 1) {
+    const double co[3] = {-b->s, 1.0 + 2.0 * b->s, -b->s};
+    rc = make_plan(1, n, co, 1, &b->plan);
+  } else {
+    const double co[5] = {b->s, -4.0 * b->s, 1.0 + 6.0 * b->s, -4.0 * b->s, b->s};
+    rc = make_plan(2, n, co, 1, &b->plan);
+  }
+  if (rc != CHX_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CHX_OK;
+}
+
+int batch1d_destroy(chx_batch1d b) {
+  delete b;
+  return CHX_OK;
+}
+
+size_t batch1d_ws_bytes(chx_batch1d b, int batch) {
+  if (!b || batch <= 0) return 0;
+  size_t ws = align256((size_t)b->n * batch * sizeof(double));
+  if (b->plan->has_chunk)
+    ws += align256((size_t)b->plan->chunk.S * 2 * b->plan->P * (size_t)batch * sizeof(double));
+  return ws;
+}
+
+int batch1d_step(chx_batch1d b, int batch, double* x, long ld, int nsteps, void* ws,
+                 size_t ws_bytes, chx_stream s) {
+  if (!b || !x || batch < 0 || nsteps < 1) return CHX_EINVAL;
+  if (batch == 0) return CHX_OK;
+  if (ld < batch) return CHX_EINVAL;
+  if (!ws || ws_bytes < batch1d_ws_bytes(b, batch)) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  auto* base = static_cast<unsigned char*>(ws);
+  double* y = reinterpret_cast<double*>(base);
+  double* rho = reinterpret_cast<double*>(base + align256((size_t)b->n * batch * sizeof(double)));
+  hipStream_t st = static_cast<hipStream_t>(s);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k)
+    e = launch_batch1d_step(b->kind, b->plan->has_chunk, b->plan->dchunk, b->plan->dwhole, x, ld,
+                            batch, b->n, b->s, b->al, y, rho, st);
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
 int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
                     const double* weights, int left, int right, int top, int bottom, int periodic,
                     int premap, chx_stream s) {

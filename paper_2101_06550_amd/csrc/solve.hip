@@ -567,6 +567,119 @@ static BandT<T> band_of(const double* coef) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched 1D periodic schemes (Ch.4 eq. disc, Ch.5 eq. 5:1ddiffscheme,
+// Ch.6 eq. 6:1Dnumerical): the right-hand side of each step is a 3- or
+// 5-point stencil of the state, so the first pass of the chunked solve forms
+// it on the fly from the interleaved state (rows k M - 2 .. k M + M + 1 of
+// each 64-system segment) and sweeps the chunk interior in registers.
+template <int KIND>
+__device__ __forceinline__ double b1d_rhs(const double* X, int q, double s, double al) {
+  if (KIND == 0)
+    return -s * X[q - 2] + 4.0 * s * X[q - 1] + (1.0 - 6.0 * s) * X[q] + 4.0 * s * X[q + 1] -
+           s * X[q + 2];
+  if (KIND == 1) return s * X[q - 1] + (1.0 - 2.0 * s) * X[q] + s * X[q + 1];
+  const double ml = X[q - 1] * X[q - 1] * X[q - 1] - X[q - 1];
+  const double mc = X[q] * X[q] * X[q] - X[q];
+  const double mr = X[q + 1] * X[q + 1] * X[q + 1] - X[q + 1];
+  return X[q] + al * (ml - 2.0 * mc + mr);
+}
+
+template <int KIND, int P, int M>
+__global__ __launch_bounds__(256) void batch1d_sweep(const double* __restrict__ x, long ld,
+                                                     double* __restrict__ y, long ldy, int batch,
+                                                     int n, int S, const double* __restrict__ rec,
+                                                     BandT<double> bd, double* __restrict__ rho,
+                                                     double s, double al) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long sys = (long)blockIdx.x * 64 + lane;
+  const int k = blockIdx.y * 4 + wave;
+  if (sys >= batch || k >= S) return;
+  double X[M + 4];
+#pragma unroll
+  for (int q = 0; q < M + 4; ++q) {
+    int row = k * M - 2 + q;
+    row += (row < 0) ? n : 0;
+    row -= (row >= n) ? n : 0;
+    X[q] = x[(long)row * ld + sys];
+  }
+  double f[M];
+#pragma unroll
+  for (int p = 0; p < M; ++p) f[p] = b1d_rhs<KIND>(X, p + 2, s, al);
+  chunk_sweep<P, M, double>(f, rec, bd.c[0]);
+  double pa[P], pb[P];
+  chunk_parts<P, M, double>(f, bd, pa, pb);
+  double* yb = y + (long)k * M * ldy + sys;
+#pragma unroll
+  for (int p = 0; p < M - P; ++p) __builtin_nontemporal_store(f[p], &yb[(long)p * ldy]);
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    rho[((long)k * 2 * P + a) * batch + sys] = pa[a];
+    rho[((long)k * 2 * P + P + a) * batch + sys] = pb[a];
+  }
+}
+
+// Lengths without the chunked plan: the right-hand side alone, one thread
+// per (system, unknown), into y (pitch ldy).
+template <int KIND>
+__global__ __launch_bounds__(256) void batch1d_rhs(const double* __restrict__ x, long ld,
+                                                   double* __restrict__ y, long ldy, int batch,
+                                                   int n, double s, double al) {
+  const long sys = (long)blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (sys >= batch) return;
+  double X[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    int row = i - 2 + q;
+    row = (row % n + n) % n;
+    X[q] = x[(long)row * ld + sys];
+  }
+  y[(long)i * ldy + sys] = b1d_rhs<KIND>(X, 2, s, al);
+}
+
+hipError_t launch_batch1d_step(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
+                               double* x, long ld, int batch, int n, double s, double al,
+                               double* y, double* rho, hipStream_t st) {
+  const int P = kind == 1 ? 1 : 2;
+  if (chunked) {
+    dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
+    const BandT<double> bd = band_of<double>(c.coef);
+#define CHX_B1D(K_, P_)                                                                          \
+  hipLaunchKernelGGL((batch1d_sweep<K_, P_, kChunk>), grid, dim3(256), 0, st, x, ld, y,          \
+                     (long)batch, batch, n, c.S, c.rec, bd, rho, s, al)
+    if (kind == 0) CHX_B1D(0, 2);
+    else if (kind == 1) CHX_B1D(1, 1);
+    else CHX_B1D(2, 2);
+#undef CHX_B1D
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = P == 2 ? launch_reduced_il<2>(c, rho, batch, y, batch, kChunk, kChunk - 2, st)
+               : launch_reduced_il<1>(c, rho, batch, y, batch, kChunk, kChunk - 1, st);
+    if (e != hipSuccess) return e;
+    if (P == 2)
+      hipLaunchKernelGGL((correct_il<2, kChunk, double, double, false>), grid, dim3(256), 0, st, y,
+                         (long)batch, x, ld, batch, c.S, c.rec);
+    else
+      hipLaunchKernelGGL((correct_il<1, kChunk, double, double, false>), grid, dim3(256), 0, st, y,
+                         (long)batch, x, ld, batch, c.S, c.rec);
+    return hipGetLastError();
+  }
+  dim3 grid((batch + 255) / 256, n);
+  if (kind == 0)
+    hipLaunchKernelGGL(batch1d_rhs<0>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
+  else if (kind == 1)
+    hipLaunchKernelGGL(batch1d_rhs<1>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
+  else
+    hipLaunchKernelGGL(batch1d_rhs<2>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = P == 2 ? launch_whole<2>(w, y, 1, batch, batch, st) : launch_whole<1>(w, y, 1, batch, batch, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpy2DAsync(x, ld * sizeof(double), y, (size_t)batch * sizeof(double),
+                          (size_t)batch * sizeof(double), n, hipMemcpyDeviceToDevice, st);
+}
+
+// ---------------------------------------------------------------------------
 // Split row pass, for rows of 4096 or 8192 points (R = 2 or 1 rows per
 // group).  Only the separator rows (the last P rows of every 32-row column
 // chunk) need the column separators; every other row can be row-solved while

@@ -1,0 +1,79 @@
+"""GPU parity of the batched 1D periodic schemes (Ch.4 Crank-Nicolson
+hyperdiffusion, Ch.5 Crank-Nicolson diffusion, Ch.6 1D Cahn-Hilliard)
+against the oracle, for chunked lengths (right-hand side fused into the chunk
+sweep) and other lengths (whole-system sweeps)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2101_06550_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+L2PI = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def chx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_06550_amd import chx as m
+    m.load()
+    return m
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# (kind, n, batch, L, dt, a, D)
+CASES = [(0, 64, 1000, 1.0, 1e-8, 1.0, 1.0), (0, 1024, 300, 1.0, 1e-12, 1.0, 1.0),
+         (1, 256, 513, 1.0, 1e-4, 1.0, 1.0), (1, 50, 33, 1.0, 1e-3, 1.0, 1.0),
+         (2, 256, 4096, L2PI, 2.5e-3, 0.01, 1.0), (2, 96, 70, L2PI, 1e-3, 0.02, 0.7),
+         (2, 40, 65, L2PI, 1e-3, 0.01, 1.0), (2, 32, 64, L2PI, 1e-3, 0.01, 1.0)]
+
+
+@pytest.mark.parametrize("kind,n,batch,L,dt,a,D", CASES)
+def test_steps_match_oracle(chx, orc, kind, n, batch, L, dt, a, D):
+    x0 = inputs.uniform(40 + kind, (n, batch), -0.1, 0.1)
+    b = chx.batch1d_create(kind, n, L, dt, a, D)
+    x = torch.tensor(x0, device="cuda")
+    print(f"[case] batch1d kind={kind} n={n} batch={batch}", flush=True)
+    chx.batch1d_step(b, x, nsteps=3)
+    torch.cuda.synchronize()
+    ref = orc.batch1d_step(kind, x0, L, dt, a, D, nsteps=3)
+    assert rel(x.cpu().numpy(), ref) < 1e-12
+    # the mean is conserved up to the rounding of the solve: 20 eps (1 + 16 s) |x|
+    dx = L / n
+    s = {0: a * dt / (2 * dx ** 4), 1: a * dt / (2 * dx ** 2), 2: a * D * dt / dx ** 4}[kind]
+    m0, m1 = x0.mean(axis=0), x.cpu().numpy().mean(axis=0)
+    assert np.max(np.abs(m1 - m0)) < 20 * 2.2e-16 * (1 + 16 * s) * np.max(np.abs(x0))
+
+
+def test_leading_dimension(chx, orc):
+    x0 = inputs.uniform(50, (64, 100), -0.1, 0.1)
+    b = chx.batch1d_create(2, 64, L2PI, 1e-3, 0.01)
+    big = torch.full((64, 160), 9.0, dtype=torch.float64, device="cuda")
+    big[:, :100] = torch.tensor(x0, device="cuda")
+    chx.batch1d_step(b, big[:, :100], nsteps=2)
+    torch.cuda.synchronize()
+    out = big.cpu().numpy()
+    assert rel(out[:, :100], orc.batch1d_step(2, x0, L2PI, 1e-3, 0.01, nsteps=2)) < 1e-12
+    assert np.all(out[:, 100:] == 9.0)
+
+
+def test_hyperdiffusion_mode_decay(chx):
+    """A single mode decays by the exact discrete Crank-Nicolson factor."""
+    n, dt, steps = 128, 1e-9, 50
+    i = np.arange(n)[:, None]
+    m = np.array([1, 2, 9, 40])[None, :]
+    x0 = np.cos(2 * np.pi * m * i / n)
+    s = dt / (2 * (1.0 / n) ** 4)
+    s4 = 16 * np.sin(np.pi * m / n) ** 4
+    G = (1 - s * s4) / (1 + s * s4)
+    b = chx.batch1d_create(0, n, 1.0, dt, 1.0)
+    x = torch.tensor(x0, device="cuda")
+    chx.batch1d_step(b, x, nsteps=steps)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(x.cpu().numpy() - x0 * G ** steps)) < 1e-12

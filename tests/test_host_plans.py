@@ -68,6 +68,13 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.ch_create(ctypes.byref(prm), ctypes.byref(h)) == chx.CHX_EUNSUPPORTED_N
     prm = chx.ChParams(64, 64, 6.28, 6.28, 1.0, 0.01, -1.0, 0, 0)
     assert lib.ch_create(ctypes.byref(prm), ctypes.byref(h)) == chx.CHX_EINVAL
+    assert lib.batch1d_create(7, 64, 1.0, 1e-3, 1.0, 1.0, ctypes.byref(h)) == chx.CHX_EINVAL
+    assert lib.batch1d_create(0, 4, 1.0, 1e-3, 1.0, 1.0, ctypes.byref(h)) == chx.CHX_EUNSUPPORTED_N
+    assert lib.batch1d_create(1, 2, 1.0, 1e-3, 1.0, 1.0, ctypes.byref(h)) == chx.CHX_EUNSUPPORTED_N
+    assert lib.batch1d_create(2, 64, 1.0, -1.0, 1.0, 1.0, ctypes.byref(h)) == chx.CHX_EINVAL
+    assert lib.batch1d_create(2, 64, 1.0, 1e-3, 1.0, 1.0, None) == chx.CHX_EINVAL
+    assert lib.batch1d_step(None, 4, None, 4, 1, None, 0, None) == chx.CHX_EINVAL
+    assert lib.batch1d_ws_bytes(None, 4) == 0
     v = ctypes.c_int()
     assert lib.ch_get_tuning(None, 0, ctypes.byref(v)) == chx.CHX_EINVAL
     assert lib.ch_set_tuning(None, 0, 0) == chx.CHX_EINVAL
@@ -76,7 +83,8 @@ def test_bad_arguments_rejected_on_host(lib):
 def test_shape_count_matches_header():
     text = open(HEADER).read()
     for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH",
-                 "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES"):
+                 "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES", "CHX_SCHEME_P1", "CHX_SCHEME_P2",
+                 "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
         m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
         assert m and int(m.group(1)) == getattr(chx, name), name
 
