@@ -393,7 +393,9 @@ def batch1d_run(chx, torch):
     coarsening statistics (2^20 systems of N = 256 on (0, 2 pi), gamma = 0.01,
     dt = 0.1 dx, U[-0.1, 0.1], Ch.6-7) and Crank-Nicolson hyperdiffusion
     (65536 systems of N = 1024, dt = 1e-12, the Ch.4 scheme); FP64, 100 steps;
-    algorithmic traffic 34 B per unknown per step."""
+    algorithmic traffic 18 B per unknown per step (sweep: read the state,
+    write the chunk interior and 4 parts per 32 unknowns; separators: 1.5 B),
+    the correction deferred into the next sweep."""
     from paper_2101_06550_amd import inputs
     out = {}
     for name, kind, n, batch, L, dt, a in (
@@ -411,7 +413,7 @@ def batch1d_run(chx, torch):
         el = time.perf_counter() - t0
         out[name] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
                      "system_steps_per_s": batch * k / el,
-                     "algorithmic_GBps": round(34.0 * n * batch * k / el / 1e9, 1),
+                     "algorithmic_GBps": round(18.0 * n * batch * k / el / 1e9, 1),
                      "finite": bool(torch.isfinite(x).all())}
         del x, b
     return out

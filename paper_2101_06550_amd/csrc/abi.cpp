@@ -503,10 +503,10 @@ int batch1d_destroy(chx_batch1d b) {
 
 size_t batch1d_ws_bytes(chx_batch1d b, int batch) {
   if (!b || batch <= 0) return 0;
-  size_t ws = align256((size_t)b->n * batch * sizeof(double));
-  if (b->plan->has_chunk)
-    ws += align256((size_t)b->plan->chunk.S * 2 * b->plan->P * (size_t)batch * sizeof(double));
-  return ws;
+  const size_t field = align256((size_t)b->n * batch * sizeof(double));
+  if (!b->plan->has_chunk) return field;
+  return 2 * field +
+         align256((size_t)b->plan->chunk.S * 2 * b->plan->P * (size_t)batch * sizeof(double));
 }
 
 int batch1d_step(chx_batch1d b, int batch, double* x, long ld, int nsteps, void* ws,
@@ -517,13 +517,14 @@ int batch1d_step(chx_batch1d b, int batch, double* x, long ld, int nsteps, void*
   if (!ws || ws_bytes < batch1d_ws_bytes(b, batch)) return CHX_ENOMEM;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
   auto* base = static_cast<unsigned char*>(ws);
-  double* y = reinterpret_cast<double*>(base);
-  double* rho = reinterpret_cast<double*>(base + align256((size_t)b->n * batch * sizeof(double)));
-  hipStream_t st = static_cast<hipStream_t>(s);
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < nsteps && e == hipSuccess; ++k)
-    e = launch_batch1d_step(b->kind, b->plan->has_chunk, b->plan->dchunk, b->plan->dwhole, x, ld,
-                            batch, b->n, b->s, b->al, y, rho, st);
+  const size_t field = align256((size_t)b->n * batch * sizeof(double));
+  double* y0 = reinterpret_cast<double*>(base);
+  double* y1 = reinterpret_cast<double*>(base + field);
+  double* rho = reinterpret_cast<double*>(base + 2 * field);
+  const hipError_t e =
+      launch_batch1d_steps(b->kind, b->plan->has_chunk, b->plan->dchunk, b->plan->dwhole, x, ld,
+                           batch, b->n, b->s, b->al, nsteps, y0, y1, rho,
+                           static_cast<hipStream_t>(s));
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 

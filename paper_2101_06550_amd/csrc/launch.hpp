@@ -42,14 +42,17 @@ hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* 
                                    long dnparts, double dscale, double* dout, hipStream_t st);
 hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
 
-// One step of a batched 1D periodic scheme (kind 0 Crank-Nicolson
+// nsteps steps of a batched 1D periodic scheme (kind 0 Crank-Nicolson
 // hyperdiffusion, 1 Crank-Nicolson diffusion, 2 1D Cahn-Hilliard) on the
-// interleaved x (unknown i of system b at i ld + b): chunked (right-hand side
-// fused into the chunk sweep; y, rho of the chunked solve) or, for other
-// lengths, right-hand side into y (pitch batch), whole sweeps, copy back.
-hipError_t launch_batch1d_step(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
-                               double* x, long ld, int batch, int n, double s, double al,
-                               double* y, double* rho, hipStream_t st);
+// interleaved x (unknown i of system b at i ld + b).  Chunked lengths: the
+// right-hand side is fused into the chunk sweep, the steps ping-pong between
+// y0 and y1 (pitch batch) with the chunk correction deferred into the next
+// sweep, and x is written once at the end; rho holds the separator parts.
+// Other lengths: right-hand side into y0, whole sweeps, copy back, per step.
+hipError_t launch_batch1d_steps(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
+                                double* x, long ld, int batch, int n, double s, double al,
+                                int nsteps, double* y0, double* y1, double* rho,
+                                hipStream_t st);
 
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,

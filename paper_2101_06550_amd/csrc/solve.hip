@@ -584,7 +584,20 @@ __device__ __forceinline__ double b1d_rhs(const double* X, int q, double s, doub
   return X[q] + al * (ml - 2.0 * mc + mr);
 }
 
-template <int KIND, int P, int M>
+// RECON: src is the previous step's half-solved buffer (chunk interiors
+// uncorrected, separator rows final) and each value is corrected as it is
+// loaded, x = y - Zl s_prev - Zr s_own, so no separate correction pass runs
+// between steps.
+template <int P, int M>
+__device__ __forceinline__ double b1d_recon(double v, int p, const double* __restrict__ rec,
+                                            const double (&sp)[2], const double (&so)[2]) {
+  if (p >= M - P) return v;
+#pragma unroll
+  for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
+  return v;
+}
+
+template <int KIND, int P, int M, bool RECON>
 __global__ __launch_bounds__(256) void batch1d_sweep(const double* __restrict__ x, long ld,
                                                      double* __restrict__ y, long ldy, int batch,
                                                      int n, int S, const double* __restrict__ rec,
@@ -594,13 +607,32 @@ __global__ __launch_bounds__(256) void batch1d_sweep(const double* __restrict__ 
   const long sys = (long)blockIdx.x * 64 + lane;
   const int k = blockIdx.y * 4 + wave;
   if (sys >= batch || k >= S) return;
+  constexpr int MI = M - P;
+  double sm[2] = {0, 0}, sk[2] = {0, 0}, skp[2] = {0, 0};  // separators of chunks k-1, k, k+1
+  if (RECON) {
+    const int km = (k == 0) ? S - 1 : k - 1, kp = (k + 1 == S) ? 0 : k + 1;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      sm[a] = x[((long)km * M + MI + a) * ld + sys];
+      sk[a] = x[((long)k * M + MI + a) * ld + sys];
+      skp[a] = x[((long)kp * M + MI + a) * ld + sys];
+    }
+  }
   double X[M + 4];
 #pragma unroll
   for (int q = 0; q < M + 4; ++q) {
     int row = k * M - 2 + q;
     row += (row < 0) ? n : 0;
     row -= (row >= n) ? n : 0;
-    X[q] = x[(long)row * ld + sys];
+    double v = x[(long)row * ld + sys];
+    if (RECON) {
+      // q = 0, 1: the last two rows of chunk k-1 (separators for P = 2; for
+      // P = 1 the first of them is never used); q = 2 .. M+1: chunk k;
+      // q = M+2, M+3: rows 0, 1 of chunk k+1
+      if (q >= 2 && q < M + 2) v = b1d_recon<P, M>(v, q - 2, rec, sm, sk);
+      else if (q >= M + 2) v = b1d_recon<P, M>(v, q - M - 2, rec, sk, skp);
+    }
+    X[q] = v;
   }
   double f[M];
 #pragma unroll
@@ -637,46 +669,66 @@ __global__ __launch_bounds__(256) void batch1d_rhs(const double* __restrict__ x,
   y[(long)i * ldy + sys] = b1d_rhs<KIND>(X, 2, s, al);
 }
 
-hipError_t launch_batch1d_step(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
-                               double* x, long ld, int batch, int n, double s, double al,
-                               double* y, double* rho, hipStream_t st) {
+hipError_t launch_batch1d_steps(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
+                                double* x, long ld, int batch, int n, double s, double al,
+                                int nsteps, double* y0, double* y1, double* rho, hipStream_t st) {
   const int P = kind == 1 ? 1 : 2;
+  hipError_t e = hipSuccess;
   if (chunked) {
+    // step j sweeps buf[j & 1] from x (j = 0) or from buf[(j-1) & 1] with
+    // the deferred correction; the last buffer is corrected into x at the end
     dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
     const BandT<double> bd = band_of<double>(c.coef);
-#define CHX_B1D(K_, P_)                                                                          \
-  hipLaunchKernelGGL((batch1d_sweep<K_, P_, kChunk>), grid, dim3(256), 0, st, x, ld, y,          \
+    double* buf[2] = {y0, y1};
+    for (int j = 0; j < nsteps && e == hipSuccess; ++j) {
+      const double* src = j == 0 ? x : buf[(j - 1) & 1];
+      const long lsrc = j == 0 ? ld : (long)batch;
+      double* dst = buf[j & 1];
+#define CHX_B1D(K_, P_, R_)                                                                      \
+  hipLaunchKernelGGL((batch1d_sweep<K_, P_, kChunk, R_>), grid, dim3(256), 0, st, src, lsrc, dst, \
                      (long)batch, batch, n, c.S, c.rec, bd, rho, s, al)
-    if (kind == 0) CHX_B1D(0, 2);
-    else if (kind == 1) CHX_B1D(1, 1);
-    else CHX_B1D(2, 2);
+      if (j == 0) {
+        if (kind == 0) CHX_B1D(0, 2, false);
+        else if (kind == 1) CHX_B1D(1, 1, false);
+        else CHX_B1D(2, 2, false);
+      } else {
+        if (kind == 0) CHX_B1D(0, 2, true);
+        else if (kind == 1) CHX_B1D(1, 1, true);
+        else CHX_B1D(2, 2, true);
+      }
 #undef CHX_B1D
-    hipError_t e = hipGetLastError();
+      e = hipGetLastError();
+      if (e == hipSuccess)
+        e = P == 2 ? launch_reduced_il<2>(c, rho, batch, dst, batch, kChunk, kChunk - 2, st)
+                   : launch_reduced_il<1>(c, rho, batch, dst, batch, kChunk, kChunk - 1, st);
+    }
     if (e != hipSuccess) return e;
-    e = P == 2 ? launch_reduced_il<2>(c, rho, batch, y, batch, kChunk, kChunk - 2, st)
-               : launch_reduced_il<1>(c, rho, batch, y, batch, kChunk, kChunk - 1, st);
-    if (e != hipSuccess) return e;
+    const double* last = buf[(nsteps - 1) & 1];
     if (P == 2)
-      hipLaunchKernelGGL((correct_il<2, kChunk, double, double, false>), grid, dim3(256), 0, st, y,
-                         (long)batch, x, ld, batch, c.S, c.rec);
+      hipLaunchKernelGGL((correct_il<2, kChunk, double, double, false>), grid, dim3(256), 0, st,
+                         last, (long)batch, x, ld, batch, c.S, c.rec);
     else
-      hipLaunchKernelGGL((correct_il<1, kChunk, double, double, false>), grid, dim3(256), 0, st, y,
-                         (long)batch, x, ld, batch, c.S, c.rec);
+      hipLaunchKernelGGL((correct_il<1, kChunk, double, double, false>), grid, dim3(256), 0, st,
+                         last, (long)batch, x, ld, batch, c.S, c.rec);
     return hipGetLastError();
   }
   dim3 grid((batch + 255) / 256, n);
-  if (kind == 0)
-    hipLaunchKernelGGL(batch1d_rhs<0>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
-  else if (kind == 1)
-    hipLaunchKernelGGL(batch1d_rhs<1>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
-  else
-    hipLaunchKernelGGL(batch1d_rhs<2>, grid, dim3(256), 0, st, x, ld, y, (long)batch, batch, n, s, al);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = P == 2 ? launch_whole<2>(w, y, 1, batch, batch, st) : launch_whole<1>(w, y, 1, batch, batch, st);
-  if (e != hipSuccess) return e;
-  return hipMemcpy2DAsync(x, ld * sizeof(double), y, (size_t)batch * sizeof(double),
-                          (size_t)batch * sizeof(double), n, hipMemcpyDeviceToDevice, st);
+  for (int j = 0; j < nsteps && e == hipSuccess; ++j) {
+    if (kind == 0)
+      hipLaunchKernelGGL(batch1d_rhs<0>, grid, dim3(256), 0, st, x, ld, y0, (long)batch, batch, n, s, al);
+    else if (kind == 1)
+      hipLaunchKernelGGL(batch1d_rhs<1>, grid, dim3(256), 0, st, x, ld, y0, (long)batch, batch, n, s, al);
+    else
+      hipLaunchKernelGGL(batch1d_rhs<2>, grid, dim3(256), 0, st, x, ld, y0, (long)batch, batch, n, s, al);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = P == 2 ? launch_whole<2>(w, y0, 1, batch, batch, st)
+                 : launch_whole<1>(w, y0, 1, batch, batch, st);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(x, ld * sizeof(double), y0, (size_t)batch * sizeof(double),
+                           (size_t)batch * sizeof(double), n, hipMemcpyDeviceToDevice, st);
+  }
+  return e;
 }
 
 // ---------------------------------------------------------------------------
