@@ -723,6 +723,10 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     h->part_count = std::max(ch_column_pass_blocks(q.nx, h->py->chunk.S), diag_parts);
   } else {
     h->off_r = off; off += field;
+    if (q.scheme == CHX_SCHEME_P2) {  // a second right-hand side, a third state
+      h->off_b0 = off; off += field;
+      h->off_b1 = off; off += field;
+    }
     if (q.scheme == CHX_SCHEME_P2 && h->py->has_chunk) {  // column solve partials
       h->off_rho = off;
       off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(double));
@@ -986,24 +990,54 @@ int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, doub
   }
   hipStream_t st = static_cast<hipStream_t>(s);
   auto* base = static_cast<unsigned char*>(ws);
-  double* r = reinterpret_cast<double*>(base + h->off_r);
+  double* rbuf[2] = {reinterpret_cast<double*>(base + h->off_r),
+                     reinterpret_cast<double*>(base + h->off_b0)};
+  double* w = reinterpret_cast<double*>(base + h->off_b1);
   double* rho = reinterpret_cast<double*>(base + h->off_rho);
   double* part = reinterpret_cast<double*>(base + h->off_part);
   const bool col_chunk = h->py->has_chunk;
   const bool row_lds = h->px->has_chunk && h->px->chunk.S <= 256;
   hipError_t e = hipSuccess;
-  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-    if (diag_out) e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
-    if (e == hipSuccess) e = launch_ch2_rhs(c, cprev, ld, r, nx, nx, ny, h->K2, st);
-    // v = L_y^{-1} L_x^{-1} r: columns (interleaved), then rows (the two commute)
-    if (e == hipSuccess)
-      e = col_chunk ? launch_chunked_il<2>(h->py->dchunk, r, nx, nx, rho, st)
-                    : launch_whole<2>(h->py->dwhole, r, 1, nx, nx, st);
-    if (e == hipSuccess)
-      e = row_lds ? launch_rows_lds<2>(h->px->dchunk, r, nx, ny, st)
-                  : launch_whole<2>(h->px->dwhole, r, nx, 1, ny, st);
-    if (e == hipSuccess) e = launch_ch2_update(c, cprev, ld, r, nx, nx, ny, st);
+  // v = L_y^{-1} L_x^{-1} r in place: columns (interleaved), then rows
+  // (chunked columns: the chunk correction is left to whoever reads r next)
+  const DevChunk* recon = col_chunk ? &h->py->dchunk : nullptr;
+  auto solve_in_place = [&](double* r) {
+    hipError_t e2 = col_chunk ? launch_chunked_il<2>(h->py->dchunk, r, nx, nx, rho, st, false)
+                              : launch_whole<2>(h->py->dwhole, r, 1, nx, nx, st);
+    if (e2 == hipSuccess)
+      e2 = row_lds ? launch_rows_lds<2>(h->px->dchunk, r, nx, ny, st)
+                   : launch_whole<2>(h->px->dwhole, r, nx, 1, ny, st);
+    return e2;
+  };
+  // The states rotate through c, cprev and w: each later step advances the
+  // state inside the right-hand-side kernel (C_new = 2C - Cp + v, written to
+  // the buffer holding neither input) and the last update lands in c, cprev.
+  struct Buf {
+    double* p;
+    long ld;
+  };
+  Buf cur{c, ld}, prev{cprev, ld}, spare{w, nx};
+  if (diag_out) e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out, st);
+  if (e == hipSuccess)
+    e = launch_ch2_rhs(c, ld, cprev, ld, nullptr, 0, nullptr, 0, rbuf[0], nx, nx, ny, h->K2,
+                       nullptr, st);
+  if (e == hipSuccess) e = solve_in_place(rbuf[0]);
+  for (int n = 1; n < nsteps && e == hipSuccess; ++n) {
+    double* rv = rbuf[(n - 1) & 1];
+    double* rn = rbuf[n & 1];
+    e = launch_ch2_rhs(cur.p, cur.ld, prev.p, prev.ld, rv, nx, spare.p, spare.ld, rn, nx, nx, ny,
+                       h->K2, recon, st);
+    if (e == hipSuccess && diag_out)
+      e = launch_ch_diag(spare.p, spare.ld, nx, ny, h->K, part, diag_out + 2 * n, st);
+    const Buf old_prev = prev;
+    prev = cur;
+    cur = spare;
+    spare = old_prev;
+    if (e == hipSuccess) e = solve_in_place(rn);
   }
+  if (e == hipSuccess)
+    e = launch_ch2_update(cur.p, cur.ld, prev.p, prev.ld, rbuf[(nsteps - 1) & 1], nx, c, cprev,
+                          ld, nx, ny, recon, st);
   if (e == hipSuccess && diag_out)
     e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
   return e == hipSuccess ? CHX_OK : CHX_EHIP;

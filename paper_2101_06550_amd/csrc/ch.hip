@@ -479,10 +479,34 @@ hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, in
 constexpr int kT2X = 64, kT2Y = 16, kT2H = 2;
 constexpr int kT2W = kT2X + 2 * kT2H, kT2R = kT2Y + 2 * kT2H;
 
-__global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c,
-                                               const double* __restrict__ cp, long ld,
+// UPD: the state is first advanced from the previous step's solution,
+// C_new = 2 C - Cp + v, at every staged point (C_new of the tile's own points
+// is written to cnew), and the right-hand side is formed from (C_new, C).
+// RECON: v is the solution with the column-chunk correction still to apply
+// (chunk interiors uncorrected, separator rows final), corrected here as it
+// is loaded: v = V - Zl T_prev - Zr T_own.
+__device__ __forceinline__ double ch2_recon(const double* __restrict__ v, long ldv, int j, int i,
+                                            int Sc, const double* __restrict__ rec) {
+  const int kc = j / M, p = j - kc * M;
+  double x = v[(long)j * ldv + i];
+  if (p >= MI) return x;
+  const int kp = (kc == 0) ? Sc - 1 : kc - 1;
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    const double tp = v[((long)kp * M + MI + a) * ldv + i];
+    const double to = v[((long)kc * M + MI + a) * ldv + i];
+    x = x - rec[p * 8 + 4 + a] * tp - rec[p * 8 + 6 + a] * to;
+  }
+  return x;
+}
+
+template <bool UPD, bool RECON>
+__global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c, long ld,
+                                               const double* __restrict__ cp, long ldp,
+                                               const double* __restrict__ v, long ldv,
+                                               double* __restrict__ cnew, long ldn,
                                                double* __restrict__ r, long ldr, int nx, int ny,
-                                               Ch2Coef K) {
+                                               Ch2Coef K, int Sc, const double* __restrict__ rec) {
   __shared__ double cb[kT2R][kT2W];
   __shared__ double mu[kT2R][kT2W];
   __shared__ double df[kT2R][kT2W];
@@ -492,7 +516,17 @@ __global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c,
     int j = j0 - kT2H + tr, i = i0 - kT2H + tc;
     j = (j % ny + ny) % ny;
     i = (i % nx + nx) % nx;
-    const double vc = c[(long)j * ld + i], vp = cp[(long)j * ld + i];
+    double vc = c[(long)j * ld + i], vp = cp[(long)j * ldp + i];
+    if (UPD) {
+      const double vv = RECON ? ch2_recon(v, ldv, j, i, Sc, rec) : v[(long)j * ldv + i];
+      const double vn = (2.0 * vc - vp) + vv;
+      vp = vc;
+      vc = vn;
+      const int jj = j0 - kT2H + tr, ii = i0 - kT2H + tc;
+      if (tr >= kT2H && tr < kT2H + kT2Y && tc >= kT2H && tc < kT2H + kT2X && jj < ny &&
+          ii < nx)
+        cnew[(long)jj * ldn + ii] = vn;
+    }
     cb[tr][tc] = 2.0 * vc - vp;
     mu[tr][tc] = vc * vc * vc - vc;
     df[tr][tc] = vc - vp;
@@ -522,30 +556,52 @@ __global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c,
   }
 }
 
-// Cp <- C, C <- (2C - Cp) + v, elementwise.
-__global__ __launch_bounds__(256) void ch2_update(double* __restrict__ c, double* __restrict__ cp,
-                                                  long ld, const double* __restrict__ v, long ldv,
-                                                  int nx, int ny) {
+// out_prev <- C, out <- (2C - Cp) + v, elementwise: every thread reads its
+// element of all inputs before writing it, so the outputs may alias them.
+template <bool RECON>
+__global__ __launch_bounds__(256) void ch2_update(const double* c, long ldc, const double* cp,
+                                                  long ldp, const double* __restrict__ v, long ldv,
+                                                  double* out, double* out_prev, long ld, int nx,
+                                                  int ny, int Sc, const double* __restrict__ rec) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= nx || j >= ny) return;
-  const long k = (long)j * ld + i;
-  const double vc = c[k], vp = cp[k];
-  cp[k] = vc;
-  c[k] = (2.0 * vc - vp) + v[(long)j * ldv + i];
+  const double vc = c[(long)j * ldc + i], vp = cp[(long)j * ldp + i];
+  const double vv = RECON ? ch2_recon(v, ldv, j, i, Sc, rec) : v[(long)j * ldv + i];
+  out_prev[(long)j * ld + i] = vc;
+  out[(long)j * ld + i] = (2.0 * vc - vp) + vv;
 }
 
-hipError_t launch_ch2_rhs(const double* c, const double* cp, long ld, double* r, long ldr, int nx,
-                          int ny, const Ch2Coef& K, hipStream_t st) {
+hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, const double* v,
+                          long ldv, double* cnew, long ldn, double* r, long ldr, int nx, int ny,
+                          const Ch2Coef& K, const DevChunk* recon, hipStream_t st) {
   dim3 grid((nx + kT2X - 1) / kT2X, (ny + kT2Y - 1) / kT2Y);
-  hipLaunchKernelGGL(ch2_rhs, grid, dim3(256), 0, st, c, cp, ld, r, ldr, nx, ny, K);
+  const int Sc = recon ? recon->S : 0;
+  const double* rec = recon ? recon->rec : nullptr;
+  if (v && recon)
+    hipLaunchKernelGGL((ch2_rhs<true, true>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
+  else if (v)
+    hipLaunchKernelGGL((ch2_rhs<true, false>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
+  else
+    hipLaunchKernelGGL((ch2_rhs<false, false>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
   return hipGetLastError();
 }
 
-hipError_t launch_ch2_update(double* c, double* cp, long ld, const double* v, long ldv, int nx,
-                             int ny, hipStream_t st) {
+hipError_t launch_ch2_update(const double* c, long ldc, const double* cp, long ldp,
+                             const double* v, long ldv, double* out, double* out_prev, long ld,
+                             int nx, int ny, const DevChunk* recon, hipStream_t st) {
   dim3 grid((nx + 63) / 64, (ny + 3) / 4);
-  hipLaunchKernelGGL(ch2_update, grid, dim3(256), 0, st, c, cp, ld, v, ldv, nx, ny);
+  const int Sc = recon ? recon->S : 0;
+  const double* rec = recon ? recon->rec : nullptr;
+  if (recon)
+    hipLaunchKernelGGL(ch2_update<true>, grid, dim3(256), 0, st, c, ldc, cp, ldp, v, ldv, out,
+                       out_prev, ld, nx, ny, Sc, rec);
+  else
+    hipLaunchKernelGGL(ch2_update<false>, grid, dim3(256), 0, st, c, ldc, cp, ldp, v, ldv, out,
+                       out_prev, ld, nx, ny, Sc, rec);
   return hipGetLastError();
 }
 

@@ -21,10 +21,18 @@ struct Ch2Coef {
   double a, b;                   // 2/3 D gamma dt, 2/3 D dt
   double inv_dx4, inv_dy4, inv_dx2dy2, inv_dx2, inv_dy2;
 };
-hipError_t launch_ch2_rhs(const double* c, const double* cp, long ld, double* r, long ldr, int nx,
-                          int ny, const Ch2Coef& K, hipStream_t st);
-hipError_t launch_ch2_update(double* c, double* cp, long ld, const double* v, long ldv, int nx,
-                             int ny, hipStream_t st);
+// Right-hand side r of the delta-form step from (C, Cp) (v == nullptr), or,
+// with v, from (C_new, C) where C_new = 2C - Cp + v is also written to cnew
+// (which must not alias c, cp, v or r).  recon != nullptr: v still needs the
+// column-chunk correction of that plan (applied as v is read).
+hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, const double* v,
+                          long ldv, double* cnew, long ldn, double* r, long ldr, int nx, int ny,
+                          const Ch2Coef& K, const DevChunk* recon, hipStream_t st);
+// out = 2C - Cp + v, out_prev = C, elementwise (outputs may alias inputs);
+// recon as above.
+hipError_t launch_ch2_update(const double* c, long ldc, const double* cp, long ldp,
+                             const double* v, long ldv, double* out, double* out_prev, long ld,
+                             int nx, int ny, const DevChunk* recon, hipStream_t st);
 
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,

@@ -57,9 +57,11 @@ hipError_t launch_batch1d_steps(int kind, bool chunked, const DevChunk& c, const
 template <int P>
 hipError_t launch_whole(const DevWhole& w, double* x, long ss, long es, int batch,
                         hipStream_t st);
+// correct = false leaves the chunk interiors uncorrected (separator rows
+// final): the caller applies x = y - Zl s_prev - Zr s_own later.
 template <int P>
 hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
-                             hipStream_t st);
+                             hipStream_t st, bool correct = true);
 template <int P>
 hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, double* dst, long ld,
                              int drow_stride, int drow_off, hipStream_t st,

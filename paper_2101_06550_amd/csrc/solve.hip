@@ -985,13 +985,13 @@ hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, do
 
 template <int P>
 hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
-                             hipStream_t st) {
+                             hipStream_t st, bool correct) {
   dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
   hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double, double>), grid, dim3(256), 0, st, x, ld, x,
                      ld, batch, c.S, c.rec, band_of<double>(c.coef), rho);
   hipError_t e = launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0,
                                       0.0, nullptr);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !correct) return e;
   hipLaunchKernelGGL((correct_il<P, kChunk, double, double, false>), grid, dim3(256), 0, st, x, ld,
                      x, ld, batch, c.S, c.rec);
   return hipGetLastError();
@@ -1059,7 +1059,7 @@ hipError_t launch_resid_lines(const double* coef, int periodic, int n, const dou
   template hipError_t launch_whole32<P>(const DevWhole&, double*, long, long, double*, long,    \
                                         long, int, bool, hipStream_t);                           \
   template hipError_t launch_chunked_il<P>(const DevChunk&, double*, long, int, double*,        \
-                                           hipStream_t);                                         \
+                                           hipStream_t, bool);                                   \
   template hipError_t launch_chunked_il32<P>(const DevChunk&, const double*, long, float*,      \
                                              float*, double*, long, int, bool, hipStream_t);     \
   template hipError_t launch_reduced_il<P>(const DevChunk&, const double*, int, double*, long,  \
