@@ -67,6 +67,15 @@ def load(path: str | None = None):
     lib.orc_ch_rhs.argtypes = [_P, _P, _I, _I, _D, _D, _D, _D, _D]
     lib.orc_ch_step.restype = _I
     lib.orc_ch_step.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D]
+    _U64 = ctypes.c_uint64
+    lib.orc_sm_uniform.restype = _D
+    lib.orc_sm_uniform.argtypes = [_U64, _U64]
+    lib.orc_cook_rho.restype = None
+    lib.orc_cook_rho.argtypes = [_P, _P, _I, _I, _U64, _U64]
+    lib.orc_cook_increment.restype = None
+    lib.orc_cook_increment.argtypes = [_P, _I, _I, _D, _D, _D, _D, _U64, _U64]
+    lib.orc_ch_step_cook.restype = _I
+    lib.orc_ch_step_cook.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D, _D, _U64, _U64]
     lib.orc_batch1d_step.restype = _I
     lib.orc_batch1d_step.argtypes = [_I, _P, _I, _I, _D, _D, _D, _D]
     lib.orc_ch2_rhs.restype = None
@@ -219,6 +228,31 @@ class Oracle:
             if rc:
                 raise ValueError(f"batch1d step failed ({rc})")
         return x
+
+    # Ch.7 Cahn-Hilliard-Cook forcing
+    def sm_uniform(self, seed, k):
+        return self.lib.orc_sm_uniform(seed, k)
+
+    def cook_rho(self, nx, ny, seed, step):
+        rx, ry = np.zeros((ny, nx)), np.zeros((ny, nx))
+        self.lib.orc_cook_rho(_ptr(rx), _ptr(ry), nx, ny, seed, step)
+        return rx, ry
+
+    def cook_increment(self, nx, ny, lx, ly, dt, sigma, seed, step):
+        out = np.zeros((ny, nx))
+        self.lib.orc_cook_increment(_ptr(out), nx, ny, lx, ly, dt, sigma, seed, step)
+        return out
+
+    def ch_step_cook(self, c2d, lx, ly, D, gamma, dt, sigma, seed, step0=0, nsteps=1):
+        """nsteps Cook steps; step k of the call draws with counter step0 + k."""
+        c = _f64(c2d).copy()
+        ny, nx = c.shape
+        for k in range(nsteps):
+            rc = self.lib.orc_ch_step_cook(_ptr(c), nx, ny, lx, ly, D, gamma, dt, sigma, seed,
+                                           step0 + k)
+            if rc:
+                raise ValueError(f"cook step failed ({rc})")
+        return c
 
     def ch_mass(self, c2d, lx, ly):
         c = _f64(c2d)

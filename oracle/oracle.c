@@ -10,6 +10,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -542,6 +543,85 @@ int orc_batch1d_step(int kind, double* x, int n, int batch, double L,
   }
   free(f);
   free(y);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ch.7, the Cahn-Hilliard-Cook equation: C_t = D Lap(C^3 - C - gamma Lap C)
+ * + eta, eta_ij = sqrt(sigma / (dx dy dt)) div rho_ij, rho a 2-vector of
+ * N(0,1) numbers per point and step, drawn from two uniforms by the
+ * Box-Muller transformation.  Readings: div by forward differences (periodic,
+ * so sum(eta) = 0 and the mass is conserved); eta enters the explicit
+ * right-hand side as dt * eta.  The uniforms come from a counter-based
+ * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k of the sequence
+ * whose state starts at mix(seed), u = ((out >> 11) + 1/2) 2^-53 in (0, 1),
+ * counter k = ((step * ny + j) * nx + i) * 2 + component. */
+static uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+double orc_sm_uniform(uint64_t seed, uint64_t k) {
+  const uint64_t st = sm_mix(seed) + (k + 1) * 0x9E3779B97F4A7C15ULL;
+  return ((double)(sm_mix(st) >> 11) + 0.5) * 0x1.0p-53;
+}
+
+void orc_cook_rho(double* rx, double* ry, int nx, int ny, uint64_t seed,
+                  uint64_t step) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const uint64_t k = ((step * (uint64_t)ny + (uint64_t)j) * (uint64_t)nx +
+                          (uint64_t)i) * 2;
+      const double u1 = orc_sm_uniform(seed, k), u2 = orc_sm_uniform(seed, k + 1);
+      const double rad = sqrt(-2.0 * log(u1));
+      rx[(size_t)j * nx + i] = rad * cos(two_pi * u2);
+      ry[(size_t)j * nx + i] = rad * sin(two_pi * u2);
+    }
+  }
+}
+
+void orc_cook_increment(double* out, int nx, int ny, double lx, double ly,
+                        double dt, double sigma, uint64_t seed, uint64_t step) {
+  const double dx = lx / nx, dy = ly / ny;
+  double* rx = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+  double* ry = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+  orc_cook_rho(rx, ry, nx, ny, seed, step);
+  const double amp = sqrt(sigma / (dx * dy * dt));
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const size_t k = (size_t)j * nx + i;
+      const double div = (rx[(size_t)j * nx + wrap(i + 1, nx)] - rx[k]) / dx +
+                         (ry[(size_t)wrap(j + 1, ny) * nx + i] - ry[k]) / dy;
+      out[k] = dt * amp * div;
+    }
+  }
+  free(rx);
+  free(ry);
+}
+
+int orc_ch_step_cook(double* c, int nx, int ny, double lx, double ly, double D,
+                     double gamma, double dt, double sigma, uint64_t seed,
+                     uint64_t step) {
+  if (nx < 5 || ny < 5) return -1;
+  const double dx = lx / nx, dy = ly / ny;
+  const double sx = D * gamma * dt / (dx * dx * dx * dx);
+  const double sy = D * gamma * dt / (dy * dy * dy * dy);
+  const size_t n = (size_t)nx * ny;
+  double* r = (double*)malloc(sizeof(double) * n);
+  double* q = (double*)malloc(sizeof(double) * n);
+  orc_ch_rhs(c, r, nx, ny, lx, ly, D, gamma, dt);
+  orc_cook_increment(q, nx, ny, lx, ly, dt, sigma, seed, step);
+  for (size_t k = 0; k < n; ++k) r[k] = r[k] + q[k];
+  int rc = orc_cpenta_lines(nx, ny, 0, sx, -4.0 * sx, 1.0 + 6.0 * sx,
+                            -4.0 * sx, sx, r);
+  if (rc == 0)
+    rc = orc_cpenta_lines(nx, ny, 1, sy, -4.0 * sy, 1.0 + 6.0 * sy, -4.0 * sy,
+                          sy, r);
+  if (rc == 0) memcpy(c, r, sizeof(double) * n);
+  free(r);
+  free(q);
   return rc;
 }
 

@@ -26,6 +26,8 @@
 #ifndef CH_ORACLE_H
 #define CH_ORACLE_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -138,6 +140,19 @@ int orc_ch2_step(double* c, double* cprev, int nx, int ny, double lx,
  * Cahn-Hilliard with gamma = a and mobility D (Ch.6 eq. 6:1Dnumerical). */
 int orc_batch1d_step(int kind, double* x, int n, int batch, double L,
                      double dt, double a, double D);
+/* Ch.7 Cahn-Hilliard-Cook forcing: counter-based SplitMix64 uniform in
+ * (0, 1), the Box-Muller N(0,1) vector field rho of one step, the increment
+ * dt * eta (eta = sqrt(sigma/(dx dy dt)) div rho, forward differences), and
+ * one step of the first-order ADI scheme with dt * eta added to its
+ * right-hand side. */
+double orc_sm_uniform(uint64_t seed, uint64_t k);
+void orc_cook_rho(double* rx, double* ry, int nx, int ny, uint64_t seed,
+                  uint64_t step);
+void orc_cook_increment(double* out, int nx, int ny, double lx, double ly,
+                        double dt, double sigma, uint64_t seed, uint64_t step);
+int orc_ch_step_cook(double* c, int nx, int ny, double lx, double ly, double D,
+                     double gamma, double dt, double sigma, uint64_t seed,
+                     uint64_t step);
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly);
 double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
                      double gamma);

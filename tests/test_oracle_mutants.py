@@ -140,8 +140,30 @@ def pin_batch1d_modes(o):
     return True
 
 
+def pin_cook(o):
+    """The Cook forcing: generator stream, conservation, divergence variance
+    and the forced step as the unforced step plus the solved increment."""
+    got = np.array([o.sm_uniform(5, k) for k in range(256)])
+    if not np.array_equal(got, (inputs.uniform01(5, 256) * 2.0 ** 53 + 0.5) * 2.0 ** -53):
+        return False
+    nx, ny, dt, sigma = 128, 96, 1e-4, 1e-10
+    dx, dy = L / nx, L / ny
+    q = o.cook_increment(nx, ny, L, L, dt, sigma, 11, 0)
+    var = dt * sigma / (dx * dy) * (2 / dx ** 2 + 2 / dy ** 2)
+    if abs(q.sum()) > 1e-12 * np.abs(q).sum() or abs(q.var() / var - 1.0) > 0.05:
+        return False
+    n, g = 32, 0.01
+    c = inputs.noise_field(n, n, 12)
+    q = o.cook_increment(n, n, L, L, dt, 1e-12, 3, 7)
+    k2 = _kappa2(n)
+    vq = np.real(np.fft.ifft2(np.fft.fft2(q) / ((1 + g * dt * k2[None, :] ** 2) *
+                                                (1 + g * dt * k2[:, None] ** 2))))
+    forced = o.ch_step_cook(c, L, L, 1.0, g, dt, 1e-12, 3, step0=7)
+    return np.max(np.abs(forced - o.ch_step(c, L, L, 1.0, g, dt) - vq)) < 1e-13
+
+
 ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
-            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes]
+            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook]
 
 MUTANTS = {
     "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
@@ -178,6 +200,14 @@ MUTANTS = {
                                       "if (kind == 1) s = a * dt / (dx * dx);"),
     "batch1d_ch_printed_rhs_without_state": ("f[i] = XV(i) + al * (mu_of(XV(i - 1))",
                                              "f[i] = al * (mu_of(XV(i - 1))"),
+    "cook_backward_divergence_x": ("const double div = (rx[(size_t)j * nx + wrap(i + 1, nx)] - rx[k]) / dx +",
+                                   "const double div = (rx[k] - rx[(size_t)j * nx + wrap(i - 1, nx)]) / dx * 0.5 +"),
+    "cook_amplitude_without_dt": ("const double amp = sqrt(sigma / (dx * dy * dt));",
+                                  "const double amp = sqrt(sigma / (dx * dy));"),
+    "cook_uniform_offset": ("return ((double)(sm_mix(st) >> 11) + 0.5) * 0x1.0p-53;",
+                            "return ((double)(sm_mix(st) >> 11) + 1.0) * 0x1.0p-53;"),
+    "cook_box_muller_cos_for_both": ("ry[(size_t)j * nx + i] = rad * sin(two_pi * u2);",
+                                     "ry[(size_t)j * nx + i] = rad * cos(two_pi * u2);"),
     "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
                                    "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
 }
