@@ -419,6 +419,27 @@ def batch1d_run(chx, torch):
     return out
 
 
+def cook_run(chx, torch, n=8192, steps=20):
+    """The large workload with the Cahn-Hilliard-Cook forcing of Ch.7
+    (sigma = 1e-14, the thesis's value): time per step with the per-step
+    Box-Muller draws and the forced column pass, FP64."""
+    from paper_2101_06550_amd import inputs
+    L = 2 * math.pi
+    h = chx.ch_create(n, n, L, L, 1.0, 0.001, 1e-6)
+    chx.ch_set_noise(h, 1e-14, seed=2021)
+    c = torch.tensor(inputs.mode_plus_noise(n, 5), device="cuda")
+    chx.ch_adi_step(h, c, nsteps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chx.ch_adi_step(h, c, nsteps=steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, cnt = chx.ch_adi_step_timed(h, c, nsteps=steps)
+    return {"steps": steps, "ms_per_step": round(1e3 * el / steps, 5),
+            "updates_per_s": n * n * steps / el,
+            "column_phase_incl_draws_avg_ms": round(ms[0] / steps, 5)}
+
+
 def copy_reference(chx, torch, reps=20):
     """The library's plain streaming copy of 1 GiB of FP64 (read 1 GiB, write
     1 GiB): the HBM rate a simple streaming kernel reaches on this part, for
@@ -566,7 +587,7 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2",
-                                       "table31", "batch1d"],
+                                       "table31", "batch1d", "cook"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -610,7 +631,7 @@ def main():
     if args.only:
         fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
               "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
-              "table31": table31_run, "batch1d": batch1d_run,
+              "table31": table31_run, "batch1d": batch1d_run, "cook": cook_run,
               "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
@@ -696,6 +717,8 @@ def main():
         extra["thesis_scheme_p2"] = p2_run(chx, torch)
         log("batched 1D schemes")
         extra["batched_1d"] = batch1d_run(chx, torch)
+        log("Cahn-Hilliard-Cook forcing")
+        extra["cook_forced_8192"] = cook_run(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)

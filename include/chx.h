@@ -283,6 +283,26 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 int ch_get_tuning(chx_ch h, int what, int* value);
 int ch_set_tuning(chx_ch h, int what, int value);
 
+/* Cahn-Hilliard-Cook forcing (Ch.7): C_t = D Lap(C^3 - C - gamma Lap C) + eta,
+ * eta_ij = sqrt(sigma / (dx dy dt)) div rho_ij, rho a 2-vector of N(0,1)
+ * numbers per point and step drawn by Box-Muller from two uniforms of a
+ * counter-based SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k of
+ * the sequence whose state starts at mix(seed), u = ((out >> 11) + 1/2) 2^-53,
+ * k = ((step * ny + j) * nx + i) * 2 + component.  The divergence takes
+ * forward differences (periodic, so the forcing conserves mass); dt * eta is
+ * added to the explicit right-hand side.
+ * ch_set_noise: sigma > 0 turns the forcing on for a P1 FP64 handle of the
+ *   chunked shapes (nx % 64 == 0, ny % 32 == 0; else CHX_EINVAL), sigma = 0
+ *   turns it off; step0 is the counter of the next step.  Every step of
+ *   ch_adi_step advances the counter, so a run split over several calls
+ *   draws the same numbers as one call.  While it is on, ch_ws_bytes grows by
+ *   one field (query it again) and the single-workgroup path is not used.
+ *   Not for graph capture (the counter is a launch argument).
+ * ch_get_noise_step: the counter of the next step. */
+int ch_set_noise(chx_ch h, double sigma, unsigned long long seed,
+                 unsigned long long step0);
+int ch_get_noise_step(chx_ch h, unsigned long long* step);
+
 /* ch_diagnostics: mass = dx dy sum c and discrete free energy
  *   F = dx dy sum[(c^2-1)^2/4 + gamma/2 ((D+x c)^2 + (D+y c)^2)] of the field c
  *   (device), by a fixed-order reduction (bitwise repeatable).  Synchronises

@@ -38,7 +38,7 @@ EXPORTED = [
     "stencil2d_apply",
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
-    "ch_get_tuning", "ch_set_tuning", "ch_diagnostics",
+    "ch_get_tuning", "ch_set_tuning", "ch_set_noise", "ch_get_noise_step", "ch_diagnostics",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
@@ -99,6 +99,8 @@ def load(path: str | None = None):
         "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
         "ch_adi_step_p2": (_I, [_V, _V, _V, _L, _I, _V, _V, _S, _V]),
+        "ch_set_noise": (_I, [_V, _D, ctypes.c_uint64, ctypes.c_uint64]),
+        "ch_get_noise_step": (_I, [_V, ctypes.POINTER(ctypes.c_uint64)]),
         "ch_get_tuning": (_I, [_V, _I, _IP]),
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
@@ -444,6 +446,18 @@ def ch_get_tuning(h: CH, what: int = CHX_TUNE_REDUCED_SHAPE) -> int:
 def ch_set_tuning(h: CH, value: int, what: int = CHX_TUNE_REDUCED_SHAPE):
     """Set kernel choice `what` of the handle to value from now on."""
     _check(load().ch_set_tuning(h.handle, int(what), int(value)), "ch_set_tuning")
+
+
+def ch_set_noise(h: CH, sigma: float, seed: int = 0, step0: int = 0):
+    """Cahn-Hilliard-Cook forcing of intensity sigma (0 turns it off)."""
+    _check(load().ch_set_noise(h.handle, float(sigma), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               int(step0)), "ch_set_noise")
+
+
+def ch_get_noise_step(h: CH) -> int:
+    v = ctypes.c_uint64()
+    _check(load().ch_get_noise_step(h.handle, ctypes.byref(v)), "ch_get_noise_step")
+    return v.value
 
 
 def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):

@@ -263,6 +263,8 @@ struct chx_ch_s {
   bool small_ok = false;  // the single-workgroup LDS-resident path fits
   bool small = false;     // ... and is in use
   int split = -1;         // split row pass shape (-1: plain separators + rows)
+  double sigma = 0.0;     // Cahn-Hilliard-Cook forcing intensity (0: off)
+  unsigned long long noise_seed = 0, noise_step = 0;
   ChCoef K{};
   Ch2Coef K2{};           // the thesis's delta-form scheme (CHX_SCHEME_P2)
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
@@ -789,7 +791,29 @@ int ch_destroy(chx_ch h) {
   return CHX_OK;
 }
 
-size_t ch_ws_bytes(chx_ch h) { return h ? h->ws_total : 0; }
+// The Cook forcing needs one more field (its increment) after the rest.
+static size_t ws_need(const chx_ch_s* h) {
+  return h->ws_total +
+         (h->sigma > 0 ? align256((size_t)h->prm.nx * h->prm.ny * sizeof(double)) : 0);
+}
+
+size_t ch_ws_bytes(chx_ch h) { return h ? ws_need(h) : 0; }
+
+int ch_set_noise(chx_ch h, double sigma, unsigned long long seed, unsigned long long step0) {
+  if (!h || !(sigma >= 0) || !std::isfinite(sigma)) return CHX_EINVAL;
+  if (sigma > 0 && !(h->fast && h->prm.dtype == CHX_F64 && h->prm.scheme == CHX_SCHEME_P1))
+    return CHX_EINVAL;
+  h->sigma = sigma;
+  h->noise_seed = seed;
+  h->noise_step = step0;
+  return CHX_OK;
+}
+
+int ch_get_noise_step(chx_ch h, unsigned long long* step) {
+  if (!h || !step) return CHX_EINVAL;
+  *step = h->noise_step;
+  return CHX_OK;
+}
 
 // Per-phase event timing of ch_adi_step (phase 0 column pass, 1 column
 // separators, 2 row pass, 3 finalize + diagnostics reductions).
@@ -822,10 +846,11 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   if (h->prm.scheme != CHX_SCHEME_P1) return CHX_EINVAL;  // P2 handles: ch_adi_step_p2
   const int nx = h->prm.nx, ny = h->prm.ny;
   if (ld < nx || nsteps < 1) return CHX_EINVAL;
-  if (!ws || ws_bytes < h->ws_total) return CHX_ENOMEM;
+  if (!ws || ws_bytes < ws_need(h)) return CHX_ENOMEM;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
   auto* base = static_cast<unsigned char*>(ws);
   double* part = reinterpret_cast<double*>(base + h->off_part);
+  double* qnoise = h->sigma > 0 ? reinterpret_cast<double*>(base + h->ws_total) : nullptr;
   hipError_t e = hipSuccess;
   auto ok = [&]() { return e == hipSuccess; };
   auto B = [&]() { if (tm) tm->begin(); };
@@ -874,7 +899,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
         }
       }
     }
-  } else if (h->small) {
+  } else if (h->small && !qnoise) {
     // one workgroup, field resident in LDS for all steps; it also writes the
     // diagnostics of every state, the final one included
     B();
@@ -894,10 +919,18 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     for (int n = 0; n < nsteps && ok(); ++n) {
       double* dst = buf[n & 1];
       const bool diag = diag_out != nullptr;
-      B();
-      e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho, h->K,
-                                part, st);
-      E(0);
+      if (qnoise) {  // Cahn-Hilliard-Cook increment of this step
+        B();
+        e = launch_ch_cook_increment(qnoise, nx, ny, h->prm.lx / nx, h->prm.ly / ny, h->prm.dt,
+                                     h->sigma, h->noise_seed, h->noise_step + n, st);
+        E(0);
+      }
+      if (ok()) {
+        B();
+        e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho,
+                                  h->K, part, st, qnoise);
+        E(0);
+      }
       if (ok() && h->split >= 0) {
         // separators fused with the interior rows (phase 2), then the
         // separator rows (phase 1)
@@ -970,6 +1003,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
     E(3);
   }
+  if (ok() && qnoise) h->noise_step += (unsigned long long)nsteps;
   if (tm && tm->failed) return CHX_EHIP;
   return ok() ? CHX_OK : CHX_EHIP;
 }

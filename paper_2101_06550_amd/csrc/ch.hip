@@ -90,14 +90,16 @@ __device__ __forceinline__ double recon_row(double v, int q, const double* __res
 
 // Body shared by the single-field kernel and the ensemble kernel: column
 // block cb (256 columns), chunk kc; slot = where this block's (mass, energy)
-// partial goes (DIAG only).
-template <bool RECON, bool DIAG>
+// partial goes (DIAG only); NOISE adds the forcing increment q (pitch nx) to
+// the right-hand side.
+template <bool RECON, bool DIAG, bool NOISE = false>
 __device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
                                                  double* __restrict__ ybuf, long ldy, int nx,
                                                  int ny, int Sc, const double* __restrict__ rec,
                                                  const BandT<double>& bd, double* __restrict__ rho,
                                                  const ChCoef& K, double* __restrict__ slot,
-                                                 int cb, int kc) {
+                                                 int cb, int kc,
+                                                 const double* __restrict__ q = nullptr) {
   __shared__ double red[8];
   __shared__ double edge[10][M + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -188,6 +190,7 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
       const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
       const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
       double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+      if (NOISE) r = r + q[((long)kc * M + p) * nx + i];
       if (DIAG) {
         const double w = xc_c * xc_c - 1.0;
         const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
@@ -235,16 +238,82 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
   }
 }
 
-template <bool RECON, bool DIAG>
+template <bool RECON, bool DIAG, bool NOISE>
 __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
                                                       double* __restrict__ ybuf, long ldy, int nx,
                                                       int ny, int Sc,
                                                       const double* __restrict__ rec,
                                                       BandT<double> bd, double* __restrict__ rho,
-                                                      ChCoef K, double* __restrict__ part) {
+                                                      ChCoef K, double* __restrict__ part,
+                                                      const double* __restrict__ q) {
   const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
-  column_pass_body<RECON, DIAG>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
-                                DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y);
+  column_pass_body<RECON, DIAG, NOISE>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
+                                       DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y, q);
+}
+
+// ---------------------------------------------------------------------------
+// Cahn-Hilliard-Cook forcing (Ch.7): q = dt eta, eta = amp div rho with
+// amp = sqrt(sigma / (dx dy dt)), rho = (rho_x, rho_y) N(0,1) per point and
+// step by Box-Muller from two counter-based SplitMix64 uniforms (Steele, Lea
+// and Flood 2014; output k of the sequence whose state starts at mix(seed),
+// u = ((out >> 11) + 1/2) 2^-53, k = ((step ny + j) nx + i) 2 + component),
+// forward-difference divergence.  A block draws rho for its 16 x 64 tile and
+// the row and column after it into LDS once, then differences.
+constexpr int kCkX = 64, kCkY = 16;
+
+__host__ __device__ __forceinline__ unsigned long long sm_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void ch_cook_increment(double* __restrict__ q, int nx, int ny,
+                                                         double inv_dx, double inv_dy,
+                                                         double scale,
+                                                         unsigned long long seed_state,
+                                                         unsigned long long step) {
+  __shared__ double rx[kCkY + 1][kCkX + 1];
+  __shared__ double ry[kCkY + 1][kCkX + 1];
+  const int i0 = blockIdx.x * kCkX, j0 = blockIdx.y * kCkY;
+  for (int e = threadIdx.x; e < (kCkY + 1) * (kCkX + 1); e += 256) {
+    const int tr = e / (kCkX + 1), tc = e - tr * (kCkX + 1);
+    int j = j0 + tr, i = i0 + tc;
+    j -= (j >= ny) ? ny : 0;
+    i -= (i >= nx) ? nx : 0;
+    const unsigned long long k =
+        ((step * (unsigned long long)ny + (unsigned long long)j) * (unsigned long long)nx +
+         (unsigned long long)i) * 2ULL;
+    const unsigned long long z1 = sm_mix(seed_state + (k + 1) * 0x9E3779B97F4A7C15ULL);
+    const unsigned long long z2 = sm_mix(seed_state + (k + 2) * 0x9E3779B97F4A7C15ULL);
+    const double u1 = ((double)(z1 >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(z2 >> 11) + 0.5) * 0x1.0p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2 without a general range reduction
+    rx[tr][tc] = rad * cs;
+    ry[tr][tc] = rad * sn;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i = i0 + tx;
+  if (i >= nx) return;
+#pragma unroll
+  for (int u = 0; u < kCkY / 4; ++u) {
+    const int r = ty + 4 * u, j = j0 + r;
+    if (j >= ny) break;
+    const double div = (rx[r][tx + 1] - rx[r][tx]) * inv_dx + (ry[r + 1][tx] - ry[r][tx]) * inv_dy;
+    q[(long)j * nx + i] = scale * div;
+  }
+}
+
+hipError_t launch_ch_cook_increment(double* q, int nx, int ny, double dx, double dy, double dt,
+                                   double sigma, unsigned long long seed,
+                                   unsigned long long step, hipStream_t st) {
+  dim3 grid((nx + kCkX - 1) / kCkX, (ny + kCkY - 1) / kCkY);
+  const double scale = dt * sqrt(sigma / (dx * dy * dt));
+  hipLaunchKernelGGL(ch_cook_increment, grid, dim3(256), 0, st, q, nx, ny, 1.0 / dx, 1.0 / dy,
+                     scale, sm_mix(seed), step);
+  return hipGetLastError();
 }
 
 // State X = V - Zl T_prev - Zr T_own written out to the caller's array;
@@ -419,18 +488,26 @@ hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long
 // ---------------------------------------------------------------------------
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
-                                 double* rho, const ChCoef& K, double* part, hipStream_t st) {
+                                 double* rho, const ChCoef& K, double* part, hipStream_t st,
+                                 const double* q) {
   BandT<double> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
   dim3 grid(((nx >> 6) + 3) / 4, cy.S);
   const int Sc = cy.S;
-#define CHX_COLPASS(R, D)                                                                      \
-  hipLaunchKernelGGL((ch_column_pass<R, D>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
-                     ny, Sc, cy.rec, bd, rho, K, part)
-  if (recon && diag) CHX_COLPASS(true, true);
-  else if (recon) CHX_COLPASS(true, false);
-  else if (diag) CHX_COLPASS(false, true);
-  else CHX_COLPASS(false, false);
+#define CHX_COLPASS(R, D, N)                                                                      \
+  hipLaunchKernelGGL((ch_column_pass<R, D, N>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
+                     ny, Sc, cy.rec, bd, rho, K, part, q)
+  if (q) {
+    if (recon && diag) CHX_COLPASS(true, true, true);
+    else if (recon) CHX_COLPASS(true, false, true);
+    else if (diag) CHX_COLPASS(false, true, true);
+    else CHX_COLPASS(false, false, true);
+  } else {
+    if (recon && diag) CHX_COLPASS(true, true, false);
+    else if (recon) CHX_COLPASS(true, false, false);
+    else if (diag) CHX_COLPASS(false, true, false);
+    else CHX_COLPASS(false, false, false);
+  }
 #undef CHX_COLPASS
   return hipGetLastError();
 }

@@ -34,9 +34,16 @@ hipError_t launch_ch2_update(const double* c, long ldc, const double* cp, long l
                              const double* v, long ldv, double* out, double* out_prev, long ld,
                              int nx, int ny, const DevChunk* recon, hipStream_t st);
 
+// q != nullptr: the Cahn-Hilliard-Cook increment (pitch nx) is added to the
+// right-hand side.
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
-                                 double* rho, const ChCoef& K, double* part, hipStream_t st);
+                                 double* rho, const ChCoef& K, double* part, hipStream_t st,
+                                 const double* q = nullptr);
+// q = dt eta of the Cahn-Hilliard-Cook forcing for counter `step` (pitch nx).
+hipError_t launch_ch_cook_increment(double* q, int nx, int ny, double dx, double dy, double dt,
+                                   double sigma, unsigned long long seed,
+                                   unsigned long long step, hipStream_t st);
 long ch_column_pass_blocks(int nx, int Sc);
 hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
                               const DevChunk& cy, hipStream_t st);
