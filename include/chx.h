@@ -311,6 +311,13 @@ int ch_get_noise_step(chx_ch h, unsigned long long* step);
 int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
                    double* energy, chx_stream s);
 
+/* ch_moments: coarsening measure of Ch.3 "Numerical Results": out (host, 3
+ *   doubles) = <C>, <C^2> and s = 1 / (1 - <C^2>), the averages by composite
+ *   Simpson's rule in each direction of the periodic grid (weights 2/3 on
+ *   even, 4/3 on odd indices; nx and ny even, else CHX_EINVAL), fixed-order
+ *   reduction.  Synchronises stream s; CHX_ENONFINITE on NaN or Inf. */
+int ch_moments(chx_ch h, const double* c, long ld, double* out, chx_stream s);
+
 /* ------------------------------------------------------------------------
  * Uneven ensembles (the thesis's statistical ensembles of coarsening runs,
  * Ch.7 "2D Cahn--Hilliard Methodology", and its proposal of variable system

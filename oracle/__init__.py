@@ -76,6 +76,8 @@ def load(path: str | None = None):
     lib.orc_cook_increment.argtypes = [_P, _I, _I, _D, _D, _D, _D, _U64, _U64]
     lib.orc_ch_step_cook.restype = _I
     lib.orc_ch_step_cook.argtypes = [_P, _I, _I, _D, _D, _D, _D, _D, _D, _U64, _U64]
+    lib.orc_simpson_mean.restype = _D
+    lib.orc_simpson_mean.argtypes = [_P, _I, _I, _I]
     lib.orc_batch1d_step.restype = _I
     lib.orc_batch1d_step.argtypes = [_I, _P, _I, _I, _D, _D, _D, _D]
     lib.orc_ch2_rhs.restype = None
@@ -253,6 +255,15 @@ class Oracle:
             if rc:
                 raise ValueError(f"cook step failed ({rc})")
         return c
+
+    # Ch.3 "Numerical Results": Simpson averages and s(t) = 1 / (1 - <C^2>)
+    def simpson_mean(self, c2d, power=1):
+        c = _f64(c2d)
+        ny, nx = c.shape
+        return self.lib.orc_simpson_mean(_ptr(c), nx, ny, int(power))
+
+    def ch_s(self, c2d):
+        return 1.0 / (1.0 - self.simpson_mean(c2d, 2))
 
     def ch_mass(self, c2d, lx, ly):
         c = _f64(c2d)

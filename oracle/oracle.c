@@ -625,6 +625,28 @@ int orc_ch_step_cook(double* c, int nx, int ny, double lx, double ly, double D,
   return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Ch.3 "Numerical Results": s(t) = 1 / (1 - <C^2>), the spatial average by
+ * composite Simpson's rule in each direction of the periodic grid (nx, ny
+ * even): weight 2/3 on even and 4/3 on odd indices, so that <f> = sum w_i w_j
+ * f_ij / (nx ny).  Returns <C^power> (power 1 or 2); Neumaier sum. */
+double orc_simpson_mean(const double* c, int nx, int ny, int power) {
+  double s = 0.0, comp = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    const double wj = (j % 2 == 0) ? 2.0 / 3.0 : 4.0 / 3.0;
+    for (int i = 0; i < nx; ++i) {
+      const double wi = (i % 2 == 0) ? 2.0 / 3.0 : 4.0 / 3.0;
+      const double cv = c[(size_t)j * nx + i];
+      const double v = wj * wi * (power == 2 ? cv * cv : cv);
+      const double t = s + v;
+      if (fabs(s) >= fabs(v)) comp = comp + ((s - t) + v);
+      else                    comp = comp + ((v - t) + s);
+      s = t;
+    }
+  }
+  return (s + comp) / ((double)nx * ny);
+}
+
 /* Ch.2: conservation of the integral of C.  Neumaier-compensated sum. */
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly) {
   double s = 0.0, comp = 0.0;

@@ -153,6 +153,10 @@ void orc_cook_increment(double* out, int nx, int ny, double lx, double ly,
 int orc_ch_step_cook(double* c, int nx, int ny, double lx, double ly, double D,
                      double gamma, double dt, double sigma, uint64_t seed,
                      uint64_t step);
+/* Ch.3 "Numerical Results": spatial average <C^power> (power 1 or 2) by
+ * composite Simpson's rule on the periodic grid (nx, ny even); s(t) =
+ * 1 / (1 - <C^2>). */
+double orc_simpson_mean(const double* c, int nx, int ny, int power);
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly);
 double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
                      double gamma);

@@ -39,6 +39,7 @@ EXPORTED = [
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
     "ch_get_tuning", "ch_set_tuning", "ch_set_noise", "ch_get_noise_step", "ch_diagnostics",
+    "ch_moments",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
@@ -104,6 +105,7 @@ def load(path: str | None = None):
         "ch_get_tuning": (_I, [_V, _I, _IP]),
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
+        "ch_moments": (_I, [_V, _V, _L, _DP, _V]),
         "batch1d_create": (_I, [_I, _I, _D, _D, _D, _D, ctypes.POINTER(_V)]),
         "batch1d_destroy": (_I, [_V]),
         "batch1d_ws_bytes": (_S, [_V, _I]),
@@ -469,6 +471,16 @@ def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):
     if st not in (CHX_OK, CHX_ENONFINITE):
         _check(st, "ch_diagnostics")
     return m.value, e.value, st
+
+
+def ch_moments(h: CH, c, ld: int | None = None, stream=None):
+    """(<C>, <C^2>, s = 1/(1 - <C^2>)) by Simpson's rule; synchronises."""
+    ld = c.stride(0) if ld is None else ld
+    out = (ctypes.c_double * 3)()
+    st = load().ch_moments(h.handle, _devptr(c, "c"), ld, out, _stream(stream))
+    if st not in (CHX_OK, CHX_ENONFINITE):
+        _check(st, "ch_moments")
+    return out[0], out[1], out[2]
 
 
 # ------------------------------------------------------------- host inspection

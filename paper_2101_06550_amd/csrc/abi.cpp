@@ -1121,6 +1121,23 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass, double* ene
   return CHX_OK;
 }
 
+int ch_moments(chx_ch h, const double* c, long ld, double* out, chx_stream s) {
+  if (!h || !c || !out) return CHX_EINVAL;
+  if (ld < h->prm.nx || (h->prm.nx & 1) || (h->prm.ny & 1)) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  double* dev = h->dscratch + 2 * h->dscratch_parts;
+  hipError_t e = launch_ch_simpson(c, ld, h->prm.nx, h->prm.ny, h->dscratch, dev, st);
+  double host[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return CHX_EHIP;
+  out[0] = host[0];
+  out[1] = host[1];
+  out[2] = 1.0 / (1.0 - host[1]);
+  if (!std::isfinite(host[0]) || !std::isfinite(host[1])) return CHX_ENONFINITE;
+  return CHX_OK;
+}
+
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   if (!out || !prm || nruns < 1) return CHX_EINVAL;
   *out = nullptr;

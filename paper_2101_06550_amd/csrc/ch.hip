@@ -533,6 +533,44 @@ hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef
   return hipGetLastError();
 }
 
+// Ch.3 "Numerical Results": Simpson averages <C>, <C^2> on the periodic grid
+// (weights 2/3 on even, 4/3 on odd indices in each direction); one (sum w c,
+// sum w c^2) pair per 64 x 16 block, summed in fixed order by ch_diag_final.
+__global__ __launch_bounds__(256) void ch_simpson_partial(const double* __restrict__ c, long ld,
+                                                          int nx, int ny,
+                                                          double* __restrict__ part) {
+  __shared__ double red[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double s1 = 0.0, s2 = 0.0;
+  if (i < nx) {
+    const double wi = (i & 1) ? 4.0 / 3.0 : 2.0 / 3.0;
+    for (int r = 0; r < 16; r += 4) {
+      const int j = blockIdx.y * 16 + r + wave;
+      if (j >= ny) break;
+      const double w = wi * ((j & 1) ? 4.0 / 3.0 : 2.0 / 3.0);
+      const double v = c[(long)j * ld + i];
+      s1 += w * v;
+      s2 += w * v * v;
+    }
+  }
+  block_sum2(s1, s2, red);
+  if (threadIdx.x == 0) {
+    const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * b] = s1;
+    part[2 * b + 1] = s2;
+  }
+}
+
+hipError_t launch_ch_simpson(const double* c, long ld, int nx, int ny, double* part, double* out,
+                             hipStream_t st) {
+  dim3 grid((nx + 63) / 64, (ny + 15) / 16);
+  hipLaunchKernelGGL(ch_simpson_partial, grid, dim3(256), 0, st, c, ld, nx, ny, part);
+  hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, (long)grid.x * grid.y,
+                     1.0 / ((double)nx * ny), out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st) {
   hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, nparts, scale, out);

@@ -50,6 +50,9 @@ hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd
 long ch_diag_partial_blocks(int nx, int ny);
 hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef& K, double* part,
                           double* out, hipStream_t st);
+// out[0] = <C>, out[1] = <C^2> by Simpson's rule (part: ch_diag_partial_blocks pairs).
+hipError_t launch_ch_simpson(const double* c, long ld, int nx, int ny, double* part, double* out,
+                             hipStream_t st);
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st);
 hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long ldc, double* R,

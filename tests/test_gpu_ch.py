@@ -216,6 +216,22 @@ def test_split_row_pass_not_settable_for_short_rows(chx):
         chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_ROW_SPLIT)
 
 
+@pytest.mark.parametrize("ny,nx,ldx", [(128, 128, 128), (96, 192, 200), (1024, 1024, 1024)])
+def test_simpson_moments(chx, orc, ny, nx, ldx):
+    """Ch.3 s(t) = 1/(1 - <C^2>) with Simpson averages, against the oracle."""
+    c0 = inputs.noise_field(ny, nx, 41) + 0.05
+    h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, 1e-4)
+    buf = torch.zeros((ny, ldx), dtype=torch.float64, device="cuda")
+    buf[:, :nx] = torch.tensor(c0, device="cuda")
+    m1, m2, s = chx.ch_moments(h, buf, ld=ldx)
+    assert abs(m1 - orc.simpson_mean(c0, 1)) < 1e-15
+    assert abs(m2 - orc.simpson_mean(c0, 2)) < 1e-15
+    assert abs(s - orc.ch_s(c0)) < 1e-14
+    with pytest.raises(chx.ChxError):
+        chx.ch_moments(chx.ch_create(81, 64, L, L, 1.0, 0.01, 1e-4),
+                       torch.zeros((64, 81), dtype=torch.float64, device="cuda"))
+
+
 def test_diagnostics_entry(chx, orc):
     c0 = inputs.noise_field(96, 64, 13)
     h = chx.ch_create(64, 96, L, L, 1.0, 0.01, 1e-4)

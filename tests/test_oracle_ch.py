@@ -185,3 +185,25 @@ def test_diagnostics_closed_forms(orc):
     grad = s ** 2 * 4 * math.sin(k * h / 2) ** 2 * (n / 2) / h ** 2 * n
     F = (bulk + 0.5 * gamma * grad) * h * h
     assert abs(orc.ch_energy(c0, L, L, gamma) - F) < 1e-12 * F
+
+
+def test_simpson_average_against_scipy(orc):
+    """Ch.3 s(t) = 1/(1 - <C^2>), the average by Simpson's rule: on the
+    periodic extension (first row and column appended) it is scipy's
+    composite Simpson integral over (0, 2 pi)^2 divided by the area."""
+    from scipy.integrate import simpson
+    n_y, n_x = 48, 64
+    c = inputs.noise_field(n_y, n_x, 17)
+    ext = np.concatenate([c, c[:1]], axis=0)
+    ext = np.concatenate([ext, ext[:, :1]], axis=1)
+    x = np.linspace(0, 2 * np.pi, n_x + 1)
+    y = np.linspace(0, 2 * np.pi, n_y + 1)
+    for power in (1, 2):
+        ref = simpson(simpson(ext ** power, x=x, axis=1), x=y) / (2 * np.pi) ** 2
+        assert abs(orc.simpson_mean(c, power) - ref) < 1e-15 * max(1.0, abs(ref)) + 1e-17
+    # closed forms: a constant, and a mode whose doubled frequency avoids n/2
+    assert abs(orc.simpson_mean(np.full((8, 8), 0.3), 2) - 0.09) < 1e-16
+    xx = np.arange(64) * 2 * np.pi / 64
+    m = np.tile(0.7 * np.sin(3 * xx), (16, 1))
+    assert abs(orc.simpson_mean(m, 2) - 0.245) < 1e-15
+    assert abs(orc.ch_s(m) - 1 / (1 - 0.245)) < 1e-14

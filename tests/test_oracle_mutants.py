@@ -162,8 +162,20 @@ def pin_cook(o):
     return np.max(np.abs(forced - o.ch_step(c, L, L, 1.0, g, dt) - vq)) < 1e-13
 
 
+def pin_simpson(o):
+    """Ch.3 s(t): the Simpson average against scipy on the periodic extension."""
+    from scipy.integrate import simpson
+    c = inputs.noise_field(24, 32, 17)
+    ext = np.concatenate([c, c[:1]], axis=0)
+    ext = np.concatenate([ext, ext[:, :1]], axis=1)
+    x = np.linspace(0, 2 * np.pi, 33)
+    y = np.linspace(0, 2 * np.pi, 25)
+    ref = simpson(simpson(ext ** 2, x=x, axis=1), x=y) / (2 * np.pi) ** 2
+    return abs(o.simpson_mean(c, 2) - ref) < 1e-15
+
+
 ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
-            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook]
+            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook, pin_simpson]
 
 MUTANTS = {
     "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
@@ -208,6 +220,8 @@ MUTANTS = {
                             "return ((double)(sm_mix(st) >> 11) + 1.0) * 0x1.0p-53;"),
     "cook_box_muller_cos_for_both": ("ry[(size_t)j * nx + i] = rad * sin(two_pi * u2);",
                                      "ry[(size_t)j * nx + i] = rad * cos(two_pi * u2);"),
+    "simpson_weights_swapped": ("const double wi = (i % 2 == 0) ? 2.0 / 3.0 : 4.0 / 3.0;",
+                                "const double wi = (i % 2 == 0) ? 4.0 / 3.0 : 2.0 / 3.0;"),
     "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
                                    "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
 }
