@@ -318,6 +318,15 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
  *   reduction.  Synchronises stream s; CHX_ENONFINITE on NaN or Inf. */
 int ch_moments(chx_ch h, const double* c, long ld, double* out, chx_stream s);
 
+/* ch_k1: the second coarsening measure of Ch.3 "Numerical Results",
+ *   k1 = sum |C^(k)|^2 / sum |k|^-1 |C^(k)|^2 over the discrete wavevectors
+ *   k = (2 pi m / lx, 2 pi l / ly) other than k = 0, C^ the discrete Fourier
+ *   transform of c (a library real-to-complex FFT, then a fixed-order
+ *   reduction kernel).  *k1 (host).  The first call makes the transform plan
+ *   and a buffer of about two fields, kept by the handle.  Synchronises
+ *   stream s; CHX_ENONFINITE if the field has no k != 0 content. */
+int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s);
+
 /* ------------------------------------------------------------------------
  * Uneven ensembles (the thesis's statistical ensembles of coarsening runs,
  * Ch.7 "2D Cahn--Hilliard Methodology", and its proposal of variable system

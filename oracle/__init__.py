@@ -265,6 +265,23 @@ class Oracle:
     def ch_s(self, c2d):
         return 1.0 / (1.0 - self.simpson_mean(c2d, 2))
 
+    @staticmethod
+    def ch_k1(c2d, lx, ly):
+        """Ch.3 "Numerical Results": k1 = sum |C^|^2 / sum |k|^-1 |C^|^2 over
+        the discrete wavevectors k = (2 pi m / lx, 2 pi l / ly) other than
+        k = 0 (where |k|^-1 is undefined), C^ the discrete Fourier transform
+        (a library FFT, numpy's)."""
+        c = _f64(c2d)
+        ny, nx = c.shape
+        C = np.fft.fft2(c)
+        kx = 2 * np.pi * np.fft.fftfreq(nx, d=lx / nx)
+        ky = 2 * np.pi * np.fft.fftfreq(ny, d=ly / ny)
+        k = np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
+        p = np.abs(C) ** 2
+        p[0, 0] = 0.0
+        k[0, 0] = 1.0
+        return float(np.sum(p) / np.sum(p / k))
+
     def ch_mass(self, c2d, lx, ly):
         c = _f64(c2d)
         ny, nx = c.shape

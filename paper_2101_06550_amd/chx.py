@@ -39,7 +39,7 @@ EXPORTED = [
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
     "ch_get_tuning", "ch_set_tuning", "ch_set_noise", "ch_get_noise_step", "ch_diagnostics",
-    "ch_moments",
+    "ch_moments", "ch_k1",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
@@ -106,6 +106,7 @@ def load(path: str | None = None):
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
         "ch_moments": (_I, [_V, _V, _L, _DP, _V]),
+        "ch_k1": (_I, [_V, _V, _L, _DP, _V]),
         "batch1d_create": (_I, [_I, _I, _D, _D, _D, _D, ctypes.POINTER(_V)]),
         "batch1d_destroy": (_I, [_V]),
         "batch1d_ws_bytes": (_S, [_V, _I]),
@@ -481,6 +482,14 @@ def ch_moments(h: CH, c, ld: int | None = None, stream=None):
     if st not in (CHX_OK, CHX_ENONFINITE):
         _check(st, "ch_moments")
     return out[0], out[1], out[2]
+
+
+def ch_k1(h: CH, c, ld: int | None = None, stream=None) -> float:
+    """k1 = sum |C^|^2 / sum |k|^-1 |C^|^2 (k != 0); synchronises."""
+    ld = c.stride(0) if ld is None else ld
+    v = ctypes.c_double()
+    _check(load().ch_k1(h.handle, _devptr(c, "c"), ld, ctypes.byref(v), _stream(stream)), "ch_k1")
+    return v.value
 
 
 # ------------------------------------------------------------- host inspection

@@ -1,6 +1,7 @@
 // abi.cpp -- the extern "C" boundary declared in include/chx.h: argument
 // checks, plan construction and upload, kernel dispatch.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -273,11 +274,17 @@ struct chx_ch_s {
   double cxs[5] = {}, cys[5] = {};
   long part_count = 0;
   double* dscratch = nullptr;  // ch_diagnostics: partials + 2 outputs
+  // ch_k1: transform plan and buffers, made on first use
+  bool fft_ready = false;
+  hipfftHandle fft{};
+  void* fft_mem = nullptr;
   long dscratch_parts = 0;
   ~chx_ch_s() {
     delete px;
     delete py;
     if (dscratch) (void)hipFree(dscratch);
+    if (fft_ready) (void)hipfftDestroy(fft);
+    if (fft_mem) (void)hipFree(fft_mem);
   }
 };
 
@@ -1136,6 +1143,44 @@ int ch_moments(chx_ch h, const double* c, long ld, double* out, chx_stream s) {
   out[2] = 1.0 / (1.0 - host[1]);
   if (!std::isfinite(host[0]) || !std::isfinite(host[1])) return CHX_ENONFINITE;
   return CHX_OK;
+}
+
+int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s) {
+  if (!h || !c || !k1) return CHX_EINVAL;
+  const int nx = h->prm.nx, ny = h->prm.ny;
+  if (ld < nx) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  const size_t real_b = align256((size_t)nx * ny * sizeof(double));
+  const size_t spec_b = align256((size_t)(nx / 2 + 1) * ny * sizeof(double2));
+  const long nb = ch_k1_blocks(nx, ny);
+  const size_t part_b = align256((size_t)(2 * nb + 2) * sizeof(double));
+  if (!h->fft_ready) {
+    if (hipMalloc(&h->fft_mem, real_b + spec_b + part_b) != hipSuccess) {
+      h->fft_mem = nullptr;
+      return CHX_ENOMEM;
+    }
+    if (hipfftPlan2d(&h->fft, ny, nx, HIPFFT_D2Z) != HIPFFT_SUCCESS) return CHX_EHIP;
+    h->fft_ready = true;
+  }
+  auto* base = static_cast<unsigned char*>(h->fft_mem);
+  double* real = reinterpret_cast<double*>(base);
+  auto* spec = reinterpret_cast<double2*>(base + real_b);
+  double* part = reinterpret_cast<double*>(base + real_b + spec_b);
+  double* dout = part + 2 * nb;
+  // the transform takes a compact copy (it may also overwrite its input)
+  hipError_t e = hipMemcpy2DAsync(real, nx * sizeof(double), c, ld * sizeof(double),
+                                  nx * sizeof(double), ny, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return CHX_EHIP;
+  if (hipfftSetStream(h->fft, st) != HIPFFT_SUCCESS ||
+      hipfftExecD2Z(h->fft, real, reinterpret_cast<hipfftDoubleComplex*>(spec)) != HIPFFT_SUCCESS)
+    return CHX_EHIP;
+  e = launch_ch_k1(spec, nx, ny, h->prm.lx, h->prm.ly, part, dout, st);
+  double host[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(host, dout, sizeof(host), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return CHX_EHIP;
+  *k1 = host[0] / host[1];
+  return std::isfinite(*k1) ? CHX_OK : CHX_ENONFINITE;
 }
 
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {

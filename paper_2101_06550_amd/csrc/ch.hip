@@ -571,6 +571,49 @@ hipError_t launch_ch_simpson(const double* c, long ld, int nx, int ny, double* p
   return hipGetLastError();
 }
 
+// Ch.3 "Numerical Results": k1 = sum |C^|^2 / sum |k|^-1 |C^|^2 from the
+// half spectrum of a real-to-complex transform (ny rows of nx/2 + 1 values;
+// columns 0 and nx/2 count once, the others twice for their conjugates),
+// k = (2 pi m / lx, 2 pi l / ly), k = 0 left out.  One (sum, weighted sum)
+// pair per block of 256 values, summed in fixed order by ch_diag_final.
+__global__ __launch_bounds__(256) void ch_k1_partial(const double2* __restrict__ spec, int nx,
+                                                     int ny, double kx0, double ky0,
+                                                     double* __restrict__ part) {
+  __shared__ double red[8];
+  const int nh = nx / 2 + 1;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  if (e < (long)nh * ny) {
+    const int l = (int)(e / nh), m = (int)(e - (long)l * nh);
+    if (l != 0 || m != 0) {
+      const double2 v = spec[e];
+      const double w = (m == 0 || 2 * m == nx) ? 1.0 : 2.0;
+      const int ls = (2 * l <= ny) ? l : l - ny;
+      const double kx = kx0 * m, ky = ky0 * ls;
+      const double pw = w * (v.x * v.x + v.y * v.y);
+      s1 = pw;
+      s2 = pw / sqrt(kx * kx + ky * ky);
+    }
+  }
+  block_sum2(s1, s2, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+long ch_k1_blocks(int nx, int ny) { return ((long)(nx / 2 + 1) * ny + 255) / 256; }
+
+hipError_t launch_ch_k1(const double2* spec, int nx, int ny, double lx, double ly, double* part,
+                        double* out, hipStream_t st) {
+  const long nb = ch_k1_blocks(nx, ny);
+  const double two_pi = 6.283185307179586476925286766559;
+  hipLaunchKernelGGL(ch_k1_partial, dim3((unsigned)nb), dim3(256), 0, st, spec, nx, ny,
+                     two_pi / lx, two_pi / ly, part);
+  hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, nb, 1.0, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st) {
   hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, nparts, scale, out);

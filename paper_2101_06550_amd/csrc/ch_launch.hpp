@@ -53,6 +53,11 @@ hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef
 // out[0] = <C>, out[1] = <C^2> by Simpson's rule (part: ch_diag_partial_blocks pairs).
 hipError_t launch_ch_simpson(const double* c, long ld, int nx, int ny, double* part, double* out,
                              hipStream_t st);
+// out[0] = sum |C^|^2, out[1] = sum |k|^-1 |C^|^2 over the half spectrum of
+// a real-to-complex transform (ny x (nx/2 + 1)); part: ch_k1_blocks pairs.
+long ch_k1_blocks(int nx, int ny);
+hipError_t launch_ch_k1(const double2* spec, int nx, int ny, double lx, double ly, double* part,
+                        double* out, hipStream_t st);
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st);
 hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long ldc, double* R,

@@ -232,6 +232,22 @@ def test_simpson_moments(chx, orc, ny, nx, ldx):
                        torch.zeros((64, 81), dtype=torch.float64, device="cuda"))
 
 
+@pytest.mark.parametrize("ny,nx,ldx,lx", [(128, 128, 128, L), (96, 192, 200, 2 * L),
+                                          (1024, 1024, 1024, L), (81, 64, 64, L)])
+def test_k1_against_oracle(chx, orc, ny, nx, ldx, lx):
+    c0 = inputs.noise_field(ny, nx, 42) + 0.1
+    h = chx.ch_create(nx, ny, lx, L, 1.0, 0.01, 1e-4)
+    buf = torch.zeros((ny, ldx), dtype=torch.float64, device="cuda")
+    buf[:, :nx] = torch.tensor(c0, device="cuda")
+    for _ in range(2):  # the second call reuses the plan
+        k1 = chx.ch_k1(h, buf, ld=ldx)
+        assert abs(k1 - orc.ch_k1(c0, lx, L)) < 1e-12 * k1
+    x = np.arange(nx) * lx / nx
+    y = np.arange(ny) * L / ny
+    mode = np.cos(2 * np.pi * 3 * x[None, :] / lx + 0 * y[:, None])
+    assert abs(chx.ch_k1(h, torch.tensor(mode, device="cuda")) - 2 * np.pi * 3 / lx) < 1e-12
+
+
 def test_diagnostics_entry(chx, orc):
     c0 = inputs.noise_field(96, 64, 13)
     h = chx.ch_create(64, 96, L, L, 1.0, 0.01, 1e-4)

@@ -77,6 +77,7 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.batch1d_ws_bytes(None, 4) == 0
     assert lib.ch_set_noise(None, 1e-10, 1, 0) == chx.CHX_EINVAL
     assert lib.ch_moments(None, None, 8, None, None) == chx.CHX_EINVAL
+    assert lib.ch_k1(None, None, 8, None, None) == chx.CHX_EINVAL
     assert lib.ch_get_noise_step(None, None) == chx.CHX_EINVAL
     v = ctypes.c_int()
     assert lib.ch_get_tuning(None, 0, ctypes.byref(v)) == chx.CHX_EINVAL

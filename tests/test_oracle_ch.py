@@ -207,3 +207,19 @@ def test_simpson_average_against_scipy(orc):
     m = np.tile(0.7 * np.sin(3 * xx), (16, 1))
     assert abs(orc.simpson_mean(m, 2) - 0.245) < 1e-15
     assert abs(orc.ch_s(m) - 1 / (1 - 0.245)) < 1e-14
+
+
+def test_k1_closed_forms(orc):
+    """k1 of a single Fourier mode is its wavenumber; of two modes with
+    amplitudes a, b it is (a^2 + b^2) / (a^2/|k_a| + b^2/|k_b|); the mean
+    does not enter."""
+    n = 64
+    x = np.arange(n) * 2 * np.pi / n
+    X, Y = np.meshgrid(x, x)
+    assert abs(orc.ch_k1(0.3 + np.cos(3 * X + 4 * Y), L, L) - 5.0) < 1e-12
+    a, b = 0.7, 0.2
+    c = a * np.sin(2 * X) + b * np.cos(6 * X + 8 * Y)
+    ref = (a ** 2 + b ** 2) / (a ** 2 / 2 + b ** 2 / 10)
+    assert abs(orc.ch_k1(c, L, L) - ref) < 1e-12
+    # a rectangular box rescales the wavenumbers
+    assert abs(orc.ch_k1(np.cos(3 * X), 4 * np.pi, L) - 1.5) < 1e-12
