@@ -57,6 +57,10 @@ def load(path: str | None = None):
     lib.orc_cyclic_penta_solve.argtypes = [_I, _D, _D, _D, _D, _D, _P, _P]
     lib.orc_cyclic_tri_solve.restype = _I
     lib.orc_cyclic_tri_solve.argtypes = [_I, _D, _D, _D, _P, _P]
+    lib.orc_penta_rows_batch.restype = _I
+    lib.orc_penta_rows_batch.argtypes = [_I, _I, ctypes.c_long, _I] + [_P] * 6
+    lib.orc_tri_rows_batch.restype = _I
+    lib.orc_tri_rows_batch.argtypes = [_I, _I, ctypes.c_long, _I] + [_P] * 4
     lib.orc_cpenta_lines.restype = _I
     lib.orc_cpenta_lines.argtypes = [_I, _I, _I, _D, _D, _D, _D, _D, _P]
     lib.orc_ctri_lines.restype = _I
@@ -151,6 +155,31 @@ class Oracle:
                                            _ptr(x))
         if rc:
             raise ValueError(f"cyclic tri solve failed ({rc})")
+        return x
+
+    # Ch.4 "Implementation on GPU" / Ch.5: batches with one matrix per system
+    def penta_rows_batch(self, a, b, c, d, e, f, periodic):
+        """Every argument is an (n, batch) array (entry i of system s at
+        [i, s]); row i of system s is a x_{i-2} + b x_{i-1} + c x_i + d x_{i+1}
+        + e x_{i+2} = f_i, wrapping mod n when ``periodic``.  Returns x."""
+        a, b, c, d, e = map(_f64, (a, b, c, d, e))
+        x = _f64(f).copy()
+        n, batch = x.shape
+        rc = self.lib.orc_penta_rows_batch(n, batch, batch, int(bool(periodic)),
+                                           *[_ptr(v) for v in (a, b, c, d, e, x)])
+        if rc:
+            raise ValueError(f"batched penta solve failed ({rc})")
+        return x
+
+    def tri_rows_batch(self, a, b, c, f, periodic):
+        """As ``penta_rows_batch`` for rows a x_{i-1} + b x_i + c x_{i+1}."""
+        a, b, c = map(_f64, (a, b, c))
+        x = _f64(f).copy()
+        n, batch = x.shape
+        rc = self.lib.orc_tri_rows_batch(n, batch, batch, int(bool(periodic)),
+                                         *[_ptr(v) for v in (a, b, c, x)])
+        if rc:
+            raise ValueError(f"batched tri solve failed ({rc})")
         return x
 
     def cpenta_lines(self, data2d, direction, coefs):

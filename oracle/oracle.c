@@ -108,25 +108,28 @@ void orc_tri_solve(int n, const double* a, const double* chat,
  * (n-2)x(n-2) block E, the coupling blocks k (columns n-2, n-1 restricted to
  * rows 0..n-3) and h^T (rows n-2, n-1 restricted to columns 0..n-3), and the
  * 2x2 block C22, all read off the periodic pattern entry by entry. */
-static double cyc_penta_entry(int n, double a, double b, double c, double d,
-                              double e, int row, int col) {
+static double cyc_penta_entry(const double* a, const double* b, const double* c,
+                              const double* d, const double* e, int n, int row,
+                              int col) {
+  /* row `row` of the periodic matrix holds a x[row-2] + b x[row-1] + c x[row]
+   * + d x[row+1] + e x[row+2], indices mod n, each coefficient of that row */
   int off = ((col - row) % n + n) % n;
   double v = 0.0;
-  if (off == 0) v = v + c;
-  if (off == 1) v = v + d;
-  if (off == 2) v = v + e;
-  if (off == n - 2) v = v + a;
-  if (off == n - 1) v = v + b;
+  if (off == 0) v = v + c[row];
+  if (off == 1) v = v + d[row];
+  if (off == 2) v = v + e[row];
+  if (off == n - 2) v = v + a[row];
+  if (off == n - 1) v = v + b[row];
   return v;
 }
 
-int orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
-                       orc_cpenta* p) {
+int orc_cpenta_prepare_rows(int n, const double* a, const double* b,
+                            const double* c, const double* d, const double* e,
+                            orc_cpenta* p) {
   if (n < 5 || !p) return -1;
   memset(p, 0, sizeof(*p));
   const int m = n - 2;
   p->n = n; p->m = m;
-  p->a = a; p->b = b; p->c = c; p->d = d; p->e = e;
   size_t sz = sizeof(double) * (size_t)m;
   p->alpha = (double*)malloc(sz); p->beta = (double*)malloc(sz);
   p->gam = (double*)malloc(sz);   p->del = (double*)malloc(sz);
@@ -142,18 +145,18 @@ int orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
          *tc = (double*)calloc(m, 8), *td = (double*)calloc(m, 8),
          *te = (double*)calloc(m, 8);
   for (int i = 0; i < m; ++i) {
-    if (i - 2 >= 0) { ea[i] = cyc_penta_entry(n, a, b, c, d, e, i, i - 2);
-                      ta[i] = cyc_penta_entry(n, a, b, c, d, e, i - 2, i); }
-    if (i - 1 >= 0) { eb[i] = cyc_penta_entry(n, a, b, c, d, e, i, i - 1);
-                      tb[i] = cyc_penta_entry(n, a, b, c, d, e, i - 1, i); }
-    ec[i] = cyc_penta_entry(n, a, b, c, d, e, i, i);
+    if (i - 2 >= 0) { ea[i] = cyc_penta_entry(a, b, c, d, e, n, i, i - 2);
+                      ta[i] = cyc_penta_entry(a, b, c, d, e, n, i - 2, i); }
+    if (i - 1 >= 0) { eb[i] = cyc_penta_entry(a, b, c, d, e, n, i, i - 1);
+                      tb[i] = cyc_penta_entry(a, b, c, d, e, n, i - 1, i); }
+    ec[i] = cyc_penta_entry(a, b, c, d, e, n, i, i);
     tc[i] = ec[i];
-    if (i + 1 < m) { ed[i] = cyc_penta_entry(n, a, b, c, d, e, i, i + 1);
-                     td[i] = cyc_penta_entry(n, a, b, c, d, e, i + 1, i); }
-    if (i + 2 < m) { ee[i] = cyc_penta_entry(n, a, b, c, d, e, i, i + 2);
-                     te[i] = cyc_penta_entry(n, a, b, c, d, e, i + 2, i); }
-    p->kcol0[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 2);
-    p->kcol1[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 1);
+    if (i + 1 < m) { ed[i] = cyc_penta_entry(a, b, c, d, e, n, i, i + 1);
+                     td[i] = cyc_penta_entry(a, b, c, d, e, n, i + 1, i); }
+    if (i + 2 < m) { ee[i] = cyc_penta_entry(a, b, c, d, e, n, i, i + 2);
+                     te[i] = cyc_penta_entry(a, b, c, d, e, n, i + 2, i); }
+    p->kcol0[i] = cyc_penta_entry(a, b, c, d, e, n, i, n - 2);
+    p->kcol1[i] = cyc_penta_entry(a, b, c, d, e, n, i, n - 1);
   }
   int rc = orc_penta_lr_factor(m, ea, eb, ec, ed, ee, p->alpha, p->beta,
                                p->gam, p->del, p->eps);
@@ -166,15 +169,15 @@ int orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
     rc = orc_penta_lr_factor(m, ta, tb, tc, td, te, talpha, tbeta, tgam, tdel,
                              teps);
   if (rc == 0) {
-    for (int i = 0; i < m; ++i) hcol[i] = cyc_penta_entry(n, a, b, c, d, e, n - 2, i);
+    for (int i = 0; i < m; ++i) hcol[i] = cyc_penta_entry(a, b, c, d, e, n, n - 2, i);
     orc_penta_lr_solve(m, talpha, tbeta, tgam, tdel, teps, hcol, p->q0);
-    for (int i = 0; i < m; ++i) hcol[i] = cyc_penta_entry(n, a, b, c, d, e, n - 1, i);
+    for (int i = 0; i < m; ++i) hcol[i] = cyc_penta_entry(a, b, c, d, e, n, n - 1, i);
     orc_penta_lr_solve(m, talpha, tbeta, tgam, tdel, teps, hcol, p->q1);
     /* M = C22 - h^T E^{-1} k, then its 2x2 inverse (eq. first_two) */
-    double m00 = cyc_penta_entry(n, a, b, c, d, e, n - 2, n - 2);
-    double m01 = cyc_penta_entry(n, a, b, c, d, e, n - 2, n - 1);
-    double m10 = cyc_penta_entry(n, a, b, c, d, e, n - 1, n - 2);
-    double m11 = cyc_penta_entry(n, a, b, c, d, e, n - 1, n - 1);
+    double m00 = cyc_penta_entry(a, b, c, d, e, n, n - 2, n - 2);
+    double m01 = cyc_penta_entry(a, b, c, d, e, n, n - 2, n - 1);
+    double m10 = cyc_penta_entry(a, b, c, d, e, n, n - 1, n - 2);
+    double m11 = cyc_penta_entry(a, b, c, d, e, n, n - 1, n - 1);
     for (int i = 0; i < m; ++i) {
       m00 = m00 - p->q0[i] * p->kcol0[i];
       m01 = m01 - p->q0[i] * p->kcol1[i];
@@ -194,6 +197,19 @@ int orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
   free(talpha); free(tbeta); free(tgam); free(tdel); free(teps); free(hcol);
   if (rc != 0) { orc_cpenta_free(p); return -2; }
   return 0;
+}
+
+int orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
+                       orc_cpenta* p) {
+  if (n < 5 || !p) return -1;
+  size_t sz = sizeof(double) * (size_t)n;
+  double *ra = (double*)malloc(sz), *rb = (double*)malloc(sz),
+         *rc_ = (double*)malloc(sz), *rd = (double*)malloc(sz),
+         *re = (double*)malloc(sz);
+  for (int i = 0; i < n; ++i) { ra[i] = a; rb[i] = b; rc_[i] = c; rd[i] = d; re[i] = e; }
+  int rc = orc_cpenta_prepare_rows(n, ra, rb, rc_, rd, re, p);
+  free(ra); free(rb); free(rc_); free(rd); free(re);
+  return rc;
 }
 
 /* Per right-hand side: the last two unknowns first (eq. first_two), then the
@@ -235,32 +251,46 @@ int orc_cyclic_penta_solve(int n, double a, double b, double c, double d,
 
 /* ------------------------------------------------------------------------ */
 /* Ch.5 "Periodic Tridiagonal Matrix": A = A' + u v^T with
- * u = (-b, 0, ..., 0, c)^T, v = (1, 0, ..., 0, -a/b)^T; A' is A without its
- * corners, with 2b in the first and b + ac/b in the last diagonal entry.
- * A' z = u once; per RHS A' y = f and x = y - (v.y)/(1 + v.z) z. */
-int orc_ctri_prepare(int n, double a, double b, double c, orc_ctri* p) {
-  if (n < 3 || !p || b == 0.0) return -1;
+ * u = (-b_0, 0, ..., 0, c_{n-1})^T, v = (1, 0, ..., 0, -a_0/b_0)^T; A' is A
+ * without its corners, with 2 b_0 in the first and b_{n-1} + a_0 c_{n-1}/b_0
+ * in the last diagonal entry (the thesis's choice gamma = -b, written with
+ * the coefficients of the rows they come from).  A' z = u once; per RHS
+ * A' y = f and x = y - (v.y)/(1 + v.z) z. */
+int orc_ctri_prepare_rows(int n, const double* a, const double* b,
+                          const double* c, orc_ctri* p) {
+  if (n < 3 || !p || b[0] == 0.0) return -1;
   memset(p, 0, sizeof(*p));
-  p->n = n; p->a = a; p->b = b; p->c = c;
+  p->n = n; p->a = a[0]; p->b = b[0]; p->c = c[n - 1];
   size_t sz = sizeof(double) * (size_t)n;
   p->sub = (double*)malloc(sz); p->chat = (double*)malloc(sz);
   p->den = (double*)malloc(sz); p->z = (double*)malloc(sz);
   double *dg = (double*)malloc(sz), *sp = (double*)malloc(sz),
          *u = (double*)calloc(n, 8);
-  for (int i = 0; i < n; ++i) { p->sub[i] = a; dg[i] = b; sp[i] = c; }
-  dg[0] = 2.0 * b;
-  dg[n - 1] = b + a * c / b;
+  for (int i = 0; i < n; ++i) { p->sub[i] = a[i]; dg[i] = b[i]; sp[i] = c[i]; }
+  dg[0] = 2.0 * b[0];
+  dg[n - 1] = b[n - 1] + a[0] * c[n - 1] / b[0];
   int rc = orc_tri_prefactor(n, p->sub, dg, sp, p->chat, p->den);
   if (rc == 0) {
-    u[0] = -b;
-    u[n - 1] = c;
+    u[0] = -b[0];
+    u[n - 1] = c[n - 1];
     orc_tri_solve(n, p->sub, p->chat, p->den, u, p->z);
-    p->vz = p->z[0] - (a / b) * p->z[n - 1];
+    p->vz = p->z[0] - (a[0] / b[0]) * p->z[n - 1];
     if (!(1.0 + p->vz != 0.0)) rc = -1;
   }
   free(dg); free(sp); free(u);
   if (rc) { orc_ctri_free(p); return -2; }
   return 0;
+}
+
+int orc_ctri_prepare(int n, double a, double b, double c, orc_ctri* p) {
+  if (n < 3 || !p || b == 0.0) return -1;
+  size_t sz = sizeof(double) * (size_t)n;
+  double *ra = (double*)malloc(sz), *rb = (double*)malloc(sz),
+         *rc_ = (double*)malloc(sz);
+  for (int i = 0; i < n; ++i) { ra[i] = a; rb[i] = b; rc_[i] = c; }
+  int rc = orc_ctri_prepare_rows(n, ra, rb, rc_, p);
+  free(ra); free(rb); free(rc_);
+  return rc;
 }
 
 void orc_ctri_apply(const orc_ctri* p, const double* f, double* x) {
@@ -290,6 +320,81 @@ int orc_cyclic_tri_solve(int n, double a, double b, double c, const double* f,
 }
 
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Batches with one matrix per system (Ch.4 "Implementation on GPU": every
+ * system its own five diagonals and right-hand side, interleaved).  Entry i
+ * of system s of every array sits at [i*ld + s]; x holds the right-hand sides
+ * on entry and the solutions on exit.  Non-periodic systems use the LR
+ * factorisation and sweeps of Ch.4 (tridiagonal: Thomas with
+ * pre-factorisation, Ch.5); periodic ones the bordering of the last two
+ * unknowns (Ch.4) or the Sherman-Morrison correction (Ch.5), each built from
+ * that system's own rows.  Returns 0, or -1 on bad arguments, or -(2 + s) if
+ * the factorisation of system s fails. */
+static void gather_col(const double* src, long ld, int s, int n, double* out) {
+  for (int i = 0; i < n; ++i) out[i] = src[(long)i * ld + s];
+}
+
+int orc_penta_rows_batch(int n, int batch, long ld, int periodic,
+                         const double* a, const double* b, const double* c,
+                         const double* d, const double* e, double* x) {
+  if (batch < 0 || ld < batch || n < (periodic ? 5 : 3)) return -1;
+  size_t sz = sizeof(double) * (size_t)n;
+  double *ra = (double*)malloc(sz), *rb = (double*)malloc(sz),
+         *rc_ = (double*)malloc(sz), *rd = (double*)malloc(sz),
+         *re = (double*)malloc(sz), *f = (double*)malloc(sz),
+         *xs = (double*)malloc(sz);
+  double *al = (double*)malloc(sz), *be = (double*)malloc(sz),
+         *ga = (double*)malloc(sz), *de = (double*)malloc(sz),
+         *ep = (double*)malloc(sz);
+  int rc = 0;
+  for (int s = 0; s < batch && rc == 0; ++s) {
+    gather_col(a, ld, s, n, ra); gather_col(b, ld, s, n, rb);
+    gather_col(c, ld, s, n, rc_); gather_col(d, ld, s, n, rd);
+    gather_col(e, ld, s, n, re); gather_col(x, ld, s, n, f);
+    if (periodic) {
+      orc_cpenta p;
+      if (orc_cpenta_prepare_rows(n, ra, rb, rc_, rd, re, &p) != 0) { rc = -(2 + s); break; }
+      orc_cpenta_apply(&p, f, xs);
+      orc_cpenta_free(&p);
+    } else {
+      if (orc_penta_lr_factor(n, ra, rb, rc_, rd, re, al, be, ga, de, ep) != 0) { rc = -(2 + s); break; }
+      orc_penta_lr_solve(n, al, be, ga, de, ep, f, xs);
+    }
+    for (int i = 0; i < n; ++i) x[(long)i * ld + s] = xs[i];
+  }
+  free(ra); free(rb); free(rc_); free(rd); free(re); free(f); free(xs);
+  free(al); free(be); free(ga); free(de); free(ep);
+  return rc;
+}
+
+int orc_tri_rows_batch(int n, int batch, long ld, int periodic,
+                       const double* a, const double* b, const double* c,
+                       double* x) {
+  if (batch < 0 || ld < batch || n < (periodic ? 3 : 2)) return -1;
+  size_t sz = sizeof(double) * (size_t)n;
+  double *ra = (double*)malloc(sz), *rb = (double*)malloc(sz),
+         *rc_ = (double*)malloc(sz), *f = (double*)malloc(sz),
+         *xs = (double*)malloc(sz), *chat = (double*)malloc(sz),
+         *den = (double*)malloc(sz);
+  int rc = 0;
+  for (int s = 0; s < batch && rc == 0; ++s) {
+    gather_col(a, ld, s, n, ra); gather_col(b, ld, s, n, rb);
+    gather_col(c, ld, s, n, rc_); gather_col(x, ld, s, n, f);
+    if (periodic) {
+      orc_ctri p;
+      if (orc_ctri_prepare_rows(n, ra, rb, rc_, &p) != 0) { rc = -(2 + s); break; }
+      orc_ctri_apply(&p, f, xs);
+      orc_ctri_free(&p);
+    } else {
+      if (orc_tri_prefactor(n, ra, rb, rc_, chat, den) != 0) { rc = -(2 + s); break; }
+      orc_tri_solve(n, ra, chat, den, f, xs);
+    }
+    for (int i = 0; i < n; ++i) x[(long)i * ld + s] = xs[i];
+  }
+  free(ra); free(rb); free(rc_); free(f); free(xs); free(chat); free(den);
+  return rc;
+}
+
 /* Lines of a 2D array: direction 0 solves along x for every row, direction 1
  * along y for every column; one prepared matrix serves every line (the
  * thesis factors a constant matrix once and reuses it). */

@@ -70,6 +70,11 @@ typedef struct {
 
 int  orc_cpenta_prepare(int n, double a, double b, double c, double d, double e,
                         orc_cpenta* p);
+/* The same for a cyclic matrix whose row i holds its own coefficients
+ * a[i] x[i-2] + b[i] x[i-1] + c[i] x[i] + d[i] x[i+1] + e[i] x[i+2]. */
+int  orc_cpenta_prepare_rows(int n, const double* a, const double* b,
+                             const double* c, const double* d, const double* e,
+                             orc_cpenta* p);
 void orc_cpenta_apply(const orc_cpenta* p, const double* f, double* x);
 void orc_cpenta_free(orc_cpenta* p);
 /* One-shot convenience: x = A^{-1} f; returns 0 or <0 on bad arguments. */
@@ -86,10 +91,25 @@ typedef struct {
 } orc_ctri;
 
 int  orc_ctri_prepare(int n, double a, double b, double c, orc_ctri* p);
+/* Row i: a[i] x[i-1] + b[i] x[i] + c[i] x[i+1], indices mod n. */
+int  orc_ctri_prepare_rows(int n, const double* a, const double* b,
+                           const double* c, orc_ctri* p);
 void orc_ctri_apply(const orc_ctri* p, const double* f, double* x);
 void orc_ctri_free(orc_ctri* p);
 int  orc_cyclic_tri_solve(int n, double a, double b, double c, const double* f,
                           double* x);
+
+/* Batches with one matrix per system, interleaved: entry i of system s of
+ * every array at [i*ld + s]; x holds the right-hand sides in and the
+ * solutions out.  periodic != 0: rows wrap mod n (penta n >= 5, tri n >= 3);
+ * otherwise entries outside the matrix are ignored (penta n >= 3, tri n >= 2).
+ * Returns 0, -1 on bad arguments, -(2 + s) if system s cannot be factored. */
+int orc_penta_rows_batch(int n, int batch, long ld, int periodic,
+                         const double* a, const double* b, const double* c,
+                         const double* d, const double* e, double* x);
+int orc_tri_rows_batch(int n, int batch, long ld, int periodic,
+                       const double* a, const double* b, const double* c,
+                       double* x);
 
 /* Batched line solves over a 2D array: direction 0 = along x (each row j is
  * one system, elements contiguous), direction 1 = along y (each column i is

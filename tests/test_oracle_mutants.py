@@ -57,6 +57,43 @@ def pin_tri_dense(o):
     return True
 
 
+def _dense_rows(coefs, offsets, s, periodic):
+    """Dense matrix of system s of a batch given per-row diagonals (n, batch)."""
+    n = coefs[0].shape[0]
+    A = np.zeros((n, n))
+    for i in range(n):
+        for off, co in zip(offsets, coefs):
+            j = i + off
+            if periodic:
+                A[i, j % n] += co[i, s]
+            elif 0 <= j < n:
+                A[i, j] += co[i, s]
+    return A
+
+
+def pin_rows_dense(o):
+    """Batches with one matrix per system against dense LU, system by system."""
+    rng = np.random.default_rng(12)
+    for periodic in (False, True):
+        for n in (5, 6, 11):
+            B = 4
+            a, b, d, e = (rng.uniform(-1, 1, (n, B)) for _ in range(4))
+            c = 5.0 + rng.uniform(0, 1, (n, B))
+            f = rng.uniform(-1, 1, (n, B))
+            x = o.penta_rows_batch(a, b, c, d, e, f, periodic)
+            t_a, t_c = (rng.uniform(-1, 1, (n, B)) for _ in range(2))
+            t_b = 2.5 + rng.uniform(0, 1, (n, B))
+            y = o.tri_rows_batch(t_a, t_b, t_c, f, periodic)
+            for s in range(B):
+                A5 = _dense_rows((a, b, c, d, e), (-2, -1, 0, 1, 2), s, periodic)
+                A3 = _dense_rows((t_a, t_b, t_c), (-1, 0, 1), s, periodic)
+                if np.max(np.abs(x[:, s] - np.linalg.solve(A5, f[:, s]))) > 1e-13:
+                    return False
+                if np.max(np.abs(y[:, s] - np.linalg.solve(A3, f[:, s]))) > 1e-13:
+                    return False
+    return True
+
+
 def pin_step_fft(o):
     n, D, g, dt = 32, 1.0, 0.01, 1e-3
     c = inputs.noise_field(n, n, 5)
@@ -174,7 +211,7 @@ def pin_simpson(o):
     return abs(o.simpson_mean(c, 2) - ref) < 1e-15
 
 
-ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_step_fft, pin_energy_closed_form,
+ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_rows_dense, pin_step_fft, pin_energy_closed_form,
             pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook, pin_simpson]
 
 MUTANTS = {
@@ -187,10 +224,15 @@ MUTANTS = {
     "lr_forward_drops_eps": ("if (i >= 2) num = num - eps[i] * g[i - 2];", ""),
     "navon_untransposed": ("rc = orc_penta_lr_factor(m, ta, tb, tc, td, te, talpha,",
                            "rc = orc_penta_lr_factor(m, ea, eb, ec, ed, ee, talpha,"),
-    "navon_k_column": ("p->kcol1[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 1);",
-                       "p->kcol1[i] = cyc_penta_entry(n, a, b, c, d, e, i, n - 2);"),
-    "corner_swap": ("if (off == n - 2) v = v + a;\n  if (off == n - 1) v = v + b;",
-                    "if (off == n - 2) v = v + b;\n  if (off == n - 1) v = v + a;"),
+    "navon_k_column": ("p->kcol1[i] = cyc_penta_entry(a, b, c, d, e, n, i, n - 1);",
+                       "p->kcol1[i] = cyc_penta_entry(a, b, c, d, e, n, i, n - 2);"),
+    "corner_swap": ("if (off == n - 2) v = v + a[row];\n  if (off == n - 1) v = v + b[row];",
+                    "if (off == n - 2) v = v + b[row];\n  if (off == n - 1) v = v + a[row];"),
+    "rows_entry_from_column": ("if (off == 1) v = v + d[row];", "if (off == 1) v = v + d[col];"),
+    "rows_tri_corner_from_last_row": ("dg[n - 1] = b[n - 1] + a[0] * c[n - 1] / b[0];",
+                                      "dg[n - 1] = b[n - 1] + a[n - 1] * c[n - 1] / b[0];"),
+    "rows_batch_skips_last_system": ("for (int s = 0; s < batch && rc == 0; ++s) {\n    gather_col(a, ld, s, n, ra); gather_col(b, ld, s, n, rb);\n    gather_col(c, ld, s, n, rc_); gather_col(x, ld, s, n, f);",
+                                     "for (int s = 0; s + 1 < batch && rc == 0; ++s) {\n    gather_col(a, ld, s, n, ra); gather_col(b, ld, s, n, rb);\n    gather_col(c, ld, s, n, rc_); gather_col(x, ld, s, n, f);"),
     "sherman_morrison_sign": ("for (int i = 0; i < n; ++i) x[i] = y[i] - fac * p->z[i];",
                               "for (int i = 0; i < n; ++i) x[i] = y[i] + fac * p->z[i];"),
     "thomas_back_typo": ("for (int i = n - 2; i >= 0; --i) x[i] = dh[i] - chat[i] * x[i + 1];",
