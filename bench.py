@@ -250,6 +250,62 @@ def solve_throughput(chx, torch, reps=10):
     return out
 
 
+def per_system_throughput(chx, torch, reps=10):
+    """Batches with one matrix per system (Ch.4 benchmark shape: identical
+    periodic Crank-Nicolson hyperdiffusion systems, gamma = D = L = 1,
+    dt = 1e-8, n = 1024, 65536 systems, each stored with its own diagonals),
+    in the factor-once mode and in the Rewrite mode (factor and solve at every
+    call); the tridiagonal analogue with beta = 0.5.  Algorithmic bytes: the
+    accesses a one-thread-per-system two-pass solve must make per unknown
+    (periodic penta: rewrite 17, solve 13; tri: rewrite 11, solve 9; 8 B
+    each)."""
+    from paper_2101_06550_amd import inputs
+    n, batch = 1024, 65536
+    sig = 1e-8 / (2 * (1.0 / n) ** 4)
+    dev = dict(dtype=torch.float64, device="cuda")
+    f = torch.tensor(inputs.uniform(4, (n, batch), -1, 1), **dev)
+    out = {"n": n, "systems": batch, "periodic": True}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def entry(ms, acc):
+        gbs = 8 * acc * n * batch / (ms * 1e-3) / 1e9
+        return {"ms": round(ms, 4), "solves_per_s": batch / (ms * 1e-3),
+                "algorithmic_bytes_per_unknown": 8 * acc, "effective_GBps": round(gbs, 1),
+                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+    diag = [torch.full((n, batch), v, **dev)
+            for v in (sig, -4 * sig, 1 + 6 * sig, -4 * sig, sig)]
+    x = f.clone()
+    ws = torch.empty(chx.penta_batch_ws_bytes(n, batch, True, chx.CHX_BATCH_REWRITE) + 256,
+                     dtype=torch.uint8, device="cuda")
+    out["penta_rewrite"] = entry(timed(lambda: chx.penta_batch_rewrite(*diag, x, ws=ws)), 17)
+    del ws
+    fws = chx.penta_batch_factor(*diag)
+    out["penta_solve_factored"] = entry(
+        timed(lambda: chx.penta_batch_solve(*diag, x, ws=fws)), 13)
+    del diag, fws
+    tri = [torch.full((n, batch), v, **dev) for v in (-0.5, 2.0, -0.5)]
+    ws = torch.empty(chx.tri_batch_ws_bytes(n, batch, True, chx.CHX_BATCH_REWRITE) + 256,
+                     dtype=torch.uint8, device="cuda")
+    out["tri_rewrite"] = entry(timed(lambda: chx.tri_batch_rewrite(*tri, x, ws=ws)), 11)
+    del ws
+    fws = chx.tri_batch_factor(*tri)
+    out["tri_solve_factored"] = entry(timed(lambda: chx.tri_batch_solve(*tri, x, ws=fws)), 9)
+    out["finite"] = bool(torch.isfinite(x).all())
+    del tri, fws, x, f
+    return out
+
+
 def ensemble_throughput(chx, torch, steps=2000, warmup=20):
     """Uneven ensemble: 96 x 128^2 + 96 x 256^2 + 64 x 512^2 runs (seeds
     1000-1255, U[-0.1, 0.1]), D = 1, gamma = 0.01, dt = 1e-4, FP64; all runs
@@ -722,6 +778,8 @@ def main():
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)
+        log("batched solves with one matrix per system")
+        extra["per_system_N1024_batch65536"] = per_system_throughput(chx, torch)
 
     if not args.no_ensemble:
         log("uneven ensemble")

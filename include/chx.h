@@ -132,6 +132,68 @@ int tri_solve_batch(chx_tri_plan p, int batch, void* x_inout, long ld,
                     size_t ws_bytes, chx_stream s);
 
 /* ------------------------------------------------------------------------
+ * Batches with one matrix per system (Ch.4 "Implementation on GPU", the
+ * cuPentBatch design: every system its own diagonals, one thread per system
+ * on interleaved data, factorisation split from the solve; Ch.5 for the
+ * tridiagonal case).  Every array -- the diagonals and x -- is interleaved
+ * with one leading dimension: entry i of system s at i*ld + s, ld >= batch,
+ * device FP64.
+ *   Penta row i: a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} +
+ *   e_i x_{i+2} = f_i; tri row i: a_i x_{i-1} + b_i x_i + c_i x_{i+1} = f_i.
+ *   periodic = 0: entries that fall outside the matrix are ignored (a_0, a_1,
+ *   b_0, d_{n-1}, e_{n-2}, e_{n-1}; tri a_0, c_{n-1}); n >= 3 (tri n >= 2).
+ *   periodic = 1: indices wrap mod n (Ch.4 bordering of the last two
+ *   unknowns; Ch.5 Sherman-Morrison with A' built from each system's rows,
+ *   which needs b_0 != 0); n >= 5 (tri n >= 3).
+ * No pivoting, as in the thesis: the LR (Thomas) factorisation must exist,
+ * e.g. diagonally dominant or symmetric positive definite matrices.  A zero
+ * pivot is not detected on the device: that system's solution is non-finite
+ * and the other systems are unaffected.
+ *
+ * penta_batch_factor / tri_batch_factor: factor every system once, IN PLACE
+ *   (the thesis overwrites the matrix with its factors): b <- beta,
+ *   c <- 1/alpha, d <- gamma, e <- delta (a kept); tri b <- 1/den, c <- chat.
+ *   Periodic systems also fill ws with their correction vectors; their rows
+ *   n-2 and n-1 are left as given.
+ * penta_batch_solve / tri_batch_solve: solve with those factors (and that ws)
+ *   for the right-hand sides in x, solution returned in x; repeatable.
+ * penta_batch_rewrite / tri_batch_rewrite: the thesis's "Rewrite" mode for
+ *   matrices that change every step: factor and solve in one pass, the
+ *   diagonals left untouched, the back sweep's coefficients kept in ws.
+ * *_batch_ws_bytes(n, batch, periodic, mode): device workspace (256-byte
+ *   aligned) for mode CHX_BATCH_FACTOR (the factor/solve pair, which must
+ *   share one ws; 0 when not periodic, ws may then be NULL) or
+ *   CHX_BATCH_REWRITE; 0 also for invalid arguments.
+ * Errors: CHX_EINVAL (NULL array, ld < batch, periodic not 0/1, ws NULL or
+ *   misaligned when needed), CHX_EUNSUPPORTED_N, CHX_ENOMEM (ws_bytes short),
+ *   CHX_EHIP (launch failed).  batch = 0 does nothing.  Asynchronous on s.
+ */
+#define CHX_BATCH_FACTOR 0
+#define CHX_BATCH_REWRITE 1
+size_t penta_batch_ws_bytes(int n, int batch, int periodic, int mode);
+int penta_batch_factor(int n, int batch, int periodic, double* a, double* b,
+                       double* c, double* d, double* e, long ld, void* ws,
+                       size_t ws_bytes, chx_stream s);
+int penta_batch_solve(int n, int batch, int periodic, const double* a,
+                      const double* b, const double* c, const double* d,
+                      const double* e, long ld, const void* ws,
+                      size_t ws_bytes, double* x, chx_stream s);
+int penta_batch_rewrite(int n, int batch, int periodic, const double* a,
+                        const double* b, const double* c, const double* d,
+                        const double* e, long ld, double* x, void* ws,
+                        size_t ws_bytes, chx_stream s);
+size_t tri_batch_ws_bytes(int n, int batch, int periodic, int mode);
+int tri_batch_factor(int n, int batch, int periodic, double* a, double* b,
+                     double* c, long ld, void* ws, size_t ws_bytes,
+                     chx_stream s);
+int tri_batch_solve(int n, int batch, int periodic, const double* a,
+                    const double* b, const double* c, long ld, const void* ws,
+                    size_t ws_bytes, double* x, chx_stream s);
+int tri_batch_rewrite(int n, int batch, int periodic, const double* a,
+                      const double* b, const double* c, long ld, double* x,
+                      void* ws, size_t ws_bytes, chx_stream s);
+
+/* ------------------------------------------------------------------------
  * stencil2d_apply: cuSten-style 2D stencil in the xy direction (Ch.3
  *   "Software API").  out[j][i] = sum_{q=-top..bottom} sum_{p=-left..right}
  *   w[(q+top)*(left+right+1) + (p+left)] * pre(in[j+q][i+p]),

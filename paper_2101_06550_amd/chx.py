@@ -29,12 +29,16 @@ CHX_F64 = 0
 CHX_F32_REFINED = 1
 CHX_INTERLEAVED = 0
 CHX_CONTIGUOUS = 1
+CHX_BATCH_FACTOR = 0
+CHX_BATCH_REWRITE = 1
 
 # Every symbol that include/chx.h declares.
 EXPORTED = [
     "chx_version", "chx_status_string", "chx_stream_copy",
     "penta_factor", "penta_plan_destroy", "penta_solve_ws_bytes", "penta_solve_batch",
     "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
+    "penta_batch_ws_bytes", "penta_batch_factor", "penta_batch_solve", "penta_batch_rewrite",
+    "tri_batch_ws_bytes", "tri_batch_factor", "tri_batch_solve", "tri_batch_rewrite",
     "stencil2d_apply",
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
@@ -93,6 +97,14 @@ def load(path: str | None = None):
         "tri_plan_destroy": (_I, [_V]),
         "tri_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
         "tri_solve_batch": (_I, [_V, _I, _V, _L, _I, _I, _I, _V, _S, _V]),
+        "penta_batch_ws_bytes": (_S, [_I, _I, _I, _I]),
+        "penta_batch_factor": (_I, [_I, _I, _I] + [_V] * 5 + [_L, _V, _S, _V]),
+        "penta_batch_solve": (_I, [_I, _I, _I] + [_V] * 5 + [_L, _V, _S, _V, _V]),
+        "penta_batch_rewrite": (_I, [_I, _I, _I] + [_V] * 5 + [_L, _V, _V, _S, _V]),
+        "tri_batch_ws_bytes": (_S, [_I, _I, _I, _I]),
+        "tri_batch_factor": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _S, _V]),
+        "tri_batch_solve": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _S, _V, _V]),
+        "tri_batch_rewrite": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _V, _S, _V]),
         "stencil2d_apply": (_I, [_V, _V, _I, _I, _L, _DP, _I, _I, _I, _I, _I, _I, _V]),
         "ch_create": (_I, [ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
         "ch_destroy": (_I, [_V]),
@@ -263,6 +275,103 @@ def tri_solve_batch(plan: TriPlan, batch: int, x, ld: int | None = None,
 
 
 # ----------------------------------------------------------------------- stencil
+# ------------------------------------------ batches with one matrix per system
+def _band_args(arrays, names, x=None, batch=None):
+    """Common (n, ld, batch) of interleaved (n, >= batch) arrays sharing one
+    row stride."""
+    ref = arrays[0]
+    if ref.dim() != 2:
+        raise ChxError(CHX_EINVAL, f"{names[0]} must be a 2D (n, batch) tensor")
+    n, ld = ref.shape[0], ref.stride(0)
+    for t, nm in zip(list(arrays) + ([x] if x is not None else []),
+                     list(names) + (["x"] if x is not None else [])):
+        if t.dim() != 2 or t.shape[0] != n or t.stride(1) != 1 or t.stride(0) != ld:
+            raise ChxError(CHX_EINVAL, f"{nm} must be (n, batch) with the common row stride")
+    b = ref.shape[1] if batch is None else int(batch)
+    if b > ref.shape[1]:
+        raise ChxError(CHX_EINVAL, "batch exceeds the arrays' width")
+    return n, ld, b
+
+
+def penta_batch_ws_bytes(n: int, batch: int, periodic: bool = True,
+                         mode: int = CHX_BATCH_FACTOR) -> int:
+    return load().penta_batch_ws_bytes(n, batch, int(bool(periodic)), int(mode))
+
+
+def tri_batch_ws_bytes(n: int, batch: int, periodic: bool = True,
+                       mode: int = CHX_BATCH_FACTOR) -> int:
+    return load().tri_batch_ws_bytes(n, batch, int(bool(periodic)), int(mode))
+
+
+def penta_batch_factor(a, b, c, d, e, periodic: bool = True, ws=None, batch=None, stream=None):
+    """Factor every system in place (b, c, d, e are overwritten); returns the
+    workspace tensor that penta_batch_solve must be given (None if unused)."""
+    n, ld, bt = _band_args((a, b, c, d, e), "abcde", batch=batch)
+    ws, wsp, avail = _workspace(penta_batch_ws_bytes(n, bt, periodic), ws, a.device)
+    _check(load().penta_batch_factor(n, bt, int(bool(periodic)),
+                                     *[_devptr(t, nm) for t, nm in zip((a, b, c, d, e), "abcde")],
+                                     ld, wsp, avail, _stream(stream)), "penta_batch_factor")
+    return ws
+
+
+def penta_batch_solve(a, b, c, d, e, x, ws=None, periodic: bool = True, batch=None, stream=None):
+    """Solve with the factors left by penta_batch_factor; x in place."""
+    n, ld, bt = _band_args((a, b, c, d, e), "abcde", x=x, batch=batch)
+    need = penta_batch_ws_bytes(n, bt, periodic)
+    if need and ws is None:
+        raise ChxError(CHX_EINVAL, "periodic systems need the workspace of penta_batch_factor")
+    ws, wsp, avail = _workspace(need, ws, a.device)
+    _check(load().penta_batch_solve(n, bt, int(bool(periodic)),
+                                    *[_devptr(t, nm) for t, nm in zip((a, b, c, d, e), "abcde")],
+                                    ld, wsp, avail, _devptr(x, "x"), _stream(stream)),
+           "penta_batch_solve")
+
+
+def penta_batch_rewrite(a, b, c, d, e, x, periodic: bool = True, ws=None, batch=None,
+                        stream=None):
+    """Factor and solve in one pass (the diagonals are left as they are)."""
+    n, ld, bt = _band_args((a, b, c, d, e), "abcde", x=x, batch=batch)
+    ws, wsp, avail = _workspace(penta_batch_ws_bytes(n, bt, periodic, CHX_BATCH_REWRITE), ws,
+                                a.device)
+    _check(load().penta_batch_rewrite(n, bt, int(bool(periodic)),
+                                      *[_devptr(t, nm) for t, nm in zip((a, b, c, d, e), "abcde")],
+                                      ld, _devptr(x, "x"), wsp, avail, _stream(stream)),
+           "penta_batch_rewrite")
+    return ws
+
+
+def tri_batch_factor(a, b, c, periodic: bool = True, ws=None, batch=None, stream=None):
+    n, ld, bt = _band_args((a, b, c), "abc", batch=batch)
+    ws, wsp, avail = _workspace(tri_batch_ws_bytes(n, bt, periodic), ws, a.device)
+    _check(load().tri_batch_factor(n, bt, int(bool(periodic)),
+                                   *[_devptr(t, nm) for t, nm in zip((a, b, c), "abc")],
+                                   ld, wsp, avail, _stream(stream)), "tri_batch_factor")
+    return ws
+
+
+def tri_batch_solve(a, b, c, x, ws=None, periodic: bool = True, batch=None, stream=None):
+    n, ld, bt = _band_args((a, b, c), "abc", x=x, batch=batch)
+    need = tri_batch_ws_bytes(n, bt, periodic)
+    if need and ws is None:
+        raise ChxError(CHX_EINVAL, "periodic systems need the workspace of tri_batch_factor")
+    ws, wsp, avail = _workspace(need, ws, a.device)
+    _check(load().tri_batch_solve(n, bt, int(bool(periodic)),
+                                  *[_devptr(t, nm) for t, nm in zip((a, b, c), "abc")],
+                                  ld, wsp, avail, _devptr(x, "x"), _stream(stream)),
+           "tri_batch_solve")
+
+
+def tri_batch_rewrite(a, b, c, x, periodic: bool = True, ws=None, batch=None, stream=None):
+    n, ld, bt = _band_args((a, b, c), "abc", x=x, batch=batch)
+    ws, wsp, avail = _workspace(tri_batch_ws_bytes(n, bt, periodic, CHX_BATCH_REWRITE), ws,
+                                a.device)
+    _check(load().tri_batch_rewrite(n, bt, int(bool(periodic)),
+                                    *[_devptr(t, nm) for t, nm in zip((a, b, c), "abc")],
+                                    ld, _devptr(x, "x"), wsp, avail, _stream(stream)),
+           "tri_batch_rewrite")
+    return ws
+
+
 def stencil2d_apply(inp, out, weights, left: int, right: int, top: int, bottom: int,
                     periodic: bool = True, premap: int = 0, ld: int | None = None,
                     stream=None) -> None:

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libchx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "abi.cpp", "solve.hip", "stencil.hip", "ch.hip", "util.hip"]
+SOURCES = ["plan.cpp", "abi.cpp", "solve.hip", "stencil.hip", "ch.hip", "util.hip", "varband.hip"]
 ARCH = os.environ.get("CHX_OFFLOAD_ARCH", "gfx950")
 
 

@@ -232,3 +232,44 @@ def test_reduced_blocks_are_truncated_below_rounding():
     assert blocks.shape[0] < 8192 // 32          # truncated
     assert norms.max() == norms[-dlo]              # B_0 is the largest
     assert min(norms[0], norms[-1]) < 1e-12 * norms.max()
+
+
+def test_per_system_batch_workspace_and_argument_checks(lib):
+    """Workspace sizes and host-side rejections of the per-system batched
+    solves (no device work is enqueued on any of these paths)."""
+    import ctypes
+    F, R = chx.CHX_BATCH_FACTOR, chx.CHX_BATCH_REWRITE
+    ldw = 128  # 100 systems, rows padded to 32 entries (256 bytes)
+    assert chx.penta_batch_ws_bytes(5, 100, True, F) == (4 * 3 + 4) * ldw * 8
+    assert chx.penta_batch_ws_bytes(5, 100, True, R) == 4 * 3 * ldw * 8
+    assert chx.penta_batch_ws_bytes(5, 100, False, F) == 0
+    assert chx.penta_batch_ws_bytes(5, 100, False, R) == 2 * 5 * ldw * 8
+    assert chx.tri_batch_ws_bytes(9, 100, True, F) == (2 * 9 + 1) * ldw * 8
+    assert chx.tri_batch_ws_bytes(9, 100, True, R) == 2 * 9 * ldw * 8
+    assert chx.tri_batch_ws_bytes(9, 100, False, R) == 9 * ldw * 8
+    assert chx.penta_batch_ws_bytes(4, 100, True, F) == 0      # below the minimum size
+    assert chx.penta_batch_ws_bytes(8, 100, True, 7) == 0      # unknown mode
+    p = [ctypes.c_void_p((k + 1) << 20) for k in range(6)]
+    ws = ctypes.c_void_p(1 << 32)
+    # sizes below the minimum
+    assert lib.penta_batch_factor(4, 8, 1, *p[:5], 8, ws, 1 << 20, None) == chx.CHX_EUNSUPPORTED_N
+    assert lib.penta_batch_rewrite(2, 8, 0, *p[:5], 8, p[5], ws, 1 << 20, None) == \
+        chx.CHX_EUNSUPPORTED_N
+    assert lib.tri_batch_rewrite(2, 8, 1, *p[:3], 8, p[5], ws, 1 << 20, None) == \
+        chx.CHX_EUNSUPPORTED_N
+    assert lib.tri_batch_solve(1, 8, 0, *p[:3], 8, ws, 1 << 20, p[5], None) == \
+        chx.CHX_EUNSUPPORTED_N
+    # ld < batch, periodic flag not 0/1, NULL arrays
+    assert lib.penta_batch_solve(8, 8, 1, *p[:5], 7, ws, 1 << 20, p[5], None) == chx.CHX_EINVAL
+    assert lib.penta_batch_solve(8, 8, 2, *p[:5], 8, ws, 1 << 20, p[5], None) == chx.CHX_EINVAL
+    assert lib.penta_batch_rewrite(8, 8, 1, *p[:4], None, 8, p[5], ws, 1 << 20, None) == \
+        chx.CHX_EINVAL
+    assert lib.tri_batch_factor(8, 8, 1, p[0], None, p[2], 8, ws, 1 << 20, None) == chx.CHX_EINVAL
+    # workspace missing, misaligned or short
+    assert lib.penta_batch_factor(8, 8, 1, *p[:5], 8, None, 1 << 20, None) == chx.CHX_EINVAL
+    assert lib.penta_batch_factor(8, 8, 1, *p[:5], 8, ctypes.c_void_p((1 << 32) + 8), 1 << 20,
+                                  None) == chx.CHX_EINVAL
+    need = chx.penta_batch_ws_bytes(8, 8, True, R)
+    assert lib.penta_batch_rewrite(8, 8, 1, *p[:5], 8, p[5], ws, need - 8, None) == chx.CHX_ENOMEM
+    need = chx.tri_batch_ws_bytes(8, 8, True, F)
+    assert lib.tri_batch_solve(8, 8, 1, *p[:3], 8, ws, need - 8, p[5], None) == chx.CHX_ENOMEM
