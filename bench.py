@@ -328,6 +328,20 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
         out[name] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
                      "updates_per_s": points * k / el,
                      "algorithmic_GBps": round(34.0 * points * k / el / 1e9, 1)}
+    del ens
+    # the same runs FP32-refined (2 passes: kappa = 706 at 512^2), replayed
+    # from a graph; the runs of a class advance one after another
+    ens = chx.ch_ensemble_create([(n, n, L, L, 1.0, 0.01, 1e-4) for n in sizes],
+                                 dtype=chx.CHX_F32_REFINED, refine_passes=2)
+    k = 20
+    chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["f32_refined_2pass_graph"] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
+                                      "updates_per_s": points * k / el}
     del fields, ens
     return out
 

@@ -399,9 +399,15 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s);
  * same grid and parameters share one factorisation, and with use_graph the
  * whole nsteps sequence is captured once in a hipGraph and replayed.
  *
- * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array).  Every run
- *   must use CHX_F64 and CHX_SCHEME_P1 with nx % 64 == 0, ny % 32 == 0, nx <= 8192; at most 8
- *   distinct (grid, D, gamma, dt) classes; else CHX_EINVAL.
+ * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array), all with
+ *   CHX_SCHEME_P1 and one dtype.  CHX_F64: nx % 64 == 0, ny % 32 == 0,
+ *   nx <= 8192, at most 8 distinct (grid, D, gamma, dt) classes.
+ *   CHX_F32_REFINED (the precision pattern of ch_create's refined step):
+ *   each run as ch_create accepts it, at most 8 distinct (grid, D, gamma, dt,
+ *   refine_passes) classes; the runs of a class share one refined step and
+ *   advance one after another, each with its own launches (so the refined
+ *   ensemble is launch-bound for small grids).  Otherwise CHX_EINVAL (or
+ *   ch_create's status for a refined class it rejects).
  * ch_ensemble_ws_bytes: device workspace for ch_ensemble_step.
  * ch_ensemble_step: advance every run by nsteps >= 1 steps in place.
  *   c_runs: host array of nruns device pointers (row-major fields); ld_runs:

@@ -635,11 +635,12 @@ def chx_host_whole_tables(P: int, coef, n: int, periodic: bool = True):
 # --------------------------------------------------------------------- ensembles
 class Ensemble:
     """Handle of ch_ensemble_create: many independent runs (each a tuple
-    (nx, ny, lx, ly, D, gamma, dt)) advanced together."""
+    (nx, ny, lx, ly, D, gamma, dt)) advanced together, all in FP64 or all
+    FP32-refined with ``refine_passes`` passes."""
 
-    def __init__(self, runs):
+    def __init__(self, runs, dtype: int = CHX_F64, refine_passes: int = 0):
         lib = load()
-        arr = (ChParams * len(runs))(*[ChParams(nx, ny, lx, ly, D, g, dt, CHX_F64, 0)
+        arr = (ChParams * len(runs))(*[ChParams(nx, ny, lx, ly, D, g, dt, dtype, refine_passes)
                                        for (nx, ny, lx, ly, D, g, dt) in runs])
         h = ctypes.c_void_p()
         _check(lib.ch_ensemble_create(len(runs), arr, ctypes.byref(h)), "ch_ensemble_create")
@@ -659,8 +660,8 @@ class Ensemble:
             pass
 
 
-def ch_ensemble_create(runs) -> Ensemble:
-    return Ensemble(runs)
+def ch_ensemble_create(runs, dtype: int = CHX_F64, refine_passes: int = 0) -> Ensemble:
+    return Ensemble(runs, dtype, refine_passes)
 
 
 def ch_ensemble_destroy(e: Ensemble) -> None:

@@ -317,7 +317,12 @@ struct chx_ens_s {
   int g_nsteps = -1;
   double* g_diag = nullptr;
   void* g_ws = nullptr;
+  // FP32-refined ensembles: one refined single-run handle per class; the
+  // runs advance one after another through it, sharing one workspace
+  bool refined = false;
+  std::vector<chx_ch> rh;
   ~chx_ens_s() {
+    for (auto h : rh) (void)ch_destroy(h);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -350,8 +355,12 @@ ChCoef make_coef(const chx_ch_params& q) {
   return K;
 }
 
+int ens_launch_refined(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws,
+                       hipStream_t st);
+
 int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws,
                    hipStream_t st) {
+  if (E->refined) return ens_launch_refined(E, nsteps, diag_out, ws, st);
   hipError_t e = hipSuccess;
   const long dstride = 2L * (nsteps + 1);
   const int4* it = E->ditems;
@@ -1015,6 +1024,23 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   return ok() ? CHX_OK : CHX_EHIP;
 }
 
+namespace {
+// The runs of an FP32-refined ensemble in turn, each through its class's
+// refined step (all on stream st, so they share the one workspace).
+int ens_launch_refined(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws,
+                       hipStream_t st) {
+  const long dstride = 2L * (nsteps + 1);
+  for (int r = 0; r < E->nruns; ++r) {
+    const EnsRun& R = E->runs[r];
+    const int rc = run_steps(E->rh[R.cls], R.c, R.ldc, nsteps,
+                             diag_out ? diag_out + r * dstride : nullptr, ws, E->ws_total, st,
+                             nullptr);
+    if (rc != CHX_OK) return rc;
+  }
+  return CHX_OK;
+}
+}  // namespace
+
 int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, double* diag_out,
                    void* ws, size_t ws_bytes, chx_stream s) {
   if (!h || !c || !cprev) return CHX_EINVAL;
@@ -1183,6 +1209,43 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s) {
   return std::isfinite(*k1) ? CHX_OK : CHX_ENONFINITE;
 }
 
+// FP32-refined ensemble: a class is a (grid, parameters, refinement passes)
+// combination; each gets one refined single-run handle.
+static int ens_create_refined(chx_ens_s* E) {
+  E->refined = true;
+  std::vector<chx_ch_params> reps;
+  E->runs.resize(E->nruns);
+  size_t ws = 256;
+  for (int r = 0; r < E->nruns; ++r) {
+    const chx_ch_params& q = E->prm[r];
+    if (q.scheme != CHX_SCHEME_P1) return CHX_EINVAL;
+    int cls = -1;
+    for (size_t c = 0; c < reps.size(); ++c)
+      if (same_grid(reps[c], q) && reps[c].refine_passes == q.refine_passes) cls = (int)c;
+    if (cls < 0) {
+      if ((int)reps.size() == kEnsMaxClasses) return CHX_EINVAL;
+      chx_ch h = nullptr;
+      const int rc = ch_create(&q, &h);
+      if (rc != CHX_OK) return rc;
+      E->rh.push_back(h);
+      cls = (int)reps.size();
+      reps.push_back(q);
+      ws = std::max(ws, ch_ws_bytes(h));
+    }
+    EnsRun& R = E->runs[r];
+    R.c = nullptr;
+    R.ldc = q.nx;
+    R.off_b0 = R.off_b1 = R.off_rho = R.off_part = 0;
+    R.nx = q.nx;
+    R.ny = q.ny;
+    R.cls = cls;
+    R.ncb = R.Sc = R.ndbx = R.ndby = 0;
+    R.ncolblocks = 0;
+  }
+  E->ws_total = ws;
+  return CHX_OK;
+}
+
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   if (!out || !prm || nruns < 1) return CHX_EINVAL;
   *out = nullptr;
@@ -1190,6 +1253,21 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   if (!E) return CHX_ENOMEM;
   E->nruns = nruns;
   E->prm.assign(prm, prm + nruns);
+  int nref = 0;
+  for (int r = 0; r < nruns; ++r) nref += prm[r].dtype == CHX_F32_REFINED;
+  if (nref > 0) {
+    if (nref != nruns) {  // one precision per ensemble
+      delete E;
+      return CHX_EINVAL;
+    }
+    const int rc = ens_create_refined(E);
+    if (rc != CHX_OK) {
+      delete E;
+      return rc;
+    }
+    *out = E;
+    return CHX_OK;
+  }
   std::vector<int> cls_of(nruns, -1);
   std::vector<chx_ch_params> reps;
   for (int r = 0; r < nruns; ++r) {
@@ -1382,7 +1460,16 @@ int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int 
       changed = true;
     }
   }
-  if (changed) {  // work already queued may still read the table
+  if (changed && E->refined && E->gexec) {
+    // the refined runs' launches carry the field pointers themselves, so a
+    // cached graph of them is stale: drop it once the queued work is done
+    if (hipStreamSynchronize(st) != hipSuccess) return CHX_EHIP;
+    (void)hipGraphExecDestroy(E->gexec);
+    if (E->graph) (void)hipGraphDestroy(E->graph);
+    E->gexec = nullptr;
+    E->graph = nullptr;
+  }
+  if (changed && !E->refined) {  // work already queued may still read the table
     if (hipStreamSynchronize(st) != hipSuccess) return CHX_EHIP;
     if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * E->nruns, hipMemcpyHostToDevice) !=
         hipSuccess)

@@ -126,3 +126,68 @@ def test_uneven_workload_full_size(chx, orc):
         n = sizes[r]
         ref = orc.ch_step(c0[r], L, L, 1.0, 0.01, 1e-4)
         assert rel(fields[r].cpu().numpy(), ref) < 1e-12, r
+
+
+def test_refined_ensemble_matches_single_refined_runs(chx, orc):
+    """FP32-refined ensembles (2 passes): each run equals the same run advanced
+    by a single refined handle, bit for bit (same kernels, same order), and
+    one step stays within the refined target of the oracle."""
+    runs = RUNS[:6]
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs],
+                                 dtype=chx.CHX_F32_REFINED, refine_passes=2)
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, _, _, _, seed) in runs]
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    print("[case] refined ensemble one step", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=1, use_graph=False)
+    torch.cuda.synchronize()
+    for (nx, ny, D, g, dt, seed), c, f in zip(runs, c0, fields):
+        assert rel(f.cpu().numpy(), orc.ch_step(c, L, L, D, g, dt)) < 1e-10, (nx, ny, seed)
+    n = 3
+    diag = torch.zeros(len(runs) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    print("[case] refined ensemble 3 steps vs single refined handles", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=n, diag_out=diag, use_graph=True)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(runs), n + 1, 2)
+    for r, ((nx, ny, D, g, dt, seed), c) in enumerate(zip(runs, c0)):
+        h = chx.ch_create(nx, ny, L, L, D, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=2)
+        single = torch.tensor(c, device="cuda")
+        chx.ch_adi_step(h, single, nsteps=1)
+        sd = torch.zeros(2 * (n + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, single, nsteps=n, diag_out=sd)
+        torch.cuda.synchronize()
+        assert torch.equal(single, fields[r]), r
+        assert np.array_equal(sd.cpu().numpy().reshape(n + 1, 2), d[r]), r
+
+
+def test_refined_ensemble_graph_follows_new_pointers(chx):
+    """A captured refined-ensemble graph carries the field pointers; new
+    fields must be stepped, old ones left alone."""
+    runs = RUNS[:3]
+    spec = [(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs]
+    ens = chx.ch_ensemble_create(spec, dtype=chx.CHX_F32_REFINED, refine_passes=1)
+    ref = chx.ch_ensemble_create(spec, dtype=chx.CHX_F32_REFINED, refine_passes=1)
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, _, _, _, seed) in runs]
+    f1 = [torch.tensor(c, device="cuda") for c in c0]
+    f2 = [torch.tensor(c, device="cuda") for c in c0]
+    fr = [torch.tensor(c, device="cuda") for c in c0]
+    for rep in range(3):
+        print(f"[case] refined ensemble graph, new pointers {rep}", flush=True)
+        chx.ch_ensemble_step(ens, f1, nsteps=2, use_graph=True)
+        torch.cuda.synchronize()
+        keep = [t.clone() for t in f1]
+        chx.ch_ensemble_step(ens, f2, nsteps=2, use_graph=True)
+        chx.ch_ensemble_step(ref, fr, nsteps=2, use_graph=False)
+        torch.cuda.synchronize()
+        for a, b, k in zip(f2, fr, keep):
+            assert torch.equal(a, b), rep
+        for a, k in zip(f1, keep):
+            assert torch.equal(a, k), rep
+
+
+def test_mixed_precision_ensemble_rejected(chx):
+    lib = chx.load()
+    import ctypes
+    arr = (chx.ChParams * 2)(chx.ChParams(64, 64, L, L, 1.0, 0.01, 1e-4, chx.CHX_F64, 0),
+                             chx.ChParams(64, 64, L, L, 1.0, 0.01, 1e-4, chx.CHX_F32_REFINED, 1))
+    h = ctypes.c_void_p()
+    assert lib.ch_ensemble_create(2, arr, ctypes.byref(h)) == chx.CHX_EINVAL
