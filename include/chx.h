@@ -427,6 +427,22 @@ int ch_ensemble_step(chx_ens e, double* const* c_runs, const long* ld_runs,
                      int nsteps, double* diag_out, void* ws, size_t ws_bytes,
                      int use_graph, chx_stream s);
 
+/* Per-run coarsening measures of an ensemble (Ch.3 "Numerical Results",
+ * gathered per run for the ensemble statistics of Ch.7), for the fields in
+ * c_runs / ld_runs laid out as for ch_ensemble_step:
+ * ch_ensemble_moments: out (host, 3 per run) = <C>, <C^2>, s = 1/(1 - <C^2>)
+ *   of run r at out[3r..3r+2], as ch_moments computes them (every run's nx
+ *   and ny even, else CHX_EINVAL).
+ * ch_ensemble_k1: k1 (host, 1 per run) as ch_k1 defines it; the runs of one
+ *   grid size share one batched real-to-complex transform.
+ * The first call of each makes its buffers (and the transform plans), kept
+ * by the handle.  Both synchronise stream s and return CHX_ENONFINITE if any
+ * run's value is NaN or infinite (the others are still written). */
+int ch_ensemble_moments(chx_ens e, double* const* c_runs, const long* ld_runs,
+                        double* out, chx_stream s);
+int ch_ensemble_k1(chx_ens e, double* const* c_runs, const long* ld_runs,
+                   double* k1, chx_stream s);
+
 /* ------------------------------------------------------------------------
  * Host-side plan inspection (no device work; usable without a GPU).  They
  * return the tables that penta_factor / tri_factor compute and upload, so the

@@ -46,6 +46,7 @@ EXPORTED = [
     "ch_moments", "ch_k1",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
+    "ch_ensemble_moments", "ch_ensemble_k1",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
 
@@ -128,6 +129,8 @@ def load(path: str | None = None):
         "ch_ensemble_ws_bytes": (_S, [_V]),
         "ch_ensemble_step": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _I, _V, _V, _S,
                                   _I, _V]),
+        "ch_ensemble_moments": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
+        "ch_ensemble_k1": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
         "chx_host_chunk_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _I, _IP]),
         "chx_host_whole_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _IP]),
     }
@@ -692,3 +695,31 @@ def ch_ensemble_step(e: Ensemble, fields, nsteps: int = 1, diag_out=None, use_gr
     dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
     _check(lib.ch_ensemble_step(e.handle, ptrs, lds, nsteps, dptr, wsp, avail, int(use_graph),
                                 _stream(stream)), "ch_ensemble_step")
+
+
+def _ens_fields(e: Ensemble, fields):
+    if len(fields) != e.nruns:
+        raise ChxError(CHX_EINVAL, "one field per run")
+    ptrs = (ctypes.c_void_p * e.nruns)(*[_devptr(f, "field").value for f in fields])
+    lds = (ctypes.c_long * e.nruns)(*[f.stride(0) for f in fields])
+    return ptrs, lds
+
+
+def ch_ensemble_moments(e: Ensemble, fields, stream=None):
+    """Per run (<C>, <C^2>, s) as an (nruns, 3) numpy array (synchronises)."""
+    import numpy as np
+    ptrs, lds = _ens_fields(e, fields)
+    out = np.zeros(3 * e.nruns)
+    _check(load().ch_ensemble_moments(e.handle, ptrs, lds, out.ctypes.data_as(_DP),
+                                      _stream(stream)), "ch_ensemble_moments")
+    return out.reshape(e.nruns, 3)
+
+
+def ch_ensemble_k1(e: Ensemble, fields, stream=None):
+    """Per run k1 as a numpy array of nruns values (synchronises)."""
+    import numpy as np
+    ptrs, lds = _ens_fields(e, fields)
+    out = np.zeros(e.nruns)
+    _check(load().ch_ensemble_k1(e.handle, ptrs, lds, out.ctypes.data_as(_DP), _stream(stream)),
+           "ch_ensemble_k1")
+    return out

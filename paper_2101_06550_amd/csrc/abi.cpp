@@ -321,8 +321,24 @@ struct chx_ens_s {
   // runs advance one after another through it, sharing one workspace
   bool refined = false;
   std::vector<chx_ch> rh;
+  // per-run coarsening measures: Simpson partials, and a batched real-to-
+  // complex transform per grid size (made on first use)
+  void* mom_mem = nullptr;
+  std::vector<long> mom_off;  // per run: offset (doubles) of its partials
+  void* k1_mem = nullptr;
+  struct FftGroup {
+    int nx, ny;
+    std::vector<int> runs;
+    hipfftHandle plan;
+  };
+  std::vector<FftGroup> k1_groups;
+  size_t k1_real_off = 0, k1_spec_off = 0, k1_part_off = 0;
+  std::vector<long> k1_poff;  // per run: offset (doubles) of its partials
   ~chx_ens_s() {
     for (auto h : rh) (void)ch_destroy(h);
+    for (auto& g : k1_groups) (void)hipfftDestroy(g.plan);
+    if (mom_mem) (void)hipFree(mom_mem);
+    if (k1_mem) (void)hipFree(k1_mem);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -1506,6 +1522,145 @@ int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int 
     E->g_ws = ws;
   }
   return hipGraphLaunch(E->gexec, st) == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
+// Per-run coarsening measures of an ensemble (the s(t) and k1(t) of each
+// run, Ch.3 "Numerical Results", for the Ch.7 statistics).
+static int ens_fields(chx_ens E, double* const* c_runs, const long* ld_runs,
+                      std::vector<const double*>& c, std::vector<long>& ld) {
+  c.resize(E->nruns);
+  ld.resize(E->nruns);
+  for (int r = 0; r < E->nruns; ++r) {
+    c[r] = c_runs[r];
+    ld[r] = ld_runs ? ld_runs[r] : E->prm[r].nx;
+    if (!c[r] || ld[r] < E->prm[r].nx) return CHX_EINVAL;
+  }
+  return CHX_OK;
+}
+
+int ch_ensemble_moments(chx_ens E, double* const* c_runs, const long* ld_runs, double* out,
+                        chx_stream s) {
+  if (!E || !c_runs || !out) return CHX_EINVAL;
+  std::vector<const double*> c;
+  std::vector<long> ld;
+  int rc = ens_fields(E, c_runs, ld_runs, c, ld);
+  if (rc != CHX_OK) return rc;
+  for (int r = 0; r < E->nruns; ++r)
+    if ((E->prm[r].nx & 1) || (E->prm[r].ny & 1)) return CHX_EINVAL;
+  if (!E->mom_mem) {
+    long off = 2L * E->nruns;  // the per-run outputs first
+    E->mom_off.resize(E->nruns);
+    for (int r = 0; r < E->nruns; ++r) {
+      E->mom_off[r] = off;
+      off += 2L * ((E->prm[r].nx + 63) / 64) * ((E->prm[r].ny + 15) / 16);
+    }
+    if (hipMalloc(&E->mom_mem, (size_t)off * sizeof(double)) != hipSuccess) {
+      E->mom_mem = nullptr;
+      return CHX_ENOMEM;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(s);
+  double* base = static_cast<double*>(E->mom_mem);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < E->nruns && e == hipSuccess; ++r)
+    e = launch_ch_simpson(c[r], ld[r], E->prm[r].nx, E->prm[r].ny, base + E->mom_off[r],
+                          base + 2 * r, st);
+  std::vector<double> host(2 * E->nruns);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), base, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return CHX_EHIP;
+  bool finite = true;
+  for (int r = 0; r < E->nruns; ++r) {
+    out[3 * r] = host[2 * r];
+    out[3 * r + 1] = host[2 * r + 1];
+    out[3 * r + 2] = 1.0 / (1.0 - host[2 * r + 1]);
+    finite = finite && std::isfinite(host[2 * r]) && std::isfinite(host[2 * r + 1]);
+  }
+  return finite ? CHX_OK : CHX_ENONFINITE;
+}
+
+int ch_ensemble_k1(chx_ens E, double* const* c_runs, const long* ld_runs, double* k1,
+                   chx_stream s) {
+  if (!E || !c_runs || !k1) return CHX_EINVAL;
+  std::vector<const double*> c;
+  std::vector<long> ld;
+  int rc = ens_fields(E, c_runs, ld_runs, c, ld);
+  if (rc != CHX_OK) return rc;
+  if (!E->k1_mem) {
+    // runs grouped by grid size; one batched transform per group, the
+    // groups taking turns in one real and one spectrum buffer
+    for (int r = 0; r < E->nruns; ++r) {
+      const int nx = E->prm[r].nx, ny = E->prm[r].ny;
+      size_t g = 0;
+      while (g < E->k1_groups.size() && !(E->k1_groups[g].nx == nx && E->k1_groups[g].ny == ny))
+        ++g;
+      if (g == E->k1_groups.size()) E->k1_groups.push_back({nx, ny, {}, 0});
+      E->k1_groups[g].runs.push_back(r);
+    }
+    size_t real_max = 0, spec_max = 0;
+    for (auto& g : E->k1_groups) {
+      const size_t nb = g.runs.size();
+      real_max = std::max(real_max, nb * g.nx * g.ny);
+      spec_max = std::max(spec_max, nb * (g.nx / 2 + 1) * g.ny);
+      int dims[2] = {g.ny, g.nx};
+      if (hipfftPlanMany(&g.plan, 2, dims, nullptr, 1, g.nx * g.ny, nullptr, 1,
+                         (g.nx / 2 + 1) * g.ny, HIPFFT_D2Z, (int)nb) != HIPFFT_SUCCESS) {
+        g.plan = 0;
+        return CHX_EHIP;
+      }
+    }
+    E->k1_real_off = 0;
+    E->k1_spec_off = align256(real_max * sizeof(double));
+    E->k1_part_off = E->k1_spec_off + align256(spec_max * sizeof(double2));
+    long off = 2L * E->nruns;  // per-run outputs first
+    E->k1_poff.resize(E->nruns);
+    for (int r = 0; r < E->nruns; ++r) {
+      E->k1_poff[r] = off;
+      off += 2 * ch_k1_blocks(E->prm[r].nx, E->prm[r].ny);
+    }
+    if (hipMalloc(&E->k1_mem, E->k1_part_off + (size_t)off * sizeof(double)) != hipSuccess) {
+      E->k1_mem = nullptr;
+      return CHX_ENOMEM;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(s);
+  auto* base = static_cast<unsigned char*>(E->k1_mem);
+  double* real = reinterpret_cast<double*>(base + E->k1_real_off);
+  auto* spec = reinterpret_cast<double2*>(base + E->k1_spec_off);
+  double* parts = reinterpret_cast<double*>(base + E->k1_part_off);
+  hipError_t e = hipSuccess;
+  for (auto& g : E->k1_groups) {
+    const long pts = (long)g.nx * g.ny, sp = (long)(g.nx / 2 + 1) * g.ny;
+    for (size_t j = 0; j < g.runs.size() && e == hipSuccess; ++j) {
+      const int r = g.runs[j];
+      e = hipMemcpy2DAsync(real + j * pts, g.nx * sizeof(double), c[r], ld[r] * sizeof(double),
+                           g.nx * sizeof(double), g.ny, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) break;
+    if (hipfftSetStream(g.plan, st) != HIPFFT_SUCCESS ||
+        hipfftExecD2Z(g.plan, real, reinterpret_cast<hipfftDoubleComplex*>(spec)) !=
+            HIPFFT_SUCCESS)
+      return CHX_EHIP;
+    for (size_t j = 0; j < g.runs.size() && e == hipSuccess; ++j) {
+      const int r = g.runs[j];
+      e = launch_ch_k1(spec + j * sp, g.nx, g.ny, E->prm[r].lx, E->prm[r].ly,
+                       parts + E->k1_poff[r], parts + 2 * r, st);
+    }
+  }
+  std::vector<double> host(2 * E->nruns);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), parts, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return CHX_EHIP;
+  bool finite = true;
+  for (int r = 0; r < E->nruns; ++r) {
+    k1[r] = host[2 * r] / host[2 * r + 1];
+    finite = finite && std::isfinite(k1[r]);
+  }
+  return finite ? CHX_OK : CHX_ENONFINITE;
 }
 
 // Host-side plan inspection (no device work): the factorisation tables that

@@ -58,6 +58,14 @@ def noise_field(n_y: int, n_x: int, seed: int, amp: float = 0.1) -> np.ndarray:
     return uniform(seed, (n_y, n_x), -amp, amp)
 
 
+def asymmetric_mixture(n_y: int, n_x: int, seed: int, lo: float = 0.4,
+                       hi: float = 0.6) -> np.ndarray:
+    """c0 ~ U[lo, hi] iid: the thesis's asymmetric (off-critical) mixture of
+    the Ch.7 ensembles, U[0.4, 0.6], whose minority phase coarsens by
+    Ostwald ripening."""
+    return uniform(seed, (n_y, n_x), lo, hi)
+
+
 def mode_plus_noise(n: int, seed: int, amp: float = 0.05, kx: int = 3, ky: int = 5,
                     noise: float = 0.01, length: float = 2 * math.pi) -> np.ndarray:
     """c0 = amp sin(kx x) sin(ky y) + U[-noise, noise] on an n x n grid of

@@ -191,3 +191,63 @@ def test_mixed_precision_ensemble_rejected(chx):
                              chx.ChParams(64, 64, L, L, 1.0, 0.01, 1e-4, chx.CHX_F32_REFINED, 1))
     h = ctypes.c_void_p()
     assert lib.ch_ensemble_create(2, arr, ctypes.byref(h)) == chx.CHX_EINVAL
+
+
+def test_ensemble_coarsening_measures_per_run(chx, orc):
+    """Per-run <C>, <C^2>, s and k1 of an ensemble (symmetric and asymmetric
+    mixtures, several grid sizes, padded leading dimensions) against the
+    oracle and against the single-run entry points."""
+    runs = [(64, 64, 0), (128, 64, 1), (64, 64, 1), (256, 128, 0), (128, 64, 0)]
+    L2 = 2 * L
+    spec = [(nx, ny, L, L2 if asym else L, 1.0, 0.01, 1e-4) for (nx, ny, asym) in runs]
+    ens = chx.ch_ensemble_create(spec)
+    fields, host = [], []
+    for r, (nx, ny, asym) in enumerate(runs):
+        c = (inputs.asymmetric_mixture(ny, nx, 2000 + r) if asym
+             else inputs.noise_field(ny, nx, 2000 + r) + 0.02)
+        buf = torch.zeros((ny, nx + 8), dtype=torch.float64, device="cuda")
+        buf[:, :nx] = torch.tensor(c, device="cuda")
+        fields.append(buf[:, :nx])
+        host.append(c)
+    print("[case] ensemble moments and k1", flush=True)
+    for rep in range(2):  # the second call reuses buffers and plans
+        mom = chx.ch_ensemble_moments(ens, fields)
+        k1 = chx.ch_ensemble_k1(ens, fields)
+        for r, ((nx, ny, asym), c) in enumerate(zip(runs, host)):
+            assert abs(mom[r, 0] - orc.simpson_mean(c, 1)) < 1e-15, r
+            assert abs(mom[r, 1] - orc.simpson_mean(c, 2)) < 1e-15, r
+            assert abs(mom[r, 2] - orc.ch_s(c)) < 1e-13 * abs(mom[r, 2]), r
+            ly = L2 if asym else L
+            assert abs(k1[r] - orc.ch_k1(c, L, ly)) < 1e-12 * k1[r], r
+            h = chx.ch_create(nx, ny, L, ly, 1.0, 0.01, 1e-4)
+            assert tuple(chx.ch_moments(h, fields[r])) == tuple(mom[r]), r
+            assert abs(chx.ch_k1(h, fields[r]) - k1[r]) < 1e-13 * k1[r], r
+
+
+def test_asymmetric_mixture_ensemble_steps(chx, orc):
+    """Ch.7 asymmetric mixtures (U[0.4, 0.6]) on 2pi and 4pi boxes with
+    dt = 0.1 dx: one step per run against the oracle, then mass kept over
+    50 steps while s(t) and the free energy move."""
+    runs = [(128, 128, L), (128, 128, 2 * L), (256, 256, 2 * L)]
+    spec = [(n, n, lx, lx, 1.0, 0.01, 0.1 * lx / n) for (n, _, lx) in runs]
+    ens = chx.ch_ensemble_create(spec)
+    c0 = [inputs.asymmetric_mixture(n, n, 3000 + r) for r, (n, _, _) in enumerate(runs)]
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    print("[case] asymmetric ensemble one step", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=1, use_graph=False)
+    torch.cuda.synchronize()
+    for (n, _, lx), c, f in zip(runs, c0, fields):
+        ref = orc.ch_step(c, lx, lx, 1.0, 0.01, 0.1 * lx / n)
+        assert rel(f.cpu().numpy(), ref) < 1e-12, (n, lx)
+    s0 = chx.ch_ensemble_moments(ens, fields)[:, 2].copy()
+    n = 50
+    diag = torch.zeros(len(runs) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    chx.ch_ensemble_step(ens, fields, nsteps=n, diag_out=diag)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(runs), n + 1, 2)
+    for r, ((m, _, lx), c) in enumerate(zip(runs, c0)):
+        mass0 = orc.ch_mass(c, lx, lx)
+        assert abs(d[r, -1, 0] - mass0) < 1e-12 * abs(mass0), r
+        assert np.all(np.diff(d[r, :, 1]) <= 1e-12 * np.abs(d[r, :-1, 1])), r
+    s1 = chx.ch_ensemble_moments(ens, fields)[:, 2]
+    assert np.all(s1 != s0)
