@@ -328,6 +328,18 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
         out[name] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
                      "updates_per_s": points * k / el,
                      "algorithmic_GBps": round(34.0 * points * k / el / 1e9, 1)}
+    # the same runs with Cahn-Hilliard-Cook forcing (sigma = 1e-10, seed
+    # 5000 + r per run), replayed from a graph
+    chx.ch_ensemble_set_noise(ens, 1e-10, [5000 + r for r in range(len(sizes))])
+    k = min(steps, 200)
+    chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["cook_forced_graph"] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
+                                "updates_per_s": points * k / el}
     del ens
     # the same runs FP32-refined (2 passes: kappa = 706 at 512^2), replayed
     # from a graph; the runs of a class advance one after another

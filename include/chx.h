@@ -427,6 +427,22 @@ int ch_ensemble_step(chx_ens e, double* const* c_runs, const long* ld_runs,
                      int nsteps, double* diag_out, void* ws, size_t ws_bytes,
                      int use_graph, chx_stream s);
 
+/* ch_ensemble_set_noise: Cahn-Hilliard-Cook forcing (Ch.7) for every run of
+ *   an FP64 ensemble: intensity sigma >= 0 (0 switches it off), run r drawing
+ *   with seeds[r] (host array of nruns) and the ensemble's step counter,
+ *   starting at step0; the draws are those ch_set_noise defines, so run r
+ *   gets the same forcing as a single handle given (sigma, seeds[r], step0).
+ *   The counter lives on the device and every call of ch_ensemble_step moves
+ *   it on by nsteps, graph replays included.  Synchronises the device; makes
+ *   one increment field per multi-kernel run on first use (single-workgroup
+ *   runs draw their increments on the fly).  CHX_EINVAL for sigma < 0 or
+ *   not finite, seeds NULL with sigma > 0, or sigma > 0 on an FP32-refined
+ *   ensemble.
+ * ch_ensemble_get_noise_step: the counter's value after the calls so far. */
+int ch_ensemble_set_noise(chx_ens e, double sigma, const unsigned long long* seeds,
+                          unsigned long long step0);
+int ch_ensemble_get_noise_step(chx_ens e, unsigned long long* step);
+
 /* Per-run coarsening measures of an ensemble (Ch.3 "Numerical Results",
  * gathered per run for the ensemble statistics of Ch.7), for the fields in
  * c_runs / ld_runs laid out as for ch_ensemble_step:

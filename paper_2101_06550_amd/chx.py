@@ -46,7 +46,8 @@ EXPORTED = [
     "ch_moments", "ch_k1",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
-    "ch_ensemble_moments", "ch_ensemble_k1",
+    "ch_ensemble_moments", "ch_ensemble_k1", "ch_ensemble_set_noise",
+    "ch_ensemble_get_noise_step",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
 
@@ -129,6 +130,8 @@ def load(path: str | None = None):
         "ch_ensemble_ws_bytes": (_S, [_V]),
         "ch_ensemble_step": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _I, _V, _V, _S,
                                   _I, _V]),
+        "ch_ensemble_set_noise": (_I, [_V, _D, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64]),
+        "ch_ensemble_get_noise_step": (_I, [_V, ctypes.POINTER(ctypes.c_uint64)]),
         "ch_ensemble_moments": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
         "ch_ensemble_k1": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
         "chx_host_chunk_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _I, _IP]),
@@ -723,3 +726,22 @@ def ch_ensemble_k1(e: Ensemble, fields, stream=None):
     _check(load().ch_ensemble_k1(e.handle, ptrs, lds, out.ctypes.data_as(_DP), _stream(stream)),
            "ch_ensemble_k1")
     return out
+
+
+def ch_ensemble_set_noise(e: Ensemble, sigma: float, seeds=None, step0: int = 0):
+    """Cahn-Hilliard-Cook forcing for every run; seeds: one per run."""
+    if seeds is None:
+        seeds = [0] * e.nruns
+    if len(seeds) != e.nruns:
+        raise ChxError(CHX_EINVAL, "one seed per run")
+    arr = (ctypes.c_uint64 * e.nruns)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in seeds])
+    _check(load().ch_ensemble_set_noise(e.handle, float(sigma), arr,
+                                        int(step0) & 0xFFFFFFFFFFFFFFFF),
+           "ch_ensemble_set_noise")
+
+
+def ch_ensemble_get_noise_step(e: Ensemble) -> int:
+    v = ctypes.c_uint64()
+    _check(load().ch_ensemble_get_noise_step(e.handle, ctypes.byref(v)),
+           "ch_ensemble_get_noise_step")
+    return v.value

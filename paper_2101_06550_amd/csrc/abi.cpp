@@ -321,6 +321,14 @@ struct chx_ens_s {
   // runs advance one after another through it, sharing one workspace
   bool refined = false;
   std::vector<chx_ch> rh;
+  // Cahn-Hilliard-Cook forcing: counter on the device (so graph replays
+  // advance it), its host mirror, increment fields of the multi-kernel runs
+  bool noise = false;
+  unsigned long long* dnoise = nullptr;
+  unsigned long long noise_step = 0;
+  void* qmem = nullptr;
+  int n_ck = 0;
+  long o_ck = 0;
   // per-run coarsening measures: Simpson partials, and a batched real-to-
   // complex transform per grid size (made on first use)
   void* mom_mem = nullptr;
@@ -338,6 +346,8 @@ struct chx_ens_s {
     for (auto h : rh) (void)ch_destroy(h);
     for (auto& g : k1_groups) (void)hipfftDestroy(g.plan);
     if (mom_mem) (void)hipFree(mom_mem);
+    if (dnoise) (void)hipFree(dnoise);
+    if (qmem) (void)hipFree(qmem);
     if (k1_mem) (void)hipFree(k1_mem);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -392,12 +402,15 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
     }
     if (e == hipSuccess)
       e = launch_ens_small_steps(E->druns, E->hcls, E->dsmall, E->nsmall, E->small_threads,
-                                 E->small_lds, nsteps, diag_out, dstride, ss);
+                                 E->small_lds, nsteps, diag_out, dstride,
+                                 E->noise ? E->dnoise : nullptr, ss);
     if (e == hipSuccess && fork) e = hipEventRecord(E->ev_join, E->side);
   }
   for (int n = 0; E->nbig > 0 && n < nsteps && e == hipSuccess; ++n) {
-    e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->druns, E->hcls, it + E->o_col,
-                               E->n_col, ws, n, st);
+    if (E->noise) e = launch_ens_cook_increment(E->druns, it + E->o_ck, E->n_ck, E->dnoise, n, st);
+    if (e == hipSuccess)
+      e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->noise, E->druns, E->hcls,
+                                 it + E->o_col, E->n_col, ws, n, st);
     if (e == hipSuccess)
       e = launch_ens_reduced(E->druns, E->hcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
                              E->red_lds, st);
@@ -412,6 +425,8 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
     const hipError_t j = hipStreamWaitEvent(st, E->ev_join, 0);
     if (e == hipSuccess) e = j;
   }
+  // every run has read the counter: move it on by this call's steps
+  if (e == hipSuccess && E->noise) e = launch_ens_noise_advance(E->dnoise, nsteps, st);
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
@@ -931,13 +946,20 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
         }
       }
     }
-  } else if (h->small && !qnoise) {
+  } else if (h->small) {
     // one workgroup, field resident in LDS for all steps; it also writes the
     // diagnostics of every state, the final one included
     B();
+    SmallNoise nz{};
+    if (qnoise) {
+      const double dx = h->prm.lx / nx, dy = h->prm.ly / ny;
+      nz = SmallNoise{chx_sm_mix(h->noise_seed), h->noise_step,
+                      h->prm.dt * std::sqrt(h->sigma / (dx * dy * h->prm.dt)), 1.0 / dx, 1.0 / dy};
+    }
     e = launch_ch_small_steps(c, ld, nx, ny, nsteps, h->py->dchunk, h->px->dchunk, h->K, diag_out,
-                              st);
+                              qnoise ? &nz : nullptr, st);
     E(0);
+    if (ok() && qnoise) h->noise_step += (unsigned long long)nsteps;
     if (tm && tm->failed) return CHX_EHIP;
     return ok() ? CHX_OK : CHX_EHIP;
   } else if (h->fast) {
@@ -1257,6 +1279,9 @@ static int ens_create_refined(chx_ens_s* E) {
     R.cls = cls;
     R.ncb = R.Sc = R.ndbx = R.ndby = 0;
     R.ncolblocks = 0;
+    R.q = nullptr;
+    R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
+    R.nseed = 0;
   }
   E->ws_total = ws;
   return CHX_OK;
@@ -1371,6 +1396,9 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     R.ndbx = (q.nx + 63) / 64;
     R.ndby = (q.ny + 15) / 16;
     R.ncolblocks = (long)R.ncb * R.Sc;
+    R.q = nullptr;
+    R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
+    R.nseed = 0;
     E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
     if (is_small[r]) {  // no workspace: the field stays in LDS
       R.off_b0 = R.off_b1 = R.off_rho = R.off_part = 0;
@@ -1415,6 +1443,11 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     for (int by = 0; by < E->runs[r].ndby; ++by)
       for (int bx = 0; bx < E->runs[r].ndbx; ++bx) add(r, bx, by);
   E->n_dpart = (int)(items.size() - E->o_dpart);
+  E->o_ck = (long)items.size();
+  for (int r : order)
+    for (int by = 0; by < (E->runs[r].ny + 15) / 16; ++by)
+      for (int bx = 0; bx < (E->runs[r].nx + 63) / 64; ++bx) add(r, bx, by);
+  E->n_ck = (int)(items.size() - E->o_ck);
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
   const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
@@ -1459,6 +1492,9 @@ int ch_ensemble_destroy(chx_ens e) {
 
 size_t ch_ensemble_ws_bytes(chx_ens e) { return e ? e->ws_total : 0; }
 
+static int ens_step_launch(chx_ens E, int nsteps, double* diag_out, void* ws, unsigned char* w,
+                           int use_graph, hipStream_t st);
+
 int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int nsteps,
                      double* diag_out, void* ws, size_t ws_bytes, int use_graph, chx_stream s) {
   if (!E || !c_runs || nsteps < 1) return CHX_EINVAL;
@@ -1492,6 +1528,14 @@ int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int 
       return CHX_EHIP;
   }
   auto* w = static_cast<unsigned char*>(ws);
+  const int rc_step = ens_step_launch(E, nsteps, diag_out, ws, w, use_graph, st);
+  if (rc_step == CHX_OK && E->noise) E->noise_step += (unsigned long long)nsteps;
+  return rc_step;
+}
+
+// The launches of one ensemble call, eager or from the cached graph.
+static int ens_step_launch(chx_ens E, int nsteps, double* diag_out, void* ws, unsigned char* w,
+                           int use_graph, hipStream_t st) {
   if (!use_graph) return ens_launch_all(E, nsteps, diag_out, w, st);
   if (!E->gexec || E->g_nsteps != nsteps || E->g_diag != diag_out || E->g_ws != ws) {
     if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
@@ -1522,6 +1566,67 @@ int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int 
     E->g_ws = ws;
   }
   return hipGraphLaunch(E->gexec, st) == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
+static void ens_drop_graph(chx_ens E) {
+  if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
+  if (E->graph) (void)hipGraphDestroy(E->graph);
+  E->gexec = nullptr;
+  E->graph = nullptr;
+}
+
+int ch_ensemble_set_noise(chx_ens E, double sigma, const unsigned long long* seeds,
+                          unsigned long long step0) {
+  if (!E || !(sigma >= 0) || !std::isfinite(sigma)) return CHX_EINVAL;
+  if (E->refined) return sigma > 0 ? CHX_EINVAL : CHX_OK;  // FP64 ensembles only
+  if (sigma > 0 && !seeds) return CHX_EINVAL;
+  // queued work may still read the run table or the counter
+  if (hipDeviceSynchronize() != hipSuccess) return CHX_EHIP;
+  if (sigma > 0) {
+    if (!E->dnoise && hipMalloc(&E->dnoise, sizeof(unsigned long long)) != hipSuccess) {
+      E->dnoise = nullptr;
+      return CHX_ENOMEM;
+    }
+    if (!E->qmem && E->nbig > 0) {
+      size_t bytes = 0;
+      for (const auto& R : E->runs)
+        if (R.off_b0 != R.off_b1) bytes += align256((size_t)R.nx * R.ny * sizeof(double));
+      if (hipMalloc(&E->qmem, bytes) != hipSuccess) {
+        E->qmem = nullptr;
+        return CHX_ENOMEM;
+      }
+    }
+    size_t off = 0;
+    for (int r = 0; r < E->nruns; ++r) {
+      EnsRun& R = E->runs[r];
+      const chx_ch_params& q = E->prm[r];
+      const double dx = q.lx / q.nx, dy = q.ly / q.ny;
+      R.nscale = q.dt * std::sqrt(sigma / (dx * dy * q.dt));
+      R.ninv_dx = 1.0 / dx;
+      R.ninv_dy = 1.0 / dy;
+      R.nseed = chx_sm_mix(seeds[r]);
+      R.q = nullptr;
+      if (R.off_b0 != R.off_b1) {  // a multi-kernel run: its increment field
+        R.q = reinterpret_cast<double*>(static_cast<unsigned char*>(E->qmem) + off);
+        off += align256((size_t)R.nx * R.ny * sizeof(double));
+      }
+    }
+    if (hipMemcpy(E->dnoise, &step0, sizeof(step0), hipMemcpyHostToDevice) != hipSuccess)
+      return CHX_EHIP;
+  }
+  if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * E->nruns, hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return CHX_EHIP;
+  E->noise = sigma > 0;
+  E->noise_step = step0;
+  ens_drop_graph(E);  // the launch sequence changes with the forcing
+  return CHX_OK;
+}
+
+int ch_ensemble_get_noise_step(chx_ens E, unsigned long long* step) {
+  if (!E || !step) return CHX_EINVAL;
+  *step = E->noise_step;
+  return CHX_OK;
 }
 
 // Per-run coarsening measures of an ensemble (the s(t) and k1(t) of each

@@ -261,37 +261,37 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
 // the row and column after it into LDS once, then differences.
 constexpr int kCkX = 64, kCkY = 16;
 
-__host__ __device__ __forceinline__ unsigned long long sm_mix(unsigned long long z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
+// One N(0,1) pair (rho_x, rho_y) of point (i, j) at step `step`.
+__device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigned long long step,
+                                          int j, int i, int nx, int ny, double& rx, double& ry) {
+  const unsigned long long k =
+      ((step * (unsigned long long)ny + (unsigned long long)j) * (unsigned long long)nx +
+       (unsigned long long)i) * 2ULL;
+  const unsigned long long z1 = chx_sm_mix(seed_state + (k + 1) * 0x9E3779B97F4A7C15ULL);
+  const unsigned long long z2 = chx_sm_mix(seed_state + (k + 2) * 0x9E3779B97F4A7C15ULL);
+  const double u1 = ((double)(z1 >> 11) + 0.5) * 0x1.0p-53;
+  const double u2 = ((double)(z2 >> 11) + 0.5) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2 without a general range reduction
+  rx = rad * cs;
+  ry = rad * sn;
 }
 
-__global__ __launch_bounds__(256) void ch_cook_increment(double* __restrict__ q, int nx, int ny,
-                                                         double inv_dx, double inv_dy,
-                                                         double scale,
-                                                         unsigned long long seed_state,
-                                                         unsigned long long step) {
+// The increment of the tile (bx, by) of one field (pitch nx).
+__device__ __forceinline__ void cook_tile_body(double* __restrict__ q, int nx, int ny,
+                                               double inv_dx, double inv_dy, double scale,
+                                               unsigned long long seed_state,
+                                               unsigned long long step, int bx, int by) {
   __shared__ double rx[kCkY + 1][kCkX + 1];
   __shared__ double ry[kCkY + 1][kCkX + 1];
-  const int i0 = blockIdx.x * kCkX, j0 = blockIdx.y * kCkY;
+  const int i0 = bx * kCkX, j0 = by * kCkY;
   for (int e = threadIdx.x; e < (kCkY + 1) * (kCkX + 1); e += 256) {
     const int tr = e / (kCkX + 1), tc = e - tr * (kCkX + 1);
     int j = j0 + tr, i = i0 + tc;
     j -= (j >= ny) ? ny : 0;
     i -= (i >= nx) ? nx : 0;
-    const unsigned long long k =
-        ((step * (unsigned long long)ny + (unsigned long long)j) * (unsigned long long)nx +
-         (unsigned long long)i) * 2ULL;
-    const unsigned long long z1 = sm_mix(seed_state + (k + 1) * 0x9E3779B97F4A7C15ULL);
-    const unsigned long long z2 = sm_mix(seed_state + (k + 2) * 0x9E3779B97F4A7C15ULL);
-    const double u1 = ((double)(z1 >> 11) + 0.5) * 0x1.0p-53;
-    const double u2 = ((double)(z2 >> 11) + 0.5) * 0x1.0p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2 without a general range reduction
-    rx[tr][tc] = rad * cs;
-    ry[tr][tc] = rad * sn;
+    cook_pair(seed_state, step, j, i, nx, ny, rx[tr][tc], ry[tr][tc]);
   }
   __syncthreads();
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -306,13 +306,21 @@ __global__ __launch_bounds__(256) void ch_cook_increment(double* __restrict__ q,
   }
 }
 
+__global__ __launch_bounds__(256) void ch_cook_increment(double* __restrict__ q, int nx, int ny,
+                                                         double inv_dx, double inv_dy,
+                                                         double scale,
+                                                         unsigned long long seed_state,
+                                                         unsigned long long step) {
+  cook_tile_body(q, nx, ny, inv_dx, inv_dy, scale, seed_state, step, blockIdx.x, blockIdx.y);
+}
+
 hipError_t launch_ch_cook_increment(double* q, int nx, int ny, double dx, double dy, double dt,
                                    double sigma, unsigned long long seed,
                                    unsigned long long step, hipStream_t st) {
   dim3 grid((nx + kCkX - 1) / kCkX, (ny + kCkY - 1) / kCkY);
   const double scale = dt * sqrt(sigma / (dx * dy * dt));
   hipLaunchKernelGGL(ch_cook_increment, grid, dim3(256), 0, st, q, nx, ny, 1.0 / dx, 1.0 / dy,
-                     scale, sm_mix(seed), step);
+                     scale, chx_sm_mix(seed), step);
   return hipGetLastError();
 }
 
@@ -788,11 +796,12 @@ __device__ __forceinline__ int wrap_mod(int j, int S) {
   return j < 0 ? j + S : j;
 }
 
-template <bool DIAG>
+template <bool DIAG, bool NOISE>
 __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ldc, int nx, int ny,
                                                  int nsteps, const DevChunk& cy,
                                                  const DevChunk& cx, const ChCoef& K,
-                                                 double* __restrict__ diag, double* smem) {
+                                                 double* __restrict__ diag, double* smem,
+                                                 const SmallNoise& nz) {
   __shared__ double red[2 * (kSmallMaxThreads / 64)];
   const int PX = nx + (nx >> 5);
   double* F = smem;
@@ -843,6 +852,11 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
       double xc_c = F[sfi(row_of(1), ic, PX)];
       double e1 = edge(row_of(1));
       double xl_c = dpp_from_left(xc_c, e1), xr_c = dpp_from_right(xc_c, e1);
+      // forcing: the draws of this row's point and of the one below it are
+      // carried from row to row; the right neighbour's are drawn per row
+      const unsigned long long nstep = nz.step0 + (unsigned long long)n;
+      double nrx_c = 0.0, nry_c = 0.0;
+      if (NOISE) cook_pair(nz.seed_state, nstep, kc * M, ic, nx, ny, nrx_c, nry_c);
 #pragma unroll
       for (int p = 0; p < M; ++p) {
         const int rp = row_of(p + 2);
@@ -861,6 +875,16 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
         const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
         const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
         double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+        if (NOISE) {
+          const int j = kc * M + p, jn = (j + 1 == ny) ? 0 : j + 1;
+          double rx_e, ry_e, rx_n, ry_n;
+          cook_pair(nz.seed_state, nstep, j, ir, nx, ny, rx_e, ry_e);
+          cook_pair(nz.seed_state, nstep, jn, ic, nx, ny, rx_n, ry_n);
+          const double div = (rx_e - nrx_c) * nz.inv_dx + (ry_n - nry_c) * nz.inv_dy;
+          r = r + nz.scale * div;
+          nrx_c = rx_n;
+          nry_c = ry_n;
+        }
         if (DIAG) {
           const double w = xc_c * xc_c - 1.0;
           const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
@@ -1003,13 +1027,13 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
   }
 }
 
-template <bool DIAG>
+template <bool DIAG, bool NOISE>
 __global__ __launch_bounds__(kSmallMaxThreads) void ch_small_steps(double* c, long ldc, int nx,
                                                                    int ny, int nsteps, DevChunk cy,
                                                                    DevChunk cx, ChCoef K,
-                                                                   double* diag) {
+                                                                   double* diag, SmallNoise nz) {
   extern __shared__ double smem_small[];
-  small_steps_body<DIAG>(c, ldc, nx, ny, nsteps, cy, cx, K, diag, smem_small);
+  small_steps_body<DIAG, NOISE>(c, ldc, nx, ny, nsteps, cy, cx, K, diag, smem_small, nz);
 }
 
 size_t ch_small_lds_bytes(int nx, int ny) {
@@ -1024,15 +1048,18 @@ bool ch_small_fits(int nx, int ny, size_t max_lds) {
 
 hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps,
                                  const DevChunk& cy, const DevChunk& cx, const ChCoef& K,
-                                 double* diag, hipStream_t st) {
+                                 double* diag, const SmallNoise* nz, hipStream_t st) {
   const int nt = nx * ny / M;
   const size_t lds = ch_small_lds_bytes(nx, ny);
-  if (diag)
-    hipLaunchKernelGGL(ch_small_steps<true>, dim3(1), dim3(nt), lds, st, c, ldc, nx, ny, nsteps,
-                       cy, cx, K, diag);
-  else
-    hipLaunchKernelGGL(ch_small_steps<false>, dim3(1), dim3(nt), lds, st, c, ldc, nx, ny, nsteps,
-                       cy, cx, K, diag);
+  const SmallNoise z = nz ? *nz : SmallNoise{};
+#define CHX_SMALL(D, N)                                                                     \
+  hipLaunchKernelGGL((ch_small_steps<D, N>), dim3(1), dim3(nt), lds, st, c, ldc, nx, ny, nsteps, \
+                     cy, cx, K, diag, z)
+  if (diag && nz) CHX_SMALL(true, true);
+  else if (diag) CHX_SMALL(true, false);
+  else if (nz) CHX_SMALL(false, true);
+  else CHX_SMALL(false, false);
+#undef CHX_SMALL
   return hipGetLastError();
 }
 
@@ -1042,7 +1069,7 @@ __device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, i
   return reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
 }
 
-template <bool RECON, bool DIAG>
+template <bool RECON, bool DIAG, bool NOISE>
 __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict__ runs,
                                                        EnsClasses cls,
                                                        const int4* __restrict__ items,
@@ -1057,9 +1084,28 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   for (int k = 0; k < 5; ++k) bd.c[k] = C.py.coef[k];
   double* part = reinterpret_cast<double*>(ws + R.off_part);
   double* rho = reinterpret_cast<double*>(ws + R.off_rho);
-  column_pass_body<RECON, DIAG>(src, lds, ens_buf(ws, R, step), R.nx, R.nx, R.ny, R.Sc, C.py.rec,
-                                bd, rho, C.K, DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
-                                it.y, it.z);
+  column_pass_body<RECON, DIAG, NOISE>(src, lds, ens_buf(ws, R, step), R.nx, R.nx, R.ny, R.Sc,
+                                       C.py.rec, bd, rho, C.K,
+                                       DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
+                                       it.y, it.z, R.q);
+}
+
+// Forcing increments of the ensemble's multi-kernel runs for step
+// (*noise_step + n); item {run, tile x, tile y}.
+__global__ __launch_bounds__(256) void ens_cook_increment(const EnsRun* __restrict__ runs,
+                                                          const int4* __restrict__ items,
+                                                          const unsigned long long* noise_step,
+                                                          int n) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  cook_tile_body(R.q, R.nx, R.ny, R.ninv_dx, R.ninv_dy, R.nscale, R.nseed,
+                 *noise_step + (unsigned long long)n, it.y, it.z);
+}
+
+// The ensemble's forcing counter moves on by the steps of one call (one
+// thread, an ordinary global store).
+__global__ void ens_noise_advance(unsigned long long* noise_step, int nsteps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *noise_step += (unsigned long long)nsteps;
 }
 
 __global__ __launch_bounds__(256) void ens_finalize(const EnsRun* __restrict__ runs,
@@ -1097,40 +1143,61 @@ __global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__
 // Small runs of an ensemble: block b advances run small[b] through all nsteps
 // steps with its field resident in LDS (blockDim and LDS sized for the
 // largest small run; the threads beyond a smaller run's tasks stay idle).
-template <bool DIAG>
+template <bool DIAG, bool NOISE>
 __global__ __launch_bounds__(kSmallMaxThreads) void ens_small_steps(
     const EnsRun* __restrict__ runs, EnsClasses cls, const int* __restrict__ small, int nsteps,
-    double* diag_out, long diag_stride) {
+    double* diag_out, long diag_stride, const unsigned long long* noise_step) {
   extern __shared__ double smem_small[];
   const int r = small[blockIdx.x];
   const EnsRun R = runs[r];
   const EnsClass& C = cls.c[R.cls];
-  small_steps_body<DIAG>(R.c, R.ldc, R.nx, R.ny, nsteps, C.py, C.px, C.K,
-                         DIAG ? diag_out + r * diag_stride : nullptr, smem_small);
+  SmallNoise nz{};
+  if (NOISE) nz = SmallNoise{R.nseed, *noise_step, R.nscale, R.ninv_dx, R.ninv_dy};
+  small_steps_body<DIAG, NOISE>(R.c, R.ldc, R.nx, R.ny, nsteps, C.py, C.px, C.K,
+                                DIAG ? diag_out + r * diag_stride : nullptr, smem_small, nz);
 }
 
 hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, const int* small,
                                   int nsmall, int threads, size_t lds, int nsteps,
-                                  double* diag_out, long diag_stride, hipStream_t st) {
-  if (diag_out)
-    hipLaunchKernelGGL(ens_small_steps<true>, dim3(nsmall), dim3(threads), lds, st, runs, cls,
-                       small, nsteps, diag_out, diag_stride);
-  else
-    hipLaunchKernelGGL(ens_small_steps<false>, dim3(nsmall), dim3(threads), lds, st, runs, cls,
-                       small, nsteps, diag_out, diag_stride);
+                                  double* diag_out, long diag_stride,
+                                  const unsigned long long* noise_step, hipStream_t st) {
+#define CHX_ENSSMALL(D, N)                                                                   \
+  hipLaunchKernelGGL((ens_small_steps<D, N>), dim3(nsmall), dim3(threads), lds, st, runs, cls, \
+                     small, nsteps, diag_out, diag_stride, noise_step)
+  if (diag_out && noise_step) CHX_ENSSMALL(true, true);
+  else if (diag_out) CHX_ENSSMALL(true, false);
+  else if (noise_step) CHX_ENSSMALL(false, true);
+  else CHX_ENSSMALL(false, false);
+#undef CHX_ENSSMALL
   return hipGetLastError();
 }
 
-hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs, const EnsClasses& cls,
-                                  const int4* items, int nitems, unsigned char* ws, int step,
-                                  hipStream_t st) {
-#define CHX_ENSCOL(R, D)                                                                        \
-  hipLaunchKernelGGL((ens_column_pass<R, D>), dim3(nitems), dim3(256), 0, st, runs, cls, items, \
+hipError_t launch_ens_cook_increment(const EnsRun* runs, const int4* items, int nitems,
+                                     const unsigned long long* noise_step, int n,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(ens_cook_increment, dim3(nitems), dim3(256), 0, st, runs, items, noise_step,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_noise_advance(unsigned long long* noise_step, int nsteps, hipStream_t st) {
+  hipLaunchKernelGGL(ens_noise_advance, dim3(1), dim3(64), 0, st, noise_step, nsteps);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_column_pass(bool recon, bool diag, bool noise, const EnsRun* runs,
+                                  const EnsClasses& cls, const int4* items, int nitems,
+                                  unsigned char* ws, int step, hipStream_t st) {
+#define CHX_ENSCOL(R, D, N)                                                                        \
+  hipLaunchKernelGGL((ens_column_pass<R, D, N>), dim3(nitems), dim3(256), 0, st, runs, cls, items, \
                      ws, step)
-  if (recon && diag) CHX_ENSCOL(true, true);
-  else if (recon) CHX_ENSCOL(true, false);
-  else if (diag) CHX_ENSCOL(false, true);
-  else CHX_ENSCOL(false, false);
+#define CHX_ENSCOL2(R, D) \
+  if (noise) CHX_ENSCOL(R, D, true); else CHX_ENSCOL(R, D, false)
+  if (recon && diag) { CHX_ENSCOL2(true, true); }
+  else if (recon) { CHX_ENSCOL2(true, false); }
+  else if (diag) { CHX_ENSCOL2(false, true); }
+  else { CHX_ENSCOL2(false, false); }
+#undef CHX_ENSCOL2
 #undef CHX_ENSCOL
   return hipGetLastError();
 }

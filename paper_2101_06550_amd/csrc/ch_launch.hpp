@@ -68,9 +68,15 @@ hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long
 constexpr int kSmallMaxThreads = 512;
 size_t ch_small_lds_bytes(int nx, int ny);
 bool ch_small_fits(int nx, int ny, size_t max_lds);
+// Forcing of the single-workgroup step (Cahn-Hilliard-Cook): generator state
+// mix(seed), counter step of the call's first step, dt amp, 1/dx, 1/dy.
+struct SmallNoise {
+  unsigned long long seed_state, step0;
+  double scale, inv_dx, inv_dy;
+};
 hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps,
                                  const DevChunk& cy, const DevChunk& cx, const ChCoef& K,
-                                 double* diag, hipStream_t st);
+                                 double* diag, const SmallNoise* nz, hipStream_t st);
 hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, int nx, int ny,
                                const ChCoef& K, hipStream_t st);
 

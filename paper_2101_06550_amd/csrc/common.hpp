@@ -17,6 +17,14 @@ struct BandT {
 // Chunk length of the chunked kernels (unknowns per thread-chunk).
 constexpr int kChunk = 32;
 
+// SplitMix64 finaliser (Steele, Lea and Flood 2014): the mixing function of
+// the counter-based generator of the Cahn-Hilliard-Cook forcing.
+__host__ __device__ __forceinline__ unsigned long long chx_sm_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
 __device__ __forceinline__ int wrap_once(int j, int S) {
   j += (j < 0) ? S : 0;
   j -= (j >= S) ? S : 0;

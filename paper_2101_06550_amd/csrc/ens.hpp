@@ -22,6 +22,11 @@ struct EnsRun {
   int ncb, Sc;             // column-pass blocks per chunk row, column chunks
   int ndbx, ndby;          // diagnostic-partial blocks (64 x 16 points each)
   long ncolblocks;         // column-pass blocks = ncb * Sc
+  // Cahn-Hilliard-Cook forcing (set by ch_ensemble_set_noise): increment
+  // field (multi-kernel runs), dt amp, 1/dx, 1/dy, generator state mix(seed)
+  double* q;
+  double nscale, ninv_dx, ninv_dy;
+  unsigned long long nseed;
 };
 
 struct EnsClass {
@@ -36,9 +41,15 @@ struct EnsClasses {
 };
 
 // Work items are int4 {run, a, b, 0}.
-hipError_t launch_ens_column_pass(bool recon, bool diag, const EnsRun* runs,
+hipError_t launch_ens_column_pass(bool recon, bool diag, bool noise, const EnsRun* runs,
                                   const EnsClasses& cls, const int4* items, int nitems,
                                   unsigned char* ws, int step, hipStream_t st);
+// Forcing increments of step (*noise_step + n); items {run, tile x, tile y}
+// over 64 x 16 tiles; and the counter's advance by nsteps after a call.
+hipError_t launch_ens_cook_increment(const EnsRun* runs, const int4* items, int nitems,
+                                     const unsigned long long* noise_step, int n,
+                                     hipStream_t st);
+hipError_t launch_ens_noise_advance(unsigned long long* noise_step, int nsteps, hipStream_t st);
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
                               long diag_stride, size_t lds_bytes, hipStream_t st);
@@ -51,7 +62,8 @@ hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const 
 // block b = run small[b]; threads / lds sized for the largest of them.
 hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, const int* small,
                                   int nsmall, int threads, size_t lds, int nsteps,
-                                  double* diag_out, long diag_stride, hipStream_t st);
+                                  double* diag_out, long diag_stride,
+                                  const unsigned long long* noise_step, hipStream_t st);
 // Diagnostics of the final state of the runs big[0..nbig).
 hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                            int nitems, const int* big, int nbig, unsigned char* ws,

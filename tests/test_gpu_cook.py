@@ -90,3 +90,80 @@ def test_noise_arguments_rejected(chx):
                               refine_passes=1)):
         with pytest.raises(chx.ChxError):
             chx.ch_set_noise(bad, 1e-10)
+
+
+# runs of an ensemble: single-workgroup sizes and multi-kernel sizes
+ENS_RUNS = [(64, 64, 1.0, 0.01, 1e-4), (128, 128, 1.0, 0.01, 1e-4), (256, 256, 1.0, 0.01, 1e-4),
+            (256, 128, 1.0, 0.02, 5e-5), (512, 256, 1.0, 0.01, 1e-4)]
+SIGMA = 1e-10
+
+
+def _ens(chx):
+    return chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt) in ENS_RUNS])
+
+
+def test_ensemble_forcing_matches_oracle_and_single_runs(chx, orc):
+    """Every run of a forced ensemble gets the draws of a single handle with
+    its seed: one step against the oracle, and several steps (graph replays,
+    the counter carried across calls) bit for bit against single handles."""
+    seeds = [101, 202, 303, 404, 505]
+    c0 = [inputs.noise_field(ny, nx, 60 + r) for r, (nx, ny, *_) in enumerate(ENS_RUNS)]
+    ens = _ens(chx)
+    chx.ch_ensemble_set_noise(ens, SIGMA, seeds, step0=7)
+    f = [torch.tensor(c, device="cuda") for c in c0]
+    print("[case] forced ensemble one step", flush=True)
+    chx.ch_ensemble_step(ens, f, nsteps=1, use_graph=False)
+    torch.cuda.synchronize()
+    assert chx.ch_ensemble_get_noise_step(ens) == 8
+    for (nx, ny, D, g, dt), c, t, sd in zip(ENS_RUNS, c0, f, seeds):
+        ref = orc.ch_step_cook(c, L, L, D, g, dt, SIGMA, sd, step0=7)
+        assert rel(t.cpu().numpy(), ref) < 1e-12, (nx, ny)
+        assert rel(orc.ch_step(c, L, L, D, g, dt), ref) > 1e-10, (nx, ny)  # forcing visible
+    print("[case] forced ensemble graph replays vs single handles", flush=True)
+    for rep in range(3):
+        chx.ch_ensemble_step(ens, f, nsteps=2, use_graph=True)
+    torch.cuda.synchronize()
+    assert chx.ch_ensemble_get_noise_step(ens) == 14
+    for r, ((nx, ny, D, g, dt), c) in enumerate(zip(ENS_RUNS, c0)):
+        h = chx.ch_create(nx, ny, L, L, D, g, dt)
+        chx.ch_set_noise(h, SIGMA, seed=seeds[r], step0=7)
+        s = torch.tensor(c, device="cuda")
+        chx.ch_adi_step(h, s, nsteps=1)
+        for rep in range(3):
+            chx.ch_adi_step(h, s, nsteps=2)
+        torch.cuda.synchronize()
+        assert torch.equal(s, f[r]), (nx, ny)
+
+
+def test_ensemble_forcing_off_equals_unforced(chx):
+    c0 = [inputs.noise_field(ny, nx, 70 + r) for r, (nx, ny, *_) in enumerate(ENS_RUNS)]
+    a = _ens(chx)
+    b = _ens(chx)
+    chx.ch_ensemble_set_noise(b, SIGMA, [1] * len(ENS_RUNS))
+    chx.ch_ensemble_set_noise(b, 0.0)
+    fa = [torch.tensor(c, device="cuda") for c in c0]
+    fb = [torch.tensor(c, device="cuda") for c in c0]
+    print("[case] ensemble forcing switched off", flush=True)
+    chx.ch_ensemble_step(a, fa, nsteps=3)
+    chx.ch_ensemble_step(b, fb, nsteps=3)
+    torch.cuda.synchronize()
+    for x, y in zip(fa, fb):
+        assert torch.equal(x, y)
+    with pytest.raises(chx.ChxError):
+        chx.ch_ensemble_set_noise(a, -1.0, [1] * len(ENS_RUNS))
+
+
+def test_forced_ensemble_conserves_mass(chx, orc):
+    c0 = [inputs.noise_field(ny, nx, 80 + r) for r, (nx, ny, *_) in enumerate(ENS_RUNS)]
+    ens = _ens(chx)
+    chx.ch_ensemble_set_noise(ens, 1e-8, [9, 8, 7, 6, 5])
+    f = [torch.tensor(c, device="cuda") for c in c0]
+    n = 20
+    d = torch.zeros(len(ENS_RUNS) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    print("[case] forced ensemble mass", flush=True)
+    chx.ch_ensemble_step(ens, f, nsteps=n, diag_out=d)
+    torch.cuda.synchronize()
+    dd = d.cpu().numpy().reshape(len(ENS_RUNS), n + 1, 2)
+    for r, c in enumerate(c0):
+        scale = np.sum(np.abs(c)) * (L / c.shape[1]) * (L / c.shape[0])
+        assert abs(dd[r, -1, 0] - dd[r, 0, 0]) < 1e-12 * scale, r
