@@ -77,3 +77,25 @@ def test_hyperdiffusion_mode_decay(chx):
     chx.batch1d_step(b, x, nsteps=steps)
     torch.cuda.synchronize()
     assert np.max(np.abs(x.cpu().numpy() - x0 * G ** steps)) < 1e-12
+
+
+@pytest.mark.parametrize("kind,n,batch,L,dt,a,D", [
+    (2, 256, 1 << 20, L2PI, 0.1 * L2PI / 256, 0.01, 1.0),   # benchmark's 1D Cahn-Hilliard batch
+    (0, 1024, 65536, 1.0, 1e-8, 1.0, 1.0)])                  # benchmark's hyperdiffusion batch
+def test_benchmark_batches_sampled(chx, orc, kind, n, batch, L, dt, a, D):
+    """The benchmark's batch shapes, in its launch configuration, on sampled
+    systems (the systems are independent, so the oracle steps those alone)."""
+    x0 = inputs.uniform(90 + kind, (n, batch), -0.1, 0.1)
+    b = chx.batch1d_create(kind, n, L, dt, a, D)
+    x = torch.tensor(x0, device="cuda")
+    print(f"[case] batch1d full kind={kind} n={n} batch={batch}", flush=True)
+    chx.batch1d_step(b, x, nsteps=2)
+    torch.cuda.synchronize()
+    pick = [0, 1, 63, 64, 65, 4097, batch // 2 + 3, batch - 2, batch - 1]
+    ref = orc.batch1d_step(kind, np.ascontiguousarray(x0[:, pick]), L, dt, a, D, nsteps=2)
+    # a backward-stable solve of a matrix with kappa = 1 + 16 s is accurate to
+    # about kappa eps per step (s = 5498 for the hyperdiffusion batch)
+    dx = L / n
+    s = {0: a * dt / (2 * dx ** 4), 2: a * D * dt / dx ** 4}[kind]
+    tol = max(1e-12, 20 * np.finfo(float).eps * (1 + 16 * s))
+    assert rel(x[:, pick].cpu().numpy(), ref) < tol

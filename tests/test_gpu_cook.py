@@ -167,3 +167,18 @@ def test_forced_ensemble_conserves_mass(chx, orc):
     for r, c in enumerate(c0):
         scale = np.sum(np.abs(c)) * (L / c.shape[1]) * (L / c.shape[0])
         assert abs(dd[r, -1, 0] - dd[r, 0, 0]) < 1e-12 * scale, r
+
+
+def test_forced_large_run_one_step(chx, orc):
+    """The benchmark's forced workload (8192^2, gamma = 0.001, dt = 1e-6,
+    sigma = 1e-14, seed 2021) for one step against the oracle."""
+    n = 8192
+    c0 = inputs.mode_plus_noise(n, 5)
+    h = chx.ch_create(n, n, L, L, 1.0, 0.001, 1e-6)
+    chx.ch_set_noise(h, 1e-14, seed=2021)
+    c = torch.tensor(c0, device="cuda")
+    print("[case] cook 8192 one step", flush=True)
+    chx.ch_adi_step(h, c, nsteps=1)
+    torch.cuda.synchronize()
+    ref = orc.ch_step_cook(c0, L, L, 1.0, 0.001, 1e-6, 1e-14, 2021)
+    assert rel(c.cpu().numpy(), ref) < 1e-12
