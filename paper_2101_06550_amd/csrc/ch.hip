@@ -642,7 +642,8 @@ hipError_t launch_ch_rhs_plain(const double* c, long ld, double* r, long ldr, in
 // ch2_rhs stages a 16 x 64 tile with a 2-point halo of Cbar = 2C - Cp,
 // mu = C^3 - C and d = C - Cp in LDS and evaluates the 13-point biharmonic and
 // the 5-point Laplacian from there.
-constexpr int kT2X = 64, kT2Y = 16, kT2H = 2;
+constexpr int kT2X = 64, kT2Y = 32, kT2H = 2;
+constexpr int kT2T = 512;  // threads of a ch2_rhs block: 8 waves, 4 rows each
 constexpr int kT2W = kT2X + 2 * kT2H, kT2R = kT2Y + 2 * kT2H;
 
 // UPD: the state is first advanced from the previous step's solution,
@@ -667,46 +668,128 @@ __device__ __forceinline__ double ch2_recon(const double* __restrict__ v, long l
 }
 
 template <bool UPD, bool RECON>
-__global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c, long ld,
-                                               const double* __restrict__ cp, long ldp,
-                                               const double* __restrict__ v, long ldv,
-                                               double* __restrict__ cnew, long ldn,
-                                               double* __restrict__ r, long ldr, int nx, int ny,
-                                               Ch2Coef K, int Sc, const double* __restrict__ rec) {
+__global__ __launch_bounds__(kT2T) void ch2_rhs(const double* __restrict__ c, long ld,
+                                                const double* __restrict__ cp, long ldp,
+                                                const double* __restrict__ v, long ldv,
+                                                double* __restrict__ cnew, long ldn,
+                                                double* __restrict__ r, long ldr, int nx, int ny,
+                                                Ch2Coef K, int Sc, const double* __restrict__ rec) {
   __shared__ double cb[kT2R][kT2W];
   __shared__ double mu[kT2R][kT2W];
-  __shared__ double df[kT2R][kT2W];
+  // RECON: the separator rows of the chunks kb-2 .. kb+1 (kb = the chunk of
+  // the tile's first row), which hold every correction the tile's rows need
+  __shared__ double sep[RECON ? 4 : 1][P][kT2W];
   const int i0 = blockIdx.x * kT2X, j0 = blockIdx.y * kT2Y;
-  for (int e = threadIdx.x; e < kT2R * kT2W; e += 256) {
-    const int tr = e / kT2W, tc = e - tr * kT2W;
-    int j = j0 - kT2H + tr, i = i0 - kT2H + tc;
-    j = (j % ny + ny) % ny;
-    i = (i % nx + nx) % nx;
-    double vc = c[(long)j * ld + i], vp = cp[(long)j * ldp + i];
+  const int kb = j0 / M;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  constexpr int kRows = kT2Y / (kT2T / 64);  // output rows per thread
+  constexpr int kHalo = kT2R * kT2W - kT2Y * kT2X;
+  constexpr int kItH = (kHalo + kT2T - 1) / kT2T;
+  if (RECON) {
+    for (int e = threadIdx.x; e < 4 * P * kT2W; e += kT2T) {
+      const int sl = e / (P * kT2W), rem = e - sl * P * kT2W;
+      const int a = rem / kT2W, tc = rem - a * kT2W;
+      int kc = kb - 2 + sl;
+      while (kc < 0) kc += Sc;
+      while (kc >= Sc) kc -= Sc;
+      int i = i0 - kT2H + tc;
+      i += (i < 0) ? nx : 0;
+      while (i >= nx) i -= nx;
+      sep[sl][a][tc] = v[((long)kc * M + MI + a) * ldv + i];
+    }
+  }
+  // staged points: first this thread's own output points (tile row
+  // kT2H + ty + 8u, column kT2H + tx: aligned 64-wide rows), then the halo
+  // ring; every load is issued before any is used
+  auto halo_rc = [&](int e, int& tr, int& tc) {
+    if (e < 2 * kT2H * kT2W) {  // the kT2H rows above and below, full width
+      const int r4 = e / kT2W;
+      tc = e - r4 * kT2W;
+      tr = r4 < kT2H ? r4 : kT2Y + r4;
+    } else {  // the kT2H columns left and right of the interior rows
+      const int e2 = e - 2 * kT2H * kT2W;
+      const int row = e2 / (2 * kT2H), c4 = e2 - row * (2 * kT2H);
+      tr = kT2H + row;
+      tc = c4 < kT2H ? c4 : kT2X + c4;
+    }
+  };
+  auto wrapped = [&](int tr, int tc, int& j, int& i) {
+    j = j0 - kT2H + tr;
+    i = i0 - kT2H + tc;
+    j += (j < 0) ? ny : 0;
+    while (j >= ny) j -= ny;
+    i += (i < 0) ? nx : 0;
+    while (i >= nx) i -= nx;
+  };
+  double lc[kRows + kItH], lp[kRows + kItH], lv[kRows + kItH];
+#pragma unroll
+  for (int k = 0; k < kRows + kItH; ++k) {
+    int tr, tc;
+    bool ok = true;
+    if (k < kRows) {
+      tr = kT2H + ty + (kT2T / 64) * k;
+      tc = kT2H + tx;
+    } else {
+      const int e = threadIdx.x + kT2T * (k - kRows);
+      ok = e < kHalo;
+      halo_rc(ok ? e : 0, tr, tc);
+    }
+    lc[k] = lp[k] = lv[k] = 0.0;
+    if (ok) {
+      int j, i;
+      wrapped(tr, tc, j, i);
+      lc[k] = c[(long)j * ld + i];
+      lp[k] = cp[(long)j * ldp + i];
+      if (UPD) lv[k] = v[(long)j * ldv + i];
+    }
+  }
+  if (RECON) __syncthreads();  // sep
+  double dfo[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows + kItH; ++k) {
+    int tr, tc;
+    if (k < kRows) {
+      tr = kT2H + ty + (kT2T / 64) * k;
+      tc = kT2H + tx;
+    } else {
+      const int e = threadIdx.x + kT2T * (k - kRows);
+      if (e >= kHalo) break;
+      halo_rc(e, tr, tc);
+    }
+    const int ju = j0 - kT2H + tr, iu = i0 - kT2H + tc;  // unwrapped
+    double vc = lc[k], vp = lp[k];
     if (UPD) {
-      const double vv = RECON ? ch2_recon(v, ldv, j, i, Sc, rec) : v[(long)j * ldv + i];
+      double vv = lv[k];
+      if (RECON) {
+        // chunk of the unwrapped row, relative to kb: -1, 0 or 1
+        const int kcu = (ju + M) / M - 1;
+        const int pp = ju - kcu * M;
+        if (pp < MI) {
+          const int so = kcu - kb + 2, sp = so - 1;
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            vv = vv - rec[pp * 8 + 4 + a] * sep[sp][a][tc] - rec[pp * 8 + 6 + a] * sep[so][a][tc];
+        }
+      }
       const double vn = (2.0 * vc - vp) + vv;
       vp = vc;
       vc = vn;
-      const int jj = j0 - kT2H + tr, ii = i0 - kT2H + tc;
-      if (tr >= kT2H && tr < kT2H + kT2Y && tc >= kT2H && tc < kT2H + kT2X && jj < ny &&
-          ii < nx)
-        cnew[(long)jj * ldn + ii] = vn;
+      if (k < kRows && ju < ny && iu < nx)
+        __builtin_nontemporal_store(vn, &cnew[(long)ju * ldn + iu]);
     }
+    if (k < kRows) dfo[k] = vc - vp;
     cb[tr][tc] = 2.0 * vc - vp;
     mu[tr][tc] = vc * vc * vc - vc;
-    df[tr][tc] = vc - vp;
   }
   __syncthreads();
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int i = i0 + tx;
   if (i >= nx) return;
   const int q = tx + kT2H;
 #pragma unroll
-  for (int u = 0; u < kT2Y / 4; ++u) {
-    const int j = j0 + ty + 4 * u;
+  for (int u = 0; u < kRows; ++u) {
+    const int j = j0 + ty + (kT2T / 64) * u;
     if (j >= ny) break;
-    const int w = ty + 4 * u + kT2H;
+    const int w = ty + (kT2T / 64) * u + kT2H;
     const double d4x = (cb[w][q - 2] - 4.0 * cb[w][q - 1] + 6.0 * cb[w][q] - 4.0 * cb[w][q + 1] +
                         cb[w][q + 2]) * K.inv_dx4;
     const double d4y = (cb[w - 2][q] - 4.0 * cb[w - 1][q] + 6.0 * cb[w][q] - 4.0 * cb[w + 1][q] +
@@ -718,7 +801,7 @@ __global__ __launch_bounds__(256) void ch2_rhs(const double* __restrict__ c, lon
     const double bih = d4x + 2.0 * dxxyy + d4y;
     const double lap = (mu[w][q + 1] + mu[w][q - 1] - 2.0 * mu[w][q]) * K.inv_dx2 +
                        (mu[w + 1][q] + mu[w - 1][q] - 2.0 * mu[w][q]) * K.inv_dy2;
-    r[(long)j * ldr + i] = -(2.0 / 3.0) * df[w][q] - K.a * bih + K.b * lap;
+    __builtin_nontemporal_store(-(2.0 / 3.0) * dfo[u] - K.a * bih + K.b * lap, &r[(long)j * ldr + i]);
   }
 }
 
@@ -745,13 +828,13 @@ hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, 
   const int Sc = recon ? recon->S : 0;
   const double* rec = recon ? recon->rec : nullptr;
   if (v && recon)
-    hipLaunchKernelGGL((ch2_rhs<true, true>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+    hipLaunchKernelGGL((ch2_rhs<true, true>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
                        cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
   else if (v)
-    hipLaunchKernelGGL((ch2_rhs<true, false>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+    hipLaunchKernelGGL((ch2_rhs<true, false>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
                        cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
   else
-    hipLaunchKernelGGL((ch2_rhs<false, false>), grid, dim3(256), 0, st, c, ld, cp, ldp, v, ldv,
+    hipLaunchKernelGGL((ch2_rhs<false, false>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
                        cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
   return hipGetLastError();
 }
