@@ -417,6 +417,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                (long)blockIdx.x * R, sh);
 }
 
+// Fixed-order sum of dnparts (mass, energy) partial pairs by one block of at
+// least 256 threads: a 256-way split and tree whatever the block size, so the
+// order (and rounding) of the sum never depends on the kernel's tile shape.
+__device__ __forceinline__ void diag_tail_sum(const double* __restrict__ dpart, long dnparts,
+                                              double dscale, double* __restrict__ dout,
+                                              double* sm2) {
+      __syncthreads();
+      constexpr int nt = 256;
+      if ((int)threadIdx.x < nt) {
+        const long per = (dnparts + nt - 1) / nt;
+        const long b0 = (long)threadIdx.x * per;
+        const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
+        double m = 0.0, e = 0.0;
+        long b = b0;
+        for (; b + 8 <= b1; b += 8) {
+          double2 q[8];
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
+  #pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            m += q[u].x;
+            e += q[u].y;
+          }
+        }
+        for (; b < b1; ++b) {
+          m += dpart[2 * b];
+          e += dpart[2 * b + 1];
+        }
+        sm2[threadIdx.x] = m;
+        sm2[nt + threadIdx.x] = e;
+      }
+      __syncthreads();
+      for (int h = nt / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+          sm2[threadIdx.x] += sm2[threadIdx.x + h];
+          sm2[nt + threadIdx.x] += sm2[nt + threadIdx.x + h];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        dout[0] = sm2[0] * dscale;
+        dout[1] = sm2[nt] * dscale;
+      }
+}
+
 // Reduced separator system with an LDS window: a block (W waves) owns 64
 // systems and KB = W G consecutive chunks; it stages rho_j = pa_j - pb_{j+1}
 // for the KB + dcount - 1 chunks its convolutions touch (U window entries
@@ -500,48 +545,7 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
       }
     }
   }
-  if (dout != nullptr) {  // the caller passes dout to one block only
-    // a fixed 256-way split and tree, whatever the block size, so the sum's
-    // order (and rounding) does not depend on the tile shape
-    __syncthreads();
-    double* sm2 = reinterpret_cast<double*>(smraw);
-    constexpr int nt = 256;
-    if ((int)threadIdx.x < nt) {
-      const long per = (dnparts + nt - 1) / nt;
-      const long b0 = (long)threadIdx.x * per;
-      const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
-      double m = 0.0, e = 0.0;
-      long b = b0;
-      for (; b + 8 <= b1; b += 8) {
-        double2 q[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          m += q[u].x;
-          e += q[u].y;
-        }
-      }
-      for (; b < b1; ++b) {
-        m += dpart[2 * b];
-        e += dpart[2 * b + 1];
-      }
-      sm2[threadIdx.x] = m;
-      sm2[nt + threadIdx.x] = e;
-    }
-    __syncthreads();
-    for (int h = nt / 2; h >= 1; h >>= 1) {
-      if ((int)threadIdx.x < h) {
-        sm2[threadIdx.x] += sm2[threadIdx.x + h];
-        sm2[nt + threadIdx.x] += sm2[nt + threadIdx.x + h];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      dout[0] = sm2[0] * dscale;
-      dout[1] = sm2[nt] * dscale;
-    }
-  }
+  if (dout != nullptr) diag_tail_sum(dpart, dnparts, dscale, dout, reinterpret_cast<double*>(smraw));
 }
 
 template <int P, typename T, typename Td, int W, int G, int U>
