@@ -357,9 +357,9 @@ int ch_set_tuning(chx_ch h, int what, int value);
  *   chunked shapes (nx % 64 == 0, ny % 32 == 0; else CHX_EINVAL), sigma = 0
  *   turns it off; step0 is the counter of the next step.  Every step of
  *   ch_adi_step advances the counter, so a run split over several calls
- *   draws the same numbers as one call.  While it is on, ch_ws_bytes grows by
- *   one field (query it again) and the single-workgroup path is not used.
- *   Not for graph capture (the counter is a launch argument).
+ *   draws the same numbers as one call.  The draws are made inside the step
+ *   kernels (no extra workspace), the single-workgroup path included.  Not
+ *   for graph capture (the counter is a launch argument).
  * ch_get_noise_step: the counter of the next step. */
 int ch_set_noise(chx_ch h, double sigma, unsigned long long seed,
                  unsigned long long step0);
@@ -433,9 +433,8 @@ int ch_ensemble_step(chx_ens e, double* const* c_runs, const long* ld_runs,
  *   starting at step0; the draws are those ch_set_noise defines, so run r
  *   gets the same forcing as a single handle given (sigma, seeds[r], step0).
  *   The counter lives on the device and every call of ch_ensemble_step moves
- *   it on by nsteps, graph replays included.  Synchronises the device; makes
- *   one increment field per multi-kernel run on first use (single-workgroup
- *   runs draw their increments on the fly).  CHX_EINVAL for sigma < 0 or
+ *   it on by nsteps, graph replays included (the draws are made inside the
+ *   step kernels).  Synchronises the device.  CHX_EINVAL for sigma < 0 or
  *   not finite, seeds NULL with sigma > 0, or sigma > 0 on an FP32-refined
  *   ensemble.
  * ch_ensemble_get_noise_step: the counter's value after the calls so far. */

@@ -322,13 +322,11 @@ struct chx_ens_s {
   bool refined = false;
   std::vector<chx_ch> rh;
   // Cahn-Hilliard-Cook forcing: counter on the device (so graph replays
-  // advance it), its host mirror, increment fields of the multi-kernel runs
+  // advance it) and its host mirror
   bool noise = false;
   unsigned long long* dnoise = nullptr;
   unsigned long long noise_step = 0;
-  void* qmem = nullptr;
-  int n_ck = 0;
-  long o_ck = 0;
+
   // per-run coarsening measures: Simpson partials, and a batched real-to-
   // complex transform per grid size (made on first use)
   void* mom_mem = nullptr;
@@ -347,7 +345,7 @@ struct chx_ens_s {
     for (auto& g : k1_groups) (void)hipfftDestroy(g.plan);
     if (mom_mem) (void)hipFree(mom_mem);
     if (dnoise) (void)hipFree(dnoise);
-    if (qmem) (void)hipFree(qmem);
+
     if (k1_mem) (void)hipFree(k1_mem);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -407,10 +405,8 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
     if (e == hipSuccess && fork) e = hipEventRecord(E->ev_join, E->side);
   }
   for (int n = 0; E->nbig > 0 && n < nsteps && e == hipSuccess; ++n) {
-    if (E->noise) e = launch_ens_cook_increment(E->druns, it + E->o_ck, E->n_ck, E->dnoise, n, st);
-    if (e == hipSuccess)
-      e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->noise, E->druns, E->hcls,
-                                 it + E->o_col, E->n_col, ws, n, st);
+    e = launch_ens_column_pass(n > 0, diag_out != nullptr, E->noise ? E->dnoise : nullptr,
+                               E->druns, E->hcls, it + E->o_col, E->n_col, ws, n, st);
     if (e == hipSuccess)
       e = launch_ens_reduced(E->druns, E->hcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
                              E->red_lds, st);
@@ -838,11 +834,8 @@ int ch_destroy(chx_ch h) {
   return CHX_OK;
 }
 
-// The Cook forcing needs one more field (its increment) after the rest.
-static size_t ws_need(const chx_ch_s* h) {
-  return h->ws_total +
-         (h->sigma > 0 ? align256((size_t)h->prm.nx * h->prm.ny * sizeof(double)) : 0);
-}
+// The Cook forcing is drawn inside the kernels: no extra workspace.
+static size_t ws_need(const chx_ch_s* h) { return h->ws_total; }
 
 size_t ch_ws_bytes(chx_ch h) { return h ? ws_need(h) : 0; }
 
@@ -897,7 +890,13 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
   auto* base = static_cast<unsigned char*>(ws);
   double* part = reinterpret_cast<double*>(base + h->off_part);
-  double* qnoise = h->sigma > 0 ? reinterpret_cast<double*>(base + h->ws_total) : nullptr;
+  const bool noise = h->sigma > 0;
+  // the forcing's draw parameters of step k of this call
+  auto noise_of = [&](int k) {
+    const double dx = h->prm.lx / nx, dy = h->prm.ly / ny;
+    return SmallNoise{chx_sm_mix(h->noise_seed), h->noise_step + (unsigned long long)k,
+                      h->prm.dt * std::sqrt(h->sigma / (dx * dy * h->prm.dt)), 1.0 / dx, 1.0 / dy};
+  };
   hipError_t e = hipSuccess;
   auto ok = [&]() { return e == hipSuccess; };
   auto B = [&]() { if (tm) tm->begin(); };
@@ -950,16 +949,11 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     // one workgroup, field resident in LDS for all steps; it also writes the
     // diagnostics of every state, the final one included
     B();
-    SmallNoise nz{};
-    if (qnoise) {
-      const double dx = h->prm.lx / nx, dy = h->prm.ly / ny;
-      nz = SmallNoise{chx_sm_mix(h->noise_seed), h->noise_step,
-                      h->prm.dt * std::sqrt(h->sigma / (dx * dy * h->prm.dt)), 1.0 / dx, 1.0 / dy};
-    }
+    const SmallNoise nz = noise_of(0);
     e = launch_ch_small_steps(c, ld, nx, ny, nsteps, h->py->dchunk, h->px->dchunk, h->K, diag_out,
-                              qnoise ? &nz : nullptr, st);
+                              noise ? &nz : nullptr, st);
     E(0);
-    if (ok() && qnoise) h->noise_step += (unsigned long long)nsteps;
+    if (ok() && noise) h->noise_step += (unsigned long long)nsteps;
     if (tm && tm->failed) return CHX_EHIP;
     return ok() ? CHX_OK : CHX_EHIP;
   } else if (h->fast) {
@@ -973,16 +967,11 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     for (int n = 0; n < nsteps && ok(); ++n) {
       double* dst = buf[n & 1];
       const bool diag = diag_out != nullptr;
-      if (qnoise) {  // Cahn-Hilliard-Cook increment of this step
-        B();
-        e = launch_ch_cook_increment(qnoise, nx, ny, h->prm.lx / nx, h->prm.ly / ny, h->prm.dt,
-                                     h->sigma, h->noise_seed, h->noise_step + n, st);
-        E(0);
-      }
       if (ok()) {
         B();
+        const SmallNoise nz = noise_of(n);  // Cahn-Hilliard-Cook draws of this step
         e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho,
-                                  h->K, part, st, qnoise);
+                                  h->K, part, st, noise ? &nz : nullptr);
         E(0);
       }
       if (ok() && h->split >= 0) {
@@ -1057,7 +1046,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
     E(3);
   }
-  if (ok() && qnoise) h->noise_step += (unsigned long long)nsteps;
+  if (ok() && noise) h->noise_step += (unsigned long long)nsteps;
   if (tm && tm->failed) return CHX_EHIP;
   return ok() ? CHX_OK : CHX_EHIP;
 }
@@ -1279,7 +1268,6 @@ static int ens_create_refined(chx_ens_s* E) {
     R.cls = cls;
     R.ncb = R.Sc = R.ndbx = R.ndby = 0;
     R.ncolblocks = 0;
-    R.q = nullptr;
     R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
     R.nseed = 0;
   }
@@ -1396,7 +1384,6 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     R.ndbx = (q.nx + 63) / 64;
     R.ndby = (q.ny + 15) / 16;
     R.ncolblocks = (long)R.ncb * R.Sc;
-    R.q = nullptr;
     R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
     R.nseed = 0;
     E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
@@ -1443,11 +1430,7 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     for (int by = 0; by < E->runs[r].ndby; ++by)
       for (int bx = 0; bx < E->runs[r].ndbx; ++bx) add(r, bx, by);
   E->n_dpart = (int)(items.size() - E->o_dpart);
-  E->o_ck = (long)items.size();
-  for (int r : order)
-    for (int by = 0; by < (E->runs[r].ny + 15) / 16; ++by)
-      for (int bx = 0; bx < (E->runs[r].nx + 63) / 64; ++bx) add(r, bx, by);
-  E->n_ck = (int)(items.size() - E->o_ck);
+
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
   const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
@@ -1587,16 +1570,6 @@ int ch_ensemble_set_noise(chx_ens E, double sigma, const unsigned long long* see
       E->dnoise = nullptr;
       return CHX_ENOMEM;
     }
-    if (!E->qmem && E->nbig > 0) {
-      size_t bytes = 0;
-      for (const auto& R : E->runs)
-        if (R.off_b0 != R.off_b1) bytes += align256((size_t)R.nx * R.ny * sizeof(double));
-      if (hipMalloc(&E->qmem, bytes) != hipSuccess) {
-        E->qmem = nullptr;
-        return CHX_ENOMEM;
-      }
-    }
-    size_t off = 0;
     for (int r = 0; r < E->nruns; ++r) {
       EnsRun& R = E->runs[r];
       const chx_ch_params& q = E->prm[r];
@@ -1605,11 +1578,6 @@ int ch_ensemble_set_noise(chx_ens E, double sigma, const unsigned long long* see
       R.ninv_dx = 1.0 / dx;
       R.ninv_dy = 1.0 / dy;
       R.nseed = chx_sm_mix(seeds[r]);
-      R.q = nullptr;
-      if (R.off_b0 != R.off_b1) {  // a multi-kernel run: its increment field
-        R.q = reinterpret_cast<double*>(static_cast<unsigned char*>(E->qmem) + off);
-        off += align256((size_t)R.nx * R.ny * sizeof(double));
-      }
     }
     if (hipMemcpy(E->dnoise, &step0, sizeof(step0), hipMemcpyHostToDevice) != hipSuccess)
       return CHX_EHIP;

@@ -88,20 +88,46 @@ __device__ __forceinline__ double recon_row(double v, int q, const double* __res
   return recon_value<RECON>(v, q - 1, rec, tp, to);
 }
 
+// Cahn-Hilliard-Cook forcing (Ch.7): q = dt eta, eta = amp div rho with
+// amp = sqrt(sigma / (dx dy dt)), rho = (rho_x, rho_y) N(0,1) per point and
+// step by Box-Muller from two counter-based SplitMix64 uniforms (Steele, Lea
+// and Flood 2014; output k of the sequence whose state starts at mix(seed),
+// u = ((out >> 11) + 1/2) 2^-53, k = ((step ny + j) nx + i) 2 + component),
+// forward-difference divergence.  The kernels that add it draw rho where
+// they form the right-hand side (no increment field in memory).
+// One N(0,1) pair (rho_x, rho_y) of point (i, j) at step `step`.
+__device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigned long long step,
+                                          int j, int i, int nx, int ny, double& rx, double& ry) {
+  const unsigned long long k =
+      ((step * (unsigned long long)ny + (unsigned long long)j) * (unsigned long long)nx +
+       (unsigned long long)i) * 2ULL;
+  const unsigned long long z1 = chx_sm_mix(seed_state + (k + 1) * 0x9E3779B97F4A7C15ULL);
+  const unsigned long long z2 = chx_sm_mix(seed_state + (k + 2) * 0x9E3779B97F4A7C15ULL);
+  const double u1 = ((double)(z1 >> 11) + 0.5) * 0x1.0p-53;
+  const double u2 = ((double)(z2 >> 11) + 0.5) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2 without a general range reduction
+  rx = rad * cs;
+  ry = rad * sn;
+}
+
 // Body shared by the single-field kernel and the ensemble kernel: column
 // block cb (256 columns), chunk kc; slot = where this block's (mass, energy)
-// partial goes (DIAG only); NOISE adds the forcing increment q (pitch nx) to
-// the right-hand side.
+// partial goes (DIAG only); NOISE adds the Cahn-Hilliard-Cook increment of
+// step nz.step0, drawn here: each thread carries its column's pair down the
+// rows and takes the right neighbour's rho_x from the next lane (the wave's
+// last lane from LDS, drawn before the barrier).
 template <bool RECON, bool DIAG, bool NOISE = false>
 __device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
                                                  double* __restrict__ ybuf, long ldy, int nx,
                                                  int ny, int Sc, const double* __restrict__ rec,
                                                  const BandT<double>& bd, double* __restrict__ rho,
                                                  const ChCoef& K, double* __restrict__ slot,
-                                                 int cb, int kc,
-                                                 const double* __restrict__ q = nullptr) {
+                                                 int cb, int kc, const SmallNoise& nz = {}) {
   __shared__ double red[8];
   __shared__ double edge[10][M + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
+  __shared__ double nedge[NOISE ? 4 : 1][M];  // rho_x right of wave w's last lane
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nseg = nx >> 6;
   const int seg0 = cb * 4;
@@ -129,6 +155,12 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
       v = recon_row<RECON>(v, q, rec, tp, to, tn);
     }
     edge[side][q] = v;
+  }
+  if (NOISE && (int)threadIdx.x < nw * M) {
+    const int w = threadIdx.x / M, p = threadIdx.x - w * M;
+    double rx, ry;
+    cook_pair(nz.seed_state, nz.step0, kc * M + p, ((seg0 + w + 1) * 64) % nx, nx, ny, rx, ry);
+    nedge[w][p] = rx;
   }
 
   double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
@@ -173,6 +205,8 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
     double xl_m = dpp_from_left(xc_m, es[0]), xr_m = dpp_from_right(xc_m, es[0]);
     double xc_c = X[1];
     double xl_c = dpp_from_left(xc_c, es[1]), xr_c = dpp_from_right(xc_c, es[1]);
+    double nrx = 0.0, nry = 0.0;  // this column's forcing pair at the current row
+    if (NOISE) cook_pair(nz.seed_state, nz.step0, kc * M, i, nx, ny, nrx, nry);
 #pragma unroll
     for (int p = 0; p < M; ++p) {
       double xc_p = X[p + 2];
@@ -190,7 +224,16 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
       const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
       const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
       double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
-      if (NOISE) r = r + q[((long)kc * M + p) * nx + i];
+      if (NOISE) {
+        const int j = kc * M + p, jn = (j + 1 == ny) ? 0 : j + 1;
+        double rx_n, ry_n;
+        cook_pair(nz.seed_state, nz.step0, jn, i, nx, ny, rx_n, ry_n);
+        const double rx_e = dpp_from_right(nrx, nedge[wave][p]);
+        const double div = (rx_e - nrx) * nz.inv_dx + (ry_n - nry) * nz.inv_dy;
+        r = r + nz.scale * div;
+        nrx = rx_n;
+        nry = ry_n;
+      }
       if (DIAG) {
         const double w = xc_c * xc_c - 1.0;
         const double gx = (xr_c - xc_c) * K.inv_dx, gy = (xc_p - xc_c) * K.inv_dy;
@@ -245,84 +288,13 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
                                                       const double* __restrict__ rec,
                                                       BandT<double> bd, double* __restrict__ rho,
                                                       ChCoef K, double* __restrict__ part,
-                                                      const double* __restrict__ q) {
+                                                      SmallNoise nz) {
   const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
   column_pass_body<RECON, DIAG, NOISE>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
-                                       DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y, q);
+                                       DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y, nz);
 }
 
 // ---------------------------------------------------------------------------
-// Cahn-Hilliard-Cook forcing (Ch.7): q = dt eta, eta = amp div rho with
-// amp = sqrt(sigma / (dx dy dt)), rho = (rho_x, rho_y) N(0,1) per point and
-// step by Box-Muller from two counter-based SplitMix64 uniforms (Steele, Lea
-// and Flood 2014; output k of the sequence whose state starts at mix(seed),
-// u = ((out >> 11) + 1/2) 2^-53, k = ((step ny + j) nx + i) 2 + component),
-// forward-difference divergence.  A block draws rho for its 16 x 64 tile and
-// the row and column after it into LDS once, then differences.
-constexpr int kCkX = 64, kCkY = 16;
-
-// One N(0,1) pair (rho_x, rho_y) of point (i, j) at step `step`.
-__device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigned long long step,
-                                          int j, int i, int nx, int ny, double& rx, double& ry) {
-  const unsigned long long k =
-      ((step * (unsigned long long)ny + (unsigned long long)j) * (unsigned long long)nx +
-       (unsigned long long)i) * 2ULL;
-  const unsigned long long z1 = chx_sm_mix(seed_state + (k + 1) * 0x9E3779B97F4A7C15ULL);
-  const unsigned long long z2 = chx_sm_mix(seed_state + (k + 2) * 0x9E3779B97F4A7C15ULL);
-  const double u1 = ((double)(z1 >> 11) + 0.5) * 0x1.0p-53;
-  const double u2 = ((double)(z2 >> 11) + 0.5) * 0x1.0p-53;
-  const double rad = sqrt(-2.0 * log(u1));
-  double sn, cs;
-  sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2 without a general range reduction
-  rx = rad * cs;
-  ry = rad * sn;
-}
-
-// The increment of the tile (bx, by) of one field (pitch nx).
-__device__ __forceinline__ void cook_tile_body(double* __restrict__ q, int nx, int ny,
-                                               double inv_dx, double inv_dy, double scale,
-                                               unsigned long long seed_state,
-                                               unsigned long long step, int bx, int by) {
-  __shared__ double rx[kCkY + 1][kCkX + 1];
-  __shared__ double ry[kCkY + 1][kCkX + 1];
-  const int i0 = bx * kCkX, j0 = by * kCkY;
-  for (int e = threadIdx.x; e < (kCkY + 1) * (kCkX + 1); e += 256) {
-    const int tr = e / (kCkX + 1), tc = e - tr * (kCkX + 1);
-    int j = j0 + tr, i = i0 + tc;
-    j -= (j >= ny) ? ny : 0;
-    i -= (i >= nx) ? nx : 0;
-    cook_pair(seed_state, step, j, i, nx, ny, rx[tr][tc], ry[tr][tc]);
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int i = i0 + tx;
-  if (i >= nx) return;
-#pragma unroll
-  for (int u = 0; u < kCkY / 4; ++u) {
-    const int r = ty + 4 * u, j = j0 + r;
-    if (j >= ny) break;
-    const double div = (rx[r][tx + 1] - rx[r][tx]) * inv_dx + (ry[r + 1][tx] - ry[r][tx]) * inv_dy;
-    q[(long)j * nx + i] = scale * div;
-  }
-}
-
-__global__ __launch_bounds__(256) void ch_cook_increment(double* __restrict__ q, int nx, int ny,
-                                                         double inv_dx, double inv_dy,
-                                                         double scale,
-                                                         unsigned long long seed_state,
-                                                         unsigned long long step) {
-  cook_tile_body(q, nx, ny, inv_dx, inv_dy, scale, seed_state, step, blockIdx.x, blockIdx.y);
-}
-
-hipError_t launch_ch_cook_increment(double* q, int nx, int ny, double dx, double dy, double dt,
-                                   double sigma, unsigned long long seed,
-                                   unsigned long long step, hipStream_t st) {
-  dim3 grid((nx + kCkX - 1) / kCkX, (ny + kCkY - 1) / kCkY);
-  const double scale = dt * sqrt(sigma / (dx * dy * dt));
-  hipLaunchKernelGGL(ch_cook_increment, grid, dim3(256), 0, st, q, nx, ny, 1.0 / dx, 1.0 / dy,
-                     scale, chx_sm_mix(seed), step);
-  return hipGetLastError();
-}
 
 // State X = V - Zl T_prev - Zr T_own written out to the caller's array;
 // block (bx, by) covers 64 columns x 4 rows.
@@ -497,15 +469,16 @@ hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
                                  double* rho, const ChCoef& K, double* part, hipStream_t st,
-                                 const double* q) {
+                                 const SmallNoise* nz) {
   BandT<double> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
   dim3 grid(((nx >> 6) + 3) / 4, cy.S);
   const int Sc = cy.S;
+  const SmallNoise z = nz ? *nz : SmallNoise{};
 #define CHX_COLPASS(R, D, N)                                                                      \
   hipLaunchKernelGGL((ch_column_pass<R, D, N>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
-                     ny, Sc, cy.rec, bd, rho, K, part, q)
-  if (q) {
+                     ny, Sc, cy.rec, bd, rho, K, part, z)
+  if (nz) {
     if (recon && diag) CHX_COLPASS(true, true, true);
     else if (recon) CHX_COLPASS(true, false, true);
     else if (diag) CHX_COLPASS(false, true, true);
@@ -1156,7 +1129,8 @@ template <bool RECON, bool DIAG, bool NOISE>
 __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict__ runs,
                                                        EnsClasses cls,
                                                        const int4* __restrict__ items,
-                                                       unsigned char* ws, int step) {
+                                                       unsigned char* ws, int step,
+                                                       const unsigned long long* noise_step) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
   const EnsClass& C = cls.c[R.cls];
@@ -1170,19 +1144,11 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   column_pass_body<RECON, DIAG, NOISE>(src, lds, ens_buf(ws, R, step), R.nx, R.nx, R.ny, R.Sc,
                                        C.py.rec, bd, rho, C.K,
                                        DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
-                                       it.y, it.z, R.q);
-}
-
-// Forcing increments of the ensemble's multi-kernel runs for step
-// (*noise_step + n); item {run, tile x, tile y}.
-__global__ __launch_bounds__(256) void ens_cook_increment(const EnsRun* __restrict__ runs,
-                                                          const int4* __restrict__ items,
-                                                          const unsigned long long* noise_step,
-                                                          int n) {
-  const int4 it = items[blockIdx.x];
-  const EnsRun R = runs[it.x];
-  cook_tile_body(R.q, R.nx, R.ny, R.ninv_dx, R.ninv_dy, R.nscale, R.nseed,
-                 *noise_step + (unsigned long long)n, it.y, it.z);
+                                       it.y, it.z,
+                                       NOISE ? SmallNoise{R.nseed,
+                                                          *noise_step + (unsigned long long)step,
+                                                          R.nscale, R.ninv_dx, R.ninv_dy}
+                                             : SmallNoise{});
 }
 
 // The ensemble's forcing counter moves on by the steps of one call (one
@@ -1255,25 +1221,18 @@ hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, con
   return hipGetLastError();
 }
 
-hipError_t launch_ens_cook_increment(const EnsRun* runs, const int4* items, int nitems,
-                                     const unsigned long long* noise_step, int n,
-                                     hipStream_t st) {
-  hipLaunchKernelGGL(ens_cook_increment, dim3(nitems), dim3(256), 0, st, runs, items, noise_step,
-                     n);
-  return hipGetLastError();
-}
-
 hipError_t launch_ens_noise_advance(unsigned long long* noise_step, int nsteps, hipStream_t st) {
   hipLaunchKernelGGL(ens_noise_advance, dim3(1), dim3(64), 0, st, noise_step, nsteps);
   return hipGetLastError();
 }
 
-hipError_t launch_ens_column_pass(bool recon, bool diag, bool noise, const EnsRun* runs,
-                                  const EnsClasses& cls, const int4* items, int nitems,
-                                  unsigned char* ws, int step, hipStream_t st) {
+hipError_t launch_ens_column_pass(bool recon, bool diag, const unsigned long long* noise_step,
+                                  const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                                  int nitems, unsigned char* ws, int step, hipStream_t st) {
+  const bool noise = noise_step != nullptr;
 #define CHX_ENSCOL(R, D, N)                                                                        \
   hipLaunchKernelGGL((ens_column_pass<R, D, N>), dim3(nitems), dim3(256), 0, st, runs, cls, items, \
-                     ws, step)
+                     ws, step, noise_step)
 #define CHX_ENSCOL2(R, D) \
   if (noise) CHX_ENSCOL(R, D, true); else CHX_ENSCOL(R, D, false)
   if (recon && diag) { CHX_ENSCOL2(true, true); }

@@ -36,14 +36,19 @@ hipError_t launch_ch2_update(const double* c, long ldc, const double* cp, long l
 
 // q != nullptr: the Cahn-Hilliard-Cook increment (pitch nx) is added to the
 // right-hand side.
+// Cahn-Hilliard-Cook forcing drawn inside a kernel: generator state
+// mix(seed), the counter step (of the call's first step for the
+// single-workgroup kernel, of the pass otherwise), dt amp, 1/dx, 1/dy.
+struct SmallNoise {
+  unsigned long long seed_state, step0;
+  double scale, inv_dx, inv_dy;
+};
+
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
                                  double* rho, const ChCoef& K, double* part, hipStream_t st,
-                                 const double* q = nullptr);
+                                 const SmallNoise* nz = nullptr);
 // q = dt eta of the Cahn-Hilliard-Cook forcing for counter `step` (pitch nx).
-hipError_t launch_ch_cook_increment(double* q, int nx, int ny, double dx, double dy, double dt,
-                                   double sigma, unsigned long long seed,
-                                   unsigned long long step, hipStream_t st);
 long ch_column_pass_blocks(int nx, int Sc);
 hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
                               const DevChunk& cy, hipStream_t st);
@@ -68,12 +73,6 @@ hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long
 constexpr int kSmallMaxThreads = 512;
 size_t ch_small_lds_bytes(int nx, int ny);
 bool ch_small_fits(int nx, int ny, size_t max_lds);
-// Forcing of the single-workgroup step (Cahn-Hilliard-Cook): generator state
-// mix(seed), counter step of the call's first step, dt amp, 1/dx, 1/dy.
-struct SmallNoise {
-  unsigned long long seed_state, step0;
-  double scale, inv_dx, inv_dy;
-};
 hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps,
                                  const DevChunk& cy, const DevChunk& cx, const ChCoef& K,
                                  double* diag, const SmallNoise* nz, hipStream_t st);

@@ -22,9 +22,8 @@ struct EnsRun {
   int ncb, Sc;             // column-pass blocks per chunk row, column chunks
   int ndbx, ndby;          // diagnostic-partial blocks (64 x 16 points each)
   long ncolblocks;         // column-pass blocks = ncb * Sc
-  // Cahn-Hilliard-Cook forcing (set by ch_ensemble_set_noise): increment
-  // field (multi-kernel runs), dt amp, 1/dx, 1/dy, generator state mix(seed)
-  double* q;
+  // Cahn-Hilliard-Cook forcing (set by ch_ensemble_set_noise): dt amp,
+  // 1/dx, 1/dy, generator state mix(seed)
   double nscale, ninv_dx, ninv_dy;
   unsigned long long nseed;
 };
@@ -41,14 +40,12 @@ struct EnsClasses {
 };
 
 // Work items are int4 {run, a, b, 0}.
-hipError_t launch_ens_column_pass(bool recon, bool diag, bool noise, const EnsRun* runs,
-                                  const EnsClasses& cls, const int4* items, int nitems,
-                                  unsigned char* ws, int step, hipStream_t st);
-// Forcing increments of step (*noise_step + n); items {run, tile x, tile y}
-// over 64 x 16 tiles; and the counter's advance by nsteps after a call.
-hipError_t launch_ens_cook_increment(const EnsRun* runs, const int4* items, int nitems,
-                                     const unsigned long long* noise_step, int n,
-                                     hipStream_t st);
+// noise_step: NULL, or the device counter of a forced ensemble (step
+// *noise_step + step is drawn inside the pass).
+hipError_t launch_ens_column_pass(bool recon, bool diag, const unsigned long long* noise_step,
+                                  const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                                  int nitems, unsigned char* ws, int step, hipStream_t st);
+// The forcing counter's advance by nsteps after a call.
 hipError_t launch_ens_noise_advance(unsigned long long* noise_step, int nsteps, hipStream_t st);
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,

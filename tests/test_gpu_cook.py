@@ -71,7 +71,7 @@ def test_zero_intensity_is_the_unforced_step(chx):
     chx.ch_adi_step(h, plain, nsteps=3)
     w0 = chx.ch_ws_bytes(h)
     chx.ch_set_noise(h, 1e-10, seed=1)
-    assert chx.ch_ws_bytes(h) > w0
+    assert chx.ch_ws_bytes(h) == w0  # the draws are made inside the kernels
     chx.ch_set_noise(h, 0.0)
     assert chx.ch_ws_bytes(h) == w0
     again = torch.tensor(c0, device="cuda")
