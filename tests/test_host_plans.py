@@ -273,3 +273,16 @@ def test_per_system_batch_workspace_and_argument_checks(lib):
     assert lib.penta_batch_rewrite(8, 8, 1, *p[:5], 8, p[5], ws, need - 8, None) == chx.CHX_ENOMEM
     need = chx.tri_batch_ws_bytes(8, 8, True, F)
     assert lib.tri_batch_solve(8, 8, 1, *p[:3], 8, ws, need - 8, p[5], None) == chx.CHX_ENOMEM
+
+
+def test_ensemble_extras_reject_bad_arguments_on_host(lib):
+    """The ensemble's forcing and per-run measures check their arguments before
+    any device work."""
+    import ctypes
+    u = ctypes.c_uint64()
+    d = (ctypes.c_double * 3)()
+    assert lib.ch_ensemble_set_noise(None, 1e-10, None, 0) == chx.CHX_EINVAL
+    assert lib.ch_ensemble_get_noise_step(None, ctypes.byref(u)) == chx.CHX_EINVAL
+    assert lib.ch_ensemble_moments(None, None, None, d, None) == chx.CHX_EINVAL
+    assert lib.ch_ensemble_k1(None, None, None, d, None) == chx.CHX_EINVAL
+    assert lib.ch_ensemble_step(None, None, None, 1, None, None, 0, 0, None) == chx.CHX_EINVAL
