@@ -1095,8 +1095,12 @@ int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, doub
   // v = L_y^{-1} L_x^{-1} r in place: columns (interleaved), then rows
   // (chunked columns: the chunk correction is left to whoever reads r next)
   const DevChunk* recon = col_chunk ? &h->py->dchunk : nullptr;
+  // with chunked columns the right-hand-side kernel has already run the
+  // column chunk sweep (y in r, separator parts in rho)
+  const DevChunk* sweep = col_chunk ? &h->py->dchunk : nullptr;
   auto solve_in_place = [&](double* r) {
-    hipError_t e2 = col_chunk ? launch_chunked_il<2>(h->py->dchunk, r, nx, nx, rho, st, false)
+    hipError_t e2 = col_chunk ? launch_reduced_il<2>(h->py->dchunk, rho, nx, r, nx, kChunk,
+                                                     kChunk - 2, st)
                               : launch_whole<2>(h->py->dwhole, r, 1, nx, nx, st);
     if (e2 == hipSuccess)
       e2 = row_lds ? launch_rows_lds<2>(h->px->dchunk, r, nx, ny, st)
@@ -1114,13 +1118,13 @@ int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, doub
   if (diag_out) e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out, st);
   if (e == hipSuccess)
     e = launch_ch2_rhs(c, ld, cprev, ld, nullptr, 0, nullptr, 0, rbuf[0], nx, nx, ny, h->K2,
-                       nullptr, st);
+                       nullptr, sweep, rho, st);
   if (e == hipSuccess) e = solve_in_place(rbuf[0]);
   for (int n = 1; n < nsteps && e == hipSuccess; ++n) {
     double* rv = rbuf[(n - 1) & 1];
     double* rn = rbuf[n & 1];
     e = launch_ch2_rhs(cur.p, cur.ld, prev.p, prev.ld, rv, nx, spare.p, spare.ld, rn, nx, nx, ny,
-                       h->K2, recon, st);
+                       h->K2, recon, sweep, rho, st);
     if (e == hipSuccess && diag_out)
       e = launch_ch_diag(spare.p, spare.ld, nx, ny, h->K, part, diag_out + 2 * n, st);
     const Buf old_prev = prev;

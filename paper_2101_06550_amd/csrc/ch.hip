@@ -640,13 +640,21 @@ __device__ __forceinline__ double ch2_recon(const double* __restrict__ v, long l
   return x;
 }
 
-template <bool UPD, bool RECON>
+// SWEEP: the tile is one 32-row column chunk, so the block also runs that
+// chunk's column sweep: r goes to LDS (over the staged tile) instead of
+// memory, one wave sweeps the 64 columns and writes the chunk interiors y
+// into r and the separator parts into rho, as the interleaved chunk sweep
+// would (same helpers, same arithmetic).
+static_assert(kT2Y == M, "a fused column sweep needs one chunk per tile");
+template <bool UPD, bool RECON, bool SWEEP>
 __global__ __launch_bounds__(kT2T) void ch2_rhs(const double* __restrict__ c, long ld,
                                                 const double* __restrict__ cp, long ldp,
                                                 const double* __restrict__ v, long ldv,
                                                 double* __restrict__ cnew, long ldn,
                                                 double* __restrict__ r, long ldr, int nx, int ny,
-                                                Ch2Coef K, int Sc, const double* __restrict__ rec) {
+                                                Ch2Coef K, int Sc, const double* __restrict__ rec,
+                                                const double* __restrict__ srec, BandT<double> sbd,
+                                                double* __restrict__ rhop) {
   __shared__ double cb[kT2R][kT2W];
   __shared__ double mu[kT2R][kT2W];
   // RECON: the separator rows of the chunks kb-2 .. kb+1 (kb = the chunk of
@@ -756,12 +764,13 @@ __global__ __launch_bounds__(kT2T) void ch2_rhs(const double* __restrict__ c, lo
   }
   __syncthreads();
   const int i = i0 + tx;
-  if (i >= nx) return;
   const int q = tx + kT2H;
+  double rv[kRows];
 #pragma unroll
   for (int u = 0; u < kRows; ++u) {
     const int j = j0 + ty + (kT2T / 64) * u;
-    if (j >= ny) break;
+    rv[u] = 0.0;
+    if (i >= nx || j >= ny) continue;
     const int w = ty + (kT2T / 64) * u + kT2H;
     const double d4x = (cb[w][q - 2] - 4.0 * cb[w][q - 1] + 6.0 * cb[w][q] - 4.0 * cb[w][q + 1] +
                         cb[w][q + 2]) * K.inv_dx4;
@@ -774,7 +783,31 @@ __global__ __launch_bounds__(kT2T) void ch2_rhs(const double* __restrict__ c, lo
     const double bih = d4x + 2.0 * dxxyy + d4y;
     const double lap = (mu[w][q + 1] + mu[w][q - 1] - 2.0 * mu[w][q]) * K.inv_dx2 +
                        (mu[w + 1][q] + mu[w - 1][q] - 2.0 * mu[w][q]) * K.inv_dy2;
-    __builtin_nontemporal_store(-(2.0 / 3.0) * dfo[u] - K.a * bih + K.b * lap, &r[(long)j * ldr + i]);
+    rv[u] = -(2.0 / 3.0) * dfo[u] - K.a * bih + K.b * lap;
+    if (!SWEEP) __builtin_nontemporal_store(rv[u], &r[(long)j * ldr + i]);
+  }
+  if (SWEEP) {
+    __syncthreads();  // every read of the staged tile is done
+    double* rt = &cb[0][0];  // r of the chunk: row p at rt[p * kT2W + column]
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) rt[(ty + (kT2T / 64) * u) * kT2W + tx] = rv[u];
+    __syncthreads();
+    if (ty == 0 && i < nx) {
+      double f[M];
+#pragma unroll
+      for (int p = 0; p < M; ++p) f[p] = rt[p * kT2W + tx];
+      chunk_sweep<P, M, double>(f, srec, sbd.c[0]);
+      double pa[P], pb[P];
+      chunk_parts<P, M, double>(f, sbd, pa, pb);
+#pragma unroll
+      for (int p = 0; p < MI; ++p) __builtin_nontemporal_store(f[p], &r[(long)(j0 + p) * ldr + i]);
+      const int kc = j0 / M;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        rhop[((long)kc * 2 * P + a) * nx + i] = pa[a];
+        rhop[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+      }
+    }
   }
 }
 
@@ -796,19 +829,30 @@ __global__ __launch_bounds__(256) void ch2_update(const double* c, long ldc, con
 
 hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, const double* v,
                           long ldv, double* cnew, long ldn, double* r, long ldr, int nx, int ny,
-                          const Ch2Coef& K, const DevChunk* recon, hipStream_t st) {
+                          const Ch2Coef& K, const DevChunk* recon, const DevChunk* sweep,
+                          double* rho, hipStream_t st) {
   dim3 grid((nx + kT2X - 1) / kT2X, (ny + kT2Y - 1) / kT2Y);
   const int Sc = recon ? recon->S : 0;
   const double* rec = recon ? recon->rec : nullptr;
-  if (v && recon)
-    hipLaunchKernelGGL((ch2_rhs<true, true>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
-                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
-  else if (v)
-    hipLaunchKernelGGL((ch2_rhs<true, false>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
-                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
-  else
-    hipLaunchKernelGGL((ch2_rhs<false, false>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv,
-                       cnew, ldn, r, ldr, nx, ny, K, Sc, rec);
+  BandT<double> sbd{};
+  const double* srec = nullptr;
+  if (sweep) {
+    for (int k = 0; k < 5; ++k) sbd.c[k] = sweep->coef[k];
+    srec = sweep->rec;
+  }
+#define CHX_CH2(U, R, W)                                                                        \
+  hipLaunchKernelGGL((ch2_rhs<U, R, W>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv, cnew, \
+                     ldn, r, ldr, nx, ny, K, Sc, rec, srec, sbd, rho)
+  if (sweep) {
+    if (v && recon) CHX_CH2(true, true, true);
+    else if (v) CHX_CH2(true, false, true);
+    else CHX_CH2(false, false, true);
+  } else {
+    if (v && recon) CHX_CH2(true, true, false);
+    else if (v) CHX_CH2(true, false, false);
+    else CHX_CH2(false, false, false);
+  }
+#undef CHX_CH2
   return hipGetLastError();
 }
 

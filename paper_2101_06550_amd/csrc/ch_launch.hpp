@@ -24,10 +24,14 @@ struct Ch2Coef {
 // Right-hand side r of the delta-form step from (C, Cp) (v == nullptr), or,
 // with v, from (C_new, C) where C_new = 2C - Cp + v is also written to cnew
 // (which must not alias c, cp, v or r).  recon != nullptr: v still needs the
-// column-chunk correction of that plan (applied as v is read).
+// column-chunk correction of that plan (applied as v is read).  sweep !=
+// nullptr (a chunked column plan, ny a multiple of 32): the kernel also runs
+// the column chunk sweep, leaving the chunk interiors y in r and the
+// separator parts in rho ([S][4][nx]) for the separator kernel.
 hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, const double* v,
                           long ldv, double* cnew, long ldn, double* r, long ldr, int nx, int ny,
-                          const Ch2Coef& K, const DevChunk* recon, hipStream_t st);
+                          const Ch2Coef& K, const DevChunk* recon, const DevChunk* sweep,
+                          double* rho, hipStream_t st);
 // out = 2C - Cp + v, out_prev = C, elementwise (outputs may alias inputs);
 // recon as above.
 hipError_t launch_ch2_update(const double* c, long ldc, const double* cp, long ldp,
