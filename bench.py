@@ -177,6 +177,43 @@ def summarize_trace(trace_dir, out_path, command, note):
     return {k: sum(v) / len(v) for k, v in stats.items()}
 
 
+def summarize_leg(trace_dir, out_path, title, command, note):
+    """Per-kernel duration statistics of every dispatch of a rocprofv3
+    --kernel-trace run of one side measurement (`bench.py --only ...`)."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(trace_dir):
+        for f in files:
+            if f.endswith("kernel_trace.csv"):
+                with open(os.path.join(root, f)) as fh:
+                    rows += list(csv.DictReader(fh))
+    def short(raw):
+        sig = raw.split("(")[0].replace("void ", "").strip()
+        if sig.startswith("chx::"):  # this library: keep the template arguments
+            return sig[len("chx::"):]
+        base = sig.split("<")[0].split("::")[-1]
+        return base or raw[:60]
+
+    stats = {}
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        stats.setdefault(name, []).append(d)
+    total = sum(sum(v) for v in stats.values())
+    lines = [f"# Kernel trace: {title}", "",
+             "Command (run from the repository root on one MI355X):", "", "    " + command, "",
+             "Summarised with `python bench.py --summarize-leg <trace dir> <this file> ...` over "
+             "every dispatch of the run (handle creation, warm-up and timed calls).", "",
+             note, "",
+             "| Kernel | Calls | Total ns | Average ns | % | Min ns | Max ns |",
+             "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1]))[:16]:
+        lines.append(f"| {name} | {len(v)} | {sum(v)} | {sum(v) / len(v):.1f} | "
+                     f"{100.0 * sum(v) / total:.2f} | {min(v)} | {max(v)} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def stored_traffic(kernel):
     """Bytes per dispatch of `kernel` from the committed profile, or None if
     the profile is absent or was taken on different sources."""
@@ -668,7 +705,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
-    ap.add_argument("--only", choices=["solves", "ensemble", "precision", "small", "tuning", "p2",
+    ap.add_argument("--only", choices=["solves", "per_system", "ensemble", "precision", "small",
+                                       "tuning", "p2",
                                        "table31", "batch1d", "cook"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -677,6 +715,9 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace run into the kernel profile")
     ap.add_argument("--trace-note", default="",
                     help="text added to the kernel profile (--summarize-trace)")
+    ap.add_argument("--summarize-leg", nargs=3, metavar=("TRACE_DIR", "OUT", "ONLY"),
+                    help="summarise a rocprofv3 --kernel-trace run of `bench.py --only ONLY` "
+                         "into the markdown file OUT and exit")
     ap.add_argument("--large-only", action="store_true",
                     help="only the large workload: no side measurements (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -688,6 +729,20 @@ def main():
                "--output-format csv -- python3 bench.py --steps 3 --warmup 0 --no-cpu-baseline "
                "--large-only --calibrate-copy")
         print(json.dumps(summarize_pmc(*args.summarize_pmc, TRAFFIC_PROFILE, cmd)))
+        return
+    if args.summarize_leg:
+        tdir, out, only = args.summarize_leg
+        titles = {"p2": "thesis delta-form scheme (P2), 1024 x 1024 and 8192 x 8192, FP64",
+                  "cook": "Cahn-Hilliard-Cook forced step, 8192 x 8192, FP64",
+                  "ensemble": "uneven ensemble of 256 runs (96 x 128^2, 96 x 256^2, 64 x 512^2): "
+                              "FP64, forced, FP32-refined",
+                  "per_system": "batched solves with one matrix per system, n = 1024, "
+                                "65536 systems",
+                  "batch1d": "batched 1D schemes (Cahn-Hilliard 2^20 x 256, hyperdiffusion "
+                             "65536 x 1024)"}
+        cmd = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_" + only + " -o run "
+               "--output-format csv -- python3 bench.py --only " + only)
+        summarize_leg(tdir, out, titles.get(only, only), cmd, args.trace_note)
         return
     if args.summarize_trace:
         cmd = ("rocprofv3 --kernel-trace --stats -T -d gpurun_out/prof_large -o run "
@@ -711,7 +766,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     if args.only:
-        fn = {"solves": solve_throughput, "ensemble": ensemble_throughput,
+        fn = {"solves": solve_throughput, "per_system": per_system_throughput,
+              "ensemble": ensemble_throughput,
               "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
               "table31": table31_run, "batch1d": batch1d_run, "cook": cook_run,
               "precision": lambda c, t: {
