@@ -342,7 +342,8 @@ struct chx_ens_s {
   std::vector<long> k1_poff;  // per run: offset (doubles) of its partials
   ~chx_ens_s() {
     for (auto h : rh) (void)ch_destroy(h);
-    for (auto& g : k1_groups) (void)hipfftDestroy(g.plan);
+    for (auto& g : k1_groups)
+      if (g.plan) (void)hipfftDestroy(g.plan);
     if (mom_mem) (void)hipFree(mom_mem);
     if (dnoise) (void)hipFree(dnoise);
 
@@ -1658,6 +1659,13 @@ int ch_ensemble_moments(chx_ens E, double* const* c_runs, const long* ld_runs, d
   return finite ? CHX_OK : CHX_ENONFINITE;
 }
 
+// Undo a partial set-up of the transforms (a later call starts afresh).
+static void ens_k1_reset(chx_ens E) {
+  for (auto& g : E->k1_groups)
+    if (g.plan) (void)hipfftDestroy(g.plan);
+  E->k1_groups.clear();
+}
+
 int ch_ensemble_k1(chx_ens E, double* const* c_runs, const long* ld_runs, double* k1,
                    chx_stream s) {
   if (!E || !c_runs || !k1) return CHX_EINVAL;
@@ -1685,6 +1693,7 @@ int ch_ensemble_k1(chx_ens E, double* const* c_runs, const long* ld_runs, double
       if (hipfftPlanMany(&g.plan, 2, dims, nullptr, 1, g.nx * g.ny, nullptr, 1,
                          (g.nx / 2 + 1) * g.ny, HIPFFT_D2Z, (int)nb) != HIPFFT_SUCCESS) {
         g.plan = 0;
+        ens_k1_reset(E);
         return CHX_EHIP;
       }
     }
@@ -1699,6 +1708,7 @@ int ch_ensemble_k1(chx_ens E, double* const* c_runs, const long* ld_runs, double
     }
     if (hipMalloc(&E->k1_mem, E->k1_part_off + (size_t)off * sizeof(double)) != hipSuccess) {
       E->k1_mem = nullptr;
+      ens_k1_reset(E);
       return CHX_ENOMEM;
     }
   }

@@ -235,10 +235,10 @@ __global__ __launch_bounds__(kThreads) void penta_batch_factor_k(
   const int m = PER ? n - 2 : n;
   PentaTail tl{};
   if (PER) penta_load_tail<PER, false>(n, ld, s, a, b, c, d, e, nullptr, tl);
-  double* w0 = ws;
-  double* w1 = ws + (long)m * ldw;
-  double* p0 = ws + 2L * m * ldw;
-  double* p1 = ws + 3L * m * ldw;
+  double* w0 = PER ? ws : nullptr;
+  double* w1 = PER ? ws + (long)m * ldw : nullptr;
+  double* p0 = PER ? ws + 2L * m * ldw : nullptr;
+  double* p1 = PER ? ws + 3L * m * ldw : nullptr;
   PentaFwd st;
   int i = 0;
   for (; i + kU <= m; i += kU) {
@@ -305,8 +305,8 @@ __global__ __launch_bounds__(kThreads) void penta_batch_solve_k(
   const long s = (long)blockIdx.x * kThreads + threadIdx.x;
   if (s >= batch) return;
   const int m = PER ? n - 2 : n;
-  const double* w0 = ws;
-  const double* w1 = ws + (long)m * ldw;
+  const double* w0 = PER ? ws : nullptr;
+  const double* w1 = PER ? ws + (long)m * ldw : nullptr;
   double g1 = 0.0, g2 = 0.0, s0 = 0.0, s1 = 0.0;
   int i = 0;
   for (; i + kU <= m; i += kU) {
@@ -356,7 +356,8 @@ __global__ __launch_bounds__(kThreads) void penta_batch_solve_k(
     t0 = mv[s] * r0 + mv[ldw + s] * r1;
     t1 = mv[2 * ldw + s] * r0 + mv[3 * ldw + s] * r1;
   }
-  penta_back<PER>(m, s, d, ld, e, ld, ws + 2L * m * ldw, ws + 3L * m * ldw, ldw, t0, t1, x, ld);
+  penta_back<PER>(m, s, d, ld, e, ld, PER ? ws + 2L * m * ldw : nullptr,
+                  PER ? ws + 3L * m * ldw : nullptr, ldw, t0, t1, x, ld);
   if (PER) {
     x[(long)(n - 2) * ld + s] = t0;
     x[(long)(n - 1) * ld + s] = t1;
@@ -375,8 +376,8 @@ __global__ __launch_bounds__(kThreads) void penta_batch_rewrite_k(
   if (PER) penta_load_tail<PER, true>(n, ld, s, a, b, c, d, e, x, tl);
   double* gm = ws;
   double* dl = ws + (long)m * ldw;
-  double* p0 = ws + 2L * m * ldw;
-  double* p1 = ws + 3L * m * ldw;
+  double* p0 = PER ? ws + 2L * m * ldw : nullptr;
+  double* p1 = PER ? ws + 3L * m * ldw : nullptr;
   PentaFwd st;
   int i = 0;
   for (; i + kU <= m; i += kU) {
@@ -526,8 +527,8 @@ __global__ __launch_bounds__(kThreads) void tri_batch_factor_k(int n, int batch,
   if (s >= batch) return;
   const double a0 = PER ? a[s] : 0.0, b0 = PER ? b[s] : 0.0;
   const double cl = PER ? c[(long)(n - 1) * ld + s] : 0.0;
-  double* zu = ws;
-  double* wv = ws + (long)n * ldw;
+  double* zu = PER ? ws : nullptr;
+  double* wv = PER ? ws + (long)n * ldw : nullptr;
   TriFwd st;
   for (int i = 0; i < n; ++i) {
     const long r = (long)i * ld + s;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_solve_k(int n, int batch, 
                                                               long ldw, double* __restrict__ x) {
   const long s = (long)blockIdx.x * kThreads + threadIdx.x;
   if (s >= batch) return;
-  const double* wv = ws + (long)n * ldw;
+  const double* wv = PER ? ws + (long)n * ldw : nullptr;
   double y1 = 0.0, sy = 0.0;
   int i = 0;
   for (; i + kU <= n; i += kU) {
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_solve_k(int n, int batch, 
     y1 = y;
   }
   const double phi = PER ? sy * ws[2L * n * ldw + s] : 0.0;
-  tri_back<PER>(n, s, c, ld, ws, ldw, phi, x, ld);
+  tri_back<PER>(n, s, c, ld, PER ? ws : nullptr, ldw, phi, x, ld);
 }
 
 template <bool PER>
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_rewrite_k(
   const double a0 = PER ? a[s] : 0.0, b0 = PER ? b[s] : 0.0;
   const double cl = PER ? c[(long)(n - 1) * ld + s] : 0.0;
   double* chv = ws;
-  double* zu = ws + (long)n * ldw;
+  double* zu = PER ? ws + (long)n * ldw : nullptr;
   TriFwd st;
   int i = 0;
   for (; i + kU <= n; i += kU) {
