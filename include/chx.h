@@ -331,7 +331,11 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   separator kernel and then the row pass; 0 .. CHX_NUM_SPLIT_SHAPES-1 run
  *   the separators in the same launch as the rows that do not need them
  *   (every row but the last two of each 32-row chunk), in that tile shape,
- *   then the remaining rows.  Chosen by the same timing as the tile shape.
+ *   then the remaining rows; -2 (CHX_ROW_SPLIT_OVERLAP) runs the separators
+ *   and then the separator rows on a second stream of the handle while the
+ *   other rows are solved on the caller's stream (joined by events before
+ *   the next step; ch_adi_step_timed keeps the -1 order so that its kernel
+ *   timings stay meaningful).  Chosen by the same timing as the tile shape.
  *   Results are bitwise identical either way.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown
@@ -342,6 +346,7 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 #define CHX_TUNE_ROW_SPLIT 2
 #define CHX_NUM_REDUCED_SHAPES 7
 #define CHX_NUM_SPLIT_SHAPES 3
+#define CHX_ROW_SPLIT_OVERLAP (-2)
 int ch_get_tuning(chx_ch h, int what, int* value);
 int ch_set_tuning(chx_ch h, int what, int value);
 

@@ -550,6 +550,7 @@ CHX_TUNE_REDUCED_SHAPE = 0
 CHX_TUNE_SMALL_PATH = 1
 CHX_TUNE_ROW_SPLIT = 2
 CHX_NUM_REDUCED_SHAPES = 7
+CHX_ROW_SPLIT_OVERLAP = -2
 CHX_NUM_SPLIT_SHAPES = 3
 
 

@@ -263,7 +263,11 @@ struct chx_ch_s {
   bool fast = false;
   bool small_ok = false;  // the single-workgroup LDS-resident path fits
   bool small = false;     // ... and is in use
-  int split = -1;         // split row pass shape (-1: plain separators + rows)
+  int split = -1;         // split row pass shape (-1: plain separators + rows,
+                          // kSplitOverlap: separators beside the interior rows)
+  // the second stream of the overlapped schedule and its fork / join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double sigma = 0.0;     // Cahn-Hilliard-Cook forcing intensity (0: off)
   unsigned long long noise_seed = 0, noise_step = 0;
   ChCoef K{};
@@ -285,6 +289,9 @@ struct chx_ch_s {
     if (dscratch) (void)hipFree(dscratch);
     if (fft_ready) (void)hipfftDestroy(fft);
     if (fft_mem) (void)hipFree(fft_mem);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -622,6 +629,10 @@ size_t device_max_lds() {
   return (size_t)v;
 }
 
+// Row-split value of the overlapped schedule: the column separator kernel and
+// then the separator rows on a second stream, the interior rows beside them.
+constexpr int kSplitOverlap = -2;
+
 Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   const DevChunk& c = py->dchunk;
   const auto key = std::make_tuple(nx, ny, c.S, c.dlo, c.dcount);
@@ -676,6 +687,35 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
       best_ms = ms;
       best.split = shape;
     }
+  }
+  if (ok && rows_subsets_fit(px->dchunk)) {
+    hipStream_t side = nullptr;
+    hipEvent_t ef = nullptr, ej = nullptr;
+    bool ok2 = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&ef, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&ej, hipEventDisableTiming) == hipSuccess;
+    if (ok2) {
+      DevChunk cb = c;
+      cb.red_shape = best.red_shape;
+      const float ms = time_it([&]() {
+        hipError_t e = hipEventRecord(ef, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ef, 0);
+        if (e == hipSuccess) e = launch_reduced_il<2>(cb, rho, nx, dst, nx, kChunk, kChunk - 2, side);
+        if (e == hipSuccess) e = launch_rows_sep(dst, nx, ny, px->dchunk, side);
+        if (e == hipSuccess) e = hipEventRecord(ej, side);
+        if (e == hipSuccess) e = launch_rows_interior(dst, nx, ny, px->dchunk, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ej, 0);
+        return e;
+      });
+      if (ok && ms < best_ms) {
+        best_ms = ms;
+        best.split = kSplitOverlap;
+      }
+    }
+    if (side) (void)hipStreamSynchronize(side);
+    if (ef) (void)hipEventDestroy(ef);
+    if (ej) (void)hipEventDestroy(ej);
+    if (side) (void)hipStreamDestroy(side);
   }
   if (st) (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);
@@ -790,6 +830,14 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   }
   h->small_ok = h->fast && q.dtype == CHX_F64 && ch_small_fits(q.nx, q.ny, device_max_lds());
   h->small = h->small_ok;
+  if (h->fast && q.dtype == CHX_F64 && rows_subsets_fit(h->px->dchunk)) {
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+      delete h;
+      return CHX_EHIP;
+    }
+  }
   if (h->fast && q.dtype == CHX_F64 && !h->small) {
     const Tuned t = tune_step(h->py, h->px, q.nx, q.ny);
     h->py->dchunk.red_shape = t.red_shape;
@@ -821,9 +869,12 @@ int ch_set_tuning(chx_ch h, int what, int value) {
       h->small = value == 1;
       return CHX_OK;
     case CHX_TUNE_ROW_SPLIT:
-      if (value != -1 &&
-          !(h->fast && h->prm.dtype == CHX_F64 && split_fits(h->py->dchunk, h->px->dchunk, value)))
+      if (value == kSplitOverlap) {
+        if (!h->side) return CHX_EINVAL;
+      } else if (value != -1 && !(h->fast && h->prm.dtype == CHX_F64 &&
+                                  split_fits(h->py->dchunk, h->px->dchunk, value))) {
         return CHX_EINVAL;
+      }
       h->split = value;
       return CHX_OK;
     default: return CHX_EINVAL;
@@ -975,7 +1026,23 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
                                   h->K, part, st, noise ? &nz : nullptr);
         E(0);
       }
-      if (ok() && h->split >= 0) {
+      if (ok() && h->split == kSplitOverlap && !tm) {
+        // separators, then the separator rows, on the second stream; the
+        // interior rows (which need no separator) beside them on st
+        e = hipEventRecord(h->ev_fork, st);
+        if (ok()) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
+        if (ok()) {
+          e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, h->side,
+                                   diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
+                                   diag ? diag_out + 2 * n : nullptr);
+          if (e == hipSuccess) e = launch_rows_sep(dst, nx, ny, h->px->dchunk, h->side);
+          // join even after a failure, so no capture is left forked
+          const hipError_t j1 = hipEventRecord(h->ev_join, h->side);
+          if (e == hipSuccess) e = launch_rows_interior(dst, nx, ny, h->px->dchunk, st);
+          const hipError_t j2 = hipStreamWaitEvent(st, h->ev_join, 0);
+          if (e == hipSuccess) e = j1 != hipSuccess ? j1 : j2;
+        }
+      } else if (ok() && h->split >= 0) {
         // separators fused with the interior rows (phase 2), then the
         // separator rows (phase 1)
         B();

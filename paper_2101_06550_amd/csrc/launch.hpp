@@ -41,6 +41,11 @@ hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* 
                                    int nx, int ny, const DevChunk& cx, const double* dpart,
                                    long dnparts, double dscale, double* dout, hipStream_t st);
 hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
+// The interior rows of every 32-row chunk (the rows that need no column
+// separator); rows_subsets_fit: row lengths whose rows split this way (the
+// row plan has 128 or 256 chunks).
+bool rows_subsets_fit(const DevChunk& cx);
+hipError_t launch_rows_interior(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
 
 // nsteps steps of a batched 1D periodic scheme (kind 0 Crank-Nicolson
 // hyperdiffusion, 1 Crank-Nicolson diffusion, 2 1D Cahn-Hilliard) on the

@@ -779,6 +779,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                            sh);
 }
 
+// The interior rows alone (every row but the last two of each 32-row chunk):
+// they need no column separator, so they can be solved while the separator
+// kernel runs on another stream.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rows_interior(
+    double* x, int nx, int ny, DevChunk cx, BandT<double> bdx) {
+  __shared__ RowLds<2, kChunk, double> sh;
+  const int R = 256 / cx.S;
+  row_solve_body<2, kChunk, double, false>(x, nx, x, nx, ny, nx, cx.S, R, cx.rec, bdx, cx.blocks,
+                                           cx.dlo, cx.dcount, split_row0(blockIdx.x, R, false),
+                                           sh);
+}
+
 // (chunks per wave, window entries staged at once) of the fused kernel's
 // separator part.
 constexpr int kSplitG[kNumSplitShapes] = {8, 8, 4};
@@ -810,6 +822,17 @@ hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* 
     default: CHX_SPLIT(4, 4); break;
   }
 #undef CHX_SPLIT
+  return hipGetLastError();
+}
+
+bool rows_subsets_fit(const DevChunk& cx) { return cx.S == 128 || cx.S == 256; }
+
+hipError_t launch_rows_interior(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st) {
+  if (!rows_subsets_fit(cx)) return hipErrorInvalidValue;
+  const int R = 256 / cx.S;
+  const dim3 grid((unsigned)((ny / kChunk) * ((kChunk - 2) / R)));
+  hipLaunchKernelGGL(rows_interior, grid, dim3(256), 0, st, x, nx, ny, cx,
+                     band_of<double>(cx.coef));
   return hipGetLastError();
 }
 

@@ -186,9 +186,10 @@ def test_split_row_pass_bitwise(chx, orc, ny, nx, dt):
     c0 = inputs.noise_field(ny, nx, 21)
     h = chx.ch_create(nx, ny, L, L, 1.0, 0.001, dt)
     tuned = chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)
-    assert -1 <= tuned < chx.CHX_NUM_SPLIT_SHAPES
+    assert chx.CHX_ROW_SPLIT_OVERLAP <= tuned < chx.CHX_NUM_SPLIT_SHAPES
     ref = None
-    for split in [-1] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
+    # -2: separators and separator rows on a second stream beside the interior rows
+    for split in [-1, chx.CHX_ROW_SPLIT_OVERLAP] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
         print(f"[case] row split {split} {ny}x{nx}", flush=True)
         chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
         c = torch.tensor(c0, device="cuda")

@@ -91,6 +91,8 @@ def test_shape_count_matches_header():
                  "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
         m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
         assert m and int(m.group(1)) == getattr(chx, name), name
+    m = re.search(r"#define\s+CHX_ROW_SPLIT_OVERLAP\s+\((-?\d+)\)", text)
+    assert m and int(m.group(1)) == chx.CHX_ROW_SPLIT_OVERLAP
 
 
 def test_non_positive_pivot_is_reported():
