@@ -121,7 +121,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
     blob = {"source_sha256": source_hash(), "scale": scale, "kernels": table}
     lines = ["# HBM traffic per dispatch: CH ADI step, 8192 x 8192, FP64", "",
              "Commands (run from the repository root on one MI355X, each pass on its own):", "",
-             "    " + command.replace("{C}", "FETCH_SIZE"), "    " + command.replace("{C}", "WRITE_SIZE"),
+             "    " + command.replace("{C}", "FETCH_SIZE").replace("{D}", os.path.relpath(fetch_dir)),
+             "    " + command.replace("{C}", "WRITE_SIZE").replace("{D}", os.path.relpath(write_dir)),
              "", "Summarised with `python bench.py --summarize-pmc <fetch dir> <write dir>`.",
              f"Copy calibration (1 GiB streaming copy, same run): FETCH_SIZE x "
              f"{scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}.", "",
@@ -725,9 +726,10 @@ def main():
                          "reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.summarize_pmc:
-        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {C} -d gpurun_out/pmc_{C} -o run "
-               "--output-format csv -- python3 bench.py --steps 3 --warmup 0 --no-cpu-baseline "
-               "--large-only --calibrate-copy")
+        # the recorded commands name the trace directories given here
+        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {C} -d {D} -o run --output-format csv -- "
+               "python3 bench.py --steps 3 --warmup 0 --no-cpu-baseline --large-only "
+               "--calibrate-copy")
         print(json.dumps(summarize_pmc(*args.summarize_pmc, TRAFFIC_PROFILE, cmd)))
         return
     if args.summarize_leg:
@@ -740,20 +742,21 @@ def main():
                                 "65536 systems",
                   "batch1d": "batched 1D schemes (Cahn-Hilliard 2^20 x 256, hyperdiffusion "
                              "65536 x 1024)"}
-        cmd = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_" + only + " -o run "
+        cmd = ("rocprofv3 --kernel-trace --stats -d " + os.path.relpath(tdir) + " -o run "
                "--output-format csv -- python3 bench.py --only " + only)
         summarize_leg(tdir, out, titles.get(only, only), cmd, args.trace_note)
         return
     if args.summarize_trace:
-        cmd = ("rocprofv3 --kernel-trace --stats -T -d gpurun_out/prof_large -o run "
-               "--output-format csv -- python3 bench.py --no-cpu-baseline --large-only "
+        cmd = ("rocprofv3 --kernel-trace --stats -T -d " + os.path.relpath(args.summarize_trace) +
+               " -o run --output-format csv -- python3 bench.py --no-cpu-baseline --large-only "
                "--calibrate-copy --steps 20 --warmup 2")
         print(json.dumps(summarize_trace(args.summarize_trace, KERNEL_PROFILE, cmd,
                                          args.trace_note)))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is described in DESIGN.md and not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); ensembles would "
+              "shard by runs and a large grid by row slabs, which this build does not run.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
