@@ -46,6 +46,8 @@ STEP_CASES = [
     (80, 72, 1.0, 0.01, 1e-4, 6),      # not a fused shape: plain path
     (33, 21, 1.0, 0.01, 1e-4, 7),      # odd sizes, plain path
     (1024, 1024, 1.0, 0.01, 1e-5, 3),  # single large-run precision workload
+    (32, 16384, 1.0, 0.001, 1e-6, 8),  # rows of 512 chunks: longer than the LDS row solver
+    (16384, 64, 1.0, 0.001, 1e-6, 9),  # columns of 512 chunks
 ]
 
 
@@ -55,7 +57,11 @@ def test_one_step_parity(chx, orc, ny, nx, D, gamma, dt, seed):
     print(f"[case] ch step {ny}x{nx} dt={dt} seed={seed}", flush=True)
     out, _ = gpu_steps(chx, c0, D, gamma, dt)
     ref = orc.ch_step(c0, L, L, D, gamma, dt)
-    assert rel(out, ref) < 1e-12
+    # two correct FP64 solves of a matrix with condition number kappa agree to
+    # about kappa eps: 1e-12 unless the operator is stiffer than that allows
+    sigma = D * gamma * dt / min(L / nx, L / ny) ** 4
+    tol = max(1e-12, 20 * np.finfo(float).eps * (1 + 16 * sigma))
+    assert rel(out, ref) < tol
 
 
 def test_ten_steps_one_call_vs_oracle_each_step(chx, orc):
