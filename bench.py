@@ -535,6 +535,22 @@ def batch1d_run(chx, torch):
                      "system_steps_per_s": batch * k / el,
                      "algorithmic_GBps": round(18.0 * n * batch * k / el / 1e9, 1),
                      "finite": bool(torch.isfinite(x).all())}
+        if kind == 0:
+            # the thesis's Rewrite mode on the same batch: diagonals written and
+            # every system factored and solved afresh each step; 192 B per unknown
+            # (right-hand side 16, five bands 40, fused factor-and-solve 136)
+            ws = chx.batch1d_step_rewrite(b, x, nsteps=2)
+            torch.cuda.synchronize()
+            kr = 20
+            t0 = time.perf_counter()
+            chx.batch1d_step_rewrite(b, x, nsteps=kr, ws=ws)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[name + "_rewrite"] = {"steps": kr, "ms_per_step": round(1e3 * el / kr, 5),
+                                      "system_steps_per_s": batch * kr / el,
+                                      "algorithmic_GBps": round(192.0 * n * batch * kr / el / 1e9, 1),
+                                      "finite": bool(torch.isfinite(x).all())}
+            del ws
         del x, b
     return out
 

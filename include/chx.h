@@ -237,6 +237,18 @@ int batch1d_destroy(chx_batch1d b);
 size_t batch1d_ws_bytes(chx_batch1d b, int batch);
 int batch1d_step(chx_batch1d b, int batch, double* x_inout, long ld, int nsteps,
                  void* ws, size_t ws_bytes, chx_stream s);
+/* batch1d_step_rewrite: the same nsteps steps in the thesis's "Rewrite" mode
+ *   (Ch.4 "Performance Analysis", cuPentBatchRewrite): every step forms the
+ *   right-hand side, writes every system's diagonals afresh (as for a matrix
+ *   that changes from step to step) and factors and solves each system in
+ *   one pass (penta_batch_rewrite / tri_batch_rewrite, periodic), one thread
+ *   per system.  Any n the kind allows.  batch1d_rewrite_ws_bytes: its device
+ *   workspace (256-byte aligned): two fields, the bands and the solver's
+ *   workspace.  Same results as batch1d_step up to rounding; much more
+ *   memory traffic (kept for the comparison the thesis makes). */
+size_t batch1d_rewrite_ws_bytes(chx_batch1d b, int batch);
+int batch1d_step_rewrite(chx_batch1d b, int batch, double* x, long ld,
+                         int nsteps, void* ws, size_t ws_bytes, chx_stream s);
 
 /* ------------------------------------------------------------------------
  * Cahn-Hilliard ADI stepping (Ch.2 eq. 2:ch, Ch.3 eq. 3:ch_adi).

@@ -45,6 +45,7 @@ EXPORTED = [
     "ch_get_tuning", "ch_set_tuning", "ch_set_noise", "ch_get_noise_step", "ch_diagnostics",
     "ch_moments", "ch_k1",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
+    "batch1d_rewrite_ws_bytes", "batch1d_step_rewrite",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "ch_ensemble_moments", "ch_ensemble_k1", "ch_ensemble_set_noise",
     "ch_ensemble_get_noise_step",
@@ -125,6 +126,8 @@ def load(path: str | None = None):
         "batch1d_destroy": (_I, [_V]),
         "batch1d_ws_bytes": (_S, [_V, _I]),
         "batch1d_step": (_I, [_V, _I, _V, _L, _I, _V, _S, _V]),
+        "batch1d_rewrite_ws_bytes": (_S, [_V, _I]),
+        "batch1d_step_rewrite": (_I, [_V, _I, _V, _L, _I, _V, _S, _V]),
         "ch_ensemble_create": (_I, [_I, ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
         "ch_ensemble_destroy": (_I, [_V]),
         "ch_ensemble_ws_bytes": (_S, [_V]),
@@ -544,6 +547,22 @@ def batch1d_step(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None = None,
     _, wsp, avail = _workspace(nbytes, ws, x.device)
     _check(lib.batch1d_step(b.handle, batch, _devptr(x, "x"), ld, nsteps, wsp, avail,
                             _stream(stream)), "batch1d_step")
+
+
+def batch1d_step_rewrite(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None = None,
+                         stream=None):
+    """The same steps in the rewrite mode (diagonals written and every system
+    factored and solved afresh each step)."""
+    lib = load()
+    if x.dim() != 2 or x.shape[0] != b.n:
+        raise ChxError(CHX_EINVAL, "batch1d_step_rewrite: x must be (n, batch)")
+    batch = x.shape[1]
+    ld = x.stride(0) if ld is None else ld
+    nbytes = lib.batch1d_rewrite_ws_bytes(b.handle, batch)
+    ws, wsp, avail = _workspace(nbytes, ws, x.device)
+    _check(lib.batch1d_step_rewrite(b.handle, batch, _devptr(x, "x"), ld, nsteps, wsp, avail,
+                                    _stream(stream)), "batch1d_step_rewrite")
+    return ws
 
 
 CHX_TUNE_REDUCED_SHAPE = 0

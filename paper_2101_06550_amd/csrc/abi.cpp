@@ -581,6 +581,53 @@ int batch1d_step(chx_batch1d b, int batch, double* x, long ld, int nsteps, void*
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
+// Rewrite mode (the thesis's cuPentBatchRewrite benchmark): per step the
+// right-hand side, every system's diagonals written afresh, then a fused
+// factor-and-solve of each system; the state ping-pongs between two fields of
+// the workspace (pitch batch) and lands in x at the end.
+static size_t b1d_field(const chx_batch1d_s* b, int batch) {
+  return align256((size_t)b->n * batch * sizeof(double));
+}
+
+size_t batch1d_rewrite_ws_bytes(chx_batch1d b, int batch) {
+  if (!b || batch <= 0) return 0;
+  const int P = b->plan->P;
+  return (2 + (2 * P + 1)) * b1d_field(b, batch) + align256(vb_rewrite_ws_bytes(P, b->n, batch));
+}
+
+int batch1d_step_rewrite(chx_batch1d b, int batch, double* x, long ld, int nsteps, void* ws,
+                         size_t ws_bytes, chx_stream s) {
+  if (!b || !x || batch < 0 || nsteps < 1) return CHX_EINVAL;
+  if (batch == 0) return CHX_OK;
+  if (ld < batch) return CHX_EINVAL;
+  if (!ws || ws_bytes < batch1d_rewrite_ws_bytes(b, batch)) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(s);
+  auto* base = static_cast<unsigned char*>(ws);
+  const size_t field = b1d_field(b, batch);
+  const int P = b->plan->P, nb = 2 * P + 1, n = b->n;
+  double* f[2] = {reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + field)};
+  double* bands[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < nb; ++k) bands[k] = reinterpret_cast<double*>(base + (2 + k) * field);
+  double* rw = reinterpret_cast<double*>(base + (2 + nb) * field);
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < nsteps && e == hipSuccess; ++j) {
+    const double* src = j == 0 ? x : f[(j - 1) & 1];
+    const long lsrc = j == 0 ? ld : (long)batch;
+    double* dst = f[j & 1];
+    e = launch_batch1d_rhs(b->kind, src, lsrc, dst, batch, batch, n, b->s, b->al, st);
+    if (e == hipSuccess) e = vb_fill_bands(nb, bands, b->plan->coef, n, batch, batch, st);
+    if (e == hipSuccess)
+      e = P == 2 ? vb_penta_rewrite_periodic(n, batch, bands, batch, dst, rw, st)
+                 : vb_tri_rewrite_periodic(n, batch, bands, batch, dst, rw, st);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(x, ld * sizeof(double), f[(nsteps - 1) & 1],
+                         (size_t)batch * sizeof(double), (size_t)batch * sizeof(double), n,
+                         hipMemcpyDeviceToDevice, st);
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
+}
+
 int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
                     const double* weights, int left, int right, int top, int bottom, int periodic,
                     int premap, chx_stream s) {

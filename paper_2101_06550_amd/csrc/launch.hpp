@@ -54,6 +54,20 @@ hipError_t launch_rows_interior(double* x, int nx, int ny, const DevChunk& cx, h
 // y0 and y1 (pitch batch) with the chunk correction deferred into the next
 // sweep, and x is written once at the end; rho holds the separator parts.
 // Other lengths: right-hand side into y0, whole sweeps, copy back, per step.
+// The scheme's right-hand side alone, y = f(x), one thread per (system, unknown).
+hipError_t launch_batch1d_rhs(int kind, const double* x, long ld, double* y, long ldy, int batch,
+                              int n, double s, double al, hipStream_t st);
+// Batches with one matrix per system (varband.hip): every band array set to a
+// constant (nb arrays, entry i of system s at i * ld + s), and the fused
+// factor-and-solve of periodic penta / tri systems in place on x (same ld for
+// bands and x; ws of the rewrite mode, rows of ldw = batch rounded up to 32).
+hipError_t vb_fill_bands(int nb, double* const* bands, const double* values, int n, int batch,
+                         long ld, hipStream_t st);
+hipError_t vb_penta_rewrite_periodic(int n, int batch, const double* const* bands, long ld,
+                                     double* x, double* ws, hipStream_t st);
+hipError_t vb_tri_rewrite_periodic(int n, int batch, const double* const* bands, long ld,
+                                   double* x, double* ws, hipStream_t st);
+size_t vb_rewrite_ws_bytes(int P, int n, int batch);
 hipError_t launch_batch1d_steps(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
                                 double* x, long ld, int batch, int n, double s, double al,
                                 int nsteps, double* y0, double* y1, double* rho,

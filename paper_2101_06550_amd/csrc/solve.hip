@@ -673,6 +673,18 @@ __global__ __launch_bounds__(256) void batch1d_rhs(const double* __restrict__ x,
   y[(long)i * ldy + sys] = b1d_rhs<KIND>(X, 2, s, al);
 }
 
+hipError_t launch_batch1d_rhs(int kind, const double* x, long ld, double* y, long ldy, int batch,
+                              int n, double s, double al, hipStream_t st) {
+  dim3 grid((batch + 255) / 256, n);
+  if (kind == 0)
+    hipLaunchKernelGGL(batch1d_rhs<0>, grid, dim3(256), 0, st, x, ld, y, ldy, batch, n, s, al);
+  else if (kind == 1)
+    hipLaunchKernelGGL(batch1d_rhs<1>, grid, dim3(256), 0, st, x, ld, y, ldy, batch, n, s, al);
+  else
+    hipLaunchKernelGGL(batch1d_rhs<2>, grid, dim3(256), 0, st, x, ld, y, ldy, batch, n, s, al);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch1d_steps(int kind, bool chunked, const DevChunk& c, const DevWhole& w,
                                 double* x, long ld, int batch, int n, double s, double al,
                                 int nsteps, double* y0, double* y1, double* rho, hipStream_t st) {

@@ -32,6 +32,7 @@
 #include <cstdint>
 
 #include "../../include/chx.h"
+#include "launch.hpp"
 
 namespace chx_vb {
 
@@ -669,9 +670,62 @@ dim3 grid_of(int batch) { return dim3((unsigned)((batch + kThreads - 1) / kThrea
 
 int launched() { return hipGetLastError() == hipSuccess ? CHX_OK : CHX_EHIP; }
 
+// Every entry of up to five band arrays set to that band's value.
+struct FillBands {
+  double* band[5];
+  double value[5];
+};
+
+__global__ __launch_bounds__(kThreads) void fill_bands_k(FillBands fb, int nb, int n, int batch,
+                                                         long ld) {
+  const long s = (long)blockIdx.x * kThreads + threadIdx.x;
+  const int i = blockIdx.y;
+  if (s >= batch) return;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k < nb) fb.band[k][(long)i * ld + s] = fb.value[k];
+}
+
 }  // namespace chx_vb
 
 using namespace chx_vb;
+
+// Internal launchers for the batched 1D schemes' rewrite mode.
+namespace chx {
+
+hipError_t vb_fill_bands(int nb, double* const* bands, const double* values, int n, int batch,
+                         long ld, hipStream_t st) {
+  if (nb < 1 || nb > 5) return hipErrorInvalidValue;
+  FillBands fb{};
+  for (int k = 0; k < nb; ++k) {
+    fb.band[k] = bands[k];
+    fb.value[k] = values[k];
+  }
+  hipLaunchKernelGGL(fill_bands_k, dim3((unsigned)((batch + kThreads - 1) / kThreads), n),
+                     dim3(kThreads), 0, st, fb, nb, n, batch, ld);
+  return hipGetLastError();
+}
+
+size_t vb_rewrite_ws_bytes(int P, int n, int batch) {
+  return P == 2 ? penta_ws_doubles(n, batch, 1, CHX_BATCH_REWRITE) * sizeof(double)
+                : tri_ws_doubles(n, batch, 1, CHX_BATCH_REWRITE) * sizeof(double);
+}
+
+hipError_t vb_penta_rewrite_periodic(int n, int batch, const double* const* b, long ld, double* x,
+                                     double* ws, hipStream_t st) {
+  hipLaunchKernelGGL(penta_batch_rewrite_k<true>, grid_of(batch), dim3(kThreads), 0, st, n, batch,
+                     ld, b[0], b[1], b[2], b[3], b[4], x, ws, ws_ld(batch));
+  return hipGetLastError();
+}
+
+hipError_t vb_tri_rewrite_periodic(int n, int batch, const double* const* b, long ld, double* x,
+                                   double* ws, hipStream_t st) {
+  hipLaunchKernelGGL(tri_batch_rewrite_k<true>, grid_of(batch), dim3(kThreads), 0, st, n, batch,
+                     ld, b[0], b[1], b[2], x, ws, ws_ld(batch));
+  return hipGetLastError();
+}
+
+}  // namespace chx
 
 extern "C" {
 

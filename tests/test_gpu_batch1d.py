@@ -99,3 +99,30 @@ def test_benchmark_batches_sampled(chx, orc, kind, n, batch, L, dt, a, D):
     s = {0: a * dt / (2 * dx ** 4), 2: a * D * dt / dx ** 4}[kind]
     tol = max(1e-12, 20 * np.finfo(float).eps * (1 + 16 * s))
     assert rel(x[:, pick].cpu().numpy(), ref) < tol
+
+
+# the thesis's Rewrite mode: diagonals written and every system factored afresh each step
+REWRITE_CASES = [(0, 64, 1000, 1.0, 1e-8, 1.0, 1.0), (0, 100, 129, 1.0, 1e-9, 1.0, 1.0),
+                 (1, 256, 513, 1.0, 1e-4, 1.0, 1.0), (1, 50, 33, 1.0, 1e-3, 1.0, 1.0),
+                 (2, 256, 4096, L2PI, 2.5e-3, 0.01, 1.0), (2, 40, 65, L2PI, 1e-3, 0.01, 1.0)]
+
+
+@pytest.mark.parametrize("kind,n,batch,L,dt,a,D", REWRITE_CASES)
+def test_rewrite_mode_matches_oracle_and_constant_mode(chx, orc, kind, n, batch, L, dt, a, D):
+    x0 = inputs.uniform(60 + kind, (n, batch), -0.1, 0.1)
+    b = chx.batch1d_create(kind, n, L, dt, a, D)
+    buf = torch.zeros((n, batch + 5), dtype=torch.float64, device="cuda")
+    x = buf[:, :batch]
+    x.copy_(torch.from_numpy(x0))
+    print(f"[case] batch1d rewrite kind={kind} n={n} batch={batch}", flush=True)
+    chx.batch1d_step_rewrite(b, x, nsteps=3)
+    y = torch.tensor(x0, device="cuda")
+    chx.batch1d_step(b, y, nsteps=3)
+    torch.cuda.synchronize()
+    ref = orc.batch1d_step(kind, x0, L, dt, a, D, nsteps=3)
+    dx = L / n
+    s = {0: a * dt / (2 * dx ** 4), 1: a * dt / (2 * dx ** 2), 2: a * D * dt / dx ** 4}[kind]
+    tol = max(1e-12, 20 * np.finfo(float).eps * (1 + 16 * s))
+    assert rel(x.cpu().numpy(), ref) < tol
+    assert rel(x.cpu().numpy(), y.cpu().numpy()) < tol
+    assert torch.all(buf[:, batch:] == 0)  # the padding is not written
