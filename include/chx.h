@@ -310,7 +310,8 @@ int ch_adi_step_p2(chx_ch h, double* c_inout, double* cprev_inout, long ld,
                    chx_stream s);
 
 /* ch_adi_step_timed: ch_adi_step with a HIP event recorded on stream s
- *   around every kernel it launches; synchronises s and returns, per phase,
+ *   around every kernel of every sample_every-th step (>= 1; 1 = every step)
+ *   and around the final launches; synchronises s and returns, per phase,
  *   the summed kernel time in milliseconds (phase_ms, host, 4 doubles) and the
  *   number of launches (phase_launches, host, 4 ints).  Phases: 0 column pass
  *   (right-hand side + column sweeps), 1 column separator system, 2 row solves,
@@ -321,7 +322,7 @@ int ch_adi_step_p2(chx_ch h, double* c_inout, double* cprev_inout, long ld,
  *   little overhead between kernels. */
 int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
                       double* diag_out, void* ws, size_t ws_bytes, chx_stream s,
-                      double* phase_ms, int* phase_launches);
+                      int sample_every, double* phase_ms, int* phase_launches);
 
 /* Kernel choices of the FP64 step (autotuning).
  * CHX_TUNE_SMALL_PATH: grids with nx % 64 == 0, ny % 32 == 0, nx ny <= 16384
@@ -346,8 +347,8 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   then the remaining rows; -2 (CHX_ROW_SPLIT_OVERLAP) runs the separators
  *   and then the separator rows on a second stream of the handle while the
  *   other rows are solved on the caller's stream (joined by events before
- *   the next step; ch_adi_step_timed keeps the -1 order so that its kernel
- *   timings stay meaningful).  Chosen by the same timing as the tile shape.
+ *   the next step; the steps ch_adi_step_timed times keep the -1 order so
+ *   that their kernel timings stay meaningful).  Chosen by the same timing as the tile shape.
  *   Results are bitwise identical either way.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown

@@ -113,7 +113,7 @@ def load(path: str | None = None):
         "ch_destroy": (_I, [_V]),
         "ch_ws_bytes": (_S, [_V]),
         "ch_adi_step": (_I, [_V, _V, _L, _I, _V, _V, _S, _V]),
-        "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _DP, _IP]),
+        "ch_adi_step_timed": (_I, [_V, _V, _L, _I, _V, _V, _S, _V, _I, _DP, _IP]),
         "ch_adi_step_p2": (_I, [_V, _V, _V, _L, _I, _V, _V, _S, _V]),
         "ch_set_noise": (_I, [_V, _D, ctypes.c_uint64, ctypes.c_uint64]),
         "ch_get_noise_step": (_I, [_V, ctypes.POINTER(ctypes.c_uint64)]),
@@ -470,10 +470,11 @@ def ch_adi_step_p2(h: CH, c, cprev, nsteps: int = 1, diag_out=None, ws=None,
 
 
 def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
-                      ld: int | None = None, stream=None):
-    """ch_adi_step with per-phase HIP-event kernel timing; returns
-    (phase_ms[4], phase_launches[4]) for phases column pass, column
-    separators, row solves, finalize/diagnostics.  Synchronises."""
+                      ld: int | None = None, stream=None, sample_every: int = 1):
+    """ch_adi_step with per-phase HIP-event kernel timing of every
+    sample_every-th step; returns (phase_ms[4], phase_launches[4]) for phases
+    column pass, column separators, row solves, finalize/diagnostics.
+    Synchronises."""
     lib = load()
     ld = c.stride(0) if ld is None else ld
     nbytes = lib.ch_ws_bytes(h.handle)
@@ -487,7 +488,8 @@ def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
     ms = (ctypes.c_double * 4)()
     cnt = (ctypes.c_int * 4)()
     _check(lib.ch_adi_step_timed(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
-                                 _stream(stream), ms, cnt), "ch_adi_step_timed")
+                                 _stream(stream), int(sample_every), ms, cnt),
+           "ch_adi_step_timed")
     return list(ms), list(cnt)
 
 

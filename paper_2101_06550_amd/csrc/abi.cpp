@@ -961,6 +961,9 @@ struct PhaseTimer {
   std::vector<hipEvent_t> ev;
   std::vector<int> phase;
   bool failed = false;
+  int every = 1;    // time the kernels of every `every`-th step (and the last launches)
+  bool on = true;   // timing the current step
+  void step(int n) { on = (n % every) == 0; }
   void begin() {
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess) { failed = true; return; }
@@ -998,8 +1001,8 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   };
   hipError_t e = hipSuccess;
   auto ok = [&]() { return e == hipSuccess; };
-  auto B = [&]() { if (tm) tm->begin(); };
-  auto E = [&](int ph) { if (tm) tm->end(ph); };
+  auto B = [&]() { if (tm && tm->on) tm->begin(); };
+  auto E = [&](int ph) { if (tm && tm->on) tm->end(ph); };
   if (h->prm.dtype == CHX_F32_REFINED) {
     // r = RHS(c) in FP64; c = A32^{-1} r by FP32 column and row sweeps; then
     // refine: R = r - A c (FP64), c += A32^{-1} R
@@ -1008,6 +1011,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     float* y32 = reinterpret_cast<float*>(base + h->off_y32);
     float* rho32 = reinterpret_cast<float*>(base + h->off_rho32);
     for (int n = 0; n < nsteps && ok(); ++n) {
+      if (tm) tm->step(n);
       if (diag_out) {
         B();
         e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
@@ -1064,6 +1068,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     bool recon = false;
     const long colblocks = ch_column_pass_blocks(nx, h->py->chunk.S);
     for (int n = 0; n < nsteps && ok(); ++n) {
+      if (tm) tm->step(n);
       double* dst = buf[n & 1];
       const bool diag = diag_out != nullptr;
       if (ok()) {
@@ -1073,7 +1078,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
                                   h->K, part, st, noise ? &nz : nullptr);
         E(0);
       }
-      if (ok() && h->split == kSplitOverlap && !tm) {
+      if (ok() && h->split == kSplitOverlap && !(tm && tm->on)) {
         // separators, then the separator rows, on the second stream; the
         // interior rows (which need no separator) beside them on st
         e = hipEventRecord(h->ev_fork, st);
@@ -1120,6 +1125,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       lds = nx;
       recon = true;
     }
+    if (tm) tm->on = true;
     if (ok()) {
       B();
       e = launch_ch_finalize(src, lds, c, ld, nx, ny, h->py->dchunk, st);
@@ -1128,6 +1134,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   } else {
     double* r = reinterpret_cast<double*>(base + h->off_r);
     for (int n = 0; n < nsteps && ok(); ++n) {
+      if (tm) tm->step(n);
       if (diag_out) {
         B();
         e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
@@ -1156,6 +1163,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       }
     }
   }
+  if (tm) tm->on = true;
   if (ok() && diag_out) {
     B();
     e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * nsteps, st);
@@ -1263,10 +1271,12 @@ int ch_adi_step(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void
 }
 
 int ch_adi_step_timed(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
-                      size_t ws_bytes, chx_stream s, double* phase_ms, int* phase_launches) {
-  if (!phase_ms || !phase_launches) return CHX_EINVAL;
+                      size_t ws_bytes, chx_stream s, int sample_every, double* phase_ms,
+                      int* phase_launches) {
+  if (!phase_ms || !phase_launches || sample_every < 1) return CHX_EINVAL;
   PhaseTimer tm;
   tm.st = static_cast<hipStream_t>(s);
+  tm.every = sample_every;
   int rc = run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, tm.st, &tm);
   if (rc) return rc;
   if (hipStreamSynchronize(tm.st) != hipSuccess) return CHX_EHIP;
