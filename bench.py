@@ -274,16 +274,19 @@ def solve_throughput(chx, torch, reps=10):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         if bpu is None:
-            # chunk sweep (read f, write y, 4 parts/chunk) + separators + correction
+            # first pass (read f, write 4 separator parts per chunk) + separators
+            # + second pass (read the interior of f and the separators of the
+            # chunk and its predecessor, write the interior of x)
             mi = CHUNK - 2
-            bpu = (8 + 8 * mi / CHUNK + 32 / CHUNK) + (32 + 16) / CHUNK + \
-                  (2 * 8 * mi / CHUNK + 32 / CHUNK)
+            bpu = (8 + 32 / CHUNK) + (32 + 16) / CHUNK + (2 * 8 * mi / CHUNK + 32 / CHUNK)
         gbs = bpu * n * batch / (ms * 1e-3) / 1e9
         out[name] = {"systems": batch, "n": n, "ms_per_solve_batch": round(ms, 4),
                      "solves_per_s": batch / (ms * 1e-3),
                      "algorithmic_bytes_per_unknown": round(bpu, 3),
                      "effective_GBps": round(gbs, 1),
-                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     # a two-sweep one-thread-per-system solve moves 32 B per unknown
+                     "GBps_at_32B_per_unknown": round(32 * n * batch / (ms * 1e-3) / 1e9, 1)}
         del x, ws
     return out
 

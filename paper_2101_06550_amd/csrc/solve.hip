@@ -91,11 +91,12 @@ __global__ __launch_bounds__(256) void whole_sweep(double* work, long ss, long e
 // ---------------------------------------------------------------------------
 // Interleaved layout: element i of system s at i*ld + s.  Block = 64 systems
 // (one wave, 512-byte coalesced rows) x 4 chunks (4 waves).
-template <int P, int M, typename T, typename Ty>
+template <int P, int M, typename T, typename Ty, bool STORE_Y = true>
 __global__ __launch_bounds__(256) void chunk_sweep_il(const double* src, long lds, Ty* y, long ldy,
                                                       int batch, int S, const T* __restrict__ rec,
                                                       BandT<T> bd, T* __restrict__ rho) {
-  // src: right-hand sides (FP64); y: chunk-interior solutions (may alias src)
+  // src: right-hand sides (FP64); y: chunk-interior solutions (may alias src);
+  // STORE_Y = false: only the separator parts are written
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long s = (long)blockIdx.x * 64 + lane;
   const int k = blockIdx.y * 4 + wave;
@@ -107,13 +108,52 @@ __global__ __launch_bounds__(256) void chunk_sweep_il(const double* src, long ld
   chunk_sweep<P, M, T>(f, rec, bd.c[0]);
   T pa[P], pb[P];
   chunk_parts<P, M, T>(f, bd, pa, pb);
-  Ty* yb = y + (long)k * M * ldy + s;
+  if (STORE_Y) {
+    Ty* yb = y + (long)k * M * ldy + s;
 #pragma unroll
-  for (int p = 0; p < M - P; ++p) __builtin_nontemporal_store((Ty)f[p], &yb[(long)p * ldy]);
+    for (int p = 0; p < M - P; ++p) __builtin_nontemporal_store((Ty)f[p], &yb[(long)p * ldy]);
+  }
 #pragma unroll
   for (int a = 0; a < P; ++a) {
     rho[((long)k * 2 * P + a) * batch + s] = pa[a];
     rho[((long)k * 2 * P + P + a) * batch + s] = pb[a];
+  }
+}
+
+// Second pass of a standalone solve: x holds the right-hand sides in the
+// chunk interiors (untouched by the first pass) and the solved separators in
+// the separator rows; each chunk is swept again (the same arithmetic as the
+// first pass, recomputed instead of stored and re-read) and corrected,
+// x = E_m^{-1} f - Zl s_prev - Zr s_own, in place.
+template <int P, int M>
+__global__ __launch_bounds__(256) void chunk_resolve_il(double* x, long ld, int batch, int S,
+                                                        const double* __restrict__ rec,
+                                                        BandT<double> bd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long s = (long)blockIdx.x * 64 + lane;
+  const int k = blockIdx.y * 4 + wave;
+  if (s >= batch || k >= S) return;
+  constexpr int MI = M - P;
+  const int kp = wrap_once(k - 1, S);
+  double sp[P], so[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    sp[a] = x[((long)kp * M + MI + a) * ld + s];
+    so[a] = x[((long)k * M + MI + a) * ld + s];
+  }
+  double f[M];
+  double* base = x + (long)k * M * ld + s;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) f[p] = base[(long)p * ld];
+#pragma unroll
+  for (int p = MI; p < M; ++p) f[p] = 0.0;  // not read by the interior sweep
+  chunk_sweep<P, M, double>(f, rec, bd.c[0]);
+#pragma unroll
+  for (int p = 0; p < MI; ++p) {
+    double v = f[p];
+#pragma unroll
+    for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
+    __builtin_nontemporal_store(v, &base[(long)p * ld]);
   }
 }
 
@@ -1026,13 +1066,21 @@ template <int P>
 hipError_t launch_chunked_il(const DevChunk& c, double* x, long ld, int batch, double* rho,
                              hipStream_t st, bool correct) {
   dim3 grid((batch + 63) / 64, (c.S + 3) / 4);
-  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double, double>), grid, dim3(256), 0, st, x, ld, x,
-                     ld, batch, c.S, c.rec, band_of<double>(c.coef), rho);
+  if (!correct) {  // the chunk interiors y stay for the caller to correct later
+    hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double, double>), grid, dim3(256), 0, st, x, ld,
+                       x, ld, batch, c.S, c.rec, band_of<double>(c.coef), rho);
+    return launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0, 0.0,
+                                nullptr);
+  }
+  // separator parts only; separators into the separator rows; then every
+  // chunk swept again from its right-hand side and corrected
+  hipLaunchKernelGGL((chunk_sweep_il<P, kChunk, double, double, false>), grid, dim3(256), 0, st,
+                     x, ld, x, ld, batch, c.S, c.rec, band_of<double>(c.coef), rho);
   hipError_t e = launch_reduced_il<P>(c, rho, batch, x, ld, kChunk, kChunk - P, st, nullptr, 0,
                                       0.0, nullptr);
-  if (e != hipSuccess || !correct) return e;
-  hipLaunchKernelGGL((correct_il<P, kChunk, double, double, false>), grid, dim3(256), 0, st, x, ld,
-                     x, ld, batch, c.S, c.rec);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((chunk_resolve_il<P, kChunk>), grid, dim3(256), 0, st, x, ld, batch, c.S,
+                     c.rec, band_of<double>(c.coef));
   return hipGetLastError();
 }
 
