@@ -60,13 +60,19 @@ def reduced_bytes(nx, ny):
     return 8 * 4 * sc * nx + 8 * 2 * sc * nx
 
 
+# library sources that no kernel of the ADI step (nor the calibration copy)
+# is built from: the standalone stencil and the per-system batched solves
+NOT_IN_STEP = ("stencil.hip", "varband.hip")
+
+
 def source_hash():
-    """sha256 over the HIP/C++ sources of the library (what the counters
-    were taken on)."""
+    """sha256 over the HIP/C++ sources that the step's kernels, their launch
+    and tuning code and the calibration copy are built from (what the
+    counters were taken on)."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".hpp", ".cpp")) and name not in NOT_IN_STEP:
             with open(os.path.join(CSRC, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -344,6 +350,48 @@ def per_system_throughput(chx, torch, reps=10):
     out["tri_solve_factored"] = entry(timed(lambda: chx.tri_batch_solve(*tri, x, ws=fws)), 9)
     out["finite"] = bool(torch.isfinite(x).all())
     del tri, fws, x, f
+    return out
+
+
+def stencil_throughput(chx, torch, n=8192, reps=20):
+    """The standalone 2D stencil (Ch.3 API) on an n x n FP64 field, input and
+    output separate: the 5-point Laplacian, the same applied to c^3 - c (the
+    non-linear Cahn-Hilliard term), a full 5 x 5 stencil, the 8th-order second
+    derivative in x of the Ch.3 example (non-periodic) and a full 9 x 9
+    stencil.  Algorithmic bytes: 16 per point (each input read once, each
+    output written once); flops: 2 per weight per point (every weight of the
+    rectangle is applied, zeros included)."""
+    from paper_2101_06550_amd import inputs
+    dev = dict(dtype=torch.float64, device="cuda")
+    x = torch.tensor(inputs.uniform(11, (n, n), -1, 1), **dev)
+    y = torch.empty_like(x)
+    lap = [0, 1, 0, 1, -4, 1, 0, 1, 0]
+    d8 = [-1 / 560, 8 / 315, -1 / 5, 8 / 5, -205 / 72, 8 / 5, -1 / 5, 8 / 315, -1 / 560]
+    cases = {"laplacian_5pt": (lap, (1, 1, 1, 1), True, 0),
+             "laplacian_of_c3_minus_c": (lap, (1, 1, 1, 1), True, 1),
+             "full_5x5": (list(inputs.uniform(12, (25,), -1, 1)), (2, 2, 2, 2), True, 0),
+             "x_8th_order_nonperiodic": (d8, (4, 4, 0, 0), False, 0),
+             "full_9x9": (list(inputs.uniform(13, (81,), -1, 1)), (4, 4, 4, 4), True, 0)}
+    out = {"n": n}
+    for name, (w, ext, per, pm) in cases.items():
+        def run():
+            chx.stencil2d_apply(x, y, w, *ext, periodic=per, premap=pm)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = 16.0 * n * n / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "points_per_s": n * n / (ms * 1e-3),
+                     "effective_GBps": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "fp64_TFLOPs": round(2.0 * len(w) * n * n / (ms * 1e-3) / 1e12, 2)}
+    out["finite"] = bool(torch.isfinite(y).all())
+    del x, y
     return out
 
 
@@ -727,7 +775,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--only", choices=["solves", "per_system", "ensemble", "precision", "small",
                                        "tuning", "p2",
-                                       "table31", "batch1d", "cook"],
+                                       "table31", "batch1d", "cook", "stencil"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -760,7 +808,8 @@ def main():
                   "per_system": "batched solves with one matrix per system, n = 1024, "
                                 "65536 systems",
                   "batch1d": "batched 1D schemes (Cahn-Hilliard 2^20 x 256, hyperdiffusion "
-                             "65536 x 1024)"}
+                             "65536 x 1024)",
+                  "stencil": "standalone 2D stencils on 8192 x 8192, FP64"}
         cmd = ("rocprofv3 --kernel-trace --stats -d " + os.path.relpath(tdir) + " -o run "
                "--output-format csv -- python3 bench.py --only " + only)
         summarize_leg(tdir, out, titles.get(only, only), cmd, args.trace_note)
@@ -792,6 +841,7 @@ def main():
               "ensemble": ensemble_throughput,
               "small": small_run, "tuning": tuning_sweep, "p2": p2_run,
               "table31": table31_run, "batch1d": batch1d_run, "cook": cook_run,
+              "stencil": stencil_throughput,
               "precision": lambda c, t: {
                   "solves": solve_precision(c, t), "run_1024": precision_run(c, t)}}[args.only]
         print(json.dumps({args.only: fn(chx, torch)}), flush=True)
@@ -876,6 +926,8 @@ def main():
         extra["batched_1d"] = batch1d_run(chx, torch)
         log("Cahn-Hilliard-Cook forcing")
         extra["cook_forced_8192"] = cook_run(chx, torch)
+        log("standalone 2D stencils")
+        extra["stencil_8192"] = stencil_throughput(chx, torch)
     if not args.no_solves:
         log("standalone batched solves")
         extra["penta_solve_N1024_batch131072"] = solve_throughput(chx, torch)

@@ -41,6 +41,11 @@ constexpr int kThreads = 256;
 #define CHX_VB_U 8
 #endif
 constexpr int kU = CHX_VB_U;  // rows staged per batch of loads
+// The solve kernels stage fewer rows: with one system per thread the batch
+// gives one wave per SIMD, and at 65536 systems x 1024 both factored solves
+// ran fastest at 6 (penta 1.46 ms against 1.84 ms at 8; tri 0.89 against
+// 1.07), while the fused factor-and-solve kernels were best at 8.
+constexpr int kUS = 6;
 
 // ---------------------------------------------------------------------------
 // Pentadiagonal.  Row i: a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} +
@@ -181,7 +186,7 @@ __device__ __forceinline__ void penta_minv(const PentaTail& tl, const PentaFwd& 
 }
 
 // Back sweep R x = g - (L^{-1}k) t over rows m-1..0; x holds g on entry.
-template <bool PER>
+template <int U, bool PER>
 __device__ __forceinline__ void penta_back(int m, long s, const double* __restrict__ gam,
                                            long ldg, const double* __restrict__ del, long ldd,
                                            const double* __restrict__ pk0,
@@ -189,10 +194,10 @@ __device__ __forceinline__ void penta_back(int m, long s, const double* __restri
                                            double t1, double* __restrict__ x, long ld) {
   double x1 = 0.0, x2 = 0.0;
   int i = m - 1;
-  for (; i + 1 >= kU; i -= kU) {
-    double vg[kU], vga[kU], vde[kU], vp[kU], vq[kU];
+  for (; i + 1 >= U; i -= U) {
+    double vg[U], vga[U], vde[U], vp[U], vq[U];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < U; ++u) {
       const long r = i - u;
       vg[u] = x[r * ld + s];
       vga[u] = gam[r * ldg + s];
@@ -203,7 +208,7 @@ __device__ __forceinline__ void penta_back(int m, long s, const double* __restri
       }
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < U; ++u) {
       double v = vg[u];
       if (PER) v = v - vp[u] * t0 - vq[u] * t1;
       v = v - vga[u] * x1 - vde[u] * x2;
@@ -310,10 +315,10 @@ __global__ __launch_bounds__(kThreads) void penta_batch_solve_k(
   const double* w1 = PER ? ws + (long)m * ldw : nullptr;
   double g1 = 0.0, g2 = 0.0, s0 = 0.0, s1 = 0.0;
   int i = 0;
-  for (; i + kU <= m; i += kU) {
-    double va[kU], vb[kU], vc[kU], vf[kU], vw0[kU], vw1[kU];
+  for (; i + kUS <= m; i += kUS) {
+    double va[kUS], vb[kUS], vc[kUS], vf[kUS], vw0[kUS], vw1[kUS];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUS; ++u) {
       const long r = (long)(i + u) * ld + s;
       va[u] = a[r];
       vb[u] = b[r];
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void penta_batch_solve_k(
       }
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUS; ++u) {
       const double eps = (i + u >= 2) ? va[u] : 0.0;
       const double g = (vf[u] - eps * g2 - vb[u] * g1) * vc[u];
       x[(long)(i + u) * ld + s] = g;
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void penta_batch_solve_k(
     t0 = mv[s] * r0 + mv[ldw + s] * r1;
     t1 = mv[2 * ldw + s] * r0 + mv[3 * ldw + s] * r1;
   }
-  penta_back<PER>(m, s, d, ld, e, ld, PER ? ws + 2L * m * ldw : nullptr,
+  penta_back<kUS, PER>(m, s, d, ld, e, ld, PER ? ws + 2L * m * ldw : nullptr,
                   PER ? ws + 3L * m * ldw : nullptr, ldw, t0, t1, x, ld);
   if (PER) {
     x[(long)(n - 2) * ld + s] = t0;
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(kThreads) void penta_batch_rewrite_k(
     t0 = mi[0] * r0 + mi[1] * r1;
     t1 = mi[2] * r0 + mi[3] * r1;
   }
-  penta_back<PER>(m, s, gm, ldw, dl, ldw, p0, p1, ldw, t0, t1, x, ld);
+  penta_back<kU, PER>(m, s, gm, ldw, dl, ldw, p0, p1, ldw, t0, t1, x, ld);
   if (PER) {
     x[(long)(n - 2) * ld + s] = t0;
     x[(long)(n - 1) * ld + s] = t1;
@@ -484,23 +489,23 @@ __device__ __forceinline__ void tri_fwd_row(int i, int n, double ra, double rb, 
 }
 
 // x_i = (y_i - phi z_i) - chat_i x_{i+1}, rows n-1..0; x holds y on entry.
-template <bool PER>
+template <int U, bool PER>
 __device__ __forceinline__ void tri_back(int n, long s, const double* __restrict__ ch, long ldc,
                                          const double* __restrict__ zu, long ldw, double phi,
                                          double* __restrict__ x, long ld) {
   double x1 = 0.0;
   int i = n - 1;
-  for (; i + 1 >= kU; i -= kU) {
-    double vy[kU], vc[kU], vz[kU];
+  for (; i + 1 >= U; i -= U) {
+    double vy[U], vc[U], vz[U];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < U; ++u) {
       const long r = i - u;
       vy[u] = x[r * ld + s];
       vc[u] = ch[r * ldc + s];
       if (PER) vz[u] = zu[r * ldw + s];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < U; ++u) {
       double v = vy[u];
       if (PER) v = v - phi * vz[u];
       v = v - vc[u] * x1;
@@ -557,10 +562,10 @@ __global__ __launch_bounds__(kThreads) void tri_batch_solve_k(int n, int batch, 
   const double* wv = PER ? ws + (long)n * ldw : nullptr;
   double y1 = 0.0, sy = 0.0;
   int i = 0;
-  for (; i + kU <= n; i += kU) {
-    double va[kU], vb[kU], vf[kU], vw[kU];
+  for (; i + kUS <= n; i += kUS) {
+    double va[kUS], vb[kUS], vf[kUS], vw[kUS];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUS; ++u) {
       const long r = (long)(i + u) * ld + s;
       va[u] = a[r];
       vb[u] = b[r];
@@ -568,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_solve_k(int n, int batch, 
       if (PER) vw[u] = wv[(long)(i + u) * ldw + s];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kUS; ++u) {
       const double ai = (i + u >= 1) ? va[u] : 0.0;
       const double y = (vf[u] - ai * y1) * vb[u];
       x[(long)(i + u) * ld + s] = y;
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_solve_k(int n, int batch, 
     y1 = y;
   }
   const double phi = PER ? sy * ws[2L * n * ldw + s] : 0.0;
-  tri_back<PER>(n, s, c, ld, PER ? ws : nullptr, ldw, phi, x, ld);
+  tri_back<kUS, PER>(n, s, c, ld, PER ? ws : nullptr, ldw, phi, x, ld);
 }
 
 template <bool PER>
@@ -631,7 +636,7 @@ __global__ __launch_bounds__(kThreads) void tri_batch_rewrite_k(
     if (PER) zu[rw] = z;
   }
   const double phi = PER ? st.sy / (1.0 + st.sz) : 0.0;
-  tri_back<PER>(n, s, chv, ldw, zu, ldw, phi, x, ld);
+  tri_back<kU, PER>(n, s, chv, ldw, zu, ldw, phi, x, ld);
 }
 
 // ---------------------------------------------------------------------------

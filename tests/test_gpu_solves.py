@@ -197,6 +197,11 @@ def test_repeatable_bitwise(chx):
 STENCIL_CASES = [
     ((64, 64), (1, 1, 1, 1), 1, 0), ((70, 33), (2, 1, 0, 3), 1, 1), ((128, 200), (4, 4, 4, 4), 1, 0),
     ((65, 17), (0, 2, 2, 0), 0, 0), ((40, 130), (3, 3, 1, 1), 0, 1), ((5, 7), (2, 2, 2, 2), 1, 1),
+    # fields smaller than the extent (repeated wrap), ragged tiles, one-sided
+    # extents in every class
+    ((3, 2), (4, 4, 4, 4), 1, 0), ((2, 200), (2, 2, 4, 4), 1, 0), ((1, 1), (1, 1, 1, 1), 1, 1),
+    ((130, 65), (0, 3, 2, 1), 1, 1), ((67, 129), (4, 0, 0, 4), 0, 0),
+    ((129, 191), (1, 4, 3, 0), 1, 0), ((64, 64), (0, 0, 0, 0), 1, 0),
 ]
 
 
@@ -216,6 +221,39 @@ def test_stencil_parity(chx, orc, shape, ext, periodic, premap):
                         bottom, periodic=bool(periodic), premap=premap,
                         out=np.full(shape, 3.5))
     np.testing.assert_allclose(xo.cpu().numpy(), ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("ext,premap", [((1, 1, 1, 1), 1), ((2, 2, 2, 2), 0), ((4, 4, 4, 4), 0),
+                                         ((3, 0, 4, 1), 1)])
+def test_stencil_full_size_sampled(chx, orc, ext, premap):
+    """The benchmark's 8192 x 8192 periodic field: windows around sampled
+    points (the four corners, tile edges, interior points) cut out of the
+    field with periodic wrap, solved by the oracle as non-periodic stencils,
+    whose interior equals the periodic result at those points."""
+    n = 8192
+    left, right, top, bottom = ext
+    print(f"[case] stencil 8192^2 ext={ext} premap={premap}", flush=True)
+    x = inputs.uniform(21, (n, n), -1, 1)
+    w = inputs.uniform(22, ((top + bottom + 1) * (left + right + 1),), -1, 1)
+    xin = torch.tensor(x, device="cuda")
+    xo = torch.empty_like(xin)
+    chx.stencil2d_apply(xin, xo, list(w), left, right, top, bottom, periodic=True, premap=premap)
+    torch.cuda.synchronize()
+    del xin
+    half = 6
+    for jc, ic in [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (63, 64), (64, 63),
+                   (4095, 4160), (5000, 127), (8127, 8128)]:
+        rows = np.arange(jc - half - top, jc + half + bottom + 1) % n
+        cols = np.arange(ic - half - left, ic + half + right + 1) % n
+        win = x[np.ix_(rows, cols)]
+        ref = orc.stencil2d(win, w.reshape(top + bottom + 1, left + right + 1), left, right, top,
+                            bottom, periodic=False, premap=premap,
+                            out=np.zeros_like(win))[top:top + 2 * half + 1,
+                                                    left:left + 2 * half + 1]
+        orows = np.arange(jc - half, jc + half + 1) % n
+        ocols = np.arange(ic - half, ic + half + 1) % n
+        got = xo[torch.tensor(orows, device="cuda")][:, torch.tensor(ocols, device="cuda")]
+        np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=0, atol=1e-13)
 
 
 def test_stencil_eighth_order_example(chx):
