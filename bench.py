@@ -195,7 +195,7 @@ def summarize_leg(trace_dir, out_path, title, command, note):
                 with open(os.path.join(root, f)) as fh:
                     rows += list(csv.DictReader(fh))
     def short(raw):
-        sig = raw.split("(")[0].replace("void ", "").strip()
+        sig = raw.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
         if sig.startswith("chx::"):  # this library: keep the template arguments
             return sig[len("chx::"):]
         base = sig.split("<")[0].split("::")[-1]

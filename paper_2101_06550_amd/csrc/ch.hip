@@ -827,6 +827,129 @@ __global__ __launch_bounds__(256) void ch2_update(const double* c, long ldc, con
   out[(long)j * ld + i] = (2.0 * vc - vp) + vv;
 }
 
+// The same right-hand side and column chunk sweep in column-streaming form:
+// one wave per 60 output columns of one 32-row chunk.  The wave's 64 lanes
+// hold columns i0 - 2 .. i0 + 61 (periodically wrapped), so the x-neighbours
+// at distance 1 and 2 of the 60 output lanes (2 .. 61) come from DPP lane
+// shifts, with no LDS and no barrier; every lane walks the chunk's rows and
+// two halo rows on each side, issuing the loads of row t + kPf2 while it works
+// on row t, and sweeps its own column in registers.  The arithmetic is that of
+// ch2_rhs + chunk_sweep, in the same order.
+constexpr int kSeg2 = 60;  // output columns per wave
+constexpr int kPf2 = 8;    // rows of loads in flight ahead of the row being worked
+
+template <bool UPD, bool RECON>
+__global__ __launch_bounds__(256) void ch2_column_pass(
+    const double* __restrict__ c, long ld, const double* __restrict__ cp, long ldp,
+    const double* __restrict__ v, long ldv, double* __restrict__ cnew, long ldn,
+    double* __restrict__ r, long ldr, int nx, int ny, Ch2Coef K, int Sc,
+    const double* __restrict__ rec, const double* __restrict__ srec, BandT<double> sbd,
+    double* __restrict__ rhop) {
+  constexpr int Q = M + 4;  // rows kc M - 2 .. kc M + M + 1
+  const int lane = threadIdx.x & 63;
+  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (seg >= (nx + kSeg2 - 1) / kSeg2) return;  // no barrier in this kernel
+  const int kc = blockIdx.y;
+  int i = (seg * kSeg2 - 2 + lane) % nx;
+  i += (i < 0) ? nx : 0;
+  const int io = seg * kSeg2 + lane - 2;
+  const bool own = lane >= 2 && lane < 62 && io < nx;
+
+  auto row = [&](int t) -> long {
+    int j = kc * M - 2 + t;
+    j += (j < 0) ? ny : 0;
+    j -= (j >= ny) ? ny : 0;
+    return j;
+  };
+  // separator rows (final values) of the chunks kc - 1, kc, kc + 1
+  double tp[P] = {}, to[P] = {}, tn[P] = {};
+  if (RECON) {
+    const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      tp[a] = v[((long)kcm * M + MI + a) * ldv + i];
+      to[a] = v[((long)kc * M + MI + a) * ldv + i];
+      tn[a] = v[((long)kcp * M + MI + a) * ldv + i];
+    }
+  }
+  double lc[Q], lp[Q], lv[Q];
+  auto load = [&](int t) {
+    const long j = row(t);
+    lc[t] = c[j * ld + i];
+    lp[t] = cp[j * ldp + i];
+    lv[t] = UPD ? v[j * ldv + i] : 0.0;
+  };
+#pragma unroll
+  for (int t = 0; t < kPf2; ++t) load(t);
+
+  double C[Q], Pv[Q], B[Q], U[Q], BL[Q], BR[Q], f[M];
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    if (t + kPf2 < Q) load(t + kPf2);
+    // row t: state update (with the deferred column correction of v)
+    double vc = lc[t], vp = lp[t];
+    if (UPD) {
+      double vv = lv[t];
+      if (RECON && t >= 2) {
+        // own rows: chunk kc, position t - 2; the two rows below: chunk kc + 1,
+        // positions 0 and 1; the two rows above are kc - 1's separators
+        const bool below = t >= M + 2;
+        const int pp = below ? t - M - 2 : t - 2;
+        if (pp < MI) {
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            vv = vv - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
+                 rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+        }
+      }
+      const double vn = (2.0 * vc - vp) + vv;
+      vp = vc;
+      vc = vn;
+      if (t >= 2 && t < M + 2 && own)
+        __builtin_nontemporal_store(vn, &cnew[((long)kc * M + t - 2) * ldn + io]);
+    }
+    C[t] = vc;
+    Pv[t] = vp;
+    B[t] = 2.0 * vc - vp;
+    U[t] = vc * vc * vc - vc;
+    BL[t] = dpp_from_left(B[t], B[t]);
+    BR[t] = dpp_from_right(B[t], B[t]);
+    if (t >= 4) {  // right-hand side of row w = t - 2 (own row w - 2)
+      const int w = t - 2;
+      const double BL2 = dpp_from_left(BL[w], BL[w]), BR2 = dpp_from_right(BR[w], BR[w]);
+      const double CL = dpp_from_left(C[w], C[w]), CR = dpp_from_right(C[w], C[w]);
+      const double mu_l = CL * CL * CL - CL, mu_r = CR * CR * CR - CR;
+      const double d4x = (BL2 - 4.0 * BL[w] + 6.0 * B[w] - 4.0 * BR[w] + BR2) * K.inv_dx4;
+      const double d4y =
+          (B[w - 2] - 4.0 * B[w - 1] + 6.0 * B[w] - 4.0 * B[w + 1] + B[w + 2]) * K.inv_dy4;
+      const double dyy_w = BL[w + 1] + BL[w - 1] - 2.0 * BL[w];
+      const double dyy_c = B[w + 1] + B[w - 1] - 2.0 * B[w];
+      const double dyy_e = BR[w + 1] + BR[w - 1] - 2.0 * BR[w];
+      const double dxxyy = (dyy_e + dyy_w - 2.0 * dyy_c) * K.inv_dx2dy2;
+      const double bih = d4x + 2.0 * dxxyy + d4y;
+      const double lap = (mu_r + mu_l - 2.0 * U[w]) * K.inv_dx2 +
+                         (U[w + 1] + U[w - 1] - 2.0 * U[w]) * K.inv_dy2;
+      f[w - 2] = -(2.0 / 3.0) * (C[w] - Pv[w]) - K.a * bih + K.b * lap;
+    }
+    // this row's values are complete here and the next row's loads are issued
+    // after this point (empty volatile asms keep their order)
+    asm volatile("" : "+v"(B[t]), "+v"(BL[t]), "+v"(BR[t]), "+v"(U[t]), "+v"(C[t]),
+                 "+v"(Pv[t])::"memory");
+    if (t >= 4) asm volatile("" : "+v"(f[t - 4]));
+  }
+  chunk_sweep<P, M, double>(f, srec, sbd.c[0]);
+  double pa[P], pb[P];
+  chunk_parts<P, M, double>(f, sbd, pa, pb);
+  if (!own) return;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) __builtin_nontemporal_store(f[p], &r[((long)kc * M + p) * ldr + io]);
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    rhop[((long)kc * 2 * P + a) * nx + io] = pa[a];
+    rhop[((long)kc * 2 * P + P + a) * nx + io] = pb[a];
+  }
+}
+
 hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, const double* v,
                           long ldv, double* cnew, long ldn, double* r, long ldr, int nx, int ny,
                           const Ch2Coef& K, const DevChunk* recon, const DevChunk* sweep,
@@ -843,7 +966,25 @@ hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, 
 #define CHX_CH2(U, R, W)                                                                        \
   hipLaunchKernelGGL((ch2_rhs<U, R, W>), grid, dim3(kT2T), 0, st, c, ld, cp, ldp, v, ldv, cnew, \
                      ldn, r, ldr, nx, ny, K, Sc, rec, srec, sbd, rho)
-  if (sweep) {
+  // the column-streaming kernel runs one wave per (60-column segment, chunk):
+  // it takes over once that fills every SIMD twice; smaller grids keep the
+  // tile kernel, whose eight waves per 64 x 32 tile fill the chip sooner
+  // (1024 x 1024: 0.039 ms per step with it, 0.043 with the column kernel)
+  const bool columns = sweep && (long)((nx + kSeg2 - 1) / kSeg2) * sweep->S >= 2048;
+  if (columns) {
+    const int Scol = sweep->S;
+    if ((long)Scol * M != ny || (recon && recon->S != Scol)) return hipErrorInvalidValue;
+    // blocks in chunk-row order (measured: banding whole chunk rows onto one
+    // XCD, so shared halo rows meet in one L2, was 3-4 % slower)
+    const dim3 g2((unsigned)(((nx + kSeg2 - 1) / kSeg2 + 3) / 4), (unsigned)Scol);
+#define CHX_CH2C(U, R)                                                                       \
+  hipLaunchKernelGGL((ch2_column_pass<U, R>), g2, dim3(256), 0, st, c, ld, cp, ldp, v, ldv, cnew, \
+                     ldn, r, ldr, nx, ny, K, Scol, rec, srec, sbd, rho)
+    if (v && recon) CHX_CH2C(true, true);
+    else if (v) CHX_CH2C(true, false);
+    else CHX_CH2C(false, false);
+#undef CHX_CH2C
+  } else if (sweep) {
     if (v && recon) CHX_CH2(true, true, true);
     else if (v) CHX_CH2(true, false, true);
     else CHX_CH2(false, false, true);

@@ -77,6 +77,27 @@ def test_steps_in_one_call_vs_oracle(chx, orc):
     assert abs(dd[-1, 1] - orc.ch_energy(ref, L, L, 0.01)) < 1e-11 * abs(dd[-1, 1])
 
 
+@pytest.mark.parametrize("ny,nx,dt", [(96, 192, 1e-4), (32, 100, 1e-4), (64, 4096, 1e-6),
+                                      (256, 61, 1e-4), (128, 120, 1e-4), (64, 64, 1e-4),
+                                      (2048, 2000, 1e-6)])
+def test_steps_across_chunks_and_segments(chx, orc, ny, nx, dt):
+    """Several steps (the state update and deferred column correction of
+    every later step) on grids with 1 to 64 32-row chunks and widths that are
+    and are not multiples of 60 columns, from two independent rough states;
+    the largest grid (64 chunks x 34 segments of 60 columns, the last one
+    ragged) runs the column-streaming kernel, the others the tile kernel."""
+    c0 = inputs.noise_field(ny, nx, 21)
+    cp0 = inputs.noise_field(ny, nx, 22)
+    h = p2(chx, nx, ny, dt=dt)
+    c, cp = torch.tensor(c0, device="cuda"), torch.tensor(cp0, device="cuda")
+    print(f"[case] P2 four steps {ny}x{nx}", flush=True)
+    chx.ch_adi_step_p2(h, c, cp, nsteps=4)
+    torch.cuda.synchronize()
+    ref, ref_prev = orc.ch2_step(c0, cp0, L, L, 1.0, 0.01, dt, nsteps=4)
+    assert rel(c.cpu().numpy(), ref) < 4 * tol(nx, ny, dt=dt)
+    assert rel(cp.cpu().numpy(), ref_prev) < 4 * tol(nx, ny, dt=dt)
+
+
 def test_leading_dimension(chx, orc):
     c0 = inputs.noise_field(64, 128, 12)
     cp0 = inputs.noise_field(64, 128, 13)
@@ -110,15 +131,18 @@ def test_schemes_are_not_interchangeable(chx):
         chx.ch_create(64, 64, L, L, 1.0, 0.01, 1e-4, scheme=7)
 
 
-def test_large_run_one_step(chx, orc):
+def test_large_run_two_steps(chx, orc):
+    """The benchmark's 8192 x 8192 grid: the first step and one later step
+    (state update and column correction fused into the right-hand side)."""
     n = 8192
     c0 = inputs.mode_plus_noise(n, 5)
     h = p2(chx, n, n, g=0.001, dt=1e-6)
     c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
-    print("[case] P2 8192 one step", flush=True)
-    chx.ch_adi_step_p2(h, c, cp, nsteps=1)
+    print("[case] P2 8192 two steps", flush=True)
+    chx.ch_adi_step_p2(h, c, cp, nsteps=2)
     torch.cuda.synchronize()
-    ref, _ = orc.ch2_step(c0, c0, L, L, 1.0, 0.001, 1e-6)
+    ref, ref_prev = orc.ch2_step(c0, c0, L, L, 1.0, 0.001, 1e-6, nsteps=2)
     err = rel(c.cpu().numpy(), ref)
-    print(f"P2 8192 one-step error {err:.3e}")
-    assert err < tol(n, n, g=0.001, dt=1e-6)
+    print(f"P2 8192 two-step error {err:.3e}")
+    assert err < 2 * tol(n, n, g=0.001, dt=1e-6)
+    assert rel(cp.cpu().numpy(), ref_prev) < tol(n, n, g=0.001, dt=1e-6)
