@@ -917,8 +917,8 @@ __global__ __launch_bounds__(256) void ch2_column_pass(
     if (t >= 4) {  // right-hand side of row w = t - 2 (own row w - 2)
       const int w = t - 2;
       const double BL2 = dpp_from_left(BL[w], BL[w]), BR2 = dpp_from_right(BR[w], BR[w]);
-      const double CL = dpp_from_left(C[w], C[w]), CR = dpp_from_right(C[w], C[w]);
-      const double mu_l = CL * CL * CL - CL, mu_r = CR * CR * CR - CR;
+      // mu of the x-neighbours: their own C^3 - C, moved over by DPP
+      const double mu_l = dpp_from_left(U[w], U[w]), mu_r = dpp_from_right(U[w], U[w]);
       const double d4x = (BL2 - 4.0 * BL[w] + 6.0 * B[w] - 4.0 * BR[w] + BR2) * K.inv_dx4;
       const double d4y =
           (B[w - 2] - 4.0 * B[w - 1] + 6.0 * B[w] - 4.0 * B[w + 1] + B[w + 2]) * K.inv_dy4;
