@@ -823,7 +823,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); ensembles would "
-              "shard by runs and a large grid by row slabs, which this build does not run.",
+              "shard by runs and a large grid by row slabs; only one GPU is measured.",
               file=sys.stderr)
         sys.exit(2)
 
