@@ -386,6 +386,12 @@ def stencil2d_apply(inp, out, weights, left: int, right: int, top: int, bottom: 
                     stream=None) -> None:
     ny, nx = inp.shape
     ld = inp.stride(0) if ld is None else ld
+    if tuple(out.shape) != (ny, nx):
+        raise ChxError(CHX_EINVAL, "stencil2d_apply: out must have the shape of inp")
+    for t in (inp, out):  # one leading dimension serves both arrays
+        if ny > 1 and t.stride(0) != ld or nx > 1 and t.stride(1) != 1:
+            raise ChxError(CHX_EINVAL, "stencil2d_apply: inp and out must be row-major with "
+                                       "leading dimension ld")
     w = (ctypes.c_double * len(weights))(*[float(v) for v in weights])
     _check(load().stencil2d_apply(_devptr(inp, "in"), _devptr(out, "out"), nx, ny, ld, w,
                                   left, right, top, bottom, int(bool(periodic)), premap,

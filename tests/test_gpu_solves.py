@@ -256,6 +256,28 @@ def test_stencil_full_size_sampled(chx, orc, ext, premap):
         np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_stencil_leading_dimension(chx, orc, periodic):
+    """Input and output rows padded (ld = nx + 13): the stencil reads and
+    writes only the nx columns of each row."""
+    ny, nx, ld = 70, 130, 143
+    left, right, top, bottom = 2, 1, 3, 2
+    x = inputs.uniform(31, (ny, nx), -1, 1)
+    w = inputs.uniform(32, ((top + bottom + 1) * (left + right + 1),), -1, 1)
+    big_in = torch.full((ny, ld), float("nan"), dtype=torch.float64, device="cuda")
+    big_in[:, :nx] = torch.tensor(x, device="cuda")
+    big_out = torch.full((ny, ld), 3.5, dtype=torch.float64, device="cuda")
+    print(f"[case] stencil ld={ld} periodic={periodic}", flush=True)
+    chx.stencil2d_apply(big_in[:, :nx], big_out[:, :nx], list(w), left, right, top, bottom,
+                        periodic=periodic, premap=1)
+    torch.cuda.synchronize()
+    ref = orc.stencil2d(x, w.reshape(top + bottom + 1, left + right + 1), left, right, top,
+                        bottom, periodic=periodic, premap=1, out=np.full((ny, nx), 3.5))
+    o = big_out.cpu().numpy()
+    np.testing.assert_allclose(o[:, :nx], ref, rtol=0, atol=1e-13)
+    assert np.all(o[:, nx:] == 3.5)
+
+
 def test_stencil_eighth_order_example(chx):
     """Thesis Ch.3 "Standard Weights": 8th-order second derivative of sin x
     on 1024 x 512, non-periodic; interior equals -sin x, the 4 boundary

@@ -288,3 +288,22 @@ def test_ensemble_extras_reject_bad_arguments_on_host(lib):
     assert lib.ch_ensemble_moments(None, None, None, d, None) == chx.CHX_EINVAL
     assert lib.ch_ensemble_k1(None, None, None, d, None) == chx.CHX_EINVAL
     assert lib.ch_ensemble_step(None, None, None, 1, None, None, 0, 0, None) == chx.CHX_EINVAL
+
+
+def test_stencil_binding_rejects_mismatched_layouts():
+    """One leading dimension serves input and output: a padded input with a
+    packed output (or any other mismatch) is refused before the library is
+    called."""
+    import torch
+    from paper_2101_06550_amd import chx
+    big = torch.zeros((8, 16), dtype=torch.float64)
+    w = [1.0] * 9
+    with pytest.raises(chx.ChxError, match="leading dimension"):
+        chx.stencil2d_apply(big[:, :10], torch.zeros((8, 10), dtype=torch.float64), w, 1, 1, 1, 1)
+    with pytest.raises(chx.ChxError, match="leading dimension"):
+        chx.stencil2d_apply(torch.zeros((8, 10), dtype=torch.float64), big[:, :10], w, 1, 1, 1, 1)
+    with pytest.raises(chx.ChxError, match="shape of inp"):
+        chx.stencil2d_apply(torch.zeros((8, 10), dtype=torch.float64),
+                            torch.zeros((8, 11), dtype=torch.float64), w, 1, 1, 1, 1)
+    with pytest.raises(chx.ChxError, match="leading dimension"):  # column-strided view
+        chx.stencil2d_apply(big[:, ::2], torch.zeros((8, 8), dtype=torch.float64), w, 1, 1, 1, 1)
