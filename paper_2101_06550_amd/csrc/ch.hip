@@ -968,10 +968,8 @@ hipError_t launch_ch2_rhs(const double* c, long ld, const double* cp, long ldp, 
                      ldn, r, ldr, nx, ny, K, Sc, rec, srec, sbd, rho)
   // the column-streaming kernel runs one wave per (60-column segment, chunk):
   // it takes over once that fills every SIMD twice; smaller grids keep the
-  // tile kernel, whose eight waves per 64 x 32 tile fill the chip sooner.
-  // Measured per step: 2048^2 (2240 waves) 0.075 ms column vs 0.074 tile,
-  // 4096^2 0.216 vs 0.243, 8192^2 0.818 vs 0.918; 1024^2 (576 waves) 0.043
-  // column vs 0.039 tile.
+  // tile kernel, whose eight waves per 64 x 32 tile fill the chip sooner
+  // (1024 x 1024: 0.039 ms per step with it, 0.043 with the column kernel)
   const bool columns = sweep && (long)((nx + kSeg2 - 1) / kSeg2) * sweep->S >= 2048;
   if (columns) {
     const int Scol = sweep->S;
