@@ -4,6 +4,7 @@ single Fourier modes against the exact two-step recurrence of the discrete
 symbols, mass conservation, the start C^{-1} = C^0, and the first-order time
 accuracy the thesis reports for it (Table 3.1)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -97,3 +98,75 @@ def test_first_order_in_time(orc):
     errs = [np.max(np.abs(run(T / m) - ref)) for m in (160, 320, 640)]
     rates = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
     assert all(0.85 < r < 1.2 for r in rates), rates
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table31():
+    rows, par = {}, {}
+    with open(os.path.join(GOLDEN, "table31_convergence.txt")) as f:
+        for ln in f:
+            ln = ln.split("#", 1)[0].split()
+            if len(ln) == 3:
+                rows[int(ln[0])] = (float(ln[1]), float(ln[2]))
+            elif len(ln) == 2:
+                par[ln[0]] = float(ln[1])
+    return rows, par
+
+
+def _bubble_run(orc, n, par):
+    """The Table 3.1 run at N x N: C0 = eps tanh(r - pi), r measured from the
+    centre (pi, pi), to T with dt = 0.1 dx (rounded to whole steps ending at T)."""
+    dx = L / n
+    steps = int(round(par["T"] / (par["dt_over_dx"] * dx)))
+    dt = par["T"] / steps
+    x = np.arange(n) * dx
+    r = np.sqrt((x[None, :] - math.pi) ** 2 + (x[:, None] - math.pi) ** 2)
+    c0 = par["eps"] * np.tanh(r - math.pi)
+    c, _ = orc.ch2_step(c0, c0, L, L, par["D"], par["gamma"], dt, nsteps=steps)
+    return c
+
+
+def _e_n(fine, coarse):
+    """Ch.2 eq. 2:converge2D: the 2 x 2 average of the fine field at the coarse
+    points, its absolute difference from the coarse field, averaged over the
+    domain (the sum times dx_{N/2}^2 divided by the area)."""
+    avg = 0.25 * (fine[0::2, 0::2] + fine[0::2, 1::2] + fine[1::2, 0::2] + fine[1::2, 1::2])
+    return float(np.mean(np.abs(avg - coarse)))
+
+
+def test_table31_printed_errors(orc):
+    """The printed E_128, E_256 and the rate between them (Table 3.1) from the
+    oracle's scheme run at N = 64, 128, 256: a dropped term, a wrong sign or a
+    missing 2/3 changes the coarsened state at T = 10 far beyond 1 %."""
+    rows, par = _table31()
+    f = {n: _bubble_run(orc, n, par) for n in (64, 128, 256)}
+    e128, e256 = _e_n(f[128], f[64]), _e_n(f[256], f[128])
+    assert abs(e128 - rows[128][0]) <= 0.01 * rows[128][0], e128
+    assert abs(e256 - rows[256][0]) <= 0.01 * rows[256][0], e256
+    assert abs(math.log2(e128 / e256) - rows[128][1]) <= 0.01, math.log2(e128 / e256)
+
+
+def test_two_correct_steps_differ_by_eps_times_condition(orc):
+    """The scale behind the P2 GPU tolerance: from rough states (independent
+    noise for C^n and C^{n-1}) the right-hand side holds the stiff biharmonic
+    of 2C^n - C^{n-1}, which the implicit solve cancels again, so two correct
+    FP64 evaluations of one step (the oracle's LR sweeps and the Fourier-space
+    solve) differ by a modest multiple of eps (1 + 16 s'); at the 8192-point
+    rows of the large workload (gamma = 0.001, dt = 1e-6: s' = 1926) that is
+    about 7e-12, while from the workload's own smooth state it stays near
+    rounding of the result."""
+    ny, nx, g, dt = 32, 8192, 0.001, 1e-6
+    s = 2.0 / 3.0 * g * dt / (L / nx) ** 4
+    unit = 2.220446049250313e-16 * (1 + 16 * s)
+    c, cp = inputs.noise_field(ny, nx, 5), inputs.noise_field(ny, nx, 6)
+    out, _ = orc.ch2_step(c, cp, L, L, 1.0, g, dt)
+    e = np.max(np.abs(out - fft_step(c, cp, 1.0, g, dt))) / np.max(np.abs(out))
+    assert 0.3 * unit < e < 3 * unit, (e, unit)
+    x = np.arange(nx) * L / nx
+    y = np.arange(ny) * L / ny
+    sm = 0.05 * np.sin(3 * x[None, :]) * np.sin(5 * y[:, None]) + 0.02 * (c - 0.5) / 10
+    out, _ = orc.ch2_step(sm, sm, L, L, 1.0, g, dt)
+    e_smooth = np.max(np.abs(out - fft_step(sm, sm, 1.0, g, dt))) / np.max(np.abs(out))
+    assert e_smooth < 0.2 * unit, (e_smooth, unit)
