@@ -518,17 +518,16 @@ def p2_run(chx, torch):
     return out
 
 
-def table31_run(chx, torch, sizes=(64, 128, 256, 512, 1024, 2048, 4096), T=10.0,
-                eps_values=(1e-6, 1.0)):
+def table31_run(chx, torch, sizes=(64, 128, 256, 512, 1024, 2048, 4096, 8192), T=10.0,
+                eps=1e-6):
     """The convergence study of Table 3.1 with the thesis's scheme on the GPU:
-    C(x, 0) = eps tanh(r - pi), r = |x|, D = 1, gamma = 0.01, to T = 10 with
+    C(x, 0) = eps tanh(r - pi) with r the distance from the box's centre
+    (pi, pi) and eps = 1e-6 as printed, D = 1, gamma = 0.01, to T = 10 with
     dt = 0.1 dx (rounded to a whole number of steps ending exactly at T), and
-    E_N = mean over the coarse cells of |(2 x 2 average of C_N) - C_{N/2}|;
-    eps = 1e-6 as printed, and eps = 1 (an interface of full amplitude)."""
-    return {f"eps_{e:g}": _table31_one(chx, torch, sizes, T, e) for e in eps_values}
-
-
-def _table31_one(chx, torch, sizes, T, eps):
+    E_N = mean over the coarse cells of |(2 x 2 average of C_N) - C_{N/2}|
+    (Ch.2 eq. 2:converge2D); the printed column is reported beside it."""
+    printed = {128: 0.1510, 256: 0.0246, 512: 0.0116, 1024: 0.0057, 2048: 0.0028,
+               4096: 0.0014, 8192: 0.0007}
     L = 2 * math.pi
     fields, out = {}, {}
     for n in sizes:
@@ -536,23 +535,29 @@ def _table31_one(chx, torch, sizes, T, eps):
         steps = int(round(T / (0.1 * dx)))
         dt = T / steps
         x = np.arange(n) * dx
-        c0 = eps * np.tanh(np.sqrt(x[None, :] ** 2 + x[:, None] ** 2) - math.pi)
+        r = np.sqrt((x[None, :] - math.pi) ** 2 + (x[:, None] - math.pi) ** 2)
+        c0 = eps * np.tanh(r - math.pi)
         h = chx.ch_create(n, n, L, L, 1.0, 0.01, dt, scheme=chx.CHX_SCHEME_P2)
         c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        chx.ch_adi_step_p2(h, c, cp, nsteps=steps)
-        torch.cuda.synchronize()
+        done = 0
+        while done < steps:  # chunks of at most 4096 steps keep progress visible
+            k = min(4096, steps - done)
+            chx.ch_adi_step_p2(h, c, cp, nsteps=k)
+            torch.cuda.synchronize()
+            done += k
         el = time.perf_counter() - t0
         fields[n] = c.cpu().numpy()
         out[str(n)] = {"steps": steps, "dt": dt, "seconds": round(el, 3),
                        "max_abs_C": float(np.max(np.abs(fields[n])))}
-        log(f"table 3.1 run eps={eps:g} N={n}: {steps} steps in {el:.2f} s")
+        log(f"table 3.1 run N={n}: {steps} steps in {el:.2f} s")
         del c, cp, h
-    for n in sizes[1:]:
-        f, cg = fields[n], fields[n // 2]
-        avg = 0.25 * (f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2])
-        out[str(n)]["E_N"] = float(np.mean(np.abs(avg - cg)))
+        if n // 2 in fields:
+            f, cg = fields[n], fields.pop(n // 2)
+            avg = 0.25 * (f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2])
+            out[str(n)]["E_N"] = float(np.mean(np.abs(avg - cg)))
+            out[str(n)]["E_N_printed"] = printed.get(n)
     for n in sizes[1:-1]:
         out[str(n)]["log2_E_N_over_E_2N"] = math.log2(out[str(n)]["E_N"] /
                                                       out[str(2 * n)]["E_N"])
@@ -868,16 +873,28 @@ def main():
                                                               device="cuda"))
         torch.cuda.synchronize()
         del cw
-    # the timed region: K steps in one call; HIP events on the library's
-    # stream around every kernel of every `every`-th step give the per-kernel
-    # durations of this same run (sampling keeps their overhead negligible)
-    every = max(1, K // 50)
-    log(f"timing {K} steps (kernels of every {every}th step timed by events)")
+    # the timed region: K plain steps in one call (no instrumentation), the
+    # host clock around it with the device synchronised on both sides
+    log(f"timing {K} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phase_ms, phase_n = chx.ch_adi_step_timed(h, c, nsteps=K, diag_out=diag, sample_every=every)
+    chx.ch_adi_step(h, c, nsteps=K, diag_out=diag)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # then the same K steps again from the same initial state, with HIP events
+    # recorded on the library's stream around every kernel of every step
+    # (events created before the call): the per-kernel durations of the
+    # roofline; this pass is reported beside the headline, not as it
+    log(f"per-kernel event timing of the same {K} steps")
+    ct = torch.tensor(c0, device="cuda")
+    dt_ = torch.zeros_like(diag)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phase_ms, phase_n = chx.ch_adi_step_timed(h, ct, nsteps=K, diag_out=dt_, sample_every=1)
+    torch.cuda.synchronize()
+    el_timed = time.perf_counter() - t1
+    timed_same = bool(torch.equal(ct, c)) and bool(torch.equal(dt_, diag))
+    del ct, dt_
     d = diag.cpu().numpy()
     mass, energy = d[0::2], d[1::2]
     l1 = float(np.sum(np.abs(c0))) * (L / n) ** 2
@@ -996,6 +1013,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
+        "instrumented_pass": {"ms_per_step": round(1e3 * el_timed / K, 5),
+                              "bitwise_equal_to_timed_run": timed_same},
         "tuning": {"separator_kernel_shape": chx.ch_get_tuning(h),
                    "row_split_shape": split,
                    "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH)},

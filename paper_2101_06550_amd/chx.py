@@ -174,6 +174,46 @@ def _devptr(t, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _storage_elems(t) -> int:
+    """Elements of t's dtype from t's first element to the end of its storage."""
+    return t.untyped_storage().nbytes() // t.element_size() - t.storage_offset()
+
+
+def _field_ld(t, nx: int, ny: int, ld, what: str) -> int:
+    """Leading dimension of a (ny, >= nx) field with unit column stride whose
+    rows, ld apart, lie inside its storage (the kernels read and write
+    (ny - 1) * ld + nx elements from its start); ChxError otherwise."""
+    if t.dim() != 2 or t.shape[0] != ny or t.shape[1] < nx:
+        raise ChxError(CHX_EINVAL, f"{what} must be a ({ny}, >= {nx}) tensor, got "
+                                   f"{tuple(t.shape)}")
+    if nx > 1 and t.stride(1) != 1:
+        raise ChxError(CHX_EINVAL, f"{what} must have unit column stride")
+    ld = t.stride(0) if ld is None else int(ld)
+    if (ny > 1 and t.stride(0) != ld) or ld < nx:
+        raise ChxError(CHX_EINVAL, f"{what}: leading dimension {ld} must be its row stride "
+                                   f"and >= {nx}")
+    if (ny - 1) * ld + nx > _storage_elems(t):
+        raise ChxError(CHX_EINVAL, f"{what}: rows run past the end of its storage")
+    return ld
+
+
+def _field(t, nx: int, ny: int, ld, what: str):
+    """Device pointer and leading dimension of a float64 device field that
+    passes _field_ld."""
+    ld = _field_ld(t, nx, ny, ld, what)
+    return _devptr(t, what), ld
+
+
+def _diag(diag_out, count: int, what: str = "diag_out"):
+    """Device pointer of an optional float64 diagnostics buffer of >= count
+    contiguous values (null when diag_out is None)."""
+    if diag_out is None:
+        return ctypes.c_void_p(0)
+    if not diag_out.is_contiguous() or diag_out.numel() < count:
+        raise ChxError(CHX_EINVAL, f"{what} must be contiguous with >= {count} values")
+    return _devptr(diag_out, what)
+
+
 def _workspace(nbytes: int, ws, device):
     import torch
     if nbytes == 0:
@@ -259,10 +299,18 @@ def _solve(kind, plan, batch, x, ld, layout, dtype, refine_passes, ws, stream):
     lib = load()
     if ld is None:
         ld = x.stride(0) if x.dim() == 2 else (batch if layout == CHX_INTERLEAVED else plan.n)
+    if batch > 0:  # element (s, i) at i * ld + s (interleaved) or s * ld + i (contiguous)
+        span = (plan.n - 1) * ld + batch if layout == CHX_INTERLEAVED else (batch - 1) * ld + plan.n
+        if x.dim() == 2 and x.stride(-1) != 1:
+            raise ChxError(CHX_EINVAL, f"{kind}_solve_batch: x must have unit last stride")
+        if ld >= 1 and span > _storage_elems(x):
+            raise ChxError(CHX_EINVAL, f"{kind}_solve_batch: {span} elements needed from x's "
+                                       "start, its storage holds fewer")
+    xp = _devptr(x, "x")
     nbytes = getattr(lib, f"{kind}_solve_ws_bytes")(plan.handle, batch, layout, dtype,
                                                     refine_passes)
     keep, wsp, avail = _workspace(nbytes, ws, x.device)
-    st = getattr(lib, f"{kind}_solve_batch")(plan.handle, batch, _devptr(x, "x"), ld, layout,
+    st = getattr(lib, f"{kind}_solve_batch")(plan.handle, batch, xp, ld, layout,
                                              dtype, refine_passes, wsp, avail, _stream(stream))
     _check(st, f"{kind}_solve_batch")
     return keep
@@ -435,23 +483,30 @@ def ch_ws_bytes(h: CH) -> int:
     return load().ch_ws_bytes(h.handle)
 
 
+def _handle_ws(h, lib, ws, device):
+    """The caller's workspace, else one allocated on first use and cached on
+    the handle (reallocated when too small or on another device)."""
+    nbytes = lib.ch_ws_bytes(h.handle)
+    if ws is None:
+        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != device:
+            import torch
+            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ws = h._ws
+    return _workspace(nbytes, ws, device)
+
+
 def ch_adi_step(h: CH, c, nsteps: int = 1, diag_out=None, ws=None, ld: int | None = None,
                 stream=None):
     """Advance the float64 device field c (ny, nx) by nsteps in place.  The
     workspace is allocated on first use and cached on the handle unless
     given.  diag_out: optional float64 device tensor of 2*(nsteps+1)."""
     lib = load()
-    ld = c.stride(0) if ld is None else ld
-    nbytes = lib.ch_ws_bytes(h.handle)
-    if ws is None:
-        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
-            import torch
-            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
-        ws = h._ws
-    _, wsp, avail = _workspace(nbytes, ws, c.device)
-    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
-    _check(lib.ch_adi_step(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
-                           _stream(stream)), "ch_adi_step")
+    ld = _field_ld(c, h.params.nx, h.params.ny, ld, "c")
+    dptr = _diag(diag_out, 2 * (int(nsteps) + 1))
+    cp_ = _devptr(c, "c")
+    _, wsp, avail = _handle_ws(h, lib, ws, c.device)
+    _check(lib.ch_adi_step(h.handle, cp_, ld, nsteps, dptr, wsp, avail, _stream(stream)),
+           "ch_adi_step")
 
 
 def ch_adi_step_p2(h: CH, c, cprev, nsteps: int = 1, diag_out=None, ws=None,
@@ -460,19 +515,14 @@ def ch_adi_step_p2(h: CH, c, cprev, nsteps: int = 1, diag_out=None, ws=None,
     place: c = C^n, cprev = C^{n-1} on entry (a copy of C^0 to start), the
     states nsteps later on exit."""
     lib = load()
-    ld = c.stride(0) if ld is None else ld
-    if cprev.stride(0) != ld:
+    ld = _field_ld(c, h.params.nx, h.params.ny, ld, "c")
+    if _field_ld(cprev, h.params.nx, h.params.ny, None, "cprev") != ld:
         raise ChxError(CHX_EINVAL, "ch_adi_step_p2: c and cprev need one leading dimension")
-    nbytes = lib.ch_ws_bytes(h.handle)
-    if ws is None:
-        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
-            import torch
-            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
-        ws = h._ws
-    _, wsp, avail = _workspace(nbytes, ws, c.device)
-    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
-    _check(lib.ch_adi_step_p2(h.handle, _devptr(c, "c"), _devptr(cprev, "cprev"), ld, nsteps,
-                              dptr, wsp, avail, _stream(stream)), "ch_adi_step_p2")
+    dptr = _diag(diag_out, 2 * (int(nsteps) + 1))
+    cp_, pp_ = _devptr(c, "c"), _devptr(cprev, "cprev")
+    _, wsp, avail = _handle_ws(h, lib, ws, c.device)
+    _check(lib.ch_adi_step_p2(h.handle, cp_, pp_, ld, nsteps, dptr, wsp, avail,
+                              _stream(stream)), "ch_adi_step_p2")
 
 
 def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
@@ -482,18 +532,13 @@ def ch_adi_step_timed(h: CH, c, nsteps: int = 1, diag_out=None, ws=None,
     column pass, column separators, row solves, finalize/diagnostics.
     Synchronises."""
     lib = load()
-    ld = c.stride(0) if ld is None else ld
-    nbytes = lib.ch_ws_bytes(h.handle)
-    if ws is None:
-        if h._ws is None or h._ws.numel() < nbytes + 256 or h._ws.device != c.device:
-            import torch
-            h._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
-        ws = h._ws
-    _, wsp, avail = _workspace(nbytes, ws, c.device)
-    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
+    ld = _field_ld(c, h.params.nx, h.params.ny, ld, "c")
+    dptr = _diag(diag_out, 2 * (int(nsteps) + 1))
+    cp_ = _devptr(c, "c")
+    _, wsp, avail = _handle_ws(h, lib, ws, c.device)
     ms = (ctypes.c_double * 4)()
     cnt = (ctypes.c_int * 4)()
-    _check(lib.ch_adi_step_timed(h.handle, _devptr(c, "c"), ld, nsteps, dptr, wsp, avail,
+    _check(lib.ch_adi_step_timed(h.handle, cp_, ld, nsteps, dptr, wsp, avail,
                                  _stream(stream), int(sample_every), ms, cnt),
            "ch_adi_step_timed")
     return list(ms), list(cnt)
@@ -542,10 +587,12 @@ def batch1d_create(kind, n, L, dt, a, D=1.0) -> Batch1D:
 def batch1d_step(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None = None, stream=None):
     """Advance the interleaved float64 device batch x (n, batch) in place."""
     lib = load()
-    if x.dim() != 2 or x.shape[0] != b.n:
-        raise ChxError(CHX_EINVAL, "batch1d_step: x must be (n, batch)")
+    if x.dim() != 2 or x.shape[0] != b.n or (x.shape[1] > 1 and x.stride(1) != 1):
+        raise ChxError(CHX_EINVAL, "batch1d_step: x must be (n, batch) with unit column stride")
     batch = x.shape[1]
     ld = x.stride(0) if ld is None else ld
+    if (b.n > 1 and x.stride(0) != ld) or ld < batch:
+        raise ChxError(CHX_EINVAL, "batch1d_step: ld must be x's row stride")
     nbytes = lib.batch1d_ws_bytes(b.handle, batch)
     if ws is None:
         if b._ws is None or b._ws.numel() < nbytes + 256 or b._ws.device != x.device:
@@ -562,10 +609,13 @@ def batch1d_step_rewrite(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None
     """The same steps in the rewrite mode (diagonals written and every system
     factored and solved afresh each step)."""
     lib = load()
-    if x.dim() != 2 or x.shape[0] != b.n:
-        raise ChxError(CHX_EINVAL, "batch1d_step_rewrite: x must be (n, batch)")
+    if x.dim() != 2 or x.shape[0] != b.n or (x.shape[1] > 1 and x.stride(1) != 1):
+        raise ChxError(CHX_EINVAL, "batch1d_step_rewrite: x must be (n, batch) with unit "
+                                   "column stride")
     batch = x.shape[1]
     ld = x.stride(0) if ld is None else ld
+    if (b.n > 1 and x.stride(0) != ld) or ld < batch:
+        raise ChxError(CHX_EINVAL, "batch1d_step_rewrite: ld must be x's row stride")
     nbytes = lib.batch1d_rewrite_ws_bytes(b.handle, batch)
     ws, wsp, avail = _workspace(nbytes, ws, x.device)
     _check(lib.batch1d_step_rewrite(b.handle, batch, _devptr(x, "x"), ld, nsteps, wsp, avail,
@@ -608,9 +658,9 @@ def ch_get_noise_step(h: CH) -> int:
 
 def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):
     """(mass, free energy) of the device field c; synchronises the stream."""
-    ld = c.stride(0) if ld is None else ld
+    cp_, ld = _field(c, h.params.nx, h.params.ny, ld, "c")
     m, e = ctypes.c_double(), ctypes.c_double()
-    st = load().ch_diagnostics(h.handle, _devptr(c, "c"), ld, ctypes.byref(m), ctypes.byref(e),
+    st = load().ch_diagnostics(h.handle, cp_, ld, ctypes.byref(m), ctypes.byref(e),
                                _stream(stream))
     if st not in (CHX_OK, CHX_ENONFINITE):
         _check(st, "ch_diagnostics")
@@ -619,9 +669,9 @@ def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):
 
 def ch_moments(h: CH, c, ld: int | None = None, stream=None):
     """(<C>, <C^2>, s = 1/(1 - <C^2>)) by Simpson's rule; synchronises."""
-    ld = c.stride(0) if ld is None else ld
+    cp_, ld = _field(c, h.params.nx, h.params.ny, ld, "c")
     out = (ctypes.c_double * 3)()
-    st = load().ch_moments(h.handle, _devptr(c, "c"), ld, out, _stream(stream))
+    st = load().ch_moments(h.handle, cp_, ld, out, _stream(stream))
     if st not in (CHX_OK, CHX_ENONFINITE):
         _check(st, "ch_moments")
     return out[0], out[1], out[2]
@@ -629,9 +679,9 @@ def ch_moments(h: CH, c, ld: int | None = None, stream=None):
 
 def ch_k1(h: CH, c, ld: int | None = None, stream=None) -> float:
     """k1 = sum |C^|^2 / sum |k|^-1 |C^|^2 (k != 0); synchronises."""
-    ld = c.stride(0) if ld is None else ld
+    cp_, ld = _field(c, h.params.nx, h.params.ny, ld, "c")
     v = ctypes.c_double()
-    _check(load().ch_k1(h.handle, _devptr(c, "c"), ld, ctypes.byref(v), _stream(stream)), "ch_k1")
+    _check(load().ch_k1(h.handle, cp_, ld, ctypes.byref(v), _stream(stream)), "ch_k1")
     return v.value
 
 
@@ -680,6 +730,7 @@ class Ensemble:
         _check(lib.ch_ensemble_create(len(runs), arr, ctypes.byref(h)), "ch_ensemble_create")
         self.handle = h
         self.nruns = len(runs)
+        self.shapes = [(int(r[0]), int(r[1])) for r in runs]  # (nx, ny) per run
         self._ws = None
 
     def close(self):
@@ -713,17 +764,15 @@ def ch_ensemble_step(e: Ensemble, fields, nsteps: int = 1, diag_out=None, use_gr
     nruns * 2 * (nsteps + 1) values."""
     import torch
     lib = load()
-    if len(fields) != e.nruns:
-        raise ChxError(CHX_EINVAL, "one field per run")
+    ptrs, lds = _ens_fields(e, fields)
+    dptr = _diag(diag_out, e.nruns * 2 * (int(nsteps) + 1))
     nbytes = lib.ch_ensemble_ws_bytes(e.handle)
     if ws is None:
-        if e._ws is None or e._ws.numel() < nbytes + 256:
+        if (e._ws is None or e._ws.numel() < nbytes + 256 or
+                e._ws.device != fields[0].device):
             e._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=fields[0].device)
         ws = e._ws
     _, wsp, avail = _workspace(nbytes, ws, fields[0].device)
-    ptrs = (ctypes.c_void_p * e.nruns)(*[_devptr(f, "field").value for f in fields])
-    lds = (ctypes.c_long * e.nruns)(*[f.stride(0) for f in fields])
-    dptr = _devptr(diag_out, "diag_out") if diag_out is not None else ctypes.c_void_p(0)
     _check(lib.ch_ensemble_step(e.handle, ptrs, lds, nsteps, dptr, wsp, avail, int(use_graph),
                                 _stream(stream)), "ch_ensemble_step")
 
@@ -731,9 +780,11 @@ def ch_ensemble_step(e: Ensemble, fields, nsteps: int = 1, diag_out=None, use_gr
 def _ens_fields(e: Ensemble, fields):
     if len(fields) != e.nruns:
         raise ChxError(CHX_EINVAL, "one field per run")
-    ptrs = (ctypes.c_void_p * e.nruns)(*[_devptr(f, "field").value for f in fields])
-    lds = (ctypes.c_long * e.nruns)(*[f.stride(0) for f in fields])
-    return ptrs, lds
+    lds = [_field_ld(f, nx, ny, None, f"field {r}")
+           for r, (f, (nx, ny)) in enumerate(zip(fields, e.shapes))]
+    ptrs = (ctypes.c_void_p * e.nruns)(*[_devptr(f, f"field {r}").value
+                                         for r, f in enumerate(fields)])
+    return ptrs, (ctypes.c_long * e.nruns)(*lds)
 
 
 def ch_ensemble_moments(e: Ensemble, fields, stream=None):

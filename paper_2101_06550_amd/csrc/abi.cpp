@@ -955,27 +955,36 @@ int ch_get_noise_step(chx_ch h, unsigned long long* step) {
 }
 
 // Per-phase event timing of ch_adi_step (phase 0 column pass, 1 column
-// separators, 2 row pass, 3 finalize + diagnostics reductions).
+// separators, 2 row pass, 3 finalize + diagnostics reductions).  Every event
+// is created before the first launch (reserve), so the launch sequence only
+// records events: no event creation between kernels.
 struct PhaseTimer {
   hipStream_t st = nullptr;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;  // created up front
+  size_t used = 0;
   std::vector<int> phase;
   bool failed = false;
   int every = 1;    // time the kernels of every `every`-th step (and the last launches)
   bool on = true;   // timing the current step
-  void step(int n) { on = (n % every) == 0; }
-  void begin() {
-    hipEvent_t a;
-    if (hipEventCreate(&a) != hipSuccess) { failed = true; return; }
-    ev.push_back(a);
-    if (hipEventRecord(a, st) != hipSuccess) failed = true;
+  bool reserve(size_t n) {
+    ev.reserve(n);
+    for (size_t k = 0; k < n; ++k) {
+      hipEvent_t a;
+      if (hipEventCreate(&a) != hipSuccess) return false;
+      ev.push_back(a);
+    }
+    phase.reserve(n / 2);
+    return true;
   }
+  void step(int n) { on = (n % every) == 0; }
+  void record() {
+    if (used >= ev.size()) { failed = true; return; }
+    if (hipEventRecord(ev[used++], st) != hipSuccess) failed = true;
+  }
+  void begin() { record(); }
   void end(int ph) {
-    hipEvent_t b;
-    if (hipEventCreate(&b) != hipSuccess) { failed = true; return; }
-    ev.push_back(b);
     phase.push_back(ph);
-    if (hipEventRecord(b, st) != hipSuccess) failed = true;
+    record();
   }
   ~PhaseTimer() {
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -1277,6 +1286,10 @@ int ch_adi_step_timed(chx_ch h, double* c, long ld, int nsteps, double* diag_out
   PhaseTimer tm;
   tm.st = static_cast<hipStream_t>(s);
   tm.every = sample_every;
+  // at most 13 timed launches per sampled step (the refined step with 3
+  // passes and diagnostics: 4 + 3 per pass), and 4 around the call
+  const size_t sampled = (size_t)(nsteps / sample_every) + 1;
+  if (!tm.reserve(2 * (16 * sampled + 4))) return CHX_EHIP;
   int rc = run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, tm.st, &tm);
   if (rc) return rc;
   if (hipStreamSynchronize(tm.st) != hipSuccess) return CHX_EHIP;

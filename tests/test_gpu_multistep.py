@@ -1,0 +1,133 @@
+"""GPU parity of several ADI steps in one call on the multi-kernel path
+against the oracle's time loop (Ch.3 eq. 3:ch_adi advanced step after step).
+
+Every step after the first of such a call applies the previous step's
+column-chunk correction while it reads the state (the deferred correction of
+the chunked column solve, Ch.4 bordering across 32-row chunks), and the call
+ends with the correction written into the caller's array.  These cases cover
+grids with several chunks and several 256-column blocks of the column pass,
+a ragged last block of one wave, two chunks (the wrap chunk is both
+neighbours), the benchmark's 8192^2 launch configuration, the forced step,
+and the per-step diagnostics of every state against the oracle's."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2101_06550_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def chx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_06550_amd import chx as m
+    m.load()
+    return m
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def oracle_states(orc, c0, g, dt, k):
+    """The oracle's states after 0, 1, ..., k steps."""
+    out = [c0]
+    for _ in range(k):
+        out.append(orc.ch_step(out[-1], L, L, 1.0, g, dt))
+    return out
+
+
+# (ny, nx, gamma, dt, steps, seed): chunks = ny / 32, column blocks = nx / 256 (ragged: nx % 256)
+CASES = [(1024, 1024, 0.01, 1e-5, 3, 61),   # 32 chunks x 4 blocks
+         (96, 320, 0.01, 1e-4, 3, 62),      # 3 chunks, last block one wave
+         (160, 576, 0.01, 1e-4, 4, 63),     # 5 chunks, last block one wave
+         (64, 2048, 0.01, 1e-5, 3, 64),     # 2 chunks: the wrap chunk is both neighbours
+         (256, 448, 0.01, 1e-4, 5, 65)]     # 8 chunks, last block three waves
+
+
+@pytest.mark.parametrize("ny,nx,g,dt,k,seed", CASES)
+def test_steps_in_one_call_match_oracle(chx, orc, ny, nx, g, dt, k, seed):
+    c0 = inputs.noise_field(ny, nx, seed)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)  # the multi-kernel path
+    c = torch.tensor(c0, device="cuda")
+    d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+    print(f"[case] {k} steps in one call {ny}x{nx}", flush=True)
+    chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+    torch.cuda.synchronize()
+    ref = oracle_states(orc, c0, g, dt, k)
+    err = rel(c.cpu().numpy(), ref[k])
+    assert err < k * 1e-12, f"{k} steps: {err:.3e}"
+    dd = d.cpu().numpy().reshape(k + 1, 2)
+    l1 = np.sum(np.abs(c0)) * (L / nx) * (L / ny)
+    for j in range(k + 1):  # mass and free energy of every state of the call
+        m, e = orc.ch_mass(ref[j], L, L), orc.ch_energy(ref[j], L, L, g)
+        assert abs(dd[j, 0] - m) <= 1e-12 * l1, (j, dd[j, 0], m)
+        assert abs(dd[j, 1] - e) <= max(j, 1) * 1e-12 * abs(e), (j, dd[j, 1], e)
+
+
+def test_every_row_order_matches_oracle_over_steps(chx, orc):
+    """Rows of 8192 points (the benchmark's row length): every row-pass order
+    the tuner may pick, three steps in one call, against the oracle."""
+    ny, nx, g, dt, k = 96, 8192, 0.001, 1e-6, 3
+    c0 = inputs.noise_field(ny, nx, 66)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    ref = oracle_states(orc, c0, g, dt, k)[k]
+    for split in [-1, chx.CHX_ROW_SPLIT_OVERLAP] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
+        print(f"[case] row order {split}, {k} steps {ny}x{nx}", flush=True)
+        chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
+        c = torch.tensor(c0, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=k)
+        torch.cuda.synchronize()
+        err = rel(c.cpu().numpy(), ref)
+        assert err < k * 1e-12, f"row order {split}: {err:.3e}"
+
+
+def test_forced_steps_in_one_call_match_oracle(chx, orc):
+    """Cahn-Hilliard-Cook forcing drawn inside the column pass of every step,
+    three steps in one call on the multi-kernel path."""
+    ny = nx = 1024
+    dt, sigma, k = 1e-5, 1e-12, 3
+    c0 = inputs.noise_field(ny, nx, 67)
+    h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, dt)
+    chx.ch_set_noise(h, sigma, seed=91, step0=4)
+    c = torch.tensor(c0, device="cuda")
+    print("[case] forced 3 steps 1024x1024", flush=True)
+    chx.ch_adi_step(h, c, nsteps=k)
+    torch.cuda.synchronize()
+    ref = orc.ch_step_cook(c0, L, L, 1.0, 0.01, dt, sigma, 91, step0=4, nsteps=k)
+    err = rel(c.cpu().numpy(), ref)
+    assert err < k * 1e-12, f"forced {k} steps: {err:.3e}"
+    assert rel(orc.ch_step(c0, L, L, 1.0, 0.01, dt, nsteps=k), ref) > 1e-9  # forcing matters
+
+
+def test_large_run_two_steps_in_one_call(chx, orc):
+    """8192 x 8192 in the benchmark's configuration (gamma = 0.001, dt = 1e-6,
+    c0 = 0.05 sin 3x sin 5y + noise, tuned kernel shapes): two steps in one
+    call, every point against the oracle's two steps, and both states'
+    diagnostics."""
+    n, g, dt, k = 8192, 0.001, 1e-6, 2
+    c0 = inputs.mode_plus_noise(n, 5)
+    h = chx.ch_create(n, n, L, L, 1.0, g, dt)
+    c = torch.tensor(c0, device="cuda")
+    d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+    print("[case] 8192x8192 two steps in one call", flush=True)
+    chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+    torch.cuda.synchronize()
+    out = c.cpu().numpy()
+    del c
+    ref = oracle_states(orc, c0, g, dt, k)
+    err = rel(out, ref[k])
+    print(f"8192^2 two-step error {err:.3e}", flush=True)
+    assert err < k * 1e-12, f"two steps: {err:.3e}"
+    dd = d.cpu().numpy().reshape(k + 1, 2)
+    l1 = np.sum(np.abs(c0)) * (L / n) ** 2
+    for j in range(k + 1):
+        m, e = orc.ch_mass(ref[j], L, L), orc.ch_energy(ref[j], L, L, g)
+        assert abs(dd[j, 0] - m) <= 1e-12 * l1, (j, dd[j, 0], m)
+        assert abs(dd[j, 1] - e) <= 1e-12 * abs(e), (j, dd[j, 1], e)

@@ -143,6 +143,6 @@ def test_large_run_two_steps(chx, orc):
     torch.cuda.synchronize()
     ref, ref_prev = orc.ch2_step(c0, c0, L, L, 1.0, 0.001, 1e-6, nsteps=2)
     err = rel(c.cpu().numpy(), ref)
-    print(f"P2 8192 two-step error {err:.3e}")
-    assert err < 2 * tol(n, n, g=0.001, dt=1e-6)
+    print(f"P2 8192 two-step error {err:.3e}", flush=True)
+    assert err < 2 * tol(n, n, g=0.001, dt=1e-6), f"P2 8192^2 two steps: {err:.3e}"
     assert rel(cp.cpu().numpy(), ref_prev) < tol(n, n, g=0.001, dt=1e-6)

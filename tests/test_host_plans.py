@@ -307,3 +307,91 @@ def test_stencil_binding_rejects_mismatched_layouts():
                             torch.zeros((8, 11), dtype=torch.float64), w, 1, 1, 1, 1)
     with pytest.raises(chx.ChxError, match="leading dimension"):  # column-strided view
         chx.stencil2d_apply(big[:, ::2], torch.zeros((8, 8), dtype=torch.float64), w, 1, 1, 1, 1)
+
+
+class _FakeHandle:
+    """Stand-in for a CH handle: the binding's argument checks read only the
+    grid shape; every call below is refused before the library is reached."""
+
+    def __init__(self, nx, ny):
+        from paper_2101_06550_amd import chx
+        self.params = chx.ChParams(nx, ny, 1.0, 1.0, 1.0, 0.01, 1e-4, 0, 0, 0)
+        self.handle = None
+        self._ws = None
+
+
+@pytest.mark.parametrize("call", ["ch_adi_step", "ch_adi_step_timed", "ch_diagnostics",
+                                  "ch_moments", "ch_k1"])
+def test_step_binding_rejects_fields_that_do_not_fit(call):
+    """A field whose rows (ny of them, ld apart, nx used) do not lie inside the
+    tensor, or that is not row-major, is refused before any kernel could read
+    or write past it."""
+    import torch
+    from paper_2101_06550_amd import chx
+    h = _FakeHandle(64, 32)
+    fn = getattr(chx, call)
+    f64 = torch.float64
+    with pytest.raises(chx.ChxError, match=r"\(32, >= 64\)"):  # too few rows
+        fn(h, torch.zeros((31, 64), dtype=f64))
+    with pytest.raises(chx.ChxError, match=r"\(32, >= 64\)"):  # too few columns
+        fn(h, torch.zeros((32, 63), dtype=f64))
+    with pytest.raises(chx.ChxError, match=r"\(32, >= 64\)"):  # flat buffer
+        fn(h, torch.zeros(64 * 32, dtype=f64))
+    with pytest.raises(chx.ChxError, match="unit column stride"):
+        fn(h, torch.zeros((32, 128), dtype=f64)[:, ::2])
+    with pytest.raises(chx.ChxError, match="leading dimension"):  # ld below nx
+        fn(h, torch.zeros((32, 64), dtype=f64), ld=32)
+    with pytest.raises(chx.ChxError, match="leading dimension"):  # ld not the row stride
+        fn(h, torch.zeros((32, 64), dtype=f64), ld=80)
+    with pytest.raises(chx.ChxError, match="device tensor"):  # shape fine: only the device
+        fn(h, torch.zeros((32, 80), dtype=f64))
+
+
+def test_step_binding_rejects_short_diagnostics_and_bad_pairs():
+    import torch
+    from paper_2101_06550_amd import chx
+    h = _FakeHandle(64, 32)
+    c = torch.zeros((32, 64), dtype=torch.float64)
+    for call in (chx.ch_adi_step, chx.ch_adi_step_timed):
+        with pytest.raises(chx.ChxError, match=">= 8 values"):  # 3 steps: 2 * 4 values
+            call(h, c, nsteps=3, diag_out=torch.zeros(7, dtype=torch.float64))
+        with pytest.raises(chx.ChxError, match="contiguous"):
+            call(h, c, nsteps=1, diag_out=torch.zeros(8, dtype=torch.float64)[::2])
+    with pytest.raises(chx.ChxError, match=r"cprev must be a \(32, >= 64\)"):
+        chx.ch_adi_step_p2(h, c, torch.zeros((16, 64), dtype=torch.float64))
+    with pytest.raises(chx.ChxError, match="one leading dimension"):
+        chx.ch_adi_step_p2(h, c, torch.zeros((32, 72), dtype=torch.float64))
+    with pytest.raises(chx.ChxError, match=">= 6 values"):
+        chx.ch_adi_step_p2(h, c, c.clone(), nsteps=2, diag_out=torch.zeros(5, dtype=torch.float64))
+
+
+def test_ensemble_binding_checks_every_run():
+    import torch
+    from paper_2101_06550_amd import chx
+    e = chx.Ensemble.__new__(chx.Ensemble)  # shapes only; the library is never reached
+    e.handle, e.nruns, e.shapes, e._ws = None, 2, [(64, 32), (128, 64)], None
+    ok0 = torch.zeros((32, 64), dtype=torch.float64)
+    with pytest.raises(chx.ChxError, match=r"field 1 must be a \(64, >= 128\)"):
+        chx.ch_ensemble_step(e, [ok0, torch.zeros((64, 64), dtype=torch.float64)])
+    with pytest.raises(chx.ChxError, match="one field per run"):
+        chx.ch_ensemble_step(e, [ok0])
+    with pytest.raises(chx.ChxError, match=r"field 1 must be a"):
+        chx.ch_ensemble_moments(e, [ok0, ok0])
+    e.handle = None
+
+
+def test_solve_binding_rejects_short_buffers():
+    import torch
+    from paper_2101_06550_amd import chx
+
+    class P:
+        handle, n = None, 64
+
+    x = torch.zeros(64 * 100 - 1, dtype=torch.float64)  # one element short of (n - 1) 100 + 100
+    with pytest.raises(chx.ChxError, match="storage holds fewer"):
+        chx.penta_solve_batch(P(), 100, x, ld=100, layout=chx.CHX_INTERLEAVED)
+    with pytest.raises(chx.ChxError, match="storage holds fewer"):
+        chx.tri_solve_batch(P(), 100, x, ld=64, layout=chx.CHX_CONTIGUOUS)
+    with pytest.raises(chx.ChxError, match="unit last stride"):
+        chx.penta_solve_batch(P(), 10, torch.zeros((64, 40), dtype=torch.float64)[:, ::2],
+                              ld=40)
