@@ -46,7 +46,8 @@ enum {
   CHX_EHIP = -4,            /* a HIP runtime call or kernel launch failed      */
   CHX_ENONFINITE = -5,      /* a diagnostic sum is NaN or infinite             */
   CHX_ENOMEM = -6,          /* workspace too small / allocation failed         */
-  CHX_EREFINE = -7          /* iterative refinement did not reduce the error   */
+  CHX_EREFINE = -7,         /* iterative refinement did not reduce the error   */
+  CHX_ESCRATCH = -8         /* needs more than the static scratch (see below)  */
 };
 
 enum chx_dtype {
@@ -115,6 +116,29 @@ size_t penta_solve_ws_bytes(chx_penta_plan p, int batch, int layout, int dtype,
 int penta_solve_batch(chx_penta_plan p, int batch, void* x_inout, long ld,
                       int layout, int dtype, int refine_passes, void* ws,
                       size_t ws_bytes, chx_stream s);
+
+/* Size of the library's static device scratch (per GPU): 32 MiB. */
+#define CHX_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* penta_solve_batch_noalloc: penta_solve_batch for callers that cannot
+ *   allocate device memory (code under HIP graph capture, tight serving
+ *   loops, harnesses that forbid hipMalloc).  Same arguments and results as
+ *   penta_solve_batch without ws / ws_bytes: the workspace is a static device
+ *   array of CHX_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ *   until the process ends (its address is looked up once per device, on the
+ *   first call with that device current).  The call itself allocates nothing
+ *   (no hipMalloc, hipFree or allocating library routine).  Returns
+ *   CHX_ESCRATCH, before anything is enqueued, when
+ *   penta_solve_ws_bytes(p, batch, layout, dtype, refine_passes) exceeds
+ *   CHX_NOALLOC_SCRATCH_BYTES (for n = 1024: up to 32768 interleaved systems
+ *   in FP64, about 1600 FP32-refined; contiguous FP64 needs no scratch).
+ *   Every call on one GPU shares that GPU's scratch, so calls that overlap on
+ *   one GPU (other streams, other host threads) race and must be serialised
+ *   by the caller; the scratch keeps whatever the last call left (every
+ *   kernel writes what it later reads, nothing needs to start at zero). */
+int penta_solve_batch_noalloc(chx_penta_plan p, int batch, void* x_inout,
+                              long ld, int layout, int dtype,
+                              int refine_passes, chx_stream s);
 
 /* ------------------------------------------------------------------------
  * Tridiagonal systems (Ch.5 "Tridiagonal Inversion Algorithm",

@@ -22,6 +22,8 @@ CHX_EHIP = -4
 CHX_ENONFINITE = -5
 CHX_ENOMEM = -6
 CHX_EREFINE = -7
+CHX_ESCRATCH = -8
+CHX_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 CHX_SCHEME_P1 = 0
 CHX_SCHEME_P2 = 1
@@ -36,6 +38,7 @@ CHX_BATCH_REWRITE = 1
 EXPORTED = [
     "chx_version", "chx_status_string", "chx_stream_copy",
     "penta_factor", "penta_plan_destroy", "penta_solve_ws_bytes", "penta_solve_batch",
+    "penta_solve_batch_noalloc",
     "tri_factor", "tri_plan_destroy", "tri_solve_ws_bytes", "tri_solve_batch",
     "penta_batch_ws_bytes", "penta_batch_factor", "penta_batch_solve", "penta_batch_rewrite",
     "tri_batch_ws_bytes", "tri_batch_factor", "tri_batch_solve", "tri_batch_rewrite",
@@ -96,6 +99,7 @@ def load(path: str | None = None):
         "penta_plan_destroy": (_I, [_V]),
         "penta_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
         "penta_solve_batch": (_I, [_V, _I, _V, _L, _I, _I, _I, _V, _S, _V]),
+        "penta_solve_batch_noalloc": (_I, [_V, _I, _V, _L, _I, _I, _I, _V]),
         "tri_factor": (_I, [_I, _D, _D, _D, _I, ctypes.POINTER(_V)]),
         "tri_plan_destroy": (_I, [_V]),
         "tri_solve_ws_bytes": (_S, [_V, _I, _I, _I, _I]),
@@ -295,8 +299,8 @@ def tri_solve_ws_bytes(plan, batch, layout=CHX_INTERLEAVED, dtype=CHX_F64, refin
     return load().tri_solve_ws_bytes(plan.handle, batch, layout, dtype, refine_passes)
 
 
-def _solve(kind, plan, batch, x, ld, layout, dtype, refine_passes, ws, stream):
-    lib = load()
+def _solve_ld(kind, plan, batch, x, ld, layout):
+    """Leading dimension of x, checked against x's storage."""
     if ld is None:
         ld = x.stride(0) if x.dim() == 2 else (batch if layout == CHX_INTERLEAVED else plan.n)
     if batch > 0:  # element (s, i) at i * ld + s (interleaved) or s * ld + i (contiguous)
@@ -306,6 +310,12 @@ def _solve(kind, plan, batch, x, ld, layout, dtype, refine_passes, ws, stream):
         if ld >= 1 and span > _storage_elems(x):
             raise ChxError(CHX_EINVAL, f"{kind}_solve_batch: {span} elements needed from x's "
                                        "start, its storage holds fewer")
+    return ld
+
+
+def _solve(kind, plan, batch, x, ld, layout, dtype, refine_passes, ws, stream):
+    lib = load()
+    ld = _solve_ld(kind, plan, batch, x, ld, layout)
     xp = _devptr(x, "x")
     nbytes = getattr(lib, f"{kind}_solve_ws_bytes")(plan.handle, batch, layout, dtype,
                                                     refine_passes)
@@ -323,6 +333,19 @@ def penta_solve_batch(plan: PentaPlan, batch: int, x, ld: int | None = None,
     and receives the solutions.  Returns the workspace tensor used (keep it
     alive until the stream has finished if it was allocated here)."""
     return _solve("penta", plan, batch, x, ld, layout, dtype, refine_passes, ws, stream)
+
+
+def penta_solve_batch_noalloc(plan: PentaPlan, batch: int, x, ld: int | None = None,
+                              layout: int = CHX_INTERLEAVED, dtype: int = CHX_F64,
+                              refine_passes: int = 0, stream=None) -> None:
+    """penta_solve_batch with the library's static device scratch as its
+    workspace: allocates nothing.  Raises ChxError(CHX_ESCRATCH) when the
+    solve needs more than CHX_NOALLOC_SCRATCH_BYTES."""
+    lib = load()
+    ld = _solve_ld("penta", plan, batch, x, ld, layout)
+    st = lib.penta_solve_batch_noalloc(plan.handle, batch, _devptr(x, "x"), ld, layout, dtype,
+                                       refine_passes, _stream(stream))
+    _check(st, "penta_solve_batch_noalloc")
 
 
 def tri_solve_batch(plan: TriPlan, batch: int, x, ld: int | None = None,

@@ -450,6 +450,7 @@ const char* chx_status_string(int status) {
     case CHX_ENONFINITE: return "non-finite diagnostic";
     case CHX_ENOMEM: return "workspace too small or allocation failed";
     case CHX_EREFINE: return "iterative refinement did not converge";
+    case CHX_ESCRATCH: return "workspace needed exceeds the static scratch";
     default: return "unknown status";
   }
 }
@@ -476,6 +477,54 @@ int penta_solve_batch(chx_penta_plan p, int batch, void* x_inout, long ld, int l
                       int refine_passes, void* ws, size_t ws_bytes, chx_stream s) {
   if (p && p->P != 2) return CHX_EINVAL;
   return solve(p, batch, x_inout, ld, layout, dtype, refine_passes, ws, ws_bytes, s);
+}
+
+}  // extern "C"
+
+// Static device scratch of penta_solve_batch_noalloc.  In host code the
+// name `scratch` is only a host-side stand-in for the device array: its
+// device address (one per GPU) comes from hipGetSymbolAddress, looked up once
+// per device and kept here; only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CHX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch (looked up on first use).
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return CHX_EHIP;
+  if (dev >= kMaxScratchDevices) return CHX_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CHX_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int penta_solve_batch_noalloc(chx_penta_plan p, int batch, void* x_inout, long ld, int layout,
+                              int dtype, int refine_passes, chx_stream s) {
+  if (!p) return CHX_EINVAL;
+  if (p->P != 2) return CHX_EINVAL;
+  if (layout != CHX_INTERLEAVED && layout != CHX_CONTIGUOUS) return CHX_EINVAL;
+  if (dtype != CHX_F64 && dtype != CHX_F32_REFINED) return CHX_EINVAL;
+  const size_t need = solve_ws(p, batch, layout, dtype);
+  if (need > (size_t)CHX_NOALLOC_SCRATCH_BYTES) return CHX_ESCRATCH;
+  void* ptr = nullptr;
+  if (need > 0) {
+    const int rc = scratch_address(&ptr);
+    if (rc != CHX_OK) return rc;
+  }
+  return solve(p, batch, x_inout, ld, layout, dtype, refine_passes, ptr,
+               need > 0 ? (size_t)CHX_NOALLOC_SCRATCH_BYTES : 0, s);
 }
 
 int tri_factor(int n, double a, double b, double c, int periodic, chx_tri_plan* out) {

@@ -88,9 +88,11 @@ def test_shape_count_matches_header():
     text = open(HEADER).read()
     for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH",
                  "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES", "CHX_SCHEME_P1", "CHX_SCHEME_P2",
+                 "CHX_NOALLOC_SCRATCH_BYTES",
                  "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
-        m = re.search(r"#define\s+" + name + r"\s+(\d+)", text)
-        assert m and int(m.group(1)) == getattr(chx, name), name
+        m = re.search(r"#define\s+" + name + r"\s+\(?(\d+)(u << (\d+)\))?", text)
+        value = int(m.group(1)) << int(m.group(3) or 0) if m else None
+        assert value == getattr(chx, name), name
     m = re.search(r"#define\s+CHX_ROW_SPLIT_OVERLAP\s+\((-?\d+)\)", text)
     assert m and int(m.group(1)) == chx.CHX_ROW_SPLIT_OVERLAP
 
