@@ -431,20 +431,41 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
                                 "updates_per_s": points * k / el}
     del ens
     # the same runs FP32-refined (2 passes: kappa = 706 at 512^2), replayed
-    # from a graph; the runs of a class advance one after another
+    # from a graph: every phase of the refined step one launch for all runs
     ens = chx.ch_ensemble_create([(n, n, L, L, 1.0, 0.01, 1e-4) for n in sizes],
                                  dtype=chx.CHX_F32_REFINED, refine_passes=2)
-    k = 20
+    k = min(steps, 100)
     chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    rb = refined_bytes_per_point(2)
     out["f32_refined_2pass_graph"] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
-                                      "updates_per_s": points * k / el}
+                                      "updates_per_s": points * k / el,
+                                      "algorithmic_bytes_per_point": rb,
+                                      "algorithmic_GBps": round(rb * points * k / el / 1e9, 1)}
+    f64 = out["graph"]["updates_per_s"]
+    ref = out["f32_refined_2pass_graph"]["updates_per_s"]
+    out["f32_refined_vs_f64"] = {
+        "refined_beats_f64": bool(ref > f64), "updates_ratio_refined_over_f64": round(ref / f64, 3),
+        "bytes_per_point_f64": 34.0, "bytes_per_point_refined_2pass": rb,
+        "why": "both paths stream HBM at similar rates; FP64 sweeps cost no more time than FP32 "
+               "ones here, and refinement must still read and write FP64 right-hand sides, "
+               "states and the deferred FP32 solutions of every pass"}
     del fields, ens
     return out
+
+
+def refined_bytes_per_point(p):
+    """Algorithmic HBM bytes per point of one FP32-refined ADI step with p
+    refinement passes: first column pass (read c 8, write r 8, FP32 chunk
+    interiors 3.75, parts 0.5), FP32 separators 0.75, FP32 row solves 8; pass k
+    adds the residual column pass (read r 8 and V_0..V_{k-1} 4 k, write 4.25),
+    separators 0.75 and rows 8; the final pass reads V_0..V_p (4 (p + 1)) and
+    writes c (8).  70, 103, 140 B for p = 1, 2, 3 (the FP64 step: 34 B)."""
+    return 29.0 + sum(21.0 + 4.0 * k for k in range(1, p + 1)) + 4.0 * (p + 1) + 8.0
 
 
 def small_run(chx, torch, steps=1000):
@@ -974,8 +995,13 @@ def main():
         chx.ch_adi_step(hr, cr, nsteps=kr)
         torch.cuda.synchronize()
         elr = time.perf_counter() - t0
+        rb = refined_bytes_per_point(3)
+        gbps = rb * n * n * kr / elr / 1e9
         extra["large_f32_refined_3pass"] = {"steps": kr, "ms_per_step": round(1e3 * elr / kr, 5),
-                                            "updates_per_s": n * n * kr / elr}
+                                            "updates_per_s": n * n * kr / elr,
+                                            "algorithmic_bytes_per_point": rb,
+                                            "algorithmic_GBps": round(gbps, 1),
+                                            "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)}
         del cr
 
     cpu = None
@@ -1017,7 +1043,8 @@ def main():
                               "bitwise_equal_to_timed_run": timed_same},
         "tuning": {"separator_kernel_shape": chx.ch_get_tuning(h),
                    "row_split_shape": split,
-                   "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH)},
+                   "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH),
+                   "column_tile_order": chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_ORDER)},
         "checks": {"mass_drift_rel_L1": mass_drift, "energy_monotone": energy_monotone},
         "extra": extra,
     }

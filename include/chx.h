@@ -52,7 +52,8 @@ enum {
 
 enum chx_dtype {
   CHX_F64 = 0,              /* FP64 sweeps and storage                          */
-  CHX_F32_REFINED = 1       /* FP32 sweeps + FP64 residual refinement (FP64 I/O) */
+  CHX_F32_REFINED = 1,      /* FP32 sweeps + FP64 residual refinement (FP64 I/O) */
+  CHX_F32 = 2               /* FP32 arrays and arithmetic (stencil2d_apply)       */
 };
 
 enum chx_layout {
@@ -112,7 +113,13 @@ size_t penta_solve_ws_bytes(chx_penta_plan p, int batch, int layout, int dtype,
  *   contiguous).  dtype CHX_F64 sweeps in FP64; CHX_F32_REFINED sweeps in FP32
  *   and applies refine_passes (1..3) FP64-residual refinement passes.  ws
  *   (device) must hold penta_solve_ws_bytes(...) bytes, aligned to 256 B.
- *   Returns CHX_EINVAL for bad arguments, CHX_ENOMEM if ws_bytes is short. */
+ *   Returns CHX_EINVAL for bad arguments, CHX_ENOMEM if ws_bytes is short,
+ *   and for CHX_F32_REFINED CHX_EREFINE (before anything is enqueued) when
+ *   the matrix is too ill-conditioned for FP32 sweeps to reduce the error:
+ *   4 kappa 2^-24 >= 1, kappa = the plan's 2-norm condition number (exact
+ *   for periodic plans, whose matrix is circulant: max / min |eigenvalue|;
+ *   the symbol's range for non-periodic ones).  Each refinement pass shrinks
+ *   the error by about kappa 2^-24. */
 int penta_solve_batch(chx_penta_plan p, int batch, void* x_inout, long ld,
                       int layout, int dtype, int refine_passes, void* ws,
                       size_t ws_bytes, chx_stream s);
@@ -228,9 +235,13 @@ int tri_batch_rewrite(int n, int batch, int periodic, const double* a,
  *   periodic != 0 wraps indices; periodic == 0 writes only the points whose
  *   whole stencil lies inside the array and leaves the boundary cells of out
  *   untouched.  in and out (device, nx x ny, leading dimension ld >= nx) must
- *   not overlap (the thesis's separate input and output buffers).
+ *   not overlap (the thesis's separate input and output buffers).  dtype
+ *   CHX_F64: FP64 arrays and arithmetic; CHX_F32: FP32 arrays, the weights
+ *   rounded to FP32 once and the sums formed in FP32 (half the bytes per
+ *   point, the thesis names single precision as future work); any other
+ *   dtype is CHX_EINVAL.
  */
-int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
+int stencil2d_apply(const void* in, void* out, int nx, int ny, long ld, int dtype,
                     const double* weights, int left, int right, int top,
                     int bottom, int periodic, int premap, chx_stream s);
 
@@ -305,7 +316,9 @@ typedef struct {
  * and row sweeps run in FP32 (FP32 copies of the factorisation), and
  * refine_passes (1..3) passes of R = r - (I + sx Px)(I + sy Py) c in FP64,
  * c += (FP32 solve of R) recover FP64 accuracy.  It needs the chunked shapes
- * (nx % 64 == 0, ny % 32 == 0, nx <= 8192), else CHX_EINVAL.
+ * (nx % 64 == 0, ny % 32 == 0, nx <= 8192), else CHX_EINVAL; ch_create
+ * returns CHX_EREFINE when 4 (kappa_x + kappa_y) 2^-24 >= 1 (the two
+ * directions' condition numbers: no contraction of the error per pass).
  *
  * ch_create: factor both directions once and pick the kernel shapes.
  * ch_destroy: free (NULL accepted).  ch_ws_bytes: workspace for ch_adi_step. */
@@ -374,6 +387,19 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   the next step; the steps ch_adi_step_timed times keep the -1 order so
  *   that their kernel timings stay meaningful).  Chosen by the same timing as the tile shape.
  *   Results are bitwise identical either way.
+ * CHX_TUNE_COLUMN_ORDER: order in which the multi-kernel path's column pass
+ *   (and the pass that writes the final state) numbers its tiles of 256
+ *   columns x 32 rows (0 .. CHX_NUM_COLUMN_ORDERS-1): 0 row-major; 1 each of
+ *   the 8 XCDs (which receive consecutive workgroups round robin) works a
+ *   horizontal band of chunk rows; 2 each XCD works whole column blocks, chunk
+ *   after chunk.  Results are bitwise identical whatever the order.
+ * CHX_TUNE_GRAPH: 1 makes ch_adi_step capture the launches of a call into a
+ *   hipGraph (on a private stream of the handle) and replay it, re-capturing
+ *   only when the field pointer, ld, nsteps, diag_out or ws differ from the
+ *   captured call's; the graph is kept until the handle is destroyed or a
+ *   tuning choice changes.  0 (the default) launches every kernel from the
+ *   host.  Handles with Cahn-Hilliard-Cook forcing and the single-workgroup
+ *   path always launch directly.  Results are bitwise identical either way.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown
  *   `what` or a value out of range.  Not to be called while work of h is
@@ -384,6 +410,9 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 #define CHX_NUM_REDUCED_SHAPES 7
 #define CHX_NUM_SPLIT_SHAPES 3
 #define CHX_ROW_SPLIT_OVERLAP (-2)
+#define CHX_TUNE_COLUMN_ORDER 3
+#define CHX_NUM_COLUMN_ORDERS 3
+#define CHX_TUNE_GRAPH 4
 int ch_get_tuning(chx_ch h, int what, int* value);
 int ch_set_tuning(chx_ch h, int what, int value);
 
@@ -445,11 +474,12 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s);
  *   CHX_SCHEME_P1 and one dtype.  CHX_F64: nx % 64 == 0, ny % 32 == 0,
  *   nx <= 8192, at most 8 distinct (grid, D, gamma, dt) classes.
  *   CHX_F32_REFINED (the precision pattern of ch_create's refined step):
- *   each run as ch_create accepts it, at most 8 distinct (grid, D, gamma, dt,
- *   refine_passes) classes; the runs of a class share one refined step and
- *   advance one after another, each with its own launches (so the refined
- *   ensemble is launch-bound for small grids).  Otherwise CHX_EINVAL (or
- *   ch_create's status for a refined class it rejects).
+ *   each run as ch_create accepts it (refine_passes may differ between
+ *   runs), at most 8 distinct (grid, D, gamma, dt) classes; every phase of
+ *   the refined step is one launch for all runs (refinement pass k covers
+ *   the runs with at least k passes), and each run advances bitwise as a
+ *   single refined handle would.  Otherwise CHX_EINVAL (CHX_EREFINE for a
+ *   class ch_create would refuse with it).
  * ch_ensemble_ws_bytes: device workspace for ch_ensemble_step.
  * ch_ensemble_step: advance every run by nsteps >= 1 steps in place.
  *   c_runs: host array of nruns device pointers (row-major fields); ld_runs:

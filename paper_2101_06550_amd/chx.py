@@ -29,6 +29,7 @@ CHX_SCHEME_P1 = 0
 CHX_SCHEME_P2 = 1
 CHX_F64 = 0
 CHX_F32_REFINED = 1
+CHX_F32 = 2
 CHX_INTERLEAVED = 0
 CHX_CONTIGUOUS = 1
 CHX_BATCH_FACTOR = 0
@@ -112,7 +113,7 @@ def load(path: str | None = None):
         "tri_batch_factor": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _S, _V]),
         "tri_batch_solve": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _S, _V, _V]),
         "tri_batch_rewrite": (_I, [_I, _I, _I] + [_V] * 3 + [_L, _V, _V, _S, _V]),
-        "stencil2d_apply": (_I, [_V, _V, _I, _I, _L, _DP, _I, _I, _I, _I, _I, _I, _V]),
+        "stencil2d_apply": (_I, [_V, _V, _I, _I, _L, _I, _DP, _I, _I, _I, _I, _I, _I, _V]),
         "ch_create": (_I, [ctypes.POINTER(ChParams), ctypes.POINTER(_V)]),
         "ch_destroy": (_I, [_V]),
         "ch_ws_bytes": (_S, [_V]),
@@ -463,10 +464,19 @@ def stencil2d_apply(inp, out, weights, left: int, right: int, top: int, bottom: 
         if ny > 1 and t.stride(0) != ld or nx > 1 and t.stride(1) != 1:
             raise ChxError(CHX_EINVAL, "stencil2d_apply: inp and out must be row-major with "
                                        "leading dimension ld")
+    import torch
+    if inp.dtype not in (torch.float64, torch.float32) or out.dtype != inp.dtype:
+        raise ChxError(CHX_EINVAL, "stencil2d_apply: inp and out must both be float64 or "
+                                   "both float32")
+    dtype = CHX_F32 if inp.dtype == torch.float32 else CHX_F64
+    for t, what in ((inp, "in"), (out, "out")):
+        if not t.is_cuda:
+            raise ChxError(CHX_EINVAL, f"{what} must be a device tensor")
     w = (ctypes.c_double * len(weights))(*[float(v) for v in weights])
-    _check(load().stencil2d_apply(_devptr(inp, "in"), _devptr(out, "out"), nx, ny, ld, w,
-                                  left, right, top, bottom, int(bool(periodic)), premap,
-                                  _stream(stream)), "stencil2d_apply")
+    _check(load().stencil2d_apply(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  nx, ny, ld, dtype, w, left, right, top, bottom,
+                                  int(bool(periodic)), premap, _stream(stream)),
+           "stencil2d_apply")
 
 
 # ----------------------------------------------------------------- Cahn-Hilliard
@@ -652,6 +662,9 @@ CHX_TUNE_ROW_SPLIT = 2
 CHX_NUM_REDUCED_SHAPES = 7
 CHX_ROW_SPLIT_OVERLAP = -2
 CHX_NUM_SPLIT_SHAPES = 3
+CHX_TUNE_COLUMN_ORDER = 3
+CHX_NUM_COLUMN_ORDERS = 3
+CHX_TUNE_GRAPH = 4
 
 
 def ch_get_tuning(h: CH, what: int = CHX_TUNE_REDUCED_SHAPE) -> int:
@@ -743,12 +756,16 @@ def chx_host_whole_tables(P: int, coef, n: int, periodic: bool = True):
 class Ensemble:
     """Handle of ch_ensemble_create: many independent runs (each a tuple
     (nx, ny, lx, ly, D, gamma, dt)) advanced together, all in FP64 or all
-    FP32-refined with ``refine_passes`` passes."""
+    FP32-refined with ``refine_passes`` passes (one number, or one per run)."""
 
-    def __init__(self, runs, dtype: int = CHX_F64, refine_passes: int = 0):
+    def __init__(self, runs, dtype: int = CHX_F64, refine_passes=0):
         lib = load()
-        arr = (ChParams * len(runs))(*[ChParams(nx, ny, lx, ly, D, g, dt, dtype, refine_passes)
-                                       for (nx, ny, lx, ly, D, g, dt) in runs])
+        passes = (list(refine_passes) if hasattr(refine_passes, "__len__")
+                  else [refine_passes] * len(runs))
+        if len(passes) != len(runs):
+            raise ChxError(CHX_EINVAL, "ch_ensemble_create: one refine_passes per run")
+        arr = (ChParams * len(runs))(*[ChParams(nx, ny, lx, ly, D, g, dt, dtype, int(p))
+                                       for (nx, ny, lx, ly, D, g, dt), p in zip(runs, passes)])
         h = ctypes.c_void_p()
         _check(lib.ch_ensemble_create(len(runs), arr, ctypes.byref(h)), "ch_ensemble_create")
         self.handle = h
@@ -768,7 +785,7 @@ class Ensemble:
             pass
 
 
-def ch_ensemble_create(runs, dtype: int = CHX_F64, refine_passes: int = 0) -> Ensemble:
+def ch_ensemble_create(runs, dtype: int = CHX_F64, refine_passes=0) -> Ensemble:
     return Ensemble(runs, dtype, refine_passes)
 
 

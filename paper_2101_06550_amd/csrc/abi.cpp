@@ -28,6 +28,7 @@ namespace {
 struct BandPlan {
   int P = 2, n = 0, periodic = 1;
   double coef[5] = {};
+  double kappa = 1.0;  // 2-norm condition number (exact when periodic)
   WholeTables whole;
   ChunkTables chunk;
   bool has_chunk = false;
@@ -91,6 +92,34 @@ int upload(BandPlan* p) {
   return CHX_OK;
 }
 
+// Condition number of the constant-coefficient band matrix.  Periodic: the
+// matrix is circulant (normal), its eigenvalues are the symbol
+// f(theta) = sum_k coef[k + P] e^{i k theta} at theta = 2 pi m / n, and
+// kappa_2 = max |f| / min |f| exactly.  Non-periodic (banded Toeplitz): the
+// same ratio over a fine sampling of theta, the spectrum's envelope (exact in
+// the limit for symmetric matrices, an estimate otherwise).
+double band_kappa(int P, int n, const double* coef, bool periodic) {
+  const int m = periodic ? n : 8 * n;
+  double lo = INFINITY, hi = 0.0;
+  for (int q = 0; q < m; ++q) {
+    const double th = 2.0 * M_PI * (double)q / (double)m;
+    double re = 0.0, im = 0.0;
+    for (int k = -P; k <= P; ++k) {
+      re += coef[k + P] * std::cos(k * th);
+      im += coef[k + P] * std::sin(k * th);
+    }
+    const double a = std::hypot(re, im);
+    lo = std::min(lo, a);
+    hi = std::max(hi, a);
+  }
+  return lo > 0.0 ? hi / lo : INFINITY;
+}
+
+// Iterative refinement with FP32 sweeps contracts the error by about
+// c kappa 2^-24 per pass (c a small growth constant of the FP32 LR
+// factorisation and sweeps, taken as 4); at or above 1 it need not converge.
+bool refinement_fails(double kappa) { return !(4.0 * kappa * 0x1.0p-24 < 1.0); }
+
 bool finite_all(const double* v, int n) {
   for (int k = 0; k < n; ++k)
     if (!std::isfinite(v[k])) return false;
@@ -111,6 +140,7 @@ int make_plan(int P, int n, const double* coef, int periodic, PlanT** out) {
   p->n = n;
   p->periodic = periodic ? 1 : 0;
   for (int k = 0; k < 2 * P + 1; ++k) p->coef[k] = coef[k];
+  p->kappa = band_kappa(P, n, coef, p->periodic != 0);
   Band band;
   band.P = P;
   band.periodic = p->periodic != 0;
@@ -219,6 +249,7 @@ int solve(const BandPlan* p, int batch, void* x, long ld, int layout, int dtype,
   if (dtype == CHX_F32_REFINED && (refine < 1 || refine > 3)) return CHX_EINVAL;
   if (layout == CHX_INTERLEAVED && ld < batch) return CHX_EINVAL;
   if (layout == CHX_CONTIGUOUS && ld < p->n) return CHX_EINVAL;
+  if (dtype == CHX_F32_REFINED && refinement_fails(p->kappa)) return CHX_EREFINE;
   const SolveWs w = solve_ws_layout(p, batch, layout, dtype);
   if (w.total > 0 && (!ws || ws_bytes < w.total)) return CHX_ENOMEM;
   if (w.total > 0 && (reinterpret_cast<uintptr_t>(ws) & 255)) return CHX_EINVAL;
@@ -265,6 +296,7 @@ struct chx_ch_s {
   bool small = false;     // ... and is in use
   int split = -1;         // split row pass shape (-1: plain separators + rows,
                           // kSplitOverlap: separators beside the interior rows)
+  int col_order = 0;      // tile order of the column pass (CHX_TUNE_COLUMN_ORDER)
   // the second stream of the overlapped schedule and its fork / join events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -274,7 +306,7 @@ struct chx_ch_s {
   Ch2Coef K2{};           // the thesis's delta-form scheme (CHX_SCHEME_P2)
   size_t off_b0 = 0, off_b1 = 0, off_rho = 0, off_part = 0, off_r = 0, ws_total = 0;
   // FP32-sweep refined path: residual buffer, FP32 chunk solutions and partials
-  size_t off_R = 0, off_y32 = 0, off_rho32 = 0;
+  size_t off_y32 = 0, off_rho32 = 0, off_v32[4] = {};  // FP32-refined step
   double cxs[5] = {}, cys[5] = {};
   long part_count = 0;
   double* dscratch = nullptr;  // ch_diagnostics: partials + 2 outputs
@@ -283,7 +315,29 @@ struct chx_ch_s {
   hipfftHandle fft{};
   void* fft_mem = nullptr;
   long dscratch_parts = 0;
+  // CHX_TUNE_GRAPH: ch_adi_step replays a captured hipGraph of the whole call
+  // (re-captured when the field, ld, nsteps, diag_out or ws change)
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;
+  double* g_c = nullptr;
+  long g_ld = 0;
+  int g_nsteps = -1;
+  double* g_diag = nullptr;
+  void* g_ws = nullptr;
+  hipEvent_t g_done = nullptr;  // recorded after every replay
+  void drop_graph() {
+    if (gexec && g_done) (void)hipEventSynchronize(g_done);  // no replay still running
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
   ~chx_ch_s() {
+    drop_graph();
+    if (g_done) (void)hipEventDestroy(g_done);
+    if (cap) (void)hipStreamDestroy(cap);
     delete px;
     delete py;
     if (dscratch) (void)hipFree(dscratch);
@@ -313,8 +367,8 @@ struct chx_ens_s {
   size_t small_lds = 0;
   hipStream_t side = nullptr;     // small runs overlap the big runs' phases
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  int n_col = 0, n_red = 0, n_row = 0, n_fin = 0, n_dpart = 0;
-  long o_col = 0, o_red = 0, o_row = 0, o_fin = 0, o_dpart = 0;
+  int n_col = 0, n_red = 0, n_row = 0;
+  long o_col = 0, o_red = 0, o_row = 0;
   size_t ws_total = 0, red_lds = 0;
   long max_points = 0;
   // cached hipGraph of a whole call (nsteps, diag, ws)
@@ -324,10 +378,11 @@ struct chx_ens_s {
   int g_nsteps = -1;
   double* g_diag = nullptr;
   void* g_ws = nullptr;
-  // FP32-refined ensembles: one refined single-run handle per class; the
-  // runs advance one after another through it, sharing one workspace
+  // FP32-refined ensembles: work items ordered by refine passes (most
+  // first); rn_*[k] = the items of the runs that make pass k (a prefix)
   bool refined = false;
-  std::vector<chx_ch> rh;
+  int max_passes = 0;
+  int rn_col[4] = {}, rn_red[4] = {}, rn_row[4] = {};
   // Cahn-Hilliard-Cook forcing: counter on the device (so graph replays
   // advance it) and its host mirror
   bool noise = false;
@@ -348,7 +403,6 @@ struct chx_ens_s {
   size_t k1_real_off = 0, k1_spec_off = 0, k1_part_off = 0;
   std::vector<long> k1_poff;  // per run: offset (doubles) of its partials
   ~chx_ens_s() {
-    for (auto h : rh) (void)ch_destroy(h);
     for (auto& g : k1_groups)
       if (g.plan) (void)hipfftDestroy(g.plan);
     if (mom_mem) (void)hipFree(mom_mem);
@@ -420,11 +474,10 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
                              E->red_lds, st);
     if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st);
   }
+  // the states written out with their final diagnostics in the same pass
   if (e == hipSuccess && E->nbig > 0)
-    e = launch_ens_finalize(E->druns, E->hcls, it + E->o_fin, E->n_fin, ws, nsteps - 1, st);
-  if (e == hipSuccess && diag_out && E->nbig > 0)
-    e = launch_ens_diag(E->druns, E->hcls, it + E->o_dpart, E->n_dpart, E->dbig, E->nbig, ws,
-                        diag_out, dstride, nsteps, st);
+    e = launch_ens_column_final(E->druns, E->hcls, it + E->o_col, E->n_col, E->dbig, E->nbig, ws,
+                                nsteps - 1, diag_out, dstride, nsteps, st);
   if (fork) {  // join even after a failure, so no capture is left open
     const hipError_t j = hipStreamWaitEvent(st, E->ev_join, 0);
     if (e == hipSuccess) e = j;
@@ -677,22 +730,30 @@ int batch1d_step_rewrite(chx_batch1d b, int batch, double* x, long ld, int nstep
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
-int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
+int stencil2d_apply(const void* in, void* out, int nx, int ny, long ld, int dtype,
                     const double* weights, int left, int right, int top, int bottom, int periodic,
                     int premap, chx_stream s) {
   if (!in || !out || !weights) return CHX_EINVAL;
+  if (dtype != CHX_F64 && dtype != CHX_F32) return CHX_EINVAL;
   if (nx < 1 || ny < 1 || ld < nx) return CHX_EINVAL;
   if (left < 0 || right < 0 || top < 0 || bottom < 0) return CHX_EINVAL;
   if (left > 4 || right > 4 || top > 4 || bottom > 4) return CHX_EINVAL;
   if (premap != 0 && premap != 1) return CHX_EINVAL;
   const char* a0 = reinterpret_cast<const char*>(in);
   const char* b0 = reinterpret_cast<const char*>(out);
-  const size_t span = ((size_t)(ny - 1) * ld + nx) * sizeof(double);
+  const size_t elem = dtype == CHX_F32 ? sizeof(float) : sizeof(double);
+  const size_t span = ((size_t)(ny - 1) * ld + nx) * elem;
   if (a0 < b0 + span && b0 < a0 + span) return CHX_EINVAL;  // buffers overlap
   const int nw = (left + right + 1) * (top + bottom + 1);
   if (!finite_all(weights, nw)) return CHX_EINVAL;
-  hipError_t e = launch_stencil2d(in, out, nx, ny, ld, weights, left, right, top, bottom,
-                                  periodic ? 1 : 0, premap, static_cast<hipStream_t>(s));
+  const hipStream_t st = static_cast<hipStream_t>(s);
+  hipError_t e =
+      dtype == CHX_F32
+          ? launch_stencil2d_f32(static_cast<const float*>(in), static_cast<float*>(out), nx, ny,
+                                 ld, weights, left, right, top, bottom, periodic ? 1 : 0, premap,
+                                 st)
+          : launch_stencil2d(static_cast<const double*>(in), static_cast<double*>(out), nx, ny,
+                             ld, weights, left, right, top, bottom, periodic ? 1 : 0, premap, st);
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
@@ -701,8 +762,9 @@ int stencil2d_apply(const double* in, double* out, int nx, int ny, long ld,
 namespace {
 
 // Autotuning of the multi-kernel step's separator stage: every candidate is
-// launched on zeroed scratch buffers of the real size (two warm-up rounds,
-// then five timed with events on a private stream): the separator kernel in
+// launched on zeroed scratch buffers of the real size (five rounds captured
+// into a graph, replayed once to warm up and once timed with events on a
+// private stream): the separator kernel in
 // each tile shape whose LDS fits, followed by the row pass, and the split row
 // pass in each of its shapes (fused separators + interior rows, then the
 // separator rows).  The fastest combination is kept.  Results are cached per
@@ -711,6 +773,7 @@ namespace {
 struct Tuned {
   int red_shape = 0;
   int split = -1;
+  int col_order = 0;
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, Tuned> g_tune_cache;
@@ -748,14 +811,26 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
             hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
             hipMemsetAsync(rho, 0, rho_bytes, st) == hipSuccess &&
             hipMemsetAsync(dst, 0, dst_bytes, st) == hipSuccess;
-  // time(run) = milliseconds of five rounds of run() after two warm-up rounds
+  // time(run) = milliseconds of five rounds of run(), captured into a graph
+  // that is replayed once to warm up and once between two events: on small
+  // grids the kernels finish faster than the host can launch them one by one,
+  // and a timing of eager launches would measure the host instead
   auto time_it = [&](auto&& run) {
     float ms = -1.f;
-    for (int k = 0; ok && k < 2; ++k) ok = run() == hipSuccess;
-    ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    for (int k = 0; ok && k < 5; ++k) ok = run() == hipSuccess;
-    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    ok = ok && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      bool launched = true;
+      for (int k = 0; launched && k < 5; ++k) launched = run() == hipSuccess;
+      ok = hipStreamEndCapture(st, &g) == hipSuccess && launched && g != nullptr;
+    }
+    ok = ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess &&
+         hipGraphLaunch(ge, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess &&
+         hipGraphLaunch(ge, st) == hipSuccess && hipEventRecord(e1, st) == hipSuccess &&
+         hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
     return ms;
   };
   DevChunk trial = c;
@@ -813,12 +888,34 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
     if (ej) (void)hipEventDestroy(ej);
     if (side) (void)hipStreamDestroy(side);
   }
+  // tile order of the column pass: the pass with its diagnostics, reading
+  // the zeroed field as a previous step's buffer (a second field buffer
+  // takes its output)
+  double *ybuf = nullptr, *part = nullptr;
+  const long nparts = ch_column_pass_blocks(nx, c.S);
+  if (ok && hipMalloc(&ybuf, dst_bytes) == hipSuccess &&
+      hipMalloc(&part, (size_t)nparts * 2 * sizeof(double)) == hipSuccess) {
+    ChCoef K{};
+    float best_col = -1.f;
+    for (int order = 0; ok && order < CHX_NUM_COLUMN_ORDERS; ++order) {
+      const float ms = time_it([&]() {
+        return launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, c, rho, K, part, st,
+                                     nullptr, order);
+      });
+      if (ok && (best_col < 0.f || ms < best_col)) {
+        best_col = ms;
+        best.col_order = order;
+      }
+    }
+  }
   if (st) (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st) (void)hipStreamDestroy(st);
   if (rho) (void)hipFree(rho);
   if (dst) (void)hipFree(dst);
+  if (ybuf) (void)hipFree(ybuf);
+  if (part) (void)hipFree(part);
   if (!ok) {
     (void)hipGetLastError();  // a failed trial leaves the defaults
     return Tuned{};
@@ -887,16 +984,28 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     delete h;
     return CHX_EINVAL;
   }
+  // FP32 sweeps in each direction: the error of one refined pass is about
+  // (kappa_x + kappa_y) 2^-24, the two 1D solves' errors adding
+  if (q.dtype == CHX_F32_REFINED && refinement_fails(h->px->kappa + h->py->kappa)) {
+    delete h;
+    return CHX_EREFINE;
+  }
   const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
   const long diag_parts = ch_diag_partial_blocks(q.nx, q.ny);
   size_t off = 0;
   if (q.dtype == CHX_F32_REFINED) {
+    // r (FP64), the FP32 chunk-solved columns, their separator parts, and
+    // one FP32 buffer per solve of the step (the deferred solutions V_k)
+    const size_t field32 = align256((size_t)q.nx * q.ny * sizeof(float));
     h->off_r = off; off += field;
-    h->off_R = off; off += field;
-    h->off_y32 = off; off += align256((size_t)q.nx * q.ny * sizeof(float));
+    h->off_y32 = off; off += field32;
     h->off_rho32 = off;
     off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(float));
-    h->part_count = diag_parts;
+    for (int k = 0; k <= q.refine_passes; ++k) {
+      h->off_v32[k] = off;
+      off += field32;
+    }
+    h->part_count = std::max(rstep_parts(q.nx, q.ny), diag_parts);
   } else if (h->fast) {
     h->off_b0 = off; off += field;
     h->off_b1 = off; off += field;
@@ -938,6 +1047,7 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     const Tuned t = tune_step(h->py, h->px, q.nx, q.ny);
     h->py->dchunk.red_shape = t.red_shape;
     h->split = t.split;
+    h->col_order = t.col_order;
   }
   *out = h;
   return CHX_OK;
@@ -949,13 +1059,20 @@ int ch_get_tuning(chx_ch h, int what, int* value) {
     case CHX_TUNE_REDUCED_SHAPE: *value = h->py->dchunk.red_shape; return CHX_OK;
     case CHX_TUNE_SMALL_PATH: *value = h->small ? 1 : 0; return CHX_OK;
     case CHX_TUNE_ROW_SPLIT: *value = h->split; return CHX_OK;
+    case CHX_TUNE_COLUMN_ORDER: *value = h->col_order; return CHX_OK;
+    case CHX_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; return CHX_OK;
     default: return CHX_EINVAL;
   }
 }
 
 int ch_set_tuning(chx_ch h, int what, int value) {
   if (!h) return CHX_EINVAL;
+  h->drop_graph();  // a captured call holds the old choices
   switch (what) {
+    case CHX_TUNE_GRAPH:
+      if (value != 0 && value != 1) return CHX_EINVAL;
+      h->use_graph = value == 1;
+      return CHX_OK;
     case CHX_TUNE_REDUCED_SHAPE:
       if (value < 0 || value >= kNumRedShapes) return CHX_EINVAL;
       h->py->dchunk.red_shape = value;
@@ -972,6 +1089,10 @@ int ch_set_tuning(chx_ch h, int what, int value) {
         return CHX_EINVAL;
       }
       h->split = value;
+      return CHX_OK;
+    case CHX_TUNE_COLUMN_ORDER:
+      if (value < 0 || value >= CHX_NUM_COLUMN_ORDERS) return CHX_EINVAL;
+      h->col_order = value;
       return CHX_OK;
     default: return CHX_EINVAL;
   }
@@ -1062,50 +1183,60 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
   auto B = [&]() { if (tm && tm->on) tm->begin(); };
   auto E = [&](int ph) { if (tm && tm->on) tm->end(ph); };
   if (h->prm.dtype == CHX_F32_REFINED) {
-    // r = RHS(c) in FP64; c = A32^{-1} r by FP32 column and row sweeps; then
-    // refine: R = r - A c (FP64), c += A32^{-1} R
+    // pass 0: r = RHS(c) (FP64, kept) swept in FP32 down the columns, the
+    // FP32 separators, FP32 row solves into V_0; pass k: R = r - A x_{k-1}
+    // (x_{k-1} rebuilt from V_0 .. V_{k-1}) swept the same way into V_k;
+    // then c = x_p, with the final state's diagnostics on the last step
     double* r = reinterpret_cast<double*>(base + h->off_r);
-    double* Rb = reinterpret_cast<double*>(base + h->off_R);
     float* y32 = reinterpret_cast<float*>(base + h->off_y32);
     float* rho32 = reinterpret_cast<float*>(base + h->off_rho32);
+    const int np = h->prm.refine_passes;
+    float* V[4] = {};
+    for (int k = 0; k <= np; ++k) V[k] = reinterpret_cast<float*>(base + h->off_v32[k]);
+    const long rparts = rstep_parts(nx, ny);
     for (int n = 0; n < nsteps && ok(); ++n) {
       if (tm) tm->step(n);
-      if (diag_out) {
+      const bool diag = diag_out != nullptr;
+      B();
+      e = launch_rstep_first(c, ld, r, y32, rho32, nx, ny, h->py->dchunk, h->K,
+                             diag ? part : nullptr, st);
+      E(0);
+      if (ok()) {
         B();
-        e = launch_ch_diag(c, ld, nx, ny, h->K, part, diag_out + 2 * n, st);
-        E(3);
+        e = launch_reduced_il32(h->py->dchunk, rho32, nx, y32, nx, st, diag ? part : nullptr,
+                                diag ? rparts : 0, h->K.dxdy, diag ? diag_out + 2 * n : nullptr);
+        E(1);
       }
       if (ok()) {
         B();
-        e = launch_ch_rhs_plain(c, ld, r, nx, nx, ny, h->K, st);
-        E(0);
-      }
-      if (ok()) {
-        B();
-        e = launch_chunked_il32<2>(h->py->dchunk, r, nx, y32, rho32, c, ld, nx, false, st);
-        E(0);
-      }
-      if (ok()) {
-        B();
-        e = launch_rows_lds32<2>(h->px->dchunk, c, ld, c, ld, ny, false, st);
+        e = launch_rows_lds_f32(h->px->dchunk, y32, V[0], ny, st);
         E(2);
       }
-      for (int k = 0; k < h->prm.refine_passes && ok(); ++k) {
+      for (int k = 1; k <= np && ok(); ++k) {
         B();
-        e = launch_ch_residual2d(r, nx, c, ld, Rb, nx, nx, ny, h->cxs, h->cys, st);
-        E(1);
+        e = launch_rstep_resid(r, V, k, y32, rho32, nx, ny, h->py->dchunk, h->cxs, h->cys, st);
+        E(0);
         if (ok()) {
           B();
-          e = launch_chunked_il32<2>(h->py->dchunk, Rb, nx, y32, rho32, Rb, nx, nx, false, st);
-          E(0);
+          e = launch_reduced_il32(h->py->dchunk, rho32, nx, y32, nx, st);
+          E(1);
         }
         if (ok()) {
           B();
-          e = launch_rows_lds32<2>(h->px->dchunk, Rb, nx, c, ld, ny, true, st);
+          e = launch_rows_lds_f32(h->px->dchunk, y32, V[k], ny, st);
           E(2);
         }
       }
+      if (ok()) {
+        if (tm && n + 1 == nsteps) tm->on = true;
+        B();
+        e = launch_rstep_final(V, np + 1, c, ld, nx, ny, h->py->dchunk, h->K, part,
+                               (diag && n + 1 == nsteps) ? diag_out + 2 * nsteps : nullptr, st);
+        E(3);
+      }
     }
+    if (tm && tm->failed) return CHX_EHIP;
+    return ok() ? CHX_OK : CHX_EHIP;
   } else if (h->small) {
     // one workgroup, field resident in LDS for all steps; it also writes the
     // diagnostics of every state, the final one included
@@ -1133,7 +1264,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
         B();
         const SmallNoise nz = noise_of(n);  // Cahn-Hilliard-Cook draws of this step
         e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho,
-                                  h->K, part, st, noise ? &nz : nullptr);
+                                  h->K, part, st, noise ? &nz : nullptr, h->col_order);
         E(0);
       }
       if (ok() && h->split == kSplitOverlap && !(tm && tm->on)) {
@@ -1185,10 +1316,15 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     }
     if (tm) tm->on = true;
     if (ok()) {
+      // the state written out with the final diagnostics in the same pass
       B();
-      e = launch_ch_finalize(src, lds, c, ld, nx, ny, h->py->dchunk, st);
+      e = launch_ch_column_final(src, lds, c, ld, nx, ny, h->py->dchunk, h->K, part,
+                                 diag_out ? diag_out + 2 * nsteps : nullptr, st, h->col_order);
       E(3);
     }
+    if (ok() && noise) h->noise_step += (unsigned long long)nsteps;
+    if (tm && tm->failed) return CHX_EHIP;
+    return ok() ? CHX_OK : CHX_EHIP;
   } else {
     double* r = reinterpret_cast<double*>(base + h->off_r);
     for (int n = 0; n < nsteps && ok(); ++n) {
@@ -1233,19 +1369,29 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
 }
 
 namespace {
-// The runs of an FP32-refined ensemble in turn, each through its class's
-// refined step (all on stream st, so they share the one workspace).
+// An FP32-refined ensemble: the refined step's phases, one launch per phase
+// for all runs (pass k covers the runs with at least k refine passes).
 int ens_launch_refined(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws,
                        hipStream_t st) {
   const long dstride = 2L * (nsteps + 1);
-  for (int r = 0; r < E->nruns; ++r) {
-    const EnsRun& R = E->runs[r];
-    const int rc = run_steps(E->rh[R.cls], R.c, R.ldc, nsteps,
-                             diag_out ? diag_out + r * dstride : nullptr, ws, E->ws_total, st,
-                             nullptr);
-    if (rc != CHX_OK) return rc;
+  const int4* it = E->ditems;
+  hipError_t e = hipSuccess;
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    for (int k = 0; k <= E->max_passes && e == hipSuccess; ++k) {
+      e = launch_ens_rstep_column(k, k == 0 && diag_out, E->druns, E->hcls, it + E->o_col,
+                                  E->rn_col[k], ws, st);
+      if (e == hipSuccess)
+        e = launch_ens_reduced32(E->druns, E->hcls, it + E->o_red, E->rn_red[k], ws, n,
+                                 k == 0 ? diag_out : nullptr, dstride, E->red_lds, st);
+      if (e == hipSuccess)
+        e = launch_ens_rows32(E->druns, E->hcls, it + E->o_row, E->rn_row[k], ws, k, st);
+    }
+    if (e == hipSuccess)
+      e = launch_ens_rstep_final(E->druns, E->hcls, it + E->o_col, E->rn_col[0], E->dbig,
+                                 E->nbig, ws, n + 1 == nsteps ? diag_out : nullptr, dstride,
+                                 nsteps, st);
   }
-  return CHX_OK;
+  return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 }  // namespace
 
@@ -1324,8 +1470,49 @@ int ch_adi_step_p2(chx_ch h, double* c, double* cprev, long ld, int nsteps, doub
 
 int ch_adi_step(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
                 size_t ws_bytes, chx_stream s) {
-  return run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, static_cast<hipStream_t>(s),
-                   nullptr);
+  hipStream_t st = static_cast<hipStream_t>(s);
+  // forced handles draw new noise every call (host-side step counter) and
+  // the single-workgroup path is one launch already: both run eagerly
+  if (!h || !h->use_graph || h->sigma > 0 || h->small)
+    return run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, st, nullptr);
+  // the argument checks run_steps makes, before anything is captured
+  if (!c || h->prm.scheme != CHX_SCHEME_P1 || ld < h->prm.nx || nsteps < 1) return CHX_EINVAL;
+  if (!ws || ws_bytes < ws_need(h)) return CHX_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return CHX_EINVAL;
+  if (!h->gexec || h->g_c != c || h->g_ld != ld || h->g_nsteps != nsteps ||
+      h->g_diag != diag_out || h->g_ws != ws) {
+    h->drop_graph();
+    if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+      h->cap = nullptr;
+      return CHX_EHIP;
+    }
+    if (!h->g_done && hipEventCreateWithFlags(&h->g_done, hipEventDisableTiming) != hipSuccess) {
+      h->g_done = nullptr;
+      return CHX_EHIP;
+    }
+    if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return CHX_EHIP;
+    const int rc = run_steps(h, c, ld, nsteps, diag_out, ws, ws_bytes, h->cap, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (rc != CHX_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != CHX_OK ? rc : CHX_EHIP;
+    }
+    if (hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      h->gexec = nullptr;
+      return CHX_EHIP;
+    }
+    h->graph = g;
+    h->g_c = c;
+    h->g_ld = ld;
+    h->g_nsteps = nsteps;
+    h->g_diag = diag_out;
+    h->g_ws = ws;
+  }
+  if (hipGraphLaunch(h->gexec, st) != hipSuccess) return CHX_EHIP;
+  return hipEventRecord(h->g_done, st) == hipSuccess ? CHX_OK : CHX_EHIP;
 }
 
 int ch_adi_step_timed(chx_ch h, double* c, long ld, int nsteps, double* diag_out, void* ws,
@@ -1431,39 +1618,132 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s) {
 // combination; each gets one refined single-run handle.
 static int ens_create_refined(chx_ens_s* E) {
   E->refined = true;
+  const int nruns = E->nruns;
+  const std::vector<chx_ch_params>& prm = E->prm;
+  std::vector<int> cls_of(nruns, -1);
   std::vector<chx_ch_params> reps;
-  E->runs.resize(E->nruns);
-  size_t ws = 256;
-  for (int r = 0; r < E->nruns; ++r) {
-    const chx_ch_params& q = E->prm[r];
-    if (q.scheme != CHX_SCHEME_P1) return CHX_EINVAL;
-    int cls = -1;
+  for (int r = 0; r < nruns; ++r) {
+    const chx_ch_params& q = prm[r];
+    if (q.scheme != CHX_SCHEME_P1 || q.nx % 64 != 0 || q.ny % kChunk != 0 ||
+        q.nx / kChunk > 256 || q.refine_passes < 1 || q.refine_passes > 3 || !(q.lx > 0) ||
+        !(q.ly > 0) || !(q.dt > 0) || !(q.D >= 0) || !(q.gamma >= 0))
+      return CHX_EINVAL;
     for (size_t c = 0; c < reps.size(); ++c)
-      if (same_grid(reps[c], q) && reps[c].refine_passes == q.refine_passes) cls = (int)c;
-    if (cls < 0) {
+      if (same_grid(reps[c], q)) cls_of[r] = (int)c;
+    if (cls_of[r] < 0) {
       if ((int)reps.size() == kEnsMaxClasses) return CHX_EINVAL;
-      chx_ch h = nullptr;
-      const int rc = ch_create(&q, &h);
-      if (rc != CHX_OK) return rc;
-      E->rh.push_back(h);
-      cls = (int)reps.size();
+      cls_of[r] = (int)reps.size();
       reps.push_back(q);
-      ws = std::max(ws, ch_ws_bytes(h));
     }
+    E->max_passes = std::max(E->max_passes, q.refine_passes);
+  }
+  size_t lds_max = 0;
+  for (const auto& q : reps) {  // the plans ch_create makes for such a run
+    const double dx = q.lx / q.nx, dy = q.ly / q.ny;
+    const double sx = q.D * q.gamma * q.dt / (dx * dx * dx * dx);
+    const double sy = q.D * q.gamma * q.dt / (dy * dy * dy * dy);
+    const double cxs[5] = {sx, -4 * sx, 1 + 6 * sx, -4 * sx, sx};
+    const double cys[5] = {sy, -4 * sy, 1 + 6 * sy, -4 * sy, sy};
+    BandPlan *a = nullptr, *b = nullptr;
+    int rc = make_plan(2, q.nx, cxs, 1, &a);
+    if (rc == CHX_OK) rc = make_plan(2, q.ny, cys, 1, &b);
+    if (rc == CHX_OK && (!a->has_chunk || !b->has_chunk)) rc = CHX_EINVAL;
+    if (rc == CHX_OK && refinement_fails(a->kappa + b->kappa)) rc = CHX_EREFINE;
+    E->px.push_back(a);
+    E->py.push_back(b);
+    if (rc != CHX_OK) return rc;
+    EnsClass ec;
+    ec.px = a->dchunk;
+    ec.py = b->dchunk;
+    ec.K = make_coef(q);
+    E->classes.push_back(ec);
+    lds_max = std::max(lds_max, ens_reduced_lds_bytes(b->chunk.dcount));
+  }
+  if (lds_max > 64 * 1024) return CHX_EINVAL;
+  E->red_lds = lds_max;
+  // more passes first, then larger runs first
+  std::vector<int> order(nruns);
+  for (int r = 0; r < nruns; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (prm[a].refine_passes != prm[b].refine_passes)
+      return prm[a].refine_passes > prm[b].refine_passes;
+    return (long)prm[a].nx * prm[a].ny > (long)prm[b].nx * prm[b].ny;
+  });
+  size_t off = 0;
+  E->runs.resize(nruns);
+  for (int r = 0; r < nruns; ++r) {
+    const chx_ch_params& q = prm[r];
     EnsRun& R = E->runs[r];
-    R.c = nullptr;
+    std::memset(&R, 0, sizeof(R));
     R.ldc = q.nx;
-    R.off_b0 = R.off_b1 = R.off_rho = R.off_part = 0;
     R.nx = q.nx;
     R.ny = q.ny;
-    R.cls = cls;
-    R.ncb = R.Sc = R.ndbx = R.ndby = 0;
-    R.ncolblocks = 0;
-    R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
-    R.nseed = 0;
+    R.cls = cls_of[r];
+    R.Sc = q.ny / kChunk;
+    R.passes = q.refine_passes;
+    R.nseg = rstep_segments(q.nx);
+    R.ncb = (R.nseg + 3) / 4;
+    R.ncolblocks = (long)R.nseg * R.Sc;  // (mass, energy) partials of the column kernels
+    const size_t field = align256((size_t)q.nx * q.ny * sizeof(double));
+    const size_t field32 = align256((size_t)q.nx * q.ny * sizeof(float));
+    R.off_r = off; off += field;
+    R.off_y32 = off; off += field32;
+    R.off_rho32 = off; off += align256((size_t)R.Sc * 4 * q.nx * sizeof(float));
+    for (int k = 0; k <= R.passes; ++k) {
+      R.off_v[k] = off;
+      off += field32;
+    }
+    R.off_part = off;
+    off += align256((size_t)R.ncolblocks * 2 * sizeof(double));
+    E->max_points = std::max(E->max_points, (long)q.nx * q.ny);
   }
-  E->ws_total = ws;
-  return CHX_OK;
+  E->ws_total = std::max(off, (size_t)256);
+  std::vector<int4> items;
+  auto add = [&](int r, int a, int b) { items.push_back(make_int4(r, a, b, 0)); };
+  auto prefix = [&](int (&cnt)[4], long o) {
+    for (int k = 0; k < 4; ++k) cnt[k] = 0;
+    for (size_t t = (size_t)o; t < items.size(); ++t)
+      for (int k = 0; k <= prm[items[t].x].refine_passes; ++k) ++cnt[k];
+  };
+  E->o_col = (long)items.size();
+  for (int r : order)
+    for (int kc = 0; kc < E->runs[r].Sc; ++kc)
+      for (int sb = 0; sb < E->runs[r].ncb; ++sb) add(r, sb, kc);
+  prefix(E->rn_col, E->o_col);
+  E->o_red = (long)items.size();
+  for (int r : order) {
+    const int nby = (E->runs[r].Sc + 31) / 32, nbx = (E->runs[r].nx + 63) / 64;
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) add(r, bx, by);
+  }
+  prefix(E->rn_red, E->o_red);
+  E->o_row = (long)items.size();
+  for (int r : order) {
+    const int S = E->runs[r].nx / kChunk, R = 256 / S;
+    const int ng = (E->runs[r].ny + R - 1) / R;
+    for (int g = 0; g < ng; ++g) add(r, g, 0);
+  }
+  prefix(E->rn_row, E->o_row);
+  E->nbig = nruns;
+  for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
+  const size_t b_runs = align256(sizeof(EnsRun) * nruns);
+  const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
+  const size_t b_lists = align256(sizeof(int) * nruns);
+  if (hipMalloc(&E->dmem, b_runs + b_items + b_lists) != hipSuccess) {
+    E->dmem = nullptr;
+    return CHX_EHIP;
+  }
+  auto* base = static_cast<unsigned char*>(E->dmem);
+  E->druns = reinterpret_cast<EnsRun*>(base);
+  E->ditems = reinterpret_cast<int4*>(base + b_runs);
+  E->dbig = reinterpret_cast<int*>(base + b_runs + b_items);
+  bool ok = hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * nruns, hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(E->ditems, items.data(), sizeof(int4) * items.size(),
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(E->dbig, order.data(), sizeof(int) * nruns, hipMemcpyHostToDevice) ==
+                hipSuccess;
+  return ok ? CHX_OK : CHX_EHIP;
 }
 
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
@@ -1572,8 +1852,6 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     R.cls = cls_of[r];
     R.ncb = ((q.nx >> 6) + 3) / 4;
     R.Sc = q.ny / kChunk;
-    R.ndbx = (q.nx + 63) / 64;
-    R.ndby = (q.ny + 15) / 16;
     R.ncolblocks = (long)R.ncb * R.Sc;
     R.nscale = R.ninv_dx = R.ninv_dy = 0.0;
     R.nseed = 0;
@@ -1587,7 +1865,7 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     R.off_b1 = off; off += field;
     R.off_rho = off; off += align256((size_t)R.Sc * 4 * q.nx * sizeof(double));
     R.off_part = off;
-    off += align256((size_t)std::max(R.ncolblocks, (long)R.ndbx * R.ndby) * 2 * sizeof(double));
+    off += align256((size_t)R.ncolblocks * 2 * sizeof(double));
   }
   E->ws_total = std::max(off, (size_t)256);
   std::vector<int4> items;
@@ -1611,16 +1889,6 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     for (int g = 0; g < ng; ++g) add(r, g, 0);
   }
   E->n_row = (int)(items.size() - E->o_row);
-  E->o_fin = (long)items.size();
-  for (int r : order)
-    for (int by = 0; by < (E->runs[r].ny + 3) / 4; ++by)
-      for (int bx = 0; bx < (E->runs[r].nx + 63) / 64; ++bx) add(r, bx, by);
-  E->n_fin = (int)(items.size() - E->o_fin);
-  E->o_dpart = (long)items.size();
-  for (int r : order)
-    for (int by = 0; by < E->runs[r].ndby; ++by)
-      for (int bx = 0; bx < E->runs[r].ndbx; ++bx) add(r, bx, by);
-  E->n_dpart = (int)(items.size() - E->o_dpart);
 
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
@@ -1686,16 +1954,7 @@ int ch_ensemble_step(chx_ens E, double* const* c_runs, const long* ld_runs, int 
       changed = true;
     }
   }
-  if (changed && E->refined && E->gexec) {
-    // the refined runs' launches carry the field pointers themselves, so a
-    // cached graph of them is stale: drop it once the queued work is done
-    if (hipStreamSynchronize(st) != hipSuccess) return CHX_EHIP;
-    (void)hipGraphExecDestroy(E->gexec);
-    if (E->graph) (void)hipGraphDestroy(E->graph);
-    E->gexec = nullptr;
-    E->graph = nullptr;
-  }
-  if (changed && !E->refined) {  // work already queued may still read the table
+  if (changed) {  // work already queued may still read the table
     if (hipStreamSynchronize(st) != hipSuccess) return CHX_EHIP;
     if (hipMemcpy(E->druns, E->runs.data(), sizeof(EnsRun) * E->nruns, hipMemcpyHostToDevice) !=
         hipSuccess)

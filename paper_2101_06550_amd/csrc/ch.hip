@@ -17,7 +17,7 @@
 // The column-chunk correction x = y - Zl s_prev - Zr s_own mixes rows only and
 // the row solve mixes columns only, so the correction is applied AFTER the row
 // solve, by the next step's column pass while it reads the state (or by
-// ch_finalize after the last step).  Separator rows then hold the row-solved
+// the final pass ch_column_final after the last step).  Separator rows then hold the row-solved
 // separator values T, and the state is X(j) = V(j) - Zl T_prev - Zr T_own.
 #include <hip/hip_runtime.h>
 
@@ -118,7 +118,12 @@ __device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigne
 // step nz.step0, drawn here: each thread carries its column's pair down the
 // rows and takes the right neighbour's rho_x from the next lane (the wave's
 // last lane from LDS, drawn before the barrier).
-template <bool RECON, bool DIAG, bool NOISE = false>
+// FINAL: the pass after the last step of a call: the state is reconstructed
+// as it is read (RECON), its mass and free energy summed (DIAG), and the
+// state itself written to ybuf (the caller's array) -- no right-hand side, no
+// sweep; one streaming pass instead of a correction pass and a separate
+// diagnostics pass over the result.
+template <bool RECON, bool DIAG, bool NOISE = false, bool FINAL = false>
 __device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
                                                  double* __restrict__ ybuf, long ldy, int nx,
                                                  int ny, int Sc, const double* __restrict__ rec,
@@ -224,7 +229,7 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
       const double dyy_c = xc_p + xc_m - 2.0 * xc_c;
       const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
       double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
-      if (NOISE) {
+      if (NOISE && !FINAL) {
         const int j = kc * M + p, jn = (j + 1 == ny) ? 0 : j + 1;
         double rx_n, ry_n;
         cook_pair(nz.seed_state, nz.step0, jn, i, nx, ny, rx_n, ry_n);
@@ -240,36 +245,44 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
         msum += xc_c;
         esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
       }
-      if (p < MI) {  // forward sweep step of the chunk interior (g overwrites f)
-        if (p >= 2) r = r - eps * f[p - 2];
-        if (p >= 1) r = r - rec[p * 8 + 1] * f[p - 1];
-        r = r * rec[p * 8 + 0];
+      if (FINAL) {
+        __builtin_nontemporal_store(xc_c, &ybuf[((long)kc * M + p) * ldy + i]);
+        if (DIAG) asm volatile("" : "+v"(msum), "+v"(esum));
+      } else {
+        if (p < MI) {  // forward sweep step of the chunk interior (g overwrites f)
+          if (p >= 2) r = r - eps * f[p - 2];
+          if (p >= 1) r = r - rec[p * 8 + 1] * f[p - 1];
+          r = r * rec[p * 8 + 0];
+        }
+        if (DIAG) asm volatile("" : "+v"(r), "+v"(msum), "+v"(esum));
+        else asm volatile("" : "+v"(r));
+        f[p] = r;
       }
-      if (DIAG) asm volatile("" : "+v"(r), "+v"(msum), "+v"(esum));
-      else asm volatile("" : "+v"(r));
-      f[p] = r;
       xl_m = xl_c; xc_m = xc_c; xr_m = xr_c;
       xl_c = xl_p; xc_c = xc_p; xr_c = xr_p;
     }
-    // back sweep of the interior (y = R^{-1} g)
+    if (!FINAL) {
+      // back sweep of the interior (y = R^{-1} g)
 #pragma unroll
-    for (int p = MI - 1; p >= 0; --p) {
-      double v = f[p];
-      if (p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
-      if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
-      f[p] = v;
-    }
-    double pa[P], pb[P];
-    chunk_parts<P, M, double>(f, bd, pa, pb);
-    // streamed stores (non-temporal): the row pass reads y back from HBM; on
-    // gfx950 this keeps the stores out of the way of the loads (measured:
-    // both passes faster than with ordinary stores, the loads stay ordinary)
+      for (int p = MI - 1; p >= 0; --p) {
+        double v = f[p];
+        if (p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
+        if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
+        f[p] = v;
+      }
+      double pa[P], pb[P];
+      chunk_parts<P, M, double>(f, bd, pa, pb);
+      // streamed stores (non-temporal): the row pass reads y back from HBM; on
+      // gfx950 this keeps the stores out of the way of the loads (measured:
+      // both passes faster than with ordinary stores, the loads stay ordinary)
 #pragma unroll
-    for (int p = 0; p < MI; ++p) __builtin_nontemporal_store(f[p], &ybuf[((long)kc * M + p) * ldy + i]);
+      for (int p = 0; p < MI; ++p)
+        __builtin_nontemporal_store(f[p], &ybuf[((long)kc * M + p) * ldy + i]);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
-      rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+      for (int a = 0; a < P; ++a) {
+        rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
+        rho[((long)kc * 2 * P + P + a) * nx + i] = pb[a];
+      }
     }
   }
   if (DIAG) {
@@ -281,6 +294,30 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
   }
 }
 
+// Tile (column block cb, chunk kc) of launch block b (1D grid of ncb * Sc
+// blocks).  Consecutive blocks go to the 8 XCDs round robin, so the blocks of
+// XCD g are b = g, g + 8, ...; orders 1 and 2 number them so that each XCD
+// works one contiguous range of tiles: order 1 in chunk-row order (an XCD
+// holds a horizontal band of chunk rows), order 2 chunk-fastest down column
+// blocks (an XCD holds whole columns).  Order 0: plain row-major tile order.
+// A tile's diagnostics slot is its tile number, so every order sums the same
+// partials in the same order.
+__device__ __forceinline__ void column_tile(int order, long b, int ncb, int Sc, int& cb, int& kc) {
+  long t = b;
+  if (order != 0) {
+    const long T = (long)ncb * Sc, base = T >> 3, rem = T & 7;
+    const long g = b & 7, q = b >> 3;
+    t = g * base + (g < rem ? g : rem) + q;
+  }
+  if (order == 2) {
+    cb = (int)(t / Sc);
+    kc = (int)(t - (long)cb * Sc);
+  } else {
+    kc = (int)(t / ncb);
+    cb = (int)(t - (long)kc * ncb);
+  }
+}
+
 template <bool RECON, bool DIAG, bool NOISE>
 __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
                                                       double* __restrict__ ybuf, long ldy, int nx,
@@ -288,43 +325,32 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
                                                       const double* __restrict__ rec,
                                                       BandT<double> bd, double* __restrict__ rho,
                                                       ChCoef K, double* __restrict__ part,
-                                                      SmallNoise nz) {
-  const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+                                                      SmallNoise nz, int ncb, int order) {
+  int cb, kc;
+  column_tile(order, blockIdx.x, ncb, Sc, cb, kc);
+  const long slot = (long)kc * ncb + cb;
   column_pass_body<RECON, DIAG, NOISE>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
-                                       DIAG ? part + 2 * b : nullptr, blockIdx.x, blockIdx.y, nz);
+                                       DIAG ? part + 2 * slot : nullptr, cb, kc, nz);
+}
+
+// The pass after the last step: reconstruct the state, write it to dst and
+// (DIAG) leave one (mass, energy) partial per block in part.
+template <bool DIAG>
+__global__ __launch_bounds__(256) void ch_column_final(const double* __restrict__ src, long lds,
+                                                       double* __restrict__ dst, long ldd, int nx,
+                                                       int ny, int Sc,
+                                                       const double* __restrict__ rec,
+                                                       ChCoef K, double* __restrict__ part,
+                                                       int ncb, int order) {
+  int cb, kc;
+  column_tile(order, blockIdx.x, ncb, Sc, cb, kc);
+  const long slot = (long)kc * ncb + cb;
+  const BandT<double> bd{};
+  column_pass_body<true, DIAG, false, true>(src, lds, dst, ldd, nx, ny, Sc, rec, bd, nullptr, K,
+                                            DIAG ? part + 2 * slot : nullptr, cb, kc);
 }
 
 // ---------------------------------------------------------------------------
-
-// State X = V - Zl T_prev - Zr T_own written out to the caller's array;
-// block (bx, by) covers 64 columns x 4 rows.
-__device__ __forceinline__ void finalize_body(const double* __restrict__ src, long lds,
-                                              double* __restrict__ dst, long ldd, int nx, int ny,
-                                              int Sc, const double* __restrict__ rec, int bx,
-                                              int by) {
-  const int i = bx * 64 + (threadIdx.x & 63);
-  const int j = by * 4 + (threadIdx.x >> 6);
-  if (i >= nx || j >= ny) return;
-  const int kc = j / M, p = j - kc * M;
-  double v = src[(long)j * lds + i];
-  if (p < MI) {
-    const int kcm = (kc - 1 + Sc) % Sc;
-#pragma unroll
-    for (int a = 0; a < P; ++a) {
-      const double tp = src[((long)kcm * M + MI + a) * lds + i];
-      const double to = src[((long)kc * M + MI + a) * lds + i];
-      v = v - rec[p * 8 + 4 + a] * tp - rec[p * 8 + 6 + a] * to;
-    }
-  }
-  dst[(long)j * ldd + i] = v;
-}
-
-__global__ __launch_bounds__(256) void ch_finalize(const double* __restrict__ src, long lds,
-                                                   double* __restrict__ dst, long ldd, int nx,
-                                                   int ny, int Sc,
-                                                   const double* __restrict__ rec) {
-  finalize_body(src, lds, dst, ldd, nx, ny, Sc, rec, blockIdx.x, blockIdx.y);
-}
 
 // Mass and free-energy partial sums of a plain field, one per block of
 // 64 columns x 16 rows (fixed order within the block).
@@ -469,15 +495,16 @@ hipError_t launch_ch_residual2d(const double* r, long ldr, const double* c, long
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
                                  double* rho, const ChCoef& K, double* part, hipStream_t st,
-                                 const SmallNoise* nz) {
+                                 const SmallNoise* nz, int order) {
   BandT<double> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = cy.coef[k];
-  dim3 grid(((nx >> 6) + 3) / 4, cy.S);
+  const int ncb = ((nx >> 6) + 3) / 4;
   const int Sc = cy.S;
+  dim3 grid((unsigned)((long)ncb * Sc));
   const SmallNoise z = nz ? *nz : SmallNoise{};
 #define CHX_COLPASS(R, D, N)                                                                      \
   hipLaunchKernelGGL((ch_column_pass<R, D, N>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
-                     ny, Sc, cy.rec, bd, rho, K, part, z)
+                     ny, Sc, cy.rec, bd, rho, K, part, z, ncb, order)
   if (nz) {
     if (recon && diag) CHX_COLPASS(true, true, true);
     else if (recon) CHX_COLPASS(true, false, true);
@@ -495,11 +522,21 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
 
 long ch_column_pass_blocks(int nx, int Sc) { return (long)(((nx >> 6) + 3) / 4) * Sc; }
 
-hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
-                              const DevChunk& cy, hipStream_t st) {
-  dim3 grid((nx + 63) / 64, (ny + 3) / 4);
-  hipLaunchKernelGGL(ch_finalize, grid, dim3(256), 0, st, src, lds, dst, ldd, nx, ny, cy.S,
-                     cy.rec);
+
+hipError_t launch_ch_column_final(const double* src, long lds, double* dst, long ldd, int nx,
+                                  int ny, const DevChunk& cy, const ChCoef& K, double* part,
+                                  double* diag_out, hipStream_t st, int order) {
+  const int ncb = ((nx >> 6) + 3) / 4;
+  dim3 grid((unsigned)((long)ncb * cy.S));
+  if (diag_out) {
+    hipLaunchKernelGGL((ch_column_final<true>), grid, dim3(256), 0, st, src, lds, dst, ldd, nx, ny,
+                       cy.S, cy.rec, K, part, ncb, order);
+    hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, (long)grid.x, K.dxdy,
+                       diag_out);
+  } else {
+    hipLaunchKernelGGL((ch_column_final<false>), grid, dim3(256), 0, st, src, lds, dst, ldd, nx,
+                       ny, cy.S, cy.rec, K, part, ncb, order);
+  }
   return hipGetLastError();
 }
 
@@ -1342,26 +1379,27 @@ __global__ void ens_noise_advance(unsigned long long* noise_step, int nsteps) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *noise_step += (unsigned long long)nsteps;
 }
 
-__global__ __launch_bounds__(256) void ens_finalize(const EnsRun* __restrict__ runs,
-                                                    EnsClasses cls,
-                                                    const int4* __restrict__ items,
-                                                    unsigned char* ws, int last_step) {
-  const int4 it = items[blockIdx.x];
-  const EnsRun R = runs[it.x];
-  finalize_body(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx, R.ny, R.Sc, cls.c[R.cls].py.rec,
-                it.y, it.z);
-}
 
-__global__ __launch_bounds__(256) void ens_diag_partial(const EnsRun* __restrict__ runs,
+// The pass after the last step for every multi-kernel run (column-pass work
+// items): state reconstructed into the caller's field, with its diagnostics
+// partials (DIAG) in the run's column-pass partial slots.
+template <bool DIAG>
+__global__ __launch_bounds__(256) void ens_column_final(const EnsRun* __restrict__ runs,
                                                         EnsClasses cls,
                                                         const int4* __restrict__ items,
-                                                        unsigned char* ws) {
+                                                        unsigned char* ws, int last_step) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
+  const EnsClass& C = cls.c[R.cls];
   double* part = reinterpret_cast<double*>(ws + R.off_part);
-  diag_partial_body(R.c, R.ldc, R.nx, R.ny, cls.c[R.cls].K,
-                    part + 2 * ((long)it.z * R.ndbx + it.y), it.y, it.z);
+  const BandT<double> bd{};
+  column_pass_body<true, DIAG, false, true>(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx,
+                                            R.ny, R.Sc, C.py.rec, bd, nullptr, C.K,
+                                            DIAG ? part + 2 * ((long)it.z * R.ncb + it.y)
+                                                 : nullptr,
+                                            it.y, it.z);
 }
+
 
 __global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__ runs,
                                                       EnsClasses cls, const int* __restrict__ big,
@@ -1370,7 +1408,7 @@ __global__ __launch_bounds__(256) void ens_diag_final(const EnsRun* __restrict__
   const int r = big[blockIdx.x];
   const EnsRun R = runs[r];
   const double* part = reinterpret_cast<const double*>(ws + R.off_part);
-  diag_final_body(part, (long)R.ndbx * R.ndby, cls.c[R.cls].K.dxdy,
+  diag_final_body(part, R.ncolblocks, cls.c[R.cls].K.dxdy,
                   diag_out + r * diag_stride + 2 * (long)index);
 }
 
@@ -1429,19 +1467,29 @@ hipError_t launch_ens_column_pass(bool recon, bool diag, const unsigned long lon
   return hipGetLastError();
 }
 
-hipError_t launch_ens_finalize(const EnsRun* runs, const EnsClasses& cls, const int4* items,
-                               int nitems, unsigned char* ws, int last_step, hipStream_t st) {
-  hipLaunchKernelGGL(ens_finalize, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws,
-                     last_step);
+
+
+hipError_t launch_ens_diag_final(const EnsRun* runs, const EnsClasses& cls, const int* big,
+                                 int nbig, unsigned char* ws, double* diag_out, long diag_stride,
+                                 int index, hipStream_t st) {
+  hipLaunchKernelGGL(ens_diag_final, dim3(nbig), dim3(256), 0, st, runs, cls, big, ws, diag_out,
+                     diag_stride, index);
   return hipGetLastError();
 }
 
-hipError_t launch_ens_diag(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
-                           const int* big, int nbig, unsigned char* ws, double* diag_out,
-                           long diag_stride, int index, hipStream_t st) {
-  hipLaunchKernelGGL(ens_diag_partial, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws);
-  hipLaunchKernelGGL(ens_diag_final, dim3(nbig), dim3(256), 0, st, runs, cls, big, ws, diag_out,
-                     diag_stride, index);
+hipError_t launch_ens_column_final(const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                                   int nitems, const int* big, int nbig, unsigned char* ws,
+                                   int last_step, double* diag_out, long diag_stride, int index,
+                                   hipStream_t st) {
+  if (diag_out) {
+    hipLaunchKernelGGL((ens_column_final<true>), dim3(nitems), dim3(256), 0, st, runs, cls, items,
+                       ws, last_step);
+    hipLaunchKernelGGL(ens_diag_final, dim3(nbig), dim3(256), 0, st, runs, cls, big, ws,
+                       diag_out, diag_stride, index);
+  } else {
+    hipLaunchKernelGGL((ens_column_final<false>), dim3(nitems), dim3(256), 0, st, runs, cls,
+                       items, ws, last_step);
+  }
   return hipGetLastError();
 }
 

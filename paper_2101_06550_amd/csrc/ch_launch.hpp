@@ -51,11 +51,30 @@ struct SmallNoise {
 hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long lds,
                                  double* ybuf, long ldy, int nx, int ny, const DevChunk& cy,
                                  double* rho, const ChCoef& K, double* part, hipStream_t st,
-                                 const SmallNoise* nz = nullptr);
-// q = dt eta of the Cahn-Hilliard-Cook forcing for counter `step` (pitch nx).
+                                 const SmallNoise* nz = nullptr, int order = 0);
+// Blocks of one column-pass launch (one (mass, energy) partial each).
 long ch_column_pass_blocks(int nx, int Sc);
-hipError_t launch_ch_finalize(const double* src, long lds, double* dst, long ldd, int nx, int ny,
-                              const DevChunk& cy, hipStream_t st);
+// After the last step: reconstruct the state into dst and, with diag_out,
+// write its (mass, energy) there (partials in part, one per column-pass block).
+hipError_t launch_ch_column_final(const double* src, long lds, double* dst, long ldd, int nx,
+                                  int ny, const DevChunk& cy, const ChCoef& K, double* part,
+                                  double* diag_out, hipStream_t st, int order = 0);
+// FP32-refined step (refine.hip): (mass, energy) partial pairs of its column
+// kernels; pass 0 (r = RHS(c) written, FP32 column chunk sweep, DIAG when
+// part != nullptr); pass nb (residual of x rebuilt from the deferred FP32
+// solutions v[0 .. nb-1], FP32 sweep); the state x rebuilt from v[0 .. nb-1]
+// into c (and with diag_out its mass and energy there).
+int rstep_segments(int nx);  // 60-column wave segments of a row of nx
+long rstep_parts(int nx, int ny);
+hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
+                              int nx, int ny, const DevChunk& cy, const ChCoef& K, double* part,
+                              hipStream_t st);
+hipError_t launch_rstep_resid(const double* rbuf, const float* const* v, int nb, float* y32,
+                              float* rho, int nx, int ny, const DevChunk& cy, const double* cx5,
+                              const double* cy5, hipStream_t st);
+hipError_t launch_rstep_final(const float* const* v, int nb, double* c, long ld, int nx, int ny,
+                              const DevChunk& cy, const ChCoef& K, double* part, double* diag_out,
+                              hipStream_t st);
 long ch_diag_partial_blocks(int nx, int ny);
 hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef& K, double* part,
                           double* out, hipStream_t st);

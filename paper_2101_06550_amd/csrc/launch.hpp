@@ -98,6 +98,15 @@ template <int P>
 hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, float* y32,
                                float* rho32, double* out, long ldo, int batch, bool acc,
                                hipStream_t st);
+// FP32 rows of n = c.n (dense, ld = n) row-solved in FP32 into dst (FP32).
+hipError_t launch_rows_lds_f32(const DevChunk& c, const float* src, float* dst, int rows,
+                               hipStream_t st);
+// FP32 separators of the chunked interleaved solve (batch systems, ld) from
+// the FP32 parts rho into the separator rows of dst; with dout, block (0,0)
+// also finishes the fixed-order sum of dnparts (mass, energy) partials.
+hipError_t launch_reduced_il32(const DevChunk& c, const float* rho, int batch, float* dst,
+                               long ld, hipStream_t st, const double* dpart = nullptr,
+                               long dnparts = 0, double dscale = 0.0, double* dout = nullptr);
 template <int P>
 hipError_t launch_rows_lds32(const DevChunk& c, const double* src, long lds, double* dst, long ldd,
                              int rows, bool acc, hipStream_t st);
@@ -110,5 +119,8 @@ hipError_t launch_resid_lines(const double* coef, int periodic, int n, const dou
 hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long ld,
                             const double* w, int left, int right, int top, int bottom,
                             int periodic, int premap, hipStream_t st);
+hipError_t launch_stencil2d_f32(const float* in, float* out, int nx, int ny, long ld,
+                                const double* w, int left, int right, int top, int bottom,
+                                int periodic, int premap, hipStream_t st);
 
 }  // namespace chx

@@ -1,0 +1,513 @@
+// refine.hip -- column kernels of the FP32-refined ADI step (FP32 sweeps,
+// FP64 right-hand side, residual and state).
+//
+// One step of (I + sx Px)(I + sy Py) c_new = r with FP32 sweeps and FP64
+// residual refinement (x_0 = A32^{-1} r; x_{k+1} = x_k + A32^{-1}(r - A x_k)),
+// laid out like the FP64 step: a column kernel that sweeps every 32-row chunk
+// of every column in registers, the column separators, and a row kernel that
+// solves whole rows in LDS.  The column-chunk correction is deferred: the row
+// kernel writes V_k (FP32, interior rows uncorrected, separator rows final)
+// and every later kernel rebuilds the correction d_k = V_k - Zl T_prev - Zr T_own
+// as it reads V_k.  Since that rebuild is linear, the sum V_0 + ... + V_m is
+// formed first (FP64) and corrected once, giving x_m.  Per point and pass:
+//   rstep_first : read c (8 B), write r (8) and the FP32 chunk interiors (4)
+//   rstep_resid : read r (8) and V_0 .. V_{k-1} (4 k), write the FP32 chunk
+//                 interiors of R = r - A x_{k-1} swept (4)
+//   rows (FP32) : read 4, write V_k (4)
+//   rstep_final : read V_0 .. V_p (4 (p + 1)), write c (8)
+// Every kernel runs one wave per 60 output columns of one 32-row chunk: the
+// wave's 64 lanes hold columns i0 - 2 .. i0 + 61 (wrapped), so neighbours at
+// distance 1 and 2 come from DPP lane shifts -- no LDS, no barrier.  A
+// wave's (mass, energy) partial goes to slot kc * nseg + seg.
+#include <hip/hip_runtime.h>
+
+#include "ch_launch.hpp"
+#include "common.hpp"
+#include "ens.hpp"
+
+namespace chx {
+
+namespace {
+
+constexpr int M = kChunk;
+constexpr int P = 2;
+constexpr int MI = M - P;
+constexpr int kSegR = 60;  // output columns per wave
+constexpr int kPfR = 6;    // rows of loads in flight ahead of the row worked
+
+__device__ __forceinline__ double wave_sum_r(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wrap_row(int j, int ny) {
+  j += (j < 0) ? ny : 0;
+  j -= (j >= ny) ? ny : 0;
+  return j;
+}
+
+// Lane geometry of wave `seg`: column i (wrapped) and whether the lane owns
+// an output column io.
+struct Lanes {
+  int i, io;
+  bool own;
+};
+__device__ __forceinline__ Lanes lanes_of(int seg, int nx) {
+  const int lane = threadIdx.x & 63;
+  Lanes L;
+  L.io = seg * kSegR + lane - 2;
+  int i = L.io % nx;
+  L.i = i + ((i < 0) ? nx : 0);
+  L.own = lane >= 2 && lane < 62 && L.io < nx;
+  return L;
+}
+
+// Forward-sweep step p of the FP32 chunk interior (the g of chunk_sweep).
+__device__ __forceinline__ float fwd32(float v, int p, const float (&f)[M],
+                                       const float* __restrict__ rec, float eps) {
+  if (p < MI) {
+    if (p >= 2) v = v - eps * f[p - 2];
+    if (p >= 1) v = v - rec[p * 8 + 1] * f[p - 1];
+    v = v * rec[p * 8 + 0];
+  }
+  return v;
+}
+
+// Back sweep, separator parts and stores of one FP32 chunk (own lanes only).
+__device__ __forceinline__ void finish32(float (&f)[M], const float* __restrict__ rec,
+                                         const BandT<float>& bd, float* __restrict__ y32,
+                                         float* __restrict__ rho, int nx, int kc, int io,
+                                         bool own) {
+#pragma unroll
+  for (int p = MI - 1; p >= 0; --p) {
+    float v = f[p];
+    if (p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
+    if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
+    f[p] = v;
+  }
+  float pa[P], pb[P];
+  chunk_parts<P, M, float>(f, bd, pa, pb);
+  if (!own) return;
+#pragma unroll
+  for (int p = 0; p < MI; ++p) __builtin_nontemporal_store(f[p], &y32[((long)kc * M + p) * nx + io]);
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    rho[((long)kc * 2 * P + a) * nx + io] = pa[a];
+    rho[((long)kc * 2 * P + P + a) * nx + io] = pb[a];
+  }
+}
+
+}  // namespace
+
+// First pass of a refined step: r = RHS(c) in FP64 (written out for the
+// residuals of the later passes), swept in FP32; DIAG: mass and free energy
+// of c.  Window rows kc M - 1 .. kc M + M.
+template <bool DIAG>
+__device__ __forceinline__ void rstep_first_body(const double* __restrict__ c, long ld,
+                                                 double* __restrict__ rbuf,
+                                                 float* __restrict__ y32,
+                                                 float* __restrict__ rho, int nx, int ny,
+                                                 int nseg, const float* __restrict__ rec32,
+                                                 const BandT<float>& bd, const ChCoef& K,
+                                                 double* __restrict__ part, int seg, int kc) {
+  const Lanes L = lanes_of(seg, nx);
+  constexpr int Q = M + 2;
+  double X[Q];
+  auto load = [&](int t) { X[t] = c[(long)wrap_row(kc * M - 1 + t, ny) * ld + L.i]; };
+#pragma unroll
+  for (int t = 0; t < kPfR; ++t) load(t);
+  double XL[Q], XR[Q];
+  float f[M];
+  double msum = 0.0, esum = 0.0;
+  const float eps = bd.c[0];
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    if (t + kPfR < Q) load(t + kPfR);
+    XL[t] = dpp_from_left(X[t], X[t]);
+    XR[t] = dpp_from_right(X[t], X[t]);
+    if (t >= 2) {  // own row p = t - 2 at window index w = t - 1
+      const int p = t - 2, w = t - 1;
+      const double xc = X[w], xl = XL[w], xr = XR[w];
+      const double mu_c = xc * xc * xc - xc;
+      const double mu_l = xl * xl * xl - xl;
+      const double mu_r = xr * xr * xr - xr;
+      const double mu_s = X[w - 1] * X[w - 1] * X[w - 1] - X[w - 1];
+      const double mu_n = X[w + 1] * X[w + 1] * X[w + 1] - X[w + 1];
+      const double lap = K.cx * (mu_r + mu_l - 2.0 * mu_c) + K.cy * (mu_n + mu_s - 2.0 * mu_c);
+      const double dyy_w = XL[w + 1] + XL[w - 1] - 2.0 * xl;
+      const double dyy_c = X[w + 1] + X[w - 1] - 2.0 * xc;
+      const double dyy_e = XR[w + 1] + XR[w - 1] - 2.0 * xr;
+      const double r = xc + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
+      if (DIAG && L.own) {
+        const double q = xc * xc - 1.0;
+        const double gx = (xr - xc) * K.inv_dx, gy = (X[w + 1] - xc) * K.inv_dy;
+        msum += xc;
+        esum += 0.25 * q * q + K.half_gamma * (gx * gx + gy * gy);
+      }
+      if (L.own) __builtin_nontemporal_store(r, &rbuf[((long)kc * M + p) * nx + L.io]);
+      f[p] = fwd32((float)r, p, f, rec32, eps);
+      asm volatile("" : "+v"(f[p]));
+    }
+    asm volatile("" : "+v"(X[t]), "+v"(XL[t]), "+v"(XR[t])::"memory");
+  }
+  finish32(f, rec32, bd, y32, rho, nx, kc, L.io, L.own);
+  if (DIAG) {
+    msum = wave_sum_r(msum);
+    esum = wave_sum_r(esum);
+    if ((threadIdx.x & 63) == 0) {
+      part[2 * ((long)kc * nseg + seg)] = msum;
+      part[2 * ((long)kc * nseg + seg) + 1] = esum;
+    }
+  }
+}
+
+// The deferred FP32 solutions V_0 .. V_{NB-1} of a step (dense, ld = nx).
+struct RBufs {
+  const float* v[4];
+};
+
+// Sum over the buffers of rows j (FP64).
+template <int NB>
+__device__ __forceinline__ double vsum(const RBufs& B, long j, int nx, int i) {
+  double s = 0.0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) s += (double)B.v[b][j * nx + i];
+  return s;
+}
+
+// Later pass k = NB of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}
+// (window rows kc M - 2 .. kc M + M + 1, separators of chunks kc - 1, kc,
+// kc + 1 first), R = r - (I + sx Px)(I + sy Py) x in FP64, swept in FP32.
+template <int NB>
+__device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf, const RBufs& B,
+                                                 float* __restrict__ y32,
+                                                 float* __restrict__ rho, int nx, int ny,
+                                                 int Sc, const double* __restrict__ rec,
+                                                 const float* __restrict__ rec32,
+                                                 const BandT<float>& bd, const BandT<double>& ax,
+                                                 const BandT<double>& ay, int seg, int kc) {
+  const Lanes L = lanes_of(seg, nx);
+  const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
+  double tp[P], to[P], tn[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    tp[a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, L.i);
+    to[a] = vsum<NB>(B, (long)kc * M + MI + a, nx, L.i);
+    tn[a] = vsum<NB>(B, (long)kcp * M + MI + a, nx, L.i);
+  }
+  constexpr int Q = M + 4;  // window rows kc M - 2 .. kc M + M + 1
+  double U[Q], R[M];
+  auto load = [&](int t) {
+    U[t] = vsum<NB>(B, wrap_row(kc * M - 2 + t, ny), nx, L.i);
+    if (t >= 2 && t < M + 2) R[t - 2] = rbuf[((long)kc * M + t - 2) * nx + L.i];
+  };
+#pragma unroll
+  for (int t = 0; t < kPfR; ++t) load(t);
+  double X[Q];
+  float f[M];
+  const float eps = bd.c[0];
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    if (t + kPfR < Q) load(t + kPfR);
+    // the state at window row t: rows above (t < 2) are chunk kc-1's
+    // separators; own rows (2 .. M+1) chunk kc, position t - 2; the two rows
+    // below chunk kc+1, positions 0 and 1
+    double x = U[t];
+    if (t >= 2) {
+      const bool below = t >= M + 2;
+      const int pp = below ? t - M - 2 : t - 2;
+      if (pp < MI) {
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
+              rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+      }
+    }
+    X[t] = x;
+    if (t >= 4) {  // own row p = t - 4 at window index w = t - 2
+      const int p = t - 4, w = t - 2;
+      const double Ty = ay.c[0] * X[w - 2] + ay.c[1] * X[w - 1] + ay.c[2] * X[w] +
+                        ay.c[3] * X[w + 1] + ay.c[4] * X[w + 2];
+      const double l1 = dpp_from_left(Ty, Ty), l2 = dpp_from_left(l1, l1);
+      const double r1 = dpp_from_right(Ty, Ty), r2 = dpp_from_right(r1, r1);
+      const double Ax = ax.c[0] * l2 + ax.c[1] * l1 + ax.c[2] * Ty + ax.c[3] * r1 + ax.c[4] * r2;
+      f[p] = fwd32((float)(R[p] - Ax), p, f, rec32, eps);
+      asm volatile("" : "+v"(f[p]));
+    }
+    asm volatile("" : "+v"(X[t])::"memory");
+  }
+  finish32(f, rec32, bd, y32, rho, nx, kc, L.io, L.own);
+}
+
+// End of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}, written to
+// c (FP64); DIAG: mass and free energy of x.  Window rows kc M .. kc M + M.
+template <int NB, bool DIAG>
+__device__ __forceinline__ void rstep_final_body(const RBufs& B, double* __restrict__ c, long ld,
+                                                 int nx, int ny, int nseg, int Sc,
+                                                 const double* __restrict__ rec, const ChCoef& K,
+                                                 double* __restrict__ part, int seg, int kc) {
+  const Lanes L = lanes_of(seg, nx);
+  const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
+  double tp[P], to[P], tn[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    tp[a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, L.i);
+    to[a] = vsum<NB>(B, (long)kc * M + MI + a, nx, L.i);
+    tn[a] = DIAG ? vsum<NB>(B, (long)kcp * M + MI + a, nx, L.i) : 0.0;
+  }
+  constexpr int Q = M + 1;  // own rows and (DIAG) row 0 of chunk kc + 1
+  double U[Q];
+  auto load = [&](int t) {
+    if (t < M || DIAG) U[t] = vsum<NB>(B, wrap_row(kc * M + t, ny), nx, L.i);
+  };
+#pragma unroll
+  for (int t = 0; t < kPfR; ++t) load(t);
+  double X[Q];
+  double msum = 0.0, esum = 0.0;
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    if (t + kPfR < Q) load(t + kPfR);
+    if (t == M && !DIAG) break;
+    double x = U[t];
+    const bool below = t == M;
+    const int pp = below ? 0 : t;
+    if (pp < MI) {
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+        x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
+            rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+    }
+    X[t] = x;
+    if (t < M && L.own) __builtin_nontemporal_store(x, &c[((long)kc * M + t) * ld + L.io]);
+    if (DIAG && t >= 1) {  // row t - 1 with its neighbours (i + 1, j) and (i, j + 1)
+      const double xc = X[t - 1];
+      const double xr = dpp_from_right(xc, xc);
+      if (L.own) {
+        const double q = xc * xc - 1.0;
+        const double gx = (xr - xc) * K.inv_dx, gy = (X[t] - xc) * K.inv_dy;
+        msum += xc;
+        esum += 0.25 * q * q + K.half_gamma * (gx * gx + gy * gy);
+      }
+    }
+    asm volatile("" : "+v"(X[t])::"memory");
+  }
+  if (DIAG) {
+    msum = wave_sum_r(msum);
+    esum = wave_sum_r(esum);
+    if ((threadIdx.x & 63) == 0) {
+      part[2 * ((long)kc * nseg + seg)] = msum;
+      part[2 * ((long)kc * nseg + seg) + 1] = esum;
+    }
+  }
+}
+
+// Single-field kernels: block = 4 waves = 4 consecutive 60-column segments
+// of chunk blockIdx.y.
+template <bool DIAG>
+__global__ __launch_bounds__(256) void rstep_first(const double* __restrict__ c, long ld,
+                                                   double* __restrict__ rbuf,
+                                                   float* __restrict__ y32,
+                                                   float* __restrict__ rho, int nx, int ny,
+                                                   int nseg, const float* __restrict__ rec32,
+                                                   BandT<float> bd, ChCoef K,
+                                                   double* __restrict__ part) {
+  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;  // no barrier in this kernel
+  rstep_first_body<DIAG>(c, ld, rbuf, y32, rho, nx, ny, nseg, rec32, bd, K, part, seg,
+                         blockIdx.y);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void rstep_resid(const double* __restrict__ rbuf, RBufs B,
+                                                   float* __restrict__ y32,
+                                                   float* __restrict__ rho, int nx, int ny,
+                                                   int nseg, int Sc,
+                                                   const double* __restrict__ rec,
+                                                   const float* __restrict__ rec32,
+                                                   BandT<float> bd, BandT<double> ax,
+                                                   BandT<double> ay) {
+  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;  // no barrier in this kernel
+  rstep_resid_body<NB>(rbuf, B, y32, rho, nx, ny, Sc, rec, rec32, bd, ax, ay, seg, blockIdx.y);
+}
+
+template <int NB, bool DIAG>
+__global__ __launch_bounds__(256) void rstep_final(RBufs B, double* __restrict__ c, long ld,
+                                                   int nx, int ny, int nseg, int Sc,
+                                                   const double* __restrict__ rec, ChCoef K,
+                                                   double* __restrict__ part) {
+  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (seg >= nseg) return;  // no barrier in this kernel
+  rstep_final_body<NB, DIAG>(B, c, ld, nx, ny, nseg, Sc, rec, K, part, seg, blockIdx.y);
+}
+
+// Ensemble kernels: block = work item {run, segment block, chunk}; each run
+// reads its class's plan tables and its own buffers, and calls the bodies
+// the single-field kernels call (so a run advances bitwise as it would alone).
+__device__ __forceinline__ RBufs ens_vbufs(unsigned char* ws, const EnsRun& R) {
+  RBufs B{};
+#pragma unroll
+  for (int b = 0; b < 4; ++b) B.v[b] = reinterpret_cast<const float*>(ws + R.off_v[b]);
+  return B;
+}
+
+template <int PASS, bool DIAG>
+__global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict__ runs,
+                                                        EnsClasses cls,
+                                                        const int4* __restrict__ items,
+                                                        unsigned char* ws) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const int seg = it.y * 4 + (threadIdx.x >> 6);
+  if (seg >= R.nseg) return;  // no barrier in these kernels
+  const EnsClass& C = cls.c[R.cls];
+  BandT<float> bd;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) bd.c[k] = (float)C.py.coef[k];
+  double* rbuf = reinterpret_cast<double*>(ws + R.off_r);
+  float* y32 = reinterpret_cast<float*>(ws + R.off_y32);
+  float* rho = reinterpret_cast<float*>(ws + R.off_rho32);
+  if (PASS == 0) {
+    rstep_first_body<DIAG>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K,
+                           reinterpret_cast<double*>(ws + R.off_part), seg, it.z);
+  } else {
+    BandT<double> ax, ay;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ax.c[k] = C.px.coef[k];
+      ay.c[k] = C.py.coef[k];
+    }
+    rstep_resid_body<PASS>(rbuf, ens_vbufs(ws, R), y32, rho, R.nx, R.ny, R.Sc, C.py.rec,
+                           C.py.rec32, bd, ax, ay, seg, it.z);
+  }
+}
+
+template <bool DIAG>
+__global__ __launch_bounds__(256) void ens_rstep_final(const EnsRun* __restrict__ runs,
+                                                       EnsClasses cls,
+                                                       const int4* __restrict__ items,
+                                                       unsigned char* ws) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const int seg = it.y * 4 + (threadIdx.x >> 6);
+  if (seg >= R.nseg) return;
+  const EnsClass& C = cls.c[R.cls];
+  const RBufs B = ens_vbufs(ws, R);
+  double* part = reinterpret_cast<double*>(ws + R.off_part);
+  switch (R.passes) {  // uniform per block
+    case 1: rstep_final_body<2, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
+    case 2: rstep_final_body<3, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
+    default: rstep_final_body<4, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
+  }
+}
+
+hipError_t launch_ens_rstep_column(int pass, bool diag, const EnsRun* runs, const EnsClasses& cls,
+                                   const int4* items, int nitems, unsigned char* ws,
+                                   hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+#define CHX_ERC(P_, D_)                                                                      \
+  hipLaunchKernelGGL((ens_rstep_column<P_, D_>), dim3(nitems), dim3(256), 0, st, runs, cls, \
+                     items, ws)
+  if (pass == 0) {
+    if (diag) CHX_ERC(0, true);
+    else CHX_ERC(0, false);
+  } else if (pass == 1) CHX_ERC(1, false);
+  else if (pass == 2) CHX_ERC(2, false);
+  else CHX_ERC(3, false);
+#undef CHX_ERC
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_rstep_final(const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                                  int nitems, const int* big, int nbig, unsigned char* ws,
+                                  double* diag_out, long diag_stride, int index, hipStream_t st) {
+  if (diag_out) {
+    hipLaunchKernelGGL((ens_rstep_final<true>), dim3(nitems), dim3(256), 0, st, runs, cls, items,
+                       ws);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_ens_diag_final(runs, cls, big, nbig, ws, diag_out, diag_stride, index, st);
+  }
+  hipLaunchKernelGGL((ens_rstep_final<false>), dim3(nitems), dim3(256), 0, st, runs, cls, items,
+                     ws);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+int rstep_segments(int nx) { return (nx + kSegR - 1) / kSegR; }
+long rstep_parts(int nx, int ny) { return (long)rstep_segments(nx) * (ny / M); }
+
+static dim3 rstep_grid(int nx, int ny) {
+  const int nseg = (nx + kSegR - 1) / kSegR;
+  return dim3((unsigned)((nseg + 3) / 4), (unsigned)(ny / M));
+}
+
+hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
+                              int nx, int ny, const DevChunk& cy, const ChCoef& K, double* part,
+                              hipStream_t st) {
+  if (ny % M != 0 || cy.S * M != ny) return hipErrorInvalidValue;
+  BandT<float> bd;
+  for (int k = 0; k < 5; ++k) bd.c[k] = (float)cy.coef[k];
+  const int nseg = (nx + kSegR - 1) / kSegR;
+  if (part)
+    hipLaunchKernelGGL((rstep_first<true>), rstep_grid(nx, ny), dim3(256), 0, st, c, ld, rbuf,
+                       y32, rho, nx, ny, nseg, cy.rec32, bd, K, part);
+  else
+    hipLaunchKernelGGL((rstep_first<false>), rstep_grid(nx, ny), dim3(256), 0, st, c, ld, rbuf,
+                       y32, rho, nx, ny, nseg, cy.rec32, bd, K, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_rstep_resid(const double* rbuf, const float* const* v, int nb, float* y32,
+                              float* rho, int nx, int ny, const DevChunk& cy, const double* cx5,
+                              const double* cy5, hipStream_t st) {
+  if (ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 3) return hipErrorInvalidValue;
+  BandT<float> bd;
+  BandT<double> ax, ay;
+  for (int k = 0; k < 5; ++k) {
+    bd.c[k] = (float)cy.coef[k];
+    ax.c[k] = cx5[k];
+    ay.c[k] = cy5[k];
+  }
+  RBufs B{};
+  for (int b = 0; b < nb; ++b) B.v[b] = v[b];
+  const int nseg = (nx + kSegR - 1) / kSegR;
+#define CHX_RRES(NB_)                                                                           \
+  hipLaunchKernelGGL((rstep_resid<NB_>), rstep_grid(nx, ny), dim3(256), 0, st, rbuf, B, y32, rho, \
+                     nx, ny, nseg, cy.S, cy.rec, cy.rec32, bd, ax, ay)
+  if (nb == 1) CHX_RRES(1);
+  else if (nb == 2) CHX_RRES(2);
+  else CHX_RRES(3);
+#undef CHX_RRES
+  return hipGetLastError();
+}
+
+hipError_t launch_rstep_final(const float* const* v, int nb, double* c, long ld, int nx, int ny,
+                              const DevChunk& cy, const ChCoef& K, double* part, double* diag_out,
+                              hipStream_t st) {
+  if (ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 4) return hipErrorInvalidValue;
+  RBufs B{};
+  for (int b = 0; b < nb; ++b) B.v[b] = v[b];
+  const int nseg = (nx + kSegR - 1) / kSegR;
+#define CHX_RFIN(NB_, D_)                                                                         \
+  hipLaunchKernelGGL((rstep_final<NB_, D_>), rstep_grid(nx, ny), dim3(256), 0, st, B, c, ld, nx, \
+                     ny, nseg, cy.S, cy.rec, K, part)
+  if (diag_out) {
+    if (nb == 1) CHX_RFIN(1, true);
+    else if (nb == 2) CHX_RFIN(2, true);
+    else if (nb == 3) CHX_RFIN(3, true);
+    else CHX_RFIN(4, true);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_ch_diag_final(part, rstep_parts(nx, ny), K.dxdy, diag_out, st);
+  }
+  if (nb == 1) CHX_RFIN(1, false);
+  else if (nb == 2) CHX_RFIN(2, false);
+  else if (nb == 3) CHX_RFIN(3, false);
+  else CHX_RFIN(4, false);
+#undef CHX_RFIN
+  return hipGetLastError();
+}
+
+}  // namespace chx

@@ -266,33 +266,51 @@ __global__ __launch_bounds__(256) void resid_lines(const double* __restrict__ f,
 // (ld == n) need no division: the group is one contiguous range, loaded with
 // every load of a thread in flight before the first LDS store.  Strided rows
 // (ld > n) take a compact loop.
-template <int P, int M, typename T>
-__device__ __forceinline__ void row_group_stage(T* tile, const double* x, long ld, int rows, int n,
+template <int P, int M, typename T, typename Tin = double>
+__device__ __forceinline__ void row_group_stage(T* tile, const Tin* x, long ld, int rows, int n,
                                                 long row0, int nel, int t, bool dense) {
   if (dense) {
     const long nvalid = ((long)rows - row0) * n;
-    const double* base = x + row0 * n;
-    double vin[M];
+    const Tin* base = x + row0 * n;
+    Tin vin[M];
     if (nel == 256 * M && nvalid >= nel) {  // a full group: 16-byte loads, no guards
-      const double2* b2 = reinterpret_cast<const double2*>(base);
+      if constexpr (sizeof(Tin) == 4) {  // four values per load
+        const float4* b4 = reinterpret_cast<const float4*>(base);
 #pragma unroll
-      for (int u = 0; u < M / 2; ++u) {
-        const double2 v = b2[t + 256 * u];
-        vin[2 * u] = v.x;
-        vin[2 * u + 1] = v.y;
-      }
+        for (int u = 0; u < M / 4; ++u) {
+          const float4 v = b4[t + 256 * u];
+          vin[4 * u] = v.x;
+          vin[4 * u + 1] = v.y;
+          vin[4 * u + 2] = v.z;
+          vin[4 * u + 3] = v.w;
+        }
 #pragma unroll
-      for (int u = 0; u < M / 2; ++u) {
-        const int e = 2 * t + 512 * u;
-        tile[e + e / M] = (T)vin[2 * u];
-        tile[e + 1 + e / M] = (T)vin[2 * u + 1];
+        for (int u = 0; u < M / 4; ++u) {
+          const int e = 4 * t + 1024 * u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) tile[e + q + e / M] = (T)vin[4 * u + q];
+        }
+      } else {
+        const double2* b2 = reinterpret_cast<const double2*>(base);
+#pragma unroll
+        for (int u = 0; u < M / 2; ++u) {
+          const double2 v = b2[t + 256 * u];
+          vin[2 * u] = v.x;
+          vin[2 * u + 1] = v.y;
+        }
+#pragma unroll
+        for (int u = 0; u < M / 2; ++u) {
+          const int e = 2 * t + 512 * u;
+          tile[e + e / M] = (T)vin[2 * u];
+          tile[e + 1 + e / M] = (T)vin[2 * u + 1];
+        }
       }
       return;
     } else {
 #pragma unroll
       for (int u = 0; u < M; ++u) {
         const int e = t + 256 * u;
-        vin[u] = (e < nel && e < nvalid) ? base[e] : 0.0;
+        vin[u] = (e < nel && e < nvalid) ? base[e] : Tin(0);
       }
     }
 #pragma unroll
@@ -321,8 +339,8 @@ struct RowLds {
 };
 
 // Rows row0 .. row0 + R - 1 (R = 256 / S rows of n = S M unknowns each).
-template <int P, int M, typename T, bool ACC>
-__device__ __forceinline__ void row_solve_body(const double* src, long lds, double* dst, long ldd,
+template <int P, int M, typename T, bool ACC, typename Tin = double, typename Tout = double>
+__device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* dst, long ldd,
                                                int rows, int n, int S, int R,
                                                const T* __restrict__ rec, const BandT<T>& bd,
                                                const T* __restrict__ blocks, int dlo, int dcount,
@@ -334,7 +352,7 @@ __device__ __forceinline__ void row_solve_body(const double* src, long lds, doub
   const int nel = R * n;  // <= 256 * M
   const int r = t / S, k = t - r * S;
   {
-    row_group_stage<P, M, T>(tile, src, lds, rows, n, row0, nel, t, lds == n);
+    row_group_stage<P, M, T, Tin>(tile, src, lds, rows, n, row0, nel, t, lds == n);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
     T f[M];
@@ -406,41 +424,57 @@ __device__ __forceinline__ void row_solve_body(const double* src, long lds, doub
       for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
     }
     __syncthreads();
-    if (ldd == n && nel == 256 * M && ((long)rows - row0) * n >= nel) {
-      double2* b2 = reinterpret_cast<double2*>(dst + row0 * n);
+    const bool full = ldd == n && nel == 256 * M && ((long)rows - row0) * n >= nel;
+    if constexpr (sizeof(Tout) == 4) {
+      static_assert(!ACC, "FP32 output does not accumulate");
+      if (full) {  // four values per streamed 16-byte store
+        float* b = dst + row0 * n;
 #pragma unroll
-      for (int u = 0; u < M / 2; ++u) {
-        const int e = 2 * t + 512 * u;
-        double2 v;
-        v.x = (double)tile[e + e / M];
-        v.y = (double)tile[e + 1 + e / M];
-        if (ACC) {
-          const double2 o = b2[t + 256 * u];
-          v.x += o.x;
-          v.y += o.y;
+        for (int u = 0; u < M / 4; ++u) {
+          const int e = 4 * t + 1024 * u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            __builtin_nontemporal_store((float)tile[e + q + e / M], &b[e + q]);
         }
-        store_stream(b2 + t + 256 * u, v);  // streamed: not re-read before the next pass
       }
-    } else if (ldd == n) {
+    } else {
+      if (full) {
+        double2* b2 = reinterpret_cast<double2*>(dst + row0 * n);
+#pragma unroll
+        for (int u = 0; u < M / 2; ++u) {
+          const int e = 2 * t + 512 * u;
+          double2 v;
+          v.x = (double)tile[e + e / M];
+          v.y = (double)tile[e + 1 + e / M];
+          if (ACC) {
+            const double2 o = b2[t + 256 * u];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          store_stream(b2 + t + 256 * u, v);  // streamed: not re-read before the next pass
+        }
+      }
+    }
+    if (!full && ldd == n) {
       const long nvalid = ((long)rows - row0) * n;
-      double* base = dst + row0 * n;
+      Tout* base = dst + row0 * n;
 #pragma unroll
       for (int u = 0; u < M; ++u) {
         const int e = t + 256 * u;
         if (e < nel && e < nvalid) {
-          if (ACC) base[e] += (double)tile[e + e / M];
-          else base[e] = (double)tile[e + e / M];
+          if (ACC) base[e] += (Tout)tile[e + e / M];
+          else base[e] = (Tout)tile[e + e / M];
         }
       }
-    } else {
+    } else if (!full) {
 #pragma unroll 1
       for (int u = 0; u < M; ++u) {
         const int e = t + 256 * u;
         const int rr = e / n;
         const int i = e - rr * n;
         if (e < nel && row0 + rr < rows) {
-          if (ACC) dst[(row0 + rr) * ldd + i] += (double)tile[e + e / M];
-          else dst[(row0 + rr) * ldd + i] = (double)tile[e + e / M];
+          if (ACC) dst[(row0 + rr) * ldd + i] += (Tout)tile[e + e / M];
+          else dst[(row0 + rr) * ldd + i] = (Tout)tile[e + e / M];
         }
       }
     }
@@ -455,6 +489,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
   __shared__ RowLds<P, M, T> sh;
   row_solve_body<P, M, T, ACC>(src, lds, dst, ldd, rows, n, S, R, rec, bd, blocks, dlo, dcount,
                                (long)blockIdx.x * R, sh);
+}
+
+// FP32 rows in, FP32 rows out (the refined step's row solves of its FP32
+// chunk-solved columns).
+template <int P, int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void row_solve_lds_f32(
+    const float* src, long lds, float* dst, long ldd, int rows, int n, int S, int R,
+    const float* __restrict__ rec, BandT<float> bd, const float* __restrict__ blocks, int dlo,
+    int dcount) {
+  __shared__ RowLds<P, M, float> sh;
+  row_solve_body<P, M, float, false, float, float>(src, lds, dst, ldd, rows, n, S, R, rec, bd,
+                                                   blocks, dlo, dcount, (long)blockIdx.x * R, sh);
 }
 
 // Fixed-order sum of dnparts (mass, energy) partial pairs by one block of at
@@ -940,6 +986,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                                            (long)it.y * (256 / c.S), sh);
 }
 
+// FP32-refined ensembles: separators of the FP32 column buffer (dout: the
+// pass-0 diagnostics of the run's state at `step`), and FP32 row solves of it
+// into the run's V_pass.
+__global__ __launch_bounds__(512) void ens_reduced32(const EnsRun* __restrict__ runs,
+                                                     EnsClasses cls,
+                                                     const int4* __restrict__ items,
+                                                     unsigned char* ws, int step, double* diag_out,
+                                                     long diag_stride) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const DevChunk& c = cls.c[R.cls].py;
+  float* dst = reinterpret_cast<float*>(ws + R.off_y32);
+  const float* rho = reinterpret_cast<const float*>(ws + R.off_rho32);
+  const double* part = reinterpret_cast<const double*>(ws + R.off_part);
+  double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
+                     ? diag_out + it.x * diag_stride + 2 * (long)step
+                     : nullptr;
+  extern __shared__ unsigned char smraw[];
+  reduced_body<2, float, float, kRedWaves, kRedG, 4>(rho, R.nx, R.Sc, c.blocks32, c.dlo, c.dcount,
+                                                    dst, R.nx, kChunk, kChunk - 2, part,
+                                                    R.ncolblocks, cls.c[R.cls].K.dxdy, dout,
+                                                    it.y, it.z, smraw);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ens_rows32(
+    const EnsRun* __restrict__ runs, EnsClasses cls, const int4* __restrict__ items,
+    unsigned char* ws, int pass) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun R = runs[it.x];
+  const DevChunk& c = cls.c[R.cls].px;
+  BandT<float> bd;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) bd.c[k] = (float)c.coef[k];
+  const float* src = reinterpret_cast<const float*>(ws + R.off_y32);
+  float* dst = reinterpret_cast<float*>(ws + R.off_v[pass]);
+  __shared__ RowLds<2, kChunk, float> sh;
+  row_solve_body<2, kChunk, float, false, float, float>(src, R.nx, dst, R.nx, R.ny, R.nx, c.S,
+                                                        256 / c.S, c.rec32, bd, c.blocks32, c.dlo,
+                                                        c.dcount, (long)it.y * (256 / c.S), sh);
+}
+
+hipError_t launch_ens_reduced32(const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                                int nitems, unsigned char* ws, int step, double* diag_out,
+                                long diag_stride, size_t lds_bytes, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ens_reduced32, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs, cls,
+                     items, ws, step, diag_out, diag_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_ens_rows32(const EnsRun* runs, const EnsClasses& cls, const int4* items,
+                             int nitems, unsigned char* ws, int pass, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ens_rows32, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, pass);
+  return hipGetLastError();
+}
+
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
                               long diag_stride, size_t lds_bytes, hipStream_t st) {
@@ -1128,6 +1231,23 @@ hipError_t launch_rows_lds32(const DevChunk& c, const double* src, long lds, dou
                        dim3(256), 0, st, src, lds, dst, ldd, rows, c.n, c.S, R, c.rec32,
                        band_of<float>(c.coef), c.blocks32, c.dlo, c.dcount);
   return hipGetLastError();
+}
+
+hipError_t launch_rows_lds_f32(const DevChunk& c, const float* src, float* dst, int rows,
+                               hipStream_t st) {
+  const int R = 256 / c.S;
+  const long ngroups = ((long)rows + R - 1) / R;
+  hipLaunchKernelGGL((row_solve_lds_f32<2, kChunk>), dim3((unsigned)ngroups), dim3(256), 0, st,
+                     src, (long)c.n, dst, (long)c.n, rows, c.n, c.S, R, c.rec32,
+                     band_of<float>(c.coef), c.blocks32, c.dlo, c.dcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduced_il32(const DevChunk& c, const float* rho, int batch, float* dst,
+                               long ld, hipStream_t st, const double* dpart, long dnparts,
+                               double dscale, double* dout) {
+  return reduced_any<2, float, float>(c, rho, c.blocks32, batch, dst, ld, kChunk, kChunk - 2, st,
+                                      dpart, dnparts, dscale, dout, c.red_shape);
 }
 
 template <int P>

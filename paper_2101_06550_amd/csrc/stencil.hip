@@ -3,6 +3,7 @@
 // LDS, each thread writes its own outputs, input and output are separate
 // buffers.  Weights of up to 9 x 9 arrive by value in the kernel arguments;
 // premap 1 applies the stencil to v^3 - v (the non-linear Cahn-Hilliard term).
+// FP64 or FP32 arrays (the arithmetic in the arrays' type).
 //
 // One workgroup (4 waves) owns a 64-column x 32-row output tile.  The tile and
 // its halo are loaded once into LDS (premap applied on the way in); lane l of
@@ -35,8 +36,9 @@ constexpr int kTX = 64;       // tile width (one wave across)
 constexpr int kRows = 8;
 constexpr int kTY = 4 * kRows;
 
+template <typename T>
 struct StencilW {
-  double w[(2 * kMaxExt + 1) * (2 * kMaxExt + 1)];
+  T w[(2 * kMaxExt + 1) * (2 * kMaxExt + 1)];
 };
 
 // Index of a periodic neighbour.  mode 1: one wrap (the caller guarantees
@@ -52,14 +54,15 @@ __device__ __forceinline__ int wrap_index(int g, int n, int mode) {
   return g < n ? g : n - 1;
 }
 
-template <int EX, int EY>
-__global__ __launch_bounds__(256) void stencil2d_tiled(const double* __restrict__ in,
-                                                       double* __restrict__ out, int nx, int ny,
-                                                       long ld, StencilW W, int ntx, int per_xcd,
-                                                       int wrap, int premap, int left, int right,
-                                                       int top, int bottom) {
+template <int EX, int EY, typename T>
+__global__ __launch_bounds__(256) void stencil2d_tiled(const T* __restrict__ in,
+                                                       T* __restrict__ out, int nx, int ny,
+                                                       long ld, StencilW<T> W, int ntx,
+                                                       int per_xcd, int wrap, int premap,
+                                                       int left, int right, int top,
+                                                       int bottom) {
   constexpr int PX = kTX + 2 * EX, HY = kTY + 2 * EY, WX = 2 * EX + 1;
-  __shared__ double tile[HY * PX];
+  __shared__ T tile[HY * PX];
   const int b = blockIdx.x;
   const int t = per_xcd ? (b & 7) * per_xcd + (b >> 3) : b;
   const int by = t / ntx, bx = t - by * ntx;
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(256) void stencil2d_tiled(const double* __restrict_
     cok[h] = wrap || (gi >= 0 && gi < nx);
     cidx[h] = wrap ? wrap_index(gi, nx, wrap) : (gi < 0 ? 0 : (gi < nx ? gi : nx - 1));
   }
-  double val[NK][NH];
+  T val[NK][NH];
 #pragma unroll
   for (int k = 0; k < NK; ++k)
 #pragma unroll
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(256) void stencil2d_tiled(const double* __restrict_
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
       const int lx = lane + 64 * h;
-      double v = (rok[k] && cok[h]) ? val[k][h] : 0.0;
+      T v = (rok[k] && cok[h]) ? val[k][h] : T(0);
       if (premap) v = v * v * v - v;
       if (ly < HY && lx < PX) tile[ly * PX + lx] = v;
     }
@@ -108,13 +111,13 @@ __global__ __launch_bounds__(256) void stencil2d_tiled(const double* __restrict_
   if (i >= nx) return;
   if (!wrap && (i - left < 0 || i + right >= nx)) return;
 
-  double acc[kRows];
+  T acc[kRows];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) acc[r] = 0.0;
-  const double* col = tile + wv * kRows * PX + lane;
+  for (int r = 0; r < kRows; ++r) acc[r] = T(0);
+  const T* col = tile + wv * kRows * PX + lane;
 #pragma unroll
   for (int k = 0; k < kRows + 2 * EY; ++k) {
-    double v[WX];
+    T v[WX];
 #pragma unroll
     for (int p = 0; p < WX; ++p) v[p] = col[k * PX + p];
 #pragma unroll
@@ -144,40 +147,41 @@ __global__ __launch_bounds__(256) void stencil2d_tiled(const double* __restrict_
 
 int ext_class(int e) { return e <= 2 ? e : kMaxExt; }
 
-template <int EX, int EY>
-void launch_class(dim3 grid, hipStream_t st, const double* in, double* out, int nx, int ny,
-                  long ld, const StencilW& W, int ntx, int per_xcd, int wrap, int premap,
-                  int left, int right, int top, int bottom) {
-  hipLaunchKernelGGL((stencil2d_tiled<EX, EY>), grid, dim3(256), 0, st, in, out, nx, ny, ld, W,
-                     ntx, per_xcd, wrap, premap, left, right, top, bottom);
+template <int EX, int EY, typename T>
+void launch_class(dim3 grid, hipStream_t st, const T* in, T* out, int nx, int ny, long ld,
+                  const StencilW<T>& W, int ntx, int per_xcd, int wrap, int premap, int left,
+                  int right, int top, int bottom) {
+  hipLaunchKernelGGL((stencil2d_tiled<EX, EY, T>), grid, dim3(256), 0, st, in, out, nx, ny, ld,
+                     W, ntx, per_xcd, wrap, premap, left, right, top, bottom);
 }
 
-template <int EX>
-void launch_ey(int ey, dim3 grid, hipStream_t st, const double* in, double* out, int nx, int ny,
-               long ld, const StencilW& W, int ntx, int per_xcd, int wrap, int premap, int left,
+template <int EX, typename T>
+void launch_ey(int ey, dim3 grid, hipStream_t st, const T* in, T* out, int nx, int ny, long ld,
+               const StencilW<T>& W, int ntx, int per_xcd, int wrap, int premap, int left,
                int right, int top, int bottom) {
   switch (ey) {
-    case 0: launch_class<EX, 0>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    case 1: launch_class<EX, 1>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    case 2: launch_class<EX, 2>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    default: launch_class<EX, 4>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 0: launch_class<EX, 0, T>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 1: launch_class<EX, 1, T>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 2: launch_class<EX, 2, T>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    default: launch_class<EX, 4, T>(grid, st, in, out, nx, ny, ld, W, ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
   }
 }
 
-}  // namespace
-
-hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long ld,
-                            const double* w, int left, int right, int top, int bottom,
-                            int periodic, int premap, hipStream_t st) {
+template <typename T>
+hipError_t launch_stencil2d_t(const T* in, T* out, int nx, int ny, long ld, const double* w,
+                              int left, int right, int top, int bottom, int periodic, int premap,
+                              hipStream_t st) {
   const int ex = ext_class(left > right ? left : right);
   const int ey = ext_class(top > bottom ? top : bottom);
   // the user's (top + bottom + 1) x (left + right + 1) weights placed in the
-  // class's (2 ey + 1) x (2 ex + 1) rectangle, centre on centre
-  StencilW W;
-  for (double& v : W.w) v = 0.0;
+  // class's (2 ey + 1) x (2 ex + 1) rectangle, centre on centre (rounded to
+  // the array type once, here)
+  StencilW<T> W;
+  for (T& v : W.w) v = T(0);
   const int uw = left + right + 1;
   for (int q = 0; q <= top + bottom; ++q)
-    for (int p = 0; p < uw; ++p) W.w[(q - top + ey) * (2 * ex + 1) + (p - left + ex)] = w[q * uw + p];
+    for (int p = 0; p < uw; ++p)
+      W.w[(q - top + ey) * (2 * ex + 1) + (p - left + ex)] = (T)w[q * uw + p];
   const int wrap = !periodic ? 0 : (nx >= ex && ny >= ey ? 1 : 2);
   const long ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY;
   const long ntiles = ntx * nty;
@@ -185,12 +189,28 @@ hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long 
   const int per_xcd = ntiles % 8 == 0 ? (int)(ntiles / 8) : 0;
   const dim3 grid((unsigned)ntiles);
   switch (ex) {
-    case 0: launch_ey<0>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    case 1: launch_ey<1>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    case 2: launch_ey<2>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
-    default: launch_ey<4>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 0: launch_ey<0, T>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 1: launch_ey<1, T>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    case 2: launch_ey<2, T>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
+    default: launch_ey<4, T>(ey, grid, st, in, out, nx, ny, ld, W, (int)ntx, per_xcd, wrap, premap, left, right, top, bottom); break;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stencil2d(const double* in, double* out, int nx, int ny, long ld,
+                            const double* w, int left, int right, int top, int bottom,
+                            int periodic, int premap, hipStream_t st) {
+  return launch_stencil2d_t<double>(in, out, nx, ny, ld, w, left, right, top, bottom, periodic,
+                                    premap, st);
+}
+
+hipError_t launch_stencil2d_f32(const float* in, float* out, int nx, int ny, long ld,
+                                const double* w, int left, int right, int top, int bottom,
+                                int periodic, int premap, hipStream_t st) {
+  return launch_stencil2d_t<float>(in, out, nx, ny, ld, w, left, right, top, bottom, periodic,
+                                   premap, st);
 }
 
 }  // namespace chx

@@ -31,7 +31,7 @@
 #include <cstddef>
 #include <cstdint>
 
-#include "../../include/chx.h"
+#include "chx.h"
 #include "launch.hpp"
 
 namespace chx_vb {

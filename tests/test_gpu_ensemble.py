@@ -251,3 +251,35 @@ def test_asymmetric_mixture_ensemble_steps(chx, orc):
         assert np.all(np.diff(d[r, :, 1]) <= 1e-12 * np.abs(d[r, :-1, 1])), r
     s1 = chx.ch_ensemble_moments(ens, fields)[:, 2]
     assert np.all(s1 != s0)
+
+
+def test_refined_ensemble_mixed_passes_matches_single_runs(chx, orc):
+    """Runs with 1, 2 and 3 refine passes in one FP32-refined ensemble (pass k
+    covers only the runs that make it): every run bitwise equal to a single
+    refined handle with its passes, states and per-step diagnostics."""
+    runs = [(64, 64, 1.0, 0.01, 1e-4, 1100), (256, 128, 1.0, 0.01, 1e-4, 1101),
+            (128, 128, 1.0, 0.02, 5e-5, 1102), (512, 512, 1.0, 0.01, 1e-4, 1103),
+            (64, 96, 1.0, 0.01, 1e-4, 1104), (128, 128, 1.0, 0.01, 1e-4, 1105)]
+    passes = [1, 3, 2, 3, 1, 2]
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs],
+                                 dtype=chx.CHX_F32_REFINED, refine_passes=passes)
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, _, _, _, seed) in runs]
+    fields = [torch.tensor(c, device="cuda") for c in c0]
+    n = 3
+    diag = torch.zeros(len(runs) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    print("[case] refined ensemble, mixed passes, 3 steps", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=n, diag_out=diag, use_graph=True)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(runs), n + 1, 2)
+    for r, ((nx, ny, D, g, dt, seed), c, p) in enumerate(zip(runs, c0, passes)):
+        h = chx.ch_create(nx, ny, L, L, D, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=p)
+        single = torch.tensor(c, device="cuda")
+        sd = torch.zeros(2 * (n + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, single, nsteps=n, diag_out=sd)
+        torch.cuda.synchronize()
+        assert torch.equal(single, fields[r]), r
+        assert np.array_equal(sd.cpu().numpy().reshape(n + 1, 2), d[r]), r
+        ref = c
+        for _ in range(n):
+            ref = orc.ch_step(ref, L, L, D, g, dt)
+        assert rel(fields[r].cpu().numpy(), ref) < n * (1e-10 if p > 1 else 1e-8), (r, p)

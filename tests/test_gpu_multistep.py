@@ -131,3 +131,70 @@ def test_large_run_two_steps_in_one_call(chx, orc):
         m, e = orc.ch_mass(ref[j], L, L), orc.ch_energy(ref[j], L, L, g)
         assert abs(dd[j, 0] - m) <= 1e-12 * l1, (j, dd[j, 0], m)
         assert abs(dd[j, 1] - e) <= 1e-12 * abs(e), (j, dd[j, 1], e)
+
+
+@pytest.mark.parametrize("ny,nx", [(1024, 1024), (96, 320), (160, 576)])
+def test_column_orders_bitwise_and_match_oracle(chx, orc, ny, nx):
+    """Every tile order of the column pass (and of the pass that writes the
+    final state): the same sums in the same order, so bitwise identical
+    states and diagnostics, including tile counts that are not a multiple of
+    the 8 XCDs (96 x 320: 2 x 3 tiles; 160 x 576: 3 x 5)."""
+    g, dt, k = 0.01, 1e-5, 3
+    c0 = inputs.noise_field(ny, nx, 68)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)
+    outs = []
+    for order in range(chx.CHX_NUM_COLUMN_ORDERS):
+        print(f"[case] column order {order}, {k} steps {ny}x{nx}", flush=True)
+        chx.ch_set_tuning(h, order, what=chx.CHX_TUNE_COLUMN_ORDER)
+        assert chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_ORDER) == order
+        c = torch.tensor(c0, device="cuda")
+        d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+        torch.cuda.synchronize()
+        outs.append((c.cpu().numpy(), d.cpu().numpy()))
+    for c, d in outs[1:]:
+        assert np.array_equal(c, outs[0][0]) and np.array_equal(d, outs[0][1])
+    ref = oracle_states(orc, c0, g, dt, k)
+    assert rel(outs[0][0], ref[k]) < k * 1e-12
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, chx.CHX_NUM_COLUMN_ORDERS, what=chx.CHX_TUNE_COLUMN_ORDER)
+
+
+@pytest.mark.parametrize("ny,nx,dtype,passes", [(1024, 1024, 0, 0), (96, 320, 0, 0),
+                                                (256, 448, 1, 2)])
+def test_graph_replays_match_eager(chx, ny, nx, dtype, passes):
+    """CHX_TUNE_GRAPH: the call captured once and replayed several times, with
+    eager calls of another handle and synchronisations between the replays;
+    every replay bitwise equal to the eager handle's result, the diagnostics
+    too; a new field pointer is re-captured and the old field left alone."""
+    g, dt, k = 0.01, 1e-5, 3
+    c0 = inputs.noise_field(ny, nx, 69)
+    hg = chx.ch_create(nx, ny, L, L, 1.0, g, dt, dtype=dtype, refine_passes=passes)
+    he = chx.ch_create(nx, ny, L, L, 1.0, g, dt, dtype=dtype, refine_passes=passes)
+    for h in (hg, he):  # the multi-kernel path, same choices on both
+        if dtype == 0:
+            chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)
+    chx.ch_set_tuning(hg, 1, what=chx.CHX_TUNE_GRAPH)
+    assert chx.ch_get_tuning(hg, chx.CHX_TUNE_GRAPH) == 1
+    ws = torch.empty(chx.ch_ws_bytes(hg), dtype=torch.uint8, device="cuda")
+    cg = torch.tensor(c0, device="cuda")
+    ce = torch.tensor(c0, device="cuda")
+    dg = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+    de = torch.zeros_like(dg)
+    for rep in range(4):
+        print(f"[case] graph replay {rep} {ny}x{nx} dtype={dtype}", flush=True)
+        chx.ch_adi_step(hg, cg, nsteps=k, diag_out=dg, ws=ws)
+        chx.ch_adi_step(he, ce, nsteps=k, diag_out=de)
+        torch.cuda.synchronize()
+        assert torch.equal(cg, ce), rep
+        assert torch.equal(dg, de), rep
+    other = torch.tensor(c0, device="cuda")
+    keep = cg.clone()
+    chx.ch_adi_step(hg, other, nsteps=k, diag_out=dg, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(cg, keep)
+    ref = torch.tensor(c0, device="cuda")
+    chx.ch_adi_step(he, ref, nsteps=k)
+    torch.cuda.synchronize()
+    assert torch.equal(other, ref)

@@ -121,3 +121,90 @@ def test_adi_refined_large_run_one_step(chx, orc):
     err = rel(c.cpu().numpy(), orc.ch_step(c0, L, L, 1.0, 0.001, 1e-6))
     print(f"refined 8192 one-step error {err:.3e}")
     assert err < TARGET
+
+
+# (ny, nx, dt, passes, steps, seed): several 32-row chunks, 60-column wave
+# segments with a ragged last one (nx % 60 != 0), exact segments (960), two
+# chunks (the wrap chunk is both neighbours), one chunk
+STEP_CASES = [(1024, 1024, 1e-5, 2, 3, 81), (96, 320, 1e-4, 1, 3, 82), (160, 576, 1e-4, 3, 2, 83),
+              (64, 2048, 1e-5, 2, 2, 84), (256, 960, 1e-4, 2, 2, 85), (32, 128, 1e-4, 1, 4, 86)]
+
+
+@pytest.mark.parametrize("ny,nx,dt,passes,k,seed", STEP_CASES)
+def test_refined_steps_in_one_call(chx, orc, ny, nx, dt, passes, k, seed):
+    """k refined steps in one call against the oracle's k FP64 steps, and the
+    diagnostics of every state of the call."""
+    g = 0.01
+    c0 = inputs.noise_field(ny, nx, seed)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=passes)
+    c = torch.tensor(c0, device="cuda")
+    d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+    print(f"[case] refined {k} steps {ny}x{nx} passes={passes}", flush=True)
+    chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+    torch.cuda.synchronize()
+    out = c.cpu().numpy()
+    ref = [c0]
+    for _ in range(k):
+        ref.append(orc.ch_step(ref[-1], L, L, 1.0, g, dt))
+    err = rel(out, ref[k])
+    print(f"refined {ny}x{nx} p={passes}: {k}-step error {err:.3e}", flush=True)
+    assert err < k * TARGET, err
+    dd = d.cpu().numpy().reshape(k + 1, 2)
+    l1 = np.sum(np.abs(c0)) * (L / nx) * (L / ny)
+    # the last state's diagnostics are those of the returned field
+    assert abs(dd[k, 0] - orc.ch_mass(out, L, L)) <= 1e-12 * l1
+    assert abs(dd[k, 1] - orc.ch_energy(out, L, L, g)) <= 1e-12 * abs(dd[k, 1])
+    for j in range(k + 1):
+        m, e = orc.ch_mass(ref[j], L, L), orc.ch_energy(ref[j], L, L, g)
+        assert abs(dd[j, 0] - m) <= 1e-10 * l1, (j, dd[j, 0], m)
+        assert abs(dd[j, 1] - e) <= max(j, 1) * 1e-9 * abs(e), (j, dd[j, 1], e)
+
+
+def test_refined_step_error_falls_with_passes(chx, orc):
+    """kappa = 1130 (1024^2, dt = 1e-5): each pass gains log10(1 / (kappa 2^-24))
+    digits, so one pass stays above 1e-10 and two reach the FP64 level."""
+    n, dt = 1024, 1e-5
+    c0 = inputs.noise_field(n, n, 3)
+    ref = orc.ch_step(c0, L, L, 1.0, 0.01, dt)
+    errs = []
+    for passes in (1, 2, 3):
+        h = chx.ch_create(n, n, L, L, 1.0, 0.01, dt, dtype=chx.CHX_F32_REFINED,
+                          refine_passes=passes)
+        c = torch.tensor(c0, device="cuda")
+        print(f"[case] refined 1024 passes={passes}", flush=True)
+        chx.ch_adi_step(h, c, nsteps=1)
+        torch.cuda.synchronize()
+        errs.append(rel(c.cpu().numpy(), ref))
+    print("refined 1024 errors by passes", errs, flush=True)
+    assert errs[0] > 1e-11 and errs[1] < 1e-12 and errs[2] < 1e-12, errs
+
+
+def test_refinement_that_cannot_converge_is_refused(chx):
+    """CHX_EREFINE when FP32 sweeps cannot contract the error
+    (4 kappa 2^-24 >= 1; kappa = 1 + 16 sigma for the periodic penta matrix):
+    sigma = 1e9 is refused before anything is enqueued, sigma = 0.5 runs; the
+    FP64 solve of the same stiff matrix is unaffected.  A refined ADI handle
+    whose directions sum to such a kappa is refused at creation."""
+    n, batch = 1024, 64
+    f = inputs.uniform(11, (n, batch), -1, 1)
+    x = torch.tensor(f, device="cuda")
+    stiff = chx.penta_factor(n, *penta(1e9))
+    with pytest.raises(chx.ChxError) as ei:
+        chx.penta_solve_batch(stiff, batch, x, layout=0, dtype=chx.CHX_F32_REFINED,
+                              refine_passes=3)
+    assert ei.value.status == chx.CHX_EREFINE
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), f)  # nothing was enqueued
+    chx.penta_solve_batch(stiff, batch, x, layout=0)  # FP64: fine
+    mild = chx.penta_factor(n, *penta(0.5))
+    y = torch.tensor(f, device="cuda")
+    chx.penta_solve_batch(mild, batch, y, layout=0, dtype=chx.CHX_F32_REFINED, refine_passes=1)
+    torch.cuda.synchronize()
+    tri = chx.tri_factor(n, -1e9, 1 + 2e9, -1e9)
+    with pytest.raises(chx.ChxError) as ei:
+        chx.tri_solve_batch(tri, batch, x, layout=0, dtype=chx.CHX_F32_REFINED, refine_passes=1)
+    assert ei.value.status == chx.CHX_EREFINE
+    with pytest.raises(chx.ChxError) as ei:  # 1024^2, dt = 1: kappa ~ 1.1e7 per direction
+        chx.ch_create(1024, 1024, L, L, 1.0, 0.001, 1.0, dtype=chx.CHX_F32_REFINED,
+                      refine_passes=3)
+    assert ei.value.status == chx.CHX_EREFINE

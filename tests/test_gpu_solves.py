@@ -223,6 +223,36 @@ def test_stencil_parity(chx, orc, shape, ext, periodic, premap):
     np.testing.assert_allclose(xo.cpu().numpy(), ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("shape,ext,periodic,premap", STENCIL_CASES)
+def test_stencil_parity_f32(chx, orc, shape, ext, periodic, premap):
+    """FP32 arrays (dtype CHX_F32): against the oracle's FP64 stencil of the
+    same FP32 input with the FP32-rounded weights, point by point within the
+    rounding bound of an FP32 sum of n products, (n + 4) 2^-24 sum |w| |pre(v)|
+    (pre(v) = v^3 - v costs three more roundings)."""
+    ny, nx = shape
+    left, right, top, bottom = ext
+    x = inputs.uniform(6, shape, -1, 1).astype(np.float32)
+    w = inputs.uniform(7, ((top + bottom + 1) * (left + right + 1),), -1, 1)
+    w32 = w.astype(np.float32).astype(np.float64)
+    xin = torch.tensor(x, device="cuda")
+    xo = torch.full(shape, 3.5, dtype=torch.float32, device="cuda")
+    print(f"[case] stencil f32 shape={shape} ext={ext} periodic={periodic} premap={premap}",
+          flush=True)
+    chx.stencil2d_apply(xin, xo, list(w), left, right, top, bottom, periodic=bool(periodic),
+                        premap=premap)
+    torch.cuda.synchronize()
+    x64 = x.astype(np.float64)
+    W = w32.reshape(top + bottom + 1, left + right + 1)
+    ref = orc.stencil2d(x64, W, left, right, top, bottom, periodic=bool(periodic),
+                        premap=premap, out=np.full(shape, 3.5))
+    mag = np.abs(x64) ** 3 + np.abs(x64) if premap else np.abs(x64)
+    scale = orc.stencil2d(mag, np.abs(W), left, right, top, bottom, periodic=bool(periodic),
+                          premap=0, out=np.zeros(shape))
+    bound = (W.size + 4) * 2.0 ** -24 * scale + 1e-30
+    err = np.abs(xo.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
 @pytest.mark.parametrize("ext,premap", [((1, 1, 1, 1), 1), ((2, 2, 2, 2), 0), ((4, 4, 4, 4), 0),
                                          ((3, 0, 4, 1), 1)])
 def test_stencil_full_size_sampled(chx, orc, ext, premap):

@@ -56,14 +56,21 @@ def test_bad_arguments_rejected_on_host(lib):
     # null plan / pointers
     assert lib.penta_solve_batch(None, 4, None, 4, 0, 0, 0, None, 0, None) == chx.CHX_EINVAL
     w = (ctypes.c_double * 9)(*([0.0] * 9))
-    assert lib.stencil2d_apply(None, None, 8, 8, 8, w, 1, 1, 1, 1, 1, 0, None) == chx.CHX_EINVAL
+    assert lib.stencil2d_apply(None, None, 8, 8, 8, 0, w, 1, 1, 1, 1, 1, 0, None) == chx.CHX_EINVAL
     # stencil extent beyond 4
     p = ctypes.c_void_p(1 << 20)
     q = ctypes.c_void_p(1 << 30)
     big = (ctypes.c_double * 121)(*([0.0] * 121))
-    assert lib.stencil2d_apply(p, q, 64, 64, 64, big, 5, 5, 0, 0, 1, 0, None) == chx.CHX_EINVAL
-    # overlapping in/out
-    assert lib.stencil2d_apply(p, p, 8, 8, 8, w, 1, 1, 1, 1, 1, 0, None) == chx.CHX_EINVAL
+    assert lib.stencil2d_apply(p, q, 64, 64, 64, 0, big, 5, 5, 0, 0, 1, 0, None) == chx.CHX_EINVAL
+    # overlapping in/out, for either element size (FP32 arrays 4 B apart per
+    # element: 8 x 8 FP32 at p and p + 128 B overlap, FP64 at p + 256 B too)
+    assert lib.stencil2d_apply(p, p, 8, 8, 8, 0, w, 1, 1, 1, 1, 1, 0, None) == chx.CHX_EINVAL
+    p2 = ctypes.c_void_p((1 << 20) + 128)
+    assert lib.stencil2d_apply(p, p2, 8, 8, 8, chx.CHX_F32, w, 1, 1, 1, 1, 1, 0,
+                               None) == chx.CHX_EINVAL
+    # unknown dtype (CHX_F32_REFINED is not an array type)
+    assert lib.stencil2d_apply(p, q, 8, 8, 8, chx.CHX_F32_REFINED, w, 1, 1, 1, 1, 1, 0,
+                               None) == chx.CHX_EINVAL
     prm = chx.ChParams(4, 64, 6.28, 6.28, 1.0, 0.01, 1e-4, 0, 0)
     assert lib.ch_create(ctypes.byref(prm), ctypes.byref(h)) == chx.CHX_EUNSUPPORTED_N
     prm = chx.ChParams(64, 64, 6.28, 6.28, 1.0, 0.01, -1.0, 0, 0)
@@ -88,7 +95,8 @@ def test_shape_count_matches_header():
     text = open(HEADER).read()
     for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH",
                  "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES", "CHX_SCHEME_P1", "CHX_SCHEME_P2",
-                 "CHX_NOALLOC_SCRATCH_BYTES",
+                 "CHX_TUNE_COLUMN_ORDER", "CHX_NUM_COLUMN_ORDERS", "CHX_NOALLOC_SCRATCH_BYTES",
+                 "CHX_TUNE_GRAPH",
                  "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
         m = re.search(r"#define\s+" + name + r"\s+\(?(\d+)(u << (\d+)\))?", text)
         value = int(m.group(1)) << int(m.group(3) or 0) if m else None
@@ -309,6 +317,9 @@ def test_stencil_binding_rejects_mismatched_layouts():
                             torch.zeros((8, 11), dtype=torch.float64), w, 1, 1, 1, 1)
     with pytest.raises(chx.ChxError, match="leading dimension"):  # column-strided view
         chx.stencil2d_apply(big[:, ::2], torch.zeros((8, 8), dtype=torch.float64), w, 1, 1, 1, 1)
+    with pytest.raises(chx.ChxError, match="float64 or both float32"):
+        chx.stencil2d_apply(torch.zeros((8, 10), dtype=torch.float64),
+                            torch.zeros((8, 10), dtype=torch.float32), w, 1, 1, 1, 1)
 
 
 class _FakeHandle:
