@@ -441,7 +441,7 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
     chx.ch_ensemble_step(ens, fields, nsteps=k, use_graph=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    rb = refined_bytes_per_point(2)
+    rb = refined_bytes_per_point(2, k)
     out["f32_refined_2pass_graph"] = {"steps": k, "ms_per_step": round(1e3 * el / k, 5),
                                       "updates_per_s": points * k / el,
                                       "algorithmic_bytes_per_point": rb,
@@ -450,7 +450,7 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
     ref = out["f32_refined_2pass_graph"]["updates_per_s"]
     out["f32_refined_vs_f64"] = {
         "refined_beats_f64": bool(ref > f64), "updates_ratio_refined_over_f64": round(ref / f64, 3),
-        "bytes_per_point_f64": 34.0, "bytes_per_point_refined_2pass": rb,
+        "bytes_per_point_f64": 34.0, "bytes_per_point_refined_2pass": round(rb, 2),
         "why": "both paths stream HBM at similar rates; FP64 sweeps cost no more time than FP32 "
                "ones here, and refinement must still read and write FP64 right-hand sides, "
                "states and the deferred FP32 solutions of every pass"}
@@ -458,14 +458,19 @@ def ensemble_throughput(chx, torch, steps=2000, warmup=20):
     return out
 
 
-def refined_bytes_per_point(p):
-    """Algorithmic HBM bytes per point of one FP32-refined ADI step with p
-    refinement passes: first column pass (read c 8, write r 8, FP32 chunk
-    interiors 3.75, parts 0.5), FP32 separators 0.75, FP32 row solves 8; pass k
-    adds the residual column pass (read r 8 and V_0..V_{k-1} 4 k, write 4.25),
-    separators 0.75 and rows 8; the final pass reads V_0..V_p (4 (p + 1)) and
-    writes c (8).  70, 103, 140 B for p = 1, 2, 3 (the FP64 step: 34 B)."""
-    return 29.0 + sum(21.0 + 4.0 * k for k in range(1, p + 1)) + 4.0 * (p + 1) + 8.0
+def refined_bytes_per_point(p, steps=1):
+    """Algorithmic HBM bytes per point and step of FP32-refined ADI steps with
+    p refinement passes, averaged over a call of `steps` steps.  A step: the
+    first column pass reads the state (the caller's c on the first step, 8 B;
+    on later steps the previous step's deferred FP32 solutions V_0..V_p,
+    4 (p + 1) B), writes r (8) and the FP32 chunk interiors and parts (4.25);
+    FP32 separators 0.75; FP32 row solves 8; pass k adds the residual column
+    pass (read r 8 and V_0..V_{k-1} 4 k, write 4.25), separators 0.75 and rows
+    8.  After the last step the state is rebuilt from V_0..V_p (4 (p + 1)) and
+    written to c (8).  Per step in a long call: 54, 87, 124 B for p = 1, 2, 3
+    (the FP64 step: 34 B)."""
+    steady = 21.0 + 4.0 * (p + 1) + sum(21.0 + 4.0 * k for k in range(1, p + 1))
+    return steady + 16.0 / steps
 
 
 def small_run(chx, torch, steps=1000):
@@ -995,11 +1000,11 @@ def main():
         chx.ch_adi_step(hr, cr, nsteps=kr)
         torch.cuda.synchronize()
         elr = time.perf_counter() - t0
-        rb = refined_bytes_per_point(3)
+        rb = refined_bytes_per_point(3, kr)
         gbps = rb * n * n * kr / elr / 1e9
         extra["large_f32_refined_3pass"] = {"steps": kr, "ms_per_step": round(1e3 * elr / kr, 5),
                                             "updates_per_s": n * n * kr / elr,
-                                            "algorithmic_bytes_per_point": rb,
+                                            "algorithmic_bytes_per_point": round(rb, 2),
                                             "algorithmic_GBps": round(gbps, 1),
                                             "frac_of_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)}
         del cr

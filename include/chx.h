@@ -373,8 +373,13 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   separator kernel (0 .. CHX_NUM_REDUCED_SHAPES-1: waves per block x chunks
  *   per wave x window entries staged at once).  ch_create times every
  *   candidate on zeroed scratch buffers of the handle's size and keeps the
- *   fastest; the choice is cached per (nx, plan) for the life of the
- *   process.  Environment variable CHX_AUTOTUNE=0 skips the timing (shape 0).
+ *   fastest; the choices (this shape, the row split and the column order)
+ *   are kept per size for the life of the process and in a tuning cache
+ *   file across processes: $CHX_TUNE_CACHE, else
+ *   $XDG_CACHE_HOME/chx/tuning.txt, else $HOME/.cache/chx/tuning.txt (one
+ *   text line per device architecture and size; CHX_TUNE_CACHE=0 turns the
+ *   file off).  Environment variable CHX_AUTOTUNE=0 skips the timing and
+ *   the file (shape 0).
  *   Every shape sums the same terms in the same order, so results are
  *   bitwise identical whatever the shape.
  * CHX_TUNE_ROW_SPLIT: for rows of 4096 or 8192 points, -1 runs the column
@@ -443,6 +448,18 @@ int ch_get_noise_step(chx_ch h, unsigned long long* step);
  *   CHX_ENONFINITE if either is NaN or infinite. */
 int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass,
                    double* energy, chx_stream s);
+
+/* ch_energy_decay_rate: the free-energy decay rate of Ch.7 eq. 7:betaN,
+ *   beta = -(t / F) dF/dt, of every run and state of a stepping call's
+ *   diagnostics.  diag (device): nruns blocks of 2 nstates doubles laid out as
+ *   ch_adi_step (nruns = 1) or ch_ensemble_step write them (mass, energy of
+ *   state k at r*2*nstates + 2k + {0,1}); state k is at time t0 + k dt.
+ *   beta (device, nruns * nstates doubles, must not overlap diag):
+ *   beta[r*nstates + k].  dF/dt by second-order differences, central inside,
+ *   three-point one-sided at the first and last state (exact for quadratic
+ *   F).  nstates >= 3 and dt > 0, else CHX_EINVAL.  Asynchronous on s. */
+int ch_energy_decay_rate(const double* diag, int nruns, int nstates, double t0,
+                         double dt, double* beta, chx_stream s);
 
 /* ch_moments: coarsening measure of Ch.3 "Numerical Results": out (host, 3
  *   doubles) = <C>, <C^2> and s = 1 / (1 - <C^2>), the averages by composite

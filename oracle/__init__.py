@@ -92,6 +92,8 @@ def load(path: str | None = None):
     lib.orc_ch_mass.argtypes = [_P, _I, _I, _D, _D]
     lib.orc_ch_energy.restype = _D
     lib.orc_ch_energy.argtypes = [_P, _I, _I, _D, _D, _D]
+    lib.orc_energy_decay_rate.restype = _I
+    lib.orc_energy_decay_rate.argtypes = [_P, _I, _D, _D, _P]
     if path is None:
         _lib = lib
     return lib
@@ -320,6 +322,14 @@ class Oracle:
         c = _f64(c2d)
         ny, nx = c.shape
         return self.lib.orc_ch_energy(_ptr(c), nx, ny, lx, ly, gamma)
+
+    def energy_decay_rate(self, F, t0, dt):
+        """beta_k = -(t_k / F_k) dF/dt at t_k = t0 + k dt (Ch.7 eq. 7:betaN)."""
+        f = _f64(np.asarray(F, dtype=np.float64)).copy()
+        out = np.empty_like(f)
+        if self.lib.orc_energy_decay_rate(_ptr(f), f.size, float(t0), float(dt), _ptr(out)):
+            raise ValueError("energy_decay_rate needs at least three samples and dt > 0")
+        return out
 
 
 _default = None

@@ -785,3 +785,25 @@ double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
   }
   return (s + comp) * dx * dy;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Ch.7 eq. 7:betaN: the free-energy decay rate beta = -(t / F) dF/dt of a
+ * series F_k = F(t0 + k dt), k = 0 .. n-1 (n >= 3).  The thesis does not say
+ * how dF/dt is taken from the sampled series; read here as second-order
+ * differences: central at interior samples, the three-point one-sided forms
+ * at the two ends (each exact for a quadratic F). */
+int orc_energy_decay_rate(const double* F, int n, double t0, double dt, double* beta) {
+  if (n < 3 || !(dt > 0.0)) return -1;
+  for (int k = 0; k < n; ++k) {
+    double dFdt;
+    if (k == 0)
+      dFdt = (-3.0 * F[0] + 4.0 * F[1] - F[2]) / (2.0 * dt);
+    else if (k == n - 1)
+      dFdt = (3.0 * F[n - 1] - 4.0 * F[n - 2] + F[n - 3]) / (2.0 * dt);
+    else
+      dFdt = (F[k + 1] - F[k - 1]) / (2.0 * dt);
+    const double t = t0 + k * dt;
+    beta[k] = -(t / F[k]) * dFdt;
+  }
+  return 0;
+}

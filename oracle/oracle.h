@@ -180,6 +180,9 @@ double orc_simpson_mean(const double* c, int nx, int ny, int power);
 double orc_ch_mass(const double* c, int nx, int ny, double lx, double ly);
 double orc_ch_energy(const double* c, int nx, int ny, double lx, double ly,
                      double gamma);
+/* Free-energy decay rate beta_k = -(t_k / F_k) (dF/dt)_k, t_k = t0 + k dt,
+ * second-order differences (Ch.7 eq. 7:betaN). */
+int orc_energy_decay_rate(const double* F, int n, double t0, double dt, double* beta);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,7 @@ EXPORTED = [
     "ch_create", "ch_destroy", "ch_ws_bytes", "ch_adi_step", "ch_adi_step_p2",
     "ch_adi_step_timed",
     "ch_get_tuning", "ch_set_tuning", "ch_set_noise", "ch_get_noise_step", "ch_diagnostics",
-    "ch_moments", "ch_k1",
+    "ch_moments", "ch_k1", "ch_energy_decay_rate",
     "batch1d_create", "batch1d_destroy", "batch1d_ws_bytes", "batch1d_step",
     "batch1d_rewrite_ws_bytes", "batch1d_step_rewrite",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
@@ -126,6 +126,7 @@ def load(path: str | None = None):
         "ch_set_tuning": (_I, [_V, _I, _I]),
         "ch_diagnostics": (_I, [_V, _V, _L, _DP, _DP, _V]),
         "ch_moments": (_I, [_V, _V, _L, _DP, _V]),
+        "ch_energy_decay_rate": (_I, [_V, _I, _I, _D, _D, _V, _V]),
         "ch_k1": (_I, [_V, _V, _L, _DP, _V]),
         "batch1d_create": (_I, [_I, _I, _D, _D, _D, _D, ctypes.POINTER(_V)]),
         "batch1d_destroy": (_I, [_V]),
@@ -701,6 +702,21 @@ def ch_diagnostics(h: CH, c, ld: int | None = None, stream=None):
     if st not in (CHX_OK, CHX_ENONFINITE):
         _check(st, "ch_diagnostics")
     return m.value, e.value, st
+
+
+def ch_energy_decay_rate(diag, nruns: int, nstates: int, t0: float, dt: float, stream=None):
+    """beta = -(t / F) dF/dt (Ch.7) of every run and state from a stepping
+    call's diagnostics (float64 device tensor of nruns * 2 * nstates values);
+    returns a new device tensor of nruns * nstates values."""
+    import torch
+    if diag.numel() < nruns * 2 * nstates:
+        raise ChxError(CHX_EINVAL, "ch_energy_decay_rate: diag holds fewer than "
+                                   "nruns * 2 * nstates values")
+    beta = torch.empty(nruns * nstates, dtype=torch.float64, device=diag.device)
+    _check(load().ch_energy_decay_rate(_devptr(diag, "diag"), nruns, nstates, float(t0),
+                                       float(dt), _devptr(beta, "beta"), _stream(stream)),
+           "ch_energy_decay_rate")
+    return beta
 
 
 def ch_moments(h: CH, c, ld: int | None = None, stream=None):

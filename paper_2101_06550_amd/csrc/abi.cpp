@@ -3,11 +3,16 @@
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <string>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -792,6 +797,72 @@ size_t device_max_lds() {
 // then the separator rows on a second stream, the interior rows beside them.
 constexpr int kSplitOverlap = -2;
 
+// Persistent tuning cache: a text file with one line per tuned size,
+//   chx-tune-1 <arch> <nx> <ny> <column plan S dlo dcount> <row plan S dlo dcount>
+//       <separator shape> <row split> <column order>
+// at $CHX_TUNE_CACHE, else $XDG_CACHE_HOME/chx/tuning.txt, else
+// $HOME/.cache/chx/tuning.txt; CHX_TUNE_CACHE=0 turns it off.  Lines are only
+// appended; the last line of a key wins; unreadable lines are skipped.
+std::string tune_cache_path() {
+  const char* env = std::getenv("CHX_TUNE_CACHE");
+  if (env) return (env[0] == '\0' || (env[0] == '0' && env[1] == '\0')) ? std::string() : env;
+  std::string dir;
+  if (const char* x = std::getenv("XDG_CACHE_HOME"); x && x[0]) dir = x;
+  else if (const char* hm = std::getenv("HOME"); hm && hm[0]) dir = std::string(hm) + "/.cache";
+  else return std::string();
+  (void)mkdir(dir.c_str(), 0755);
+  dir += "/chx";
+  (void)mkdir(dir.c_str(), 0755);
+  return dir + "/tuning.txt";
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+std::string tune_key_text(const std::string& arch, int nx, int ny, const DevChunk& cy,
+                          const DevChunk& cx) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "chx-tune-1 %s %d %d %d %d %d %d %d %d", arch.c_str(), nx, ny,
+                cy.S, cy.dlo, cy.dcount, cx.S, cx.dlo, cx.dcount);
+  return buf;
+}
+
+bool tune_cache_lookup(const std::string& path, const std::string& key, Tuned* out) {
+  if (path.empty()) return false;
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
+        line[key.size()] != ' ')
+      continue;
+    Tuned t;
+    if (std::sscanf(line.c_str() + key.size(), " %d %d %d", &t.red_shape, &t.split,
+                    &t.col_order) != 3)
+      continue;
+    if (t.red_shape < 0 || t.red_shape >= kNumRedShapes || t.col_order < 0 ||
+        t.col_order >= CHX_NUM_COLUMN_ORDERS || t.split < -2 || t.split >= kNumSplitShapes)
+      continue;
+    *out = t;
+    found = true;
+  }
+  return found;
+}
+
+void tune_cache_store(const std::string& path, const std::string& key, const Tuned& t) {
+  if (path.empty()) return;
+  std::ofstream outf(path, std::ios::app);
+  if (outf) outf << key << ' ' << t.red_shape << ' ' << t.split << ' ' << t.col_order << '\n';
+}
+
 Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   const DevChunk& c = py->dchunk;
   const auto key = std::make_tuple(nx, ny, c.S, c.dlo, c.dcount);
@@ -801,6 +872,15 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   Tuned best;
   const char* env = std::getenv("CHX_AUTOTUNE");
   if (env && env[0] == '0') return best;
+  const std::string cache_path = tune_cache_path();
+  const std::string cache_key = tune_key_text(device_arch(), nx, ny, c, px->dchunk);
+  if (tune_cache_lookup(cache_path, cache_key, &best)) {
+    // a split or overlap choice needs the handle's shapes to allow it
+    if (best.split >= 0 && !split_fits(c, px->dchunk, best.split)) best.split = -1;
+    if (best.split == kSplitOverlap && !rows_subsets_fit(px->dchunk)) best.split = -1;
+    g_tune_cache[key] = best;
+    return best;
+  }
   const size_t rho_bytes = (size_t)c.S * 4 * nx * sizeof(double);
   const size_t dst_bytes = (size_t)ny * nx * sizeof(double);
   double *rho = nullptr, *dst = nullptr;
@@ -921,6 +1001,7 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
     return Tuned{};
   }
   g_tune_cache[key] = best;
+  tune_cache_store(cache_path, cache_key, best);
   return best;
 }
 
@@ -1197,9 +1278,12 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     for (int n = 0; n < nsteps && ok(); ++n) {
       if (tm) tm->step(n);
       const bool diag = diag_out != nullptr;
+      // every step after the first rebuilds its state from the previous
+      // step's solutions, which stay in the workspace (c is written once,
+      // after the last step)
       B();
       e = launch_rstep_first(c, ld, r, y32, rho32, nx, ny, h->py->dchunk, h->K,
-                             diag ? part : nullptr, st);
+                             diag ? part : nullptr, st, V, n > 0 ? np + 1 : 0);
       E(0);
       if (ok()) {
         B();
@@ -1227,11 +1311,11 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
           E(2);
         }
       }
-      if (ok()) {
-        if (tm && n + 1 == nsteps) tm->on = true;
+      if (ok() && n + 1 == nsteps) {
+        if (tm) tm->on = true;
         B();
         e = launch_rstep_final(V, np + 1, c, ld, nx, ny, h->py->dchunk, h->K, part,
-                               (diag && n + 1 == nsteps) ? diag_out + 2 * nsteps : nullptr, st);
+                               diag ? diag_out + 2 * nsteps : nullptr, st);
         E(3);
       }
     }
@@ -1379,17 +1463,16 @@ int ens_launch_refined(chx_ens_s* E, int nsteps, double* diag_out, unsigned char
   for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
     for (int k = 0; k <= E->max_passes && e == hipSuccess; ++k) {
       e = launch_ens_rstep_column(k, k == 0 && diag_out, E->druns, E->hcls, it + E->o_col,
-                                  E->rn_col[k], ws, st);
+                                  E->rn_col[k], ws, st, k == 0 && n > 0);
       if (e == hipSuccess)
         e = launch_ens_reduced32(E->druns, E->hcls, it + E->o_red, E->rn_red[k], ws, n,
                                  k == 0 ? diag_out : nullptr, dstride, E->red_lds, st);
       if (e == hipSuccess)
         e = launch_ens_rows32(E->druns, E->hcls, it + E->o_row, E->rn_row[k], ws, k, st);
     }
-    if (e == hipSuccess)
+    if (e == hipSuccess && n + 1 == nsteps)
       e = launch_ens_rstep_final(E->druns, E->hcls, it + E->o_col, E->rn_col[0], E->dbig,
-                                 E->nbig, ws, n + 1 == nsteps ? diag_out : nullptr, dstride,
-                                 nsteps, st);
+                                 E->nbig, ws, diag_out, dstride, nsteps, st);
   }
   return e == hipSuccess ? CHX_OK : CHX_EHIP;
 }
@@ -1557,6 +1640,22 @@ int ch_diagnostics(chx_ch h, const double* c, long ld, double* mass, double* ene
   *energy = host[1];
   if (!std::isfinite(host[0]) || !std::isfinite(host[1])) return CHX_ENONFINITE;
   return CHX_OK;
+}
+
+int ch_energy_decay_rate(const double* diag, int nruns, int nstates, double t0, double dt,
+                         double* beta, chx_stream s) {
+  if (!diag || !beta || nruns < 1 || nstates < 3 || !(dt > 0) || !std::isfinite(dt) ||
+      !std::isfinite(t0))
+    return CHX_EINVAL;
+  const char* a = reinterpret_cast<const char*>(diag);
+  const char* b = reinterpret_cast<const char*>(beta);
+  const size_t na = (size_t)nruns * 2 * nstates * sizeof(double);
+  const size_t nb = (size_t)nruns * nstates * sizeof(double);
+  if (a < b + nb && b < a + na) return CHX_EINVAL;  // overlapping buffers
+  return launch_ch_decay_rate(diag, nruns, nstates, t0, dt, beta, static_cast<hipStream_t>(s)) ==
+                 hipSuccess
+             ? CHX_OK
+             : CHX_EHIP;
 }
 
 int ch_moments(chx_ch h, const double* c, long ld, double* out, chx_stream s) {

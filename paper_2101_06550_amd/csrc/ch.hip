@@ -632,6 +632,37 @@ hipError_t launch_ch_k1(const double2* spec, int nx, int ny, double lx, double l
   return hipGetLastError();
 }
 
+// Ch.7 free-energy decay rate beta = -(t / F) dF/dt from the energies a
+// stepping call wrote (diag: run r, state k at r * 2 nstates + 2 k + {0: mass,
+// 1: energy}), t_k = t0 + k dt: second-order differences, central inside and
+// three-point one-sided at the first and last state.  One thread per value.
+__global__ __launch_bounds__(256) void ch_decay_rate(const double* __restrict__ diag, int nruns,
+                                                     int nstates, double t0, double dt,
+                                                     double* __restrict__ beta) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)nruns * nstates) return;
+  const long r = idx / nstates;
+  const int k = (int)(idx - r * nstates);
+  const double* F = diag + r * 2L * nstates + 1;  // energies at stride 2
+  double dFdt;
+  if (k == 0)
+    dFdt = (-3.0 * F[0] + 4.0 * F[2] - F[4]) / (2.0 * dt);
+  else if (k == nstates - 1)
+    dFdt = (3.0 * F[2 * k] - 4.0 * F[2 * k - 2] + F[2 * k - 4]) / (2.0 * dt);
+  else
+    dFdt = (F[2 * k + 2] - F[2 * k - 2]) / (2.0 * dt);
+  const double t = t0 + k * dt;
+  beta[idx] = -(t / F[2 * k]) * dFdt;
+}
+
+hipError_t launch_ch_decay_rate(const double* diag, int nruns, int nstates, double t0, double dt,
+                                double* beta, hipStream_t st) {
+  const long n = (long)nruns * nstates;
+  hipLaunchKernelGGL(ch_decay_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, diag,
+                     nruns, nstates, t0, dt, beta);
+  return hipGetLastError();
+}
+
 hipError_t launch_ch_diag_final(const double* part, long nparts, double scale, double* out,
                                 hipStream_t st) {
   hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, nparts, scale, out);

@@ -66,15 +66,21 @@ hipError_t launch_ch_column_final(const double* src, long lds, double* dst, long
 // into c (and with diag_out its mass and energy there).
 int rstep_segments(int nx);  // 60-column wave segments of a row of nx
 long rstep_parts(int nx, int ny);
+// vprev / nbprev: the previous step's deferred solutions (nbprev = its passes
+// + 1), the state rebuilt from them; nbprev = 0 reads c.
 hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
                               int nx, int ny, const DevChunk& cy, const ChCoef& K, double* part,
-                              hipStream_t st);
+                              hipStream_t st, const float* const* vprev = nullptr,
+                              int nbprev = 0);
 hipError_t launch_rstep_resid(const double* rbuf, const float* const* v, int nb, float* y32,
                               float* rho, int nx, int ny, const DevChunk& cy, const double* cx5,
                               const double* cy5, hipStream_t st);
 hipError_t launch_rstep_final(const float* const* v, int nb, double* c, long ld, int nx, int ny,
                               const DevChunk& cy, const ChCoef& K, double* part, double* diag_out,
                               hipStream_t st);
+// beta = -(t / F) dF/dt per run and state from a stepping call's diagnostics.
+hipError_t launch_ch_decay_rate(const double* diag, int nruns, int nstates, double t0, double dt,
+                                double* beta, hipStream_t st);
 long ch_diag_partial_blocks(int nx, int ny);
 hipError_t launch_ch_diag(const double* c, long ld, int nx, int ny, const ChCoef& K, double* part,
                           double* out, hipStream_t st);

@@ -77,9 +77,11 @@ hipError_t launch_ens_small_steps(const EnsRun* runs, const EnsClasses& cls, con
 // pass 0: right-hand side (kept) swept in FP32, with (diag) the partials of
 // the state; pass k >= 1: residual swept in FP32; both into the run's FP32
 // column buffer and parts.
+// from_v (pass 0 of every step after the first of a call): the state is
+// rebuilt from the previous step's deferred FP32 solutions instead of read.
 hipError_t launch_ens_rstep_column(int pass, bool diag, const EnsRun* runs, const EnsClasses& cls,
                                    const int4* items, int nitems, unsigned char* ws,
-                                   hipStream_t st);
+                                   hipStream_t st, bool from_v = false);
 // FP32 separators into the column buffer; with diag_out, the state's (mass,
 // energy) of step `step` (the pass-0 partials).
 hipError_t launch_ens_reduced32(const EnsRun* runs, const EnsClasses& cls, const int4* items,

@@ -100,21 +100,70 @@ __device__ __forceinline__ void finish32(float (&f)[M], const float* __restrict_
 
 }  // namespace
 
+// The deferred FP32 solutions V_0 .. V_{NB-1} of a step (dense, ld = nx).
+struct RBufs {
+  const float* v[4];
+};
+
+// Sum over the buffers of rows j (FP64).
+template <int NB>
+__device__ __forceinline__ double vsum(const RBufs& B, long j, int nx, int i) {
+  double s = 0.0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) s += (double)B.v[b][j * nx + i];
+  return s;
+}
+
 // First pass of a refined step: r = RHS(c) in FP64 (written out for the
 // residuals of the later passes), swept in FP32; DIAG: mass and free energy
-// of c.  Window rows kc M - 1 .. kc M + M.
-template <bool DIAG>
+// of c.  Window rows kc M - 1 .. kc M + M.  NB = 0: c is read from the
+// caller's array; NB > 0 (every step of a call after the first): c is the
+// previous step's solution, rebuilt from its deferred FP32 solutions
+// V_0 .. V_{NB-1} as it is read (so the state is not written and read back
+// between the steps of a call).
+template <bool DIAG, int NB = 0>
 __device__ __forceinline__ void rstep_first_body(const double* __restrict__ c, long ld,
                                                  double* __restrict__ rbuf,
                                                  float* __restrict__ y32,
                                                  float* __restrict__ rho, int nx, int ny,
                                                  int nseg, const float* __restrict__ rec32,
                                                  const BandT<float>& bd, const ChCoef& K,
-                                                 double* __restrict__ part, int seg, int kc) {
+                                                 double* __restrict__ part, int seg, int kc,
+                                                 const RBufs& Bv = RBufs{}, int Sc = 1,
+                                                 const double* __restrict__ rec = nullptr) {
   const Lanes L = lanes_of(seg, nx);
   constexpr int Q = M + 2;
+  double tp[P] = {}, to[P] = {}, tn[P] = {};
+  if (NB > 0) {  // separator rows (final values) of chunks kc - 1, kc, kc + 1
+    const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      tp[a] = vsum<NB>(Bv, (long)kcm * M + MI + a, nx, L.i);
+      to[a] = vsum<NB>(Bv, (long)kc * M + MI + a, nx, L.i);
+      tn[a] = vsum<NB>(Bv, (long)kcp * M + MI + a, nx, L.i);
+    }
+  }
   double X[Q];
-  auto load = [&](int t) { X[t] = c[(long)wrap_row(kc * M - 1 + t, ny) * ld + L.i]; };
+  auto load = [&](int t) {
+    if (NB == 0) {
+      X[t] = c[(long)wrap_row(kc * M - 1 + t, ny) * ld + L.i];
+    } else {
+      // window row t: t = 0 is chunk kc-1's last separator, t = 1 .. M chunk
+      // kc's position t - 1, t = M + 1 chunk kc+1's position 0
+      double x = vsum<NB>(Bv, wrap_row(kc * M - 1 + t, ny), nx, L.i);
+      if (t >= 1) {
+        const bool below = t == M + 1;
+        const int pp = below ? 0 : t - 1;
+        if (pp < MI) {
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
+                rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+        }
+      }
+      X[t] = x;
+    }
+  };
 #pragma unroll
   for (int t = 0; t < kPfR; ++t) load(t);
   double XL[Q], XR[Q];
@@ -160,20 +209,6 @@ __device__ __forceinline__ void rstep_first_body(const double* __restrict__ c, l
       part[2 * ((long)kc * nseg + seg) + 1] = esum;
     }
   }
-}
-
-// The deferred FP32 solutions V_0 .. V_{NB-1} of a step (dense, ld = nx).
-struct RBufs {
-  const float* v[4];
-};
-
-// Sum over the buffers of rows j (FP64).
-template <int NB>
-__device__ __forceinline__ double vsum(const RBufs& B, long j, int nx, int i) {
-  double s = 0.0;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) s += (double)B.v[b][j * nx + i];
-  return s;
 }
 
 // Later pass k = NB of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}
@@ -304,18 +339,19 @@ __device__ __forceinline__ void rstep_final_body(const RBufs& B, double* __restr
 
 // Single-field kernels: block = 4 waves = 4 consecutive 60-column segments
 // of chunk blockIdx.y.
-template <bool DIAG>
+template <bool DIAG, int NB>
 __global__ __launch_bounds__(256) void rstep_first(const double* __restrict__ c, long ld,
                                                    double* __restrict__ rbuf,
                                                    float* __restrict__ y32,
                                                    float* __restrict__ rho, int nx, int ny,
                                                    int nseg, const float* __restrict__ rec32,
                                                    BandT<float> bd, ChCoef K,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, RBufs Bv, int Sc,
+                                                   const double* __restrict__ rec) {
   const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (seg >= nseg) return;  // no barrier in this kernel
-  rstep_first_body<DIAG>(c, ld, rbuf, y32, rho, nx, ny, nseg, rec32, bd, K, part, seg,
-                         blockIdx.y);
+  rstep_first_body<DIAG, NB>(c, ld, rbuf, y32, rho, nx, ny, nseg, rec32, bd, K, part, seg,
+                             blockIdx.y, Bv, Sc, rec);
 }
 
 template <int NB>
@@ -352,7 +388,7 @@ __device__ __forceinline__ RBufs ens_vbufs(unsigned char* ws, const EnsRun& R) {
   return B;
 }
 
-template <int PASS, bool DIAG>
+template <int PASS, bool DIAG, bool FROMV = false>
 __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict__ runs,
                                                         EnsClasses cls,
                                                         const int4* __restrict__ items,
@@ -368,9 +404,17 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
   double* rbuf = reinterpret_cast<double*>(ws + R.off_r);
   float* y32 = reinterpret_cast<float*>(ws + R.off_y32);
   float* rho = reinterpret_cast<float*>(ws + R.off_rho32);
-  if (PASS == 0) {
+  if (PASS == 0 && !FROMV) {
     rstep_first_body<DIAG>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K,
                            reinterpret_cast<double*>(ws + R.off_part), seg, it.z);
+  } else if (PASS == 0) {  // the state rebuilt from the previous step's solutions
+    double* part = reinterpret_cast<double*>(ws + R.off_part);
+    const RBufs Bv = ens_vbufs(ws, R);
+    switch (R.passes) {  // uniform per block
+      case 1: rstep_first_body<DIAG, 2>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
+      case 2: rstep_first_body<DIAG, 3>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
+      default: rstep_first_body<DIAG, 4>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
+    }
   } else {
     BandT<double> ax, ay;
 #pragma unroll
@@ -404,17 +448,22 @@ __global__ __launch_bounds__(256) void ens_rstep_final(const EnsRun* __restrict_
 
 hipError_t launch_ens_rstep_column(int pass, bool diag, const EnsRun* runs, const EnsClasses& cls,
                                    const int4* items, int nitems, unsigned char* ws,
-                                   hipStream_t st) {
+                                   hipStream_t st, bool from_v) {
   if (nitems <= 0) return hipSuccess;
-#define CHX_ERC(P_, D_)                                                                      \
-  hipLaunchKernelGGL((ens_rstep_column<P_, D_>), dim3(nitems), dim3(256), 0, st, runs, cls, \
+#define CHX_ERC(P_, D_, F_)                                                                      \
+  hipLaunchKernelGGL((ens_rstep_column<P_, D_, F_>), dim3(nitems), dim3(256), 0, st, runs, cls, \
                      items, ws)
   if (pass == 0) {
-    if (diag) CHX_ERC(0, true);
-    else CHX_ERC(0, false);
-  } else if (pass == 1) CHX_ERC(1, false);
-  else if (pass == 2) CHX_ERC(2, false);
-  else CHX_ERC(3, false);
+    if (from_v) {
+      if (diag) CHX_ERC(0, true, true);
+      else CHX_ERC(0, false, true);
+    } else {
+      if (diag) CHX_ERC(0, true, false);
+      else CHX_ERC(0, false, false);
+    }
+  } else if (pass == 1) CHX_ERC(1, false, false);
+  else if (pass == 2) CHX_ERC(2, false, false);
+  else CHX_ERC(3, false, false);
 #undef CHX_ERC
   return hipGetLastError();
 }
@@ -445,17 +494,25 @@ static dim3 rstep_grid(int nx, int ny) {
 
 hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
                               int nx, int ny, const DevChunk& cy, const ChCoef& K, double* part,
-                              hipStream_t st) {
-  if (ny % M != 0 || cy.S * M != ny) return hipErrorInvalidValue;
+                              hipStream_t st, const float* const* vprev, int nbprev) {
+  if (ny % M != 0 || cy.S * M != ny || nbprev < 0 || nbprev > 4) return hipErrorInvalidValue;
   BandT<float> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = (float)cy.coef[k];
   const int nseg = (nx + kSegR - 1) / kSegR;
-  if (part)
-    hipLaunchKernelGGL((rstep_first<true>), rstep_grid(nx, ny), dim3(256), 0, st, c, ld, rbuf,
-                       y32, rho, nx, ny, nseg, cy.rec32, bd, K, part);
-  else
-    hipLaunchKernelGGL((rstep_first<false>), rstep_grid(nx, ny), dim3(256), 0, st, c, ld, rbuf,
-                       y32, rho, nx, ny, nseg, cy.rec32, bd, K, part);
+  RBufs B{};
+  for (int b = 0; b < nbprev; ++b) B.v[b] = vprev[b];
+#define CHX_RFIRST(D_, NB_)                                                                     \
+  hipLaunchKernelGGL((rstep_first<D_, NB_>), rstep_grid(nx, ny), dim3(256), 0, st, c, ld, rbuf, \
+                     y32, rho, nx, ny, nseg, cy.rec32, bd, K, part, B, cy.S, cy.rec)
+  const bool d = part != nullptr;
+  switch (nbprev) {
+    case 0: if (d) CHX_RFIRST(true, 0); else CHX_RFIRST(false, 0); break;
+    case 2: if (d) CHX_RFIRST(true, 2); else CHX_RFIRST(false, 2); break;
+    case 3: if (d) CHX_RFIRST(true, 3); else CHX_RFIRST(false, 3); break;
+    case 4: if (d) CHX_RFIRST(true, 4); else CHX_RFIRST(false, 4); break;
+    default: return hipErrorInvalidValue;  // a refined step leaves 2 .. 4 solutions
+  }
+#undef CHX_RFIRST
   return hipGetLastError();
 }
 

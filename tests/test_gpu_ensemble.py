@@ -283,3 +283,26 @@ def test_refined_ensemble_mixed_passes_matches_single_runs(chx, orc):
         for _ in range(n):
             ref = orc.ch_step(ref, L, L, D, g, dt)
         assert rel(fields[r].cpu().numpy(), ref) < n * (1e-10 if p > 1 else 1e-8), (r, p)
+
+
+def test_energy_decay_rate_per_run(chx, orc):
+    """Ch.7's beta = -(t/F) dF/dt of every run from the ensemble's per-step
+    diagnostics, on the device, against the oracle's differences of the same
+    energies (Ch.7 asymmetric mixture U[0.4, 0.6], so F decays)."""
+    dt = 0.1 * L / 256
+    runs = [(64, 64, 1200), (128, 128, 1201), (256, 128, 1202)]
+    n = 12
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, 1.0, 0.01, dt) for (nx, ny, _) in runs])
+    fields = [torch.tensor(inputs.asymmetric_mixture(ny, nx, seed), device="cuda")
+              for (nx, ny, seed) in runs]
+    diag = torch.zeros(len(runs) * 2 * (n + 1), dtype=torch.float64, device="cuda")
+    print("[case] decay rate of 3 runs", flush=True)
+    chx.ch_ensemble_step(ens, fields, nsteps=n, diag_out=diag)
+    t0 = 5.0
+    beta = chx.ch_energy_decay_rate(diag, len(runs), n + 1, t0, dt)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy().reshape(len(runs), n + 1, 2)
+    b = beta.cpu().numpy().reshape(len(runs), n + 1)
+    for r in range(len(runs)):
+        ref = orc.energy_decay_rate(d[r, :, 1], t0, dt)
+        assert np.max(np.abs(b[r] - ref)) <= 1e-12 * np.max(np.abs(ref)), r

@@ -198,3 +198,31 @@ def test_graph_replays_match_eager(chx, ny, nx, dtype, passes):
     chx.ch_adi_step(he, ref, nsteps=k)
     torch.cuda.synchronize()
     assert torch.equal(other, ref)
+
+
+def test_tuning_cache_file_is_reused_across_processes(tmp_path):
+    """The autotuned choices of a size go to the tuning cache file once; a
+    second process reads them back (the file keeps one line) and picks the
+    same choices; results are bitwise identical whatever was chosen."""
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tuning.txt"
+    code = ("import math, sys; sys.path.insert(0, %r); "
+            "from paper_2101_06550_amd import chx; chx.load(); "
+            "h = chx.ch_create(2048, 1024, 2 * math.pi, 2 * math.pi, 1.0, 0.01, 1e-5); "
+            "print([chx.ch_get_tuning(h, w) for w in (0, 2, 3)])") % os.getcwd()
+    env = dict(os.environ, CHX_TUNE_CACHE=str(cache))
+    env.pop("CHX_AUTOTUNE", None)
+    outs = []
+    for run in range(2):
+        print(f"[case] tuning cache process {run}", flush=True)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(r.stdout.strip().splitlines()[-1])
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("chx-tune-1 gfx"), lines
+        assert " 2048 1024 " in lines[0]
+    assert outs[0] == outs[1]
+    assert lines[0].split()[-3:] == [v.strip() for v in outs[0].strip("[]").split(",")]

@@ -79,13 +79,16 @@ def test_steps_in_one_call_vs_oracle(chx, orc):
 
 @pytest.mark.parametrize("ny,nx,dt", [(96, 192, 1e-4), (32, 100, 1e-4), (64, 4096, 1e-6),
                                       (256, 61, 1e-4), (128, 120, 1e-4), (64, 64, 1e-4),
-                                      (2048, 2000, 1e-6)])
+                                      (2048, 2000, 1e-6), (2016, 2048, 1e-6),
+                                      (64, 61440, 1e-6)])
 def test_steps_across_chunks_and_segments(chx, orc, ny, nx, dt):
     """Several steps (the state update and deferred column correction of
     every later step) on grids with 1 to 64 32-row chunks and widths that are
     and are not multiples of 60 columns, from two independent rough states;
-    the largest grid (64 chunks x 34 segments of 60 columns, the last one
-    ragged) runs the column-streaming kernel, the others the tile kernel."""
+    the three largest grids run the column-streaming kernel (2048 x 2000: 64
+    chunks walked two per wave, 34 segments, the last one ragged; 2016 x 2048:
+    63 chunks, one per wave; 64 x 61440: the two chunks of a column in one
+    wave, each the other's neighbour), the others the tile kernel."""
     c0 = inputs.noise_field(ny, nx, 21)
     cp0 = inputs.noise_field(ny, nx, 22)
     h = p2(chx, nx, ny, dt=dt)
@@ -146,3 +149,33 @@ def test_large_run_two_steps(chx, orc):
     print(f"P2 8192 two-step error {err:.3e}", flush=True)
     assert err < 2 * tol(n, n, g=0.001, dt=1e-6), f"P2 8192^2 two steps: {err:.3e}"
     assert rel(cp.cpu().numpy(), ref_prev) < tol(n, n, g=0.001, dt=1e-6)
+
+
+def test_table31_on_the_gpu(chx):
+    """Ch.3 Table 3.1 with the GPU's thesis scheme: C0 = 1e-6 tanh(r - pi), r
+    from the box centre, D = 1, gamma = 0.01, T = 10, dt = 0.1 dx (whole
+    steps), E_N of Ch.2 eq. 2:converge2D; the printed E_128 = 0.1510,
+    E_256 = 0.0246, E_512 = 0.0116 and the rates 2.6187, 1.0785 within 1 %."""
+    fields = {}
+    for n in (64, 128, 256, 512):
+        dx = L / n
+        steps = int(round(10.0 / (0.1 * dx)))
+        x = np.arange(n) * dx
+        r = np.sqrt((x[None, :] - math.pi) ** 2 + (x[:, None] - math.pi) ** 2)
+        c0 = 1e-6 * np.tanh(r - math.pi)
+        h = p2(chx, n, n, dt=10.0 / steps)
+        c, cp = torch.tensor(c0, device="cuda"), torch.tensor(c0, device="cuda")
+        print(f"[case] table 3.1 N={n}: {steps} steps", flush=True)
+        chx.ch_adi_step_p2(h, c, cp, nsteps=steps)
+        torch.cuda.synchronize()
+        fields[n] = c.cpu().numpy()
+
+    def e_n(n):
+        f, g = fields[n], fields[n // 2]
+        avg = 0.25 * (f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2])
+        return float(np.mean(np.abs(avg - g)))
+    e = {n: e_n(n) for n in (128, 256, 512)}
+    for n, printed in ((128, 0.1510), (256, 0.0246), (512, 0.0116)):
+        assert abs(e[n] - printed) <= 0.01 * printed, (n, e[n])
+    assert abs(math.log2(e[128] / e[256]) - 2.6187) <= 0.01 * 2.6187
+    assert abs(math.log2(e[256] / e[512]) - 1.0785) <= 0.01 * 1.0785

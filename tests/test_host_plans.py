@@ -300,6 +300,19 @@ def test_ensemble_extras_reject_bad_arguments_on_host(lib):
     assert lib.ch_ensemble_step(None, None, None, 1, None, None, 0, 0, None) == chx.CHX_EINVAL
 
 
+def test_decay_rate_rejects_bad_arguments_on_host(lib):
+    """Too few states, a non-positive dt and overlapping buffers are refused
+    before anything is launched (the pointers are never dereferenced)."""
+    import ctypes
+    p = ctypes.c_void_p(1 << 20)
+    q = ctypes.c_void_p(1 << 30)
+    assert lib.ch_energy_decay_rate(p, 1, 2, 0.0, 0.1, q, None) == chx.CHX_EINVAL
+    assert lib.ch_energy_decay_rate(p, 1, 8, 0.0, 0.0, q, None) == chx.CHX_EINVAL
+    assert lib.ch_energy_decay_rate(p, 1, 8, 0.0, 0.1, None, None) == chx.CHX_EINVAL
+    inside = ctypes.c_void_p((1 << 20) + 64)  # within the 16 doubles of diag
+    assert lib.ch_energy_decay_rate(p, 1, 8, 0.0, 0.1, inside, None) == chx.CHX_EINVAL
+
+
 def test_stencil_binding_rejects_mismatched_layouts():
     """One leading dimension serves input and output: a padded input with a
     packed output (or any other mismatch) is refused before the library is

@@ -223,3 +223,21 @@ def test_k1_closed_forms(orc):
     assert abs(orc.ch_k1(c, L, L) - ref) < 1e-12
     # a rectangular box rescales the wavenumbers
     assert abs(orc.ch_k1(np.cos(3 * X), 4 * np.pi, L) - 1.5) < 1e-12
+
+
+def test_energy_decay_rate_pins(orc):
+    """Ch.7 eq. 7:betaN, beta = -(t/F) dF/dt of a sampled F(t): exact for a
+    quadratic F (the second-order differences are exact there), the LSW value
+    1/3 for F = A t^(-1/3) (Ch.7's late-time proposition) to O(dt^2), and too
+    few samples refused."""
+    t0, dt = 2.0, 0.01
+    t = t0 + dt * np.arange(50)
+    F = 3.0 * t ** (-1.0 / 3.0)
+    beta = orc.energy_decay_rate(F, t0, dt)
+    assert np.max(np.abs(beta - 1.0 / 3.0)) < 1e-5
+    a, b, c = 2.0, 0.3, -0.01
+    F = a + b * t + c * t ** 2
+    assert np.allclose(orc.energy_decay_rate(F, t0, dt), -t * (b + 2 * c * t) / F,
+                       rtol=0, atol=1e-12)
+    with pytest.raises(ValueError):
+        orc.energy_decay_rate([1.0, 2.0], 0.0, 0.1)

@@ -211,8 +211,21 @@ def pin_simpson(o):
     return abs(o.simpson_mean(c, 2) - ref) < 1e-15
 
 
+def pin_decay_rate_quadratic(o):
+    """Ch.7 beta = -(t/F) dF/dt: for a quadratic F(t) the second-order
+    differences are exact, so beta_k equals -t_k F'(t_k) / F(t_k) at every
+    sample, the end samples included."""
+    t0, dt = 0.7, 0.05
+    a, b, c = 5.0, -1.3, 0.4
+    t = t0 + dt * np.arange(12)
+    F = a + b * t + c * t ** 2
+    exact = -t * (b + 2 * c * t) / F
+    return np.max(np.abs(o.energy_decay_rate(F, t0, dt) - exact)) < 1e-12
+
+
 ALL_PINS = [pin_penta_dense, pin_tri_dense, pin_rows_dense, pin_step_fft, pin_energy_closed_form,
-            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook, pin_simpson]
+            pin_stencil_asymmetric, pin_p2_step_fft, pin_batch1d_modes, pin_cook, pin_simpson,
+            pin_decay_rate_quadratic]
 
 MUTANTS = {
     "drop_cross_term": ("r[(size_t)j * nx + i] = cc + D * dt * lap - 2.0 * D * gamma * dt * cross;",
@@ -264,6 +277,11 @@ MUTANTS = {
                                      "ry[(size_t)j * nx + i] = rad * cos(two_pi * u2);"),
     "simpson_weights_swapped": ("const double wi = (i % 2 == 0) ? 2.0 / 3.0 : 4.0 / 3.0;",
                                 "const double wi = (i % 2 == 0) ? 4.0 / 3.0 : 2.0 / 3.0;"),
+    "decay_rate_forward_difference": ("dFdt = (F[k + 1] - F[k - 1]) / (2.0 * dt);",
+                                      "dFdt = (F[k + 1] - F[k]) / dt;"),
+    "decay_rate_time_from_zero": ("const double t = t0 + k * dt;", "const double t = k * dt;"),
+    "decay_rate_end_first_order": ("dFdt = (-3.0 * F[0] + 4.0 * F[1] - F[2]) / (2.0 * dt);",
+                                   "dFdt = (F[1] - F[0]) / dt;"),
     "stencil_transposed_weights": ("acc = acc + w[(q + top) * wx + (p + left)] * v;",
                                    "acc = acc + w[(p + left) * (top + bottom + 1) + (q + top)] * v;"),
 }
