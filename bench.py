@@ -43,11 +43,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def column_pass_bytes(nx, ny):
-    """Algorithmic HBM bytes of one column-pass launch: read the state once,
-    write the chunk-interior solution, write 4 separator parts per chunk."""
+def column_pass_bytes(nx, ny, m=CHUNK):
+    """Algorithmic HBM bytes of one column-pass launch with m-point chunks:
+    read the state once, write the chunk-interior solution, write 4
+    separator parts per chunk."""
     n = nx * ny
-    sc = ny // CHUNK
+    sc = ny // m
     return 8 * n + 8 * nx * (ny - 2 * sc) + 8 * 4 * sc * nx
 
 
@@ -55,8 +56,8 @@ def row_pass_bytes(nx, ny):
     return 16 * nx * ny
 
 
-def reduced_bytes(nx, ny):
-    sc = ny // CHUNK
+def reduced_bytes(nx, ny, m=CHUNK):
+    sc = ny // m
     return 8 * 4 * sc * nx + 8 * 2 * sc * nx
 
 
@@ -358,13 +359,11 @@ def stencil_throughput(chx, torch, n=8192, reps=20):
     output separate: the 5-point Laplacian, the same applied to c^3 - c (the
     non-linear Cahn-Hilliard term), a full 5 x 5 stencil, the 8th-order second
     derivative in x of the Ch.3 example (non-periodic) and a full 9 x 9
-    stencil.  Algorithmic bytes: 16 per point (each input read once, each
+    stencil, on FP64 arrays and again on FP32 arrays (names ending _f32).
+    Algorithmic bytes: 16 (FP32: 8) per point (each input read once, each
     output written once); flops: 2 per weight per point (every weight of the
     rectangle is applied, zeros included)."""
     from paper_2101_06550_amd import inputs
-    dev = dict(dtype=torch.float64, device="cuda")
-    x = torch.tensor(inputs.uniform(11, (n, n), -1, 1), **dev)
-    y = torch.empty_like(x)
     lap = [0, 1, 0, 1, -4, 1, 0, 1, 0]
     d8 = [-1 / 560, 8 / 315, -1 / 5, 8 / 5, -205 / 72, 8 / 5, -1 / 5, 8 / 315, -1 / 560]
     cases = {"laplacian_5pt": (lap, (1, 1, 1, 1), True, 0),
@@ -373,25 +372,34 @@ def stencil_throughput(chx, torch, n=8192, reps=20):
              "x_8th_order_nonperiodic": (d8, (4, 4, 0, 0), False, 0),
              "full_9x9": (list(inputs.uniform(13, (81,), -1, 1)), (4, 4, 4, 4), True, 0)}
     out = {"n": n}
-    for name, (w, ext, per, pm) in cases.items():
-        def run():
-            chx.stencil2d_apply(x, y, w, *ext, periodic=per, premap=pm)
-        run()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+    finite = True
+    # FP64 arrays (16 B per point), then the same stencils on FP32 arrays
+    # (dtype CHX_F32: 8 B per point, sums in FP32)
+    for dt_, tag, prec in ((torch.float64, "", "fp64"), (torch.float32, "_f32", "fp32")):
+        x = torch.tensor(inputs.uniform(11, (n, n), -1, 1), dtype=dt_, device="cuda")
+        y = torch.empty_like(x)
+        bpp = 2.0 * x.element_size()
+        for name, (w, ext, per, pm) in cases.items():
+            def run():
+                chx.stencil2d_apply(x, y, w, *ext, periodic=per, premap=pm)
             run()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        gbs = 16.0 * n * n / (ms * 1e-3) / 1e9
-        out[name] = {"ms": round(ms, 4), "points_per_s": n * n / (ms * 1e-3),
-                     "effective_GBps": round(gbs, 1),
-                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                     "fp64_TFLOPs": round(2.0 * len(w) * n * n / (ms * 1e-3) / 1e12, 2)}
-    out["finite"] = bool(torch.isfinite(y).all())
-    del x, y
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = bpp * n * n / (ms * 1e-3) / 1e9
+            out[name + tag] = {"ms": round(ms, 4), "points_per_s": n * n / (ms * 1e-3),
+                               "effective_GBps": round(gbs, 1),
+                               "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                               f"{prec}_TFLOPs": round(2.0 * len(w) * n * n / (ms * 1e-3) / 1e12,
+                                                       2)}
+        finite = finite and bool(torch.isfinite(y).all())
+        del x, y
+    out["finite"] = finite
     return out
 
 
@@ -690,6 +698,8 @@ def tuning_sweep(chx, torch, n=8192, steps=20):
                      "row_split": chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)}}
     choices = [("shape", k, -1) for k in range(chx.CHX_NUM_REDUCED_SHAPES)] + \
               [("split", 0, k) for k in range(chx.CHX_NUM_SPLIT_SHAPES)]
+    for what in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):  # split forms need 32
+        chx.ch_set_tuning(h, CHUNK, what=what)
     for kind, shape, split in choices:
         chx.ch_set_tuning(h, shape)
         chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
@@ -840,7 +850,7 @@ def main():
                                 "65536 systems",
                   "batch1d": "batched 1D schemes (Cahn-Hilliard 2^20 x 256, hyperdiffusion "
                              "65536 x 1024)",
-                  "stencil": "standalone 2D stencils on 8192 x 8192, FP64"}
+                  "stencil": "standalone 2D stencils on 8192 x 8192, FP64 and FP32"}
         cmd = ("rocprofv3 --kernel-trace --stats -d " + os.path.relpath(tdir) + " -o run "
                "--output-format csv -- python3 bench.py --only " + only)
         summarize_leg(tdir, out, titles.get(only, only), cmd, args.trace_note)
@@ -936,7 +946,9 @@ def main():
                      row_pass_bytes(n, n) - sep_rows + reduced_bytes(n, n), None]
     else:
         names = ["column_pass", "column_separators", "row_pass", "finalize_and_diag"]
-        bytes_per = [column_pass_bytes(n, n), reduced_bytes(n, n), row_pass_bytes(n, n), None]
+        mcol = chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_CHUNK)
+        bytes_per = [column_pass_bytes(n, n, mcol), reduced_bytes(n, n, mcol),
+                     row_pass_bytes(n, n), None]
     phases = {}
     for k, nm in enumerate(names):
         if phase_n[k] == 0:
@@ -1049,7 +1061,9 @@ def main():
         "tuning": {"separator_kernel_shape": chx.ch_get_tuning(h),
                    "row_split_shape": split,
                    "single_workgroup_path": chx.ch_get_tuning(h, chx.CHX_TUNE_SMALL_PATH),
-                   "column_tile_order": chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_ORDER)},
+                   "column_tile_order": chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_ORDER),
+                   "column_chunk": chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_CHUNK),
+                   "row_chunk": chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_CHUNK)},
         "checks": {"mass_drift_rel_L1": mass_drift, "energy_monotone": energy_monotone},
         "extra": extra,
     }

@@ -405,6 +405,17 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   tuning choice changes.  0 (the default) launches every kernel from the
  *   host.  Handles with Cahn-Hilliard-Cook forcing and the single-workgroup
  *   path always launch directly.  Results are bitwise identical either way.
+ * CHX_TUNE_COLUMN_CHUNK, CHX_TUNE_ROW_CHUNK: length of the chunks that the
+ *   multi-kernel FP64 path's column and row solves are partitioned into
+ *   (each chunk swept on its own, its last two unknowns the separators
+ *   that the separator system couples): 32, or 16
+ *   where the length is a multiple of 16 (and for rows at most 4096 points).
+ *   Shorter chunks halve the serial sweep of each workgroup and double the
+ *   separators; on small grids, where one round of workgroups covers the
+ *   field, that wins.  Chosen by the same timing as the tile shape; 16 needs
+ *   the row split -1 (and the split needs 32 in both directions: CHX_EINVAL
+ *   otherwise).  The two lengths solve the same systems with different
+ *   rounding: results agree to rounding, not bitwise.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown
  *   `what` or a value out of range.  Not to be called while work of h is
@@ -418,6 +429,8 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 #define CHX_TUNE_COLUMN_ORDER 3
 #define CHX_NUM_COLUMN_ORDERS 3
 #define CHX_TUNE_GRAPH 4
+#define CHX_TUNE_COLUMN_CHUNK 5
+#define CHX_TUNE_ROW_CHUNK 6
 int ch_get_tuning(chx_ch h, int what, int* value);
 int ch_set_tuning(chx_ch h, int what, int value);
 

@@ -666,6 +666,8 @@ CHX_NUM_SPLIT_SHAPES = 3
 CHX_TUNE_COLUMN_ORDER = 3
 CHX_NUM_COLUMN_ORDERS = 3
 CHX_TUNE_GRAPH = 4
+CHX_TUNE_COLUMN_CHUNK = 5
+CHX_TUNE_ROW_CHUNK = 6
 
 
 def ch_get_tuning(h: CH, what: int = CHX_TUNE_REDUCED_SHAPE) -> int:

@@ -39,6 +39,12 @@ struct BandPlan {
   bool has_chunk = false;
   DevWhole dwhole;
   DevChunk dchunk;
+  // 16-point chunks as well (the ADI step's plans, when n allows): twice the
+  // parallelism and half the serial sweep of the 32-point chunks, for grids
+  // whose passes are too small to fill the chip
+  ChunkTables chunk16;
+  bool has_chunk16 = false;
+  DevChunk dchunk16;
   void* dmem = nullptr;
   int device = 0;
 
@@ -57,6 +63,10 @@ int upload(BandPlan* p) {
   const size_t o_c32 = off; off = align256(off + p->chunk.rec32.size() * sizeof(float));
   const size_t o_b = off; off = align256(off + p->chunk.blocks.size() * sizeof(double));
   const size_t o_b32 = off; off = align256(off + p->chunk.blocks32.size() * sizeof(float));
+  const size_t o_h = off; off = align256(off + p->chunk16.rec.size() * sizeof(double));
+  const size_t o_h32 = off; off = align256(off + p->chunk16.rec32.size() * sizeof(float));
+  const size_t o_hb = off; off = align256(off + p->chunk16.blocks.size() * sizeof(double));
+  const size_t o_hb32 = off; off = align256(off + p->chunk16.blocks32.size() * sizeof(float));
   if (hipGetDevice(&p->device) != hipSuccess) return CHX_EHIP;
   if (hipMalloc(&p->dmem, off > 0 ? off : 256) != hipSuccess) {
     p->dmem = nullptr;
@@ -72,6 +82,10 @@ int upload(BandPlan* p) {
   put(o_c32, p->chunk.rec32.data(), p->chunk.rec32.size() * sizeof(float));
   put(o_b, p->chunk.blocks.data(), p->chunk.blocks.size() * sizeof(double));
   put(o_b32, p->chunk.blocks32.data(), p->chunk.blocks32.size() * sizeof(float));
+  put(o_h, p->chunk16.rec.data(), p->chunk16.rec.size() * sizeof(double));
+  put(o_h32, p->chunk16.rec32.data(), p->chunk16.rec32.size() * sizeof(float));
+  put(o_hb, p->chunk16.blocks.data(), p->chunk16.blocks.size() * sizeof(double));
+  put(o_hb32, p->chunk16.blocks32.data(), p->chunk16.blocks32.size() * sizeof(float));
   if (hipMemcpy(p->dmem, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
     return CHX_EHIP;
   auto* base = static_cast<unsigned char*>(p->dmem);
@@ -93,6 +107,21 @@ int upload(BandPlan* p) {
     p->dchunk.rec32 = reinterpret_cast<const float*>(base + o_c32);
     p->dchunk.blocks = reinterpret_cast<const double*>(base + o_b);
     p->dchunk.blocks32 = reinterpret_cast<const float*>(base + o_b32);
+    p->dchunk.M = p->chunk.m;
+  }
+  if (p->has_chunk16) {
+    DevChunk& d = p->dchunk16;
+    d.n = p->n;
+    d.P = p->P;
+    d.S = p->chunk16.S;
+    d.dlo = p->chunk16.dlo;
+    d.dcount = p->chunk16.dcount;
+    d.M = p->chunk16.m;
+    for (int k = 0; k < 5; ++k) d.coef[k] = p->coef[k];
+    d.rec = reinterpret_cast<const double*>(base + o_h);
+    d.rec32 = reinterpret_cast<const float*>(base + o_h32);
+    d.blocks = reinterpret_cast<const double*>(base + o_hb);
+    d.blocks32 = reinterpret_cast<const float*>(base + o_hb32);
   }
   return CHX_OK;
 }
@@ -133,7 +162,8 @@ bool finite_all(const double* v, int n) {
 
 // Build (host) and upload (device) a band plan.
 template <class PlanT>
-int make_plan(int P, int n, const double* coef, int periodic, PlanT** out) {
+int make_plan(int P, int n, const double* coef, int periodic, PlanT** out,
+              bool chunk16 = false) {
   if (!out) return CHX_EINVAL;
   *out = nullptr;
   const int nmin = (P == 2) ? 5 : 3;
@@ -155,6 +185,11 @@ int make_plan(int P, int n, const double* coef, int periodic, PlanT** out) {
     rc = build_chunk(band, n, kChunk, &p->chunk);
     p->has_chunk = (rc == CHX_OK);
     if (rc == CHX_EINVAL) rc = CHX_OK;  // shape not eligible: keep the whole-system path
+  }
+  if (rc == CHX_OK && chunk16 && p->has_chunk && n % 16 == 0) {
+    const int rc16 = build_chunk(band, n, 16, &p->chunk16);
+    p->has_chunk16 = (rc16 == CHX_OK);
+    if (rc16 != CHX_OK && rc16 != CHX_EINVAL) rc = rc16;
   }
   if (rc == CHX_OK) rc = upload(p);
   if (rc != CHX_OK) {
@@ -302,6 +337,8 @@ struct chx_ch_s {
   int split = -1;         // split row pass shape (-1: plain separators + rows,
                           // kSplitOverlap: separators beside the interior rows)
   int col_order = 0;      // tile order of the column pass (CHX_TUNE_COLUMN_ORDER)
+  int mcol = kChunk;      // chunk length of the column solves (32, or 16: CHX_TUNE_COLUMN_CHUNK)
+  int mrow = kChunk;      // chunk length of the row solves (CHX_TUNE_ROW_CHUNK)
   // the second stream of the overlapped schedule and its fork / join events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -779,6 +816,7 @@ struct Tuned {
   int red_shape = 0;
   int split = -1;
   int col_order = 0;
+  int mcol = kChunk, mrow = kChunk;  // chunk lengths of the column and row solves
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, Tuned> g_tune_cache;
@@ -797,9 +835,13 @@ size_t device_max_lds() {
 // then the separator rows on a second stream, the interior rows beside them.
 constexpr int kSplitOverlap = -2;
 
+// Rows of the row plan solved in 16-point chunks: tables built and a row of
+// at most 256 chunks (one workgroup per row group).
+bool rows16_fit(const BandPlan* px) { return px->has_chunk16 && px->dchunk16.S <= 256; }
+
 // Persistent tuning cache: a text file with one line per tuned size,
-//   chx-tune-1 <arch> <nx> <ny> <column plan S dlo dcount> <row plan S dlo dcount>
-//       <separator shape> <row split> <column order>
+//   chx-tune-2 <arch> <nx> <ny> <column plan S dlo dcount> <row plan S dlo dcount>
+//       <separator shape> <row split> <column order> <column chunk> <row chunk>
 // at $CHX_TUNE_CACHE, else $XDG_CACHE_HOME/chx/tuning.txt, else
 // $HOME/.cache/chx/tuning.txt; CHX_TUNE_CACHE=0 turns it off.  Lines are only
 // appended; the last line of a key wins; unreadable lines are skipped.
@@ -830,7 +872,7 @@ std::string device_arch() {
 std::string tune_key_text(const std::string& arch, int nx, int ny, const DevChunk& cy,
                           const DevChunk& cx) {
   char buf[256];
-  std::snprintf(buf, sizeof buf, "chx-tune-1 %s %d %d %d %d %d %d %d %d", arch.c_str(), nx, ny,
+  std::snprintf(buf, sizeof buf, "chx-tune-2 %s %d %d %d %d %d %d %d %d", arch.c_str(), nx, ny,
                 cy.S, cy.dlo, cy.dcount, cx.S, cx.dlo, cx.dcount);
   return buf;
 }
@@ -845,11 +887,12 @@ bool tune_cache_lookup(const std::string& path, const std::string& key, Tuned* o
         line[key.size()] != ' ')
       continue;
     Tuned t;
-    if (std::sscanf(line.c_str() + key.size(), " %d %d %d", &t.red_shape, &t.split,
-                    &t.col_order) != 3)
+    if (std::sscanf(line.c_str() + key.size(), " %d %d %d %d %d", &t.red_shape, &t.split,
+                    &t.col_order, &t.mcol, &t.mrow) != 5)
       continue;
     if (t.red_shape < 0 || t.red_shape >= kNumRedShapes || t.col_order < 0 ||
-        t.col_order >= CHX_NUM_COLUMN_ORDERS || t.split < -2 || t.split >= kNumSplitShapes)
+        t.col_order >= CHX_NUM_COLUMN_ORDERS || t.split < -2 || t.split >= kNumSplitShapes ||
+        (t.mcol != 16 && t.mcol != kChunk) || (t.mrow != 16 && t.mrow != kChunk))
       continue;
     *out = t;
     found = true;
@@ -860,7 +903,9 @@ bool tune_cache_lookup(const std::string& path, const std::string& key, Tuned* o
 void tune_cache_store(const std::string& path, const std::string& key, const Tuned& t) {
   if (path.empty()) return;
   std::ofstream outf(path, std::ios::app);
-  if (outf) outf << key << ' ' << t.red_shape << ' ' << t.split << ' ' << t.col_order << '\n';
+  if (outf)
+    outf << key << ' ' << t.red_shape << ' ' << t.split << ' ' << t.col_order << ' ' << t.mcol
+         << ' ' << t.mrow << '\n';
 }
 
 Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
@@ -878,10 +923,14 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
     // a split or overlap choice needs the handle's shapes to allow it
     if (best.split >= 0 && !split_fits(c, px->dchunk, best.split)) best.split = -1;
     if (best.split == kSplitOverlap && !rows_subsets_fit(px->dchunk)) best.split = -1;
+    if (best.mcol == 16 && !py->has_chunk16) best.mcol = kChunk;
+    if (best.mrow == 16 && !rows16_fit(px)) best.mrow = kChunk;
     g_tune_cache[key] = best;
     return best;
   }
-  const size_t rho_bytes = (size_t)c.S * 4 * nx * sizeof(double);
+  // buffers sized for the shorter chunks where the plans have them
+  const int Smax = py->has_chunk16 ? py->dchunk16.S : c.S;
+  const size_t rho_bytes = (size_t)Smax * 4 * nx * sizeof(double);
   const size_t dst_bytes = (size_t)ny * nx * sizeof(double);
   double *rho = nullptr, *dst = nullptr;
   hipStream_t st = nullptr;
@@ -972,7 +1021,7 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   // the zeroed field as a previous step's buffer (a second field buffer
   // takes its output)
   double *ybuf = nullptr, *part = nullptr;
-  const long nparts = ch_column_pass_blocks(nx, c.S);
+  const long nparts = ch_column_pass_blocks(nx, Smax);
   if (ok && hipMalloc(&ybuf, dst_bytes) == hipSuccess &&
       hipMalloc(&part, (size_t)nparts * 2 * sizeof(double)) == hipSuccess) {
     ChCoef K{};
@@ -986,6 +1035,34 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
         best_col = ms;
         best.col_order = order;
       }
+    }
+    // chunk lengths: the whole step (column pass, separators, rows) with
+    // 32- or 16-point chunks in each direction where the plans allow them;
+    // the split and overlapped row orders are 32-point forms
+    if (ok && (py->has_chunk16 || rows16_fit(px))) {
+      float best_step = -1.f;
+      Tuned keep = best;
+      for (int mc : {kChunk, 16}) {
+        for (int mr : {kChunk, 16}) {
+          if ((mc == 16 && !py->has_chunk16) || (mr == 16 && !rows16_fit(px))) continue;
+          DevChunk cy = mc == 16 ? py->dchunk16 : py->dchunk;
+          const DevChunk& cx = mr == 16 ? px->dchunk16 : px->dchunk;
+          cy.red_shape = keep.red_shape;
+          const float ms = time_it([&]() {
+            hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho,
+                                                 K, part, st, nullptr, keep.col_order);
+            if (e == hipSuccess)
+              e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, st);
+            return e == hipSuccess ? launch_rows_lds<2>(cx, ybuf, nx, ny, st) : e;
+          });
+          if (ok && (best_step < 0.f || ms < best_step)) {
+            best_step = ms;
+            best.mcol = mc;
+            best.mrow = mr;
+          }
+        }
+      }
+      if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
     }
   }
   if (st) (void)hipStreamSynchronize(st);
@@ -1035,8 +1112,11 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   const double sy = wgt * q.D * q.gamma * q.dt / (dy * dy * dy * dy);
   const double cxs[5] = {sx, -4 * sx, 1 + 6 * sx, -4 * sx, sx};
   const double cys[5] = {sy, -4 * sy, 1 + 6 * sy, -4 * sy, sy};
-  int rc = make_plan(2, q.nx, cxs, 1, &h->px);
-  if (rc == CHX_OK) rc = make_plan(2, q.ny, cys, 1, &h->py);
+  // FP64 P1 handles also carry 16-point chunk tables: on small grids the
+  // shorter serial sweeps may beat the 32-point ones (the tuner decides)
+  const bool c16 = q.scheme == CHX_SCHEME_P1 && q.dtype == CHX_F64;
+  int rc = make_plan(2, q.nx, cxs, 1, &h->px, c16);
+  if (rc == CHX_OK) rc = make_plan(2, q.ny, cys, 1, &h->py, c16);
   if (rc != CHX_OK) {
     delete h;
     return rc;
@@ -1088,11 +1168,14 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     }
     h->part_count = std::max(rstep_parts(q.nx, q.ny), diag_parts);
   } else if (h->fast) {
+    // separator parts and column-pass partials sized for the shorter chunks
+    // where the column plan has them
+    const int S = h->py->has_chunk16 ? h->py->chunk16.S : h->py->chunk.S;
     h->off_b0 = off; off += field;
     h->off_b1 = off; off += field;
     h->off_rho = off;
-    off += align256((size_t)h->py->chunk.S * 4 * q.nx * sizeof(double));
-    h->part_count = std::max(ch_column_pass_blocks(q.nx, h->py->chunk.S), diag_parts);
+    off += align256((size_t)S * 4 * q.nx * sizeof(double));
+    h->part_count = std::max(ch_column_pass_blocks(q.nx, S), diag_parts);
   } else {
     h->off_r = off; off += field;
     if (q.scheme == CHX_SCHEME_P2) {  // a second right-hand side, a third state
@@ -1129,6 +1212,8 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
     h->py->dchunk.red_shape = t.red_shape;
     h->split = t.split;
     h->col_order = t.col_order;
+    h->mcol = t.mcol;
+    h->mrow = t.mrow;
   }
   *out = h;
   return CHX_OK;
@@ -1142,6 +1227,8 @@ int ch_get_tuning(chx_ch h, int what, int* value) {
     case CHX_TUNE_ROW_SPLIT: *value = h->split; return CHX_OK;
     case CHX_TUNE_COLUMN_ORDER: *value = h->col_order; return CHX_OK;
     case CHX_TUNE_GRAPH: *value = h->use_graph ? 1 : 0; return CHX_OK;
+    case CHX_TUNE_COLUMN_CHUNK: *value = h->mcol; return CHX_OK;
+    case CHX_TUNE_ROW_CHUNK: *value = h->mrow; return CHX_OK;
     default: return CHX_EINVAL;
   }
 }
@@ -1163,6 +1250,8 @@ int ch_set_tuning(chx_ch h, int what, int value) {
       h->small = value == 1;
       return CHX_OK;
     case CHX_TUNE_ROW_SPLIT:
+      // the split and overlapped row orders are forms of the 32-point chunks
+      if (value != -1 && (h->mcol != kChunk || h->mrow != kChunk)) return CHX_EINVAL;
       if (value == kSplitOverlap) {
         if (!h->side) return CHX_EINVAL;
       } else if (value != -1 && !(h->fast && h->prm.dtype == CHX_F64 &&
@@ -1170,6 +1259,16 @@ int ch_set_tuning(chx_ch h, int what, int value) {
         return CHX_EINVAL;
       }
       h->split = value;
+      return CHX_OK;
+    case CHX_TUNE_COLUMN_CHUNK:
+      if (value != kChunk && !(value == 16 && h->fast && h->py->has_chunk16)) return CHX_EINVAL;
+      if (value != kChunk && h->split != -1) return CHX_EINVAL;
+      h->mcol = value;
+      return CHX_OK;
+    case CHX_TUNE_ROW_CHUNK:
+      if (value != kChunk && !(value == 16 && h->fast && rows16_fit(h->px))) return CHX_EINVAL;
+      if (value != kChunk && h->split != -1) return CHX_EINVAL;
+      h->mrow = value;
       return CHX_OK;
     case CHX_TUNE_COLUMN_ORDER:
       if (value < 0 || value >= CHX_NUM_COLUMN_ORDERS) return CHX_EINVAL;
@@ -1339,7 +1438,12 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     const double* src = c;
     long lds = ld;
     bool recon = false;
-    const long colblocks = ch_column_pass_blocks(nx, h->py->chunk.S);
+    // the chunk plans of the two directions (the separator shape is chosen
+    // on the 32-point plan and applies to either)
+    DevChunk cy = h->mcol == 16 ? h->py->dchunk16 : h->py->dchunk;
+    cy.red_shape = h->py->dchunk.red_shape;
+    const DevChunk& cx = h->mrow == 16 ? h->px->dchunk16 : h->px->dchunk;
+    const long colblocks = ch_column_pass_blocks(nx, cy.S);
     for (int n = 0; n < nsteps && ok(); ++n) {
       if (tm) tm->step(n);
       double* dst = buf[n & 1];
@@ -1347,7 +1451,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       if (ok()) {
         B();
         const SmallNoise nz = noise_of(n);  // Cahn-Hilliard-Cook draws of this step
-        e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, h->py->dchunk, rho,
+        e = launch_ch_column_pass(recon, diag, src, lds, dst, nx, nx, ny, cy, rho,
                                   h->K, part, st, noise ? &nz : nullptr, h->col_order);
         E(0);
       }
@@ -1383,14 +1487,14 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
       } else {
         if (ok()) {
           B();
-          e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, st,
+          e = launch_reduced_il<2>(cy, rho, nx, dst, nx, cy.M, cy.M - 2, st,
                                    diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
                                    diag ? diag_out + 2 * n : nullptr);
           E(1);
         }
         if (ok()) {
           B();
-          e = launch_rows_lds<2>(h->px->dchunk, dst, nx, ny, st);
+          e = launch_rows_lds<2>(cx, dst, nx, ny, st);
           E(2);
         }
       }
@@ -1402,7 +1506,7 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
     if (ok()) {
       // the state written out with the final diagnostics in the same pass
       B();
-      e = launch_ch_column_final(src, lds, c, ld, nx, ny, h->py->dchunk, h->K, part,
+      e = launch_ch_column_final(src, lds, c, ld, nx, ny, cy, h->K, part,
                                  diag_out ? diag_out + 2 * nsteps : nullptr, st, h->col_order);
       E(3);
     }

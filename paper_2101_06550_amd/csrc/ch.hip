@@ -59,10 +59,11 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 // State value at row-position p (0..M-1) of a chunk for one column, given V
 // at that row and the separator rows (row-solved values T) of the previous
 // chunk (tp) and of the chunk itself (to).  Separator rows are the state.
-template <bool RECON>
+template <bool RECON, int MM = kChunk>
 __device__ __forceinline__ double recon_value(double v, int p, const double* __restrict__ rec,
                                               const double (&tp)[P], const double (&to)[P]) {
-  if (!RECON || p >= MI) return v;
+  constexpr int MMI = MM - P;
+  if (!RECON || p >= MMI) return v;
   double x = v;
 #pragma unroll
   for (int a = 0; a < P; ++a) x = x - rec[p * 8 + 4 + a] * tp[a] - rec[p * 8 + 6 + a] * to[a];
@@ -77,15 +78,15 @@ __device__ __forceinline__ double recon_value(double v, int p, const double* __r
 // lane-0 and lane-63 state values are exchanged through LDS (one barrier),
 // and the two columns just outside the block are loaded and reconstructed by
 // 68 threads of the block before the barrier.
-template <bool RECON>
+template <bool RECON, int MM = kChunk>
 __device__ __forceinline__ double recon_row(double v, int q, const double* __restrict__ rec,
                                             const double (&tp)[P], const double (&to)[P],
                                             const double (&tn)[P]) {
-  // q = 0: last row of chunk kc-1 (separator); q = 1..M: own row q-1;
-  // q = M+1: row 0 of chunk kc+1
+  // q = 0: last row of chunk kc-1 (separator); q = 1..MM: own row q-1;
+  // q = MM+1: row 0 of chunk kc+1
   if (q == 0) return v;
-  if (q == M + 1) return recon_value<RECON>(v, 0, rec, to, tn);
-  return recon_value<RECON>(v, q - 1, rec, tp, to);
+  if (q == MM + 1) return recon_value<RECON, MM>(v, 0, rec, to, tn);
+  return recon_value<RECON, MM>(v, q - 1, rec, tp, to);
 }
 
 // Cahn-Hilliard-Cook forcing (Ch.7): q = dt eta, eta = amp div rho with
@@ -123,16 +124,17 @@ __device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigne
 // state itself written to ybuf (the caller's array) -- no right-hand side, no
 // sweep; one streaming pass instead of a correction pass and a separate
 // diagnostics pass over the result.
-template <bool RECON, bool DIAG, bool NOISE = false, bool FINAL = false>
+template <bool RECON, bool DIAG, bool NOISE = false, bool FINAL = false, int MM = kChunk>
 __device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
                                                  double* __restrict__ ybuf, long ldy, int nx,
                                                  int ny, int Sc, const double* __restrict__ rec,
                                                  const BandT<double>& bd, double* __restrict__ rho,
                                                  const ChCoef& K, double* __restrict__ slot,
                                                  int cb, int kc, const SmallNoise& nz = {}) {
+  constexpr int MMI = MM - P;
   __shared__ double red[8];
-  __shared__ double edge[10][M + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
-  __shared__ double nedge[NOISE ? 4 : 1][M];  // rho_x right of wave w's last lane
+  __shared__ double edge[10][MM + 2];  // 0: outer left, 1: outer right, 2+w: lane 0, 6+w: lane 63
+  __shared__ double nedge[NOISE ? 4 : 1][MM];  // rho_x right of wave w's last lane
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nseg = nx >> 6;
   const int seg0 = cb * 4;
@@ -140,57 +142,57 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
   const bool live = wave < nw;
   const int i = (seg0 + wave) * 64 + lane;
   const int kcm = (kc - 1 + Sc) % Sc, kcp = (kc + 1) % Sc;
-  const long rowm1 = ((long)kc * M - 1 + ny) % ny;
-  const long rowp = ((long)kc * M + M) % ny;
+  const long rowm1 = ((long)kc * MM - 1 + ny) % ny;
+  const long rowp = ((long)kc * MM + MM) % ny;
 
-  // the two columns outside the block: thread t < 2(M+2) takes side t/(M+2), row t%(M+2)
-  if (threadIdx.x < 2 * (M + 2)) {
-    const int side = threadIdx.x / (M + 2), q = threadIdx.x - side * (M + 2);
+  // the two columns outside the block: thread t < 2(MM+2) takes side t/(MM+2), row t%(MM+2)
+  if (threadIdx.x < 2 * (MM + 2)) {
+    const int side = threadIdx.x / (MM + 2), q = threadIdx.x - side * (MM + 2);
     const int ic = side == 0 ? (seg0 * 64 - 1 + nx) % nx : (seg0 * 64 + nw * 64) % nx;
-    const long row = q == 0 ? rowm1 : (q == M + 1 ? rowp : (long)kc * M + q - 1);
+    const long row = q == 0 ? rowm1 : (q == MM + 1 ? rowp : (long)kc * MM + q - 1);
     double v = src[row * lds + ic];
     if (RECON) {
       double tp[P], to[P], tn[P];
 #pragma unroll
       for (int a = 0; a < P; ++a) {
-        tp[a] = src[((long)kcm * M + MI + a) * lds + ic];
-        to[a] = src[((long)kc * M + MI + a) * lds + ic];
-        tn[a] = src[((long)kcp * M + MI + a) * lds + ic];
+        tp[a] = src[((long)kcm * MM + MMI + a) * lds + ic];
+        to[a] = src[((long)kc * MM + MMI + a) * lds + ic];
+        tn[a] = src[((long)kcp * MM + MMI + a) * lds + ic];
       }
-      v = recon_row<RECON>(v, q, rec, tp, to, tn);
+      v = recon_row<RECON, MM>(v, q, rec, tp, to, tn);
     }
     edge[side][q] = v;
   }
-  if (NOISE && (int)threadIdx.x < nw * M) {
-    const int w = threadIdx.x / M, p = threadIdx.x - w * M;
+  if (NOISE && (int)threadIdx.x < nw * MM) {
+    const int w = threadIdx.x / MM, p = threadIdx.x - w * MM;
     double rx, ry;
-    cook_pair(nz.seed_state, nz.step0, kc * M + p, ((seg0 + w + 1) * 64) % nx, nx, ny, rx, ry);
+    cook_pair(nz.seed_state, nz.step0, kc * MM + p, ((seg0 + w + 1) * 64) % nx, nx, ny, rx, ry);
     nedge[w][p] = rx;
   }
 
   double tp[P] = {0, 0}, to[P] = {0, 0}, tn[P] = {0, 0};
-  double X[M + 2];
+  double X[MM + 2];
   if (live) {
     if (RECON) {
 #pragma unroll
       for (int a = 0; a < P; ++a) {
-        tp[a] = src[((long)kcm * M + MI + a) * lds + i];
-        to[a] = src[((long)kc * M + MI + a) * lds + i];
-        tn[a] = src[((long)kcp * M + MI + a) * lds + i];
+        tp[a] = src[((long)kcm * MM + MMI + a) * lds + i];
+        to[a] = src[((long)kc * MM + MMI + a) * lds + i];
+        tn[a] = src[((long)kcp * MM + MMI + a) * lds + i];
       }
     }
     X[0] = src[rowm1 * lds + i];
 #pragma unroll
-    for (int p = 0; p < M; ++p) X[p + 1] = src[((long)kc * M + p) * lds + i];
-    X[M + 1] = src[rowp * lds + i];
+    for (int p = 0; p < MM; ++p) X[p + 1] = src[((long)kc * MM + p) * lds + i];
+    X[MM + 1] = src[rowp * lds + i];
 #pragma unroll
-    for (int q = 0; q < M + 2; ++q) X[q] = recon_row<RECON>(X[q], q, rec, tp, to, tn);
+    for (int q = 0; q < MM + 2; ++q) X[q] = recon_row<RECON, MM>(X[q], q, rec, tp, to, tn);
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < M + 2; ++q) edge[2 + wave][q] = X[q];
+      for (int q = 0; q < MM + 2; ++q) edge[2 + wave][q] = X[q];
     } else if (lane == 63) {
 #pragma unroll
-      for (int q = 0; q < M + 2; ++q) edge[6 + wave][q] = X[q];
+      for (int q = 0; q < MM + 2; ++q) edge[6 + wave][q] = X[q];
     }
   }
   __syncthreads();
@@ -204,16 +206,16 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
     // Rows are processed strictly in order: an empty volatile asm on the next
     // row's value (volatile asms keep their order) and on each row's result
     // stop the compiler from computing every row's neighbours up front.
-    double f[M];
+    double f[MM];
     const double eps = bd.c[0];
     double xc_m = X[0];
     double xl_m = dpp_from_left(xc_m, es[0]), xr_m = dpp_from_right(xc_m, es[0]);
     double xc_c = X[1];
     double xl_c = dpp_from_left(xc_c, es[1]), xr_c = dpp_from_right(xc_c, es[1]);
     double nrx = 0.0, nry = 0.0;  // this column's forcing pair at the current row
-    if (NOISE) cook_pair(nz.seed_state, nz.step0, kc * M, i, nx, ny, nrx, nry);
+    if (NOISE) cook_pair(nz.seed_state, nz.step0, kc * MM, i, nx, ny, nrx, nry);
 #pragma unroll
-    for (int p = 0; p < M; ++p) {
+    for (int p = 0; p < MM; ++p) {
       double xc_p = X[p + 2];
       double en = es[p + 2];
       asm volatile("" : "+v"(xc_p), "+v"(en));
@@ -230,7 +232,7 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
       const double dyy_e = xr_p + xr_m - 2.0 * xr_c;
       double r = xc_c + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
       if (NOISE && !FINAL) {
-        const int j = kc * M + p, jn = (j + 1 == ny) ? 0 : j + 1;
+        const int j = kc * MM + p, jn = (j + 1 == ny) ? 0 : j + 1;
         double rx_n, ry_n;
         cook_pair(nz.seed_state, nz.step0, jn, i, nx, ny, rx_n, ry_n);
         const double rx_e = dpp_from_right(nrx, nedge[wave][p]);
@@ -246,10 +248,10 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
         esum += 0.25 * w * w + K.half_gamma * (gx * gx + gy * gy);
       }
       if (FINAL) {
-        __builtin_nontemporal_store(xc_c, &ybuf[((long)kc * M + p) * ldy + i]);
+        __builtin_nontemporal_store(xc_c, &ybuf[((long)kc * MM + p) * ldy + i]);
         if (DIAG) asm volatile("" : "+v"(msum), "+v"(esum));
       } else {
-        if (p < MI) {  // forward sweep step of the chunk interior (g overwrites f)
+        if (p < MMI) {  // forward sweep step of the chunk interior (g overwrites f)
           if (p >= 2) r = r - eps * f[p - 2];
           if (p >= 1) r = r - rec[p * 8 + 1] * f[p - 1];
           r = r * rec[p * 8 + 0];
@@ -264,20 +266,20 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
     if (!FINAL) {
       // back sweep of the interior (y = R^{-1} g)
 #pragma unroll
-      for (int p = MI - 1; p >= 0; --p) {
+      for (int p = MMI - 1; p >= 0; --p) {
         double v = f[p];
-        if (p + 2 < MI) v = v - rec[p * 8 + 3] * f[p + 2];
-        if (p + 1 < MI) v = v - rec[p * 8 + 2] * f[p + 1];
+        if (p + 2 < MMI) v = v - rec[p * 8 + 3] * f[p + 2];
+        if (p + 1 < MMI) v = v - rec[p * 8 + 2] * f[p + 1];
         f[p] = v;
       }
       double pa[P], pb[P];
-      chunk_parts<P, M, double>(f, bd, pa, pb);
+      chunk_parts<P, MM, double>(f, bd, pa, pb);
       // streamed stores (non-temporal): the row pass reads y back from HBM; on
       // gfx950 this keeps the stores out of the way of the loads (measured:
       // both passes faster than with ordinary stores, the loads stay ordinary)
 #pragma unroll
-      for (int p = 0; p < MI; ++p)
-        __builtin_nontemporal_store(f[p], &ybuf[((long)kc * M + p) * ldy + i]);
+      for (int p = 0; p < MMI; ++p)
+        __builtin_nontemporal_store(f[p], &ybuf[((long)kc * MM + p) * ldy + i]);
 #pragma unroll
       for (int a = 0; a < P; ++a) {
         rho[((long)kc * 2 * P + a) * nx + i] = pa[a];
@@ -318,7 +320,7 @@ __device__ __forceinline__ void column_tile(int order, long b, int ncb, int Sc, 
   }
 }
 
-template <bool RECON, bool DIAG, bool NOISE>
+template <bool RECON, bool DIAG, bool NOISE, int MM>
 __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__ src, long lds,
                                                       double* __restrict__ ybuf, long ldy, int nx,
                                                       int ny, int Sc,
@@ -329,13 +331,13 @@ __global__ __launch_bounds__(256) void ch_column_pass(const double* __restrict__
   int cb, kc;
   column_tile(order, blockIdx.x, ncb, Sc, cb, kc);
   const long slot = (long)kc * ncb + cb;
-  column_pass_body<RECON, DIAG, NOISE>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
-                                       DIAG ? part + 2 * slot : nullptr, cb, kc, nz);
+  column_pass_body<RECON, DIAG, NOISE, false, MM>(src, lds, ybuf, ldy, nx, ny, Sc, rec, bd, rho, K,
+                                                  DIAG ? part + 2 * slot : nullptr, cb, kc, nz);
 }
 
 // The pass after the last step: reconstruct the state, write it to dst and
 // (DIAG) leave one (mass, energy) partial per block in part.
-template <bool DIAG>
+template <bool DIAG, int MM>
 __global__ __launch_bounds__(256) void ch_column_final(const double* __restrict__ src, long lds,
                                                        double* __restrict__ dst, long ldd, int nx,
                                                        int ny, int Sc,
@@ -346,8 +348,8 @@ __global__ __launch_bounds__(256) void ch_column_final(const double* __restrict_
   column_tile(order, blockIdx.x, ncb, Sc, cb, kc);
   const long slot = (long)kc * ncb + cb;
   const BandT<double> bd{};
-  column_pass_body<true, DIAG, false, true>(src, lds, dst, ldd, nx, ny, Sc, rec, bd, nullptr, K,
-                                            DIAG ? part + 2 * slot : nullptr, cb, kc);
+  column_pass_body<true, DIAG, false, true, MM>(src, lds, dst, ldd, nx, ny, Sc, rec, bd, nullptr,
+                                                K, DIAG ? part + 2 * slot : nullptr, cb, kc);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,9 +504,15 @@ hipError_t launch_ch_column_pass(bool recon, bool diag, const double* src, long 
   const int Sc = cy.S;
   dim3 grid((unsigned)((long)ncb * Sc));
   const SmallNoise z = nz ? *nz : SmallNoise{};
-#define CHX_COLPASS(R, D, N)                                                                      \
-  hipLaunchKernelGGL((ch_column_pass<R, D, N>), grid, dim3(256), 0, st, src, lds, ybuf, ldy, nx, \
-                     ny, Sc, cy.rec, bd, rho, K, part, z, ncb, order)
+#define CHX_COLPASS(R, D, N)                                                                    \
+  do {                                                                                          \
+    if (cy.M == 16)                                                                             \
+      hipLaunchKernelGGL((ch_column_pass<R, D, N, 16>), grid, dim3(256), 0, st, src, lds, ybuf, \
+                         ldy, nx, ny, Sc, cy.rec, bd, rho, K, part, z, ncb, order);             \
+    else                                                                                        \
+      hipLaunchKernelGGL((ch_column_pass<R, D, N, kChunk>), grid, dim3(256), 0, st, src, lds,   \
+                         ybuf, ldy, nx, ny, Sc, cy.rec, bd, rho, K, part, z, ncb, order);       \
+  } while (0)
   if (nz) {
     if (recon && diag) CHX_COLPASS(true, true, true);
     else if (recon) CHX_COLPASS(true, false, true);
@@ -528,15 +536,19 @@ hipError_t launch_ch_column_final(const double* src, long lds, double* dst, long
                                   double* diag_out, hipStream_t st, int order) {
   const int ncb = ((nx >> 6) + 3) / 4;
   dim3 grid((unsigned)((long)ncb * cy.S));
+#define CHX_COLFIN(D, MM_)                                                                       \
+  hipLaunchKernelGGL((ch_column_final<D, MM_>), grid, dim3(256), 0, st, src, lds, dst, ldd, nx, ny, \
+                     cy.S, cy.rec, K, part, ncb, order)
   if (diag_out) {
-    hipLaunchKernelGGL((ch_column_final<true>), grid, dim3(256), 0, st, src, lds, dst, ldd, nx, ny,
-                       cy.S, cy.rec, K, part, ncb, order);
+    if (cy.M == 16) CHX_COLFIN(true, 16);
+    else CHX_COLFIN(true, kChunk);
     hipLaunchKernelGGL(ch_diag_final, dim3(1), dim3(256), 0, st, part, (long)grid.x, K.dxdy,
                        diag_out);
   } else {
-    hipLaunchKernelGGL((ch_column_final<false>), grid, dim3(256), 0, st, src, lds, dst, ldd, nx,
-                       ny, cy.S, cy.rec, K, part, ncb, order);
+    if (cy.M == 16) CHX_COLFIN(false, 16);
+    else CHX_COLFIN(false, kChunk);
   }
+#undef CHX_COLFIN
   return hipGetLastError();
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
+
 namespace chx {
 
 // Device copy of WholeTables (one-thread-per-system kernels).
@@ -14,11 +16,12 @@ struct DevWhole {
   const float* rec32 = nullptr;  // device, mi * 8
 };
 
-// Device copy of ChunkTables (chunked kernels, chunk length kChunk).
+// Device copy of ChunkTables (chunked kernels, chunk length M).
 struct DevChunk {
   int n = 0, P = 2, S = 0, dlo = 0, dcount = 0;
+  int M = kChunk;                   // chunk length (32, or 16 for the step's small-grid plans)
   double coef[5] = {};
-  const double* rec = nullptr;      // device, (kChunk - P) * 8
+  const double* rec = nullptr;      // device, (M - P) * 8
   const double* blocks = nullptr;   // device, dcount * 4
   const float* rec32 = nullptr;
   const float* blocks32 = nullptr;

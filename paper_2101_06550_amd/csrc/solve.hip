@@ -1211,9 +1211,14 @@ template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
   const int R = 256 / c.S;
   const long ngroups = ((long)rows + R - 1) / R;
-  hipLaunchKernelGGL((row_solve_lds<P, kChunk, double, false>), dim3((unsigned)ngroups), dim3(256),
-                     0, st, x, ld, x, ld, rows, c.n, c.S, R, c.rec, band_of<double>(c.coef),
-                     c.blocks, c.dlo, c.dcount);
+  if (P == 2 && c.M == 16)
+    hipLaunchKernelGGL((row_solve_lds<P, 16, double, false>), dim3((unsigned)ngroups), dim3(256),
+                       0, st, x, ld, x, ld, rows, c.n, c.S, R, c.rec, band_of<double>(c.coef),
+                       c.blocks, c.dlo, c.dcount);
+  else
+    hipLaunchKernelGGL((row_solve_lds<P, kChunk, double, false>), dim3((unsigned)ngroups),
+                       dim3(256), 0, st, x, ld, x, ld, rows, c.n, c.S, R, c.rec,
+                       band_of<double>(c.coef), c.blocks, c.dlo, c.dcount);
   return hipGetLastError();
 }
 

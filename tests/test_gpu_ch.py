@@ -181,7 +181,7 @@ def test_single_workgroup_path_not_settable_where_it_does_not_fit(chx):
     with pytest.raises(chx.ChxError):
         chx.ch_set_tuning(h, 1, what=chx.CHX_TUNE_SMALL_PATH)
     with pytest.raises(chx.ChxError):
-        chx.ch_set_tuning(h, 0, what=5)
+        chx.ch_set_tuning(h, 0, what=99)
 
 
 @pytest.mark.parametrize("ny,nx,dt", [(64, 4096, 1e-6), (96, 8192, 1e-6), (512, 8192, 1e-6)])
@@ -193,6 +193,10 @@ def test_split_row_pass_bitwise(chx, orc, ny, nx, dt):
     h = chx.ch_create(nx, ny, L, L, 1.0, 0.001, dt)
     tuned = chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_SPLIT)
     assert chx.CHX_ROW_SPLIT_OVERLAP <= tuned < chx.CHX_NUM_SPLIT_SHAPES
+    chunks = [chx.ch_get_tuning(h, w) for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK)]
+    assert tuned == -1 or chunks == [32, 32]  # the split forms are 32-point forms
+    for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):
+        chx.ch_set_tuning(h, 32, what=w)
     ref = None
     # -2: separators and separator rows on a second stream beside the interior rows
     for split in [-1, chx.CHX_ROW_SPLIT_OVERLAP] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
@@ -208,6 +212,9 @@ def test_split_row_pass_bitwise(chx, orc, ny, nx, dt):
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), split
     chx.ch_set_tuning(h, tuned, what=chx.CHX_TUNE_ROW_SPLIT)
+    if tuned == -1:
+        for w, m in zip((chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK), chunks):
+            chx.ch_set_tuning(h, m, what=w)
     c = torch.tensor(c0, device="cuda")
     chx.ch_adi_step(h, c, nsteps=1)
     torch.cuda.synchronize()

@@ -77,6 +77,8 @@ def test_every_row_order_matches_oracle_over_steps(chx, orc):
     ny, nx, g, dt, k = 96, 8192, 0.001, 1e-6, 3
     c0 = inputs.noise_field(ny, nx, 66)
     h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):  # split forms need 32
+        chx.ch_set_tuning(h, 32, what=w)
     ref = oracle_states(orc, c0, g, dt, k)[k]
     for split in [-1, chx.CHX_ROW_SPLIT_OVERLAP] + list(range(chx.CHX_NUM_SPLIT_SHAPES)):
         print(f"[case] row order {split}, {k} steps {ny}x{nx}", flush=True)
@@ -88,16 +90,21 @@ def test_every_row_order_matches_oracle_over_steps(chx, orc):
         assert err < k * 1e-12, f"row order {split}: {err:.3e}"
 
 
-def test_forced_steps_in_one_call_match_oracle(chx, orc):
+@pytest.mark.parametrize("mchunk", [32, 16])
+def test_forced_steps_in_one_call_match_oracle(chx, orc, mchunk):
     """Cahn-Hilliard-Cook forcing drawn inside the column pass of every step,
-    three steps in one call on the multi-kernel path."""
+    three steps in one call on the multi-kernel path, with 32- and 16-point
+    chunks in both directions."""
     ny = nx = 1024
     dt, sigma, k = 1e-5, 1e-12, 3
     c0 = inputs.noise_field(ny, nx, 67)
     h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, dt)
+    chx.ch_set_tuning(h, -1, what=chx.CHX_TUNE_ROW_SPLIT)
+    for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):
+        chx.ch_set_tuning(h, mchunk, what=w)
     chx.ch_set_noise(h, sigma, seed=91, step0=4)
     c = torch.tensor(c0, device="cuda")
-    print("[case] forced 3 steps 1024x1024", flush=True)
+    print(f"[case] forced 3 steps 1024x1024 chunks {mchunk}", flush=True)
     chx.ch_adi_step(h, c, nsteps=k)
     torch.cuda.synchronize()
     ref = orc.ch_step_cook(c0, L, L, 1.0, 0.01, dt, sigma, 91, step0=4, nsteps=k)
@@ -161,6 +168,73 @@ def test_column_orders_bitwise_and_match_oracle(chx, orc, ny, nx):
         chx.ch_set_tuning(h, chx.CHX_NUM_COLUMN_ORDERS, what=chx.CHX_TUNE_COLUMN_ORDER)
 
 
+# (ny, nx): 16-point chunks = ny / 16 down the columns, nx / 16 along the rows
+# (gamma dt / dx^4 kept moderate: the row systems of 4096 points at gamma =
+# 0.01, dt = 1e-5 have condition numbers near 3e5, and either chunk length
+# then misses the 1e-12 bound by rounding alone)
+CHUNK_CASES = [(1024, 1024, 0.01, 1e-5, 3, 71),   # 64 x 64 short chunks, 4 column blocks
+               (96, 320, 0.01, 1e-5, 3, 72),      # 6 x 20, last column block one wave
+               (64, 2048, 0.01, 1e-5, 2, 73),     # 4 x 128
+               (160, 576, 0.01, 1e-5, 4, 74),     # 10 x 36, last block one wave
+               (288, 4096, 0.001, 1e-6, 2, 75)]   # 18 x 256: the longest row of 16-point chunks
+
+
+@pytest.mark.parametrize("ny,nx,g,dt,k,seed", CHUNK_CASES)
+def test_chunk_lengths_match_oracle(chx, orc, ny, nx, g, dt, k, seed):
+    """CHX_TUNE_COLUMN_CHUNK / CHX_TUNE_ROW_CHUNK: 32- and 16-point chunks in
+    each direction (the 16-point separator system has twice the separators
+    and its own decay window), several steps in one call with the deferred
+    column correction and the per-step diagnostics, against the oracle; the
+    four choices agree to rounding."""
+    c0 = inputs.noise_field(ny, nx, seed)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)
+    chx.ch_set_tuning(h, -1, what=chx.CHX_TUNE_ROW_SPLIT)
+    ref = oracle_states(orc, c0, g, dt, k)
+    l1 = np.sum(np.abs(c0)) * (L / nx) * (L / ny)
+    for mc in (32, 16):
+        for mr in (32, 16):
+            print(f"[case] chunks {mc}/{mr}, {k} steps {ny}x{nx}", flush=True)
+            chx.ch_set_tuning(h, mc, what=chx.CHX_TUNE_COLUMN_CHUNK)
+            chx.ch_set_tuning(h, mr, what=chx.CHX_TUNE_ROW_CHUNK)
+            assert chx.ch_get_tuning(h, chx.CHX_TUNE_COLUMN_CHUNK) == mc
+            assert chx.ch_get_tuning(h, chx.CHX_TUNE_ROW_CHUNK) == mr
+            c = torch.tensor(c0, device="cuda")
+            d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+            chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+            torch.cuda.synchronize()
+            err = rel(c.cpu().numpy(), ref[k])
+            assert err < k * 1e-12, f"chunks {mc}/{mr}: {err:.3e}"
+            dd = d.cpu().numpy().reshape(k + 1, 2)
+            for j in range(k + 1):
+                m, e = orc.ch_mass(ref[j], L, L), orc.ch_energy(ref[j], L, L, g)
+                assert abs(dd[j, 0] - m) <= 1e-12 * l1, (mc, mr, j, dd[j, 0], m)
+                assert abs(dd[j, 1] - e) <= max(j, 1) * 1e-12 * abs(e), (mc, mr, j)
+
+
+def test_chunk_length_choices_refused_where_they_do_not_apply(chx):
+    """16-point rows need at most 256 chunks (4096 points); any chunk other
+    than 16 or 32 is refused; 16 and the split row forms exclude each other."""
+    h = chx.ch_create(8192, 96, L, L, 1.0, 0.001, 1e-6)
+    for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):
+        chx.ch_set_tuning(h, 32, what=w)
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 16, what=chx.CHX_TUNE_ROW_CHUNK)  # 512 chunks a row
+    for bad in (0, 8, 24, 64):
+        for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):
+            with pytest.raises(chx.ChxError):
+                chx.ch_set_tuning(h, bad, what=w)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_ROW_SPLIT)
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 16, what=chx.CHX_TUNE_COLUMN_CHUNK)
+    chx.ch_set_tuning(h, -1, what=chx.CHX_TUNE_ROW_SPLIT)
+    chx.ch_set_tuning(h, 16, what=chx.CHX_TUNE_COLUMN_CHUNK)
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_ROW_SPLIT)
+    with pytest.raises(chx.ChxError):
+        chx.ch_set_tuning(h, chx.CHX_ROW_SPLIT_OVERLAP, what=chx.CHX_TUNE_ROW_SPLIT)
+
+
 @pytest.mark.parametrize("ny,nx,dtype,passes", [(1024, 1024, 0, 0), (96, 320, 0, 0),
                                                 (256, 448, 1, 2)])
 def test_graph_replays_match_eager(chx, ny, nx, dtype, passes):
@@ -211,7 +285,7 @@ def test_tuning_cache_file_is_reused_across_processes(tmp_path):
     code = ("import math, sys; sys.path.insert(0, %r); "
             "from paper_2101_06550_amd import chx; chx.load(); "
             "h = chx.ch_create(2048, 1024, 2 * math.pi, 2 * math.pi, 1.0, 0.01, 1e-5); "
-            "print([chx.ch_get_tuning(h, w) for w in (0, 2, 3)])") % os.getcwd()
+            "print([chx.ch_get_tuning(h, w) for w in (0, 2, 3, 5, 6)])") % os.getcwd()
     env = dict(os.environ, CHX_TUNE_CACHE=str(cache))
     env.pop("CHX_AUTOTUNE", None)
     outs = []
@@ -222,7 +296,7 @@ def test_tuning_cache_file_is_reused_across_processes(tmp_path):
         assert r.returncode == 0, r.stderr[-2000:]
         outs.append(r.stdout.strip().splitlines()[-1])
         lines = cache.read_text().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("chx-tune-1 gfx"), lines
+        assert len(lines) == 1 and lines[0].startswith("chx-tune-2 gfx"), lines
         assert " 2048 1024 " in lines[0]
     assert outs[0] == outs[1]
-    assert lines[0].split()[-3:] == [v.strip() for v in outs[0].strip("[]").split(",")]
+    assert lines[0].split()[-5:] == [v.strip() for v in outs[0].strip("[]").split(",")]

@@ -96,7 +96,7 @@ def test_shape_count_matches_header():
     for name in ("CHX_NUM_REDUCED_SHAPES", "CHX_TUNE_REDUCED_SHAPE", "CHX_TUNE_SMALL_PATH",
                  "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES", "CHX_SCHEME_P1", "CHX_SCHEME_P2",
                  "CHX_TUNE_COLUMN_ORDER", "CHX_NUM_COLUMN_ORDERS", "CHX_NOALLOC_SCRATCH_BYTES",
-                 "CHX_TUNE_GRAPH",
+                 "CHX_TUNE_GRAPH", "CHX_TUNE_COLUMN_CHUNK", "CHX_TUNE_ROW_CHUNK",
                  "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
         m = re.search(r"#define\s+" + name + r"\s+\(?(\d+)(u << (\d+)\))?", text)
         value = int(m.group(1)) << int(m.group(3) or 0) if m else None
