@@ -372,8 +372,10 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  * CHX_TUNE_REDUCED_SHAPE: tile shape of the multi-kernel path's column
  *   separator kernel (0 .. CHX_NUM_REDUCED_SHAPES-1: waves per block x chunks
  *   per wave x window entries staged at once).  ch_create times every
- *   candidate on zeroed scratch buffers of the handle's size and keeps the
- *   fastest; the choices (this shape, the row split and the column order)
+ *   candidate inside whole steps (column pass, separators, rows, for each
+ *   chunk length) on zeroed scratch buffers of the handle's size and keeps
+ *   the fastest; the choices (this shape, the row split, the column order
+ *   and the chunk lengths)
  *   are kept per size for the life of the process and in a tuning cache
  *   file across processes: $CHX_TUNE_CACHE, else
  *   $XDG_CACHE_HOME/chx/tuning.txt, else $HOME/.cache/chx/tuning.txt (one
@@ -423,7 +425,7 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 #define CHX_TUNE_REDUCED_SHAPE 0
 #define CHX_TUNE_SMALL_PATH 1
 #define CHX_TUNE_ROW_SPLIT 2
-#define CHX_NUM_REDUCED_SHAPES 7
+#define CHX_NUM_REDUCED_SHAPES 12
 #define CHX_NUM_SPLIT_SHAPES 3
 #define CHX_ROW_SPLIT_OVERLAP (-2)
 #define CHX_TUNE_COLUMN_ORDER 3
@@ -502,7 +504,10 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s);
  *
  * ch_ensemble_create: nruns >= 1 parameter sets (prm, host array), all with
  *   CHX_SCHEME_P1 and one dtype.  CHX_F64: nx % 64 == 0, ny % 32 == 0,
- *   nx <= 8192, at most 8 distinct (grid, D, gamma, dt) classes.
+ *   nx <= 8192, at most 8 distinct (grid, D, gamma, dt) classes; ensembles
+ *   solve with 32-point chunks, so a run advances bitwise as a single
+ *   handle whose CHX_TUNE_COLUMN_CHUNK and CHX_TUNE_ROW_CHUNK are 32 would
+ *   (to rounding as one tuned to 16).
  *   CHX_F32_REFINED (the precision pattern of ch_create's refined step):
  *   each run as ch_create accepts it (refine_passes may differ between
  *   runs), at most 8 distinct (grid, D, gamma, dt) classes; every phase of

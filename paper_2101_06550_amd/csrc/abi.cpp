@@ -964,8 +964,9 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   };
   DevChunk trial = c;
   float best_ms = -1.f;
+  const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
   for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
-    if (reduced_lds_bytes(shape, 2, sizeof(double), c.dcount, true) > 64 * 1024) continue;
+    if (reduced_lds_bytes(shape, 2, sizeof(double), c.dcount, true) > max_lds) continue;
     trial.red_shape = shape;
     const float ms = time_it([&]() {
       hipError_t e = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st);
@@ -1036,18 +1037,23 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
         best.col_order = order;
       }
     }
-    // chunk lengths: the whole step (column pass, separators, rows) with
-    // 32- or 16-point chunks in each direction where the plans allow them;
-    // the split and overlapped row orders are 32-point forms
-    if (ok && (py->has_chunk16 || rows16_fit(px))) {
-      float best_step = -1.f;
-      Tuned keep = best;
-      for (int mc : {kChunk, 16}) {
-        for (int mr : {kChunk, 16}) {
-          if ((mc == 16 && !py->has_chunk16) || (mr == 16 && !rows16_fit(px))) continue;
-          DevChunk cy = mc == 16 ? py->dchunk16 : py->dchunk;
-          const DevChunk& cx = mr == 16 ? px->dchunk16 : px->dchunk;
-          cy.red_shape = keep.red_shape;
+    // whole steps (column pass, separators, rows) for the separator shape
+    // and the chunk lengths, 32 or 16 points in each direction where the
+    // plans allow them: timed alone on warm buffers, the separator kernel
+    // reads its parts from L2, while in a step it reads what the column pass
+    // has just written on other XCDs, so shapes rank differently there.
+    // The split and overlapped row orders are 32-point forms, kept only
+    // where the 32-point lengths win.
+    float best_step = -1.f;
+    const Tuned keep = best;
+    for (int mc : {kChunk, 16}) {
+      for (int mr : {kChunk, 16}) {
+        if ((mc == 16 && !py->has_chunk16) || (mr == 16 && !rows16_fit(px))) continue;
+        DevChunk cy = mc == 16 ? py->dchunk16 : py->dchunk;
+        const DevChunk& cx = mr == 16 ? px->dchunk16 : px->dchunk;
+        for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
+          if (reduced_lds_bytes(shape, 2, sizeof(double), cy.dcount, true) > max_lds) continue;
+          cy.red_shape = shape;
           const float ms = time_it([&]() {
             hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho,
                                                  K, part, st, nullptr, keep.col_order);
@@ -1059,11 +1065,12 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
             best_step = ms;
             best.mcol = mc;
             best.mrow = mr;
+            best.red_shape = shape;
           }
         }
       }
-      if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
     }
+    if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
   }
   if (st) (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);

@@ -185,6 +185,11 @@ __device__ __forceinline__ void column_pass_body(const double* __restrict__ src,
 #pragma unroll
     for (int p = 0; p < MM; ++p) X[p + 1] = src[((long)kc * MM + p) * lds + i];
     X[MM + 1] = src[rowp * lds + i];
+    // (left to the compiler, these sums sink into the row loop and the
+    // correction table spills through VGPR lanes; computing each where its
+    // load completes removes the spills and a sixth of the vector
+    // instructions but waits for every load before the first row, and
+    // measured 2-3 % slower)
 #pragma unroll
     for (int q = 0; q < MM + 2; ++q) X[q] = recon_row<RECON, MM>(X[q], q, rec, tp, to, tn);
     if (lane == 0) {

@@ -31,7 +31,9 @@ struct DevChunk {
 // Number of candidate tile shapes of the separator kernel, and the LDS one
 // launch of shape `shape` needs (elem = sizeof the sweep type; diag = the
 // launch also finishes the diagnostics sum).
-constexpr int kNumRedShapes = 7;
+constexpr int kNumRedShapes = 12;
+// LDS one workgroup may allocate on gfx950 (160 KB per CU)
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag);
 
 // Split row pass of the ADI step (penta, FP64, rows of 4096 or 8192 points):

@@ -1099,8 +1099,12 @@ hipError_t launch_whole32(const DevWhole& w, double* work, long ss, long es, dou
 struct RedShape {
   int W, G, U;
 };
-constexpr RedShape kRedShapes[kNumRedShapes] = {{8, 4, 4}, {8, 4, 8}, {8, 2, 4}, {4, 8, 4},
-                                                {4, 8, 8}, {4, 4, 4}, {16, 2, 4}};
+// (7, 8: larger windows, whose LDS only gfx950's 160 KB holds at the decay
+// windows of large grids; 9 .. 11: few chunks per block, for small grids
+// where the chunk count is too low to fill the chip with the others)
+constexpr RedShape kRedShapes[kNumRedShapes] = {{8, 4, 4},  {8, 4, 8},  {8, 2, 4}, {4, 8, 4},
+                                                {4, 8, 8},  {4, 4, 4},  {16, 2, 4}, {16, 3, 4},
+                                                {16, 4, 4}, {4, 1, 8},  {4, 2, 8}, {8, 1, 8}};
 
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag) {
   const RedShape& r = kRedShapes[shape];
@@ -1127,11 +1131,11 @@ static hipError_t reduced_any(const DevChunk& c, const T* rho, const T* blocks, 
                               int shape) {
   if (shape < 0 || shape >= kNumRedShapes) shape = 0;
   size_t lds = reduced_lds_bytes(shape, P, sizeof(T), c.dcount, dout != nullptr);
-  if (lds > 64 * 1024 && shape != 0) {
+  if (lds > kMaxLdsBytes && shape != 0) {
     shape = 0;
     lds = reduced_lds_bytes(0, P, sizeof(T), c.dcount, dout != nullptr);
   }
-  if (lds <= 64 * 1024) {
+  if (lds <= kMaxLdsBytes) {
     const RedShape& r = kRedShapes[shape];
     const int kb = r.W * r.G;
     dim3 grid((batch + 63) / 64, (c.S + kb - 1) / kb);
@@ -1145,7 +1149,12 @@ static hipError_t reduced_any(const DevChunk& c, const T* rho, const T* blocks, 
       case 3: CHX_RED(4, 8, 4); break;
       case 4: CHX_RED(4, 8, 8); break;
       case 5: CHX_RED(4, 4, 4); break;
-      default: CHX_RED(16, 2, 4); break;
+      case 6: CHX_RED(16, 2, 4); break;
+      case 7: CHX_RED(16, 3, 4); break;
+      case 8: CHX_RED(16, 4, 4); break;
+      case 9: CHX_RED(4, 1, 8); break;
+      case 10: CHX_RED(4, 2, 8); break;
+      default: CHX_RED(8, 1, 8); break;
     }
 #undef CHX_RED
   } else {

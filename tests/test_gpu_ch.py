@@ -106,21 +106,26 @@ def test_every_separator_shape_gives_identical_steps(chx, orc, ny, nx, dt):
     c0 = inputs.noise_field(ny, nx, 13)
     h = chx.ch_create(nx, ny, L, L, 1.0, 0.01, dt)
     chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)  # the multi-kernel path
+    chx.ch_set_tuning(h, -1, what=chx.CHX_TUNE_ROW_SPLIT)
     assert 0 <= chx.ch_get_tuning(h) < chx.CHX_NUM_REDUCED_SHAPES
-    ref = None
-    for shape in range(chx.CHX_NUM_REDUCED_SHAPES):
-        print(f"[case] separator shape {shape} {ny}x{nx}", flush=True)
-        chx.ch_set_tuning(h, shape)
-        assert chx.ch_get_tuning(h) == shape
-        c = torch.tensor(c0, device="cuda")
-        d = torch.zeros(2 * 4, dtype=torch.float64, device="cuda")
-        chx.ch_adi_step(h, c, nsteps=3, diag_out=d)
-        torch.cuda.synchronize()
-        out = (c.cpu().numpy(), d.cpu().numpy())
-        if ref is None:
-            ref = out
-        else:
-            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
+    ref3 = orc.ch_step(c0, L, L, 1.0, 0.01, dt, nsteps=3)
+    for mc in (32, 16):  # the separator system of either column chunk length
+        chx.ch_set_tuning(h, mc, what=chx.CHX_TUNE_COLUMN_CHUNK)
+        ref = None
+        for shape in range(chx.CHX_NUM_REDUCED_SHAPES):
+            print(f"[case] separator shape {shape} chunks {mc} {ny}x{nx}", flush=True)
+            chx.ch_set_tuning(h, shape)
+            assert chx.ch_get_tuning(h) == shape
+            c = torch.tensor(c0, device="cuda")
+            d = torch.zeros(2 * 4, dtype=torch.float64, device="cuda")
+            chx.ch_adi_step(h, c, nsteps=3, diag_out=d)
+            torch.cuda.synchronize()
+            out = (c.cpu().numpy(), d.cpu().numpy())
+            if ref is None:
+                ref = out
+            else:
+                assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
+        assert rel(ref[0], ref3) < 3e-12, mc
     chx.ch_set_tuning(h, 0)
     c = torch.tensor(c0, device="cuda")
     chx.ch_adi_step(h, c, nsteps=1)

@@ -126,6 +126,8 @@ def test_ensemble_forcing_matches_oracle_and_single_runs(chx, orc):
     assert chx.ch_ensemble_get_noise_step(ens) == 14
     for r, ((nx, ny, D, g, dt), c) in enumerate(zip(ENS_RUNS, c0)):
         h = chx.ch_create(nx, ny, L, L, D, g, dt)
+        for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):  # the ensemble's chunks
+            chx.ch_set_tuning(h, 32, what=w)
         chx.ch_set_noise(h, SIGMA, seed=seeds[r], step0=7)
         s = torch.tensor(c, device="cuda")
         chx.ch_adi_step(h, s, nsteps=1)

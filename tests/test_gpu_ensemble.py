@@ -60,6 +60,8 @@ def test_multistep_bitwise_equals_single_field_path(chx):
     d = diag.cpu().numpy().reshape(len(RUNS), n + 1, 2)
     for r, ((nx, ny, D, g, dt, seed), c) in enumerate(zip(RUNS, c0)):
         h = chx.ch_create(nx, ny, L, L, D, g, dt)
+        for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):  # the ensemble's chunks
+            chx.ch_set_tuning(h, 32, what=w)
         single = torch.tensor(c, device="cuda")
         sd = torch.zeros(2 * (n + 1), dtype=torch.float64, device="cuda")
         chx.ch_adi_step(h, single, nsteps=n, diag_out=sd)
