@@ -1020,7 +1020,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
   for (int k = 0; k < 5; ++k) bd.c[k] = (float)c.coef[k];
   const float* src = reinterpret_cast<const float*>(ws + R.off_y32);
-  float* dst = reinterpret_cast<float*>(ws + R.off_v[pass]);
+  // read from the run table, not from the copy R: an index known only at
+  // run time would place the whole copy in scratch memory (176 bytes stored
+  // and reloaded per thread, more than the thread's share of the rows)
+  float* dst = reinterpret_cast<float*>(ws + runs[it.x].off_v[pass]);
   __shared__ RowLds<2, kChunk, float> sh;
   row_solve_body<2, kChunk, float, false, float, float>(src, R.nx, dst, R.nx, R.ny, R.nx, c.S,
                                                         256 / c.S, c.rec32, bd, c.blocks32, c.dlo,
