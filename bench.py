@@ -259,6 +259,62 @@ def cpu_baseline(c0, L, D, gamma, dt, budget_s=12.0, max_steps=3):
                       f"workload ({el:.1f} s, single thread)"}, first
 
 
+def _oracle_worker(job):
+    """One process of the all-cores oracle timing: the serial oracle on its
+    share of a workload until budget_s has passed.  Returns (units, seconds)."""
+    kind, share, budget_s = job
+    import oracle
+    from paper_2101_06550_amd import inputs
+    orc = oracle.oracle()
+    L = 2 * math.pi
+    units, t0 = 0, time.perf_counter()
+    if kind == "ensemble":  # whole steps of this process's runs, in turn
+        fields = [(n, inputs.noise_field(n, n, 1000 + r)) for r, n in share]
+        while time.perf_counter() - t0 < budget_s:
+            for k, (n, c) in enumerate(fields):
+                fields[k] = (n, orc.ch_step(c, L, L, 1.0, 0.01, 1e-4))
+                units += n * n
+                if time.perf_counter() - t0 >= budget_s:
+                    break
+    else:  # cyclic penta solves, N = 1024, alpha = 0.5: this process's systems as rows
+        a = 0.5
+        coefs = (a, -4 * a, 1 + 6 * a, -4 * a, a)
+        rhs = np.stack([inputs.uniform(2 + s, (1024,), -1, 1) for s in share])
+        while time.perf_counter() - t0 < budget_s:
+            orc.cpenta_lines(rhs, 0, coefs)
+            units += len(share)
+    return units, time.perf_counter() - t0
+
+
+def cpu_all_cores(budget_s=8.0, procs=None):
+    """The serial oracle run as independent processes on all host cores (at
+    most 16), for the two workloads made of independent pieces: the uneven
+    ensemble (each process steps its share of the 256 runs) and the batched
+    cyclic penta solves (each process solves its share of 1024 systems).
+    Aggregate rate = total units / longest process time."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    procs = procs or min(16, os.cpu_count() or 1)
+    sizes = [128] * 96 + [256] * 96 + [512] * 64
+    runs = list(enumerate(sizes))
+    out = {"cores": procs, "kind": "oracle, one serial process per core"}
+    ctx = multiprocessing.get_context("spawn")  # no fork of a process that holds the GPU
+    with ProcessPoolExecutor(max_workers=procs, mp_context=ctx) as ex:
+        for kind, items, unit in (("ensemble", runs, "grid-point updates/s"),
+                                  ("solves", list(range(1024)), "solves/s")):
+            jobs = [(kind, items[p::procs], budget_s) for p in range(procs)]
+            res = list(ex.map(_oracle_worker, jobs))
+            total = sum(u for u, _ in res)
+            el = max(t for _, t in res)
+            out[kind] = {"value": total / el, "unit": unit,
+                         "sample": f"{procs} processes x {budget_s:.0f} s of the serial oracle "
+                                   + ("stepping their share of the 256 runs (96 x 128^2, "
+                                      "96 x 256^2, 64 x 512^2)" if kind == "ensemble" else
+                                      "solving their share of 1024 cyclic penta systems "
+                                      "(N = 1024, alpha = 0.5)")}
+    return out
+
+
 def solve_throughput(chx, torch, reps=10):
     """Standalone batched cyclic penta solves, N = 1024, alpha = 0.5, scaled
     batch of 131072 systems (1 GiB FP64), interleaved and contiguous."""
@@ -832,7 +888,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--only", choices=["solves", "per_system", "ensemble", "precision", "small",
                                        "tuning", "p2",
-                                       "table31", "batch1d", "cook", "stencil"],
+                                       "table31", "batch1d", "cook", "stencil", "cpu_all_cores"],
                     help="run only this side measurement and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the traffic profile and exit")
@@ -877,6 +933,9 @@ def main():
                "--calibrate-copy --steps 20 --warmup 2")
         print(json.dumps(summarize_trace(args.summarize_trace, KERNEL_PROFILE, cmd,
                                          args.trace_note)))
+        return
+    if args.only == "cpu_all_cores":  # host only: the oracle on every core
+        print(json.dumps({"cpu_all_cores": cpu_all_cores()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); ensembles would "
@@ -1071,6 +1130,13 @@ def main():
             errs[tag] = rel_inf(probe.cpu().numpy(), first)
             del probe
         extra["large_one_step_rel_err_vs_oracle"] = errs
+        log("oracle on all host cores (ensemble runs, batched solves)")
+        allc = cpu_all_cores()
+        ens = extra.get("ensemble_256_runs_fp64", {}).get("graph")
+        if ens:
+            allc["ensemble"]["gpu_fp64_over_oracle_all_cores"] = round(
+                ens["updates_per_s"] / allc["ensemble"]["value"], 1)
+        extra["oracle_all_cores"] = allc
 
     res = {
         "metric": METRIC,
