@@ -491,6 +491,129 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                (long)blockIdx.x * R, sh);
 }
 
+// Dense rows in whole groups (R = 256 / S rows of n = S M points per
+// workgroup, rows % R == 0, ld == n): the same solve as row_solve_body,
+// staged through an LDS tile of HALF the group.  All of the group's loads
+// are issued up front into registers; the first half of the group (chunks
+// 0..127) goes through the tile to threads 0..127, then the second half to
+// threads 128..255, and the output leaves the same way in two halves.  At
+// M = 32, 46 KB of LDS instead of 80 KB: three groups per CU instead of two,
+// so more of HBM's latency is covered (three more barriers per group).
+// Arithmetic identical to row_solve_body (bitwise equal results).
+template <int P, int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void row_solve_half(
+    double* x, int S, const double* __restrict__ rec, BandT<double> bd,
+    const double* __restrict__ blocks, int dlo, int dcount) {
+  constexpr int H = 128, NG = 256 * M;  // chunks per half, elements per group
+  __shared__ double tile[H * (M + 1)];
+  __shared__ double rhol[256 * 2 * P];
+  __shared__ double sepl[256 * P];
+  const int t = threadIdx.x;
+  const int r = t / S, k = t - r * S, rs = r * S;  // row in the group, chunk in the row
+  double2* b2 = reinterpret_cast<double2*>(x + (long)blockIdx.x * NG);
+  double2 vin[M / 2];
+#pragma unroll
+  for (int u = 0; u < M / 2; ++u) vin[u] = b2[t + 256 * u];
+  // element e = 2t + 512u of the group lies in half u / (M/4); within its
+  // half at e' = e - half NG/2, LDS slot e' + e' / M
+  double f[M];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int u = half * (M / 4); u < (half + 1) * (M / 4); ++u) {
+      const int e = 2 * t + 512 * (u - half * (M / 4));
+      tile[e + e / M] = vin[u].x;
+      tile[e + 1 + e / M] = vin[u].y;
+    }
+    __syncthreads();
+    if ((t >= H) == (half == 1)) {
+      const int tl = t - half * H;
+#pragma unroll
+      for (int p = 0; p < M; ++p) f[p] = tile[tl * (M + 1) + p];
+    }
+    __syncthreads();
+  }
+  chunk_sweep<P, M, double>(f, rec, bd.c[0]);
+  {
+    double pa[P], pb[P];
+    chunk_parts<P, M, double>(f, bd, pa, pb);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      rhol[a * 256 + t] = pa[a];
+      rhol[(P + a) * 256 + t] = pb[a];
+    }
+  }
+  __syncthreads();
+  {
+    // rho_j = pa_j - pb_{j+1} for the chunks j = k + dlo + u of this row, in
+    // the order of row_solve_body (four at a time, then the rest)
+    double acc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) acc[a] = 0;
+    int u = 0;
+    for (; u + 4 <= dcount; u += 4) {
+      double rr2[4][P];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = wrap_once(k + dlo + u + q, S);
+        const int jn = wrap_once(j + 1, S);
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          rr2[q][a] = rhol[a * 256 + rs + j] - rhol[(P + a) * 256 + rs + jn];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double* B = blocks + (u + q) * 4;
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int c = 0; c < P; ++c) acc[a] = acc[a] + B[a * 2 + c] * rr2[q][c];
+      }
+    }
+    for (; u < dcount; ++u) {
+      const int j = wrap_once(k + dlo + u, S);
+      const int jn = wrap_once(j + 1, S);
+      const double* B = blocks + u * 4;
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int c = 0; c < P; ++c)
+          acc[a] = acc[a] + B[a * 2 + c] * (rhol[c * 256 + rs + j] - rhol[(P + c) * 256 + rs + jn]);
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a) sepl[a * 256 + t] = acc[a];
+  }
+  __syncthreads();
+  {
+    const int kp = wrap_once(k - 1, S);
+    double sp[P], so[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      sp[a] = sepl[a * 256 + rs + kp];
+      so[a] = sepl[a * 256 + t];
+    }
+    chunk_correct<P, M, double>(f, rec, sp, so);
+  }
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if ((t >= H) == (half == 1)) {
+      const int tl = t - half * H;
+#pragma unroll
+      for (int p = 0; p < M; ++p) tile[tl * (M + 1) + p] = f[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = half * (M / 4); u < (half + 1) * (M / 4); ++u) {
+      const int e = 2 * t + 512 * (u - half * (M / 4));
+      double2 v;
+      v.x = tile[e + e / M];
+      v.y = tile[e + 1 + e / M];
+      store_stream(b2 + t + 256 * u, v);  // streamed: not re-read before the next pass
+    }
+    if (half == 0) __syncthreads();
+  }
+}
+
 // FP32 rows in, FP32 rows out (the refined step's row solves of its FP32
 // chunk-solved columns).
 template <int P, int M>
@@ -1219,11 +1342,22 @@ hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, f
   return hipGetLastError();
 }
 
+// Dense rows in whole groups take the half-tile row kernel.
+constexpr bool kRowsHalfTile = true;
+
 template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
   const int R = 256 / c.S;
   const long ngroups = ((long)rows + R - 1) / R;
-  if (P == 2 && c.M == 16)
+  // dense rows in whole groups of 256 chunks: the half-tile kernel
+  const bool half = kRowsHalfTile && P == 2 && ld == c.n && 256 % c.S == 0 && rows % R == 0;
+  if (half && c.M == kChunk)
+    hipLaunchKernelGGL((row_solve_half<2, kChunk>), dim3((unsigned)ngroups), dim3(256), 0, st, x,
+                       c.S, c.rec, band_of<double>(c.coef), c.blocks, c.dlo, c.dcount);
+  else if (half && c.M == 16)
+    hipLaunchKernelGGL((row_solve_half<2, 16>), dim3((unsigned)ngroups), dim3(256), 0, st, x,
+                       c.S, c.rec, band_of<double>(c.coef), c.blocks, c.dlo, c.dcount);
+  else if (P == 2 && c.M == 16)
     hipLaunchKernelGGL((row_solve_lds<P, 16, double, false>), dim3((unsigned)ngroups), dim3(256),
                        0, st, x, ld, x, ld, rows, c.n, c.S, R, c.rec, band_of<double>(c.coef),
                        c.blocks, c.dlo, c.dcount);
