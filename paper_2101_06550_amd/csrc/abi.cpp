@@ -411,6 +411,7 @@ struct chx_ens_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int n_col = 0, n_red = 0, n_row = 0;
   long o_col = 0, o_red = 0, o_row = 0;
+  bool rows_half = false;  // every row item a dense whole group: half-tile row kernel
   size_t ws_total = 0, red_lds = 0;
   long max_points = 0;
   // cached hipGraph of a whole call (nsteps, diag, ws)
@@ -514,7 +515,8 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
     if (e == hipSuccess)
       e = launch_ens_reduced(E->druns, E->hcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
                              E->red_lds, st);
-    if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st);
+    if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st,
+                                             E->rows_half);
   }
   // the states written out with their final diagnostics in the same pass
   if (e == hipSuccess && E->nbig > 0)
@@ -2093,10 +2095,12 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
   }
   E->n_red = (int)(items.size() - E->o_red);
   E->o_row = (long)items.size();
+  E->rows_half = true;
   for (int r : order) {
     const int S = E->runs[r].nx / kChunk, R = 256 / S;
     const int ng = (E->runs[r].ny + R - 1) / R;
     for (int g = 0; g < ng; ++g) add(r, g, 0);
+    if (256 % S != 0 || E->runs[r].ny % R != 0) E->rows_half = false;
   }
   E->n_row = (int)(items.size() - E->o_row);
 

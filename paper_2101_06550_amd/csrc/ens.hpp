@@ -56,7 +56,8 @@ hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const i
                               long diag_stride, size_t lds_bytes, hipStream_t st);
 size_t ens_reduced_lds_bytes(int dcount);
 hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
-                           unsigned char* ws, int step, hipStream_t st);
+                           unsigned char* ws, int step, hipStream_t st,
+                           bool half = false);
 // After the last step, over the column-pass items: every multi-kernel run's
 // state into its field, and with diag_out its (mass, energy) at `index`.
 hipError_t launch_ens_column_final(const EnsRun* runs, const EnsClasses& cls, const int4* items,

@@ -491,6 +491,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                (long)blockIdx.x * R, sh);
 }
 
+// Dense rows in whole groups take the half-tile row kernels.
+constexpr bool kRowsHalfTile = true;
+
 // Dense rows in whole groups (R = 256 / S rows of n = S M points per
 // workgroup, rows % R == 0, ld == n): the same solve as row_solve_body,
 // staged through an LDS tile of HALF the group.  All of the group's loads
@@ -501,16 +504,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
 // so more of HBM's latency is covered (three more barriers per group).
 // Arithmetic identical to row_solve_body (bitwise equal results).
 template <int P, int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void row_solve_half(
-    double* x, int S, const double* __restrict__ rec, BandT<double> bd,
-    const double* __restrict__ blocks, int dlo, int dcount) {
-  constexpr int H = 128, NG = 256 * M;  // chunks per half, elements per group
+__device__ __forceinline__ void row_half_body(double* xg, int S, const double* __restrict__ rec,
+                                              const BandT<double>& bd,
+                                              const double* __restrict__ blocks, int dlo,
+                                              int dcount) {
+  constexpr int H = 128;  // chunks per half
   __shared__ double tile[H * (M + 1)];
   __shared__ double rhol[256 * 2 * P];
   __shared__ double sepl[256 * P];
   const int t = threadIdx.x;
   const int r = t / S, k = t - r * S, rs = r * S;  // row in the group, chunk in the row
-  double2* b2 = reinterpret_cast<double2*>(x + (long)blockIdx.x * NG);
+  double2* b2 = reinterpret_cast<double2*>(xg);
   double2 vin[M / 2];
 #pragma unroll
   for (int u = 0; u < M / 2; ++u) vin[u] = b2[t + 256 * u];
@@ -612,6 +616,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
     }
     if (half == 0) __syncthreads();
   }
+}
+
+template <int P, int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void row_solve_half(
+    double* x, int S, const double* __restrict__ rec, BandT<double> bd,
+    const double* __restrict__ blocks, int dlo, int dcount) {
+  row_half_body<P, M>(x + (long)blockIdx.x * (256 * M), S, rec, bd, blocks, dlo, dcount);
 }
 
 // FP32 rows in, FP32 rows out (the refined step's row solves of its FP32
@@ -1109,6 +1120,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                                            (long)it.y * (256 / c.S), sh);
 }
 
+// The same with the half-tile body, for ensembles whose every run has dense
+// rows in whole groups (bitwise equal to ens_rows).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void ens_rows_half(
+    const EnsRun* __restrict__ runs, EnsClasses cls, const int4* __restrict__ items,
+    unsigned char* ws, int step) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun& R = runs[it.x];
+  const DevChunk& c = cls.c[R.cls].px;
+  BandT<double> bd;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) bd.c[k] = c.coef[k];
+  double* x = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+  row_half_body<2, kChunk>(x + (long)it.y * (256 * kChunk), c.S, c.rec, bd, c.blocks, c.dlo,
+                           c.dcount);
+}
+
 // FP32-refined ensembles: separators of the FP32 column buffer (dout: the
 // pass-0 diagnostics of the run's state at `step`), and FP32 row solves of it
 // into the run's V_pass.
@@ -1178,8 +1205,11 @@ hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const i
 }
 
 hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
-                           unsigned char* ws, int step, hipStream_t st) {
-  hipLaunchKernelGGL(ens_rows, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, step);
+                           unsigned char* ws, int step, hipStream_t st, bool half) {
+  if (half && kRowsHalfTile)
+    hipLaunchKernelGGL(ens_rows_half, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, step);
+  else
+    hipLaunchKernelGGL(ens_rows, dim3(nitems), dim3(256), 0, st, runs, cls, items, ws, step);
   return hipGetLastError();
 }
 
@@ -1341,9 +1371,6 @@ hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, f
                        (long)batch, out, ldo, batch, c.S, c.rec32);
   return hipGetLastError();
 }
-
-// Dense rows in whole groups take the half-tile row kernel.
-constexpr bool kRowsHalfTile = true;
 
 template <int P>
 hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
