@@ -910,6 +910,54 @@ void tune_cache_store(const std::string& path, const std::string& key, const Tun
          << ' ' << t.mrow << '\n';
 }
 
+// Times a launch sequence from a captured graph: reps repetitions of run()
+// captured once, replayed once to warm up and twice between events, the
+// faster replay kept.  On small grids the kernels finish faster than the
+// host can launch them one by one, and a timing of eager launches would
+// measure the host instead; small grids take more repetitions, so that a
+// replay lasts long enough to rank candidates a few per cent apart.
+struct GraphTimer {
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = false;
+  int reps = 5;
+  GraphTimer(long points) {
+    reps = points <= (4L << 20) ? 20 : 5;
+    ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  }
+  ~GraphTimer() {
+    if (st) (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  template <typename F>
+  float time(F&& run) {
+    float best = -1.f;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    ok = ok && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      bool launched = true;
+      for (int k = 0; launched && k < reps; ++k) launched = run() == hipSuccess;
+      ok = hipStreamEndCapture(st, &g) == hipSuccess && launched && g != nullptr;
+    }
+    ok = ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess &&
+         hipGraphLaunch(ge, st) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k) {
+      float ms = -1.f;
+      ok = hipEventRecord(e0, st) == hipSuccess && hipGraphLaunch(ge, st) == hipSuccess &&
+           hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      if (ok && (best < 0.f || ms < best)) best = ms;
+    }
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    return best;
+  }
+};
+
 Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   const DevChunk& c = py->dchunk;
   const auto key = std::make_tuple(nx, ny, c.S, c.dlo, c.dcount);
@@ -935,35 +983,13 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   const size_t rho_bytes = (size_t)Smax * 4 * nx * sizeof(double);
   const size_t dst_bytes = (size_t)ny * nx * sizeof(double);
   double *rho = nullptr, *dst = nullptr;
-  hipStream_t st = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  bool ok = hipMalloc(&rho, rho_bytes) == hipSuccess && hipMalloc(&dst, dst_bytes) == hipSuccess &&
-            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-            hipMemsetAsync(rho, 0, rho_bytes, st) == hipSuccess &&
-            hipMemsetAsync(dst, 0, dst_bytes, st) == hipSuccess;
-  // time(run) = milliseconds of five rounds of run(), captured into a graph
-  // that is replayed once to warm up and once between two events: on small
-  // grids the kernels finish faster than the host can launch them one by one,
-  // and a timing of eager launches would measure the host instead
-  auto time_it = [&](auto&& run) {
-    float ms = -1.f;
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    ok = ok && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-      bool launched = true;
-      for (int k = 0; launched && k < 5; ++k) launched = run() == hipSuccess;
-      ok = hipStreamEndCapture(st, &g) == hipSuccess && launched && g != nullptr;
-    }
-    ok = ok && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess &&
-         hipGraphLaunch(ge, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess &&
-         hipGraphLaunch(ge, st) == hipSuccess && hipEventRecord(e1, st) == hipSuccess &&
-         hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    if (ge) (void)hipGraphExecDestroy(ge);
-    if (g) (void)hipGraphDestroy(g);
-    return ms;
-  };
+  GraphTimer timer((long)nx * ny);
+  hipStream_t st = timer.st;
+  bool& ok = timer.ok;
+  ok = ok && hipMalloc(&rho, rho_bytes) == hipSuccess && hipMalloc(&dst, dst_bytes) == hipSuccess &&
+       hipMemsetAsync(rho, 0, rho_bytes, st) == hipSuccess &&
+       hipMemsetAsync(dst, 0, dst_bytes, st) == hipSuccess;
+  auto time_it = [&](auto&& run) { return timer.time(run); };
   DevChunk trial = c;
   float best_ms = -1.f;
   const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
@@ -1075,9 +1101,6 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
     if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
   }
   if (st) (void)hipStreamSynchronize(st);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (st) (void)hipStreamDestroy(st);
   if (rho) (void)hipFree(rho);
   if (dst) (void)hipFree(dst);
   if (ybuf) (void)hipFree(ybuf);
@@ -1089,6 +1112,70 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   g_tune_cache[key] = best;
   tune_cache_store(cache_path, cache_key, best);
   return best;
+}
+
+// The FP32 separator kernel's tile shape for refined handles, timed inside a
+// refinement pass (residual and column sweep, separators, row solves) on
+// zeroed buffers; cached like tune_step's choices (key "chx-tune-2r ...").
+int tune_refined(const BandPlan* py, const BandPlan* px, int nx, int ny, const double* cxs,
+                 const double* cys) {
+  const DevChunk& c = py->dchunk;
+  static std::map<std::tuple<int, int, int, int, int>, int> cache;
+  const auto key = std::make_tuple(nx, ny, c.S, c.dlo, c.dcount);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const char* env = std::getenv("CHX_AUTOTUNE");
+  if (env && env[0] == '0') return 0;
+  const std::string cache_path = tune_cache_path();
+  std::string cache_key = tune_key_text(device_arch(), nx, ny, c, px->dchunk);
+  cache_key.replace(0, 10, "chx-tune-2r");
+  Tuned t;
+  if (tune_cache_lookup(cache_path, cache_key, &t)) {
+    cache[key] = t.red_shape;
+    return t.red_shape;
+  }
+  const size_t pts = (size_t)nx * ny;
+  const size_t b_r = pts * sizeof(double), b_f = pts * sizeof(float);
+  const size_t b_rho = (size_t)c.S * 4 * nx * sizeof(float);
+  double* r = nullptr;
+  float *y32 = nullptr, *rho = nullptr, *v0 = nullptr, *v1 = nullptr;
+  GraphTimer timer((long)pts);
+  bool& ok = timer.ok;
+  ok = ok && hipMalloc(&r, b_r) == hipSuccess && hipMalloc(&y32, b_f) == hipSuccess &&
+       hipMalloc(&rho, b_rho) == hipSuccess && hipMalloc(&v0, b_f) == hipSuccess &&
+       hipMalloc(&v1, b_f) == hipSuccess && hipMemsetAsync(r, 0, b_r, timer.st) == hipSuccess &&
+       hipMemsetAsync(y32, 0, b_f, timer.st) == hipSuccess &&
+       hipMemsetAsync(rho, 0, b_rho, timer.st) == hipSuccess &&
+       hipMemsetAsync(v0, 0, b_f, timer.st) == hipSuccess &&
+       hipMemsetAsync(v1, 0, b_f, timer.st) == hipSuccess;
+  const float* V[2] = {v0, v1};
+  DevChunk trial = c;
+  float best_ms = -1.f;
+  const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
+  for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
+    if (reduced_lds_bytes(shape, 2, sizeof(float), c.dcount, false) > max_lds) continue;
+    trial.red_shape = shape;
+    const float ms = timer.time([&]() {
+      hipError_t e = launch_rstep_resid(r, V, 1, y32, rho, nx, ny, c, cxs, cys, timer.st);
+      if (e == hipSuccess) e = launch_reduced_il32(trial, rho, nx, y32, nx, timer.st);
+      return e == hipSuccess ? launch_rows_lds_f32(px->dchunk, y32, v1, ny, timer.st) : e;
+    });
+    if (ok && (best_ms < 0.f || ms < best_ms)) {
+      best_ms = ms;
+      t.red_shape = shape;
+    }
+  }
+  if (timer.st) (void)hipStreamSynchronize(timer.st);
+  for (void* p : {(void*)r, (void*)y32, (void*)rho, (void*)v0, (void*)v1})
+    if (p) (void)hipFree(p);
+  if (!ok) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  cache[key] = t.red_shape;
+  tune_cache_store(cache_path, cache_key, t);
+  return t.red_shape;
 }
 
 }  // namespace
@@ -1216,6 +1303,8 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
       return CHX_EHIP;
     }
   }
+  if (q.dtype == CHX_F32_REFINED)
+    h->py->dchunk.red_shape = tune_refined(h->py, h->px, q.nx, q.ny, h->cxs, h->cys);
   if (h->fast && q.dtype == CHX_F64 && !h->small) {
     const Tuned t = tune_step(h->py, h->px, q.nx, q.ny);
     h->py->dchunk.red_shape = t.red_shape;

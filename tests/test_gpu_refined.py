@@ -208,3 +208,28 @@ def test_refinement_that_cannot_converge_is_refused(chx):
         chx.ch_create(1024, 1024, L, L, 1.0, 0.001, 1.0, dtype=chx.CHX_F32_REFINED,
                       refine_passes=3)
     assert ei.value.status == chx.CHX_EREFINE
+
+
+@pytest.mark.parametrize("ny,nx", [(1024, 1024), (96, 320)])
+def test_refined_separator_shapes_bitwise(chx, orc, ny, nx):
+    """Refined handles tune the FP32 separator kernel's tile shape too: every
+    shape sums the same terms in the same order, so two refined steps are
+    bitwise identical whatever the shape, and match the oracle."""
+    g, dt, k = 0.01, 1e-5, 2
+    c0 = inputs.noise_field(ny, nx, 77)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt, dtype=chx.CHX_F32_REFINED, refine_passes=2)
+    assert 0 <= chx.ch_get_tuning(h) < chx.CHX_NUM_REDUCED_SHAPES
+    ref = None
+    for shape in range(chx.CHX_NUM_REDUCED_SHAPES):
+        print(f"[case] refined separator shape {shape} {ny}x{nx}", flush=True)
+        chx.ch_set_tuning(h, shape)
+        c = torch.tensor(c0, device="cuda")
+        d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+        chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+        torch.cuda.synchronize()
+        out = (c.cpu().numpy(), d.cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), shape
+    assert rel(ref[0], orc.ch_step(c0, L, L, 1.0, g, dt, nsteps=k)) < k * TARGET
