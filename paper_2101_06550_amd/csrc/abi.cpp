@@ -1305,6 +1305,12 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   }
   if (q.dtype == CHX_F32_REFINED)
     h->py->dchunk.red_shape = tune_refined(h->py, h->px, q.nx, q.ny, h->cxs, h->cys);
+  // the thesis scheme's separators and rows are the same kernels as the P1
+  // step's: its separator shape is tuned by the same whole-step timing (on
+  // its own plans; 32-point chunks, the only length it takes)
+  if (q.scheme == CHX_SCHEME_P2 && h->py->has_chunk && h->px->has_chunk && q.nx % 64 == 0 &&
+      h->px->chunk.S <= 256)
+    h->py->dchunk.red_shape = tune_step(h->py, h->px, q.nx, q.ny).red_shape;
   if (h->fast && q.dtype == CHX_F64 && !h->small) {
     const Tuned t = tune_step(h->py, h->px, q.nx, q.ny);
     h->py->dchunk.red_shape = t.red_shape;
