@@ -384,16 +384,18 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   the file (shape 0).
  *   Every shape sums the same terms in the same order, so results are
  *   bitwise identical whatever the shape.
- * CHX_TUNE_ROW_SPLIT: for rows of 4096 or 8192 points, -1 runs the column
- *   separator kernel and then the row pass; 0 .. CHX_NUM_SPLIT_SHAPES-1 run
- *   the separators in the same launch as the rows that do not need them
- *   (every row but the last two of each 32-row chunk), in that tile shape,
- *   then the remaining rows; -2 (CHX_ROW_SPLIT_OVERLAP) runs the separators
- *   and then the separator rows on a second stream of the handle while the
- *   other rows are solved on the caller's stream (joined by events before
- *   the next step; the steps ch_adi_step_timed times keep the -1 order so
- *   that their kernel timings stay meaningful).  Chosen by the same timing as the tile shape.
- *   Results are bitwise identical either way.
+ * CHX_TUNE_ROW_SPLIT: -1 runs the column separator kernel and then the row
+ *   pass; -2 (CHX_ROW_SPLIT_OVERLAP) runs the separators and then the
+ *   separator rows (the last two of every column chunk) on a second stream
+ *   of the handle while the other rows, which need no separator, are solved
+ *   on the caller's stream (joined by events before the next step; the
+ *   steps ch_adi_step_timed times keep the -1 order so that their kernel
+ *   timings stay meaningful), for either chunk length; for rows of 4096 or
+ *   8192 points with 32-point chunks in both directions, 0 ..
+ *   CHX_NUM_SPLIT_SHAPES-1 run the separators in the same launch as the
+ *   interior rows, in that tile shape, then the separator rows.  Chosen by
+ *   the same timing as the tile shape.  Results are bitwise identical
+ *   whatever the order.
  * CHX_TUNE_COLUMN_ORDER: order in which the multi-kernel path's column pass
  *   (and the pass that writes the final state) numbers its tiles of 256
  *   columns x 32 rows (0 .. CHX_NUM_COLUMN_ORDERS-1): 0 row-major; 1 each of
@@ -415,8 +417,8 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   Shorter chunks halve the serial sweep of each workgroup and double the
  *   separators; on small grids, where one round of workgroups covers the
  *   field, that wins.  Chosen by the same timing as the tile shape; 16 needs
- *   the row split -1 (and the split needs 32 in both directions: CHX_EINVAL
- *   otherwise).  The two lengths solve the same systems with different
+ *   the row split -1 or -2 (the fused split shapes need 32 in both
+ *   directions: CHX_EINVAL otherwise).  The two lengths solve the same systems with different
  *   rounding: results agree to rounding, not bitwise.
  * ch_get_tuning: *value = the current choice of `what`.
  * ch_set_tuning: set it from now on; CHX_EINVAL for a NULL handle, an unknown

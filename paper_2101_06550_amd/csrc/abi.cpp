@@ -972,7 +972,6 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   if (tune_cache_lookup(cache_path, cache_key, &best)) {
     // a split or overlap choice needs the handle's shapes to allow it
     if (best.split >= 0 && !split_fits(c, px->dchunk, best.split)) best.split = -1;
-    if (best.split == kSplitOverlap && !rows_subsets_fit(px->dchunk)) best.split = -1;
     if (best.mcol == 16 && !py->has_chunk16) best.mcol = kChunk;
     if (best.mrow == 16 && !rows16_fit(px)) best.mrow = kChunk;
     g_tune_cache[key] = best;
@@ -1017,35 +1016,6 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
       best.split = shape;
     }
   }
-  if (ok && rows_subsets_fit(px->dchunk)) {
-    hipStream_t side = nullptr;
-    hipEvent_t ef = nullptr, ej = nullptr;
-    bool ok2 = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
-               hipEventCreateWithFlags(&ef, hipEventDisableTiming) == hipSuccess &&
-               hipEventCreateWithFlags(&ej, hipEventDisableTiming) == hipSuccess;
-    if (ok2) {
-      DevChunk cb = c;
-      cb.red_shape = best.red_shape;
-      const float ms = time_it([&]() {
-        hipError_t e = hipEventRecord(ef, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, ef, 0);
-        if (e == hipSuccess) e = launch_reduced_il<2>(cb, rho, nx, dst, nx, kChunk, kChunk - 2, side);
-        if (e == hipSuccess) e = launch_rows_sep(dst, nx, ny, px->dchunk, side);
-        if (e == hipSuccess) e = hipEventRecord(ej, side);
-        if (e == hipSuccess) e = launch_rows_interior(dst, nx, ny, px->dchunk, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, ej, 0);
-        return e;
-      });
-      if (ok && ms < best_ms) {
-        best_ms = ms;
-        best.split = kSplitOverlap;
-      }
-    }
-    if (side) (void)hipStreamSynchronize(side);
-    if (ef) (void)hipEventDestroy(ef);
-    if (ej) (void)hipEventDestroy(ej);
-    if (side) (void)hipStreamDestroy(side);
-  }
   // tile order of the column pass: the pass with its diagnostics, reading
   // the zeroed field as a previous step's buffer (a second field buffer
   // takes its output)
@@ -1065,20 +1035,30 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
         best.col_order = order;
       }
     }
-    // whole steps (column pass, separators, rows) for the separator shape
-    // and the chunk lengths, 32 or 16 points in each direction where the
-    // plans allow them: timed alone on warm buffers, the separator kernel
-    // reads its parts from L2, while in a step it reads what the column pass
-    // has just written on other XCDs, so shapes rank differently there.
-    // The split and overlapped row orders are 32-point forms, kept only
-    // where the 32-point lengths win.
+    // whole steps (column pass, separators, rows) for the separator shape,
+    // the chunk lengths (32 or 16 points in each direction where the plans
+    // allow them) and the overlapped row order: timed alone on warm
+    // buffers, the separator kernel reads its parts from L2, while in a step
+    // it reads what the column pass has just written on other XCDs, so
+    // shapes rank differently there.  The overlapped order (separators and
+    // then the separator rows on a second stream beside the interior rows)
+    // is timed with each length pair's best shape.  The fused split forms
+    // are 32-point forms, kept only where the plain 32-point step wins.
+    hipStream_t side = nullptr;
+    hipEvent_t ef = nullptr, ej = nullptr;
+    const bool ok2 = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreateWithFlags(&ef, hipEventDisableTiming) == hipSuccess &&
+                     hipEventCreateWithFlags(&ej, hipEventDisableTiming) == hipSuccess;
     float best_step = -1.f;
+    bool overlap = false;
     const Tuned keep = best;
     for (int mc : {kChunk, 16}) {
       for (int mr : {kChunk, 16}) {
         if ((mc == 16 && !py->has_chunk16) || (mr == 16 && !rows16_fit(px))) continue;
         DevChunk cy = mc == 16 ? py->dchunk16 : py->dchunk;
         const DevChunk& cx = mr == 16 ? px->dchunk16 : px->dchunk;
+        float pair_ms = -1.f;
+        int pair_shape = 0;
         for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
           if (reduced_lds_bytes(shape, 2, sizeof(double), cy.dcount, true) > max_lds) continue;
           cy.red_shape = shape;
@@ -1089,16 +1069,48 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
               e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, st);
             return e == hipSuccess ? launch_rows_lds<2>(cx, ybuf, nx, ny, st) : e;
           });
+          if (ok && (pair_ms < 0.f || ms < pair_ms)) {
+            pair_ms = ms;
+            pair_shape = shape;
+          }
           if (ok && (best_step < 0.f || ms < best_step)) {
             best_step = ms;
             best.mcol = mc;
             best.mrow = mr;
             best.red_shape = shape;
+            overlap = false;
           }
+        }
+        if (!ok || !ok2 || pair_ms < 0.f) continue;
+        cy.red_shape = pair_shape;
+        const float ms = time_it([&]() {
+          hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho, K,
+                                               part, st, nullptr, keep.col_order);
+          if (e == hipSuccess) e = hipEventRecord(ef, st);
+          if (e == hipSuccess) e = hipStreamWaitEvent(side, ef, 0);
+          if (e == hipSuccess)
+            e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, side);
+          if (e == hipSuccess) e = launch_rows_subset(true, ybuf, nx, ny, cy.M, cx, side);
+          if (e == hipSuccess) e = hipEventRecord(ej, side);
+          if (e == hipSuccess) e = launch_rows_subset(false, ybuf, nx, ny, cy.M, cx, st);
+          if (e == hipSuccess) e = hipStreamWaitEvent(st, ej, 0);
+          return e;
+        });
+        if (ok && ms < best_step) {
+          best_step = ms;
+          best.mcol = mc;
+          best.mrow = mr;
+          best.red_shape = pair_shape;
+          overlap = true;
         }
       }
     }
-    if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
+    if (side) (void)hipStreamSynchronize(side);
+    if (ef) (void)hipEventDestroy(ef);
+    if (ej) (void)hipEventDestroy(ej);
+    if (side) (void)hipStreamDestroy(side);
+    if (overlap) best.split = kSplitOverlap;
+    else if (best.mcol != kChunk || best.mrow != kChunk) best.split = -1;
   }
   if (st) (void)hipStreamSynchronize(st);
   if (rho) (void)hipFree(rho);
@@ -1295,7 +1307,7 @@ int ch_create(const chx_ch_params* prm, chx_ch* out) {
   }
   h->small_ok = h->fast && q.dtype == CHX_F64 && ch_small_fits(q.nx, q.ny, device_max_lds());
   h->small = h->small_ok;
-  if (h->fast && q.dtype == CHX_F64 && rows_subsets_fit(h->px->dchunk)) {
+  if (h->fast && q.dtype == CHX_F64) {
     if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -1354,8 +1366,9 @@ int ch_set_tuning(chx_ch h, int what, int value) {
       h->small = value == 1;
       return CHX_OK;
     case CHX_TUNE_ROW_SPLIT:
-      // the split and overlapped row orders are forms of the 32-point chunks
-      if (value != -1 && (h->mcol != kChunk || h->mrow != kChunk)) return CHX_EINVAL;
+      // the fused split forms are forms of the 32-point chunks; the
+      // overlapped order takes either length
+      if (value >= 0 && (h->mcol != kChunk || h->mrow != kChunk)) return CHX_EINVAL;
       if (value == kSplitOverlap) {
         if (!h->side) return CHX_EINVAL;
       } else if (value != -1 && !(h->fast && h->prm.dtype == CHX_F64 &&
@@ -1366,12 +1379,12 @@ int ch_set_tuning(chx_ch h, int what, int value) {
       return CHX_OK;
     case CHX_TUNE_COLUMN_CHUNK:
       if (value != kChunk && !(value == 16 && h->fast && h->py->has_chunk16)) return CHX_EINVAL;
-      if (value != kChunk && h->split != -1) return CHX_EINVAL;
+      if (value != kChunk && h->split >= 0) return CHX_EINVAL;
       h->mcol = value;
       return CHX_OK;
     case CHX_TUNE_ROW_CHUNK:
       if (value != kChunk && !(value == 16 && h->fast && rows16_fit(h->px))) return CHX_EINVAL;
-      if (value != kChunk && h->split != -1) return CHX_EINVAL;
+      if (value != kChunk && h->split >= 0) return CHX_EINVAL;
       h->mrow = value;
       return CHX_OK;
     case CHX_TUNE_COLUMN_ORDER:
@@ -1565,13 +1578,13 @@ static int run_steps(chx_ch h, double* c, long ld, int nsteps, double* diag_out,
         e = hipEventRecord(h->ev_fork, st);
         if (ok()) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
         if (ok()) {
-          e = launch_reduced_il<2>(h->py->dchunk, rho, nx, dst, nx, kChunk, kChunk - 2, h->side,
+          e = launch_reduced_il<2>(cy, rho, nx, dst, nx, cy.M, cy.M - 2, h->side,
                                    diag ? part : nullptr, diag ? colblocks : 0, h->K.dxdy,
                                    diag ? diag_out + 2 * n : nullptr);
-          if (e == hipSuccess) e = launch_rows_sep(dst, nx, ny, h->px->dchunk, h->side);
+          if (e == hipSuccess) e = launch_rows_subset(true, dst, nx, ny, cy.M, cx, h->side);
           // join even after a failure, so no capture is left forked
           const hipError_t j1 = hipEventRecord(h->ev_join, h->side);
-          if (e == hipSuccess) e = launch_rows_interior(dst, nx, ny, h->px->dchunk, st);
+          if (e == hipSuccess) e = launch_rows_subset(false, dst, nx, ny, cy.M, cx, st);
           const hipError_t j2 = hipStreamWaitEvent(st, h->ev_join, 0);
           if (e == hipSuccess) e = j1 != hipSuccess ? j1 : j2;
         }

@@ -42,15 +42,14 @@ size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag);
 // says whether a shape's window fits the row tile's LDS.
 constexpr int kNumSplitShapes = 3;
 bool split_fits(const DevChunk& cy, const DevChunk& cx, int shape);
+// Separator rows (sep) or interior rows of a step whose column chunks are Mc
+// rows long, for a row plan of at most 256 chunks (16- or 32-point).
+hipError_t launch_rows_subset(bool sep, double* x, int nx, int ny, int Mc, const DevChunk& cx,
+                              hipStream_t st);
 hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* rho, double* x,
                                    int nx, int ny, const DevChunk& cx, const double* dpart,
                                    long dnparts, double dscale, double* dout, hipStream_t st);
 hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
-// The interior rows of every 32-row chunk (the rows that need no column
-// separator); rows_subsets_fit: row lengths whose rows split this way (the
-// row plan has 128 or 256 chunks).
-bool rows_subsets_fit(const DevChunk& cx);
-hipError_t launch_rows_interior(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st);
 
 // nsteps steps of a batched 1D periodic scheme (kind 0 Crank-Nicolson
 // hyperdiffusion, 1 Crank-Nicolson diffusion, 2 1D Cahn-Hilliard) on the

@@ -266,12 +266,29 @@ __global__ __launch_bounds__(256) void resid_lines(const double* __restrict__ f,
 // (ld == n) need no division: the group is one contiguous range, loaded with
 // every load of a thread in flight before the first LDS store.  Strided rows
 // (ld > n) take a compact loop.
-template <int P, int M, typename T, typename Tin = double>
+// Which rows a row kernel solves: row q of its list is row map(q) of the
+// array.  IdRows solves rows 0 .. rows-1; SubsetRows the separator rows (the
+// last two of every column chunk of length Mc: per = 2, off = Mc - 2) or the
+// interior rows (per = Mc - 2, off = 0), so that the two subsets can be
+// solved on two streams, the interior rows while the separators are formed.
+struct IdRows {
+  static constexpr bool identity = true;
+  __device__ long operator()(long q) const { return q; }
+};
+struct SubsetRows {
+  static constexpr bool identity = false;
+  int Mc, per, off;
+  __device__ long operator()(long q) const { return (q / per) * Mc + off + q % per; }
+};
+
+template <int P, int M, typename T, typename Tin = double, class Map = IdRows>
 __device__ __forceinline__ void row_group_stage(T* tile, const Tin* x, long ld, int rows, int n,
-                                                long row0, int nel, int t, bool dense) {
+                                                long row0, int nel, int t, bool dense,
+                                                const Map& map = Map()) {
+  // dense: the group's rows are consecutive rows of a dense array
   if (dense) {
     const long nvalid = ((long)rows - row0) * n;
-    const Tin* base = x + row0 * n;
+    const Tin* base = x + map(row0) * n;
     Tin vin[M];
     if (nel == 256 * M && nvalid >= nel) {  // a full group: 16-byte loads, no guards
       if constexpr (sizeof(Tin) == 4) {  // four values per load
@@ -324,7 +341,7 @@ __device__ __forceinline__ void row_group_stage(T* tile, const Tin* x, long ld, 
       const int e = t + 256 * u;
       const int r = e / n;
       const int i = e - r * n;
-      if (e < nel) tile[e + e / M] = (row0 + r < rows) ? (T)x[(row0 + r) * ld + i] : T(0);
+      if (e < nel) tile[e + e / M] = (row0 + r < rows) ? (T)x[map(row0 + r) * ld + i] : T(0);
     }
   }
 }
@@ -339,20 +356,30 @@ struct RowLds {
 };
 
 // Rows row0 .. row0 + R - 1 (R = 256 / S rows of n = S M unknowns each).
-template <int P, int M, typename T, bool ACC, typename Tin = double, typename Tout = double>
+template <int P, int M, typename T, bool ACC, typename Tin = double, typename Tout = double,
+          class Map = IdRows>
 __device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* dst, long ldd,
                                                int rows, int n, int S, int R,
                                                const T* __restrict__ rec, const BandT<T>& bd,
                                                const T* __restrict__ blocks, int dlo, int dcount,
-                                               long row0, RowLds<P, M, T>& sh) {
+                                               long row0, RowLds<P, M, T>& sh,
+                                               const Map& map = Map()) {
   T* tile = sh.tile;
   T* rhol = sh.rhol;
   T* sepl = sh.sepl;
   const int t = threadIdx.x;
   const int nel = R * n;  // <= 256 * M
   const int r = t / S, k = t - r * S;
+  // the group's valid rows are consecutive rows of the array (always so for
+  // IdRows): then dense arrays take the contiguous loads and stores
+  bool contig = true;
+  if constexpr (!Map::identity) {
+    const long last = (row0 + R <= rows ? row0 + R : rows) - 1;
+    contig = map(last) - map(row0) == last - row0;
+  }
   {
-    row_group_stage<P, M, T, Tin>(tile, src, lds, rows, n, row0, nel, t, lds == n);
+    row_group_stage<P, M, T, Tin, Map>(tile, src, lds, rows, n, row0, nel, t, lds == n && contig,
+                                       map);
     __syncthreads();
     const bool active = (r < R) && (row0 + r < rows);
     T f[M];
@@ -424,11 +451,12 @@ __device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* d
       for (int p = 0; p < M; ++p) tile[t * (M + 1) + p] = f[p];
     }
     __syncthreads();
-    const bool full = ldd == n && nel == 256 * M && ((long)rows - row0) * n >= nel;
+    const bool dense_out = ldd == n && contig;
+    const bool full = dense_out && nel == 256 * M && ((long)rows - row0) * n >= nel;
     if constexpr (sizeof(Tout) == 4) {
       static_assert(!ACC, "FP32 output does not accumulate");
       if (full) {  // four values per streamed 16-byte store
-        float* b = dst + row0 * n;
+        float* b = dst + map(row0) * n;
 #pragma unroll
         for (int u = 0; u < M / 4; ++u) {
           const int e = 4 * t + 1024 * u;
@@ -439,7 +467,7 @@ __device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* d
       }
     } else {
       if (full) {
-        double2* b2 = reinterpret_cast<double2*>(dst + row0 * n);
+        double2* b2 = reinterpret_cast<double2*>(dst + map(row0) * n);
 #pragma unroll
         for (int u = 0; u < M / 2; ++u) {
           const int e = 2 * t + 512 * u;
@@ -455,9 +483,9 @@ __device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* d
         }
       }
     }
-    if (!full && ldd == n) {
+    if (!full && dense_out) {
       const long nvalid = ((long)rows - row0) * n;
-      Tout* base = dst + row0 * n;
+      Tout* base = dst + map(row0) * n;
 #pragma unroll
       for (int u = 0; u < M; ++u) {
         const int e = t + 256 * u;
@@ -473,8 +501,8 @@ __device__ __forceinline__ void row_solve_body(const Tin* src, long lds, Tout* d
         const int rr = e / n;
         const int i = e - rr * n;
         if (e < nel && row0 + rr < rows) {
-          if (ACC) dst[(row0 + rr) * ldd + i] += (Tout)tile[e + e / M];
-          else dst[(row0 + rr) * ldd + i] = (Tout)tile[e + e / M];
+          if (ACC) dst[map(row0 + rr) * ldd + i] += (Tout)tile[e + e / M];
+          else dst[map(row0 + rr) * ldd + i] = (Tout)tile[e + e / M];
         }
       }
     }
@@ -1011,16 +1039,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
                                            sh);
 }
 
-// The interior rows alone (every row but the last two of each 32-row chunk):
-// they need no column separator, so they can be solved while the separator
-// kernel runs on another stream.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rows_interior(
-    double* x, int nx, int ny, DevChunk cx, BandT<double> bdx) {
-  __shared__ RowLds<2, kChunk, double> sh;
+
+// The separator rows (SEP) or the interior rows of a step whose columns are
+// chunked by Mc rows, for any row plan: groups of R = 256 / S consecutive
+// rows of the subset (a group may span two column chunks; rows are
+// independent).  Used by the overlapped row order: the interior rows need no
+// column separator, so they are solved on one stream while the separators
+// and then the separator rows are formed on another.
+template <bool SEP, int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void rows_subset(
+    double* x, int nx, int ny, int Mc, DevChunk cx, BandT<double> bdx) {
+  __shared__ RowLds<2, M, double> sh;
   const int R = 256 / cx.S;
-  row_solve_body<2, kChunk, double, false>(x, nx, x, nx, ny, nx, cx.S, R, cx.rec, bdx, cx.blocks,
-                                           cx.dlo, cx.dcount, split_row0(blockIdx.x, R, false),
-                                           sh);
+  const int per = SEP ? 2 : Mc - 2;
+  const SubsetRows map{Mc, per, SEP ? Mc - 2 : 0};
+  const int count = (ny / Mc) * per;
+  row_solve_body<2, M, double, false, double, double, SubsetRows>(
+      x, nx, x, nx, count, nx, cx.S, R, cx.rec, bdx, cx.blocks, cx.dlo, cx.dcount,
+      (long)blockIdx.x * R, sh, map);
+}
+
+hipError_t launch_rows_subset(bool sep, double* x, int nx, int ny, int Mc, const DevChunk& cx,
+                              hipStream_t st) {
+  if (cx.S > 256 || ny % Mc != 0 || (cx.M != kChunk && cx.M != 16)) return hipErrorInvalidValue;
+  const int R = 256 / cx.S;
+  const long count = (long)(ny / Mc) * (sep ? 2 : Mc - 2);
+  const dim3 grid((unsigned)((count + R - 1) / R));
+  const BandT<double> bd = band_of<double>(cx.coef);
+#define CHX_SUB(S_, M_) \
+  hipLaunchKernelGGL((rows_subset<S_, M_>), grid, dim3(256), 0, st, x, nx, ny, Mc, cx, bd)
+  if (sep) {
+    if (cx.M == 16) CHX_SUB(true, 16);
+    else CHX_SUB(true, kChunk);
+  } else {
+    if (cx.M == 16) CHX_SUB(false, 16);
+    else CHX_SUB(false, kChunk);
+  }
+#undef CHX_SUB
+  return hipGetLastError();
 }
 
 // (chunks per wave, window entries staged at once) of the fused kernel's
@@ -1057,16 +1113,6 @@ hipError_t launch_rows_split_fused(int shape, const DevChunk& cy, const double* 
   return hipGetLastError();
 }
 
-bool rows_subsets_fit(const DevChunk& cx) { return cx.S == 128 || cx.S == 256; }
-
-hipError_t launch_rows_interior(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st) {
-  if (!rows_subsets_fit(cx)) return hipErrorInvalidValue;
-  const int R = 256 / cx.S;
-  const dim3 grid((unsigned)((ny / kChunk) * ((kChunk - 2) / R)));
-  hipLaunchKernelGGL(rows_interior, grid, dim3(256), 0, st, x, nx, ny, cx,
-                     band_of<double>(cx.coef));
-  return hipGetLastError();
-}
 
 hipError_t launch_rows_sep(double* x, int nx, int ny, const DevChunk& cx, hipStream_t st) {
   const int R = 256 / cx.S;

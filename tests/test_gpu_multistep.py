@@ -212,9 +212,42 @@ def test_chunk_lengths_match_oracle(chx, orc, ny, nx, g, dt, k, seed):
                 assert abs(dd[j, 1] - e) <= max(j, 1) * 1e-12 * abs(e), (mc, mr, j)
 
 
+@pytest.mark.parametrize("ny,nx,seed", [(1024, 1024, 81), (96, 320, 82), (160, 576, 83),
+                                        (64, 2048, 84)])
+def test_overlapped_row_order_any_chunk_lengths(chx, orc, ny, nx, seed):
+    """CHX_ROW_SPLIT_OVERLAP for every chunk-length pair: the separator rows on
+    the handle's second stream beside the interior rows, in row groups that
+    span column chunks (groups of R = 256 / S rows of the 14- or 30-row
+    interiors, ragged last groups); bitwise equal to the plain order, three
+    steps with diagnostics, and against the oracle."""
+    g, dt, k = 0.01, 1e-5, 3
+    c0 = inputs.noise_field(ny, nx, seed)
+    h = chx.ch_create(nx, ny, L, L, 1.0, g, dt)
+    chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_SMALL_PATH)
+    ref = oracle_states(orc, c0, g, dt, k)[k]
+    for mc in (32, 16):
+        for mr in (32, 16):
+            outs = []
+            for split in (-1, chx.CHX_ROW_SPLIT_OVERLAP):
+                print(f"[case] row order {split} chunks {mc}/{mr} {ny}x{nx}", flush=True)
+                chx.ch_set_tuning(h, -1, what=chx.CHX_TUNE_ROW_SPLIT)
+                chx.ch_set_tuning(h, mc, what=chx.CHX_TUNE_COLUMN_CHUNK)
+                chx.ch_set_tuning(h, mr, what=chx.CHX_TUNE_ROW_CHUNK)
+                chx.ch_set_tuning(h, split, what=chx.CHX_TUNE_ROW_SPLIT)
+                c = torch.tensor(c0, device="cuda")
+                d = torch.zeros(2 * (k + 1), dtype=torch.float64, device="cuda")
+                chx.ch_adi_step(h, c, nsteps=k, diag_out=d)
+                torch.cuda.synchronize()
+                outs.append((c.cpu().numpy(), d.cpu().numpy()))
+            assert np.array_equal(outs[0][0], outs[1][0]), (mc, mr)
+            assert np.array_equal(outs[0][1], outs[1][1]), (mc, mr)
+            assert rel(outs[1][0], ref) < k * 1e-12, (mc, mr)
+
+
 def test_chunk_length_choices_refused_where_they_do_not_apply(chx):
     """16-point rows need at most 256 chunks (4096 points); any chunk other
-    than 16 or 32 is refused; 16 and the split row forms exclude each other."""
+    than 16 or 32 is refused; 16 and the fused split row forms exclude each
+    other (the overlapped order takes either)."""
     h = chx.ch_create(8192, 96, L, L, 1.0, 0.001, 1e-6)
     for w in (chx.CHX_TUNE_COLUMN_CHUNK, chx.CHX_TUNE_ROW_CHUNK):
         chx.ch_set_tuning(h, 32, what=w)
@@ -231,8 +264,7 @@ def test_chunk_length_choices_refused_where_they_do_not_apply(chx):
     chx.ch_set_tuning(h, 16, what=chx.CHX_TUNE_COLUMN_CHUNK)
     with pytest.raises(chx.ChxError):
         chx.ch_set_tuning(h, 0, what=chx.CHX_TUNE_ROW_SPLIT)
-    with pytest.raises(chx.ChxError):
-        chx.ch_set_tuning(h, chx.CHX_ROW_SPLIT_OVERLAP, what=chx.CHX_TUNE_ROW_SPLIT)
+    chx.ch_set_tuning(h, chx.CHX_ROW_SPLIT_OVERLAP, what=chx.CHX_TUNE_ROW_SPLIT)  # any length
 
 
 @pytest.mark.parametrize("ny,nx,dtype,passes", [(1024, 1024, 0, 0), (96, 320, 0, 0),
