@@ -136,7 +136,11 @@ def test_schemes_are_not_interchangeable(chx):
 
 def test_large_run_two_steps(chx, orc):
     """The benchmark's 8192 x 8192 grid: the first step and one later step
-    (state update and column correction fused into the right-hand side)."""
+    (state update and column correction fused into the right-hand side).
+    Measured error 1.17e-12 (the kernels' results do not depend on tuned
+    choices, so it is reproducible); the bound is about ten times that, well
+    inside the eps (1 + 16 s') scale (2.7e-10 here) that two correct FP64
+    steps of this scheme may differ by."""
     n = 8192
     c0 = inputs.mode_plus_noise(n, 5)
     h = p2(chx, n, n, g=0.001, dt=1e-6)
@@ -147,7 +151,8 @@ def test_large_run_two_steps(chx, orc):
     ref, ref_prev = orc.ch2_step(c0, c0, L, L, 1.0, 0.001, 1e-6, nsteps=2)
     err = rel(c.cpu().numpy(), ref)
     print(f"P2 8192 two-step error {err:.3e}", flush=True)
-    assert err < 2 * tol(n, n, g=0.001, dt=1e-6), f"P2 8192^2 two steps: {err:.3e}"
+    assert err < 1.5e-11, f"P2 8192^2 two steps: {err:.3e}"
+    assert 1.5e-11 < 2 * tol(n, n, g=0.001, dt=1e-6)
     assert rel(cp.cpu().numpy(), ref_prev) < tol(n, n, g=0.001, dt=1e-6)
 
 
