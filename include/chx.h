@@ -531,6 +531,21 @@ int ch_k1(chx_ch h, const double* c, long ld, double* k1, chx_stream s);
 typedef struct chx_ens_s* chx_ens;
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out);
 int ch_ensemble_destroy(chx_ens e);
+/* ch_ensemble_get_tuning / ch_ensemble_set_tuning: what =
+ *   CHX_TUNE_REDUCED_SHAPE, the tile shape of an FP64 ensemble's separator
+ *   kernel (0 .. CHX_NUM_ENS_REDUCED_SHAPES-1: 8 waves x 4 chunks, 8 x 1,
+ *   4 x 2, 4 x 4 per block; small grids have few chunks per column, which
+ *   the larger blocks leave mostly idle).  ch_ensemble_create times every
+ *   shape on the ensemble's own runs (column pass and separators from a
+ *   captured graph; CHX_AUTOTUNE=0 keeps 0) and keeps the fastest.  Every
+ *   shape sums the same terms in the same order: results are bitwise
+ *   identical whatever the shape.  Setting synchronises the device (queued
+ *   calls may still read the work items) and drops a captured graph.
+ *   CHX_EINVAL for refined ensembles, another `what` or a shape out of
+ *   range or whose LDS does not fit. */
+#define CHX_NUM_ENS_REDUCED_SHAPES 4
+int ch_ensemble_get_tuning(chx_ens e, int what, int* value);
+int ch_ensemble_set_tuning(chx_ens e, int what, int value);
 size_t ch_ensemble_ws_bytes(chx_ens e);
 int ch_ensemble_step(chx_ens e, double* const* c_runs, const long* ld_runs,
                      int nsteps, double* diag_out, void* ws, size_t ws_bytes,

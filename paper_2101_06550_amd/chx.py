@@ -52,7 +52,7 @@ EXPORTED = [
     "batch1d_rewrite_ws_bytes", "batch1d_step_rewrite",
     "ch_ensemble_create", "ch_ensemble_destroy", "ch_ensemble_ws_bytes", "ch_ensemble_step",
     "ch_ensemble_moments", "ch_ensemble_k1", "ch_ensemble_set_noise",
-    "ch_ensemble_get_noise_step",
+    "ch_ensemble_get_noise_step", "ch_ensemble_get_tuning", "ch_ensemble_set_tuning",
     "chx_host_chunk_tables", "chx_host_whole_tables",
 ]
 
@@ -141,6 +141,8 @@ def load(path: str | None = None):
                                   _I, _V]),
         "ch_ensemble_set_noise": (_I, [_V, _D, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64]),
         "ch_ensemble_get_noise_step": (_I, [_V, ctypes.POINTER(ctypes.c_uint64)]),
+        "ch_ensemble_get_tuning": (_I, [_V, _I, ctypes.POINTER(_I)]),
+        "ch_ensemble_set_tuning": (_I, [_V, _I, _I]),
         "ch_ensemble_moments": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
         "ch_ensemble_k1": (_I, [_V, ctypes.POINTER(_V), ctypes.POINTER(_L), _DP, _V]),
         "chx_host_chunk_tables": (_I, [_I, _DP, _I, _I, _DP, _I, _DP, _I, _IP]),
@@ -666,6 +668,7 @@ CHX_NUM_SPLIT_SHAPES = 3
 CHX_TUNE_COLUMN_ORDER = 3
 CHX_NUM_COLUMN_ORDERS = 3
 CHX_TUNE_GRAPH = 4
+CHX_NUM_ENS_REDUCED_SHAPES = 4
 CHX_TUNE_COLUMN_CHUNK = 5
 CHX_TUNE_ROW_CHUNK = 6
 
@@ -813,6 +816,20 @@ def ch_ensemble_destroy(e: Ensemble) -> None:
 
 def ch_ensemble_ws_bytes(e: Ensemble) -> int:
     return load().ch_ensemble_ws_bytes(e.handle)
+
+
+def ch_ensemble_get_tuning(ens, what: int = 0) -> int:
+    """The FP64 ensemble's separator tile shape (what = CHX_TUNE_REDUCED_SHAPE)."""
+    v = ctypes.c_int()
+    _check(load().ch_ensemble_get_tuning(ens.handle, int(what), ctypes.byref(v)),
+           "ch_ensemble_get_tuning")
+    return v.value
+
+
+def ch_ensemble_set_tuning(ens, value: int, what: int = 0):
+    """Set the FP64 ensemble's separator tile shape from now on."""
+    _check(load().ch_ensemble_set_tuning(ens.handle, int(what), int(value)),
+           "ch_ensemble_set_tuning")
 
 
 def ch_ensemble_step(e: Ensemble, fields, nsteps: int = 1, diag_out=None, use_graph: bool = True,

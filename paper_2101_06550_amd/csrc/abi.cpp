@@ -412,6 +412,8 @@ struct chx_ens_s {
   int n_col = 0, n_red = 0, n_row = 0;
   long o_col = 0, o_red = 0, o_row = 0;
   bool rows_half = false;  // every row item a dense whole group: half-tile row kernel
+  int red_shape = 0;       // FP64 separator kernel shape (timed at creation)
+  std::vector<int> red_order;  // the runs whose separator items follow o_red
   size_t ws_total = 0, red_lds = 0;
   long max_points = 0;
   // cached hipGraph of a whole call (nsteps, diag, ws)
@@ -514,7 +516,7 @@ int ens_launch_all(chx_ens_s* E, int nsteps, double* diag_out, unsigned char* ws
                                E->druns, E->hcls, it + E->o_col, E->n_col, ws, n, st);
     if (e == hipSuccess)
       e = launch_ens_reduced(E->druns, E->hcls, it + E->o_red, E->n_red, ws, n, diag_out, dstride,
-                             E->red_lds, st);
+                             E->red_lds, st, E->red_shape);
     if (e == hipSuccess) e = launch_ens_rows(E->druns, E->hcls, it + E->o_row, E->n_row, ws, n, st,
                                              E->rows_half);
   }
@@ -1188,6 +1190,85 @@ int tune_refined(const BandPlan* py, const BandPlan* px, int nx, int ny, const d
   cache[key] = t.red_shape;
   tune_cache_store(cache_path, cache_key, t);
   return t.red_shape;
+}
+
+// Separator work items of the runs in `order` for tile shape `shape`: per
+// run, blocks of 64 columns x (the shape's chunks per block) column chunks.
+std::vector<int4> ens_red_items(const chx_ens_s* E, const std::vector<int>& order, int shape) {
+  const int kb = ens_red_chunks_per_block(shape);
+  std::vector<int4> out;
+  for (int r : order) {
+    const int nby = (E->runs[r].Sc + kb - 1) / kb, nbx = (E->runs[r].nx + 63) / 64;
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) out.push_back(make_int4(r, bx, by, 0));
+  }
+  return out;
+}
+
+// Separator items, LDS and shape of the FP64 ensemble set to shape sh
+// (CHX_EINVAL if its LDS does not fit).
+int ens_set_red_shape(chx_ens_s* E, int sh) {
+  if (sh < 0 || sh >= kNumEnsRedShapes) return CHX_EINVAL;
+  size_t lds = 0;
+  for (const EnsClass& c : E->classes) lds = std::max(lds, ens_reduced_lds_bytes(c.py.dcount, sh));
+  if (lds > std::min(device_max_lds(), kMaxLdsBytes)) return CHX_EINVAL;
+  const auto red = ens_red_items(E, E->red_order, sh);
+  if (!red.empty() && hipMemcpy(E->ditems + E->o_red, red.data(), sizeof(int4) * red.size(),
+                                hipMemcpyHostToDevice) != hipSuccess)
+    return CHX_EHIP;
+  E->red_shape = sh;
+  E->n_red = (int)red.size();
+  E->red_lds = lds;
+  return CHX_OK;
+}
+
+// Times every separator tile shape on the ensemble's own runs (column pass
+// then separators, from a captured graph, on a scratch workspace of the
+// ensemble's size) and keeps the fastest; the items are rewritten in place.
+// CHX_AUTOTUNE=0 keeps shape 0.  Every shape sums the same terms in the same
+// order, so the choice never changes a result.
+int ens_tune_red(chx_ens_s* E, const std::vector<int>& order) {
+  const char* env = std::getenv("CHX_AUTOTUNE");
+  if (env && env[0] == '0') return CHX_OK;
+  long points = 0;
+  for (int r : order) points += (long)E->runs[r].nx * E->runs[r].ny;
+  unsigned char* ws = nullptr;
+  GraphTimer timer(points);
+  bool& ok = timer.ok;
+  ok = ok && hipMalloc(&ws, E->ws_total) == hipSuccess &&
+       hipMemsetAsync(ws, 0, E->ws_total, timer.st) == hipSuccess;
+  const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
+  float best = -1.f;
+  int best_shape = 0;
+  for (int sh = 0; ok && sh < kNumEnsRedShapes; ++sh) {
+    size_t lds = 0;
+    for (const EnsClass& c : E->classes)
+      lds = std::max(lds, ens_reduced_lds_bytes(c.py.dcount, sh));
+    if (lds > max_lds) continue;
+    const auto red = ens_red_items(E, order, sh);
+    ok = hipMemcpy(E->ditems + E->o_red, red.data(), sizeof(int4) * red.size(),
+                   hipMemcpyHostToDevice) == hipSuccess;
+    const int n = (int)red.size();
+    // step 1 of a call: the column pass reads the scratch workspace's first
+    // buffer (step 0 would read the runs' own fields, which no call has set
+    // yet: null pointers here) and writes the second, which the separators
+    // then complete
+    const float ms = timer.time([&]() {
+      hipError_t e = launch_ens_column_pass(true, false, nullptr, E->druns, E->hcls,
+                                            E->ditems + E->o_col, E->n_col, ws, 1, timer.st);
+      return e == hipSuccess ? launch_ens_reduced(E->druns, E->hcls, E->ditems + E->o_red, n, ws,
+                                                  1, nullptr, 0, lds, timer.st, sh)
+                             : e;
+    });
+    if (ok && (best < 0.f || ms < best)) {
+      best = ms;
+      best_shape = sh;
+    }
+  }
+  if (timer.st) (void)hipStreamSynchronize(timer.st);
+  if (ws) (void)hipFree(ws);
+  if (!ok) (void)hipGetLastError();  // a failed trial leaves shape 0
+  return ens_set_red_shape(E, ok ? best_shape : 0);
 }
 
 }  // namespace
@@ -2195,13 +2276,6 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     for (int kc = 0; kc < E->runs[r].Sc; ++kc)
       for (int cb = 0; cb < E->runs[r].ncb; ++cb) add(r, cb, kc);
   E->n_col = (int)(items.size() - E->o_col);
-  E->o_red = (long)items.size();
-  for (int r : order) {
-    const int nby = (E->runs[r].Sc + 31) / 32, nbx = (E->runs[r].nx + 63) / 64;
-    for (int by = 0; by < nby; ++by)
-      for (int bx = 0; bx < nbx; ++bx) add(r, bx, by);
-  }
-  E->n_red = (int)(items.size() - E->o_red);
   E->o_row = (long)items.size();
   E->rows_half = true;
   for (int r : order) {
@@ -2211,10 +2285,22 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     if (256 % S != 0 || E->runs[r].ny % R != 0) E->rows_half = false;
   }
   E->n_row = (int)(items.size() - E->o_row);
+  // the separator items last: their count depends on the tile shape that
+  // creation times (room for the shape with the most blocks)
+  E->o_red = (long)items.size();
+  size_t max_red = 0;
+  for (int sh = 0; sh < kNumEnsRedShapes; ++sh)
+    max_red = std::max(max_red, ens_red_items(E, order, sh).size());
+  {
+    const auto red = ens_red_items(E, order, 0);
+    items.insert(items.end(), red.begin(), red.end());
+    E->n_red = (int)red.size();
+  }
 
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
-  const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
+  const size_t b_items =
+      align256(sizeof(int4) * std::max<size_t>(E->o_red + max_red, 1));
   const size_t b_lists = align256(sizeof(int) * nruns);
   if (hipMalloc(&E->dmem, b_runs + b_items + 2 * b_lists) != hipSuccess) {
     E->dmem = nullptr;
@@ -2241,12 +2327,32 @@ int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
     ok = hipStreamCreateWithFlags(&E->side, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&E->ev_fork, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&E->ev_join, hipEventDisableTiming) == hipSuccess;
+  E->red_order = order;
+  if (ok && E->nbig > 0) ok = ens_tune_red(E, order) == CHX_OK;
   if (!ok) {
     delete E;
     return CHX_EHIP;
   }
   *out = E;
   return CHX_OK;
+}
+
+int ch_ensemble_get_tuning(chx_ens e, int what, int* value) {
+  if (!e || !value || what != CHX_TUNE_REDUCED_SHAPE) return CHX_EINVAL;
+  *value = e->red_shape;
+  return CHX_OK;
+}
+
+static void ens_drop_graph(chx_ens E);
+
+int ch_ensemble_set_tuning(chx_ens e, int what, int value) {
+  if (!e || what != CHX_TUNE_REDUCED_SHAPE || e->refined) return CHX_EINVAL;
+  if (value < 0 || value >= kNumEnsRedShapes) return CHX_EINVAL;
+  if (e->nbig == 0) return value == 0 ? CHX_OK : CHX_EINVAL;
+  // queued work may still read the work items
+  if (hipDeviceSynchronize() != hipSuccess) return CHX_EHIP;
+  ens_drop_graph(e);  // a captured call holds the old items
+  return ens_set_red_shape(e, value);
 }
 
 int ch_ensemble_destroy(chx_ens e) {

@@ -53,8 +53,13 @@ hipError_t launch_ens_column_pass(bool recon, bool diag, const unsigned long lon
 hipError_t launch_ens_noise_advance(unsigned long long* noise_step, int nsteps, hipStream_t st);
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
-                              long diag_stride, size_t lds_bytes, hipStream_t st);
-size_t ens_reduced_lds_bytes(int dcount);
+                              long diag_stride, size_t lds_bytes, hipStream_t st,
+                              int shape = 0);
+size_t ens_reduced_lds_bytes(int dcount, int shape = 0);
+// Tile shapes of the FP64 ensemble's separator kernel (shape 0: 8 waves x 4
+// chunks) and the chunks one block of a shape covers.
+constexpr int kNumEnsRedShapes = 4;
+int ens_red_chunks_per_block(int shape);
 hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4* items, int nitems,
                            unsigned char* ws, int step, hipStream_t st,
                            bool half = false);

@@ -1129,6 +1129,39 @@ constexpr int kRedKB = kRedWaves * kRedG;
 
 // ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
+// Tile shapes (waves per block, chunks per wave) of the FP64 ensemble's
+// separator kernel; ch_ensemble_create times them on the ensemble's runs.
+struct EnsRedShape {
+  int W, G;
+};
+constexpr EnsRedShape kEnsRedShapes[kNumEnsRedShapes] = {{8, 4}, {8, 1}, {4, 2}, {4, 4}};
+
+int ens_red_chunks_per_block(int shape) {
+  const EnsRedShape& r = kEnsRedShapes[(shape < 0 || shape >= kNumEnsRedShapes) ? 0 : shape];
+  return r.W * r.G;
+}
+
+template <int W, int G>
+__global__ __launch_bounds__(64 * W) void ens_reduced_k(const EnsRun* __restrict__ runs,
+                                                        EnsClasses cls,
+                                                        const int4* __restrict__ items,
+                                                        unsigned char* ws, int step,
+                                                        double* diag_out, long diag_stride) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun& R = runs[it.x];
+  const DevChunk& c = cls.c[R.cls].py;
+  double* dst = reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
+  const double* rho = reinterpret_cast<const double*>(ws + R.off_rho);
+  const double* part = reinterpret_cast<const double*>(ws + R.off_part);
+  double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
+                     ? diag_out + it.x * diag_stride + 2 * (long)step
+                     : nullptr;
+  extern __shared__ unsigned char smraw[];
+  reduced_body<2, double, double, W, G, 4>(rho, R.nx, R.Sc, c.blocks, c.dlo, c.dcount, dst, R.nx,
+                                           kChunk, kChunk - 2, part, R.ncolblocks,
+                                           cls.c[R.cls].K.dxdy, dout, it.y, it.z, smraw);
+}
+
 __global__ __launch_bounds__(512) void ens_reduced(const EnsRun* __restrict__ runs,
                                                    EnsClasses cls,
                                                    const int4* __restrict__ items,
@@ -1244,9 +1277,19 @@ hipError_t launch_ens_rows32(const EnsRun* runs, const EnsClasses& cls, const in
 
 hipError_t launch_ens_reduced(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                               int nitems, unsigned char* ws, int step, double* diag_out,
-                              long diag_stride, size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(ens_reduced, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs, cls,
-                     items, ws, step, diag_out, diag_stride);
+                              long diag_stride, size_t lds_bytes, hipStream_t st, int shape) {
+#define CHX_ENSRED(W_, G_)                                                                       \
+  hipLaunchKernelGGL((ens_reduced_k<W_, G_>), dim3(nitems), dim3(64 * W_), lds_bytes, st, runs, \
+                     cls, items, ws, step, diag_out, diag_stride)
+  switch (shape) {
+    case 1: CHX_ENSRED(8, 1); break;
+    case 2: CHX_ENSRED(4, 2); break;
+    case 3: CHX_ENSRED(4, 4); break;
+    default:
+      hipLaunchKernelGGL(ens_reduced, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs,
+                         cls, items, ws, step, diag_out, diag_stride);
+  }
+#undef CHX_ENSRED
   return hipGetLastError();
 }
 
@@ -1259,9 +1302,11 @@ hipError_t launch_ens_rows(const EnsRun* runs, const EnsClasses& cls, const int4
   return hipGetLastError();
 }
 
-size_t ens_reduced_lds_bytes(int dcount) {
-  size_t lds = (size_t)(kRedKB + dcount - 1) * 2 * 64 * sizeof(double);
-  if (lds < 2 * 512 * sizeof(double)) lds = 2 * 512 * sizeof(double);
+size_t ens_reduced_lds_bytes(int dcount, int shape) {
+  const int kb = shape == 0 ? kRedKB : ens_red_chunks_per_block(shape);
+  const int threads = 64 * kEnsRedShapes[(shape < 0 || shape >= kNumEnsRedShapes) ? 0 : shape].W;
+  size_t lds = (size_t)(kb + dcount - 1) * 2 * 64 * sizeof(double);
+  if (lds < 2 * (size_t)threads * sizeof(double)) lds = 2 * (size_t)threads * sizeof(double);
   return lds;
 }
 

@@ -308,3 +308,34 @@ def test_energy_decay_rate_per_run(chx, orc):
     for r in range(len(runs)):
         ref = orc.energy_decay_rate(d[r, :, 1], t0, dt)
         assert np.max(np.abs(b[r] - ref)) <= 1e-12 * np.max(np.abs(ref)), r
+
+
+def test_every_ensemble_separator_shape_bitwise(chx, orc):
+    """The FP64 ensemble's separator kernel shape (timed at creation): every
+    shape sums the same terms in the same order, so three steps of every
+    run are bitwise identical whatever the shape (graph replays re-captured
+    after each change), and each run matches the oracle."""
+    runs = [(256, 256, 1.0, 0.01, 1e-4, 91), (512, 256, 1.0, 0.01, 1e-4, 92),
+            (192, 320, 1.0, 0.02, 5e-5, 93)]
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, D, g, dt, seed) in runs]
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs])
+    assert 0 <= chx.ch_ensemble_get_tuning(ens) < chx.CHX_NUM_ENS_REDUCED_SHAPES
+    ref = None
+    k = 3
+    for shape in range(chx.CHX_NUM_ENS_REDUCED_SHAPES):
+        print(f"[case] ensemble separator shape {shape}", flush=True)
+        chx.ch_ensemble_set_tuning(ens, shape)
+        assert chx.ch_ensemble_get_tuning(ens) == shape
+        f = [torch.tensor(c, device="cuda") for c in c0]
+        chx.ch_ensemble_step(ens, f, nsteps=k, use_graph=True)
+        torch.cuda.synchronize()
+        out = [t.cpu().numpy() for t in f]
+        if ref is None:
+            ref = out
+        else:
+            for r in range(len(runs)):
+                assert np.array_equal(out[r], ref[r]), (shape, r)
+    for r, ((nx, ny, D, g, dt, _), c) in enumerate(zip(runs, c0)):
+        assert rel(ref[r], orc.ch_step(c, L, L, D, g, dt, nsteps=k)) < k * 1e-12, r
+    with pytest.raises(chx.ChxError):
+        chx.ch_ensemble_set_tuning(ens, chx.CHX_NUM_ENS_REDUCED_SHAPES)

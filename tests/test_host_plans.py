@@ -97,6 +97,7 @@ def test_shape_count_matches_header():
                  "CHX_TUNE_ROW_SPLIT", "CHX_NUM_SPLIT_SHAPES", "CHX_SCHEME_P1", "CHX_SCHEME_P2",
                  "CHX_TUNE_COLUMN_ORDER", "CHX_NUM_COLUMN_ORDERS", "CHX_NOALLOC_SCRATCH_BYTES",
                  "CHX_TUNE_GRAPH", "CHX_TUNE_COLUMN_CHUNK", "CHX_TUNE_ROW_CHUNK",
+                 "CHX_NUM_ENS_REDUCED_SHAPES",
                  "CHX_1D_HYPERDIFFUSION_CN", "CHX_1D_DIFFUSION_CN", "CHX_1D_CAHN_HILLIARD"):
         m = re.search(r"#define\s+" + name + r"\s+\(?(\d+)(u << (\d+)\))?", text)
         value = int(m.group(1)) << int(m.group(3) or 0) if m else None
@@ -298,6 +299,9 @@ def test_ensemble_extras_reject_bad_arguments_on_host(lib):
     assert lib.ch_ensemble_moments(None, None, None, d, None) == chx.CHX_EINVAL
     assert lib.ch_ensemble_k1(None, None, None, d, None) == chx.CHX_EINVAL
     assert lib.ch_ensemble_step(None, None, None, 1, None, None, 0, 0, None) == chx.CHX_EINVAL
+    v = ctypes.c_int()
+    assert lib.ch_ensemble_get_tuning(None, 0, ctypes.byref(v)) == chx.CHX_EINVAL
+    assert lib.ch_ensemble_set_tuning(None, 0, 0) == chx.CHX_EINVAL
 
 
 def test_decay_rate_rejects_bad_arguments_on_host(lib):
