@@ -2107,9 +2107,10 @@ static int ens_create_refined(chx_ens_s* E) {
       for (int k = 0; k <= prm[items[t].x].refine_passes; ++k) ++cnt[k];
   };
   E->o_col = (long)items.size();
-  for (int r : order)
-    for (int kc = 0; kc < E->runs[r].Sc; ++kc)
-      for (int sb = 0; sb < E->runs[r].ncb; ++sb) add(r, sb, kc);
+  for (int r : order) {  // blocks of four (segment, chunk) pairs of the run
+    const long pairs = (long)E->runs[r].nseg * E->runs[r].Sc;
+    for (long b = 0; b < (pairs + 3) / 4; ++b) add(r, (int)b, 0);
+  }
   prefix(E->rn_col, E->o_col);
   E->o_red = (long)items.size();
   for (int r : order) {

@@ -395,8 +395,11 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
                                                         unsigned char* ws) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  const int seg = it.y * 4 + (threadIdx.x >> 6);
-  if (seg >= R.nseg) return;  // no barrier in these kernels
+  // a run's (segment, chunk) pairs packed four to a block, so that blocks
+  // are full on grids whose rows span few 60-column segments
+  const int li = it.y * 4 + (threadIdx.x >> 6);
+  const int seg = li % R.nseg, kc = li / R.nseg;
+  if (kc >= R.Sc) return;  // no barrier in these kernels
   const EnsClass& C = cls.c[R.cls];
   BandT<float> bd;
 #pragma unroll
@@ -406,14 +409,14 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
   float* rho = reinterpret_cast<float*>(ws + R.off_rho32);
   if (PASS == 0 && !FROMV) {
     rstep_first_body<DIAG>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K,
-                           reinterpret_cast<double*>(ws + R.off_part), seg, it.z);
+                           reinterpret_cast<double*>(ws + R.off_part), seg, kc);
   } else if (PASS == 0) {  // the state rebuilt from the previous step's solutions
     double* part = reinterpret_cast<double*>(ws + R.off_part);
     const RBufs Bv = ens_vbufs(ws, R);
     switch (R.passes) {  // uniform per block
-      case 1: rstep_first_body<DIAG, 2>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
-      case 2: rstep_first_body<DIAG, 3>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
-      default: rstep_first_body<DIAG, 4>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, it.z, Bv, R.Sc, C.py.rec); break;
+      case 1: rstep_first_body<DIAG, 2>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
+      case 2: rstep_first_body<DIAG, 3>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
+      default: rstep_first_body<DIAG, 4>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
     }
   } else {
     BandT<double> ax, ay;
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
       ay.c[k] = C.py.coef[k];
     }
     rstep_resid_body<PASS>(rbuf, ens_vbufs(ws, R), y32, rho, R.nx, R.ny, R.Sc, C.py.rec,
-                           C.py.rec32, bd, ax, ay, seg, it.z);
+                           C.py.rec32, bd, ax, ay, seg, kc);
   }
 }
 
@@ -434,15 +437,16 @@ __global__ __launch_bounds__(256) void ens_rstep_final(const EnsRun* __restrict_
                                                        unsigned char* ws) {
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
-  const int seg = it.y * 4 + (threadIdx.x >> 6);
-  if (seg >= R.nseg) return;
+  const int li = it.y * 4 + (threadIdx.x >> 6);  // packed as in ens_rstep_column
+  const int seg = li % R.nseg, kc = li / R.nseg;
+  if (kc >= R.Sc) return;
   const EnsClass& C = cls.c[R.cls];
   const RBufs B = ens_vbufs(ws, R);
   double* part = reinterpret_cast<double*>(ws + R.off_part);
   switch (R.passes) {  // uniform per block
-    case 1: rstep_final_body<2, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
-    case 2: rstep_final_body<3, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
-    default: rstep_final_body<4, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, it.z); break;
+    case 1: rstep_final_body<2, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
+    case 2: rstep_final_body<3, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
+    default: rstep_final_body<4, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
   }
 }
 
