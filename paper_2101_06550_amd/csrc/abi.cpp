@@ -1219,6 +1219,11 @@ int ens_set_red_shape(chx_ens_s* E, int sh) {
   E->red_shape = sh;
   E->n_red = (int)red.size();
   E->red_lds = lds;
+  if (E->refined) {  // items of the runs that make refinement pass k (a prefix)
+    for (int k = 0; k < 4; ++k) E->rn_red[k] = 0;
+    for (const int4& it : red)
+      for (int k = 0; k <= E->prm[it.x].refine_passes; ++k) ++E->rn_red[k];
+  }
   return CHX_OK;
 }
 
@@ -1249,11 +1254,20 @@ int ens_tune_red(chx_ens_s* E, const std::vector<int>& order) {
     ok = hipMemcpy(E->ditems + E->o_red, red.data(), sizeof(int4) * red.size(),
                    hipMemcpyHostToDevice) == hipSuccess;
     const int n = (int)red.size();
-    // step 1 of a call: the column pass reads the scratch workspace's first
-    // buffer (step 0 would read the runs' own fields, which no call has set
-    // yet: null pointers here) and writes the second, which the separators
-    // then complete
+    // FP64: step 1 of a call, the column pass reads the scratch workspace's
+    // first buffer (step 0 would read the runs' own fields, which no call has
+    // set yet: null pointers here) and writes the second, which the
+    // separators then complete.  Refined: refinement pass 1 (its residual
+    // reads only workspace buffers) and its FP32 separators.
     const float ms = timer.time([&]() {
+      if (E->refined) {
+        hipError_t e = launch_ens_rstep_column(1, false, E->druns, E->hcls, E->ditems + E->o_col,
+                                               E->rn_col[1], ws, timer.st);
+        return e == hipSuccess
+                   ? launch_ens_reduced32(E->druns, E->hcls, E->ditems + E->o_red, n, ws, 1,
+                                          nullptr, 0, lds, timer.st, sh)
+                   : e;
+      }
       hipError_t e = launch_ens_column_pass(true, false, nullptr, E->druns, E->hcls,
                                             E->ditems + E->o_col, E->n_col, ws, 1, timer.st);
       return e == hipSuccess ? launch_ens_reduced(E->druns, E->hcls, E->ditems + E->o_red, n, ws,
@@ -1768,7 +1782,8 @@ int ens_launch_refined(chx_ens_s* E, int nsteps, double* diag_out, unsigned char
                                   E->rn_col[k], ws, st, k == 0 && n > 0);
       if (e == hipSuccess)
         e = launch_ens_reduced32(E->druns, E->hcls, it + E->o_red, E->rn_red[k], ws, n,
-                                 k == 0 ? diag_out : nullptr, dstride, E->red_lds, st);
+                                 k == 0 ? diag_out : nullptr, dstride, E->red_lds, st,
+                                 E->red_shape);
       if (e == hipSuccess)
         e = launch_ens_rows32(E->druns, E->hcls, it + E->o_row, E->rn_row[k], ws, k, st);
     }
@@ -2112,13 +2127,6 @@ static int ens_create_refined(chx_ens_s* E) {
     for (long b = 0; b < (pairs + 3) / 4; ++b) add(r, (int)b, 0);
   }
   prefix(E->rn_col, E->o_col);
-  E->o_red = (long)items.size();
-  for (int r : order) {
-    const int nby = (E->runs[r].Sc + 31) / 32, nbx = (E->runs[r].nx + 63) / 64;
-    for (int by = 0; by < nby; ++by)
-      for (int bx = 0; bx < nbx; ++bx) add(r, bx, by);
-  }
-  prefix(E->rn_red, E->o_red);
   E->o_row = (long)items.size();
   for (int r : order) {
     const int S = E->runs[r].nx / kChunk, R = 256 / S;
@@ -2126,10 +2134,24 @@ static int ens_create_refined(chx_ens_s* E) {
     for (int g = 0; g < ng; ++g) add(r, g, 0);
   }
   prefix(E->rn_row, E->o_row);
+  // the separator items last: their count depends on the tile shape that
+  // creation times (room for the shape with the most blocks)
+  E->o_red = (long)items.size();
+  size_t max_red = 0;
+  for (int sh = 0; sh < kNumEnsRedShapes; ++sh)
+    max_red = std::max(max_red, ens_red_items(E, order, sh).size());
+  {
+    const auto red = ens_red_items(E, order, 0);
+    items.insert(items.end(), red.begin(), red.end());
+  }
+  prefix(E->rn_red, E->o_red);
+  E->n_red = (int)(items.size() - E->o_red);
+  E->red_order = order;
   E->nbig = nruns;
   for (size_t c = 0; c < E->classes.size(); ++c) E->hcls.c[c] = E->classes[c];
   const size_t b_runs = align256(sizeof(EnsRun) * nruns);
-  const size_t b_items = align256(sizeof(int4) * std::max<size_t>(items.size(), 1));
+  const size_t b_items =
+      align256(sizeof(int4) * std::max<size_t>(E->o_red + max_red, 1));
   const size_t b_lists = align256(sizeof(int) * nruns);
   if (hipMalloc(&E->dmem, b_runs + b_items + b_lists) != hipSuccess) {
     E->dmem = nullptr;
@@ -2145,7 +2167,7 @@ static int ens_create_refined(chx_ens_s* E) {
                       hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(E->dbig, order.data(), sizeof(int) * nruns, hipMemcpyHostToDevice) ==
                 hipSuccess;
-  return ok ? CHX_OK : CHX_EHIP;
+  return ok ? ens_tune_red(E, order) : CHX_EHIP;
 }
 
 int ch_ensemble_create(int nruns, const chx_ch_params* prm, chx_ens* out) {
@@ -2347,7 +2369,7 @@ int ch_ensemble_get_tuning(chx_ens e, int what, int* value) {
 static void ens_drop_graph(chx_ens E);
 
 int ch_ensemble_set_tuning(chx_ens e, int what, int value) {
-  if (!e || what != CHX_TUNE_REDUCED_SHAPE || e->refined) return CHX_EINVAL;
+  if (!e || what != CHX_TUNE_REDUCED_SHAPE) return CHX_EINVAL;
   if (value < 0 || value >= kNumEnsRedShapes) return CHX_EINVAL;
   if (e->nbig == 0) return value == 0 ? CHX_OK : CHX_EINVAL;
   // queued work may still read the work items

@@ -92,7 +92,8 @@ hipError_t launch_ens_rstep_column(int pass, bool diag, const EnsRun* runs, cons
 // energy) of step `step` (the pass-0 partials).
 hipError_t launch_ens_reduced32(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                                 int nitems, unsigned char* ws, int step, double* diag_out,
-                                long diag_stride, size_t lds_bytes, hipStream_t st);
+                                long diag_stride, size_t lds_bytes, hipStream_t st,
+                                int shape = 0);
 // FP32 row solves of the column buffer into V_pass.
 hipError_t launch_ens_rows32(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                              int nitems, unsigned char* ws, int pass, hipStream_t st);

@@ -1218,6 +1218,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
 // FP32-refined ensembles: separators of the FP32 column buffer (dout: the
 // pass-0 diagnostics of the run's state at `step`), and FP32 row solves of it
 // into the run's V_pass.
+template <int W, int G>
+__global__ __launch_bounds__(64 * W) void ens_reduced32_k(const EnsRun* __restrict__ runs,
+                                                          EnsClasses cls,
+                                                          const int4* __restrict__ items,
+                                                          unsigned char* ws, int step,
+                                                          double* diag_out, long diag_stride) {
+  const int4 it = items[blockIdx.x];
+  const EnsRun& R = runs[it.x];
+  const DevChunk& c = cls.c[R.cls].py;
+  float* dst = reinterpret_cast<float*>(ws + R.off_y32);
+  const float* rho = reinterpret_cast<const float*>(ws + R.off_rho32);
+  const double* part = reinterpret_cast<const double*>(ws + R.off_part);
+  double* dout = (diag_out != nullptr && it.y == 0 && it.z == 0)
+                     ? diag_out + it.x * diag_stride + 2 * (long)step
+                     : nullptr;
+  extern __shared__ unsigned char smraw[];
+  reduced_body<2, float, float, W, G, 4>(rho, R.nx, R.Sc, c.blocks32, c.dlo, c.dcount, dst, R.nx,
+                                         kChunk, kChunk - 2, part, R.ncolblocks,
+                                         cls.c[R.cls].K.dxdy, dout, it.y, it.z, smraw);
+}
+
 __global__ __launch_bounds__(512) void ens_reduced32(const EnsRun* __restrict__ runs,
                                                      EnsClasses cls,
                                                      const int4* __restrict__ items,
@@ -1261,10 +1282,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 
 hipError_t launch_ens_reduced32(const EnsRun* runs, const EnsClasses& cls, const int4* items,
                                 int nitems, unsigned char* ws, int step, double* diag_out,
-                                long diag_stride, size_t lds_bytes, hipStream_t st) {
+                                long diag_stride, size_t lds_bytes, hipStream_t st, int shape) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ens_reduced32, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs, cls,
-                     items, ws, step, diag_out, diag_stride);
+#define CHX_ENSRED32(W_, G_)                                                                   \
+  hipLaunchKernelGGL((ens_reduced32_k<W_, G_>), dim3(nitems), dim3(64 * W_), lds_bytes, st, \
+                     runs, cls, items, ws, step, diag_out, diag_stride)
+  switch (shape) {
+    case 1: CHX_ENSRED32(8, 1); break;
+    case 2: CHX_ENSRED32(4, 2); break;
+    case 3: CHX_ENSRED32(4, 4); break;
+    default:
+      hipLaunchKernelGGL(ens_reduced32, dim3(nitems), dim3(64 * kRedWaves), lds_bytes, st, runs,
+                         cls, items, ws, step, diag_out, diag_stride);
+  }
+#undef CHX_ENSRED32
   return hipGetLastError();
 }
 

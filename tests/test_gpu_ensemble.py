@@ -339,3 +339,29 @@ def test_every_ensemble_separator_shape_bitwise(chx, orc):
         assert rel(ref[r], orc.ch_step(c, L, L, D, g, dt, nsteps=k)) < k * 1e-12, r
     with pytest.raises(chx.ChxError):
         chx.ch_ensemble_set_tuning(ens, chx.CHX_NUM_ENS_REDUCED_SHAPES)
+
+
+def test_every_refined_ensemble_separator_shape_bitwise(chx, orc):
+    """Refined ensembles time their FP32 separator kernel's tile shape too:
+    every shape gives bitwise identical runs, each within the refined target
+    of the oracle."""
+    runs = [(256, 256, 1.0, 0.01, 1e-4, 94), (128, 256, 1.0, 0.01, 1e-4, 95)]
+    c0 = [inputs.noise_field(ny, nx, seed) for (nx, ny, D, g, dt, seed) in runs]
+    ens = chx.ch_ensemble_create([(nx, ny, L, L, D, g, dt) for (nx, ny, D, g, dt, _) in runs],
+                                 dtype=chx.CHX_F32_REFINED, refine_passes=2)
+    ref = None
+    k = 2
+    for shape in range(chx.CHX_NUM_ENS_REDUCED_SHAPES):
+        print(f"[case] refined ensemble separator shape {shape}", flush=True)
+        chx.ch_ensemble_set_tuning(ens, shape)
+        f = [torch.tensor(c, device="cuda") for c in c0]
+        chx.ch_ensemble_step(ens, f, nsteps=k, use_graph=True)
+        torch.cuda.synchronize()
+        out = [t.cpu().numpy() for t in f]
+        if ref is None:
+            ref = out
+        else:
+            for r in range(len(runs)):
+                assert np.array_equal(out[r], ref[r]), (shape, r)
+    for r, ((nx, ny, D, g, dt, _), c) in enumerate(zip(runs, c0)):
+        assert rel(ref[r], orc.ch_step(c, L, L, D, g, dt, nsteps=k)) < k * 1e-10, r
