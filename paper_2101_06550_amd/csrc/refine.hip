@@ -337,8 +337,8 @@ __device__ __forceinline__ void rstep_final_body(const RBufs& B, double* __restr
   }
 }
 
-// Single-field kernels: block = 4 waves = 4 consecutive 60-column segments
-// of chunk blockIdx.y.
+// Single-field kernels: block = 4 waves = 4 consecutive (60-column segment,
+// chunk) pairs, segments fastest (full blocks whatever the segment count).
 template <bool DIAG, int NB>
 __global__ __launch_bounds__(256) void rstep_first(const double* __restrict__ c, long ld,
                                                    double* __restrict__ rbuf,
@@ -348,10 +348,11 @@ __global__ __launch_bounds__(256) void rstep_first(const double* __restrict__ c,
                                                    BandT<float> bd, ChCoef K,
                                                    double* __restrict__ part, RBufs Bv, int Sc,
                                                    const double* __restrict__ rec) {
-  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= nseg) return;  // no barrier in this kernel
-  rstep_first_body<DIAG, NB>(c, ld, rbuf, y32, rho, nx, ny, nseg, rec32, bd, K, part, seg,
-                             blockIdx.y, Bv, Sc, rec);
+  const int li = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int seg = li % nseg, kc = li / nseg;
+  if (kc >= Sc) return;  // no barrier in this kernel
+  rstep_first_body<DIAG, NB>(c, ld, rbuf, y32, rho, nx, ny, nseg, rec32, bd, K, part, seg, kc,
+                             Bv, Sc, rec);
 }
 
 template <int NB>
@@ -363,9 +364,10 @@ __global__ __launch_bounds__(256) void rstep_resid(const double* __restrict__ rb
                                                    const float* __restrict__ rec32,
                                                    BandT<float> bd, BandT<double> ax,
                                                    BandT<double> ay) {
-  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= nseg) return;  // no barrier in this kernel
-  rstep_resid_body<NB>(rbuf, B, y32, rho, nx, ny, Sc, rec, rec32, bd, ax, ay, seg, blockIdx.y);
+  const int li = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int seg = li % nseg, kc = li / nseg;
+  if (kc >= Sc) return;  // no barrier in this kernel
+  rstep_resid_body<NB>(rbuf, B, y32, rho, nx, ny, Sc, rec, rec32, bd, ax, ay, seg, kc);
 }
 
 template <int NB, bool DIAG>
@@ -373,9 +375,10 @@ __global__ __launch_bounds__(256) void rstep_final(RBufs B, double* __restrict__
                                                    int nx, int ny, int nseg, int Sc,
                                                    const double* __restrict__ rec, ChCoef K,
                                                    double* __restrict__ part) {
-  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= nseg) return;  // no barrier in this kernel
-  rstep_final_body<NB, DIAG>(B, c, ld, nx, ny, nseg, Sc, rec, K, part, seg, blockIdx.y);
+  const int li = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int seg = li % nseg, kc = li / nseg;
+  if (kc >= Sc) return;  // no barrier in this kernel
+  rstep_final_body<NB, DIAG>(B, c, ld, nx, ny, nseg, Sc, rec, K, part, seg, kc);
 }
 
 // Ensemble kernels: block = work item {run, segment block, chunk}; each run
@@ -492,8 +495,8 @@ int rstep_segments(int nx) { return (nx + kSegR - 1) / kSegR; }
 long rstep_parts(int nx, int ny) { return (long)rstep_segments(nx) * (ny / M); }
 
 static dim3 rstep_grid(int nx, int ny) {
-  const int nseg = (nx + kSegR - 1) / kSegR;
-  return dim3((unsigned)((nseg + 3) / 4), (unsigned)(ny / M));
+  const long pairs = (long)((nx + kSegR - 1) / kSegR) * (ny / M);
+  return dim3((unsigned)((pairs + 3) / 4));
 }
 
 hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
