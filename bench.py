@@ -932,7 +932,7 @@ def main():
     if args.summarize_trace:
         cmd = ("rocprofv3 --kernel-trace --stats -T -d " + os.path.relpath(args.summarize_trace) +
                " -o run --output-format csv -- python3 bench.py --no-cpu-baseline --large-only "
-               "--calibrate-copy --steps 20 --warmup 2")
+               "--calibrate-copy --steps 500 --warmup 10")
         print(json.dumps(summarize_trace(args.summarize_trace, KERNEL_PROFILE, cmd,
                                          args.trace_note)))
         return
