@@ -734,21 +734,30 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
   const int k0 = by * KB;
   const int nwin = KB + dcount - 1;
   const bool sv = s < batch;
+  // Every load of a pass is issued before any result is used: an entry past
+  // the window re-reads the last one and a system past the batch re-reads the
+  // last system (both in bounds, neither stored), so no load sits behind a
+  // branch and the U * 2P loads of a lane are in flight together.
+  const long sl = sv ? s : (long)batch - 1;
   for (int w0 = wave; w0 < nwin; w0 += W * U) {
     T v[U][P];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int w = w0 + W * u;
-      int j = k0 + dlo + w;
-      while (j >= S) j -= S;
-      while (j < 0) j += S;
+      const int w = min(w0 + W * u, nwin - 1);
+      int j = (k0 + dlo + w) % S;
+      j += (j < 0) ? S : 0;
       const int jn = (j + 1 == S) ? 0 : j + 1;
 #pragma unroll
       for (int a = 0; a < P; ++a)
-        v[u][a] = (sv && w < nwin) ? rho[((long)j * 2 * P + a) * batch + s] -
-                                         rho[((long)jn * 2 * P + P + a) * batch + s]
-                                   : T(0);
+        v[u][a] = rho[((long)j * 2 * P + a) * batch + sl] -
+                  rho[((long)jn * 2 * P + P + a) * batch + sl];
     }
+    // keeps the compiler from sinking an entry's loads into the branch of
+    // its LDS store below, which would wait on them one entry at a time
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int a = 0; a < P; ++a) asm volatile("" : "+v"(v[u][a]));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int w = w0 + W * u;
@@ -766,22 +775,29 @@ __device__ __forceinline__ void reduced_body(const T* __restrict__ rho, int batc
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int a = 0; a < P; ++a) acc[g][a] = 0;
-    // window entry kk0 + u feeds output g through block t = u - g
-    for (int u = 0; u < G + dcount - 1; ++u) {
-      T rv[P];
+    // Output g takes block t against window entry kk0 + g + t, t ascending;
+    // win[g] holds that entry, so the G entries slide one place per block and
+    // every entry is read from LDS once.
+    T win[G][P];
 #pragma unroll
-      for (int c = 0; c < P; ++c) rv[c] = sm[((kk0 + u) * P + c) * 64 + lane];
+    for (int g = 0; g + 1 < G; ++g)
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int t = u - g;
-        if (t >= 0 && t < dcount) {
-          const T* B = blocks + t * 4;
+      for (int c = 0; c < P; ++c) win[g + 1][c] = sm[((kk0 + g) * P + c) * 64 + lane];
+#pragma unroll 4
+    for (int t = 0; t < dcount; ++t) {
 #pragma unroll
-          for (int a = 0; a < P; ++a)
+      for (int g = 0; g + 1 < G; ++g)
 #pragma unroll
-            for (int c = 0; c < P; ++c) acc[g][a] = acc[g][a] + B[a * 2 + c] * rv[c];
-        }
-      }
+        for (int c = 0; c < P; ++c) win[g][c] = win[g + 1][c];
+#pragma unroll
+      for (int c = 0; c < P; ++c) win[G - 1][c] = sm[((kk0 + t + G - 1) * P + c) * 64 + lane];
+      const T* B = blocks + t * 4;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int c = 0; c < P; ++c) acc[g][a] = acc[g][a] + B[a * 2 + c] * win[g][c];
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
