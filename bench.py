@@ -35,6 +35,7 @@ KERNEL_PROFILE = os.path.join(ROOT, "profiles", "ch_adi_8192x8192_fp64_kernel_st
 KERNEL_OF_PHASE = {"column_pass": "ch_column_pass", "column_separators": "reduced_il_lds",
                    "row_pass": "row_solve_half", "separator_rows": "rows_sep",
                    "separators_and_interior_rows": "rows_split_fused"}
+FIRST_WHOLE_COLUMN_SHAPE = 12  # separator shapes from here on run reduced_whole
 HBM_PEAK_GBS = 8000.0
 CHUNK = 32  # unknowns per thread-chunk in the library's chunked kernels
 
@@ -140,7 +141,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, command):
     lines += ["", "Algorithmic bytes per dispatch at 8192 x 8192 (what bench.py divides by "
               "the launch time): ch_column_pass 1107.3 MB (read c, write the "
               "half-solved field and the separator right-hand sides, read the previous "
-              "step's separator corrections), reduced_il_lds 100.7 MB, row_solve_lds "
+              "step's separator corrections), the separator kernel (reduced_whole or "
+              "reduced_il_lds) 100.7 MB, row_solve_half "
               "1073.7 MB (read and write the field once).",
               "", "Valid for the library sources with this hash (bench.py reports `traffic` only "
               "while it matches):", "", "<!-- traffic-json: " + json.dumps(blob) + " -->", ""]
@@ -1062,8 +1064,11 @@ def main():
     dom = max((k for k in range(3) if phase_n[k]), key=lambda k: phase_ms[k])
     dom_avg = phase_ms[dom] / phase_n[dom]
     achieved = bytes_per[dom] / (dom_avg * 1e-3) / 1e9
-    traffic = stored_traffic(KERNEL_OF_PHASE[names[dom]])
-    roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE[names[dom]],
+    kernel_of = dict(KERNEL_OF_PHASE)
+    if chx.ch_get_tuning(h) >= FIRST_WHOLE_COLUMN_SHAPE:
+        kernel_of["column_separators"] = "reduced_whole"
+    traffic = stored_traffic(kernel_of[names[dom]])
+    roofline = {"bound": "hbm", "kernel": kernel_of[names[dom]],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic)}

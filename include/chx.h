@@ -371,7 +371,10 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   bit.  Setting 1 where it does not fit is CHX_EINVAL.
  * CHX_TUNE_REDUCED_SHAPE: tile shape of the multi-kernel path's column
  *   separator kernel (0 .. CHX_NUM_REDUCED_SHAPES-1: waves per block x chunks
- *   per wave x window entries staged at once).  ch_create times every
+ *   per wave x window entries staged at once, or, for the last three, every
+ *   chunk of 32 or 16 systems per block, which loads each separator part
+ *   once; a shape that does not fit the handle's chunk count or the LDS
+ *   runs as shape 0).  ch_create times every
  *   candidate inside whole steps (column pass, separators, rows, for each
  *   chunk length) on zeroed scratch buffers of the handle's size and keeps
  *   the fastest; the choices (this shape, the row split, the column order
@@ -427,7 +430,7 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
 #define CHX_TUNE_REDUCED_SHAPE 0
 #define CHX_TUNE_SMALL_PATH 1
 #define CHX_TUNE_ROW_SPLIT 2
-#define CHX_NUM_REDUCED_SHAPES 12
+#define CHX_NUM_REDUCED_SHAPES 15
 #define CHX_NUM_SPLIT_SHAPES 3
 #define CHX_ROW_SPLIT_OVERLAP (-2)
 #define CHX_TUNE_COLUMN_ORDER 3

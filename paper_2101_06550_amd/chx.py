@@ -662,7 +662,7 @@ def batch1d_step_rewrite(b: Batch1D, x, nsteps: int = 1, ws=None, ld: int | None
 CHX_TUNE_REDUCED_SHAPE = 0
 CHX_TUNE_SMALL_PATH = 1
 CHX_TUNE_ROW_SPLIT = 2
-CHX_NUM_REDUCED_SHAPES = 12
+CHX_NUM_REDUCED_SHAPES = 15
 CHX_ROW_SPLIT_OVERLAP = -2
 CHX_NUM_SPLIT_SHAPES = 3
 CHX_TUNE_COLUMN_ORDER = 3

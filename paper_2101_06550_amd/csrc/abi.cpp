@@ -844,7 +844,7 @@ constexpr int kSplitOverlap = -2;
 bool rows16_fit(const BandPlan* px) { return px->has_chunk16 && px->dchunk16.S <= 256; }
 
 // Persistent tuning cache: a text file with one line per tuned size,
-//   chx-tune-2 <arch> <nx> <ny> <column plan S dlo dcount> <row plan S dlo dcount>
+//   chx-tune-3 <arch> <nx> <ny> <column plan S dlo dcount> <row plan S dlo dcount>
 //       <separator shape> <row split> <column order> <column chunk> <row chunk>
 // at $CHX_TUNE_CACHE, else $XDG_CACHE_HOME/chx/tuning.txt, else
 // $HOME/.cache/chx/tuning.txt; CHX_TUNE_CACHE=0 turns it off.  Lines are only
@@ -876,7 +876,7 @@ std::string device_arch() {
 std::string tune_key_text(const std::string& arch, int nx, int ny, const DevChunk& cy,
                           const DevChunk& cx) {
   char buf[256];
-  std::snprintf(buf, sizeof buf, "chx-tune-2 %s %d %d %d %d %d %d %d %d", arch.c_str(), nx, ny,
+  std::snprintf(buf, sizeof buf, "chx-tune-3 %s %d %d %d %d %d %d %d %d", arch.c_str(), nx, ny,
                 cy.S, cy.dlo, cy.dcount, cx.S, cx.dlo, cx.dcount);
   return buf;
 }
@@ -995,7 +995,7 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   float best_ms = -1.f;
   const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
   for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
-    if (reduced_lds_bytes(shape, 2, sizeof(double), c.dcount, true) > max_lds) continue;
+    if (reduced_lds_bytes(shape, 2, sizeof(double), c.S, c.dcount, true) > max_lds) continue;
     trial.red_shape = shape;
     const float ms = time_it([&]() {
       hipError_t e = launch_reduced_il<2>(trial, rho, nx, dst, nx, kChunk, kChunk - 2, st);
@@ -1062,7 +1062,7 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
         float pair_ms = -1.f;
         int pair_shape = 0;
         for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
-          if (reduced_lds_bytes(shape, 2, sizeof(double), cy.dcount, true) > max_lds) continue;
+          if (reduced_lds_bytes(shape, 2, sizeof(double), cy.S, cy.dcount, true) > max_lds) continue;
           cy.red_shape = shape;
           const float ms = time_it([&]() {
             hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho,
@@ -1130,7 +1130,7 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
 
 // The FP32 separator kernel's tile shape for refined handles, timed inside a
 // refinement pass (residual and column sweep, separators, row solves) on
-// zeroed buffers; cached like tune_step's choices (key "chx-tune-2r ...").
+// zeroed buffers; cached like tune_step's choices (key "chx-tune-3r ...").
 int tune_refined(const BandPlan* py, const BandPlan* px, int nx, int ny, const double* cxs,
                  const double* cys) {
   const DevChunk& c = py->dchunk;
@@ -1143,7 +1143,7 @@ int tune_refined(const BandPlan* py, const BandPlan* px, int nx, int ny, const d
   if (env && env[0] == '0') return 0;
   const std::string cache_path = tune_cache_path();
   std::string cache_key = tune_key_text(device_arch(), nx, ny, c, px->dchunk);
-  cache_key.replace(0, 10, "chx-tune-2r");
+  cache_key.replace(0, 10, "chx-tune-3r");
   Tuned t;
   if (tune_cache_lookup(cache_path, cache_key, &t)) {
     cache[key] = t.red_shape;
@@ -1168,7 +1168,7 @@ int tune_refined(const BandPlan* py, const BandPlan* px, int nx, int ny, const d
   float best_ms = -1.f;
   const size_t max_lds = std::min(device_max_lds(), kMaxLdsBytes);
   for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
-    if (reduced_lds_bytes(shape, 2, sizeof(float), c.dcount, false) > max_lds) continue;
+    if (reduced_lds_bytes(shape, 2, sizeof(float), c.S, c.dcount, false) > max_lds) continue;
     trial.red_shape = shape;
     const float ms = timer.time([&]() {
       hipError_t e = launch_rstep_resid(r, V, 1, y32, rho, nx, ny, c, cxs, cys, timer.st);

@@ -31,10 +31,11 @@ struct DevChunk {
 // Number of candidate tile shapes of the separator kernel, and the LDS one
 // launch of shape `shape` needs (elem = sizeof the sweep type; diag = the
 // launch also finishes the diagnostics sum).
-constexpr int kNumRedShapes = 12;
+constexpr int kNumRedShapes = 15;
 // LDS one workgroup may allocate on gfx950 (160 KB per CU)
 constexpr size_t kMaxLdsBytes = 160 * 1024;
-size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag);
+// (~0 when the shape cannot take S chunks)
+size_t reduced_lds_bytes(int shape, int P, size_t elem, int S, int dcount, bool diag);
 
 // Split row pass of the ADI step (penta, FP64, rows of 4096 or 8192 points):
 // column separators fused with the interior rows, then the separator rows.

@@ -827,6 +827,103 @@ __global__ __launch_bounds__(64 * W) void reduced_il_lds(const T* __restrict__ r
                                   blockIdx.x, blockIdx.y, smraw);
 }
 
+// Whole-column form of the same convolution: a block owns L systems and all
+// S chunks of them, so every rho_j is loaded once (the windowed form loads
+// each KB + dcount - 1 times per KB chunks) and the periodic window wraps
+// inside LDS.  Thread (c, q) = (threadIdx.x % L, threadIdx.x / L) stages
+// entries q, q + NQ, ... and computes chunks q G .. q G + G - 1 of system c,
+// each summing its dcount terms in the windowed form's order (bitwise equal).
+template <int P, typename T, typename Td, int L, int G>
+__global__ __launch_bounds__(1024) void reduced_whole(const T* __restrict__ rho, int batch, int S,
+                                                      const T* __restrict__ blocks, int dlo,
+                                                      int dcount, Td* __restrict__ dst, long ld,
+                                                      int drow_stride, int drow_off,
+                                                      const double* __restrict__ dpart,
+                                                      long dnparts, double dscale,
+                                                      double* __restrict__ dout) {
+  extern __shared__ unsigned char smraw[];
+  T* sm = reinterpret_cast<T*>(smraw);
+  const int NQ = (S + G - 1) / G;  // chunk groups, one per L threads
+  const int c = threadIdx.x % L, q = threadIdx.x / L;
+  const long s = (long)blockIdx.x * L + c;
+  const bool sv = s < batch;
+  const long sl = sv ? s : (long)batch - 1;
+  if (q < NQ) {
+    // G passes of NQ entries cover the S chunks; an entry past S re-reads
+    // chunk S - 1 (not stored), so all loads issue before any is used
+    T v[G][P];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int j = min(q + NQ * u, S - 1);
+      const int jn = (j + 1 == S) ? 0 : j + 1;
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+        v[u][a] = rho[((long)j * 2 * P + a) * batch + sl] -
+                  rho[((long)jn * 2 * P + P + a) * batch + sl];
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int a = 0; a < P; ++a) asm volatile("" : "+v"(v[u][a]));
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int j = q + NQ * u;
+      if (j < S) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) sm[(j * P + a) * L + c] = v[u][a];
+      }
+    }
+  }
+  __syncthreads();
+  const int k0 = q * G;
+  if (sv && k0 < S) {
+    T acc[G][P];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int a = 0; a < P; ++a) acc[g][a] = 0;
+    // output g takes block t against chunk (k0 + g + dlo + t) mod S; win[g]
+    // holds that entry and idx is the chunk entering the window next
+    int idx = (k0 + dlo) % S;
+    idx += (idx < 0) ? S : 0;
+    T win[G][P];
+#pragma unroll
+    for (int g = 0; g + 1 < G; ++g) {
+#pragma unroll
+      for (int a = 0; a < P; ++a) win[g + 1][a] = sm[(idx * P + a) * L + c];
+      idx = (idx + 1 == S) ? 0 : idx + 1;
+    }
+#pragma unroll 4
+    for (int t = 0; t < dcount; ++t) {
+#pragma unroll
+      for (int g = 0; g + 1 < G; ++g)
+#pragma unroll
+        for (int a = 0; a < P; ++a) win[g][a] = win[g + 1][a];
+#pragma unroll
+      for (int a = 0; a < P; ++a) win[G - 1][a] = sm[(idx * P + a) * L + c];
+      idx = (idx + 1 == S) ? 0 : idx + 1;
+      const T* B = blocks + t * 4;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int b = 0; b < P; ++b) acc[g][a] = acc[g][a] + B[a * 2 + b] * win[g][b];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k = k0 + g;
+      if (k < S) {
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          dst[((long)k * drow_stride + drow_off + a) * ld + s] = (Td)acc[g][a];
+      }
+    }
+  }
+  if (dout != nullptr && blockIdx.x == 0)
+    diag_tail_sum(dpart, dnparts, dscale, dout, reinterpret_cast<double*>(smraw));
+}
+
 template <typename T>
 static BandT<T> band_of(const double* coef) {
   BandT<T> bd;
@@ -1389,20 +1486,31 @@ hipError_t launch_whole32(const DevWhole& w, double* work, long ss, long es, dou
 }
 
 // Candidate tile shapes of the separator kernel: (waves per block, chunks
-// per wave, window entries staged per wave at once).
+// per wave, window entries staged per wave at once), or for the
+// whole-column form (L > 0) L systems per block and G chunks per thread.
 struct RedShape {
-  int W, G, U;
+  int W, G, U, L;
 };
 // (7, 8: larger windows, whose LDS only gfx950's 160 KB holds at the decay
 // windows of large grids; 9 .. 11: few chunks per block, for small grids
-// where the chunk count is too low to fill the chip with the others)
-constexpr RedShape kRedShapes[kNumRedShapes] = {{8, 4, 4},  {8, 4, 8},  {8, 2, 4}, {4, 8, 4},
-                                                {4, 8, 8},  {4, 4, 4},  {16, 2, 4}, {16, 3, 4},
-                                                {16, 4, 4}, {4, 1, 8},  {4, 2, 8}, {8, 1, 8}};
+// where the chunk count is too low to fill the chip with the others;
+// 12 .. 14: whole columns, S P L elements of LDS)
+constexpr RedShape kRedShapes[kNumRedShapes] = {
+    {8, 4, 4, 0},  {8, 4, 8, 0},  {8, 2, 4, 0}, {4, 8, 4, 0},  {4, 8, 8, 0},
+    {4, 4, 4, 0},  {16, 2, 4, 0}, {16, 3, 4, 0}, {16, 4, 4, 0}, {4, 1, 8, 0},
+    {4, 2, 8, 0},  {8, 1, 8, 0},  {0, 8, 0, 32}, {0, 4, 0, 16}, {0, 8, 0, 16}};
 
-size_t reduced_lds_bytes(int shape, int P, size_t elem, int dcount, bool diag) {
+// threads of a whole-column launch (at least 256 for the diagnostics sum)
+static int whole_threads(const RedShape& r, int S) {
+  const int t = ((r.L * ((S + r.G - 1) / r.G) + 63) / 64) * 64;
+  return t < 256 ? 256 : t;
+}
+
+size_t reduced_lds_bytes(int shape, int P, size_t elem, int S, int dcount, bool diag) {
   const RedShape& r = kRedShapes[shape];
-  size_t lds = (size_t)(r.W * r.G + dcount - 1) * P * 64 * elem;
+  if (r.L > 0 && whole_threads(r, S) > 1024) return ~(size_t)0;
+  size_t lds = r.L > 0 ? (size_t)S * P * r.L * elem
+                       : (size_t)(r.W * r.G + dcount - 1) * P * 64 * elem;
   const size_t dmin = 2 * (size_t)256 * sizeof(double);
   if (diag && lds < dmin) lds = dmin;
   return lds;
@@ -1424,12 +1532,25 @@ static hipError_t reduced_any(const DevChunk& c, const T* rho, const T* blocks, 
                               const double* dpart, long dnparts, double dscale, double* dout,
                               int shape) {
   if (shape < 0 || shape >= kNumRedShapes) shape = 0;
-  size_t lds = reduced_lds_bytes(shape, P, sizeof(T), c.dcount, dout != nullptr);
+  size_t lds = reduced_lds_bytes(shape, P, sizeof(T), c.S, c.dcount, dout != nullptr);
   if (lds > kMaxLdsBytes && shape != 0) {
     shape = 0;
-    lds = reduced_lds_bytes(0, P, sizeof(T), c.dcount, dout != nullptr);
+    lds = reduced_lds_bytes(0, P, sizeof(T), c.S, c.dcount, dout != nullptr);
   }
-  if (lds <= kMaxLdsBytes) {
+  if (lds <= kMaxLdsBytes && kRedShapes[shape].L > 0) {
+    const RedShape& r = kRedShapes[shape];
+    const dim3 grid((batch + r.L - 1) / r.L), block(whole_threads(r, c.S));
+#define CHX_WHOLE(L_, G_)                                                                   \
+  hipLaunchKernelGGL((reduced_whole<P, T, Td, L_, G_>), grid, block, lds, st, rho, batch, c.S, \
+                     blocks, c.dlo, c.dcount, dst, ld, drow_stride, drow_off, dpart, dnparts,  \
+                     dscale, dout)
+    switch (shape) {
+      case 12: CHX_WHOLE(32, 8); break;
+      case 13: CHX_WHOLE(16, 4); break;
+      default: CHX_WHOLE(16, 8); break;
+    }
+#undef CHX_WHOLE
+  } else if (lds <= kMaxLdsBytes) {
     const RedShape& r = kRedShapes[shape];
     const int kb = r.W * r.G;
     dim3 grid((batch + 63) / 64, (c.S + kb - 1) / kb);

@@ -328,7 +328,7 @@ def test_tuning_cache_file_is_reused_across_processes(tmp_path):
         assert r.returncode == 0, r.stderr[-2000:]
         outs.append(r.stdout.strip().splitlines()[-1])
         lines = cache.read_text().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("chx-tune-2 gfx"), lines
+        assert len(lines) == 1 and lines[0].startswith("chx-tune-3 gfx"), lines
         assert " 2048 1024 " in lines[0]
     assert outs[0] == outs[1]
     assert lines[0].split()[-5:] == [v.strip() for v in outs[0].strip("[]").split(",")]
