@@ -59,8 +59,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 // State value at row-position p (0..M-1) of a chunk for one column, given V
 // at that row and the separator rows (row-solved values T) of the previous
 // chunk (tp) and of the chunk itself (to).  Separator rows are the state.
-template <bool RECON, int MM = kChunk>
-__device__ __forceinline__ double recon_value(double v, int p, const double* __restrict__ rec,
+template <bool RECON, int MM = kChunk, typename RecP>
+__device__ __forceinline__ double recon_value(double v, int p, RecP __restrict__ rec,
                                               const double (&tp)[P], const double (&to)[P]) {
   constexpr int MMI = MM - P;
   if (!RECON || p >= MMI) return v;
@@ -78,8 +78,8 @@ __device__ __forceinline__ double recon_value(double v, int p, const double* __r
 // lane-0 and lane-63 state values are exchanged through LDS (one barrier),
 // and the two columns just outside the block are loaded and reconstructed by
 // 68 threads of the block before the barrier.
-template <bool RECON, int MM = kChunk>
-__device__ __forceinline__ double recon_row(double v, int q, const double* __restrict__ rec,
+template <bool RECON, int MM = kChunk, typename RecP>
+__device__ __forceinline__ double recon_row(double v, int q, RecP __restrict__ rec,
                                             const double (&tp)[P], const double (&to)[P],
                                             const double (&tn)[P]) {
   // q = 0: last row of chunk kc-1 (separator); q = 1..MM: own row q-1;
@@ -125,10 +125,10 @@ __device__ __forceinline__ void cook_pair(unsigned long long seed_state, unsigne
 // sweep; one streaming pass instead of a correction pass and a separate
 // diagnostics pass over the result.
 template <bool RECON, bool DIAG, bool NOISE = false, bool FINAL = false, int MM = kChunk,
-          bool LOADS_FIRST = false>
-__device__ __forceinline__ void column_pass_body(const double* __restrict__ src, long lds,
+          bool LOADS_FIRST = false, typename RecP = const double*, typename SrcP = const double*>
+__device__ __forceinline__ void column_pass_body(SrcP __restrict__ src, long lds,
                                                  double* __restrict__ ybuf, long ldy, int nx,
-                                                 int ny, int Sc, const double* __restrict__ rec,
+                                                 int ny, int Sc, RecP __restrict__ rec,
                                                  const BandT<double>& bd, double* __restrict__ rho,
                                                  const ChCoef& K, double* __restrict__ slot,
                                                  int cb, int kc, const SmallNoise& nz = {}) {
@@ -1404,6 +1404,20 @@ hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps
 
 // ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
+//
+// A plan table is never written while a kernel runs.  A run's table pointer
+// comes from memory (its class record), so the compiler cannot prove that
+// the kernel's own stores leave the table alone and would read it with
+// vector loads, waiting on each row's coefficients in the sweep; read through
+// the constant address space, the table goes through scalar loads, as it
+// does where the pointer is a restrict kernel argument.
+using ConstTab = const __attribute__((address_space(4))) double*;
+
+// A field pointer that comes from memory is generic: accesses through it
+// compile to flat instructions, and a flat load also counts against the
+// scalar loads' wait counter.  Device memory read through the global
+// address space instead.
+using GlobalField = const __attribute__((address_space(1))) double*;
 __device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, int step) {
   return reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
 }
@@ -1417,7 +1431,7 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
   const EnsClass& C = cls.c[R.cls];
-  const double* src = (step == 0) ? R.c : ens_buf(ws, R, step - 1);
+  const auto src = (GlobalField)((step == 0) ? R.c : ens_buf(ws, R, step - 1));
   const long lds = (step == 0) ? R.ldc : (long)R.nx;
   BandT<double> bd;
 #pragma unroll
@@ -1426,7 +1440,7 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   double* rho = reinterpret_cast<double*>(ws + R.off_rho);
   column_pass_body<RECON, DIAG, NOISE, false, kChunk, true>(src, lds, ens_buf(ws, R, step), R.nx,
                                                            R.nx, R.ny, R.Sc,
-                                       C.py.rec, bd, rho, C.K,
+                                       (ConstTab)C.py.rec, bd, rho, C.K,
                                        DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
                                        it.y, it.z,
                                        NOISE ? SmallNoise{R.nseed,
@@ -1456,7 +1470,7 @@ __global__ __launch_bounds__(256) void ens_column_final(const EnsRun* __restrict
   double* part = reinterpret_cast<double*>(ws + R.off_part);
   const BandT<double> bd{};
   column_pass_body<true, DIAG, false, true>(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx,
-                                            R.ny, R.Sc, C.py.rec, bd, nullptr, C.K,
+                                            R.ny, R.Sc, (ConstTab)C.py.rec, bd, nullptr, C.K,
                                             DIAG ? part + 2 * ((long)it.z * R.ncb + it.y)
                                                  : nullptr,
                                             it.y, it.z);

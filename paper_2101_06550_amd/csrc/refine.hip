@@ -64,8 +64,9 @@ __device__ __forceinline__ Lanes lanes_of(int seg, int nx) {
 }
 
 // Forward-sweep step p of the FP32 chunk interior (the g of chunk_sweep).
+template <typename TP32>
 __device__ __forceinline__ float fwd32(float v, int p, const float (&f)[M],
-                                       const float* __restrict__ rec, float eps) {
+                                       TP32 __restrict__ rec, float eps) {
   if (p < MI) {
     if (p >= 2) v = v - eps * f[p - 2];
     if (p >= 1) v = v - rec[p * 8 + 1] * f[p - 1];
@@ -75,7 +76,8 @@ __device__ __forceinline__ float fwd32(float v, int p, const float (&f)[M],
 }
 
 // Back sweep, separator parts and stores of one FP32 chunk (own lanes only).
-__device__ __forceinline__ void finish32(float (&f)[M], const float* __restrict__ rec,
+template <typename TP32>
+__device__ __forceinline__ void finish32(float (&f)[M], TP32 __restrict__ rec,
                                          const BandT<float>& bd, float* __restrict__ y32,
                                          float* __restrict__ rho, int nx, int kc, int io,
                                          bool own) {
@@ -105,9 +107,26 @@ struct RBufs {
   const float* v[4];
 };
 
+// The bodies below take their pointers' types as template parameters.  The
+// single-field kernels pass their restrict kernel arguments.  The ensemble
+// kernels read every pointer out of a run record, where the compiler can
+// neither place it in device memory (it would emit flat accesses, which also
+// count against the scalar loads' wait counter) nor prove the kernel's own
+// stores leave the plan tables alone (it would read them with vector loads,
+// waiting on each row's coefficients); they pass their buffers typed in the
+// global address space and the tables in the constant one.
+using GD = __attribute__((address_space(1))) double*;
+using GCD = const __attribute__((address_space(1))) double*;
+using GCF = const __attribute__((address_space(1))) float*;
+using TabD = const __attribute__((address_space(4))) double*;
+using TabF = const __attribute__((address_space(4))) float*;
+struct RBufsG {
+  GCF v[4];
+};
+
 // Sum over the buffers of rows j (FP64).
-template <int NB>
-__device__ __forceinline__ double vsum(const RBufs& B, long j, int nx, int i) {
+template <int NB, typename BV>
+__device__ __forceinline__ double vsum(const BV& B, long j, int nx, int i) {
   double s = 0.0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) s += (double)B.v[b][j * nx + i];
@@ -121,16 +140,17 @@ __device__ __forceinline__ double vsum(const RBufs& B, long j, int nx, int i) {
 // previous step's solution, rebuilt from its deferred FP32 solutions
 // V_0 .. V_{NB-1} as it is read (so the state is not written and read back
 // between the steps of a call).
-template <bool DIAG, int NB = 0>
-__device__ __forceinline__ void rstep_first_body(const double* __restrict__ c, long ld,
+template <bool DIAG, int NB = 0, typename CP = const double*, typename TP32 = const float*,
+          typename BV = RBufs, typename TP = const double*>
+__device__ __forceinline__ void rstep_first_body(CP __restrict__ c, long ld,
                                                  double* __restrict__ rbuf,
                                                  float* __restrict__ y32,
                                                  float* __restrict__ rho, int nx, int ny,
-                                                 int nseg, const float* __restrict__ rec32,
+                                                 int nseg, TP32 __restrict__ rec32,
                                                  const BandT<float>& bd, const ChCoef& K,
                                                  double* __restrict__ part, int seg, int kc,
-                                                 const RBufs& Bv = RBufs{}, int Sc = 1,
-                                                 const double* __restrict__ rec = nullptr) {
+                                                 const BV& Bv = BV{}, int Sc = 1,
+                                                 TP __restrict__ rec = nullptr) {
   const Lanes L = lanes_of(seg, nx);
   constexpr int Q = M + 2;
   double tp[P] = {}, to[P] = {}, tn[P] = {};
@@ -214,12 +234,12 @@ __device__ __forceinline__ void rstep_first_body(const double* __restrict__ c, l
 // Later pass k = NB of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}
 // (window rows kc M - 2 .. kc M + M + 1, separators of chunks kc - 1, kc,
 // kc + 1 first), R = r - (I + sx Px)(I + sy Py) x in FP64, swept in FP32.
-template <int NB>
-__device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf, const RBufs& B,
+template <int NB, typename BV, typename TP, typename TP32>
+__device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf, const BV& B,
                                                  float* __restrict__ y32,
                                                  float* __restrict__ rho, int nx, int ny,
-                                                 int Sc, const double* __restrict__ rec,
-                                                 const float* __restrict__ rec32,
+                                                 int Sc, TP __restrict__ rec,
+                                                 TP32 __restrict__ rec32,
                                                  const BandT<float>& bd, const BandT<double>& ax,
                                                  const BandT<double>& ay, int seg, int kc) {
   const Lanes L = lanes_of(seg, nx);
@@ -277,10 +297,10 @@ __device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf
 
 // End of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}, written to
 // c (FP64); DIAG: mass and free energy of x.  Window rows kc M .. kc M + M.
-template <int NB, bool DIAG>
-__device__ __forceinline__ void rstep_final_body(const RBufs& B, double* __restrict__ c, long ld,
+template <int NB, bool DIAG, typename BV, typename CP, typename TP>
+__device__ __forceinline__ void rstep_final_body(const BV& B, CP __restrict__ c, long ld,
                                                  int nx, int ny, int nseg, int Sc,
-                                                 const double* __restrict__ rec, const ChCoef& K,
+                                                 TP __restrict__ rec, const ChCoef& K,
                                                  double* __restrict__ part, int seg, int kc) {
   const Lanes L = lanes_of(seg, nx);
   const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
@@ -384,10 +404,10 @@ __global__ __launch_bounds__(256) void rstep_final(RBufs B, double* __restrict__
 // Ensemble kernels: block = work item {run, segment block, chunk}; each run
 // reads its class's plan tables and its own buffers, and calls the bodies
 // the single-field kernels call (so a run advances bitwise as it would alone).
-__device__ __forceinline__ RBufs ens_vbufs(unsigned char* ws, const EnsRun& R) {
-  RBufs B{};
+__device__ __forceinline__ RBufsG ens_vbufs(unsigned char* ws, const EnsRun& R) {
+  RBufsG B{};
 #pragma unroll
-  for (int b = 0; b < 4; ++b) B.v[b] = reinterpret_cast<const float*>(ws + R.off_v[b]);
+  for (int b = 0; b < 4; ++b) B.v[b] = (GCF)(ws + R.off_v[b]);
   return B;
 }
 
@@ -411,15 +431,16 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
   float* y32 = reinterpret_cast<float*>(ws + R.off_y32);
   float* rho = reinterpret_cast<float*>(ws + R.off_rho32);
   if (PASS == 0 && !FROMV) {
-    rstep_first_body<DIAG>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K,
-                           reinterpret_cast<double*>(ws + R.off_part), seg, kc);
+    rstep_first_body<DIAG>((GCD)R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg,
+                           (TabF)C.py.rec32, bd, C.K, reinterpret_cast<double*>(ws + R.off_part),
+                           seg, kc);
   } else if (PASS == 0) {  // the state rebuilt from the previous step's solutions
     double* part = reinterpret_cast<double*>(ws + R.off_part);
-    const RBufs Bv = ens_vbufs(ws, R);
+    const RBufsG Bv = ens_vbufs(ws, R);
     switch (R.passes) {  // uniform per block
-      case 1: rstep_first_body<DIAG, 2>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
-      case 2: rstep_first_body<DIAG, 3>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
-      default: rstep_first_body<DIAG, 4>(R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, C.py.rec); break;
+      case 1: rstep_first_body<DIAG, 2>((GCD)R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, (TabF)C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, (TabD)C.py.rec); break;
+      case 2: rstep_first_body<DIAG, 3>((GCD)R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, (TabF)C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, (TabD)C.py.rec); break;
+      default: rstep_first_body<DIAG, 4>((GCD)R.c, R.ldc, rbuf, y32, rho, R.nx, R.ny, R.nseg, (TabF)C.py.rec32, bd, C.K, part, seg, kc, Bv, R.Sc, (TabD)C.py.rec); break;
     }
   } else {
     BandT<double> ax, ay;
@@ -428,8 +449,8 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
       ax.c[k] = C.px.coef[k];
       ay.c[k] = C.py.coef[k];
     }
-    rstep_resid_body<PASS>(rbuf, ens_vbufs(ws, R), y32, rho, R.nx, R.ny, R.Sc, C.py.rec,
-                           C.py.rec32, bd, ax, ay, seg, kc);
+    rstep_resid_body<PASS>(rbuf, ens_vbufs(ws, R), y32, rho, R.nx, R.ny, R.Sc, (TabD)C.py.rec,
+                           (TabF)C.py.rec32, bd, ax, ay, seg, kc);
   }
 }
 
@@ -444,12 +465,12 @@ __global__ __launch_bounds__(256) void ens_rstep_final(const EnsRun* __restrict_
   const int seg = li % R.nseg, kc = li / R.nseg;
   if (kc >= R.Sc) return;
   const EnsClass& C = cls.c[R.cls];
-  const RBufs B = ens_vbufs(ws, R);
+  const RBufsG B = ens_vbufs(ws, R);
   double* part = reinterpret_cast<double*>(ws + R.off_part);
   switch (R.passes) {  // uniform per block
-    case 1: rstep_final_body<2, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
-    case 2: rstep_final_body<3, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
-    default: rstep_final_body<4, DIAG>(B, R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, C.py.rec, C.K, part, seg, kc); break;
+    case 1: rstep_final_body<2, DIAG>(B, (GD)R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, (TabD)C.py.rec, C.K, part, seg, kc); break;
+    case 2: rstep_final_body<3, DIAG>(B, (GD)R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, (TabD)C.py.rec, C.K, part, seg, kc); break;
+    default: rstep_final_body<4, DIAG>(B, (GD)R.c, R.ldc, R.nx, R.ny, R.nseg, R.Sc, (TabD)C.py.rec, C.K, part, seg, kc); break;
   }
 }
 
