@@ -1150,6 +1150,9 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
   const int nwave = ntask >> 6;
   const int Sy = ny / M, Sx = nx / M;
   const bool act = tid < ntask;  // whole waves: ntask is a multiple of 64
+  // the plans arrive inside structs (kernel argument or class record)
+  const TabD yrec = (TabD)cy.rec, xrec = (TabD)cx.rec;
+  const TabD yblk = (TabD)cy.blocks, xblk = (TabD)cx.blocks;
   for (int e = tid; e < nx * ny; e += blockDim.x) {
     const int j = e / nx, i = e - j * nx;
     F[sfi(j, i, PX)] = c[(long)j * ldc + i];
@@ -1262,7 +1265,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
     if (n == nsteps) break;
     // C2: column chunk sweep, separator parts, y
     if (act) {
-      chunk_sweep<2, M, double>(f, cy.rec, bdy.c[0]);
+      chunk_sweep<2, M, double>(f, yrec, bdy.c[0]);
       double pa[P], pb[P];
       chunk_parts<P, M, double>(f, bdy, pa, pb);
 #pragma unroll
@@ -1284,7 +1287,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
 #pragma unroll
         for (int a = 0; a < P; ++a)
           rv[a] = Q[a * ntask + j * nx + ic] - Q[(P + a) * ntask + jn * nx + ic];
-        const double* B = cy.blocks + t * 4;
+        const TabD B = yblk + t * 4;
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
@@ -1308,7 +1311,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
         double v = F[sfi(kc * M + p, ic, PX)];
 #pragma unroll
         for (int a = 0; a < P; ++a)
-          v = v - cy.rec[p * 8 + 4 + a] * sp[a] - cy.rec[p * 8 + 6 + a] * so[a];
+          v = v - yrec[p * 8 + 4 + a] * sp[a] - yrec[p * 8 + 6 + a] * so[a];
         F[sfi(kc * M + p, ic, PX)] = v;
       }
     }
@@ -1318,7 +1321,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
     if (act) {
 #pragma unroll
       for (int p = 0; p < M; ++p) f[p] = F[rbase + p];
-      chunk_sweep<2, M, double>(f, cx.rec, bdx.c[0]);
+      chunk_sweep<2, M, double>(f, xrec, bdx.c[0]);
       double pa[P], pb[P];
       chunk_parts<P, M, double>(f, bdx, pa, pb);
 #pragma unroll
@@ -1338,7 +1341,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
 #pragma unroll
         for (int a = 0; a < P; ++a)
           rv[a] = Q[a * ntask + rs + j] - Q[(P + a) * ntask + rs + jn];
-        const double* B = cx.blocks + t * 4;
+        const TabD B = xblk + t * 4;
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
@@ -1354,7 +1357,7 @@ __device__ __forceinline__ void small_steps_body(double* __restrict__ c, long ld
       double sp[P];
 #pragma unroll
       for (int a = 0; a < P; ++a) sp[a] = F[jr * PX + kp * (M + 1) + MI + a];
-      chunk_correct<P, M, double>(f, cx.rec, sp, so);
+      chunk_correct<P, M, double>(f, xrec, sp, so);
 #pragma unroll
       for (int p = 0; p < M; ++p) F[rbase + p] = f[p];
     }
@@ -1404,20 +1407,8 @@ hipError_t launch_ch_small_steps(double* c, long ldc, int nx, int ny, int nsteps
 
 // ---------------------------------------------------------------------------
 // Ensemble kernels: block = work item {run, a, b}; buffers by step parity.
-//
-// A plan table is never written while a kernel runs.  A run's table pointer
-// comes from memory (its class record), so the compiler cannot prove that
-// the kernel's own stores leave the table alone and would read it with
-// vector loads, waiting on each row's coefficients in the sweep; read through
-// the constant address space, the table goes through scalar loads, as it
-// does where the pointer is a restrict kernel argument.
-using ConstTab = const __attribute__((address_space(4))) double*;
-
-// A field pointer that comes from memory is generic: accesses through it
-// compile to flat instructions, and a flat load also counts against the
-// scalar loads' wait counter.  Device memory read through the global
-// address space instead.
-using GlobalField = const __attribute__((address_space(1))) double*;
+// Their run's pointers come out of memory, so they pass them typed by
+// address space (TabD, GCD).
 __device__ __forceinline__ double* ens_buf(unsigned char* ws, const EnsRun& R, int step) {
   return reinterpret_cast<double*>(ws + ((step & 1) ? R.off_b1 : R.off_b0));
 }
@@ -1431,7 +1422,7 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
   const EnsClass& C = cls.c[R.cls];
-  const auto src = (GlobalField)((step == 0) ? R.c : ens_buf(ws, R, step - 1));
+  const auto src = (GCD)((step == 0) ? R.c : ens_buf(ws, R, step - 1));
   const long lds = (step == 0) ? R.ldc : (long)R.nx;
   BandT<double> bd;
 #pragma unroll
@@ -1440,7 +1431,7 @@ __global__ __launch_bounds__(256) void ens_column_pass(const EnsRun* __restrict_
   double* rho = reinterpret_cast<double*>(ws + R.off_rho);
   column_pass_body<RECON, DIAG, NOISE, false, kChunk, true>(src, lds, ens_buf(ws, R, step), R.nx,
                                                            R.nx, R.ny, R.Sc,
-                                       (ConstTab)C.py.rec, bd, rho, C.K,
+                                       (TabD)C.py.rec, bd, rho, C.K,
                                        DIAG ? part + 2 * ((long)it.z * R.ncb + it.y) : nullptr,
                                        it.y, it.z,
                                        NOISE ? SmallNoise{R.nseed,
@@ -1470,7 +1461,7 @@ __global__ __launch_bounds__(256) void ens_column_final(const EnsRun* __restrict
   double* part = reinterpret_cast<double*>(ws + R.off_part);
   const BandT<double> bd{};
   column_pass_body<true, DIAG, false, true>(ens_buf(ws, R, last_step), R.nx, R.c, R.ldc, R.nx,
-                                            R.ny, R.Sc, (ConstTab)C.py.rec, bd, nullptr, C.K,
+                                            R.ny, R.Sc, (TabD)C.py.rec, bd, nullptr, C.K,
                                             DIAG ? part + 2 * ((long)it.z * R.ncb + it.y)
                                                  : nullptr,
                                             it.y, it.z);

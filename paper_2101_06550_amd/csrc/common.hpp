@@ -17,6 +17,21 @@ struct BandT {
 // Chunk length of the chunked kernels (unknowns per thread-chunk).
 constexpr int kChunk = 32;
 
+// Pointers typed by address space.  A pointer that a kernel reads out of
+// memory (a run record, a plan passed inside a struct) is generic: the
+// compiler can neither place it in device memory (it emits flat accesses,
+// which also count against the scalar loads' wait counter) nor prove that
+// the kernel's own stores, LDS ones included, leave the data alone (it reads
+// plan tables with vector loads and waits on each sweep row's coefficients).
+// Plan tables are never written while a kernel runs: read through the
+// constant space they go through scalar loads, as they do where the pointer
+// is a restrict kernel argument; fields go through the global space.
+using TabD = const __attribute__((address_space(4))) double*;
+using TabF = const __attribute__((address_space(4))) float*;
+using GD = __attribute__((address_space(1))) double*;
+using GCD = const __attribute__((address_space(1))) double*;
+using GCF = const __attribute__((address_space(1))) float*;
+
 // SplitMix64 finaliser (Steele, Lea and Flood 2014): the mixing function of
 // the counter-based generator of the Cahn-Hilliard-Cook forcing.
 __host__ __device__ __forceinline__ unsigned long long chx_sm_mix(unsigned long long z) {
@@ -69,8 +84,8 @@ __device__ __forceinline__ double dpp_from_right(double v, double edge) {
 // are untouched.  rec: kRec values per interior position (1/alpha, L(i,i-1),
 // R(i,i+1), R(i,i+2), ...).  eps = L(i,i-2) = the band's outermost
 // sub-diagonal (P = 2 only).
-template <int P, int M, typename T>
-__device__ __forceinline__ void chunk_sweep(T (&f)[M], const T* __restrict__ rec, T eps) {
+template <int P, int M, typename T, typename RP = const T*>
+__device__ __forceinline__ void chunk_sweep(T (&f)[M], RP __restrict__ rec, T eps) {
   constexpr int MI = M - P;
 #pragma unroll
   for (int p = 0; p < MI; ++p) {
@@ -111,8 +126,8 @@ __device__ __forceinline__ void chunk_parts(const T (&f)[M], const BandT<T>& bd,
 
 // Interior correction x = y - Zl s_prev - Zr s_own (rec[4..5] = Zl, rec[6..7] = Zr),
 // separators set to s_own.
-template <int P, int M, typename T>
-__device__ __forceinline__ void chunk_correct(T (&f)[M], const T* __restrict__ rec,
+template <int P, int M, typename T, typename RP = const T*>
+__device__ __forceinline__ void chunk_correct(T (&f)[M], RP __restrict__ rec,
                                               const T (&sp)[P], const T (&so)[P]) {
   constexpr int MI = M - P;
 #pragma unroll

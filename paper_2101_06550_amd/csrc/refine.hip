@@ -107,19 +107,9 @@ struct RBufs {
   const float* v[4];
 };
 
-// The bodies below take their pointers' types as template parameters.  The
-// single-field kernels pass their restrict kernel arguments.  The ensemble
-// kernels read every pointer out of a run record, where the compiler can
-// neither place it in device memory (it would emit flat accesses, which also
-// count against the scalar loads' wait counter) nor prove the kernel's own
-// stores leave the plan tables alone (it would read them with vector loads,
-// waiting on each row's coefficients); they pass their buffers typed in the
-// global address space and the tables in the constant one.
-using GD = __attribute__((address_space(1))) double*;
-using GCD = const __attribute__((address_space(1))) double*;
-using GCF = const __attribute__((address_space(1))) float*;
-using TabD = const __attribute__((address_space(4))) double*;
-using TabF = const __attribute__((address_space(4))) float*;
+// The bodies below take their pointers' types as template parameters: the
+// single-field kernels pass their restrict kernel arguments, the ensemble
+// kernels pointers read out of run records, typed by address space.
 struct RBufsG {
   GCF v[4];
 };
