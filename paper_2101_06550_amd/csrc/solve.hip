@@ -208,18 +208,29 @@ __global__ __launch_bounds__(256) void correct_il(const Ty* y, long ldy, double*
   }
   const Ty* yb = y + (long)k * M * ldy + s;
   double* ob = out + (long)k * M * ldo + s;
+  // every row (and, when accumulating, every old output) is loaded before
+  // the first store: y may be out, so a load placed after a store would
+  // wait for it
+  T yv[MI];
+  double ov[M];
+#pragma unroll
+  for (int p = 0; p < MI; ++p) yv[p] = (T)yb[(long)p * ldy];
+  if (ACC) {
+#pragma unroll
+    for (int p = 0; p < M; ++p) ov[p] = ob[(long)p * ldo];
+  }
 #pragma unroll
   for (int p = 0; p < MI; ++p) {
-    T v = (T)yb[(long)p * ldy];
+    T v = yv[p];
 #pragma unroll
     for (int a = 0; a < P; ++a) v = v - rec[p * 8 + 4 + a] * sp[a] - rec[p * 8 + 6 + a] * so[a];
-    if (ACC) ob[(long)p * ldo] += (double)v;
+    if (ACC) ob[(long)p * ldo] = ov[p] + (double)v;
     else __builtin_nontemporal_store((double)v, &ob[(long)p * ldo]);
   }
   if (ACC || (const void*)y != (const void*)out) {
 #pragma unroll
     for (int a = 0; a < P; ++a) {
-      if (ACC) ob[(long)(MI + a) * ldo] += (double)so[a];
+      if (ACC) ob[(long)(MI + a) * ldo] = ov[MI + a] + (double)so[a];
       else ob[(long)(MI + a) * ldo] = (double)so[a];
     }
   }
