@@ -64,7 +64,7 @@ hipError_t launch_ch_column_final(const double* src, long lds, double* dst, long
 // part != nullptr); pass nb (residual of x rebuilt from the deferred FP32
 // solutions v[0 .. nb-1], FP32 sweep); the state x rebuilt from v[0 .. nb-1]
 // into c (and with diag_out its mass and energy there).
-int rstep_segments(int nx);  // 60-column wave segments of a row of nx
+int rstep_segments(int nx);  // 64-column wave segments of a row of nx
 long rstep_parts(int nx, int ny);
 // vprev / nbprev: the previous step's deferred solutions (nbprev = its passes
 // + 1), the state rebuilt from them; nbprev = 0 reads c.

@@ -27,7 +27,7 @@ struct EnsRun {
   unsigned long long nseed;
   // FP32-refined runs: r (FP64), the FP32 column buffer and its separator
   // parts, the deferred FP32 solutions V_0 .. V_passes of a step, the refine
-  // passes and the 60-column wave segments per row
+  // passes and the 64-column wave segments per row
   long off_r, off_y32, off_rho32, off_v[4];
   int passes, nseg;
 };

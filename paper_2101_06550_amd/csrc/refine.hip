@@ -15,10 +15,14 @@
 //                 interiors of R = r - A x_{k-1} swept (4)
 //   rows (FP32) : read 4, write V_k (4)
 //   rstep_final : read V_0 .. V_p (4 (p + 1)), write c (8)
-// Every kernel runs one wave per 60 output columns of one 32-row chunk: the
-// wave's 64 lanes hold columns i0 - 2 .. i0 + 61 (wrapped), so neighbours at
-// distance 1 and 2 come from DPP lane shifts -- no LDS, no barrier.  A
-// wave's (mass, energy) partial goes to slot kc * nseg + seg.
+// Every kernel runs one wave per 64 columns (i0 = 64 seg .. i0 + 63) of one
+// 32-row chunk, so every row segment it loads or stores is whole, aligned
+// cache lines.  Neighbours at distance 1 and 2 come from DPP lane shifts --
+// no LDS, no barrier: the lanes at the wave's edges also form the state of
+// the columns just outside it (lane 0: i0 - 1, lane 1: i0 - 2, lane 63:
+// i0 + 64, lane 62: i0 + 65, wrapped), the same arithmetic the owning wave
+// does, and the shifts take those values in at the edges.  A wave's (mass,
+// energy) partial goes to slot kc * nseg + seg.
 #include <hip/hip_runtime.h>
 
 #include "ch_launch.hpp"
@@ -32,8 +36,8 @@ namespace {
 constexpr int M = kChunk;
 constexpr int P = 2;
 constexpr int MI = M - P;
-constexpr int kSegR = 60;  // output columns per wave
-constexpr int kPfR = 6;    // rows of loads in flight ahead of the row worked
+constexpr int kSegR = 64;  // output columns per wave
+constexpr int kPfR = 4;    // rows of loads in flight ahead of the row worked
 
 __device__ __forceinline__ double wave_sum_r(double v) {
 #pragma unroll
@@ -47,20 +51,39 @@ __device__ __forceinline__ int wrap_row(int j, int ny) {
   return j;
 }
 
-// Lane geometry of wave `seg`: column i (wrapped) and whether the lane owns
-// an output column io.
+// Lane geometry of wave `seg` (nx is a multiple of 64): the lane's column i,
+// and the column ex whose state it also forms for the shifts -- with HALO = 2
+// the two columns on either side of the wave (lanes 0, 1, 62, 63), with
+// HALO = 1 the nearest one (lanes 0 and 63); the other lanes their own.
 struct Lanes {
-  int i, io;
-  bool own;
+  int i, ex;
 };
+template <int HALO>
 __device__ __forceinline__ Lanes lanes_of(int seg, int nx) {
   const int lane = threadIdx.x & 63;
+  const int i0 = seg * kSegR;
   Lanes L;
-  L.io = seg * kSegR + lane - 2;
-  int i = L.io % nx;
-  L.i = i + ((i < 0) ? nx : 0);
-  L.own = lane >= 2 && lane < 62 && L.io < nx;
+  L.i = i0 + lane;
+  int ex = L.i;
+  if (lane == 0) ex = i0 - 1;
+  if (lane == 63) ex = i0 + 64;
+  if (HALO == 2 && lane == 1) ex = i0 - 2;
+  if (HALO == 2 && lane == 62) ex = i0 + 65;
+  ex += (ex < 0) ? nx : 0;
+  ex -= (ex >= nx) ? nx : 0;
+  L.ex = ex;
   return L;
+}
+
+// Value of the column at distance 1 / 2 to the left / right of the lane's,
+// h being the edge lanes' halo values of the same row (lanes_of).
+__device__ __forceinline__ double left1(double x, double h) { return dpp_from_left(x, h); }
+__device__ __forceinline__ double left2(double l1, double h) {
+  return dpp_from_left(l1, dpp_from_right(h, h));
+}
+__device__ __forceinline__ double right1(double x, double h) { return dpp_from_right(x, h); }
+__device__ __forceinline__ double right2(double r1, double h) {
+  return dpp_from_right(r1, dpp_from_left(h, h));
 }
 
 // Forward-sweep step p of the FP32 chunk interior (the g of chunk_sweep).
@@ -75,12 +98,11 @@ __device__ __forceinline__ float fwd32(float v, int p, const float (&f)[M],
   return v;
 }
 
-// Back sweep, separator parts and stores of one FP32 chunk (own lanes only).
+// Back sweep, separator parts and stores of one FP32 chunk.
 template <typename TP32>
 __device__ __forceinline__ void finish32(float (&f)[M], TP32 __restrict__ rec,
                                          const BandT<float>& bd, float* __restrict__ y32,
-                                         float* __restrict__ rho, int nx, int kc, int io,
-                                         bool own) {
+                                         float* __restrict__ rho, int nx, int kc, int io) {
 #pragma unroll
   for (int p = MI - 1; p >= 0; --p) {
     float v = f[p];
@@ -90,7 +112,6 @@ __device__ __forceinline__ void finish32(float (&f)[M], TP32 __restrict__ rec,
   }
   float pa[P], pb[P];
   chunk_parts<P, M, float>(f, bd, pa, pb);
-  if (!own) return;
 #pragma unroll
   for (int p = 0; p < MI; ++p) __builtin_nontemporal_store(f[p], &y32[((long)kc * M + p) * nx + io]);
 #pragma unroll
@@ -141,38 +162,46 @@ __device__ __forceinline__ void rstep_first_body(CP __restrict__ c, long ld,
                                                  double* __restrict__ part, int seg, int kc,
                                                  const BV& Bv = BV{}, int Sc = 1,
                                                  TP __restrict__ rec = nullptr) {
-  const Lanes L = lanes_of(seg, nx);
+  const Lanes L = lanes_of<1>(seg, nx);
   constexpr int Q = M + 2;
-  double tp[P] = {}, to[P] = {}, tn[P] = {};
-  if (NB > 0) {  // separator rows (final values) of chunks kc - 1, kc, kc + 1
+  // separator rows (final values) of chunks kc - 1, kc, kc + 1 at the lane's
+  // column (s[0]) and at its halo column (s[1])
+  double tp[2][P] = {}, to[2][P] = {}, tn[2][P] = {};
+  if (NB > 0) {
     const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      tp[a] = vsum<NB>(Bv, (long)kcm * M + MI + a, nx, L.i);
-      to[a] = vsum<NB>(Bv, (long)kc * M + MI + a, nx, L.i);
-      tn[a] = vsum<NB>(Bv, (long)kcp * M + MI + a, nx, L.i);
+    for (int h = 0; h < 2; ++h) {
+      const int col = h ? L.ex : L.i;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        tp[h][a] = vsum<NB>(Bv, (long)kcm * M + MI + a, nx, col);
+        to[h][a] = vsum<NB>(Bv, (long)kc * M + MI + a, nx, col);
+        tn[h][a] = vsum<NB>(Bv, (long)kcp * M + MI + a, nx, col);
+      }
     }
   }
-  double X[Q];
-  auto load = [&](int t) {
-    if (NB == 0) {
-      X[t] = c[(long)wrap_row(kc * M - 1 + t, ny) * ld + L.i];
-    } else {
-      // window row t: t = 0 is chunk kc-1's last separator, t = 1 .. M chunk
-      // kc's position t - 1, t = M + 1 chunk kc+1's position 0
-      double x = vsum<NB>(Bv, wrap_row(kc * M - 1 + t, ny), nx, L.i);
-      if (t >= 1) {
-        const bool below = t == M + 1;
-        const int pp = below ? 0 : t - 1;
-        if (pp < MI) {
+  double X[Q], XH[Q];
+  auto value = [&](int t, int h) {
+    const int col = h ? L.ex : L.i;
+    if (NB == 0) return (double)c[(long)wrap_row(kc * M - 1 + t, ny) * ld + col];
+    // window row t: t = 0 is chunk kc-1's last separator, t = 1 .. M chunk
+    // kc's position t - 1, t = M + 1 chunk kc+1's position 0
+    double x = vsum<NB>(Bv, wrap_row(kc * M - 1 + t, ny), nx, col);
+    if (t >= 1) {
+      const bool below = t == M + 1;
+      const int pp = below ? 0 : t - 1;
+      if (pp < MI) {
 #pragma unroll
-          for (int a = 0; a < P; ++a)
-            x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
-                rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
-        }
+        for (int a = 0; a < P; ++a)
+          x = x - rec[pp * 8 + 4 + a] * (below ? to[h][a] : tp[h][a]) -
+              rec[pp * 8 + 6 + a] * (below ? tn[h][a] : to[h][a]);
       }
-      X[t] = x;
     }
+    return x;
+  };
+  auto load = [&](int t) {
+    X[t] = value(t, 0);
+    XH[t] = value(t, 1);
   };
 #pragma unroll
   for (int t = 0; t < kPfR; ++t) load(t);
@@ -183,8 +212,8 @@ __device__ __forceinline__ void rstep_first_body(CP __restrict__ c, long ld,
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
     if (t + kPfR < Q) load(t + kPfR);
-    XL[t] = dpp_from_left(X[t], X[t]);
-    XR[t] = dpp_from_right(X[t], X[t]);
+    XL[t] = left1(X[t], XH[t]);
+    XR[t] = right1(X[t], XH[t]);
     if (t >= 2) {  // own row p = t - 2 at window index w = t - 1
       const int p = t - 2, w = t - 1;
       const double xc = X[w], xl = XL[w], xr = XR[w];
@@ -198,19 +227,19 @@ __device__ __forceinline__ void rstep_first_body(CP __restrict__ c, long ld,
       const double dyy_c = X[w + 1] + X[w - 1] - 2.0 * xc;
       const double dyy_e = XR[w + 1] + XR[w - 1] - 2.0 * xr;
       const double r = xc + lap - K.ccross * (dyy_e + dyy_w - 2.0 * dyy_c);
-      if (DIAG && L.own) {
+      if (DIAG) {
         const double q = xc * xc - 1.0;
         const double gx = (xr - xc) * K.inv_dx, gy = (X[w + 1] - xc) * K.inv_dy;
         msum += xc;
         esum += 0.25 * q * q + K.half_gamma * (gx * gx + gy * gy);
       }
-      if (L.own) __builtin_nontemporal_store(r, &rbuf[((long)kc * M + p) * nx + L.io]);
+      __builtin_nontemporal_store(r, &rbuf[((long)kc * M + p) * nx + L.i]);
       f[p] = fwd32((float)r, p, f, rec32, eps);
       asm volatile("" : "+v"(f[p]));
     }
-    asm volatile("" : "+v"(X[t]), "+v"(XL[t]), "+v"(XR[t])::"memory");
+    asm volatile("" : "+v"(X[t]), "+v"(XH[t]), "+v"(XL[t]), "+v"(XR[t])::"memory");
   }
-  finish32(f, rec32, bd, y32, rho, nx, kc, L.io, L.own);
+  finish32(f, rec32, bd, y32, rho, nx, kc, L.i);
   if (DIAG) {
     msum = wave_sum_r(msum);
     esum = wave_sum_r(esum);
@@ -232,24 +261,30 @@ __device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf
                                                  TP32 __restrict__ rec32,
                                                  const BandT<float>& bd, const BandT<double>& ax,
                                                  const BandT<double>& ay, int seg, int kc) {
-  const Lanes L = lanes_of(seg, nx);
+  const Lanes L = lanes_of<2>(seg, nx);
   const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
-  double tp[P], to[P], tn[P];
+  // separators at the lane's column (h = 0) and at its halo column (h = 1)
+  double tp[2][P], to[2][P], tn[2][P];
 #pragma unroll
-  for (int a = 0; a < P; ++a) {
-    tp[a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, L.i);
-    to[a] = vsum<NB>(B, (long)kc * M + MI + a, nx, L.i);
-    tn[a] = vsum<NB>(B, (long)kcp * M + MI + a, nx, L.i);
+  for (int h = 0; h < 2; ++h) {
+    const int col = h ? L.ex : L.i;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      tp[h][a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, col);
+      to[h][a] = vsum<NB>(B, (long)kc * M + MI + a, nx, col);
+      tn[h][a] = vsum<NB>(B, (long)kcp * M + MI + a, nx, col);
+    }
   }
   constexpr int Q = M + 4;  // window rows kc M - 2 .. kc M + M + 1
-  double U[Q], R[M];
+  double U[Q], UH[Q], R[M];
   auto load = [&](int t) {
     U[t] = vsum<NB>(B, wrap_row(kc * M - 2 + t, ny), nx, L.i);
+    UH[t] = vsum<NB>(B, wrap_row(kc * M - 2 + t, ny), nx, L.ex);
     if (t >= 2 && t < M + 2) R[t - 2] = rbuf[((long)kc * M + t - 2) * nx + L.i];
   };
 #pragma unroll
   for (int t = 0; t < kPfR; ++t) load(t);
-  double X[Q];
+  double X[Q], XH[Q];
   float f[M];
   const float eps = bd.c[0];
 #pragma unroll
@@ -258,31 +293,37 @@ __device__ __forceinline__ void rstep_resid_body(const double* __restrict__ rbuf
     // the state at window row t: rows above (t < 2) are chunk kc-1's
     // separators; own rows (2 .. M+1) chunk kc, position t - 2; the two rows
     // below chunk kc+1, positions 0 and 1
-    double x = U[t];
-    if (t >= 2) {
-      const bool below = t >= M + 2;
-      const int pp = below ? t - M - 2 : t - 2;
-      if (pp < MI) {
 #pragma unroll
-        for (int a = 0; a < P; ++a)
-          x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
-              rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+    for (int h = 0; h < 2; ++h) {
+      double x = h ? UH[t] : U[t];
+      if (t >= 2) {
+        const bool below = t >= M + 2;
+        const int pp = below ? t - M - 2 : t - 2;
+        if (pp < MI) {
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            x = x - rec[pp * 8 + 4 + a] * (below ? to[h][a] : tp[h][a]) -
+                rec[pp * 8 + 6 + a] * (below ? tn[h][a] : to[h][a]);
+        }
       }
+      if (h) XH[t] = x;
+      else X[t] = x;
     }
-    X[t] = x;
     if (t >= 4) {  // own row p = t - 4 at window index w = t - 2
       const int p = t - 4, w = t - 2;
       const double Ty = ay.c[0] * X[w - 2] + ay.c[1] * X[w - 1] + ay.c[2] * X[w] +
                         ay.c[3] * X[w + 1] + ay.c[4] * X[w + 2];
-      const double l1 = dpp_from_left(Ty, Ty), l2 = dpp_from_left(l1, l1);
-      const double r1 = dpp_from_right(Ty, Ty), r2 = dpp_from_right(r1, r1);
+      const double TyH = ay.c[0] * XH[w - 2] + ay.c[1] * XH[w - 1] + ay.c[2] * XH[w] +
+                         ay.c[3] * XH[w + 1] + ay.c[4] * XH[w + 2];
+      const double l1 = left1(Ty, TyH), l2 = left2(l1, TyH);
+      const double r1 = right1(Ty, TyH), r2 = right2(r1, TyH);
       const double Ax = ax.c[0] * l2 + ax.c[1] * l1 + ax.c[2] * Ty + ax.c[3] * r1 + ax.c[4] * r2;
       f[p] = fwd32((float)(R[p] - Ax), p, f, rec32, eps);
       asm volatile("" : "+v"(f[p]));
     }
-    asm volatile("" : "+v"(X[t])::"memory");
+    asm volatile("" : "+v"(X[t]), "+v"(XH[t])::"memory");
   }
-  finish32(f, rec32, bd, y32, rho, nx, kc, L.io, L.own);
+  finish32(f, rec32, bd, y32, rho, nx, kc, L.i);
 }
 
 // End of a refined step: x = sum of the rebuilt V_0 .. V_{NB-1}, written to
@@ -292,50 +333,60 @@ __device__ __forceinline__ void rstep_final_body(const BV& B, CP __restrict__ c,
                                                  int nx, int ny, int nseg, int Sc,
                                                  TP __restrict__ rec, const ChCoef& K,
                                                  double* __restrict__ part, int seg, int kc) {
-  const Lanes L = lanes_of(seg, nx);
+  // DIAG needs the right neighbour: lane 63 also forms column i0 + 64
+  const Lanes L = lanes_of<1>(seg, nx);
+  constexpr int NH = DIAG ? 2 : 1;
   const int kcm = (kc == 0) ? Sc - 1 : kc - 1, kcp = (kc + 1 == Sc) ? 0 : kc + 1;
-  double tp[P], to[P], tn[P];
+  double tp[2][P] = {}, to[2][P] = {}, tn[2][P] = {};
 #pragma unroll
-  for (int a = 0; a < P; ++a) {
-    tp[a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, L.i);
-    to[a] = vsum<NB>(B, (long)kc * M + MI + a, nx, L.i);
-    tn[a] = DIAG ? vsum<NB>(B, (long)kcp * M + MI + a, nx, L.i) : 0.0;
+  for (int h = 0; h < NH; ++h) {
+    const int col = h ? L.ex : L.i;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      tp[h][a] = vsum<NB>(B, (long)kcm * M + MI + a, nx, col);
+      to[h][a] = vsum<NB>(B, (long)kc * M + MI + a, nx, col);
+      tn[h][a] = DIAG ? vsum<NB>(B, (long)kcp * M + MI + a, nx, col) : 0.0;
+    }
   }
   constexpr int Q = M + 1;  // own rows and (DIAG) row 0 of chunk kc + 1
-  double U[Q];
+  double U[Q], UH[Q];
   auto load = [&](int t) {
     if (t < M || DIAG) U[t] = vsum<NB>(B, wrap_row(kc * M + t, ny), nx, L.i);
+    if (DIAG) UH[t] = vsum<NB>(B, wrap_row(kc * M + t, ny), nx, L.ex);
   };
 #pragma unroll
   for (int t = 0; t < kPfR; ++t) load(t);
-  double X[Q];
+  double X[Q], XH[Q];
   double msum = 0.0, esum = 0.0;
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
     if (t + kPfR < Q) load(t + kPfR);
     if (t == M && !DIAG) break;
-    double x = U[t];
     const bool below = t == M;
     const int pp = below ? 0 : t;
-    if (pp < MI) {
 #pragma unroll
-      for (int a = 0; a < P; ++a)
-        x = x - rec[pp * 8 + 4 + a] * (below ? to[a] : tp[a]) -
-            rec[pp * 8 + 6 + a] * (below ? tn[a] : to[a]);
+    for (int h = 0; h < NH; ++h) {
+      double x = h ? UH[t] : U[t];
+      if (pp < MI) {
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          x = x - rec[pp * 8 + 4 + a] * (below ? to[h][a] : tp[h][a]) -
+              rec[pp * 8 + 6 + a] * (below ? tn[h][a] : to[h][a]);
+      }
+      if (h) XH[t] = x;
+      else X[t] = x;
     }
-    X[t] = x;
-    if (t < M && L.own) __builtin_nontemporal_store(x, &c[((long)kc * M + t) * ld + L.io]);
+    if (t < M) __builtin_nontemporal_store(X[t], &c[((long)kc * M + t) * ld + L.i]);
     if (DIAG && t >= 1) {  // row t - 1 with its neighbours (i + 1, j) and (i, j + 1)
       const double xc = X[t - 1];
-      const double xr = dpp_from_right(xc, xc);
-      if (L.own) {
-        const double q = xc * xc - 1.0;
-        const double gx = (xr - xc) * K.inv_dx, gy = (X[t] - xc) * K.inv_dy;
-        msum += xc;
-        esum += 0.25 * q * q + K.half_gamma * (gx * gx + gy * gy);
-      }
+      const double xr = right1(xc, XH[t - 1]);
+      const double q = xc * xc - 1.0;
+      const double gx = (xr - xc) * K.inv_dx, gy = (X[t] - xc) * K.inv_dy;
+      msum += xc;
+      esum += 0.25 * q * q + K.half_gamma * (gx * gx + gy * gy);
     }
     asm volatile("" : "+v"(X[t])::"memory");
+    if (DIAG) asm volatile("" : "+v"(XH[t])::"memory");
   }
   if (DIAG) {
     msum = wave_sum_r(msum);
@@ -347,7 +398,7 @@ __device__ __forceinline__ void rstep_final_body(const BV& B, CP __restrict__ c,
   }
 }
 
-// Single-field kernels: block = 4 waves = 4 consecutive (60-column segment,
+// Single-field kernels: block = 4 waves = 4 consecutive (64-column segment,
 // chunk) pairs, segments fastest (full blocks whatever the segment count).
 template <bool DIAG, int NB>
 __global__ __launch_bounds__(256) void rstep_first(const double* __restrict__ c, long ld,
@@ -409,7 +460,7 @@ __global__ __launch_bounds__(256) void ens_rstep_column(const EnsRun* __restrict
   const int4 it = items[blockIdx.x];
   const EnsRun R = runs[it.x];
   // a run's (segment, chunk) pairs packed four to a block, so that blocks
-  // are full on grids whose rows span few 60-column segments
+  // are full on grids whose rows span few 64-column segments
   const int li = it.y * 4 + (threadIdx.x >> 6);
   const int seg = li % R.nseg, kc = li / R.nseg;
   if (kc >= R.Sc) return;  // no barrier in these kernels
@@ -513,7 +564,7 @@ static dim3 rstep_grid(int nx, int ny) {
 hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32, float* rho,
                               int nx, int ny, const DevChunk& cy, const ChCoef& K, double* part,
                               hipStream_t st, const float* const* vprev, int nbprev) {
-  if (ny % M != 0 || cy.S * M != ny || nbprev < 0 || nbprev > 4) return hipErrorInvalidValue;
+  if (nx % kSegR != 0 || ny % M != 0 || cy.S * M != ny || nbprev < 0 || nbprev > 4) return hipErrorInvalidValue;
   BandT<float> bd;
   for (int k = 0; k < 5; ++k) bd.c[k] = (float)cy.coef[k];
   const int nseg = (nx + kSegR - 1) / kSegR;
@@ -537,7 +588,7 @@ hipError_t launch_rstep_first(const double* c, long ld, double* rbuf, float* y32
 hipError_t launch_rstep_resid(const double* rbuf, const float* const* v, int nb, float* y32,
                               float* rho, int nx, int ny, const DevChunk& cy, const double* cx5,
                               const double* cy5, hipStream_t st) {
-  if (ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 3) return hipErrorInvalidValue;
+  if (nx % kSegR != 0 || ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 3) return hipErrorInvalidValue;
   BandT<float> bd;
   BandT<double> ax, ay;
   for (int k = 0; k < 5; ++k) {
@@ -561,7 +612,7 @@ hipError_t launch_rstep_resid(const double* rbuf, const float* const* v, int nb,
 hipError_t launch_rstep_final(const float* const* v, int nb, double* c, long ld, int nx, int ny,
                               const DevChunk& cy, const ChCoef& K, double* part, double* diag_out,
                               hipStream_t st) {
-  if (ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 4) return hipErrorInvalidValue;
+  if (nx % kSegR != 0 || ny % M != 0 || cy.S * M != ny || nb < 1 || nb > 4) return hipErrorInvalidValue;
   RBufs B{};
   for (int b = 0; b < nb; ++b) B.v[b] = v[b];
   const int nseg = (nx + kSegR - 1) / kSegR;
