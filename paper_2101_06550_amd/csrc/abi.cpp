@@ -1023,8 +1023,9 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
   // takes its output)
   double *ybuf = nullptr, *part = nullptr;
   const long nparts = ch_column_pass_blocks(nx, Smax);
+  // (one more pair: the separator kernel's diagnostics output)
   if (ok && hipMalloc(&ybuf, dst_bytes) == hipSuccess &&
-      hipMalloc(&part, (size_t)nparts * 2 * sizeof(double)) == hipSuccess) {
+      hipMalloc(&part, (size_t)(nparts + 1) * 2 * sizeof(double)) == hipSuccess) {
     ChCoef K{};
     float best_col = -1.f;
     for (int order = 0; ok && order < CHX_NUM_COLUMN_ORDERS; ++order) {
@@ -1051,61 +1052,100 @@ Tuned tune_step(const BandPlan* py, const BandPlan* px, int nx, int ny) {
     const bool ok2 = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess &&
                      hipEventCreateWithFlags(&ef, hipEventDisableTiming) == hipSuccess &&
                      hipEventCreateWithFlags(&ej, hipEventDisableTiming) == hipSuccess;
-    float best_step = -1.f;
-    bool overlap = false;
     const Tuned keep = best;
+    // one whole step of a candidate (chunk lengths, separator shape, order),
+    // with the diagnostics every step of the benchmark computes: the
+    // separator kernel's first block then also finishes their sum, which
+    // lengthens shapes that run in a single round of blocks
+    double* dout = part + 2 * nparts;
+    struct Cand {
+      float ms;
+      int mc, mr, shape;
+      bool overlap;
+    };
+    auto step_of = [&](const Cand& cd) {
+      DevChunk cy = cd.mc == 16 ? py->dchunk16 : py->dchunk;
+      const DevChunk& cx = cd.mr == 16 ? px->dchunk16 : px->dchunk;
+      cy.red_shape = cd.shape;
+      const long colblocks = ch_column_pass_blocks(nx, cy.S);
+      return time_it([&]() {
+        hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho, K,
+                                             part, st, nullptr, keep.col_order);
+        if (!cd.overlap) {
+          if (e == hipSuccess)
+            e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, st, part, colblocks,
+                                     K.dxdy, dout);
+          return e == hipSuccess ? launch_rows_lds<2>(cx, ybuf, nx, ny, st) : e;
+        }
+        if (e == hipSuccess) e = hipEventRecord(ef, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ef, 0);
+        if (e == hipSuccess)
+          e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, side, part, colblocks,
+                                   K.dxdy, dout);
+        if (e == hipSuccess) e = launch_rows_subset(true, ybuf, nx, ny, cy.M, cx, side);
+        if (e == hipSuccess) e = hipEventRecord(ej, side);
+        if (e == hipSuccess) e = launch_rows_subset(false, ybuf, nx, ny, cy.M, cx, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ej, 0);
+        return e;
+      });
+    };
+    std::vector<Cand> cands;
     for (int mc : {kChunk, 16}) {
       for (int mr : {kChunk, 16}) {
         if ((mc == 16 && !py->has_chunk16) || (mr == 16 && !rows16_fit(px))) continue;
-        DevChunk cy = mc == 16 ? py->dchunk16 : py->dchunk;
-        const DevChunk& cx = mr == 16 ? px->dchunk16 : px->dchunk;
-        float pair_ms = -1.f;
-        int pair_shape = 0;
+        const DevChunk& cy = mc == 16 ? py->dchunk16 : py->dchunk;
+        Cand pair{-1.f, mc, mr, 0, false};
         for (int shape = 0; ok && shape < kNumRedShapes; ++shape) {
           if (reduced_lds_bytes(shape, 2, sizeof(double), cy.S, cy.dcount, true) > max_lds) continue;
-          cy.red_shape = shape;
-          const float ms = time_it([&]() {
-            hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho,
-                                                 K, part, st, nullptr, keep.col_order);
-            if (e == hipSuccess)
-              e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, st);
-            return e == hipSuccess ? launch_rows_lds<2>(cx, ybuf, nx, ny, st) : e;
-          });
-          if (ok && (pair_ms < 0.f || ms < pair_ms)) {
-            pair_ms = ms;
-            pair_shape = shape;
-          }
-          if (ok && (best_step < 0.f || ms < best_step)) {
-            best_step = ms;
-            best.mcol = mc;
-            best.mrow = mr;
-            best.red_shape = shape;
-            overlap = false;
-          }
+          const Cand cd{step_of(Cand{0.f, mc, mr, shape, false}), mc, mr, shape, false};
+          if (!ok) break;
+          cands.push_back(cd);
+          if (pair.ms < 0.f || cd.ms < pair.ms) pair = cd;
         }
-        if (!ok || !ok2 || pair_ms < 0.f) continue;
-        cy.red_shape = pair_shape;
-        const float ms = time_it([&]() {
-          hipError_t e = launch_ch_column_pass(true, true, dst, nx, ybuf, nx, nx, ny, cy, rho, K,
-                                               part, st, nullptr, keep.col_order);
-          if (e == hipSuccess) e = hipEventRecord(ef, st);
-          if (e == hipSuccess) e = hipStreamWaitEvent(side, ef, 0);
-          if (e == hipSuccess)
-            e = launch_reduced_il<2>(cy, rho, nx, ybuf, nx, cy.M, cy.M - 2, side);
-          if (e == hipSuccess) e = launch_rows_subset(true, ybuf, nx, ny, cy.M, cx, side);
-          if (e == hipSuccess) e = hipEventRecord(ej, side);
-          if (e == hipSuccess) e = launch_rows_subset(false, ybuf, nx, ny, cy.M, cx, st);
-          if (e == hipSuccess) e = hipStreamWaitEvent(st, ej, 0);
-          return e;
-        });
-        if (ok && ms < best_step) {
-          best_step = ms;
-          best.mcol = mc;
-          best.mrow = mr;
-          best.red_shape = pair_shape;
-          overlap = true;
-        }
+        if (!ok || !ok2 || pair.ms < 0.f) continue;
+        const Cand ov{0.f, mc, mr, pair.shape, true};
+        const float ms = step_of(ov);
+        if (ok) cands.push_back(Cand{ms, mc, mr, pair.shape, true});
       }
+    }
+    // the closest candidates differ by about the run-to-run spread of one
+    // timing: the three fastest (and the fastest whole-column separator
+    // shape, if none of them is one) are timed again, in turn, from longer
+    // graphs, and the fastest of those rounds decides -- a windowed shape
+    // only if it beats the whole-column one by more than 1 %, since it moves
+    // more bytes and its lead there has not held up in longer runs
+    std::sort(cands.begin(), cands.end(),
+              [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    const Cand* whole = nullptr;
+    for (const Cand& cd : cands)
+      if (reduced_shape_whole(cd.shape) && (!whole || cd.ms < whole->ms)) whole = &cd;
+    const Cand whole_cand = whole ? *whole : Cand{};
+    if (cands.size() > 3) cands.resize(3);
+    bool have_whole = false;
+    for (const Cand& cd : cands) have_whole = have_whole || reduced_shape_whole(cd.shape);
+    if (whole && !have_whole) cands.push_back(whole_cand);
+    timer.reps *= 4;
+    for (Cand& cd : cands) cd.ms = -1.f;
+    for (int round = 0; ok && round < 2; ++round) {
+      for (Cand& cd : cands) {
+        const float ms = step_of(cd);
+        if (ok && (cd.ms < 0.f || ms < cd.ms)) cd.ms = ms;
+      }
+    }
+    timer.reps /= 4;
+    bool overlap = false;
+    if (ok && !cands.empty()) {
+      const Cand* win = &cands[0];
+      for (const Cand& cd : cands)
+        if (cd.ms < win->ms) win = &cd;
+      const Cand* wf = nullptr;  // the fastest whole-column finalist
+      for (const Cand& cd : cands)
+        if (reduced_shape_whole(cd.shape) && (!wf || cd.ms < wf->ms)) wf = &cd;
+      if (wf && !reduced_shape_whole(win->shape) && wf->ms <= 1.01f * win->ms) win = wf;
+      best.mcol = win->mc;
+      best.mrow = win->mr;
+      best.red_shape = win->shape;
+      overlap = win->overlap;
     }
     if (side) (void)hipStreamSynchronize(side);
     if (ef) (void)hipEventDestroy(ef);

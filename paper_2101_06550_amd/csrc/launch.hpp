@@ -36,6 +36,9 @@ constexpr int kNumRedShapes = 15;
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 // (~0 when the shape cannot take S chunks)
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int S, int dcount, bool diag);
+// Whether a shape is of the whole-column form (every separator part loaded
+// once) rather than the windowed one.
+bool reduced_shape_whole(int shape);
 
 // Split row pass of the ADI step (penta, FP64, rows of 4096 or 8192 points):
 // column separators fused with the interior rows, then the separator rows.

@@ -1517,6 +1517,10 @@ static int whole_threads(const RedShape& r, int S) {
   return t < 256 ? 256 : t;
 }
 
+bool reduced_shape_whole(int shape) {
+  return shape >= 0 && shape < kNumRedShapes && kRedShapes[shape].L > 0;
+}
+
 size_t reduced_lds_bytes(int shape, int P, size_t elem, int S, int dcount, bool diag) {
   const RedShape& r = kRedShapes[shape];
   if (r.L > 0 && whole_threads(r, S) > 1024) return ~(size_t)0;
