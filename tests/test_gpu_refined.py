@@ -126,8 +126,11 @@ def test_adi_refined_large_run_one_step(chx, orc):
 # (ny, nx, dt, passes, steps, seed): several 32-row chunks, 60-column wave
 # segments with a ragged last one (nx % 60 != 0), exact segments (960), two
 # chunks (the wrap chunk is both neighbours), one chunk
+# (64, 64): one 64-column wave per row, whose halo lanes wrap onto its own
+# columns
 STEP_CASES = [(1024, 1024, 1e-5, 2, 3, 81), (96, 320, 1e-4, 1, 3, 82), (160, 576, 1e-4, 3, 2, 83),
-              (64, 2048, 1e-5, 2, 2, 84), (256, 960, 1e-4, 2, 2, 85), (32, 128, 1e-4, 1, 4, 86)]
+              (64, 2048, 1e-5, 2, 2, 84), (256, 960, 1e-4, 2, 2, 85), (32, 128, 1e-4, 1, 4, 86),
+              (64, 64, 1e-4, 2, 3, 87)]
 
 
 @pytest.mark.parametrize("ny,nx,dt,passes,k,seed", STEP_CASES)
