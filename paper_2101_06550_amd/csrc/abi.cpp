@@ -310,8 +310,8 @@ int solve(const BandPlan* p, int batch, void* x, long ld, int layout, int dtype,
     }
   } else {
     if (p->has_chunk && p->chunk.S <= 256) {
-      e = (p->P == 2) ? launch_rows_lds<2>(p->dchunk, xd, ld, batch, st)
-                      : launch_rows_lds<1>(p->dchunk, xd, ld, batch, st);
+      e = (p->P == 2) ? launch_rows_lds<2>(p->dchunk, xd, ld, batch, st, true)
+                      : launch_rows_lds<1>(p->dchunk, xd, ld, batch, st, true);
     } else {
       e = (p->P == 2) ? launch_whole<2>(p->dwhole, xd, ld, 1, batch, st)
                       : launch_whole<1>(p->dwhole, xd, ld, 1, batch, st);

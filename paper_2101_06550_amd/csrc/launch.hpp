@@ -95,7 +95,9 @@ hipError_t launch_reduced_il(const DevChunk& c, const double* rho, int batch, do
                              const double* dpart = nullptr, long dnparts = 0, double dscale = 0.0,
                              double* dout = nullptr);
 template <int P>
-hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st);
+// stream_in: the rows are read with non-temporal loads (standalone solves)
+hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st,
+                           bool stream_in = false);
 
 // FP32 sweeps with FP64 input/output (the refined path): the result is
 // written to, or added into (acc), the FP64 output.

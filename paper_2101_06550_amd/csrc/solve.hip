@@ -544,8 +544,11 @@ constexpr bool kRowsHalfTile = true;
 // threads 128..255, and the output leaves the same way in two halves.  At
 // M = 32, 46 KB of LDS instead of 80 KB: three groups per CU instead of two,
 // so more of HBM's latency is covered (three more barriers per group).
-// Arithmetic identical to row_solve_body (bitwise equal results).
-template <int P, int M>
+// Arithmetic identical to row_solve_body (bitwise equal results).  NTL:
+// the group streams in with non-temporal loads (the standalone solves; in
+// the ADI step they slowed the row pass more than they sped up the column
+// pass that follows it: 0.182 -> 0.216 and 0.216 -> 0.198 ms at 8192^2).
+template <int P, int M, bool NTL = false>
 __device__ __forceinline__ void row_half_body(double* xg, int S, const double* __restrict__ rec,
                                               const BandT<double>& bd,
                                               const double* __restrict__ blocks, int dlo,
@@ -559,7 +562,16 @@ __device__ __forceinline__ void row_half_body(double* xg, int S, const double* _
   double2* b2 = reinterpret_cast<double2*>(xg);
   double2 vin[M / 2];
 #pragma unroll
-  for (int u = 0; u < M / 2; ++u) vin[u] = b2[t + 256 * u];
+  for (int u = 0; u < M / 2; ++u) {
+    if constexpr (NTL) {
+      typedef double dv2 __attribute__((ext_vector_type(2)));
+      const dv2 w = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(b2 + t + 256 * u));
+      vin[u].x = w.x;
+      vin[u].y = w.y;
+    } else {
+      vin[u] = b2[t + 256 * u];
+    }
+  }
   // element e = 2t + 512u of the group lies in half u / (M/4); within its
   // half at e' = e - half NG/2, LDS slot e' + e' / M
   double f[M];
@@ -660,11 +672,11 @@ __device__ __forceinline__ void row_half_body(double* xg, int S, const double* _
   }
 }
 
-template <int P, int M>
+template <int P, int M, bool NTL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void row_solve_half(
     double* x, int S, const double* __restrict__ rec, BandT<double> bd,
     const double* __restrict__ blocks, int dlo, int dcount) {
-  row_half_body<P, M>(x + (long)blockIdx.x * (256 * M), S, rec, bd, blocks, dlo, dcount);
+  row_half_body<P, M, NTL>(x + (long)blockIdx.x * (256 * M), S, rec, bd, blocks, dlo, dcount);
 }
 
 // FP32 rows in, FP32 rows out (the refined step's row solves of its FP32
@@ -1652,12 +1664,16 @@ hipError_t launch_chunked_il32(const DevChunk& c, const double* src, long lds, f
 }
 
 template <int P>
-hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st) {
+hipError_t launch_rows_lds(const DevChunk& c, double* x, long ld, int rows, hipStream_t st,
+                           bool stream_in) {
   const int R = 256 / c.S;
   const long ngroups = ((long)rows + R - 1) / R;
   // dense rows in whole groups of 256 chunks: the half-tile kernel
   const bool half = kRowsHalfTile && P == 2 && ld == c.n && 256 % c.S == 0 && rows % R == 0;
-  if (half && c.M == kChunk)
+  if (half && c.M == kChunk && stream_in)
+    hipLaunchKernelGGL((row_solve_half<2, kChunk, true>), dim3((unsigned)ngroups), dim3(256), 0,
+                       st, x, c.S, c.rec, band_of<double>(c.coef), c.blocks, c.dlo, c.dcount);
+  else if (half && c.M == kChunk)
     hipLaunchKernelGGL((row_solve_half<2, kChunk>), dim3((unsigned)ngroups), dim3(256), 0, st, x,
                        c.S, c.rec, band_of<double>(c.coef), c.blocks, c.dlo, c.dcount);
   else if (half && c.M == 16)
@@ -1729,7 +1745,7 @@ hipError_t launch_resid_lines(const double* coef, int periodic, int n, const dou
   template hipError_t launch_reduced_il<P>(const DevChunk&, const double*, int, double*, long,  \
                                            int, int, hipStream_t, const double*, long, double,   \
                                            double*);                                             \
-  template hipError_t launch_rows_lds<P>(const DevChunk&, double*, long, int, hipStream_t);     \
+  template hipError_t launch_rows_lds<P>(const DevChunk&, double*, long, int, hipStream_t, bool); \
   template hipError_t launch_rows_lds32<P>(const DevChunk&, const double*, long, double*, long, \
                                            int, bool, hipStream_t);                              \
   template hipError_t launch_resid_lines<P>(const double*, int, int, const double*, long, long, \
