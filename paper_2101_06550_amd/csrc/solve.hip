@@ -306,10 +306,13 @@ __device__ __forceinline__ void row_group_stage(T* tile, const Tin* x, long ld, 
     Tin vin[M];
     if (nel == 256 * M && nvalid >= nel) {  // a full group: 16-byte loads, no guards
       if constexpr (sizeof(Tin) == 4) {  // four values per load
-        const float4* b4 = reinterpret_cast<const float4*>(base);
+        // non-temporal: the FP32 rows are read once (8192^2 refined step
+        // 1.632 -> 1.611 ms with 3 passes)
+        typedef float fv4 __attribute__((ext_vector_type(4)));
+        const fv4* b4 = reinterpret_cast<const fv4*>(base);
 #pragma unroll
         for (int u = 0; u < M / 4; ++u) {
-          const float4 v = b4[t + 256 * u];
+          const fv4 v = __builtin_nontemporal_load(&b4[t + 256 * u]);
           vin[4 * u] = v.x;
           vin[4 * u + 1] = v.y;
           vin[4 * u + 2] = v.z;
