@@ -916,7 +916,9 @@ def main():
         return
     if args.summarize_leg:
         tdir, out, only = args.summarize_leg
-        titles = {"p2": "thesis delta-form scheme (P2), 1024 x 1024 and 8192 x 8192, FP64",
+        titles = {"solves": "batched cyclic penta solves, N = 1024, 131072 systems, interleaved "
+                            "and contiguous, FP64",
+                  "p2": "thesis delta-form scheme (P2), 1024 x 1024 and 8192 x 8192, FP64",
                   "cook": "Cahn-Hilliard-Cook forced step, 8192 x 8192, FP64",
                   "ensemble": "uneven ensemble of 256 runs (96 x 128^2, 96 x 256^2, 64 x 512^2): "
                               "FP64, forced, FP32-refined",
