@@ -700,43 +700,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
 __device__ __forceinline__ void diag_tail_sum(const double* __restrict__ dpart, long dnparts,
                                               double dscale, double* __restrict__ dout,
                                               double* sm2) {
-      __syncthreads();
-      constexpr int nt = 256;
-      if ((int)threadIdx.x < nt) {
-        const long per = (dnparts + nt - 1) / nt;
-        const long b0 = (long)threadIdx.x * per;
-        const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
-        double m = 0.0, e = 0.0;
-        long b = b0;
-        for (; b + 8 <= b1; b += 8) {
-          double2 q[8];
-  #pragma unroll
-          for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
-  #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            m += q[u].x;
-            e += q[u].y;
-          }
-        }
-        for (; b < b1; ++b) {
-          m += dpart[2 * b];
-          e += dpart[2 * b + 1];
-        }
-        sm2[threadIdx.x] = m;
-        sm2[nt + threadIdx.x] = e;
+  __syncthreads();
+  constexpr int nt = 256;
+  if ((int)threadIdx.x < nt) {
+    const long per = (dnparts + nt - 1) / nt;
+    const long b0 = (long)threadIdx.x * per;
+    const long b1 = (b0 + per < dnparts) ? b0 + per : dnparts;
+    double m = 0.0, e = 0.0;
+    long b = b0;
+    // batches of 32 (a 8192^2 step's whole share) and then of 8 pairs,
+    // every batch's loads issued before its adds; the adds keep their
+    // order, so the sum does not depend on the batching
+    for (; b + 32 <= b1; b += 32) {
+      double2 q[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        m += q[u].x;
+        e += q[u].y;
       }
-      __syncthreads();
-      for (int h = nt / 2; h >= 1; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-          sm2[threadIdx.x] += sm2[threadIdx.x + h];
-          sm2[nt + threadIdx.x] += sm2[nt + threadIdx.x + h];
-        }
-        __syncthreads();
+    }
+    for (; b + 8 <= b1; b += 8) {
+      double2 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = reinterpret_cast<const double2*>(dpart)[b + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        m += q[u].x;
+        e += q[u].y;
       }
-      if (threadIdx.x == 0) {
-        dout[0] = sm2[0] * dscale;
-        dout[1] = sm2[nt] * dscale;
-      }
+    }
+    for (; b < b1; ++b) {
+      m += dpart[2 * b];
+      e += dpart[2 * b + 1];
+    }
+    sm2[threadIdx.x] = m;
+    sm2[nt + threadIdx.x] = e;
+  }
+  __syncthreads();
+  for (int h = nt / 2; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sm2[threadIdx.x] += sm2[threadIdx.x + h];
+      sm2[nt + threadIdx.x] += sm2[nt + threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    dout[0] = sm2[0] * dscale;
+    dout[1] = sm2[nt] * dscale;
+  }
 }
 
 // Reduced separator system with an LDS window: a block (W waves) owns 64
