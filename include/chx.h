@@ -376,9 +376,11 @@ int ch_adi_step_timed(chx_ch h, double* c_inout, long ld, int nsteps,
  *   once; a shape that does not fit the handle's chunk count or the LDS
  *   runs as shape 0).  ch_create times every
  *   candidate inside whole steps (column pass, separators, rows, for each
- *   chunk length) on zeroed scratch buffers of the handle's size and keeps
- *   the fastest; the choices (this shape, the row split, the column order
- *   and the chunk lengths)
+ *   chunk length, with the per-step mass and energy) on zeroed scratch
+ *   buffers of the handle's size, times the fastest three again from longer
+ *   graphs, and keeps the fastest (a windowed shape only if it beats the
+ *   best whole-column one by more than 1 %); the choices (this shape, the
+ *   row split, the column order and the chunk lengths)
  *   are kept per size for the life of the process and in a tuning cache
  *   file across processes: $CHX_TUNE_CACHE, else
  *   $XDG_CACHE_HOME/chx/tuning.txt, else $HOME/.cache/chx/tuning.txt (one
