@@ -312,3 +312,52 @@ def test_ensemble_sizes_step(chx, orc):
         print(f"[case] ensemble size {n}", flush=True)
         out, _ = gpu_steps(chx, c0, 1.0, 0.01, 1e-4)
         assert rel(out, orc.ch_step(c0, L, L, 1.0, 0.01, 1e-4)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [128, 1024])
+def test_step_argument_errors_leave_the_field_untouched(chx, orc, n):
+    """Through the C-ABI itself: a null field, ld < nx, nsteps < 1, a
+    workspace that is missing, too small or not 256-byte aligned, and a P1
+    call on a P2 handle are refused with their codes before any launch; the
+    field stays bitwise as it was and a valid call afterwards still matches
+    the oracle (128^2: the single-workgroup path; 1024^2: the multi-kernel
+    path replayed from a graph)."""
+    lib = chx.load()
+    c0 = inputs.noise_field(n, n, 11)
+    print(f"[case] ch step argument errors {n}x{n}", flush=True)
+    h = chx.ch_create(n, n, L, L, 1.0, 0.01, 1e-5)
+    c = torch.tensor(c0, device="cuda")
+    need = lib.ch_ws_bytes(h.handle)
+    ws = torch.zeros(need + 512, dtype=torch.uint8, device="cuda")
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    st = chx._stream(None)
+    cp_ = c.data_ptr()
+    bad = [
+        (dict(c=None), chx.CHX_EINVAL),
+        (dict(ld=n - 1), chx.CHX_EINVAL),
+        (dict(nsteps=0), chx.CHX_EINVAL),
+        (dict(nsteps=-3), chx.CHX_EINVAL),
+        (dict(ws=None), chx.CHX_ENOMEM),
+        (dict(avail=need - 8), chx.CHX_ENOMEM),
+        (dict(ws=aligned + 8, avail=need), chx.CHX_EINVAL),
+    ]
+    for over, code in bad:
+        a = dict(c=cp_, ld=n, nsteps=1, ws=aligned, avail=need)
+        a.update(over)
+        rc = lib.ch_adi_step(h.handle, a["c"], a["ld"], a["nsteps"], None, a["ws"],
+                             a["avail"], st)
+        assert rc == code, (over, rc)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), c0)
+    h2 = chx.ch_create(n, n, L, L, 1.0, 0.01, 1e-5, scheme=chx.CHX_SCHEME_P2)
+    need2 = lib.ch_ws_bytes(h2.handle)
+    ws2 = torch.zeros(need2 + 256, dtype=torch.uint8, device="cuda")
+    a2 = (ws2.data_ptr() + 255) // 256 * 256
+    assert lib.ch_adi_step(h2.handle, cp_, n, 1, None, a2, need2, st) == chx.CHX_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), c0)
+    assert lib.ch_adi_step(h.handle, cp_, n, 2, None, aligned, need, st) == chx.CHX_OK
+    torch.cuda.synchronize()
+    ref = orc.ch_step(orc.ch_step(c0, L, L, 1.0, 0.01, 1e-5), L, L, 1.0, 0.01, 1e-5)
+    assert rel(c.cpu().numpy(), ref) < 2e-12
