@@ -126,3 +126,44 @@ def test_rewrite_mode_matches_oracle_and_constant_mode(chx, orc, kind, n, batch,
     assert rel(x.cpu().numpy(), ref) < tol
     assert rel(x.cpu().numpy(), y.cpu().numpy()) < tol
     assert torch.all(buf[:, batch:] == 0)  # the padding is not written
+
+
+@pytest.mark.parametrize("rewrite", [False, True])
+def test_step_argument_errors_leave_the_batch_untouched(chx, orc, rewrite):
+    """Through the C-ABI itself (factor-once and Rewrite steps): a null
+    batch, batch < 0, nsteps < 1, ld < batch, a workspace that is missing,
+    too small or not 256-byte aligned are refused with their codes before any
+    launch and batch = 0 is a no-op; the batch stays bitwise as it was and a
+    valid call afterwards still matches the oracle."""
+    lib = chx.load()
+    kind, n, batch, L, dt, a, D = 2, 256, 300, L2PI, 2.5e-3, 0.01, 1.0
+    x0 = inputs.uniform(47, (n, batch), -0.1, 0.1)
+    print(f"[case] batch1d argument errors rewrite={rewrite}", flush=True)
+    b = chx.batch1d_create(kind, n, L, dt, a, D)
+    x = torch.tensor(x0, device="cuda")
+    step = lib.batch1d_step_rewrite if rewrite else lib.batch1d_step
+    need = (lib.batch1d_rewrite_ws_bytes if rewrite else lib.batch1d_ws_bytes)(b.handle, batch)
+    ws = torch.zeros(need + 512, dtype=torch.uint8, device="cuda")
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    st = chx._stream(None)
+    bad = [
+        (dict(x=None), chx.CHX_EINVAL),
+        (dict(batch=-1), chx.CHX_EINVAL),
+        (dict(nsteps=0), chx.CHX_EINVAL),
+        (dict(ld=batch - 1), chx.CHX_EINVAL),
+        (dict(ws=None), chx.CHX_ENOMEM),
+        (dict(avail=need - 8), chx.CHX_ENOMEM),
+        (dict(ws=aligned + 8), chx.CHX_EINVAL),
+        (dict(batch=0), chx.CHX_OK),
+    ]
+    for over, code in bad:
+        g = dict(x=x.data_ptr(), batch=batch, ld=batch, nsteps=1, ws=aligned, avail=need)
+        g.update(over)
+        rc = step(b.handle, g["batch"], g["x"], g["ld"], g["nsteps"], g["ws"], g["avail"], st)
+        assert rc == code, (over, rc)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), x0)
+    assert step(b.handle, batch, x.data_ptr(), batch, 2, aligned, need, st) == chx.CHX_OK
+    torch.cuda.synchronize()
+    ref = orc.batch1d_step(kind, x0, L, dt, a, D, nsteps=2)
+    assert rel(x.cpu().numpy(), ref) < 1e-11
