@@ -172,3 +172,52 @@ def test_large_batch_sampled(chx, orc):
     host = [t[:, pick].cpu().numpy() for t in A]
     ref = orc.penta_rows_batch(*host, f[:, pick].cpu().numpy(), True)
     assert _err(x[:, pick].cpu().numpy(), ref) < 1e-12
+
+
+def test_penta_rewrite_argument_errors_leave_the_arrays_untouched(chx, orc):
+    """Through the C-ABI itself: a null band or right-hand side, batch < 0,
+    ld < batch, periodic other than 0/1, n below the periodic minimum, a
+    workspace that is missing, misaligned or too small are refused with their
+    codes before any launch and batch = 0 is a no-op; bands and right-hand
+    sides stay bitwise as they were and a valid call afterwards still matches
+    the oracle."""
+    lib = chx.load()
+    n, batch = 33, 70
+    print(f"[penta per-system] argument errors n={n} batch={batch}", flush=True)
+    host = _penta_system(n, batch, 77)
+    A = [torch.tensor(v, device="cuda") for v in host[:5]]
+    x = torch.tensor(host[5], device="cuda")
+    need = lib.penta_batch_ws_bytes(n, batch, 1, getattr(chx, "CHX_BATCH_REWRITE", 1))
+    assert need > 0
+    ws = torch.zeros(need + 512, dtype=torch.uint8, device="cuda")
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    st = chx._stream(None)
+    bad = [
+        (dict(a=None), chx.CHX_EINVAL),
+        (dict(x=None), chx.CHX_EINVAL),
+        (dict(batch=-1), chx.CHX_EINVAL),
+        (dict(ld=batch - 1), chx.CHX_EINVAL),
+        (dict(periodic=2), chx.CHX_EINVAL),
+        (dict(n=4), chx.CHX_EUNSUPPORTED_N),
+        (dict(ws=None), chx.CHX_EINVAL),
+        (dict(ws=aligned + 8), chx.CHX_EINVAL),
+        (dict(avail=need - 8), chx.CHX_ENOMEM),
+        (dict(batch=0), chx.CHX_OK),
+    ]
+    for over, code in bad:
+        g = dict(n=n, batch=batch, periodic=1, a=A[0].data_ptr(), ld=batch, x=x.data_ptr(),
+                 ws=aligned, avail=need)
+        g.update(over)
+        rc = lib.penta_batch_rewrite(g["n"], g["batch"], g["periodic"], g["a"],
+                                     *[t.data_ptr() for t in A[1:]], g["ld"], g["x"], g["ws"],
+                                     g["avail"], st)
+        assert rc == code, (over, rc)
+    torch.cuda.synchronize()
+    for v, t in zip(host, A + [x]):
+        assert np.array_equal(t.cpu().numpy(), v)
+    rc = lib.penta_batch_rewrite(n, batch, 1, *[t.data_ptr() for t in A], batch, x.data_ptr(),
+                                 aligned, need, st)
+    assert rc == chx.CHX_OK
+    torch.cuda.synchronize()
+    ref = orc.penta_rows_batch(*host, True)
+    assert _err(x.cpu().numpy(), ref) < 1e-12
