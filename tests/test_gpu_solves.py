@@ -323,3 +323,42 @@ def test_stencil_eighth_order_example(chx):
     o = out.cpu().numpy()
     assert np.abs(o[:, 4:-4] + np.sin(xs)[None, 4:-4]).max() < 1e-9
     assert np.all(o[:, :4] == 0) and np.all(o[:, -4:] == 0)
+
+
+def test_stencil_argument_errors_leave_the_output_untouched(chx, orc):
+    """Through the C-ABI itself: null arrays or weights, an unknown dtype,
+    empty or short-pitched fields, extents outside 0..4, an unknown pre-map,
+    overlapping input and output, and non-finite weights are refused with
+    CHX_EINVAL before any launch; the output keeps its contents and a valid
+    call afterwards still matches the oracle."""
+    import ctypes
+    lib = chx.load()
+    ny, nx = 40, 48
+    x = inputs.uniform(8, (ny, nx), -1, 1)
+    w = inputs.uniform(9, (9,), -1, 1)
+    xin = torch.tensor(x, device="cuda")
+    xo = torch.full((ny, nx), 3.5, dtype=torch.float64, device="cuda")
+    print("[case] stencil argument errors", flush=True)
+    wbuf = (ctypes.c_double * 9)(*w)
+    wnan = (ctypes.c_double * 9)(*w)
+    wnan[4] = float("nan")
+    st = chx._stream(None)
+    bad = [dict(inp=None), dict(out=None), dict(w=None), dict(dtype=7), dict(nx=0),
+           dict(ld=nx - 1), dict(left=-1), dict(bottom=5), dict(premap=2),
+           dict(out=xin.data_ptr() + 8), dict(w=wnan)]
+    for over in bad:
+        g = dict(inp=xin.data_ptr(), out=xo.data_ptr(), nx=nx, ld=nx, dtype=chx.CHX_F64, w=wbuf,
+                 left=1, right=1, top=1, bottom=1, premap=0)
+        g.update(over)
+        rc = lib.stencil2d_apply(g["inp"], g["out"], g["nx"], ny, g["ld"], g["dtype"], g["w"],
+                                 g["left"], g["right"], g["top"], g["bottom"], 1, g["premap"], st)
+        assert rc == chx.CHX_EINVAL, (over, rc)
+    torch.cuda.synchronize()
+    assert torch.all(xo == 3.5)
+    assert np.array_equal(xin.cpu().numpy(), x)
+    rc = lib.stencil2d_apply(xin.data_ptr(), xo.data_ptr(), nx, ny, nx, chx.CHX_F64, wbuf,
+                             1, 1, 1, 1, 1, 0, st)
+    assert rc == chx.CHX_OK
+    torch.cuda.synchronize()
+    ref = orc.stencil2d(x, w.reshape(3, 3), 1, 1, 1, 1, periodic=True, premap=0)
+    np.testing.assert_allclose(xo.cpu().numpy(), ref, rtol=0, atol=1e-13)
